@@ -1,0 +1,306 @@
+"""CPU oracle for the hybrid symplectic N-body hot path (Mercury-Opal, arXiv 2601.19654).
+
+TEST INFRASTRUCTURE ONLY: the tests, ``__graft_entry__.smoke()`` and the CPU
+baseline leg of ``bench.py`` are the only callers.  The product path never
+imports this package.
+
+``nbody_oracle.c`` is a plain serial FP64 implementation written from the paper
+(Sec. 2.1.1 for the integrator and its coordinates, Sec. 3.1 for the force,
+Hamiltonian, drift and encounter blocks) and from the textbook definitions it
+relies on; this module is argument marshalling around it (numpy, ctypes) plus a
+multi-system driver that repeats the single-system C routines per system.
+
+Parity status per function (pins live in ``tests/test_oracle_*.py``):
+  force, changeover, rcrit   pinned (closed forms, Newton III, torque, FD gradient)
+  Kepler drift, Stumpff      pinned (Kepler's equation, invariants, library trig)
+  encounter predicate        pinned (straight-line closed form, dense sampling)
+  energy / momenta           pinned (explicit barycentric formula, invariants)
+  transforms                 pinned (barycentre definition, round trip)
+  step                       pinned (2nd-order convergence, reversibility, E bound)
+  gas drag                   parity unpinned by the paper (limits and closed form
+                             of the chosen formula only)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "nbody_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99"]
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C99, no contraction, no fast math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        L = ctypes.CDLL(_LIB)
+        d, i, p = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
+        sig = {
+            "orc_changeover": (None, [d, d, d, p, p]),
+            "orc_rcrit": (None, [i, d, p, p, d, p]),
+            "orc_force": (None, [i, d, d, p, p, p, p]),
+            "orc_kick": (None, [i, d, p, p]),
+            "orc_momentum": (None, [i, p, p, p]),
+            "orc_sun_drift": (None, [i, d, d, p, p, p]),
+            "orc_helio_to_dh": (None, [i, d, p, p, p, p, p]),
+            "orc_dh_to_helio": (None, [i, d, p, p, p, p, p]),
+            "orc_stumpff": (None, [d, p]),
+            "orc_kepler_drift": (i, [d, d, p, p]),
+            "orc_drift": (i, [i, d, d, p, p, p]),
+            "orc_pair_min_d2": (d, [d, p, p, p, p, p, p, p, p]),
+            "orc_encounters": (None, [i, d, p, p, p, p, p, i, p, p, p, p, d, i, p, p, p]),
+            "orc_energy": (None, [i, d, d, d, p, p, p, p, p, p, p, p]),
+            "orc_drag_accel": (None, [i, d, d, p, p, p, p, d, d, d, d, p]),
+            "orc_kick_drag": (None, [i, d, d, d, p, p, p, p, d, d, d, d, p]),
+            "orc_step": (i, [i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, p, p, p, p, i, p, p, p, p]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ---------------------------------------------------------------- constants
+# Project constants (units AU, Msun, yr).  Written out here independently of
+# the HIP library; the paper fixes none of them.
+AU_CM = 1.495978707e13
+MSUN_G = 1.98840987e33
+RHO_UNIT = MSUN_G / AU_CM ** 3          # g/cm^3 per Msun/AU^3
+SIGMA_UNIT = MSUN_G / AU_CM ** 2        # g/cm^2 per Msun/AU^2
+
+
+@dataclass
+class Params:
+    G: float = (0.01720209895 * 365.25) ** 2
+    n_hill: float = 3.0
+    inner: float = 0.1
+    drag: bool = False
+    sigma0: float = 1000.0 / SIGMA_UNIT   # 1000 g/cm^2 at 1 AU
+    h: float = 0.05
+    cd: float = 1.0
+    rho_p: float = 2.0 / RHO_UNIT         # 2 g/cm^3
+
+
+# ---------------------------------------------------------------- single system
+def changeover(r, rc, inner=0.1):
+    K, dK = ctypes.c_double(), ctypes.c_double()
+    lib().orc_changeover(float(r), float(rc), float(inner), ctypes.byref(K), ctypes.byref(dK))
+    return K.value, dK.value
+
+
+def rcrit(m0, m, Q, n_hill=3.0):
+    m = _f64(m); Q = _f64(Q, (-1, 3)); rc = np.empty(len(m))
+    lib().orc_rcrit(len(m), float(m0), _ptr(m), _ptr(Q), float(n_hill), _ptr(rc))
+    return rc
+
+
+def force(m, Q, rc, G, inner=0.1):
+    m = _f64(m); Q = _f64(Q, (-1, 3)); rc = _f64(rc); a = np.empty_like(Q)
+    lib().orc_force(len(m), float(G), float(inner), _ptr(m), _ptr(Q), _ptr(rc), _ptr(a))
+    return a
+
+
+def momentum(m, V):
+    m = _f64(m); V = _f64(V, (-1, 3)); P = np.empty(3)
+    lib().orc_momentum(len(m), _ptr(m), _ptr(V), _ptr(P))
+    return P
+
+
+def kick(h, a, V):
+    a = _f64(a, (-1, 3)); V = _f64(V, (-1, 3)).copy()
+    lib().orc_kick(len(V), float(h), _ptr(a), _ptr(V))
+    return V
+
+
+def sun_drift(h, m0, m, V, Q):
+    m = _f64(m); V = _f64(V, (-1, 3)); Q = _f64(Q, (-1, 3)).copy()
+    lib().orc_sun_drift(len(m), float(h), float(m0), _ptr(m), _ptr(V), _ptr(Q))
+    return Q
+
+
+def helio_to_dh(m0, m, xh, vh):
+    m = _f64(m); xh = _f64(xh, (-1, 3)); vh = _f64(vh, (-1, 3))
+    Q = np.empty_like(xh); V = np.empty_like(vh)
+    lib().orc_helio_to_dh(len(m), float(m0), _ptr(m), _ptr(xh), _ptr(vh), _ptr(Q), _ptr(V))
+    return Q, V
+
+
+def dh_to_helio(m0, m, Q, V):
+    m = _f64(m); Q = _f64(Q, (-1, 3)); V = _f64(V, (-1, 3))
+    xh = np.empty_like(Q); vh = np.empty_like(V)
+    lib().orc_dh_to_helio(len(m), float(m0), _ptr(m), _ptr(Q), _ptr(V), _ptr(xh), _ptr(vh))
+    return xh, vh
+
+
+def stumpff(z):
+    c = np.empty(4)
+    lib().orc_stumpff(float(z), _ptr(c))
+    return c
+
+
+def drift(mu, tau, Q, V):
+    """Kepler-drift every body; returns (Q, V, flags)."""
+    Q = _f64(Q, (-1, 3)).copy(); V = _f64(V, (-1, 3)).copy()
+    flag = np.zeros(len(Q), dtype=np.int32)
+    lib().orc_drift(len(Q), float(mu), float(tau), _ptr(Q), _ptr(V), _ptr(flag))
+    return Q, V, flag
+
+
+def pair_min_d2(tau, q0i, v0i, q1i, v1i, q0j, v0j, q1j, v1j):
+    args = [_f64(t, (3,)) for t in (q0i, v0i, q1i, v1i, q0j, v0j, q1j, v1j)]
+    return lib().orc_pair_min_d2(float(tau), *[_ptr(t) for t in args])
+
+
+def encounters(tau, Q0, V0, Q1, V1, rc, cap=None, tie=1e-10):
+    """Flagged pairs (i<j, lexicographic), per-body flags, tie-band pairs."""
+    Q0, V0, Q1, V1 = (_f64(t, (-1, 3)) for t in (Q0, V0, Q1, V1))
+    rc = _f64(rc); n = len(rc)
+    cap = n * (n - 1) // 2 if cap is None else cap
+    cap_alloc = max(cap, 1)
+    ice = np.zeros(cap_alloc, np.int32); jce = np.zeros(cap_alloc, np.int32)
+    ce = np.zeros(max(n, 1), np.int32)
+    tie_cap = 1 << 16
+    ti = np.zeros(tie_cap, np.int32); tj = np.zeros(tie_cap, np.int32)
+    nce = ctypes.c_int(); ntie = ctypes.c_int()
+    lib().orc_encounters(n, float(tau), _ptr(Q0), _ptr(V0), _ptr(Q1), _ptr(V1), _ptr(rc), int(cap),
+                         _ptr(ice), _ptr(jce), _ptr(ce), ctypes.byref(nce), float(tie), tie_cap,
+                         _ptr(ti), _ptr(tj), ctypes.byref(ntie))
+    k = min(nce.value, cap)
+    t = min(ntie.value, tie_cap)
+    return {"nce": nce.value, "ice": ice[:k].copy(), "jce": jce[:k].copy(), "ce": ce[:n].copy(),
+            "tie": set(zip(ti[:t].tolist(), tj[:t].tolist())), "ntie": ntie.value}
+
+
+def energy(G, m0, m, Q, V, rc, inner=0.1):
+    m = _f64(m); Q = _f64(Q, (-1, 3)); V = _f64(V, (-1, 3)); rc = _f64(rc)
+    E, EK = ctypes.c_double(), ctypes.c_double()
+    L = np.empty(3); P = np.empty(3)
+    lib().orc_energy(len(m), float(G), float(m0), float(inner), _ptr(m), _ptr(Q), _ptr(V), _ptr(rc),
+                     ctypes.byref(E), ctypes.byref(EK), _ptr(L), _ptr(P))
+    return {"E": E.value, "EK": EK.value, "L": L, "P": P}
+
+
+def drag_accel(G, m0, m, Q, V, prm: Params):
+    m = _f64(m); Q = _f64(Q, (-1, 3)); V = _f64(V, (-1, 3))
+    P = momentum(m, V); ad = np.empty_like(Q)
+    lib().orc_drag_accel(len(m), float(G), float(m0), _ptr(m), _ptr(Q), _ptr(V), _ptr(P),
+                         prm.sigma0, prm.h, prm.cd, prm.rho_p, _ptr(ad))
+    return ad
+
+
+# ---------------------------------------------------------------- multi-system driver
+class State:
+    """Oracle state of a batch of independent systems in DH coordinates.
+
+    Mirrors the step order K(h) S(h) D(tau) C S(h) [rc, force] K(h) with the
+    force primed at construction (first-same-as-last).
+    """
+
+    def __init__(self, off, m0, m, x, v, prm: Params | None = None, frame="helio"):
+        self.prm = prm or Params()
+        self.off = np.asarray(off, dtype=np.int64)
+        self.m0 = _f64(m0).copy()
+        self.m = _f64(m).copy()
+        n = len(self.m)
+        self.Q = np.empty((n, 3)); self.V = np.empty((n, 3))
+        for s, (a, b) in enumerate(self.systems()):
+            if frame == "helio":
+                self.Q[a:b], self.V[a:b] = helio_to_dh(self.m0[s], self.m[a:b], x[a:b], v[a:b])
+            else:
+                self.Q[a:b] = x[a:b]; self.V[a:b] = v[a:b]
+        self.rc = np.empty(n)
+        self.a = np.empty((n, 3))
+        self.Q0 = self.Q.copy(); self.V0 = self.V.copy()
+        self.kflag = np.zeros(n, np.int32)
+        self.ce = np.zeros(n, np.int32)
+        self.enc = []
+        self.prime()
+
+    @classmethod
+    def from_workload(cls, w, prm: Params | None = None):
+        prm = prm or Params(G=w.G, drag=w.drag)
+        return cls(w.off, w.m0, w.m, w.x, w.v, prm)
+
+    def systems(self):
+        for s in range(len(self.m0)):
+            yield int(self.off[s]), int(self.off[s + 1])
+
+    def prime(self):
+        p = self.prm
+        for s, (a, b) in enumerate(self.systems()):
+            self.rc[a:b] = rcrit(self.m0[s], self.m[a:b], self.Q[a:b], p.n_hill)
+            self.a[a:b] = force(self.m[a:b], self.Q[a:b], self.rc[a:b], p.G, p.inner)
+
+    def step(self, tau, cap=None):
+        """One hybrid step of every system; returns the total Kepler failures.
+
+        ``self.enc`` receives, per system, the flagged pair list in global
+        indices."""
+        p = self.prm
+        L = lib()
+        nfail = 0
+        self.enc = []
+        for s, (a, b) in enumerate(self.systems()):
+            n = b - a
+            Q = np.ascontiguousarray(self.Q[a:b]); V = np.ascontiguousarray(self.V[a:b])
+            A = np.ascontiguousarray(self.a[a:b]); rc = np.ascontiguousarray(self.rc[a:b])
+            m = np.ascontiguousarray(self.m[a:b])
+            Q0 = np.empty_like(Q); V0 = np.empty_like(V)
+            kf = np.zeros(n, np.int32); ce = np.zeros(max(n, 1), np.int32)
+            scratch = np.empty_like(Q)
+            c = n * (n - 1) // 2 if cap is None else cap
+            ice = np.zeros(max(c, 1), np.int32); jce = np.zeros(max(c, 1), np.int32)
+            nce = ctypes.c_int()
+            nfail += L.orc_step(n, p.G, float(self.m0[s]), p.n_hill, p.inner, _ptr(m), _ptr(Q), _ptr(V),
+                                _ptr(A), _ptr(rc), float(tau), int(p.drag), p.sigma0, p.h, p.cd, p.rho_p,
+                                _ptr(Q0), _ptr(V0), _ptr(kf), _ptr(scratch), int(c), _ptr(ice), _ptr(jce),
+                                _ptr(ce), ctypes.byref(nce))
+            self.Q[a:b] = Q; self.V[a:b] = V; self.a[a:b] = A; self.rc[a:b] = rc
+            self.Q0[a:b] = Q0; self.V0[a:b] = V0; self.kflag[a:b] = kf; self.ce[a:b] = ce[:n]
+            k = min(nce.value, c)
+            self.enc.append((nce.value, ice[:k] + a, jce[:k] + a))
+        return nfail
+
+    def energy(self):
+        p = self.prm
+        out = []
+        for s, (a, b) in enumerate(self.systems()):
+            out.append(energy(p.G, self.m0[s], self.m[a:b], self.Q[a:b], self.V[a:b], self.rc[a:b], p.inner))
+        return out
+
+    def helio(self):
+        xh = np.empty_like(self.Q); vh = np.empty_like(self.V)
+        for s, (a, b) in enumerate(self.systems()):
+            xh[a:b], vh[a:b] = dh_to_helio(self.m0[s], self.m[a:b], self.Q[a:b], self.V[a:b])
+        return xh, vh

@@ -1,0 +1,596 @@
+/*
+ * CPU oracle for the hybrid symplectic N-body hot path of Mercury-Opal
+ * (arXiv 2601.19654).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It is a plain, serial,
+ * FP64 reference written from the paper and from the textbook definitions the
+ * paper relies on; it shares no code, header, table or constant with the HIP
+ * library.  Build flags: -O2 -fno-fast-math -ffp-contract=off.
+ *
+ * The paper prints no formula.  What it fixes, by section:
+ *   Sec. 2.1.1  the integrator is Mercury's second-order mixed-variable
+ *               symplectic (hybrid) scheme in democratic-heliocentric
+ *               coordinates (heliocentric positions, barycentric velocities);
+ *               the Hamiltonian splits into Kepler drift, interaction and
+ *               stellar-motion parts; the critical radius is a multiple of the
+ *               Hill radius, which is recomputed every step from the
+ *               star-planet separation.
+ *   Sec. 3.1    force block: per target body, a sum over all source bodies
+ *               (skipping the star); Hamiltonian block: velocity update, then
+ *               a sum over bodies, then positions; drift block: every body is
+ *               propagated on its Kepler orbit about the star, with a
+ *               per-body failure flag and a copy of positions and velocities
+ *               taken first; encounter block: per body extremes over the
+ *               step, widened by the critical radius, then every unordered
+ *               pair (i<j) whose minimum separation over the step is at or
+ *               below the critical distance is appended to a pair list and
+ *               both bodies get flag value 2.
+ * Where the paper is silent, the readings used are those listed with each
+ * function below (units, changeover function, Hill radius, encounter
+ * interpolant, drift formulation, energy, drag).
+ *
+ * Conventions: bodies are indexed 0..n-1 and exclude the star (the paper's
+ * index 1 is the star); position/velocity/acceleration arrays are row-major
+ * n x 3.  All pair and body sums are taken in index order with Neumaier
+ * compensation, so the oracle's own summation error stays near one ulp.
+ *
+ * Parity-unpinned parts: gas drag (Sec. 2.1 names aerodynamic drag; the disk
+ * model is in a companion paper that is not available).  Its tests pin only
+ * limits and closed forms of the formula chosen here.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+#include <float.h>
+
+/* ------------------------------------------------------------------ */
+/* Compensated (Neumaier) accumulation                                 */
+/* ------------------------------------------------------------------ */
+typedef struct { double s, c; } nsum;
+
+static void ns_add(nsum *a, double x)
+{
+    double t = a->s + x;
+    if (fabs(a->s) >= fabs(x))
+        a->c += (a->s - t) + x;
+    else
+        a->c += (x - t) + a->s;
+    a->s = t;
+}
+
+static double ns_val(const nsum *a) { return a->s + a->c; }
+
+/* ------------------------------------------------------------------ */
+/* Changeover function (Sec. 2.1.1: interaction part trusted only      */
+/* outside the critical radius).  Reading: y = (r - f rc)/((1-f) rc),  */
+/* K = 0 for y<=0, y^2/(2y^2-2y+1) for 0<y<1, 1 for y>=1, f = inner.   */
+/* Returns K and dK/dr.                                                 */
+/* ------------------------------------------------------------------ */
+void orc_changeover(double r, double rc, double inner, double *K, double *dKdr)
+{
+    double ri = inner * rc;
+    double width = (1.0 - inner) * rc;
+    if (r >= rc) {
+        *K = 1.0;
+        *dKdr = 0.0;
+    } else if (r <= ri) {
+        *K = 0.0;
+        *dKdr = 0.0;
+    } else {
+        double y = (r - ri) / width;
+        double den = 2.0 * y * y - 2.0 * y + 1.0;
+        *K = y * y / den;
+        *dKdr = 2.0 * y * (1.0 - y) / (den * den * width);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Critical radius (Sec. 2.1.1 footnotes): a multiple n_hill of the     */
+/* Hill radius, which depends on the star-planet separation:           */
+/* rc_i = n_hill |Q_i| (m_i / (3 m0))^(1/3).                            */
+/* ------------------------------------------------------------------ */
+void orc_rcrit(int n, double m0, const double *m, const double *Q, double n_hill, double *rc)
+{
+    for (int i = 0; i < n; ++i) {
+        double r = sqrt(Q[3 * i] * Q[3 * i] + Q[3 * i + 1] * Q[3 * i + 1] + Q[3 * i + 2] * Q[3 * i + 2]);
+        rc[i] = n_hill * r * cbrt(m[i] / (3.0 * m0));
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Interaction acceleration (Sec. 3.1, force block, loop 2).           */
+/* a_i = sum_{j != i} G m_j w(r_ij) (Q_j - Q_i),                         */
+/* w = K/r^3 - (dK/dr)/r^2 with rc_ij = max(rc_i, rc_j): the exact        */
+/* gradient of the potential -G m_i m_j K(r)/r.  Coincident distinct     */
+/* bodies (r = 0) contribute nothing; the self term is skipped by index.  */
+/* ------------------------------------------------------------------ */
+void orc_force(int n, double G, double inner, const double *m, const double *Q,
+               const double *rc, double *a)
+{
+    for (int i = 0; i < n; ++i) {
+        nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+        for (int j = 0; j < n; ++j) {
+            if (j == i)
+                continue;
+            double dx = Q[3 * j] - Q[3 * i];
+            double dy = Q[3 * j + 1] - Q[3 * i + 1];
+            double dz = Q[3 * j + 2] - Q[3 * i + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0)
+                continue;
+            double r = sqrt(r2);
+            double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
+            double K, dK;
+            orc_changeover(r, rcij, inner, &K, &dK);
+            double w = K / (r2 * r) - dK / r2;
+            double f = G * m[j] * w;
+            ns_add(&ax, f * dx);
+            ns_add(&ay, f * dy);
+            ns_add(&az, f * dz);
+        }
+        a[3 * i] = ns_val(&ax);
+        a[3 * i + 1] = ns_val(&ay);
+        a[3 * i + 2] = ns_val(&az);
+    }
+}
+
+/* Interaction kick (Sec. 3.1, Hamiltonian block loop 1): V += h a. */
+void orc_kick(int n, double h, const double *a, double *V)
+{
+    for (int k = 0; k < 3 * n; ++k)
+        V[k] += h * a[k];
+}
+
+/* Sum of m_i V_i over the system's bodies (Sec. 3.1, Hamiltonian block loop 2). */
+void orc_momentum(int n, const double *m, const double *V, double *P)
+{
+    nsum px = {0, 0}, py = {0, 0}, pz = {0, 0};
+    for (int i = 0; i < n; ++i) {
+        ns_add(&px, m[i] * V[3 * i]);
+        ns_add(&py, m[i] * V[3 * i + 1]);
+        ns_add(&pz, m[i] * V[3 * i + 2]);
+    }
+    P[0] = ns_val(&px);
+    P[1] = ns_val(&py);
+    P[2] = ns_val(&pz);
+}
+
+/* Stellar-motion drift (Hamiltonian block loops 2-3): Q += h P / m0. */
+void orc_sun_drift(int n, double h, double m0, const double *m, const double *V, double *Q)
+{
+    double P[3];
+    orc_momentum(n, m, V, P);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k)
+            Q[3 * i + k] += h * P[k] / m0;
+}
+
+/* Heliocentric -> democratic heliocentric (Sec. 2.1.1 footnote):
+ * Q = x_h, V = v_h - sum_j m_j v_h,j / (m0 + sum_j m_j). */
+void orc_helio_to_dh(int n, double m0, const double *m, const double *xh, const double *vh,
+                     double *Q, double *V)
+{
+    nsum px = {0, 0}, py = {0, 0}, pz = {0, 0}, mt = {0, 0};
+    for (int i = 0; i < n; ++i) {
+        ns_add(&px, m[i] * vh[3 * i]);
+        ns_add(&py, m[i] * vh[3 * i + 1]);
+        ns_add(&pz, m[i] * vh[3 * i + 2]);
+        ns_add(&mt, m[i]);
+    }
+    double M = m0 + ns_val(&mt);
+    double c[3] = {ns_val(&px) / M, ns_val(&py) / M, ns_val(&pz) / M};
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            Q[3 * i + k] = xh[3 * i + k];
+            V[3 * i + k] = vh[3 * i + k] - c[k];
+        }
+}
+
+/* Democratic heliocentric -> heliocentric: v_h = V + sum_j m_j V_j / m0. */
+void orc_dh_to_helio(int n, double m0, const double *m, const double *Q, const double *V,
+                     double *xh, double *vh)
+{
+    double P[3];
+    orc_momentum(n, m, V, P);
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < 3; ++k) {
+            xh[3 * i + k] = Q[3 * i + k];
+            vh[3 * i + k] = V[3 * i + k] + P[k] / m0;
+        }
+}
+
+/* ------------------------------------------------------------------ */
+/* Kepler drift (Sec. 2.1 and 3.1: every body follows its Kepler orbit  */
+/* about the star for the full step).  Reading: universal-variable      */
+/* (Stumpff-function) formulation with mu = G m0.                        */
+/* ------------------------------------------------------------------ */
+
+/* Stumpff functions c_k(z) = sum_n (-z)^n / (2n+k)!, k = 0..3.
+ * Power series for |z| <= 1, trigonometric / hyperbolic closed forms beyond. */
+void orc_stumpff(double z, double c[4])
+{
+    if (fabs(z) <= 1.0) {
+        /* c0 and c1 from their series; c2, c3 likewise (independent sums). */
+        for (int k = 0; k < 4; ++k) {
+            double term = 1.0;
+            for (int j = 2; j <= k; ++j)
+                term /= (double)j;               /* 1/k! */
+            double s = term;
+            for (int nn = 1; nn < 40; ++nn) {
+                term *= -z / ((double)(2 * nn + k - 1) * (double)(2 * nn + k));
+                double s2 = s + term;
+                if (s2 == s)
+                    break;
+                s = s2;
+            }
+            c[k] = s;
+        }
+    } else if (z > 0.0) {
+        double x = sqrt(z);
+        c[0] = cos(x);
+        c[1] = sin(x) / x;
+        c[2] = (1.0 - c[0]) / z;
+        c[3] = (1.0 - c[1]) / z;
+    } else {
+        double x = sqrt(-z);
+        c[0] = cosh(x);
+        c[1] = sinh(x) / x;
+        c[2] = (1.0 - c[0]) / z;
+        c[3] = (1.0 - c[1]) / z;
+    }
+}
+
+/* G_k(s) = s^k c_k(beta s^2), k = 0..3 */
+static void gfun(double beta, double s, double G[4])
+{
+    double c[4];
+    orc_stumpff(beta * s * s, c);
+    G[0] = c[0];
+    G[1] = s * c[1];
+    G[2] = s * s * c[2];
+    G[3] = s * s * s * c[3];
+}
+
+/* Propagate one body on its Kepler orbit (mu = G m0) for time tau.
+ * Solves F(s) = r0 s + eta0 G2(s) + zeta0 G3(s) - tau = 0 (F' = r > 0, so the
+ * root is unique) by Newton's method kept inside a bracket, with bisection
+ * whenever a Newton step leaves it; converged at |ds| <= 4u|s|; at most 100
+ * iterations.  On failure the body is left unchanged and 1 is returned. */
+int orc_kepler_drift(double mu, double tau, double *q, double *v)
+{
+    if (tau == 0.0)
+        return 0;
+    double r0 = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    double eta0 = q[0] * v[0] + q[1] * v[1] + q[2] * v[2];
+    double beta = 2.0 * mu / r0 - v2;
+    double zeta0 = mu - beta * r0;
+    if (!(r0 > 0.0) || !isfinite(r0) || !isfinite(v2))
+        return 1;
+
+    double G[4];
+    /* bracket [lo, hi] with F(lo) <= 0 <= F(hi); F(0) = -tau */
+    double lo, hi;
+    double s = tau / r0;
+    if (tau > 0.0) {
+        lo = 0.0;
+        hi = s;
+        for (int k = 0; k < 200; ++k) {
+            gfun(beta, hi, G);
+            double F = r0 * hi + eta0 * G[2] + zeta0 * G[3] - tau;
+            if (F >= 0.0 || !isfinite(F))
+                break;
+            lo = hi;
+            hi *= 2.0;
+        }
+    } else {
+        hi = 0.0;
+        lo = s;
+        for (int k = 0; k < 200; ++k) {
+            gfun(beta, lo, G);
+            double F = r0 * lo + eta0 * G[2] + zeta0 * G[3] - tau;
+            if (F <= 0.0 || !isfinite(F))
+                break;
+            hi = lo;
+            lo *= 2.0;
+        }
+    }
+    if (!(s > lo && s < hi))
+        s = 0.5 * (lo + hi);
+
+    const double tol = 4.0 * (0.5 * DBL_EPSILON);   /* 4u */
+    int ok = 0;
+    for (int it = 0; it < 100; ++it) {
+        gfun(beta, s, G);
+        double F = r0 * s + eta0 * G[2] + zeta0 * G[3] - tau;
+        double dF = r0 + eta0 * G[1] + zeta0 * G[2];   /* = r(s) */
+        if (F == 0.0) {
+            ok = 1;
+            break;
+        }
+        if (F < 0.0)
+            lo = s;
+        else
+            hi = s;
+        double sn = (isfinite(F) && dF > 0.0) ? s - F / dF : 0.5 * (lo + hi);
+        if (!(sn > lo && sn < hi))
+            sn = 0.5 * (lo + hi);             /* bisection fallback */
+        double ds = sn - s;
+        s = sn;
+        if (fabs(ds) <= tol * fabs(s) || (hi - lo) <= tol * fabs(s)) {
+            ok = 1;
+            break;
+        }
+    }
+    if (!ok)
+        return 1;
+
+    gfun(beta, s, G);
+    double r = r0 + eta0 * G[1] + zeta0 * G[2];
+    double f = 1.0 - mu * G[2] / r0;
+    double g = tau - mu * G[3];
+    double fd = -mu * G[1] / (r * r0);
+    double gd = 1.0 - mu * G[2] / r;
+    double qn[3], vn[3];
+    for (int k = 0; k < 3; ++k) {
+        qn[k] = f * q[k] + g * v[k];
+        vn[k] = fd * q[k] + gd * v[k];
+    }
+    if (!isfinite(qn[0] + qn[1] + qn[2] + vn[0] + vn[1] + vn[2]))
+        return 1;
+    memcpy(q, qn, sizeof qn);
+    memcpy(v, vn, sizeof vn);
+    return 0;
+}
+
+/* Drift every body of a system; returns the number of failures and sets
+ * flag[i] = 1 for each (those bodies keep their pre-drift state). */
+int orc_drift(int n, double mu, double tau, double *Q, double *V, int32_t *flag)
+{
+    int nfail = 0;
+    for (int i = 0; i < n; ++i) {
+        int f = orc_kepler_drift(mu, tau, Q + 3 * i, V + 3 * i);
+        if (flag)
+            flag[i] = f;
+        nfail += f;
+    }
+    return nfail;
+}
+
+/* ------------------------------------------------------------------ */
+/* Close-encounter predicate (Sec. 3.1, encounter block).  Reading: the  */
+/* squared separation d2(s), s in [0,1] over the step, is the cubic       */
+/* Hermite interpolant through f0 = |dQ0|^2, f1 = |dQ1|^2 with slopes      */
+/* g0 = 2 tau dQ0.dV0, g1 = 2 tau dQ1.dV1 (d = body j minus body i); its   */
+/* minimum over [0,1], clamped at 0, is the pair's minimum separation      */
+/* squared.  A pair i<j is flagged iff that minimum <= rc_ij^2 with        */
+/* rc_ij = max(rc_i, rc_j).                                                 */
+/* ------------------------------------------------------------------ */
+double orc_pair_min_d2(double tau, const double *q0i, const double *v0i, const double *q1i,
+                       const double *v1i, const double *q0j, const double *v0j,
+                       const double *q1j, const double *v1j)
+{
+    double d0[3], e0[3], d1[3], e1[3];
+    for (int k = 0; k < 3; ++k) {
+        d0[k] = q0j[k] - q0i[k];
+        e0[k] = v0j[k] - v0i[k];
+        d1[k] = q1j[k] - q1i[k];
+        e1[k] = v1j[k] - v1i[k];
+    }
+    double f0 = d0[0] * d0[0] + d0[1] * d0[1] + d0[2] * d0[2];
+    double f1 = d1[0] * d1[0] + d1[1] * d1[1] + d1[2] * d1[2];
+    double g0 = 2.0 * tau * (d0[0] * e0[0] + d0[1] * e0[1] + d0[2] * e0[2]);
+    double g1 = 2.0 * tau * (d1[0] * e1[0] + d1[1] * e1[1] + d1[2] * e1[2]);
+    /* power-basis coefficients of the Hermite cubic */
+    double c0 = f0, c1 = g0;
+    double c2 = -3.0 * f0 - 2.0 * g0 + 3.0 * f1 - g1;
+    double c3 = 2.0 * f0 + g0 - 2.0 * f1 + g1;
+    double fmin = f0 < f1 ? f0 : f1;
+    /* stationary points: 3 c3 s^2 + 2 c2 s + c1 = 0 */
+    double A = 3.0 * c3, B = 2.0 * c2, C = c1;
+    double roots[2];
+    int nr = 0;
+    if (A == 0.0) {
+        if (B != 0.0)
+            roots[nr++] = -C / B;
+    } else {
+        double disc = B * B - 4.0 * A * C;
+        if (disc >= 0.0) {
+            double sq = sqrt(disc);
+            double qq = -0.5 * (B + (B >= 0.0 ? sq : -sq));
+            if (qq != 0.0) {
+                roots[nr++] = qq / A;
+                roots[nr++] = C / qq;
+            } else {
+                roots[nr++] = 0.0;
+            }
+        }
+    }
+    for (int k = 0; k < nr; ++k) {
+        double s = roots[k];
+        if (s > 0.0 && s < 1.0) {
+            double fs = c0 + s * (c1 + s * (c2 + s * c3));
+            if (fs < fmin)
+                fmin = fs;
+        }
+    }
+    return fmin > 0.0 ? fmin : 0.0;
+}
+
+/* All unordered pairs i<j of one system.  Flagged pairs go to (ice, jce) in
+ * (i, j) lexicographic order (up to cap entries; the true count is returned
+ * in *nce); ce[i] = ce[j] = 2 for flagged bodies, 0 otherwise.  Pairs whose
+ * minimum lies within tie*rc_ij^2 of the threshold are reported in
+ * (tie_i, tie_j) (up to tie_cap; true count in *ntie). */
+void orc_encounters(int n, double tau, const double *Q0, const double *V0, const double *Q1,
+                    const double *V1, const double *rc, int cap, int32_t *ice, int32_t *jce,
+                    int32_t *ce, int *nce, double tie, int tie_cap, int32_t *tie_i,
+                    int32_t *tie_j, int *ntie)
+{
+    int cnt = 0, tcnt = 0;
+    for (int i = 0; i < n; ++i)
+        ce[i] = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = i + 1; j < n; ++j) {
+            double d2 = orc_pair_min_d2(tau, Q0 + 3 * i, V0 + 3 * i, Q1 + 3 * i, V1 + 3 * i,
+                                        Q0 + 3 * j, V0 + 3 * j, Q1 + 3 * j, V1 + 3 * j);
+            double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
+            double thr = rcij * rcij;
+            if (d2 <= thr) {
+                if (cnt < cap) {
+                    ice[cnt] = i;
+                    jce[cnt] = j;
+                }
+                ++cnt;
+                ce[i] = 2;
+                ce[j] = 2;
+            }
+            if (fabs(d2 - thr) <= tie * thr) {
+                if (tcnt < tie_cap) {
+                    tie_i[tcnt] = i;
+                    tie_j[tcnt] = j;
+                }
+                ++tcnt;
+            }
+        }
+    }
+    *nce = cnt;
+    *ntie = tcnt;
+}
+
+/* ------------------------------------------------------------------ */
+/* Energy, angular momentum and stellar momentum (Sec. 2.1.1, energy    */
+/* and momentum routine).  In DH variables:                              */
+/*  E  = sum m|V|^2/2 + |P|^2/(2 m0) - sum G m0 m_i/|Q_i|                  */
+/*       - sum_{i<j} G m_i m_j / r_ij                                      */
+/*  EK = the same with each pair term weighted by K(r_ij; rc_ij)          */
+/*  L  = sum m_i Q_i x V_i,   P = sum m_i V_i                              */
+/* ------------------------------------------------------------------ */
+void orc_energy(int n, double G, double m0, double inner, const double *m, const double *Q,
+                const double *V, const double *rc, double *E, double *EK, double *L, double *P)
+{
+    nsum kin = {0, 0}, star = {0, 0}, pair = {0, 0}, pairk = {0, 0};
+    nsum lx = {0, 0}, ly = {0, 0}, lz = {0, 0};
+    orc_momentum(n, m, V, P);
+    for (int i = 0; i < n; ++i) {
+        const double *q = Q + 3 * i, *v = V + 3 * i;
+        ns_add(&kin, 0.5 * m[i] * (v[0] * v[0] + v[1] * v[1] + v[2] * v[2]));
+        double r = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        ns_add(&star, -G * m0 * m[i] / r);
+        ns_add(&lx, m[i] * (q[1] * v[2] - q[2] * v[1]));
+        ns_add(&ly, m[i] * (q[2] * v[0] - q[0] * v[2]));
+        ns_add(&lz, m[i] * (q[0] * v[1] - q[1] * v[0]));
+    }
+    for (int i = 0; i < n; ++i) {
+        for (int j = i + 1; j < n; ++j) {
+            double dx = Q[3 * j] - Q[3 * i];
+            double dy = Q[3 * j + 1] - Q[3 * i + 1];
+            double dz = Q[3 * j + 2] - Q[3 * i + 2];
+            double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (r == 0.0)
+                continue;
+            double u = -G * m[i] * m[j] / r;
+            double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
+            double K, dK;
+            orc_changeover(r, rcij, inner, &K, &dK);
+            ns_add(&pair, u);
+            ns_add(&pairk, K * u);
+        }
+    }
+    double sun = (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]) / (2.0 * m0);
+    nsum e = kin;
+    ns_add(&e, star.s);
+    ns_add(&e, star.c);
+    ns_add(&e, sun);
+    nsum ek = e;
+    ns_add(&e, pair.s);
+    ns_add(&e, pair.c);
+    ns_add(&ek, pairk.s);
+    ns_add(&ek, pairk.c);
+    *E = ns_val(&e);
+    *EK = ns_val(&ek);
+    L[0] = ns_val(&lx);
+    L[1] = ns_val(&ly);
+    L[2] = ns_val(&lz);
+}
+
+/* ------------------------------------------------------------------ */
+/* Aerodynamic gas drag (Sec. 2.1 names it; the disk model itself is    */
+/* not in the paper).  PARITY UNPINNED BY THE PAPER.  Reading: quadratic */
+/* drag a = -k |u| u with u = v_helio - v_gas, k = 3 C_D rho_g/(8 rho_p s),*/
+/* s = (3 m/(4 pi rho_p))^(1/3); rho_g = Sigma(R)/(sqrt(2 pi) H)           */
+/* exp(-z^2/(2H^2)), Sigma(R) = sigma0 (R/1)^-1, H = h R;                   */
+/* v_gas = sqrt(1 - 3 h^2) sqrt(G m0/R) phi_hat (R cylindrical).            */
+/* ------------------------------------------------------------------ */
+void orc_drag_accel(int n, double G, double m0, const double *m, const double *Q,
+                    const double *V, const double *P, double sigma0, double h, double cd,
+                    double rho_p, double *ad)
+{
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i) {
+        const double *q = Q + 3 * i;
+        double vh[3];
+        for (int k = 0; k < 3; ++k)
+            vh[k] = V[3 * i + k] + P[k] / m0;
+        double R = sqrt(q[0] * q[0] + q[1] * q[1]);
+        double H = h * R;
+        double sig = sigma0 / R;
+        double rho = sig / (sqrt(2.0 * pi) * H) * exp(-q[2] * q[2] / (2.0 * H * H));
+        double vk = sqrt(G * m0 / R) * sqrt(1.0 - 3.0 * h * h);
+        double vg[3] = {-vk * q[1] / R, vk * q[0] / R, 0.0};
+        double u[3] = {vh[0] - vg[0], vh[1] - vg[1], vh[2] - vg[2]};
+        double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+        double s = cbrt(3.0 * m[i] / (4.0 * pi * rho_p));
+        double k = (m[i] > 0.0 && sigma0 > 0.0) ? 3.0 * cd * rho / (8.0 * rho_p * s) : 0.0;
+        for (int c = 0; c < 3; ++c)
+            ad[3 * i + c] = -k * um * u[c];
+    }
+}
+
+/* Kick including drag evaluated with the current velocities. */
+void orc_kick_drag(int n, double h, double G, double m0, const double *m, const double *Q,
+                   const double *a, double *V, double sigma0, double hr, double cd, double rho_p,
+                   double *scratch /* 3n */)
+{
+    double P[3];
+    orc_momentum(n, m, V, P);
+    orc_drag_accel(n, G, m0, m, Q, V, P, sigma0, hr, cd, rho_p, scratch);
+    for (int k = 0; k < 3 * n; ++k)
+        V[k] += h * (a[k] + scratch[k]);
+}
+
+/* ------------------------------------------------------------------ */
+/* One hybrid step of one system in hot-path mode (no close-encounter    */
+/* resolution): K(h) S(h) D(tau) C S(h) [rc, force] K(h), h = tau/2.     */
+/* On entry a and rc hold the force and critical radii at the current Q   */
+/* (first-same-as-last); on exit they hold those at the new Q.            */
+/* Q0, V0 receive the pre-drift copies; the encounter outputs are those    */
+/* of orc_encounters.  Returns the number of Kepler failures.              */
+/* ------------------------------------------------------------------ */
+int orc_step(int n, double G, double m0, double n_hill, double inner, const double *m,
+             double *Q, double *V, double *a, double *rc, double tau, int drag, double sigma0,
+             double hr, double cd, double rho_p, double *Q0, double *V0, int32_t *kflag,
+             double *scratch, int cap, int32_t *ice, int32_t *jce, int32_t *ce, int *nce)
+{
+    double h = 0.5 * tau;
+    if (drag)
+        orc_kick_drag(n, h, G, m0, m, Q, a, V, sigma0, hr, cd, rho_p, scratch);
+    else
+        orc_kick(n, h, a, V);
+    orc_sun_drift(n, h, m0, m, V, Q);
+    memcpy(Q0, Q, sizeof(double) * 3 * n);
+    memcpy(V0, V, sizeof(double) * 3 * n);
+    int nfail = orc_drift(n, G * m0, tau, Q, V, kflag);
+    int ntie = 0;
+    int32_t ti = 0, tj = 0;
+    orc_encounters(n, tau, Q0, V0, Q, V, rc, cap, ice, jce, ce, nce, 0.0, 0, &ti, &tj, &ntie);
+    orc_sun_drift(n, h, m0, m, V, Q);
+    orc_rcrit(n, m0, m, Q, n_hill, rc);
+    orc_force(n, G, inner, m, Q, rc, a);
+    if (drag)
+        orc_kick_drag(n, h, G, m0, m, Q, a, V, sigma0, hr, cd, rho_p, scratch);
+    else
+        orc_kick(n, h, a, V);
+    return nfail;
+}

@@ -1,0 +1,181 @@
+"""Pins for the oracle's hybrid step (Sec. 2.1.1 and the Hamiltonian, drift and
+force blocks of Sec. 3.1), in hot-path mode (encounters flagged, not resolved).
+
+Pins: angular momentum conserved to roundoff (each sub-step conserves it);
+time reversibility; second-order convergence to the exact two-body orbit;
+the two-body energy test of Sec. 4.2 (energy held within a few 1e-13 over
+1e5 yr for an e = 0.22 orbit) in the small-mass limit; bounded, non-secular
+energy error for the widely spaced ten-body test of Sec. 4.2.
+"""
+import ctypes
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads
+
+U = 2.0 ** -53
+G = workloads.G_AU_MSUN_YR
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_numbers.json")
+
+
+def _one_body_state(m1, a, e, M=0.3):
+    mu = G * (1.0 + m1)
+    x, v = workloads.elements_to_cartesian([mu], [a], [e], [0.1], [0.4], [1.3], [M])
+    return x, v
+
+
+class _Runner:
+    """Direct C-loop driver for long single-system runs."""
+
+    def __init__(self, orc, m0, m, x, v, prm):
+        from oracle import _ptr
+        self.orc, self.p, self._ptr = orc, prm, _ptr
+        self.m0 = float(m0)
+        self.m = np.ascontiguousarray(m, dtype=np.float64)
+        n = len(self.m)
+        self.Q, self.V = orc.helio_to_dh(m0, self.m, x, v)
+        self.rc = orc.rcrit(m0, self.m, self.Q, prm.n_hill)
+        self.a = orc.force(self.m, self.Q, self.rc, prm.G, prm.inner)
+        self.Q0 = np.empty_like(self.Q); self.V0 = np.empty_like(self.V)
+        self.kf = np.zeros(n, np.int32); self.ce = np.zeros(n, np.int32)
+        self.scr = np.empty_like(self.Q)
+        self.ice = np.zeros(max(n * n, 1), np.int32); self.jce = np.zeros(max(n * n, 1), np.int32)
+        self.nce = ctypes.c_int()
+        self.n = n
+
+    def step(self, tau, k=1):
+        L = self.orc.lib(); p = self.p; P = self._ptr
+        args = (self.n, p.G, self.m0, p.n_hill, p.inner, P(self.m), P(self.Q), P(self.V), P(self.a), P(self.rc),
+                float(tau), int(p.drag), p.sigma0, p.h, p.cd, p.rho_p, P(self.Q0), P(self.V0), P(self.kf),
+                P(self.scr), len(self.ice), P(self.ice), P(self.jce), P(self.ce), ctypes.byref(self.nce))
+        f = 0
+        for _ in range(k):
+            f += L.orc_step(*args)
+        return f
+
+    def energy(self):
+        return self.orc.energy(self.p.G, self.m0, self.m, self.Q, self.V, self.rc, self.p.inner)
+
+
+def test_angular_momentum_conserved(orc):
+    w = workloads.c1(100)
+    st = orc.State.from_workload(w)
+    L0 = st.energy()[0]["L"]
+    for _ in range(200):
+        st.step(w.dt)
+    L1 = st.energy()[0]["L"]
+    assert np.max(np.abs(L1 - L0)) <= 200 * 8 * U * np.linalg.norm(L0)
+
+
+def test_time_reversibility(orc):
+    w = workloads.c1(60)
+    st = orc.State.from_workload(w)
+    Q0, V0 = st.Q.copy(), st.V.copy()
+    for _ in range(50):
+        st.step(w.dt)
+    moved = np.max(np.abs(st.Q - Q0))
+    for _ in range(50):
+        st.step(-w.dt)
+    assert moved > 0.1
+    assert np.max(np.abs(st.Q - Q0)) <= 1e-12 * np.max(np.abs(Q0))
+    assert np.max(np.abs(st.V - V0)) <= 1e-12 * np.max(np.abs(V0))
+
+
+def test_second_order_convergence_two_body(orc):
+    """N = 1: the DH split S(h) D(tau) S(h) converges at second order to the
+    exact relative orbit, which is Kepler's with mu = G (m0 + m1)."""
+    import test_oracle_drift as td
+    m1 = 1e-3
+    x, v = _one_body_state(m1, 1.0, 0.1)
+    P = 2 * math.pi / math.sqrt(G * (1 + m1))
+    T = 2.0 * P
+    errs = []
+    for k in (40, 80, 160):
+        tau = T / k
+        st = orc.State([0, 1], [1.0], [m1], x, v, orc.Params(G=G))
+        for _ in range(k):
+            st.step(tau)
+        xh, vh = st.helio()
+        qe, ve = td.classical_drift(G * (1 + m1), T, x[0], v[0])
+        errs.append(np.linalg.norm(xh[0] - qe))
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.6 < r1 < 4.4 and 3.6 < r2 < 4.4, errs
+
+
+def test_energy_error_scales_as_tau_squared(orc):
+    """Finite planet mass: the energy oscillation of the DH split is O(tau^2)."""
+    m1 = workloads.M_JUPITER
+    x, v = _one_body_state(m1, 5.2, 0.22)
+    P = 2 * math.pi * math.sqrt(5.2 ** 3 / (G * (1 + m1)))
+    amp = []
+    for k in (50, 100):
+        r = _Runner(orc, 1.0, [m1], x, v, orc.Params(G=G))
+        E0 = r.energy()["E"]
+        worst = 0.0
+        for _ in range(3 * k):
+            r.step(P / k)
+            worst = max(worst, abs(r.energy()["E"] - E0) / abs(E0))
+        amp.append(worst)
+    assert 3.5 < amp[0] / amp[1] < 4.5, amp
+
+
+def test_two_body_energy_small_mass_limit(orc):
+    """Sec. 4.2 two-body test: e = 0.22, 1e5 yr, energy within a few 1e-13.
+    In the m1 -> 0 limit the splitting error vanishes and only roundoff is left."""
+    paper = json.load(open(GOLDEN))["two_body_energy"]
+    m1 = 1e-12
+    x, v = _one_body_state(m1, 5.2, paper["e"])
+    P = 2 * math.pi * math.sqrt(5.2 ** 3 / (G * (1 + m1)))
+    # About P/20 but incommensurate with the period: a step that is an exact
+    # fraction of P samples the same orbital phases every orbit, so rounding
+    # repeats and the energy drifts linearly (a step-size resonance).
+    tau = P / (20.0 * math.sqrt(1.07))
+    nsteps = int(paper["years"] / tau)
+    r = _Runner(orc, 1.0, [m1], x, v, orc.Params(G=G))
+    E0 = r.energy()["E"]
+    worst = 0.0
+    chunk = nsteps // 100
+    for _ in range(100):
+        assert r.step(tau, chunk) == 0
+        worst = max(worst, abs(r.energy()["E"] - E0) / abs(E0))
+    assert worst <= paper["abs_dE_over_E_max"], worst
+
+
+def test_widely_spaced_ten_body_energy_bounded(orc):
+    """Sec. 4.2 ten-body test: widely spaced Mars-mass bodies on circular
+    orbits; the energy error is bounded and shows no secular growth."""
+    mars = 0.107 * workloads.M_EARTH
+    n = 10
+    a = 1.0 + 0.3 * np.arange(n)
+    M = np.random.default_rng(1).uniform(0, 2 * np.pi, n)
+    x, v = workloads.elements_to_cartesian(G * (1 + mars) * np.ones(n), a, np.zeros(n), np.zeros(n),
+                                           np.zeros(n), np.zeros(n), M)
+    r = _Runner(orc, 1.0, np.full(n, mars), x, v, orc.Params(G=G))
+    E0 = r.energy()["E"]
+    dE = []
+    for _ in range(100):
+        r.step(0.05, 100)
+        dE.append(abs(r.energy()["E"] - E0) / abs(E0))
+    first, second = max(dE[:50]), max(dE[50:])
+    assert max(dE) < 1e-7
+    assert second <= 2.0 * first, (first, second)
+
+
+def test_encounters_reported_per_step(orc):
+    """A dense ring produces flagged pairs; every flagged pair is within one
+    system, ordered i<j, and both bodies carry flag 2."""
+    w = workloads.ring(200, m=1e-8)
+    st = orc.State.from_workload(w)
+    total = 0
+    for _ in range(5):
+        st.step(w.dt)
+        nce, ice, jce = st.enc[0]
+        total += nce
+        assert np.all(ice < jce)
+        flagged = set(ice.tolist()) | set(jce.tolist())
+        assert set(np.nonzero(st.ce == 2)[0].tolist()) == flagged
+    assert total > 0
