@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Benchmark of the hybrid-step hot path on one MI355X.
+
+Workload: 16384 equal-mass planetesimals (10 Earth masses in total) in a
+0.5-5 AU annulus around a solar-mass star, e ~ Rayleigh(0.01),
+i ~ Rayleigh(0.005), dt = 0.0175 yr; synthetic and seeded.
+
+A step is one whole hybrid step K S D C S F K (kick, stellar drift, Kepler
+drift, encounter check, stellar drift, critical radii + force, kick) of that
+system, replayed from a captured HIP graph; the state stays resident in HBM.
+Prints one JSON line: Gpair/s = N(N-1) x steps / wall time of the timed steps
+(FP32C pair arithmetic as the headline, FP64 alongside), steps/s, the force
+kernel against its roofline, and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pair interactions/sec (Gpair/s) + steps/sec at N=16384, FP32-comp vs FP64"
+FLOPS_PER_PAIR = 20          # direct-summation convention (see the design notes)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}   # MI355X vector FP64 / FP32 (published)
+KERNEL_SRC = os.path.join(ROOT, "paper_2601_19654_amd", "csrc", "nb_kernels.hip")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profiles(mode: str):
+    """HBM bytes per force launch from a committed rocprofv3 PMC summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"force_{mode}_c3_n16384_pmc.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m = re.search(r"kernel_source_sha256_16:\s*([0-9a-f]{16})", txt)
+    t = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    if not m or not t or m.group(1) != kernel_hash():
+        return None
+    return float(t.group(1))
+
+
+def run_mode(w, mode: str, steps: int, warmup: int, torch, nb):
+    p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64)
+    ctx = nb.Context(w.off, p, enc_cap=1 << 16, device="cuda:0")
+    ctx.upload(w.m0, w.m, w.x, w.v)
+    n = w.ntot
+    pairs = n * (n - 1)
+    # warmup (untimed), also builds the step graph
+    if warmup > 0:
+        ctx.step_async(w.dt, warmup)
+    # timed region: exactly `steps` steps of one nb_step call
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(ctx.stream)
+    stats = ctx.step(w.dt, steps, allow=(nb.NB_E_CAPACITY, nb.NB_E_KEPLER))
+    ev1.record(ctx.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    dev_ms = ev0.elapsed_time(ev1)
+    # per-kernel timing with HIP events on the context's stream
+    force_ms = ctx.time_kernel(nb.NB_K_FORCE, reps=20)
+    enc_ms = ctx.time_kernel(nb.NB_K_ENCOUNTER, reps=10)
+    a_gpu = ctx.accel()
+    x, v = ctx.download(nb.NB_DH)
+    ctx.close()
+    return {
+        "wall_s": wall, "device_ms": dev_ms, "ms_per_step": 1e3 * wall / steps,
+        "gpair_s": pairs * steps / wall / 1e9, "steps_per_s": steps / wall,
+        "force_ms": force_ms, "encounter_ms": enc_ms, "stats": stats,
+        "a": a_gpu, "Q": x,
+    }
+
+
+def roofline(mode, n, force_ms):
+    flops = FLOPS_PER_PAIR * n * (n - 1)
+    achieved = flops / (force_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[mode]
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(mode),
+            "kernel": f"k_force{'32c' if mode == 'fp32c' else '64'}",
+            "kernel_ms": round(force_ms, 4), "flops_per_launch": flops,
+            "flop_convention": f"{FLOPS_PER_PAIR} flops per ordered pair"}
+
+
+def accel_error(w, a_gpu, Q, sample=64, seed=1):
+    """Max |a_gpu - a_oracle| / A_i over a sample of targets (CPU oracle)."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(w.ntot, sample, replace=False))
+    rc = oracle.rcrit(w.m0[0], w.m, Q)
+    ref = oracle.force_subset(w.m, Q, rc, w.G, idx)
+    d = Q[None, :, :] - Q[idx, None, :]
+    r2 = np.einsum("ijk,ijk->ij", d, d)
+    r2[np.arange(len(idx)), idx] = np.inf
+    A = np.sum(w.G * w.m[None, :] / r2, axis=1)
+    return float(np.max(np.max(np.abs(a_gpu[idx] - ref), axis=1) / A))
+
+
+def cpu_baseline(w):
+    """One full hybrid step of the same workload by the CPU oracle (1 thread)."""
+    import oracle
+    oracle.build(force=False)
+    st = oracle.State.from_workload(w)      # includes the first force evaluation
+    t0 = time.perf_counter()
+    st.step(w.dt)
+    dt = time.perf_counter() - t0
+    n = w.ntot
+    return {"value": round(n * (n - 1) / dt / 1e9, 5), "unit": "Gpair/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 full hybrid step of the N={n} workload (FP64, serial), {dt:.2f} s",
+            "steps_per_s": round(1.0 / dt, 5)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--modes", default="fp32c,fp64")
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 256 MiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design note, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2601_19654_amd import nb
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    nb.lib()
+
+    w = workloads.c3(args.n)
+    modes = [m for m in args.modes.split(",") if m]
+    res = {}
+    for mode in modes:
+        print(f"[bench] mode {mode}: N={w.ntot}, warmup {args.warmup}, steps {args.steps}",
+              file=sys.stderr, flush=True)
+        res[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb)
+        print(f"[bench] mode {mode}: {res[mode]['ms_per_step']:.4f} ms/step, "
+              f"force {res[mode]['force_ms']:.4f} ms, encounter {res[mode]['encounter_ms']:.4f} ms",
+              file=sys.stderr, flush=True)
+    if args.copy_probe:
+        src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    head = "fp32c" if "fp32c" in res else modes[0]
+    r = res[head]
+    n = w.ntot
+    out = {
+        "metric": METRIC, "value": round(r["gpair_s"], 3), "unit": "Gpair/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(r["ms_per_step"], 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "fp32c" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"c3: star + {n} equal-mass planetesimals (10 Earth masses), "
+                               "a 0.5-5 AU, e,i Rayleigh 0.01/0.005, dt 0.0175 yr",
+                   "n_bodies": n, "pairs_per_step": n * (n - 1), "mode": head,
+                   "parallelism": "single GPU"},
+        "steps_per_s": round(r["steps_per_s"], 3),
+    }
+    for mode, rr in res.items():
+        out[mode] = {"gpair_s": round(rr["gpair_s"], 3), "steps_per_s": round(rr["steps_per_s"], 3),
+                     "ms_per_step": round(rr["ms_per_step"], 5),
+                     "force_kernel_ms": round(rr["force_ms"], 5),
+                     "encounter_kernel_ms": round(rr["encounter_ms"], 5),
+                     "force_gpair_s": round(n * (n - 1) / (rr["force_ms"] * 1e-3) / 1e9, 2),
+                     "nce_per_step": rr["stats"]["total_nce"] / args.steps,
+                     "accel_err_vs_oracle": accel_error(w, rr["a"], rr["Q"])}
+    out["roofline"] = roofline(head, n, r["force_ms"])
+    if "fp64" in res and head != "fp64":
+        out["roofline_fp64"] = roofline("fp64", n, res["fp64"]["force_ms"])
+    out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w)
+    out["kernel_source_sha256_16"] = kernel_hash()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * nb.h -- C ABI of the MI355X hot path of a Mercury-style hybrid symplectic
+ * N-body step (Mercury-Opal, arXiv 2601.19654).
+ *
+ * What one step computes, in democratic-heliocentric (DH) variables: heliocentric
+ * positions Q and barycentric velocities V of the bodies; the star of each
+ * system sits outside the body arrays with mass m0 (the paper's index 1, Sec. 3.1):
+ *
+ *   K(h)   V += h a                              interaction kick  (Sec. 3.1, Hamiltonian block, loop 1)
+ *   S(h)   Q += h P/m0,  P = sum m V              stellar motion     (Hamiltonian block, loops 2-3)
+ *   D(dt)  (Q0,V0) <- (Q,V); Kepler flow about    Kepler drift       (Sec. 2.1, Sec. 3.1 drift block)
+ *          the star, mu = G m0, for time dt
+ *   C      flag pairs i<j whose minimum           encounter check    (Sec. 3.1, encounter block)
+ *          separation over the step <= rc_ij
+ *   S(h)
+ *   rc_i = n_hill |Q_i| (m_i/(3 m0))^(1/3)        critical radius    (Sec. 2.1.1, Hill radius footnotes)
+ *   a_i  = sum_j G m_j w(r_ij)(Q_j - Q_i)          interaction force  (Sec. 3.1, force block, loop 2)
+ *          w = K/r^3 - (dK/dr)/r^2, rc_ij = max(rc_i, rc_j), K the changeover function
+ *   K(h)                                           h = dt/2
+ *
+ * Conventions
+ *  - Every call returns NB_OK (0) or a negative NB_E_* code; nothing throws or
+ *    aborts across the ABI.  nb_strerror() names a code; nb_last_error() gives the
+ *    context's last message.
+ *  - Bodies of all systems are stored back to back: system s owns global indices
+ *    off[s] .. off[s+1]-1.  Indices are 0-based.
+ *  - Vector arrays at the boundary are plane-major (SoA): x[c*ntot + i] is
+ *    component c (0,1,2 = x,y,z) of body i.
+ *  - Calls enqueue work on the context's HIP stream and are asynchronous, except
+ *    those that return host-visible values (counts, diagnostics, host copies),
+ *    which synchronize that stream before returning.
+ *  - One context is used by one host thread at a time.
+ *  - The library never allocates device memory: the caller allocates the
+ *    workspace (size from nb_workspace_size) and keeps it alive until nb_destroy.
+ *    Host pointers passed in are read or written before the call returns.
+ *  - Units are the caller's; G is a parameter.  The tests use AU, Msun, yr.
+ */
+#ifndef NB_H
+#define NB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NB_VERSION_MAJOR 0
+#define NB_VERSION_MINOR 1
+
+/* status codes */
+#define NB_OK            0
+#define NB_E_INVALID    -1   /* bad argument, size or layout */
+#define NB_E_NOT_READY  -2   /* no state uploaded yet, or no drift before nb_encounters */
+#define NB_E_HIP        -3   /* HIP runtime error; nb_last_error() has its text */
+#define NB_E_NONFINITE  -4   /* NaN/Inf (or a negative mass, a non-positive m0) in an upload */
+#define NB_E_CAPACITY   -5   /* encounter list overflow: the true count is still reported */
+#define NB_E_KEPLER     -6   /* >= 1 body failed to converge in the Kepler solve; those
+                                bodies keep their pre-drift state, the rest are drifted */
+#define NB_E_WORKSPACE  -7   /* workspace smaller than nb_workspace_size() or not 256-B aligned */
+
+/* pair arithmetic of the force kernel */
+#define NB_FP64   0   /* FP64 pair terms */
+#define NB_FP32C  1   /* FP32 pair terms from hi/lo split positions with compensated
+                         accumulation; pairs near the changeover zone in FP64 */
+
+/* frames */
+#define NB_HELIO  0   /* heliocentric positions and velocities */
+#define NB_DH     1   /* heliocentric positions, barycentric velocities */
+
+/* pointer kinds */
+#define NB_HOST   0
+#define NB_DEVICE 1
+
+typedef struct nb_ctx nb_ctx;
+
+typedef struct nb_params {
+    double  G;            /* gravitational constant */
+    double  n_hill;       /* critical radius in Hill radii (3) */
+    double  chg_inner;    /* inner edge of the changeover zone as a fraction of rc (0.1) */
+    int32_t mode;         /* NB_FP64 or NB_FP32C */
+    int32_t drag;         /* 0: no gas drag; 1: quadratic gas drag in every kick */
+    double  drag_sigma0;  /* gas surface density at R = 1 (mass / length^2) */
+    double  drag_h;       /* disk aspect ratio H/R */
+    double  drag_cd;      /* drag coefficient */
+    double  drag_rho_p;   /* bulk density of the bodies (mass / length^3) */
+    int32_t force_jchunk; /* sources per force work item (0: tuned default) */
+    int32_t force_r;      /* targets per lane in the force kernel: 1, 2 or 4 (0: default) */
+    int32_t enc_jchunk;   /* sources per encounter work item (0: default) */
+    int32_t reserved[5];
+} nb_params;
+
+typedef struct nb_stats {
+    int64_t total_nce;      /* flagged pairs summed over the steps */
+    int32_t max_nce;        /* largest per-step count */
+    int32_t overflow_steps; /* steps whose count exceeded the list capacity */
+    int64_t kepler_fail;    /* failed Kepler solves summed over the steps */
+    int64_t near_pairs;     /* FP32C: pairs evaluated in FP64 near the changeover zone */
+} nb_stats;
+
+/* Library version. */
+int nb_version(int *major, int *minor);
+
+/* Static text for a status code. */
+const char *nb_strerror(int code);
+
+/* Fill p with the defaults used by the tests: G = (0.01720209895*365.25)^2
+ * (AU, Msun, yr), n_hill = 3, chg_inner = 0.1, NB_FP64, no drag, drag constants for
+ * Sigma(1 AU) = 1000 g/cm^2, h = 0.05, C_D = 1, rho_p = 2 g/cm^3 in those units. */
+void nb_default_params(nb_params *p);
+
+/* Bytes of device workspace a context needs for nsys systems with host offsets
+ * off[0..nsys] (off[0] = 0, non-decreasing) and an encounter list of enc_cap pairs. */
+int nb_workspace_size(const nb_params *p, int nsys, const int32_t *off, int enc_cap, size_t *bytes);
+
+/* Create a context on the current device.  workspace: device memory of at least
+ * nb_workspace_size() bytes, 256-byte aligned, owned by the caller.  stream: a
+ * hipStream_t (NULL = the null stream; nb_step then runs without a HIP graph). */
+int nb_create(const nb_params *p, int nsys, const int32_t *off, int enc_cap, void *workspace,
+              size_t bytes, void *stream, nb_ctx **out);
+
+/* Last error message of the context (empty if none). */
+const char *nb_last_error(const nb_ctx *ctx);
+
+/* Upload a state: m0[nsys], m[ntot], x[3*ntot], v[3*ntot] (plane-major), in frame
+ * NB_HELIO (converted to DH, Sec. 2.1.1 footnote) or NB_DH.  where: NB_HOST or
+ * NB_DEVICE for all four pointers.  Validates (finite, m >= 0, m0 > 0), then
+ * computes the critical radii and the force at the new state (first-same-as-last). */
+int nb_upload(nb_ctx *ctx, const double *m0, const double *m, const double *x,
+              const double *v, int frame, int where);
+
+/* Copy the state out: x, v plane-major [3*ntot] in frame NB_HELIO or NB_DH. */
+int nb_download(nb_ctx *ctx, double *x, double *v, int frame, int where);
+
+/* Recompute critical radii and the interaction acceleration a at the current Q. */
+int nb_force(nb_ctx *ctx);
+
+/* Interaction kick with the current a: V += h a (plus drag if enabled). */
+int nb_kick(nb_ctx *ctx, double h);
+
+/* Stellar-motion drift: Q += h P / m0 per system. */
+int nb_sun_drift(nb_ctx *ctx, double h);
+
+/* Snapshot (Q0,V0) <- (Q,V), then Kepler-drift every body for dt (dt may be
+ * negative: the integration direction).  *nfail (may be NULL) receives the number of
+ * bodies whose solve failed; returns NB_E_KEPLER if any did. */
+int nb_drift(nb_ctx *ctx, double dt, int *nfail);
+
+/* Encounter check on the last drift: pairs i<j of one system whose minimum
+ * separation between (Q0,V0) and (Q,V) is <= max(rc_i, rc_j).  Writes up to cap
+ * pairs to ice/jce (global indices, sorted by (i,j)) and per-body flags ce[ntot]
+ * (2 = in an encounter, else 0); *nce = the true count.  Any of ice/jce/ce may be
+ * NULL.  Returns NB_E_CAPACITY if the count exceeds cap or the context's list. */
+int nb_encounters(nb_ctx *ctx, int cap, int *nce, int32_t *ice, int32_t *jce, int32_t *ce,
+                  int where);
+
+/* Read the list of the last encounter check (by nb_encounters or the last step
+ * of nb_step) without recomputing it. */
+int nb_get_encounters(nb_ctx *ctx, int cap, int *nce, int32_t *ice, int32_t *jce, int32_t *ce,
+                      int where);
+
+/* nsteps hybrid steps K S D C S F K of every system (graph-captured when the
+ * stream is not NULL).  st (may be NULL) receives the run's statistics.
+ * Returns NB_E_KEPLER / NB_E_CAPACITY if any step had such an event; the state
+ * is still advanced. */
+int nb_step(nb_ctx *ctx, double dt, int nsteps, nb_stats *st);
+
+/* Per system s (host arrays): E[s] total energy, EK[s] the changeover-weighted
+ * energy the hot path conserves, L[3s..3s+2] = sum m Q x V, P[3s..3s+2] = sum m V.
+ * Any pointer may be NULL.  Returns NB_E_NONFINITE if a value is not finite. */
+int nb_diagnostics(nb_ctx *ctx, double *E, double *EK, double *L, double *P);
+
+/* Copy the last interaction acceleration a (G included, drag excluded), plane-major. */
+int nb_get_accel(nb_ctx *ctx, double *a, int where);
+
+/* Copy the current critical radii rc[ntot]. */
+int nb_get_rcrit(nb_ctx *ctx, double *rc, int where);
+
+/* Kernels that nb_time_kernel can time. */
+#define NB_K_FORCE      0   /* the pair force kernel (FP64 or FP32C per the mode) */
+#define NB_K_ENCOUNTER  1   /* the encounter check plus the list sort */
+#define NB_K_DRIFT      2   /* the Kepler drift */
+#define NB_K_STEP       3   /* one whole hybrid step (all kernels of nb_step) */
+
+/* Measurement helper: enqueue kernel `which` alone `reps` times on the context's
+ * stream between two HIP events (after one untimed launch) and return the mean
+ * duration per launch in milliseconds.  The state is used as it is; NB_K_DRIFT
+ * and NB_K_STEP advance it (by dt per launch, dt = last_dt or the argument). */
+int nb_time_kernel(nb_ctx *ctx, int which, int reps, double dt, double *ms_per_launch);
+
+/* Release the context (not the workspace). */
+int nb_destroy(nb_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NB_H */

@@ -57,6 +57,7 @@ def lib():
             "orc_changeover": (None, [d, d, d, p, p]),
             "orc_rcrit": (None, [i, d, p, p, d, p]),
             "orc_force": (None, [i, d, d, p, p, p, p]),
+            "orc_force_subset": (None, [i, d, d, p, p, p, i, p, p]),
             "orc_kick": (None, [i, d, p, p]),
             "orc_momentum": (None, [i, p, p, p]),
             "orc_sun_drift": (None, [i, d, d, p, p, p]),
@@ -67,6 +68,7 @@ def lib():
             "orc_drift": (i, [i, d, d, p, p, p]),
             "orc_pair_min_d2": (d, [d, p, p, p, p, p, p, p, p]),
             "orc_encounters": (None, [i, d, p, p, p, p, p, i, p, p, p, p, d, i, p, p, p]),
+            "orc_pair_scan": (None, [i, d, p, p, p, p, p, i, d, p, p]),
             "orc_energy": (None, [i, d, d, d, p, p, p, p, p, p, p, p]),
             "orc_drag_accel": (None, [i, d, d, p, p, p, p, d, d, d, d, p]),
             "orc_kick_drag": (None, [i, d, d, d, p, p, p, p, d, d, d, d, p]),
@@ -128,6 +130,15 @@ def rcrit(m0, m, Q, n_hill=3.0):
 def force(m, Q, rc, G, inner=0.1):
     m = _f64(m); Q = _f64(Q, (-1, 3)); rc = _f64(rc); a = np.empty_like(Q)
     lib().orc_force(len(m), float(G), float(inner), _ptr(m), _ptr(Q), _ptr(rc), _ptr(a))
+    return a
+
+
+def force_subset(m, Q, rc, G, idx, inner=0.1):
+    """Accelerations of the targets idx only (same definition as force)."""
+    m = _f64(m); Q = _f64(Q, (-1, 3)); rc = _f64(rc)
+    idx = np.ascontiguousarray(idx, dtype=np.int32); a = np.empty((len(idx), 3))
+    lib().orc_force_subset(len(m), float(G), float(inner), _ptr(m), _ptr(Q), _ptr(rc), len(idx),
+                           _ptr(idx), _ptr(a))
     return a
 
 
@@ -200,6 +211,16 @@ def encounters(tau, Q0, V0, Q1, V1, rc, cap=None, tie=1e-10):
     t = min(ntie.value, tie_cap)
     return {"nce": nce.value, "ice": ice[:k].copy(), "jce": jce[:k].copy(), "ce": ce[:n].copy(),
             "tie": set(zip(ti[:t].tolist(), tj[:t].tolist())), "ntie": ntie.value}
+
+
+def pair_scan(tau, Q0, V0, Q1, V1, rc, i, tie=1e-10):
+    """Flags of every pair (i, j) of one system under the encounter predicate."""
+    Q0, V0, Q1, V1 = (_f64(t, (-1, 3)) for t in (Q0, V0, Q1, V1))
+    rc = _f64(rc); n = len(rc)
+    flag = np.zeros(n, np.int32); tflag = np.zeros(n, np.int32)
+    lib().orc_pair_scan(n, float(tau), _ptr(Q0), _ptr(V0), _ptr(Q1), _ptr(V1), _ptr(rc), int(i),
+                        float(tie), _ptr(flag), _ptr(tflag))
+    return flag.astype(bool), tflag.astype(bool)
 
 
 def energy(G, m0, m, Q, V, rc, inner=0.1):

@@ -135,6 +135,39 @@ void orc_force(int n, double G, double inner, const double *m, const double *Q,
     }
 }
 
+/* The same sum for selected targets only (large-N sampled checks): a[k] is
+ * the acceleration of body idx[k]. */
+void orc_force_subset(int n, double G, double inner, const double *m, const double *Q,
+                      const double *rc, int k, const int32_t *idx, double *a)
+{
+    for (int t = 0; t < k; ++t) {
+        int i = idx[t];
+        nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+        for (int j = 0; j < n; ++j) {
+            if (j == i)
+                continue;
+            double dx = Q[3 * j] - Q[3 * i];
+            double dy = Q[3 * j + 1] - Q[3 * i + 1];
+            double dz = Q[3 * j + 2] - Q[3 * i + 2];
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 == 0.0)
+                continue;
+            double r = sqrt(r2);
+            double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
+            double K, dK;
+            orc_changeover(r, rcij, inner, &K, &dK);
+            double w = K / (r2 * r) - dK / r2;
+            double f = G * m[j] * w;
+            ns_add(&ax, f * dx);
+            ns_add(&ay, f * dy);
+            ns_add(&az, f * dz);
+        }
+        a[3 * t] = ns_val(&ax);
+        a[3 * t + 1] = ns_val(&ay);
+        a[3 * t + 2] = ns_val(&az);
+    }
+}
+
 /* Interaction kick (Sec. 3.1, Hamiltonian block loop 1): V += h a. */
 void orc_kick(int n, double h, const double *a, double *V)
 {
@@ -457,6 +490,28 @@ void orc_encounters(int n, double tau, const double *Q0, const double *V0, const
     }
     *nce = cnt;
     *ntie = tcnt;
+}
+
+/* One body i against every other body j of the system (large-N sampled
+ * checks): flag[j] = 1 if the pair (min(i,j), max(i,j)) is flagged by the same
+ * predicate, tie[j] = 1 if its minimum lies in the tie band. */
+void orc_pair_scan(int n, double tau, const double *Q0, const double *V0, const double *Q1,
+                   const double *V1, const double *rc, int i, double tie, int32_t *flag,
+                   int32_t *tieflag)
+{
+    for (int j = 0; j < n; ++j) {
+        flag[j] = 0;
+        tieflag[j] = 0;
+        if (j == i)
+            continue;
+        int a = i < j ? i : j, b = i < j ? j : i;
+        double d2 = orc_pair_min_d2(tau, Q0 + 3 * a, V0 + 3 * a, Q1 + 3 * a, V1 + 3 * a,
+                                    Q0 + 3 * b, V0 + 3 * b, Q1 + 3 * b, V1 + 3 * b);
+        double rcij = rc[a] > rc[b] ? rc[a] : rc[b];
+        double thr = rcij * rcij;
+        flag[j] = d2 <= thr;
+        tieflag[j] = fabs(d2 - thr) <= tie * thr;
+    }
 }
 
 /* ------------------------------------------------------------------ */

@@ -1,0 +1,96 @@
+// Internal layout shared by the device kernels (nb_kernels.hip) and the host
+// runtime (nb_runtime.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nb {
+
+constexpr int kBlock = 256;      // threads of every O(N) kernel and of the pair kernels
+
+// A block of an O(N) kernel: bodies [start, end) of one system (end - start <= kBlock).
+struct RBlk {
+    int sys, start, end, pad;
+};
+
+// A force work item: targets [i0, i0+ni), sources [j0, j0+nj) of one system;
+// the partial sum goes to split slot `slot`.
+struct FWork {
+    int i0, ni, j0, nj;
+    int slot, sys, pad0, pad1;
+};
+
+// An unordered-pair work item: targets [i0, i0+ni), sources [j0, j0+nj); only
+// pairs with j > i are visited.
+struct PWork {
+    int i0, ni, j0, nj;
+};
+
+// Device statistics block (one per context).
+struct DevStats {
+    long long total_nce;
+    long long kepler_fail;
+    long long near_pairs;
+    int max_nce;
+    int overflow_steps;
+    int cur_nce;      // count of the current encounter check
+    int cur_kfail;    // failures of the current drift
+    int pad[2];
+};
+
+// Device pointers of a context; every array lives in the caller's workspace.
+struct Dev {
+    int ntot, nsys;
+    // state planes (FP64, ntot each)
+    double *m, *qx, *qy, *qz, *vx, *vy, *vz;
+    double *ax, *ay, *az, *rc;
+    double *q0x, *q0y, *q0z, *v0x, *v0y, *v0z;
+    float4 *pk;           // FP32C source records: 2 per body {xhi,yhi,zhi,m},{xlo,ylo,zlo,rc2}
+    int *kflag, *ce, *sys_of;
+    double *m0;           // nsys
+    int *off;             // nsys+1
+    int *nsplit;          // nsys: force splits per system
+    int *rb_first, *rb_count;   // nsys: O(N) blocks of each system
+    // tables
+    RBlk *rblk;  int nrb;
+    FWork *fwork; int nfw; int maxs;
+    PWork *ework; int new_;
+    PWork *dwork; int ndw;
+    // scratch
+    double *rpart;        // nrb x 4: per-block partial sums (sum m v, or sum m v + sum m)
+    double *fpart;        // 3 x maxs x ntot force partials
+    double *dpart;        // ndw x 4 double-double pair sums (E pair, EK pair)
+    double *bpart;        // nrb x 16 body partial sums for diagnostics
+    double *diag;         // nsys x 8 results: E, EK, L3, P3
+    unsigned long long *keys;  int keys_p2;   // encounter keys (i<<32 | j), pow2 capacity
+    int enc_cap;
+    int *ice, *jce;       // sorted list (enc_cap)
+    DevStats *stats;
+    int *flag;            // validation flags (4 ints)
+    double *stage;        // 6 x ntot staging for host transfers / transforms
+};
+
+struct Params {
+    double G, n_hill, inner;
+    int mode, drag;
+    double sigma0, h, cd, rho_p;
+    int force_r, force_j, enc_j;
+};
+
+// ---- launchers (nb_kernels.hip) --------------------------------------------
+hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s);
+hipError_t launch_validate(const Dev &d, const double *m0, const double *m, const double *x,
+                           const double *v, hipStream_t s);
+hipError_t launch_to_dh(const Dev &d, const double *x, const double *v, int frame, hipStream_t s);
+hipError_t launch_from_dh(const Dev &d, double *x, double *v, int frame, hipStream_t s);
+hipError_t launch_momentum(const Dev &d, hipStream_t s);
+hipError_t launch_kick(const Dev &d, const Params &p, double h, hipStream_t s);
+hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, hipStream_t s);
+hipError_t launch_drift(const Dev &d, const Params &p, double dt, hipStream_t s);
+hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s);
+hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, hipStream_t s);
+hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s);
+hipError_t launch_diagnostics(const Dev &d, const Params &p, hipStream_t s);
+
+}  // namespace nb

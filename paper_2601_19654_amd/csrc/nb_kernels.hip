@@ -1,0 +1,1310 @@
+// Device kernels of the hybrid symplectic hot path for gfx950 (MI355X).
+//
+// Paper: Mercury-Opal, arXiv 2601.19654.  Sec. 3.1 gives the five per-step
+// blocks (force, Hamiltonian, drift, encounter check) and Sec. 3.2 the data
+// kept on the device; Sec. 2.1.1 the coordinates (democratic heliocentric) and
+// the Hill-radius based critical radius.  The kernels here are a new MI355X
+// design, not a translation of the paper's OpenACC loops:
+//   * state lives in HBM as FP64 structure-of-arrays planes for the whole run;
+//   * pair kernels hold R targets per lane in VGPRs and stream sources through
+//     LDS tiles read as wave-wide broadcasts; sources are split into chunks so a
+//     single system fills all 256 CUs, and the chunk partials are summed in a
+//     fixed order (bit-reproducible runs);
+//   * O(N) phases run over blocks that never straddle two systems, with
+//     per-system sums formed from per-block partials in a fixed order;
+//   * no atomics touch floating-point data; the encounter list uses one
+//     integer atomic per wave and is sorted afterwards.
+#include "nb_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace nb {
+
+// ----------------------------------------------------------------------------
+// small helpers
+// ----------------------------------------------------------------------------
+
+// Error-free sum (Knuth two-sum) accumulated into a (hi, lo) pair.
+struct dd {
+    double hi, lo;
+};
+__device__ __forceinline__ void dd_add(dd &a, double b)
+{
+    double s = a.hi + b;
+    double bp = s - a.hi;
+    double e = (a.hi - (s - bp)) + (b - bp);
+    a.hi = s;
+    a.lo += e;
+}
+__device__ __forceinline__ void dd_add(dd &a, const dd &b)
+{
+    dd_add(a, b.hi);
+    a.lo += b.lo;
+}
+
+// 1/sqrt(x) in FP64: the hardware estimate refined by one step of the
+// third-order expansion (1-e)^(-1/2) ~ 1 + e/2 + 3e^2/8 with e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    double t = fma(0.375, e, 0.5);
+    return fma(y * e, t, y);
+}
+
+// Same, two refinement steps (diagnostics: to the last bit).
+__device__ __forceinline__ double rsqrt64_acc(double x)
+{
+    double y = rsqrt64(x);
+    double e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// Deterministic block-wide sum of W doubles per thread (fixed tree).
+template <int W>
+__device__ __forceinline__ void block_sum(double (&v)[W], double *sh)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        sh[w * kBlock + t] = v[w];
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if (t < st) {
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                sh[w * kBlock + t] += sh[w * kBlock + t + st];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        v[w] = sh[w * kBlock];
+    __syncthreads();
+}
+
+// Sum of the first W columns of the per-block partials of one system, in block order.
+template <int W>
+__device__ __forceinline__ void system_sum(const double *__restrict__ part, int stride, int first,
+                                           int count, double (&out)[W], double *sh)
+{
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        out[w] = 0.0;
+    for (int b = threadIdx.x; b < count; b += kBlock)
+#pragma unroll
+        for (int w = 0; w < W; ++w)
+            out[w] += part[(size_t)(first + b) * stride + w];
+    block_sum<W>(out, sh);
+}
+
+// Wave-aggregated integer atomic add (one atomic per wave).
+__device__ __forceinline__ void wave_count_add(long long *ctr, bool pred)
+{
+    unsigned long long mask = __ballot(pred);
+    if (mask && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)mask) - 1))
+        atomicAdd((unsigned long long *)ctr, (unsigned long long)__popcll(mask));
+}
+
+// Changeover weight w = K/r^3 - (dK/dr)/r^2 for a pair at squared distance r2
+// with pair critical radius rc (inner edge `inner` rc).  K = 0 below the inner
+// edge, 1 beyond rc and y^2/(2y^2-2y+1) in between, y = (r - inner rc)/((1-inner) rc).
+__device__ __noinline__ double changeover_w(double r2, double rc, double inner)
+{
+    if (!(r2 > 0.0))
+        return 0.0;
+    double r = sqrt(r2);
+    if (r >= rc)
+        return 1.0 / (r2 * r);
+    double r_in = inner * rc;
+    if (r <= r_in)
+        return 0.0;
+    double width = rc - r_in;
+    double y = (r - r_in) / width;
+    double q = 2.0 * y * (y - 1.0) + 1.0;
+    double K = y * y / q;
+    double dK = 2.0 * y * (1.0 - y) / (q * q * width);
+    return (K / r - dK) / r2;
+}
+
+// K itself (diagnostics).
+__device__ __forceinline__ double changeover_K(double r, double rc, double inner)
+{
+    if (r >= rc)
+        return 1.0;
+    double r_in = inner * rc;
+    if (r <= r_in)
+        return 0.0;
+    double y = (r - r_in) / (rc - r_in);
+    return y * y / (2.0 * y * (y - 1.0) + 1.0);
+}
+
+// ----------------------------------------------------------------------------
+// fills, validation, transforms
+// ----------------------------------------------------------------------------
+__global__ void k_fill_i32(int *p, int n, int value)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = value;
+}
+
+__global__ void k_validate(int ntot, int nsys, const double *__restrict__ m0,
+                           const double *__restrict__ m, const double *__restrict__ x,
+                           const double *__restrict__ v, int *flag)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (i < ntot) {
+        double mi = m[i];
+        bad = !isfinite(mi) || mi < 0.0;
+        for (int c = 0; c < 3; ++c)
+            bad |= !isfinite(x[(size_t)c * ntot + i]) || !isfinite(v[(size_t)c * ntot + i]);
+    }
+    if (i < nsys)
+        bad |= !(m0[i] > 0.0) || !isfinite(m0[i]);
+    if (bad)
+        atomicOr(flag, 1);
+}
+
+// Per-block partial of sum m v (columns 0-2) and sum m (column 3).
+__global__ void k_partial_mv(const RBlk *__restrict__ rblk, const double *__restrict__ m,
+                             const double *__restrict__ vx, const double *__restrict__ vy,
+                             const double *__restrict__ vz, double *__restrict__ part)
+{
+    __shared__ double sh[4 * kBlock];
+    RBlk b = rblk[blockIdx.x];
+    int i = b.start + threadIdx.x;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (i < b.end) {
+        double mi = m[i];
+        v[0] = mi * vx[i];
+        v[1] = mi * vy[i];
+        v[2] = mi * vz[i];
+        v[3] = mi;
+    }
+    block_sum<4>(v, sh);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < 4; ++w)
+            part[(size_t)blockIdx.x * 4 + w] = v[w];
+}
+
+// Heliocentric -> DH: Q = x, V = v - sum m v / (m0 + sum m); or a plain copy.
+__global__ void k_to_dh(const RBlk *__restrict__ rblk, const int *__restrict__ rb_first,
+                        const int *__restrict__ rb_count, const double *__restrict__ m0,
+                        const double *__restrict__ part, int ntot, const double *__restrict__ x,
+                        const double *__restrict__ v, int helio, double *qx, double *qy,
+                        double *qz, double *vx, double *vy, double *vz)
+{
+    __shared__ double sh[4 * kBlock];
+    RBlk b = rblk[blockIdx.x];
+    double c[3] = {0.0, 0.0, 0.0};
+    if (helio) {
+        double P[4];
+        system_sum<4>(part, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        double M = m0[b.sys] + P[3];
+        c[0] = P[0] / M;
+        c[1] = P[1] / M;
+        c[2] = P[2] / M;
+    }
+    int i = b.start + threadIdx.x;
+    if (i < b.end) {
+        qx[i] = x[i];
+        qy[i] = x[(size_t)ntot + i];
+        qz[i] = x[(size_t)2 * ntot + i];
+        vx[i] = v[i] - c[0];
+        vy[i] = v[(size_t)ntot + i] - c[1];
+        vz[i] = v[(size_t)2 * ntot + i] - c[2];
+    }
+}
+
+// DH -> heliocentric (v = V + P/m0) or DH copy, into plane-major x, v.
+__global__ void k_from_dh(const RBlk *__restrict__ rblk, const int *__restrict__ rb_first,
+                          const int *__restrict__ rb_count, const double *__restrict__ m0,
+                          const double *__restrict__ part, int ntot, int helio,
+                          const double *__restrict__ qx, const double *__restrict__ qy,
+                          const double *__restrict__ qz, const double *__restrict__ vx,
+                          const double *__restrict__ vy, const double *__restrict__ vz, double *x,
+                          double *v)
+{
+    __shared__ double sh[4 * kBlock];
+    RBlk b = rblk[blockIdx.x];
+    double c[3] = {0.0, 0.0, 0.0};
+    if (helio) {
+        double P[3];
+        system_sum<3>(part, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        double mm = m0[b.sys];
+        c[0] = P[0] / mm;
+        c[1] = P[1] / mm;
+        c[2] = P[2] / mm;
+    }
+    int i = b.start + threadIdx.x;
+    if (i < b.end) {
+        x[i] = qx[i];
+        x[(size_t)ntot + i] = qy[i];
+        x[(size_t)2 * ntot + i] = qz[i];
+        v[i] = vx[i] + c[0];
+        v[(size_t)ntot + i] = vy[i] + c[1];
+        v[(size_t)2 * ntot + i] = vz[i] + c[2];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Kick (Hamiltonian block loop 1), optionally with gas drag, and the partial
+// sums of m V after it (the following stellar drift needs them).
+// ----------------------------------------------------------------------------
+struct DragP {
+    double G, sigma0, h, cd, rho_p;
+};
+
+// Quadratic gas drag on one body (parity unpinned by the paper: Sec. 2.1 names
+// aerodynamic drag, its disk model is elsewhere).  a = -k |u| u, u = v_helio -
+// v_gas, k = 3 C_D rho_g / (8 rho_p s), s = (3 m/(4 pi rho_p))^(1/3),
+// rho_g = Sigma0/R / (sqrt(2 pi) h R) exp(-z^2/(2 (h R)^2)),
+// v_gas = sqrt(1 - 3 h^2) sqrt(G m0 / R) phi_hat, R cylindrical.
+__device__ void drag_accel(const DragP &p, double m0, double mi, double x, double y, double z,
+                           double ux, double uy, double uz, double &ax, double &ay, double &az)
+{
+    const double kPi = 3.141592653589793238462643;
+    double R2 = x * x + y * y;
+    double R = sqrt(R2);
+    double H = p.h * R;
+    double rho = p.sigma0 / R / (sqrt(2.0 * kPi) * H) * exp(-z * z / (2.0 * H * H));
+    double vk = sqrt(p.G * m0 / R) * sqrt(1.0 - 3.0 * p.h * p.h);
+    double gx = -vk * y / R, gy = vk * x / R;
+    double wx = ux - gx, wy = uy - gy, wz = uz;
+    double wm = sqrt(wx * wx + wy * wy + wz * wz);
+    double s = cbrt(3.0 * mi / (4.0 * kPi * p.rho_p));
+    double k = (mi > 0.0 && p.sigma0 > 0.0) ? 3.0 * p.cd * rho / (8.0 * p.rho_p * s) : 0.0;
+    ax = -k * wm * wx;
+    ay = -k * wm * wy;
+    az = -k * wm * wz;
+}
+
+__global__ void k_kick(const RBlk *__restrict__ rblk, double h, const double *__restrict__ m,
+                       const double *__restrict__ ax, const double *__restrict__ ay,
+                       const double *__restrict__ az, double *vx, double *vy, double *vz,
+                       double *__restrict__ part_out,
+                       // drag (part_in == nullptr: no drag)
+                       const double *__restrict__ part_in, const int *__restrict__ rb_first,
+                       const int *__restrict__ rb_count, const double *__restrict__ m0,
+                       const double *__restrict__ qx, const double *__restrict__ qy,
+                       const double *__restrict__ qz, DragP dp)
+{
+    __shared__ double sh[4 * kBlock];
+    RBlk b = rblk[blockIdx.x];
+    double P[3] = {0.0, 0.0, 0.0};
+    double mm = 1.0;
+    if (part_in) {
+        system_sum<3>(part_in, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        mm = m0[b.sys];
+    }
+    int i = b.start + threadIdx.x;
+    double v[3] = {0.0, 0.0, 0.0};
+    if (i < b.end) {
+        double mi = m[i];
+        double a0 = ax[i], a1 = ay[i], a2 = az[i];
+        double u0 = vx[i], u1 = vy[i], u2 = vz[i];
+        if (part_in) {
+            double d0, d1, d2;
+            drag_accel(dp, mm, mi, qx[i], qy[i], qz[i], u0 + P[0] / mm, u1 + P[1] / mm,
+                       u2 + P[2] / mm, d0, d1, d2);
+            a0 += d0;
+            a1 += d1;
+            a2 += d2;
+        }
+        u0 += h * a0;
+        u1 += h * a1;
+        u2 += h * a2;
+        vx[i] = u0;
+        vy[i] = u1;
+        vz[i] = u2;
+        v[0] = mi * u0;
+        v[1] = mi * u1;
+        v[2] = mi * u2;
+    }
+    if (part_out) {
+        block_sum<3>(v, sh);
+        if (threadIdx.x == 0) {
+            part_out[(size_t)blockIdx.x * 4 + 0] = v[0];
+            part_out[(size_t)blockIdx.x * 4 + 1] = v[1];
+            part_out[(size_t)blockIdx.x * 4 + 2] = v[2];
+            part_out[(size_t)blockIdx.x * 4 + 3] = 0.0;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Stellar drift Q += h P/m0 (Hamiltonian block loops 2-3), optionally followed
+// by the critical radius rc = n_hill |Q| (m/(3 m0))^(1/3) (Sec. 2.1.1) and the
+// FP32 hi/lo source records of the FP32C force.
+// ----------------------------------------------------------------------------
+__global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict__ rb_first,
+                            const int *__restrict__ rb_count, const double *__restrict__ m0,
+                            const double *__restrict__ part, double h, double *qx, double *qy,
+                            double *qz, int rcrit, const double *__restrict__ m, double n_hill,
+                            double *__restrict__ rc, float4 *__restrict__ pk)
+{
+    __shared__ double sh[3 * kBlock];
+    RBlk b = rblk[blockIdx.x];
+    double c[3] = {0.0, 0.0, 0.0};
+    double mm = m0[b.sys];
+    if (h != 0.0) {
+        double P[3];
+        system_sum<3>(part, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        c[0] = h * P[0] / mm;
+        c[1] = h * P[1] / mm;
+        c[2] = h * P[2] / mm;
+    }
+    int i = b.start + threadIdx.x;
+    if (i < b.end) {
+        double x = qx[i] + c[0], y = qy[i] + c[1], z = qz[i] + c[2];
+        qx[i] = x;
+        qy[i] = y;
+        qz[i] = z;
+        if (rcrit) {
+            double mi = m[i];
+            double r = sqrt(x * x + y * y + z * z);
+            double rci = n_hill * r * cbrt(mi / (3.0 * mm));
+            rc[i] = rci;
+            if (pk) {
+                float hx = (float)x, hy = (float)y, hz = (float)z;
+                float lx = (float)(x - (double)hx), ly = (float)(y - (double)hy),
+                      lz = (float)(z - (double)hz);
+                // squared radius widened by 2^-9 so the FP32 zone test is a superset of
+                // the FP64 one; never below FLT_MIN so coincident bodies take the FP64 path
+                float r2 = (float)(rci * rci * (1.0 + 0x1p-9));
+                r2 = fmaxf(r2, FLT_MIN);
+                pk[2 * (size_t)i] = make_float4(hx, hy, hz, (float)mi);
+                pk[2 * (size_t)i + 1] = make_float4(lx, ly, lz, r2);
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Kepler drift (Sec. 2.1: WHFAST-derived drift; Sec. 3.1: one body per thread
+// with a failure flag, positions and velocities copied first).  Universal
+// variables: s solves r0 s + eta0 G2(s) + zeta0 G3(s) = dt with
+// G_k(s) = s^k c_k(beta s^2), beta = 2 mu/r0 - v^2, zeta0 = mu - beta r0.
+// ----------------------------------------------------------------------------
+__host__ __device__ constexpr double inv_fact(int k)
+{
+    double f = 1.0;
+    for (int i = 2; i <= k; ++i)
+        f *= (double)i;
+    return 1.0 / f;
+}
+
+// c_k(z) = sum_n (-z)^n/(2n+k)! by a fixed-length Horner polynomial (|z| <= 1).
+template <int K>
+__device__ __forceinline__ double stumpff_series(double mz)
+{
+    double p = inv_fact(2 * 11 + K);
+#pragma unroll
+    for (int n = 10; n >= 0; --n)
+        p = fma(p, mz, inv_fact(2 * n + K));
+    return p;
+}
+
+__device__ __forceinline__ void gfuncs(double beta, double s, double &G1, double &G2, double &G3)
+{
+    double z = beta * s * s;
+    double c1, c2, c3;
+    if (fabs(z) <= 1.0) {
+        c1 = stumpff_series<1>(-z);
+        c2 = stumpff_series<2>(-z);
+        c3 = stumpff_series<3>(-z);
+    } else if (z > 0.0) {
+        double x = sqrt(z), sx, cx;
+        sincos(x, &sx, &cx);
+        c1 = sx / x;
+        c2 = (1.0 - cx) / z;
+        c3 = (1.0 - c1) / z;
+    } else {
+        double x = sqrt(-z);
+        c1 = sinh(x) / x;
+        c2 = (1.0 - cosh(x)) / z;
+        c3 = (1.0 - c1) / z;
+    }
+    G1 = s * c1;
+    G2 = s * s * c2;
+    G3 = s * s * s * c3;
+}
+
+// Returns 0 on success; on failure the body is left unchanged.
+__device__ int kepler_drift(double mu, double dt, double &x, double &y, double &z, double &u,
+                            double &v, double &w)
+{
+    if (dt == 0.0)
+        return 0;
+    double r0 = sqrt(x * x + y * y + z * z);
+    double v2 = u * u + v * v + w * w;
+    double eta0 = x * u + y * v + z * w;
+    double beta = 2.0 * mu / r0 - v2;
+    double zeta0 = mu - beta * r0;
+    if (!(r0 > 0.0) || !isfinite(r0 + v2))
+        return 1;
+
+    const double tol = 2.0 * DBL_EPSILON;   // 4 u
+    // second-order starting value of s
+    double s = dt / r0;
+    double corr = 1.0 - 0.5 * eta0 * dt / (r0 * r0);
+    if (corr > 0.5 && corr < 2.0)
+        s *= corr;
+    double lo = dt > 0.0 ? 0.0 : -INFINITY;
+    double hi = dt > 0.0 ? INFINITY : 0.0;
+    double G1, G2, G3;
+    bool ok = false;
+    for (int it = 0; it < 100; ++it) {
+        gfuncs(beta, s, G1, G2, G3);
+        double F = r0 * s + eta0 * G2 + zeta0 * G3 - dt;
+        double dF = r0 + eta0 * G1 + zeta0 * G2;
+        if (F == 0.0) {
+            ok = true;
+            break;
+        }
+        if (F < 0.0)
+            lo = s;
+        else
+            hi = s;
+        double sn = s - F / dF;
+        if (!(sn > lo && sn < hi)) {
+            if (isfinite(lo) && isfinite(hi))
+                sn = 0.5 * (lo + hi);
+            else if (isfinite(lo))
+                sn = lo > 0.0 ? 2.0 * lo : fabs(dt / r0);
+            else
+                sn = hi < 0.0 ? 2.0 * hi : -fabs(dt / r0);
+        }
+        double ds = sn - s;
+        s = sn;
+        if (fabs(ds) <= tol * fabs(s) || (hi - lo) <= tol * fabs(s)) {
+            ok = true;
+            break;
+        }
+    }
+    if (!ok)
+        return 1;
+    gfuncs(beta, s, G1, G2, G3);
+    double r = r0 + eta0 * G1 + zeta0 * G2;
+    double fm1 = -mu * G2 / r0;
+    double g = dt - mu * G3;
+    double fd = -mu * G1 / (r * r0);
+    double gdm1 = -mu * G2 / r;
+    double nx = x + (fm1 * x + g * u), ny = y + (fm1 * y + g * v), nz = z + (fm1 * z + g * w);
+    double nu = u + (fd * x + gdm1 * u), nv = v + (fd * y + gdm1 * v), nw = w + (fd * z + gdm1 * w);
+    if (!isfinite(nx + ny + nz + nu + nv + nw))
+        return 1;
+    x = nx;
+    y = ny;
+    z = nz;
+    u = nu;
+    v = nv;
+    w = nw;
+    return 0;
+}
+
+// Snapshot, drift, failure flags and counters, encounter flags cleared, and the
+// partial sums of m V after the drift (for the second stellar drift).
+__global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict__ m0, double G,
+                        double dt, const double *__restrict__ m, double *qx, double *qy,
+                        double *qz, double *vx, double *vy, double *vz, double *__restrict__ q0x,
+                        double *__restrict__ q0y, double *__restrict__ q0z,
+                        double *__restrict__ v0x, double *__restrict__ v0y,
+                        double *__restrict__ v0z, int *__restrict__ kflag, int *__restrict__ ce,
+                        DevStats *stats, double *__restrict__ part_out)
+{
+    __shared__ double sh[3 * kBlock];
+    RBlk b = rblk[blockIdx.x];
+    int i = b.start + threadIdx.x;
+    double mu = G * m0[b.sys];
+    bool fail = false;
+    double pv[3] = {0.0, 0.0, 0.0};
+    if (i < b.end) {
+        double x = qx[i], y = qy[i], z = qz[i], u = vx[i], v = vy[i], w = vz[i];
+        q0x[i] = x;
+        q0y[i] = y;
+        q0z[i] = z;
+        v0x[i] = u;
+        v0y[i] = v;
+        v0z[i] = w;
+        fail = kepler_drift(mu, dt, x, y, z, u, v, w) != 0;
+        qx[i] = x;
+        qy[i] = y;
+        qz[i] = z;
+        vx[i] = u;
+        vy[i] = v;
+        vz[i] = w;
+        kflag[i] = fail ? 1 : 0;
+        ce[i] = 0;
+        double mi = m[i];
+        pv[0] = mi * u;
+        pv[1] = mi * v;
+        pv[2] = mi * w;
+    }
+    unsigned long long mask = __ballot(fail);
+    if (mask && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)mask) - 1)) {
+        atomicAdd((unsigned long long *)&stats->kepler_fail, (unsigned long long)__popcll(mask));
+        atomicAdd(&stats->cur_kfail, (int)__popcll(mask));
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        stats->cur_nce = 0;
+    block_sum<3>(pv, sh);
+    if (threadIdx.x == 0) {
+        part_out[(size_t)blockIdx.x * 4 + 0] = pv[0];
+        part_out[(size_t)blockIdx.x * 4 + 1] = pv[1];
+        part_out[(size_t)blockIdx.x * 4 + 2] = pv[2];
+        part_out[(size_t)blockIdx.x * 4 + 3] = 0.0;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Interaction force (Sec. 3.1 force block, loop 2): per target i the sum over
+// sources j != i of m_j w(r_ij) (Q_j - Q_i); G is applied in the finalize pass.
+// Pairs at or beyond rc_ij take the Newtonian term; the rare pairs inside
+// rc_ij branch to the exact changeover weight.
+// ----------------------------------------------------------------------------
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ work,
+                                                    const double *__restrict__ qx,
+                                                    const double *__restrict__ qy,
+                                                    const double *__restrict__ qz,
+                                                    const double *__restrict__ m,
+                                                    const double *__restrict__ rc,
+                                                    double *__restrict__ fpart, int ntot, int maxs,
+                                                    double inner)
+{
+    __shared__ double4 sj[kBlock];
+    __shared__ double2 sr[kBlock];
+    const FWork wk = work[blockIdx.x];
+    const int t = threadIdx.x;
+    double xi[R], yi[R], zi[R], r2i[R], rci[R], ax[R], ay[R], az[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        int li = t + k * kBlock;
+        int i = wk.i0 + (li < wk.ni ? li : 0);
+        xi[k] = qx[i];
+        yi[k] = qy[i];
+        zi[k] = qz[i];
+        double r = rc[i];
+        rci[k] = r;
+        r2i[k] = fmax(r * r, DBL_MIN);
+        ax[k] = ay[k] = az[k] = 0.0;
+    }
+    const int jend = wk.j0 + wk.nj;
+    for (int jt = wk.j0; jt < jend; jt += kBlock) {
+        const int cnt = min(kBlock, jend - jt);
+        __syncthreads();
+        if (t < cnt) {
+            int j = jt + t;
+            double r = rc[j];
+            sj[t] = make_double4(qx[j], qy[j], qz[j], m[j]);
+            sr[t] = make_double2(fmax(r * r, DBL_MIN), r);
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int jj = 0; jj < cnt; ++jj) {
+            const double4 J = sj[jj];
+            const double2 JR = sr[jj];
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                double dx = J.x - xi[k], dy = J.y - yi[k], dz = J.z - zi[k];
+                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                double y = rsqrt64(r2);
+                double s = J.w * (y * y) * y;
+                if (r2 < fmax(r2i[k], JR.x))
+                    s = J.w * changeover_w(r2, fmax(rci[k], JR.y), inner);
+                ax[k] = fma(s, dx, ax[k]);
+                ay[k] = fma(s, dy, ay[k]);
+                az[k] = fma(s, dz, az[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        int li = t + k * kBlock;
+        if (li < wk.ni) {
+            int i = wk.i0 + li;
+            fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = ax[k];
+            fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = ay[k];
+            fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = az[k];
+        }
+    }
+}
+
+// FP32C: pair terms in FP32 from hi/lo split positions (the difference of two
+// hi parts is exact for nearby bodies, the lo parts restore the rest), summed
+// in FP32 over runs of kMerge sources and merged by two-sum into a per-target
+// (hi, lo) accumulator.  Pairs whose FP32 distance falls inside a widened
+// critical radius are evaluated in FP64 from the FP64 state instead.
+constexpr int kMerge = 32;
+
+__device__ __forceinline__ void two_sum_f(float &hi, float &lo, float t)
+{
+    float s = hi + t;
+    float bp = s - hi;
+    float e = (hi - (s - bp)) + (t - bp);
+    hi = s;
+    lo += e;
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ work,
+                                                     const float4 *__restrict__ pk,
+                                                     const double *__restrict__ qx,
+                                                     const double *__restrict__ qy,
+                                                     const double *__restrict__ qz,
+                                                     const double *__restrict__ m,
+                                                     const double *__restrict__ rc,
+                                                     double *__restrict__ fpart, int ntot,
+                                                     int maxs, double inner, DevStats *stats)
+{
+    __shared__ float4 sa[kBlock];
+    __shared__ float4 sb[kBlock];
+    const FWork wk = work[blockIdx.x];
+    const int t = threadIdx.x;
+    float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], r2i[R];
+    float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R], tx[R], ty[R], tz[R];
+    double nx[R], ny[R], nz[R];
+    int ii[R];
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        int li = t + k * kBlock;
+        int i = wk.i0 + (li < wk.ni ? li : 0);
+        ii[k] = i;
+        float4 A = pk[2 * (size_t)i], B = pk[2 * (size_t)i + 1];
+        xh[k] = A.x; yh[k] = A.y; zh[k] = A.z;
+        xl[k] = B.x; yl[k] = B.y; zl[k] = B.z;
+        r2i[k] = B.w;
+        hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = tx[k] = ty[k] = tz[k] = 0.0f;
+        nx[k] = ny[k] = nz[k] = 0.0;
+    }
+    bool any_near = false;
+    const int jend = wk.j0 + wk.nj;
+    for (int jt = wk.j0; jt < jend; jt += kBlock) {
+        const int cnt = min(kBlock, jend - jt);
+        __syncthreads();
+        if (t < cnt) {
+            sa[t] = pk[2 * (size_t)(jt + t)];
+            sb[t] = pk[2 * (size_t)(jt + t) + 1];
+        }
+        __syncthreads();
+        for (int jb = 0; jb < cnt; jb += kMerge) {
+            const int je = min(cnt, jb + kMerge);
+#pragma unroll 2
+            for (int jj = jb; jj < je; ++jj) {
+                const float4 A = sa[jj];
+                const float4 B = sb[jj];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    float dx = (A.x - xh[k]) + (B.x - xl[k]);
+                    float dy = (A.y - yh[k]) + (B.y - yl[k]);
+                    float dz = (A.z - zh[k]) + (B.z - zl[k]);
+                    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    float y = __builtin_amdgcn_rsqf(r2);
+                    float s = A.w * (y * y) * y;
+                    if (r2 < fmaxf(r2i[k], B.w)) {
+                        // FP64 changeover pair from the FP64 state
+                        int i = ii[k], j = jt + jj;
+                        double ex = qx[j] - qx[i], ey = qy[j] - qy[i], ez = qz[j] - qz[i];
+                        double d2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                        double wgt = m[j] * changeover_w(d2, fmax(rc[i], rc[j]), inner);
+                        nx[k] = fma(wgt, ex, nx[k]);
+                        ny[k] = fma(wgt, ey, ny[k]);
+                        nz[k] = fma(wgt, ez, nz[k]);
+                        s = 0.0f;
+                        any_near = true;
+                    }
+                    tx[k] = fmaf(s, dx, tx[k]);
+                    ty[k] = fmaf(s, dy, ty[k]);
+                    tz[k] = fmaf(s, dz, tz[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                two_sum_f(hx[k], lx[k], tx[k]);
+                two_sum_f(hy[k], ly[k], ty[k]);
+                two_sum_f(hz[k], lz[k], tz[k]);
+                tx[k] = ty[k] = tz[k] = 0.0f;
+            }
+        }
+    }
+    (void)any_near;
+#pragma unroll
+    for (int k = 0; k < R; ++k) {
+        int li = t + k * kBlock;
+        if (li < wk.ni) {
+            int i = wk.i0 + li;
+            fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = ((double)hx[k] + (double)lx[k]) + nx[k];
+            fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = ((double)hy[k] + (double)ly[k]) + ny[k];
+            fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = ((double)hz[k] + (double)lz[k]) + nz[k];
+        }
+    }
+}
+
+// a = G * sum over the system's splits (fixed order); optionally the kick
+// V += h a and the partial sums of m V after it.
+__global__ void k_force_finalize(const RBlk *__restrict__ rblk, const int *__restrict__ nsplit,
+                                 const double *__restrict__ fpart, int ntot, int maxs, double G,
+                                 double *__restrict__ ax, double *__restrict__ ay,
+                                 double *__restrict__ az, double h, const double *__restrict__ m,
+                                 double *vx, double *vy, double *vz, double *__restrict__ part_out)
+{
+    __shared__ double sh[3 * kBlock];
+    RBlk b = rblk[blockIdx.x];
+    int ns = nsplit[b.sys];
+    int i = b.start + threadIdx.x;
+    double pv[3] = {0.0, 0.0, 0.0};
+    if (i < b.end) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int k = 0; k < ns; ++k) {
+            s0 += fpart[((size_t)0 * maxs + k) * ntot + i];
+            s1 += fpart[((size_t)1 * maxs + k) * ntot + i];
+            s2 += fpart[((size_t)2 * maxs + k) * ntot + i];
+        }
+        s0 *= G;
+        s1 *= G;
+        s2 *= G;
+        ax[i] = s0;
+        ay[i] = s1;
+        az[i] = s2;
+        if (h != 0.0) {
+            double mi = m[i];
+            double u0 = vx[i] + h * s0, u1 = vy[i] + h * s1, u2 = vz[i] + h * s2;
+            vx[i] = u0;
+            vy[i] = u1;
+            vz[i] = u2;
+            pv[0] = mi * u0;
+            pv[1] = mi * u1;
+            pv[2] = mi * u2;
+        }
+    }
+    if (part_out) {
+        block_sum<3>(pv, sh);
+        if (threadIdx.x == 0) {
+            part_out[(size_t)blockIdx.x * 4 + 0] = pv[0];
+            part_out[(size_t)blockIdx.x * 4 + 1] = pv[1];
+            part_out[(size_t)blockIdx.x * 4 + 2] = pv[2];
+            part_out[(size_t)blockIdx.x * 4 + 3] = 0.0;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Encounter check (Sec. 3.1, encounter block): every pair i<j of a system
+// whose minimum separation over the step is <= rc_ij = max(rc_i, rc_j).  The
+// squared separation over s in [0,1] is taken as the cubic Hermite through
+// f0 = |dQ0|^2, f1 = |dQ1|^2 with slopes g0 = 2 dt dQ0.dV0, g1 = 2 dt dQ1.dV1.
+// Its minimum is bounded below by min(f0,f1) - 4/27 (max(0,-g0) + max(0,g1)),
+// which serves as a cheap conservative filter before the exact minimum.
+// ----------------------------------------------------------------------------
+__device__ double hermite_min(double f0, double f1, double g0, double g1)
+{
+    double b = 3.0 * (f1 - f0) - 2.0 * g0 - g1;   // s^2 coefficient
+    double c = 2.0 * (f0 - f1) + g0 + g1;         // s^3 coefficient
+    double best = fmin(f0, f1);
+    // f'(s) = g0 + 2 b s + 3 c s^2
+    double A = 3.0 * c, B = 2.0 * b, C = g0;
+    double s1 = -1.0, s2 = -1.0;
+    if (A != 0.0) {
+        double disc = B * B - 4.0 * A * C;
+        if (disc >= 0.0) {
+            double q = -0.5 * (B + copysign(sqrt(disc), B));
+            if (q != 0.0) {
+                s1 = q / A;
+                s2 = C / q;
+            }
+        }
+    } else if (B != 0.0) {
+        s1 = -C / B;
+    }
+    if (s1 > 0.0 && s1 < 1.0)
+        best = fmin(best, f0 + s1 * (g0 + s1 * (b + s1 * c)));
+    if (s2 > 0.0 && s2 < 1.0)
+        best = fmin(best, f0 + s2 * (g0 + s2 * (b + s2 * c)));
+    return fmax(best, 0.0);
+}
+
+struct EncRec {
+    double q0[3], v0[3], q1[3], v1[3];
+    double rc, pad;
+};
+
+__global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ work, double dt,
+                                                      const double *__restrict__ q0x,
+                                                      const double *__restrict__ q0y,
+                                                      const double *__restrict__ q0z,
+                                                      const double *__restrict__ v0x,
+                                                      const double *__restrict__ v0y,
+                                                      const double *__restrict__ v0z,
+                                                      const double *__restrict__ qx,
+                                                      const double *__restrict__ qy,
+                                                      const double *__restrict__ qz,
+                                                      const double *__restrict__ vx,
+                                                      const double *__restrict__ vy,
+                                                      const double *__restrict__ vz,
+                                                      const double *__restrict__ rc,
+                                                      unsigned long long *__restrict__ keys,
+                                                      int cap, int *__restrict__ ce,
+                                                      DevStats *stats)
+{
+    __shared__ EncRec sj[kBlock];
+    const PWork wk = work[blockIdx.x];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const double t2 = 2.0 * dt;
+    const double k427 = 4.0 / 27.0;
+    const bool has_i = t < wk.ni;
+    const int i = wk.i0 + (has_i ? t : 0);
+    double a0[3] = {q0x[i], q0y[i], q0z[i]}, b0[3] = {v0x[i], v0y[i], v0z[i]};
+    double a1[3] = {qx[i], qy[i], qz[i]}, b1[3] = {vx[i], vy[i], vz[i]};
+    const double rci = rc[i];
+    const int jend = wk.j0 + wk.nj;
+    for (int jt = wk.j0; jt < jend; jt += kBlock) {
+        const int cnt = min(kBlock, jend - jt);
+        __syncthreads();
+        if (t < cnt) {
+            int j = jt + t;
+            EncRec r;
+            r.q0[0] = q0x[j]; r.q0[1] = q0y[j]; r.q0[2] = q0z[j];
+            r.v0[0] = v0x[j]; r.v0[1] = v0y[j]; r.v0[2] = v0z[j];
+            r.q1[0] = qx[j];  r.q1[1] = qy[j];  r.q1[2] = qz[j];
+            r.v1[0] = vx[j];  r.v1[1] = vy[j];  r.v1[2] = vz[j];
+            r.rc = rc[j];
+            r.pad = 0.0;
+            sj[t] = r;
+        }
+        __syncthreads();
+        for (int jj = 0; jj < cnt; ++jj) {
+            const int j = jt + jj;
+            const EncRec &J = sj[jj];
+            double d0x = J.q0[0] - a0[0], d0y = J.q0[1] - a0[1], d0z = J.q0[2] - a0[2];
+            double d1x = J.q1[0] - a1[0], d1y = J.q1[1] - a1[1], d1z = J.q1[2] - a1[2];
+            double e0x = J.v0[0] - b0[0], e0y = J.v0[1] - b0[1], e0z = J.v0[2] - b0[2];
+            double e1x = J.v1[0] - b1[0], e1y = J.v1[1] - b1[1], e1z = J.v1[2] - b1[2];
+            double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
+            double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
+            double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
+            double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
+            double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
+            double rcij = fmax(rci, J.rc);
+            double thr = rcij * rcij;
+            bool cand = has_i && j > i &&
+                        lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1));
+            bool hit = false;
+            if (__builtin_expect(cand, 0))
+                hit = hermite_min(f0, f1, g0, g1) <= thr;
+            unsigned long long mask = __ballot(hit);
+            if (mask) {
+                int leader = __ffsll((long long)mask) - 1;
+                int base = 0;
+                if (lane == leader)
+                    base = atomicAdd(&stats->cur_nce, (int)__popcll(mask));
+                base = __shfl(base, leader);
+                if (hit) {
+                    unsigned long long below = mask & ((1ull << lane) - 1ull);
+                    int pos = base + (int)__popcll(below);
+                    if (pos < cap)
+                        keys[pos] = ((unsigned long long)(unsigned)i << 32) | (unsigned)j;
+                    __hip_atomic_store(&ce[i], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&ce[j], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    }
+}
+
+// Sort the encounter keys (one workgroup, bitonic), split them into (ice, jce),
+// and fold the count into the run statistics.
+constexpr int kSortThreads = 1024;
+constexpr int kSortLds = 8192;
+
+__global__ __launch_bounds__(kSortThreads) void k_enc_sort(unsigned long long *keys, int keys_p2,
+                                                           int cap, int *__restrict__ ice,
+                                                           int *__restrict__ jce, DevStats *stats)
+{
+    __shared__ unsigned long long sk[kSortLds];
+    const int t = threadIdx.x;
+    const int count = stats->cur_nce;
+    const int n = min(count, cap);
+    if (t == 0) {
+        stats->total_nce += count;
+        if (count > stats->max_nce)
+            stats->max_nce = count;
+        if (count > cap)
+            stats->overflow_steps += 1;
+    }
+    if (n <= 1) {
+        if (n == 1 && t == 0) {
+            ice[0] = (int)(keys[0] >> 32);
+            jce[0] = (int)(keys[0] & 0xffffffffull);
+        }
+        return;
+    }
+    int P = 1;
+    while (P < n)
+        P <<= 1;
+    const unsigned long long kMax = ~0ull;
+    if (P <= kSortLds) {
+        for (int k = t; k < P; k += kSortThreads)
+            sk[k] = k < n ? keys[k] : kMax;
+        __syncthreads();
+        for (int size = 2; size <= P; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int k = t; k < P; k += kSortThreads) {
+                    int l = k ^ stride;
+                    if (l > k) {
+                        bool up = (k & size) == 0;
+                        unsigned long long a = sk[k], b = sk[l];
+                        if ((a > b) == up) {
+                            sk[k] = b;
+                            sk[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int k = t; k < n; k += kSortThreads) {
+            ice[k] = (int)(sk[k] >> 32);
+            jce[k] = (int)(sk[k] & 0xffffffffull);
+        }
+    } else {
+        // P <= keys_p2 by construction of the key buffer
+        for (int k = n + t; k < P; k += kSortThreads)
+            keys[k] = kMax;
+        __syncthreads();
+        for (int size = 2; size <= P; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int k = t; k < P; k += kSortThreads) {
+                    int l = k ^ stride;
+                    if (l > k) {
+                        bool up = (k & size) == 0;
+                        unsigned long long a = keys[k], b = keys[l];
+                        if ((a > b) == up) {
+                            keys[k] = b;
+                            keys[l] = a;
+                        }
+                    }
+                }
+                __threadfence_block();
+                __syncthreads();
+            }
+        }
+        for (int k = t; k < n; k += kSortThreads) {
+            ice[k] = (int)(keys[k] >> 32);
+            jce[k] = (int)(keys[k] & 0xffffffffull);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Diagnostics (Sec. 2.1.1 energy and momentum routine), FP64 with error-free
+// accumulation: per pair work item the double-double sums of m_i m_j / r and of
+// K m_i m_j / r; per body block kinetic, stellar potential, L and P; then one
+// thread per system combines them in a fixed order.
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_diag_pairs(const PWork *__restrict__ work,
+                                                       const double *__restrict__ qx,
+                                                       const double *__restrict__ qy,
+                                                       const double *__restrict__ qz,
+                                                       const double *__restrict__ m,
+                                                       const double *__restrict__ rc, double inner,
+                                                       double *__restrict__ dpart)
+{
+    __shared__ double4 sj[kBlock];
+    __shared__ double sh[4 * kBlock];
+    const PWork wk = work[blockIdx.x];
+    const int t = threadIdx.x;
+    const bool has_i = t < wk.ni;
+    const int i = wk.i0 + (has_i ? t : 0);
+    const double xi = qx[i], yi = qy[i], zi = qz[i], rci = rc[i];
+    dd acc = {0.0, 0.0}, acck = {0.0, 0.0};
+    const int jend = wk.j0 + wk.nj;
+    __shared__ double srj[kBlock];
+    for (int jt = wk.j0; jt < jend; jt += kBlock) {
+        const int cnt = min(kBlock, jend - jt);
+        __syncthreads();
+        if (t < cnt) {
+            int j = jt + t;
+            sj[t] = make_double4(qx[j], qy[j], qz[j], m[j]);
+            srj[t] = rc[j];
+        }
+        __syncthreads();
+        for (int jj = 0; jj < cnt; ++jj) {
+            const int j = jt + jj;
+            if (!has_i || j <= i)
+                continue;
+            double4 J = sj[jj];
+            double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            if (!(r2 > 0.0))
+                continue;
+            double y = rsqrt64_acc(r2);
+            double u = J.w * y;
+            dd_add(acc, u);
+            double rcij = fmax(rci, srj[jj]);
+            if (r2 < rcij * rcij) {
+                double r = r2 * y;
+                u *= changeover_K(r, rcij, inner);
+            }
+            dd_add(acck, u);
+        }
+    }
+    double mi = has_i ? m[i] : 0.0;
+    // m_i times the per-target sums, then a fixed-tree sum of the (hi, lo) parts
+    double v[4] = {mi * acc.hi, mi * acc.lo, mi * acck.hi, mi * acck.lo};
+    block_sum<4>(v, sh);
+    if (t == 0)
+        for (int w = 0; w < 4; ++w)
+            dpart[(size_t)blockIdx.x * 4 + w] = v[w];
+}
+
+__global__ void k_diag_bodies(const RBlk *__restrict__ rblk, const double *__restrict__ m0,
+                              const double *__restrict__ m, const double *__restrict__ qx,
+                              const double *__restrict__ qy, const double *__restrict__ qz,
+                              const double *__restrict__ vx, const double *__restrict__ vy,
+                              const double *__restrict__ vz, double *__restrict__ bpart)
+{
+    __shared__ double sh[8 * kBlock];
+    RBlk b = rblk[blockIdx.x];
+    int i = b.start + threadIdx.x;
+    double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < b.end) {
+        double mi = m[i];
+        double x = qx[i], y = qy[i], z = qz[i], u = vx[i], w = vy[i], s = vz[i];
+        v[0] = 0.5 * mi * (u * u + w * w + s * s);
+        v[1] = -m0[b.sys] * mi / sqrt(x * x + y * y + z * z);   // G applied later
+        v[2] = mi * (y * s - z * w);
+        v[3] = mi * (z * u - x * s);
+        v[4] = mi * (x * w - y * u);
+        v[5] = mi * u;
+        v[6] = mi * w;
+        v[7] = mi * s;
+    }
+    block_sum<8>(v, sh);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < 8; ++w)
+            bpart[(size_t)blockIdx.x * 8 + w] = v[w];
+}
+
+__global__ void k_diag_final(int nsys, const int *__restrict__ rb_first,
+                             const int *__restrict__ rb_count, const int *__restrict__ dw_first,
+                             const int *__restrict__ dw_count, const double *__restrict__ bpart,
+                             const double *__restrict__ dpart, const double *__restrict__ m0,
+                             double G, double *__restrict__ out)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nsys)
+        return;
+    dd q[8];
+    for (int w = 0; w < 8; ++w)
+        q[w] = {0.0, 0.0};
+    for (int b = rb_first[s], e = b + rb_count[s]; b < e; ++b)
+        for (int w = 0; w < 8; ++w)
+            dd_add(q[w], bpart[(size_t)b * 8 + w]);
+    dd pe = {0.0, 0.0}, pk = {0.0, 0.0};
+    for (int k = dw_first[s], e = k + dw_count[s]; k < e; ++k) {
+        dd_add(pe, dd{dpart[(size_t)k * 4 + 0], dpart[(size_t)k * 4 + 1]});
+        dd_add(pk, dd{dpart[(size_t)k * 4 + 2], dpart[(size_t)k * 4 + 3]});
+    }
+    double P0 = q[5].hi + q[5].lo, P1 = q[6].hi + q[6].lo, P2 = q[7].hi + q[7].lo;
+    dd base = q[0];
+    dd_add(base, G * q[1].hi);
+    dd_add(base, G * q[1].lo);
+    dd_add(base, (P0 * P0 + P1 * P1 + P2 * P2) / (2.0 * m0[s]));
+    dd e1 = base, e2 = base;
+    dd_add(e1, -G * pe.hi);
+    dd_add(e1, -G * pe.lo);
+    dd_add(e2, -G * pk.hi);
+    dd_add(e2, -G * pk.lo);
+    double *o = out + (size_t)s * 8;
+    o[0] = e1.hi + e1.lo;
+    o[1] = e2.hi + e2.lo;
+    o[2] = q[2].hi + q[2].lo;
+    o[3] = q[3].hi + q[3].lo;
+    o[4] = q[4].hi + q[4].lo;
+    o[5] = P0;
+    o[6] = P1;
+    o[7] = P2;
+}
+
+// ----------------------------------------------------------------------------
+// launchers
+// ----------------------------------------------------------------------------
+static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s)
+{
+    if (n <= 0)
+        return hipSuccess;
+    k_fill_i32<<<cdiv(n, kBlock), kBlock, 0, s>>>(p, n, value);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const Dev &d, const double *m0, const double *m, const double *x,
+                           const double *v, hipStream_t s)
+{
+    int n = d.ntot > d.nsys ? d.ntot : d.nsys;
+    k_validate<<<cdiv(n, kBlock), kBlock, 0, s>>>(d.ntot, d.nsys, m0, m, x, v, d.flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_dh(const Dev &d, const double *x, const double *v, int frame, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    int helio = frame == 0;
+    if (helio)
+        k_partial_mv<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m, v, v + d.ntot, v + 2 * (size_t)d.ntot,
+                                               d.rpart);
+    k_to_dh<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, d.rpart, d.ntot, x, v,
+                                      helio, d.qx, d.qy, d.qz, d.vx, d.vy, d.vz);
+    return hipGetLastError();
+}
+
+hipError_t launch_from_dh(const Dev &d, double *x, double *v, int frame, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    int helio = frame == 0;
+    if (helio)
+        k_partial_mv<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m, d.vx, d.vy, d.vz, d.rpart);
+    k_from_dh<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, d.rpart, d.ntot,
+                                        helio, d.qx, d.qy, d.qz, d.vx, d.vy, d.vz, x, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_momentum(const Dev &d, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    k_partial_mv<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m, d.vx, d.vy, d.vz, d.rpart);
+    return hipGetLastError();
+}
+
+static DragP drag_params(const Params &p)
+{
+    DragP dp;
+    dp.G = p.G;
+    dp.sigma0 = p.sigma0;
+    dp.h = p.h;
+    dp.cd = p.cd;
+    dp.rho_p = p.rho_p;
+    return dp;
+}
+
+hipError_t launch_kick(const Dev &d, const Params &p, double h, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    double *part_b = d.rpart + (size_t)d.nrb * 4;
+    if (p.drag) {
+        // partial sums of m V before the kick, for the heliocentric velocity
+        k_partial_mv<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m, d.vx, d.vy, d.vz, part_b);
+        k_kick<<<d.nrb, kBlock, 0, s>>>(d.rblk, h, d.m, d.ax, d.ay, d.az, d.vx, d.vy, d.vz, d.rpart,
+                                         part_b, d.rb_first, d.rb_count, d.m0, d.qx, d.qy, d.qz,
+                                         drag_params(p));
+    } else {
+        k_kick<<<d.nrb, kBlock, 0, s>>>(d.rblk, h, d.m, d.ax, d.ay, d.az, d.vx, d.vy, d.vz, d.rpart,
+                                         nullptr, d.rb_first, d.rb_count, d.m0, d.qx, d.qy, d.qz,
+                                         drag_params(p));
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    k_sun_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, d.rpart, h, d.qx,
+                                          d.qy, d.qz, rcrit, d.m, p.n_hill, d.rc,
+                                          p.mode == 1 ? d.pk : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_drift(const Dev &d, const Params &p, double dt, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    k_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, dt, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
+                                      d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
+                                      d.stats, d.rpart);
+    return hipGetLastError();
+}
+
+hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
+{
+    if (d.nfw == 0)
+        return hipSuccess;
+    if (p.mode == 1) {
+        switch (p.force_r) {
+        case 1:
+            k_force32c<1><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
+                                                    d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+            break;
+        case 4:
+            k_force32c<4><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
+                                                    d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+            break;
+        default:
+            k_force32c<2><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
+                                                    d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+        }
+    } else {
+        switch (p.force_r) {
+        case 1:
+            k_force64<1><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
+                                                   d.ntot, d.maxs, p.inner);
+            break;
+        case 4:
+            k_force64<4><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
+                                                   d.ntot, d.maxs, p.inner);
+            break;
+        default:
+            k_force64<2><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
+                                                   d.ntot, d.maxs, p.inner);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    k_force_finalize<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.nsplit, d.fpart, d.ntot, d.maxs, p.G, d.ax,
+                                               d.ay, d.az, kick_h, d.m, d.vx, d.vy, d.vz,
+                                               kick_h != 0.0 ? d.rpart : nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s)
+{
+    if (d.new_ > 0)
+        k_encounter<<<d.new_, kBlock, 0, s>>>(d.ework, dt, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y,
+                                               d.v0z, d.qx, d.qy, d.qz, d.vx, d.vy, d.vz, d.rc,
+                                               d.keys, d.keys_p2 < d.enc_cap ? d.keys_p2 : d.enc_cap,
+                                               d.ce, d.stats);
+    k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_diagnostics(const Dev &d, const Params &p, hipStream_t s)
+{
+    if (d.ndw > 0)
+        k_diag_pairs<<<d.ndw, kBlock, 0, s>>>(d.dwork, d.qx, d.qy, d.qz, d.m, d.rc, p.inner,
+                                               d.dpart);
+    if (d.nrb > 0)
+        k_diag_bodies<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
+                                                d.vz, d.bpart);
+    const int *dw_first = d.nsplit + d.nsys;      // laid out after nsplit by the runtime
+    const int *dw_count = dw_first + d.nsys;
+    k_diag_final<<<cdiv(d.nsys, 64), 64, 0, s>>>(d.nsys, d.rb_first, d.rb_count, dw_first,
+                                                  dw_count, d.bpart, d.dpart, d.m0, p.G, d.diag);
+    return hipGetLastError();
+}
+
+}  // namespace nb

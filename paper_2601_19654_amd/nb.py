@@ -1,0 +1,285 @@
+"""ctypes binding of the C ABI in include/nb.h (argument marshalling only).
+
+Every step of the hot path runs in the HIP library ``libnbody.so``; this module
+loads it, converts arguments, and uses PyTorch only for device memory (the
+context workspace, device-resident arrays) and for the HIP stream.  There is no
+fallback: if the library is missing the import of the functions fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libnbody.so")
+
+NB_OK = 0
+NB_E_INVALID = -1
+NB_E_NOT_READY = -2
+NB_E_HIP = -3
+NB_E_NONFINITE = -4
+NB_E_CAPACITY = -5
+NB_E_KEPLER = -6
+NB_E_WORKSPACE = -7
+NB_FP64 = 0
+NB_FP32C = 1
+NB_HELIO = 0
+NB_DH = 1
+NB_HOST = 0
+NB_DEVICE = 1
+NB_K_FORCE = 0
+NB_K_ENCOUNTER = 1
+NB_K_DRIFT = 2
+NB_K_STEP = 3
+
+
+class nb_params(ctypes.Structure):
+    _fields_ = [
+        ("G", ctypes.c_double), ("n_hill", ctypes.c_double), ("chg_inner", ctypes.c_double),
+        ("mode", ctypes.c_int32), ("drag", ctypes.c_int32),
+        ("drag_sigma0", ctypes.c_double), ("drag_h", ctypes.c_double),
+        ("drag_cd", ctypes.c_double), ("drag_rho_p", ctypes.c_double),
+        ("force_jchunk", ctypes.c_int32), ("force_r", ctypes.c_int32),
+        ("enc_jchunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+    ]
+
+
+class nb_stats(ctypes.Structure):
+    _fields_ = [
+        ("total_nce", ctypes.c_int64), ("max_nce", ctypes.c_int32),
+        ("overflow_steps", ctypes.c_int32), ("kepler_fail", ctypes.c_int64),
+        ("near_pairs", ctypes.c_int64),
+    ]
+
+
+class NbError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+_lib = None
+
+# exported symbol -> (restype, argtypes)
+_P, _I, _D, _S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = {
+    "nb_version": (_I, [_P, _P]),
+    "nb_strerror": (ctypes.c_char_p, [_I]),
+    "nb_default_params": (None, [_P]),
+    "nb_workspace_size": (_I, [_P, _I, _P, _I, _P]),
+    "nb_create": (_I, [_P, _I, _P, _I, _P, _S, _P, _P]),
+    "nb_last_error": (ctypes.c_char_p, [_P]),
+    "nb_upload": (_I, [_P, _P, _P, _P, _P, _I, _I]),
+    "nb_download": (_I, [_P, _P, _P, _I, _I]),
+    "nb_force": (_I, [_P]),
+    "nb_kick": (_I, [_P, _D]),
+    "nb_sun_drift": (_I, [_P, _D]),
+    "nb_drift": (_I, [_P, _D, _P]),
+    "nb_encounters": (_I, [_P, _I, _P, _P, _P, _P, _I]),
+    "nb_get_encounters": (_I, [_P, _I, _P, _P, _P, _P, _I]),
+    "nb_step": (_I, [_P, _D, _I, _P]),
+    "nb_diagnostics": (_I, [_P, _P, _P, _P, _P]),
+    "nb_get_accel": (_I, [_P, _P, _I]),
+    "nb_get_rcrit": (_I, [_P, _P, _I]),
+    "nb_time_kernel": (_I, [_P, _I, _I, _D, _P]),
+    "nb_destroy": (_I, [_P]),
+}
+
+
+def lib():
+    """Load libnbody.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def strerror(code: int) -> str:
+    return lib().nb_strerror(code).decode()
+
+
+def default_params(**kw) -> nb_params:
+    p = nb_params()
+    lib().nb_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _addr(a):
+    """Device or host address of a torch tensor or numpy array."""
+    if hasattr(a, "data_ptr"):
+        return ctypes.c_void_p(a.data_ptr())
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+@dataclass
+class Encounters:
+    nce: int
+    ice: np.ndarray
+    jce: np.ndarray
+    ce: np.ndarray
+
+
+class Context:
+    """One nb_ctx: workspace and stream from PyTorch, every call into libnbody.
+
+    ``off`` are the system offsets (nsys+1); vectors cross the boundary
+    plane-major (3, ntot).
+    """
+
+    def __init__(self, off, params: nb_params | None = None, enc_cap: int = 1 << 16,
+                 stream=None, device=None):
+        import torch
+        self._torch = torch
+        L = lib()
+        self.params = params or default_params()
+        self.off = np.ascontiguousarray(off, dtype=np.int32)
+        self.nsys = len(self.off) - 1
+        self.ntot = int(self.off[-1])
+        self.enc_cap = int(enc_cap)
+        nbytes = ctypes.c_size_t()
+        self._check(L.nb_workspace_size(ctypes.byref(self.params), self.nsys, _addr(self.off),
+                                        self.enc_cap, ctypes.byref(nbytes)), "nb_workspace_size")
+        self.device = torch.device(device or "cuda")
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
+        self.ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            self._check(L.nb_create(ctypes.byref(self.params), self.nsys, _addr(self.off), self.enc_cap,
+                                    _addr(self.workspace), nbytes.value,
+                                    ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)),
+                        "nb_create")
+
+    def _check(self, code, what, allow=()):
+        if code != NB_OK and code not in allow:
+            msg = what
+            if getattr(self, "ctx", None):
+                detail = lib().nb_last_error(self.ctx)
+                if detail:
+                    msg += ": " + detail.decode()
+            raise NbError(code, f"{msg}: {strerror(code)}")
+        return code
+
+    # ------------------------------------------------------------ state
+    def upload(self, m0, m, x, v, frame=NB_HELIO):
+        """x, v: (ntot, 3) or (3, ntot) host arrays, or (3, ntot) device tensors."""
+        torch = self._torch
+        if isinstance(x, torch.Tensor) and x.is_cuda:
+            args = [t.contiguous() for t in (m0, m, x, v)]
+            where = NB_DEVICE
+        else:
+            x = np.asarray(x); v = np.asarray(v)
+            if x.shape == (self.ntot, 3) and self.ntot != 3:
+                x, v = x.T, v.T
+            args = [_f64(m0), _f64(m), _f64(x), _f64(v)]
+            where = NB_HOST
+        self._keep = args
+        self._check(lib().nb_upload(self.ctx, *[_addr(a) for a in args], frame, where), "nb_upload")
+
+    def download(self, frame=NB_HELIO):
+        x = np.empty((3, self.ntot)); v = np.empty((3, self.ntot))
+        self._check(lib().nb_download(self.ctx, _addr(x), _addr(v), frame, NB_HOST), "nb_download")
+        return x.T.copy(), v.T.copy()
+
+    def download_device(self, x, v, frame=NB_HELIO):
+        self._check(lib().nb_download(self.ctx, _addr(x), _addr(v), frame, NB_DEVICE), "nb_download")
+
+    # ------------------------------------------------------------ sub-steps
+    def force(self):
+        self._check(lib().nb_force(self.ctx), "nb_force")
+
+    def kick(self, h):
+        self._check(lib().nb_kick(self.ctx, float(h)), "nb_kick")
+
+    def sun_drift(self, h):
+        self._check(lib().nb_sun_drift(self.ctx, float(h)), "nb_sun_drift")
+
+    def drift(self, dt, allow_fail=False):
+        nf = ctypes.c_int()
+        self._check(lib().nb_drift(self.ctx, float(dt), ctypes.byref(nf)), "nb_drift",
+                    allow=(NB_E_KEPLER,) if allow_fail else ())
+        return nf.value
+
+    def _enc(self, fn, cap, allow_overflow):
+        cap = self.enc_cap if cap is None else cap
+        n = ctypes.c_int()
+        ice = np.zeros(max(cap, 1), np.int32); jce = np.zeros(max(cap, 1), np.int32)
+        ce = np.zeros(max(self.ntot, 1), np.int32)
+        self._check(fn(self.ctx, cap, ctypes.byref(n), _addr(ice), _addr(jce), _addr(ce), NB_HOST),
+                    fn.__name__, allow=(NB_E_CAPACITY,) if allow_overflow else ())
+        k = min(n.value, cap)
+        return Encounters(n.value, ice[:k], jce[:k], ce[:self.ntot])
+
+    def encounters(self, cap=None, allow_overflow=False):
+        return self._enc(lib().nb_encounters, cap, allow_overflow)
+
+    def last_encounters(self, cap=None, allow_overflow=False):
+        return self._enc(lib().nb_get_encounters, cap, allow_overflow)
+
+    def step(self, dt, nsteps=1, allow=()):
+        st = nb_stats()
+        self._check(lib().nb_step(self.ctx, float(dt), int(nsteps), ctypes.byref(st)), "nb_step",
+                    allow=allow)
+        return {k: getattr(st, k) for k, _ in nb_stats._fields_}
+
+    def step_async(self, dt, nsteps=1):
+        """nb_step without the statistics argument (still synchronizes at the end)."""
+        return self._check(lib().nb_step(self.ctx, float(dt), int(nsteps), None), "nb_step",
+                           allow=(NB_E_CAPACITY, NB_E_KEPLER))
+
+    # ------------------------------------------------------------ outputs
+    def diagnostics(self):
+        E = np.empty(self.nsys); EK = np.empty(self.nsys)
+        L = np.empty((self.nsys, 3)); P = np.empty((self.nsys, 3))
+        self._check(lib().nb_diagnostics(self.ctx, _addr(E), _addr(EK), _addr(L), _addr(P)),
+                    "nb_diagnostics")
+        return {"E": E, "EK": EK, "L": L, "P": P}
+
+    def accel(self):
+        a = np.empty((3, self.ntot))
+        self._check(lib().nb_get_accel(self.ctx, _addr(a), NB_HOST), "nb_get_accel")
+        return a.T.copy()
+
+    def rcrit(self):
+        rc = np.empty(self.ntot)
+        self._check(lib().nb_get_rcrit(self.ctx, _addr(rc), NB_HOST), "nb_get_rcrit")
+        return rc
+
+    def time_kernel(self, which, reps=10, dt=0.0):
+        """Mean milliseconds per launch of one kernel (HIP events on this stream)."""
+        ms = ctypes.c_double()
+        self._check(lib().nb_time_kernel(self.ctx, int(which), int(reps), float(dt), ctypes.byref(ms)),
+                    "nb_time_kernel")
+        return ms.value
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lib().nb_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def version():
+    a, b = ctypes.c_int(), ctypes.c_int()
+    lib().nb_version(ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value

@@ -1,0 +1,80 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/nb.h declares, and its host-only entry points (version, status text,
+defaults, workspace sizing, argument validation) behave.  No compute call is
+made here; those need a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nb.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nb_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def nb():
+    from paper_2601_19654_amd import nb as m
+    m.lib()
+    return m
+
+
+def test_every_declared_symbol_is_exported(nb):
+    names = _declared()
+    assert len(names) >= 18
+    for name in names:
+        assert hasattr(nb.lib(), name), name
+    assert set(names) == set(nb.SIGNATURES), set(names) ^ set(nb.SIGNATURES)
+
+
+def test_version_status_defaults(nb):
+    assert nb.version() == (0, 1)
+    assert nb.strerror(nb.NB_E_CAPACITY).startswith("encounter")
+    p = nb.default_params()
+    assert abs(p.G - (0.01720209895 * 365.25) ** 2) < 1e-14
+    assert p.n_hill == 3.0 and p.chg_inner == 0.1 and p.mode == nb.NB_FP64
+    assert abs(p.drag_sigma0 - 1.1252e-4) < 1e-7
+
+
+def _wsize(nb, off, enc_cap=1024, **kw):
+    p = nb.default_params(**kw)
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    n = ctypes.c_size_t()
+    rc = nb.lib().nb_workspace_size(ctypes.byref(p), len(off) - 1,
+                                    off.ctypes.data_as(ctypes.c_void_p), enc_cap, ctypes.byref(n))
+    return rc, n.value
+
+
+def test_workspace_size_and_validation(nb):
+    rc, a = _wsize(nb, [0, 1000])
+    assert rc == 0 and a > 1000 * 17 * 8
+    rc, b = _wsize(nb, [0, 4000])
+    assert rc == 0 and b > a
+    rc, c = _wsize(nb, [0, 400, 400, 1000])       # an empty system is allowed
+    assert rc == 0
+    assert _wsize(nb, [0, 10, 5])[0] == nb.NB_E_INVALID          # decreasing offsets
+    assert _wsize(nb, [1, 10])[0] == nb.NB_E_INVALID             # off[0] != 0
+    assert _wsize(nb, [0, 0])[0] == nb.NB_E_INVALID              # no bodies
+    assert _wsize(nb, [0, 10], mode=7)[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 10], force_r=3)[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 10], G=-1.0)[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 10], enc_cap=-1)[0] == nb.NB_E_INVALID
+
+
+def test_create_rejects_bad_workspace(nb):
+    p = nb.default_params()
+    off = np.array([0, 10], dtype=np.int32)
+    ctx = ctypes.c_void_p()
+    rc = nb.lib().nb_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.c_void_p), 16, None, 0,
+                            None, ctypes.byref(ctx))
+    assert rc == nb.NB_E_WORKSPACE and not ctx.value
+    rc = nb.lib().nb_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.c_void_p), 16,
+                            ctypes.c_void_p(0x1001), 1 << 20, None, ctypes.byref(ctx))
+    assert rc == nb.NB_E_WORKSPACE

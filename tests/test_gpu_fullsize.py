@@ -1,0 +1,115 @@
+"""GPU parity at full benchmark sizes, in the launch configuration the
+benchmark uses (default tiles), on outputs the oracle can compute one by one:
+
+  * 16384-body annulus (the benchmark workload), FP64 and FP32C: sampled
+    target accelerations, every body's Kepler drift, the encounter partners of
+    sampled bodies, and the energy/momentum diagnostics;
+  * 131072-body ring (the largest single-system case): sampled accelerations,
+    every drift, every reported encounter pair re-checked and the partners of
+    sampled bodies complete.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_common import U, ctx_for, pair_scale, rel_rows
+
+pytestmark = pytest.mark.gpu
+nb = pytest.importorskip("paper_2601_19654_amd.nb")
+
+
+def _sample(n, k, seed, extra=()):
+    rng = np.random.default_rng(seed)
+    return np.unique(np.concatenate([rng.choice(n, k, replace=False), np.asarray(extra, int)]))
+
+
+def _near_targets(Q, rc, limit=16):
+    """A few bodies that have a neighbour inside the critical radius (if any)."""
+    from scipy.spatial import cKDTree
+    pairs = cKDTree(Q).query_pairs(float(np.max(rc)), output_type="ndarray")
+    if len(pairs) == 0:
+        return []
+    d = np.linalg.norm(Q[pairs[:, 0]] - Q[pairs[:, 1]], axis=1)
+    close = pairs[d < np.maximum(rc[pairs[:, 0]], rc[pairs[:, 1]])]
+    return close[:limit].ravel()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    w = workloads.c3()
+    Q, V = oracle.helio_to_dh(w.m0[0], w.m, w.x, w.v)
+    rc = oracle.rcrit(w.m0[0], w.m, Q)
+    return w, Q, V, rc
+
+
+@pytest.mark.parametrize("mode,tol", [(0, 1e-12), (1, 4e-6)])
+def test_c3_force_sampled(c3, mode, tol):
+    w, Q, V, rc = c3
+    c = ctx_for(w, mode=mode)
+    a = c.accel()
+    idx = _sample(w.ntot, 48, 11, _near_targets(Q, rc))
+    ref = oracle.force_subset(w.m, Q, rc, w.G, idx)
+    A = pair_scale(w.m, Q, w.G, idx)
+    err = float(np.max(np.max(np.abs(a[idx] - ref), axis=1) / A))
+    print(f"c3 mode {mode}: accel error {err:.3e} A_i over {len(idx)} targets")
+    assert err <= tol
+
+
+def test_c3_drift_encounters_energy(c3):
+    w, Q, V, rc = c3
+    c = ctx_for(w)
+    d = c.diagnostics()
+    ref = oracle.energy(w.G, w.m0[0], w.m, Q, V, rc)
+    assert abs(d["E"][0] - ref["E"]) <= 1e-13 * abs(ref["E"])
+    assert abs(d["EK"][0] - ref["EK"]) <= 1e-13 * abs(ref["EK"])
+    assert np.max(np.abs(d["L"][0] - ref["L"])) <= 1e-13 * np.linalg.norm(ref["L"])
+    assert c.drift(w.dt) == 0
+    x, v = c.download(nb.NB_DH)
+    q1, v1, fl = oracle.drift(w.G, w.dt, Q, V)
+    assert not fl.any()
+    assert rel_rows(x, q1) <= 1e-13 and rel_rows(v, v1) <= 1e-13
+    e = c.encounters()
+    got = set(zip(e.ice.tolist(), e.jce.tolist()))
+    for i in _sample(w.ntot, 32, 5, [p for pr in list(got)[:16] for p in pr]):
+        f, t = oracle.pair_scan(w.dt, Q, V, q1, v1, rc, int(i))
+        want = {(min(i, j), max(i, j)) for j in np.nonzero(f)[0]}
+        have = {p for p in got if i in p}
+        tie = {(min(i, j), max(i, j)) for j in np.nonzero(t)[0]}
+        assert not ((want ^ have) - tie), i
+    print(f"c3: {e.nce} flagged pairs")
+
+
+def test_c5_max_size():
+    w = workloads.c5()
+    Q, V = oracle.helio_to_dh(w.m0[0], w.m, w.x, w.v)
+    rc = oracle.rcrit(w.m0[0], w.m, Q)
+    for mode, tol in ((1, 4e-6), (0, 1e-12)):
+        c = ctx_for(w, mode=mode, enc_cap=1 << 18)
+        a = c.accel()
+        idx = _sample(w.ntot, 12, 21, _near_targets(Q, rc, 4))
+        ref = oracle.force_subset(w.m, Q, rc, w.G, idx)
+        A = pair_scale(w.m, Q, w.G, idx, chunk=8)
+        err = float(np.max(np.max(np.abs(a[idx] - ref), axis=1) / A))
+        print(f"c5 mode {mode}: accel error {err:.3e} A_i")
+        assert err <= tol
+    assert c.drift(w.dt) == 0
+    x, v = c.download(nb.NB_DH)
+    q1, v1, fl = oracle.drift(w.G, w.dt, Q, V)
+    assert rel_rows(x, q1) <= 1e-13 and rel_rows(v, v1) <= 1e-13
+    e = c.encounters()
+    got = list(zip(e.ice.tolist(), e.jce.tolist()))
+    assert got == sorted(got) and e.nce == len(got)
+    print(f"c5: {e.nce} flagged pairs")
+    # every reported pair satisfies the predicate (or sits in the tie band)
+    for i, j in got[:2000]:
+        d2 = oracle.pair_min_d2(w.dt, Q[i], V[i], q1[i], v1[i], Q[j], V[j], q1[j], v1[j])
+        thr = max(rc[i], rc[j]) ** 2
+        assert d2 <= thr * (1 + 1e-10)
+    gs = set(got)
+    for i in _sample(w.ntot, 12, 9, [p for pr in got[:6] for p in pr]):
+        f, t = oracle.pair_scan(w.dt, Q, V, q1, v1, rc, int(i))
+        want = {(min(i, j), max(i, j)) for j in np.nonzero(f)[0]}
+        have = {p for p in gs if i in p}
+        tie = {(min(i, j), max(i, j)) for j in np.nonzero(t)[0]}
+        assert not ((want ^ have) - tie), i
