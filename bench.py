@@ -37,10 +37,10 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def traffic_from_profiles(mode: str):
+def traffic_from_profiles(mode: str, workload: str = "c3"):
     """HBM bytes per force launch from a committed rocprofv3 PMC summary, if it
     was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"force_{mode}_c3_n16384_pmc.md")
+    path = os.path.join(ROOT, "profiles", f"force_{mode}_{workload}_pmc.md")
     if not os.path.exists(path):
         return None
     txt = open(path).read()
@@ -52,11 +52,12 @@ def traffic_from_profiles(mode: str):
 
 
 def run_mode(w, mode: str, steps: int, warmup: int, torch, nb):
-    p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64)
-    ctx = nb.Context(w.off, p, enc_cap=1 << 16, device="cuda:0")
+    p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64, drag=int(w.drag))
+    ctx = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0")
+    tiles = {"source": ctx.tiles, "force_r": ctx.params.force_r, "force_jchunk": ctx.params.force_jchunk,
+             "enc_jchunk": ctx.params.enc_jchunk}
     ctx.upload(w.m0, w.m, w.x, w.v)
-    n = w.ntot
-    pairs = n * (n - 1)
+    pairs = w.pairs()
     # warmup (untimed), also builds the step graph
     if warmup > 0:
         ctx.step_async(w.dt, warmup)
@@ -81,12 +82,12 @@ def run_mode(w, mode: str, steps: int, warmup: int, torch, nb):
         "wall_s": wall, "device_ms": dev_ms, "ms_per_step": 1e3 * wall / steps,
         "gpair_s": pairs * steps / wall / 1e9, "steps_per_s": steps / wall,
         "force_ms": force_ms, "encounter_ms": enc_ms, "stats": stats,
-        "a": a_gpu, "Q": x,
+        "a": a_gpu, "Q": x, "tiles": tiles,
     }
 
 
-def roofline(mode, n, force_ms):
-    flops = FLOPS_PER_PAIR * n * (n - 1)
+def roofline(mode, pairs, force_ms):
+    flops = FLOPS_PER_PAIR * pairs
     achieved = flops / (force_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[mode]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
@@ -97,31 +98,50 @@ def roofline(mode, n, force_ms):
 
 
 def accel_error(w, a_gpu, Q, sample=64, seed=1):
-    """Max |a_gpu - a_oracle| / A_i over a sample of targets (CPU oracle)."""
+    """Max |a_gpu - a_oracle| / A_i over a sample of targets of the largest
+    system (CPU oracle, A_i = sum_j G m_j / r_ij^2)."""
     import oracle
+    s = int(np.argmax(np.diff(w.off)))
+    lo, hi = int(w.off[s]), int(w.off[s + 1])
+    m, Qs = w.m[lo:hi], Q[lo:hi]
     rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(w.ntot, sample, replace=False))
-    rc = oracle.rcrit(w.m0[0], w.m, Q)
-    ref = oracle.force_subset(w.m, Q, rc, w.G, idx)
-    d = Q[None, :, :] - Q[idx, None, :]
-    r2 = np.einsum("ijk,ijk->ij", d, d)
-    r2[np.arange(len(idx)), idx] = np.inf
-    A = np.sum(w.G * w.m[None, :] / r2, axis=1)
-    return float(np.max(np.max(np.abs(a_gpu[idx] - ref), axis=1) / A))
+    idx = np.sort(rng.choice(hi - lo, min(sample, hi - lo), replace=False))
+    rc = oracle.rcrit(w.m0[s], m, Qs)
+    ref = oracle.force_subset(m, Qs, rc, w.G, idx)
+    A = np.empty(len(idx))
+    for k, i in enumerate(idx):
+        d = Qs - Qs[i]
+        r2 = np.einsum("jk,jk->j", d, d)
+        r2[i] = np.inf
+        A[k] = np.sum(w.G * m / r2)
+    return float(np.max(np.max(np.abs(a_gpu[lo:hi][idx] - ref), axis=1) / A))
 
 
-def cpu_baseline(w):
-    """One full hybrid step of the same workload by the CPU oracle (1 thread)."""
+def cpu_baseline(w, max_pairs=4e8):
+    """Full hybrid steps of the same workload by the CPU oracle (1 thread),
+    on as many whole systems as fit about max_pairs pair interactions."""
     import oracle
+    import workloads as W
     oracle.build(force=False)
-    st = oracle.State.from_workload(w)      # includes the first force evaluation
+    sizes = np.diff(w.off)
+    keep, tot = [], 0
+    for s in range(w.nsys):
+        p = int(sizes[s]) * (int(sizes[s]) - 1)
+        if keep and tot + p > max_pairs:
+            break
+        keep.append(s)
+        tot += p
+    lo, hi = int(w.off[keep[0]]), int(w.off[keep[-1] + 1])
+    sub = W.Workload(w.name, (w.off[keep[0]:keep[-1] + 2] - lo).astype(np.int32), w.m0[keep],
+                     w.m[lo:hi], w.x[lo:hi], w.v[lo:hi], w.dt, 1, G=w.G, drag=w.drag)
+    st = oracle.State.from_workload(sub)      # includes the first force evaluation
     t0 = time.perf_counter()
     st.step(w.dt)
     dt = time.perf_counter() - t0
-    n = w.ntot
-    return {"value": round(n * (n - 1) / dt / 1e9, 5), "unit": "Gpair/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 full hybrid step of the N={n} workload (FP64, serial), {dt:.2f} s",
-            "steps_per_s": round(1.0 / dt, 5)}
+    what = f"{len(keep)} of {w.nsys} systems" if w.nsys > 1 else f"the N={w.ntot} system"
+    return {"value": round(sub.pairs() / dt / 1e9, 5), "unit": "Gpair/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 full hybrid step of {what} (FP64, serial), {dt:.2f} s",
+            "steps_per_s": round(1.0 / dt, 5) if w.nsys == 1 else None}
 
 
 def main():
@@ -130,7 +150,7 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--modes", default="fp32c,fp64")
-    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--workload", default="c3", help="c1..c5 (the headline is c3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
@@ -146,11 +166,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     nb.lib()
 
-    w = workloads.c3(args.n)
+    w = workloads.by_name(args.workload)
     modes = [m for m in args.modes.split(",") if m]
     res = {}
     for mode in modes:
-        print(f"[bench] mode {mode}: N={w.ntot}, warmup {args.warmup}, steps {args.steps}",
+        print(f"[bench] {w.name} mode {mode}: ntot={w.ntot}, warmup {args.warmup}, steps {args.steps}",
               file=sys.stderr, flush=True)
         res[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb)
         print(f"[bench] mode {mode}: {res[mode]['ms_per_step']:.4f} ms/step, "
@@ -165,6 +185,13 @@ def main():
     head = "fp32c" if "fp32c" in res else modes[0]
     r = res[head]
     n = w.ntot
+    pairs = w.pairs()
+    desc = {"c1": "c1: star + 100 planetesimals, m 1e-10..1e-8 log-uniform, a 1-3 AU, dt 0.05 yr",
+            "c2": "c2: star + Jupiter at 5.2 AU + 1000 planetesimals of 1e-9, a 2-10 AU, gas drag, dt 0.1 yr",
+            "c3": f"c3: star + {n} equal-mass planetesimals (10 Earth masses), "
+                  "a 0.5-5 AU, e,i Rayleigh 0.01/0.005, dt 0.0175 yr",
+            "c4": f"c4: {w.nsys} independent systems, N_s uniform 200..4000 (sum {n}), c1 distributions, dt 0.05 yr",
+            "c5": f"c5: star + {n} planetesimals of 1e-11 in a 0.9-1.1 AU ring, dt 0.04 yr"}[args.workload]
     out = {
         "metric": METRIC, "value": round(r["gpair_s"], 3), "unit": "Gpair/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -172,10 +199,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64" if head == "fp32c" else "f64",
         "data": "synthetic",
-        "config": {"workload": f"c3: star + {n} equal-mass planetesimals (10 Earth masses), "
-                               "a 0.5-5 AU, e,i Rayleigh 0.01/0.005, dt 0.0175 yr",
-                   "n_bodies": n, "pairs_per_step": n * (n - 1), "mode": head,
-                   "parallelism": "single GPU"},
+        "config": {"workload": desc, "n_bodies": n, "n_systems": w.nsys, "pairs_per_step": pairs,
+                   "mode": head, "tiles": r["tiles"], "parallelism": "single GPU"},
         "steps_per_s": round(r["steps_per_s"], 3),
     }
     for mode, rr in res.items():
@@ -183,12 +208,13 @@ def main():
                      "ms_per_step": round(rr["ms_per_step"], 5),
                      "force_kernel_ms": round(rr["force_ms"], 5),
                      "encounter_kernel_ms": round(rr["encounter_ms"], 5),
-                     "force_gpair_s": round(n * (n - 1) / (rr["force_ms"] * 1e-3) / 1e9, 2),
+                     "force_gpair_s": round(pairs / (rr["force_ms"] * 1e-3) / 1e9, 2),
+                     "tiles": rr["tiles"],
                      "nce_per_step": rr["stats"]["total_nce"] / args.steps,
                      "accel_err_vs_oracle": accel_error(w, rr["a"], rr["Q"])}
-    out["roofline"] = roofline(head, n, r["force_ms"])
+    out["roofline"] = roofline(head, pairs, r["force_ms"])
     if "fp64" in res and head != "fp64":
-        out["roofline_fp64"] = roofline("fp64", n, res["fp64"]["force_ms"])
+        out["roofline_fp64"] = roofline("fp64", pairs, res["fp64"]["force_ms"])
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w)
     out["kernel_source_sha256_16"] = kernel_hash()
     print(json.dumps(out), flush=True)

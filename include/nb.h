@@ -147,7 +147,9 @@ int nb_sun_drift(nb_ctx *ctx, double h);
 int nb_drift(nb_ctx *ctx, double dt, int *nfail);
 
 /* Encounter check on the last drift: pairs i<j of one system whose minimum
- * separation between (Q0,V0) and (Q,V) is <= max(rc_i, rc_j).  Writes up to cap
+ * separation between (Q0,V0) and (Q,V) is <= max(rc_i, rc_j).  Needs nb_drift
+ * since the last call that changed the state (upload, force, kick, sun drift,
+ * step), else NB_E_NOT_READY; after nb_step use nb_get_encounters.  Writes up to cap
  * pairs to ice/jce (global indices, sorted by (i,j)) and per-body flags ce[ntot]
  * (2 = in an encounter, else 0); *nce = the true count.  Any of ice/jce/ce may be
  * NULL.  Returns NB_E_CAPACITY if the count exceeds cap or the context's list. */
@@ -185,7 +187,8 @@ int nb_get_rcrit(nb_ctx *ctx, double *rc, int where);
 /* Measurement helper: enqueue kernel `which` alone `reps` times on the context's
  * stream between two HIP events (after one untimed launch) and return the mean
  * duration per launch in milliseconds.  The state is used as it is; NB_K_DRIFT
- * and NB_K_STEP advance it (by dt per launch, dt = last_dt or the argument). */
+ * and NB_K_STEP advance it by dt per launch; NB_K_ENCOUNTER overwrites the last
+ * encounter list (with the dt of the last drift or step). */
 int nb_time_kernel(nb_ctx *ctx, int which, int reps, double dt, double *ms_per_launch);
 
 /* Release the context (not the workspace). */

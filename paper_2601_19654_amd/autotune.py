@@ -1,0 +1,123 @@
+"""Tile-size search for the pair kernels, cached per (GPU arch, mode, size class).
+
+For a given batch of systems it times, with HIP events on the context's stream
+(nb_time_kernel), the force kernel over targets-per-lane x sources-per-work-item
+candidates and the encounter kernel over sources-per-work-item candidates, and
+stores the fastest choice in ``tuning.json`` under
+``<arch>/<mode>/n<max system size, next power of two>/s<systems, next power of two>``.
+``Context`` applies a cached entry whenever the caller leaves the tile fields at 0.
+
+    python -m paper_2601_19654_amd.autotune --workloads c1,c2,c3,c4,c5
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+CACHE = os.path.join(PKG, "tuning.json")
+
+FORCE_R = (1, 2, 4)
+FORCE_J = (256, 512, 1024, 2048, 4096)
+ENC_J = (256, 512, 1024, 2048, 4096)
+
+
+def _pow2(n: int) -> int:
+    p = 1
+    while p < n:
+        p <<= 1
+    return p
+
+
+def arch() -> str:
+    import torch
+    name = torch.cuda.get_device_properties(0).gcnArchName
+    return name.split(":")[0]
+
+
+def key(mode: str, off, arch_name: str | None = None) -> str:
+    sizes = np.diff(np.asarray(off))
+    return f"{arch_name or arch()}/{mode}/n{_pow2(int(sizes.max()))}/s{_pow2(len(sizes))}"
+
+
+def load_cache() -> dict:
+    if os.path.exists(CACHE):
+        with open(CACHE) as f:
+            return json.load(f)
+    return {}
+
+
+def lookup(mode: str, off, arch_name: str | None = None):
+    return load_cache().get(key(mode, off, arch_name))
+
+
+def _mode_id(mode):
+    return 1 if mode == "fp32c" else 0
+
+
+def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
+    """Time every candidate on workload w; returns the best entry (not saved)."""
+    from . import nb
+    res_force, res_enc = {}, {}
+    for r in FORCE_R:
+        for j in FORCE_J:
+            if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
+                continue
+            p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j)
+            c = nb.Context(w.off, p, enc_cap=1 << 16, device="cuda:0", tuned=False)
+            c.upload(w.m0, w.m, w.x, w.v)
+            ms = c.time_kernel(nb.NB_K_FORCE, reps=reps)
+            res_force[(r, j)] = ms
+            if verbose:
+                print(f"[autotune] {mode} force r={r} j={j}: {ms:.4f} ms", file=sys.stderr, flush=True)
+            c.close()
+    for j in ENC_J:
+        if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
+            continue
+        p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), enc_jchunk=j)
+        c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False)
+        c.upload(w.m0, w.m, w.x, w.v)
+        c.drift(w.dt, allow_fail=True)
+        ms = c.time_kernel(nb.NB_K_ENCOUNTER, reps=reps)
+        res_enc[j] = ms
+        if verbose:
+            print(f"[autotune] {mode} encounter j={j}: {ms:.4f} ms", file=sys.stderr, flush=True)
+        c.close()
+    (r, j), fms = min(res_force.items(), key=lambda kv: kv[1])
+    ej, ems = min(res_enc.items(), key=lambda kv: kv[1])
+    return {"force_r": r, "force_jchunk": j, "enc_jchunk": ej, "force_ms": round(fms, 5),
+            "encounter_ms": round(ems, 5), "workload": w.name, "tuned_at": time.strftime("%Y-%m-%d"),
+            "force_candidates": {f"r{a}_j{b}": round(v, 5) for (a, b), v in res_force.items()},
+            "encounter_candidates": {f"j{a}": round(v, 5) for a, v in res_enc.items()}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workloads", default="c1,c2,c3,c4,c5")
+    ap.add_argument("--modes", default="fp64,fp32c")
+    ap.add_argument("--reps", type=int, default=10)
+    ap.add_argument("--out", default=CACHE)
+    args = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(PKG))
+    import workloads
+    cache = load_cache()
+    a = arch()
+    for name in args.workloads.split(","):
+        w = workloads.by_name(name)
+        for mode in args.modes.split(","):
+            best = tune(w, mode, reps=args.reps)
+            cache[key(mode, w.off, a)] = best
+            print(f"[autotune] {key(mode, w.off, a)} -> r={best['force_r']} j={best['force_jchunk']} "
+                  f"enc_j={best['enc_jchunk']} ({best['force_ms']:.4f} / {best['encounter_ms']:.4f} ms)",
+                  file=sys.stderr, flush=True)
+            with open(args.out, "w") as f:
+                json.dump(cache, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

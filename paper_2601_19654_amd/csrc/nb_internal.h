@@ -47,6 +47,7 @@ struct Dev {
     double *ax, *ay, *az, *rc;
     double *q0x, *q0y, *q0z, *v0x, *v0y, *v0z;
     float4 *pk;           // FP32C source records: 2 per body {xhi,yhi,zhi,m},{xlo,ylo,zlo,rc2}
+    double4 *mr;          // per body after a drift: chord midpoint (x,y,z) and encounter reach R
     int *kflag, *ce, *sys_of;
     double *m0;           // nsys
     int *off;             // nsys+1

@@ -43,21 +43,16 @@ __device__ __forceinline__ void dd_add(dd &a, const dd &b)
     a.lo += b.lo;
 }
 
-// 1/sqrt(x) in FP64: the hardware estimate refined by one step of the
-// third-order expansion (1-e)^(-1/2) ~ 1 + e/2 + 3e^2/8 with e = 1 - x y^2.
-__device__ __forceinline__ double rsqrt64(double x)
+// 1/sqrt(x) in FP64 to the last bits (diagnostics): the hardware estimate
+// refined through (1-e)^(-1/2) ~ 1 + e/2 + 3e^2/8, e = 1 - x y^2, then one
+// Newton step.
+__device__ __forceinline__ double rsqrt64_acc(double x)
 {
     double y = __builtin_amdgcn_rsq(x);
     double e = fma(-x * y, y, 1.0);
     double t = fma(0.375, e, 0.5);
-    return fma(y * e, t, y);
-}
-
-// Same, two refinement steps (diagnostics: to the last bit).
-__device__ __forceinline__ double rsqrt64_acc(double x)
-{
-    double y = rsqrt64(x);
-    double e = fma(-x * y, y, 1.0);
+    y = fma(y * e, t, y);
+    e = fma(-x * y, y, 1.0);
     return fma(0.5 * y, e, y);
 }
 
@@ -97,14 +92,6 @@ __device__ __forceinline__ void system_sum(const double *__restrict__ part, int 
         for (int w = 0; w < W; ++w)
             out[w] += part[(size_t)(first + b) * stride + w];
     block_sum<W>(out, sh);
-}
-
-// Wave-aggregated integer atomic add (one atomic per wave).
-__device__ __forceinline__ void wave_count_add(long long *ctr, bool pred)
-{
-    unsigned long long mask = __ballot(pred);
-    if (mask && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)mask) - 1))
-        atomicAdd((unsigned long long *)ctr, (unsigned long long)__popcll(mask));
 }
 
 // Changeover weight w = K/r^3 - (dK/dr)/r^2 for a pair at squared distance r2
@@ -514,7 +501,8 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
                         double *__restrict__ q0y, double *__restrict__ q0z,
                         double *__restrict__ v0x, double *__restrict__ v0y,
                         double *__restrict__ v0z, int *__restrict__ kflag, int *__restrict__ ce,
-                        DevStats *stats, double *__restrict__ part_out)
+                        DevStats *stats, double *__restrict__ part_out,
+                        const double *__restrict__ rc, double4 *__restrict__ mr)
 {
     __shared__ double sh[3 * kBlock];
     RBlk b = rblk[blockIdx.x];
@@ -531,6 +519,20 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
         v0y[i] = v;
         v0z[i] = w;
         fail = kepler_drift(mu, dt, x, y, z, u, v, w) != 0;
+        // Encounter reach of this body over the step: chord c = Q1 - Q0 with
+        // half-length rho, endpoint velocity deviations e = dt V - c with
+        // largest norm eps; R = 2 rho + eps/2 + rc (widened by 2^-20 for
+        // rounding).  Pairs whose chord midpoints are farther apart than
+        // R_i + R_j cannot be flagged (see k_encounter).
+        {
+            double cx = x - q0x[i], cy = y - q0y[i], cz = z - q0z[i];
+            double rho = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+            double ax0 = dt * v0x[i] - cx, ay0 = dt * v0y[i] - cy, az0 = dt * v0z[i] - cz;
+            double ax1 = dt * u - cx, ay1 = dt * v - cy, az1 = dt * w - cz;
+            double eps = sqrt(fmax(ax0 * ax0 + ay0 * ay0 + az0 * az0, ax1 * ax1 + ay1 * ay1 + az1 * az1));
+            double R = (2.0 * rho + 0.5 * eps + rc[i]) * (1.0 + 0x1p-20);
+            mr[i] = make_double4(q0x[i] + 0.5 * cx, q0y[i] + 0.5 * cy, q0z[i] + 0.5 * cz, R);
+        }
         qx[i] = x;
         qy[i] = y;
         qz[i] = z;
@@ -563,9 +565,39 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
 // ----------------------------------------------------------------------------
 // Interaction force (Sec. 3.1 force block, loop 2): per target i the sum over
 // sources j != i of m_j w(r_ij) (Q_j - Q_i); G is applied in the finalize pass.
-// Pairs at or beyond rc_ij take the Newtonian term; the rare pairs inside
-// rc_ij branch to the exact changeover weight.
+// Pairs at or beyond rc_ij take the Newtonian term; pairs inside rc_ij take
+// the exact changeover weight in a divergent branch.  The branch test is one
+// compare per pair against a per-lane, per-tile threshold max(rc_i^2, max_j
+// rc_j^2); the branch itself applies the exact pair test.
 // ----------------------------------------------------------------------------
+
+// m y^3 with y = 1/sqrt(r2): the hardware estimate y0 corrected through
+// (1 - e)^(-3/2) = 1 + 3e/2 + 15e^2/8 + O(e^3), e = 1 - r2 y0^2.
+__device__ __forceinline__ double m_rinv3(double m, double r2)
+{
+    double y0 = __builtin_amdgcn_rsq(r2);
+    double y2 = y0 * y0;
+    double e = fma(-r2, y2, 1.0);
+    double c = fma(fma(1.875, e, 1.5), e, 1.0);
+    return (m * y0) * y2 * c;
+}
+
+// Largest value over the block's threads (one per thread), via wave shuffles
+// and one LDS slot per wave; `sh` holds kBlock/64 doubles.  Ends with a barrier.
+__device__ __forceinline__ double block_max(double v, double *sh)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w)
+        r = fmax(r, sh[w]);
+    return r;
+}
+
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ work,
                                                     const double *__restrict__ qx,
@@ -574,13 +606,15 @@ __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ wo
                                                     const double *__restrict__ m,
                                                     const double *__restrict__ rc,
                                                     double *__restrict__ fpart, int ntot, int maxs,
-                                                    double inner)
+                                                    double inner, DevStats *stats)
 {
     __shared__ double4 sj[kBlock];
-    __shared__ double2 sr[kBlock];
+    __shared__ double src[kBlock];
+    __shared__ double smax[2][kBlock / 64];
     const FWork wk = work[blockIdx.x];
     const int t = threadIdx.x;
-    double xi[R], yi[R], zi[R], r2i[R], rci[R], ax[R], ay[R], az[R];
+    double xi[R], yi[R], zi[R], rci[R], r2i[R], ax[R], ay[R], az[R];
+    int near = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         int li = t + k * kBlock;
@@ -588,34 +622,43 @@ __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ wo
         xi[k] = qx[i];
         yi[k] = qy[i];
         zi[k] = qz[i];
-        double r = rc[i];
-        rci[k] = r;
-        r2i[k] = fmax(r * r, DBL_MIN);
+        rci[k] = rc[i];
+        r2i[k] = fmax(rci[k] * rci[k], DBL_MIN);
         ax[k] = ay[k] = az[k] = 0.0;
     }
     const int jend = wk.j0 + wk.nj;
-    for (int jt = wk.j0; jt < jend; jt += kBlock) {
+    int buf = 0;
+    for (int jt = wk.j0; jt < jend; jt += kBlock, buf ^= 1) {
         const int cnt = min(kBlock, jend - jt);
         __syncthreads();
+        double r2j = 0.0;
         if (t < cnt) {
             int j = jt + t;
             double r = rc[j];
             sj[t] = make_double4(qx[j], qy[j], qz[j], m[j]);
-            sr[t] = make_double2(fmax(r * r, DBL_MIN), r);
+            src[t] = r;
+            r2j = r * r;
         }
-        __syncthreads();
+        const double tmax = block_max(r2j, smax[buf]);
+        double thr[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            thr[k] = fmax(r2i[k], tmax);
 #pragma unroll 2
         for (int jj = 0; jj < cnt; ++jj) {
             const double4 J = sj[jj];
-            const double2 JR = sr[jj];
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 double dx = J.x - xi[k], dy = J.y - yi[k], dz = J.z - zi[k];
                 double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                double y = rsqrt64(r2);
-                double s = J.w * (y * y) * y;
-                if (r2 < fmax(r2i[k], JR.x))
-                    s = J.w * changeover_w(r2, fmax(rci[k], JR.y), inner);
+                double s = m_rinv3(J.w, r2);
+                if (r2 < thr[k]) {
+                    double rcj = src[jj];
+                    if (r2 < fmax(r2i[k], fmax(rcj * rcj, DBL_MIN))) {
+                        s = J.w * changeover_w(r2, fmax(rci[k], rcj), inner);
+                        ++near;
+                    }
+                }
                 ax[k] = fma(s, dx, ax[k]);
                 ay[k] = fma(s, dy, ay[k]);
                 az[k] = fma(s, dz, az[k]);
@@ -632,6 +675,11 @@ __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ wo
             fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = az[k];
         }
     }
+    // pairs evaluated in the changeover zone (self pairs included), one atomic per wave
+    for (int o = 32; o > 0; o >>= 1)
+        near += __shfl_xor(near, o);
+    if ((t & 63) == 0 && near)
+        atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
 }
 
 // FP32C: pair terms in FP32 from hi/lo split positions (the difference of two
@@ -650,6 +698,20 @@ __device__ __forceinline__ void two_sum_f(float &hi, float &lo, float t)
     lo += e;
 }
 
+__device__ __forceinline__ float block_maxf(float v, float *sh)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmaxf(v, __shfl_xor(v, o));
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float r = sh[0];
+#pragma unroll
+    for (int w = 1; w < kBlock / 64; ++w)
+        r = fmaxf(r, sh[w]);
+    return r;
+}
+
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ work,
                                                      const float4 *__restrict__ pk,
@@ -663,12 +725,14 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
 {
     __shared__ float4 sa[kBlock];
     __shared__ float4 sb[kBlock];
+    __shared__ float smax[2][kBlock / 64];
     const FWork wk = work[blockIdx.x];
     const int t = threadIdx.x;
     float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], r2i[R];
     float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R], tx[R], ty[R], tz[R];
     double nx[R], ny[R], nz[R];
     int ii[R];
+    int near = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         int li = t + k * kBlock;
@@ -681,16 +745,23 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
         hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = tx[k] = ty[k] = tz[k] = 0.0f;
         nx[k] = ny[k] = nz[k] = 0.0;
     }
-    bool any_near = false;
     const int jend = wk.j0 + wk.nj;
-    for (int jt = wk.j0; jt < jend; jt += kBlock) {
+    int buf = 0;
+    for (int jt = wk.j0; jt < jend; jt += kBlock, buf ^= 1) {
         const int cnt = min(kBlock, jend - jt);
         __syncthreads();
+        float r2j = 0.0f;
         if (t < cnt) {
             sa[t] = pk[2 * (size_t)(jt + t)];
-            sb[t] = pk[2 * (size_t)(jt + t) + 1];
+            float4 B = pk[2 * (size_t)(jt + t) + 1];
+            sb[t] = B;
+            r2j = B.w;
         }
-        __syncthreads();
+        const float tmax = block_maxf(r2j, smax[buf]);
+        float thr[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k)
+            thr[k] = fmaxf(r2i[k], tmax);
         for (int jb = 0; jb < cnt; jb += kMerge) {
             const int je = min(cnt, jb + kMerge);
 #pragma unroll 2
@@ -705,17 +776,19 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
                     float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     float y = __builtin_amdgcn_rsqf(r2);
                     float s = A.w * (y * y) * y;
-                    if (r2 < fmaxf(r2i[k], B.w)) {
-                        // FP64 changeover pair from the FP64 state
-                        int i = ii[k], j = jt + jj;
-                        double ex = qx[j] - qx[i], ey = qy[j] - qy[i], ez = qz[j] - qz[i];
-                        double d2 = fma(ez, ez, fma(ey, ey, ex * ex));
-                        double wgt = m[j] * changeover_w(d2, fmax(rc[i], rc[j]), inner);
-                        nx[k] = fma(wgt, ex, nx[k]);
-                        ny[k] = fma(wgt, ey, ny[k]);
-                        nz[k] = fma(wgt, ez, nz[k]);
-                        s = 0.0f;
-                        any_near = true;
+                    if (r2 < thr[k]) {
+                        if (r2 < fmaxf(r2i[k], B.w)) {
+                            // FP64 changeover pair from the FP64 state
+                            int i = ii[k], j = jt + jj;
+                            double ex = qx[j] - qx[i], ey = qy[j] - qy[i], ez = qz[j] - qz[i];
+                            double d2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                            double wgt = m[j] * changeover_w(d2, fmax(rc[i], rc[j]), inner);
+                            nx[k] = fma(wgt, ex, nx[k]);
+                            ny[k] = fma(wgt, ey, ny[k]);
+                            nz[k] = fma(wgt, ez, nz[k]);
+                            s = 0.0f;
+                            ++near;
+                        }
                     }
                     tx[k] = fmaf(s, dx, tx[k]);
                     ty[k] = fmaf(s, dy, ty[k]);
@@ -731,7 +804,6 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
             }
         }
     }
-    (void)any_near;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
         int li = t + k * kBlock;
@@ -742,6 +814,10 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
             fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = ((double)hz[k] + (double)lz[k]) + nz[k];
         }
     }
+    for (int o = 32; o > 0; o >>= 1)
+        near += __shfl_xor(near, o);
+    if ((t & 63) == 0 && near)
+        atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
 }
 
 // a = G * sum over the system's splits (fixed order); optionally the kick
@@ -832,7 +908,18 @@ struct EncRec {
     double rc, pad;
 };
 
+// Two-stage pair test, one target per lane, sources broadcast from LDS.
+// Stage 1 (every pair): chord midpoints M and reaches R (from the drift).  The
+// Hermite data split into the straight-chord part |dQ0 + s dc|^2 (which the
+// cubic reproduces exactly and which is >= (D - rho_i - rho_j)^2, D = |dM|)
+// and the endpoint velocity deviations (weighted by Hermite basis functions
+// bounded by 4/27) give f(s) >= (D-P)^2 - (8/27)(D+P)E with P = rho_i + rho_j,
+// E = eps_i + eps_j; this exceeds (rc_i + rc_j)^2 >= rc_ij^2 whenever
+// D > R_i + R_j, R = 2 rho + eps/2 + rc.  So only pairs with
+// |dM|^2 <= (R_i + R_j)^2 go on.  Stage 2 (candidates): the 4/27 lower bound
+// on the full Hermite data, then the exact minimum.
 __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ work, double dt,
+                                                      const double4 *__restrict__ mr,
                                                       const double *__restrict__ q0x,
                                                       const double *__restrict__ q0y,
                                                       const double *__restrict__ q0z,
@@ -850,6 +937,7 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
                                                       int cap, int *__restrict__ ce,
                                                       DevStats *stats)
 {
+    __shared__ double4 smr[kBlock];
     __shared__ EncRec sj[kBlock];
     const PWork wk = work[blockIdx.x];
     const int t = threadIdx.x;
@@ -858,8 +946,9 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
     const double k427 = 4.0 / 27.0;
     const bool has_i = t < wk.ni;
     const int i = wk.i0 + (has_i ? t : 0);
-    double a0[3] = {q0x[i], q0y[i], q0z[i]}, b0[3] = {v0x[i], v0y[i], v0z[i]};
-    double a1[3] = {qx[i], qy[i], qz[i]}, b1[3] = {vx[i], vy[i], vz[i]};
+    const double4 Mi = mr[i];
+    const double a0[3] = {q0x[i], q0y[i], q0z[i]}, b0[3] = {v0x[i], v0y[i], v0z[i]};
+    const double a1[3] = {qx[i], qy[i], qz[i]}, b1[3] = {vx[i], vy[i], vz[i]};
     const double rci = rc[i];
     const int jend = wk.j0 + wk.nj;
     for (int jt = wk.j0; jt < jend; jt += kBlock) {
@@ -867,6 +956,7 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
         __syncthreads();
         if (t < cnt) {
             int j = jt + t;
+            smr[t] = mr[j];
             EncRec r;
             r.q0[0] = q0x[j]; r.q0[1] = q0y[j]; r.q0[2] = q0z[j];
             r.v0[0] = v0x[j]; r.v0[1] = v0y[j]; r.v0[2] = v0z[j];
@@ -877,25 +967,34 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
             sj[t] = r;
         }
         __syncthreads();
+        // only tiles that reach past the target index hold pairs j > i
+        const bool diag = jt < wk.i0 + wk.ni;
         for (int jj = 0; jj < cnt; ++jj) {
             const int j = jt + jj;
-            const EncRec &J = sj[jj];
-            double d0x = J.q0[0] - a0[0], d0y = J.q0[1] - a0[1], d0z = J.q0[2] - a0[2];
-            double d1x = J.q1[0] - a1[0], d1y = J.q1[1] - a1[1], d1z = J.q1[2] - a1[2];
-            double e0x = J.v0[0] - b0[0], e0y = J.v0[1] - b0[1], e0z = J.v0[2] - b0[2];
-            double e1x = J.v1[0] - b1[0], e1y = J.v1[1] - b1[1], e1z = J.v1[2] - b1[2];
-            double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
-            double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
-            double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
-            double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
-            double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
-            double rcij = fmax(rci, J.rc);
-            double thr = rcij * rcij;
-            bool cand = has_i && j > i &&
-                        lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1));
+            const double4 Mj = smr[jj];
+            double dx = Mj.x - Mi.x, dy = Mj.y - Mi.y, dz = Mj.z - Mi.z;
+            double D2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            double S = Mi.w + Mj.w;
+            bool cand = has_i && D2 <= S * S && (!diag || j > i);
+            if (!__any(cand))
+                continue;
             bool hit = false;
-            if (__builtin_expect(cand, 0))
-                hit = hermite_min(f0, f1, g0, g1) <= thr;
+            if (cand) {
+                const EncRec &J = sj[jj];
+                double d0x = J.q0[0] - a0[0], d0y = J.q0[1] - a0[1], d0z = J.q0[2] - a0[2];
+                double d1x = J.q1[0] - a1[0], d1y = J.q1[1] - a1[1], d1z = J.q1[2] - a1[2];
+                double e0x = J.v0[0] - b0[0], e0y = J.v0[1] - b0[1], e0z = J.v0[2] - b0[2];
+                double e1x = J.v1[0] - b1[0], e1y = J.v1[1] - b1[1], e1z = J.v1[2] - b1[2];
+                double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
+                double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
+                double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
+                double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
+                double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
+                double rcij = fmax(rci, J.rc);
+                double thr = rcij * rcij;
+                if (lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1)))
+                    hit = hermite_min(f0, f1, g0, g1) <= thr;
+            }
             unsigned long long mask = __ballot(hit);
             if (mask) {
                 int leader = __ffsll((long long)mask) - 1;
@@ -1231,7 +1330,7 @@ hipError_t launch_drift(const Dev &d, const Params &p, double dt, hipStream_t s)
         return hipSuccess;
     k_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, dt, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
                                       d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
-                                      d.stats, d.rpart);
+                                      d.stats, d.rpart, d.rc, d.mr);
     return hipGetLastError();
 }
 
@@ -1257,15 +1356,15 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
         switch (p.force_r) {
         case 1:
             k_force64<1><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
-                                                   d.ntot, d.maxs, p.inner);
+                                                   d.ntot, d.maxs, p.inner, d.stats);
             break;
         case 4:
             k_force64<4><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
-                                                   d.ntot, d.maxs, p.inner);
+                                                   d.ntot, d.maxs, p.inner, d.stats);
             break;
         default:
             k_force64<2><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
-                                                   d.ntot, d.maxs, p.inner);
+                                                   d.ntot, d.maxs, p.inner, d.stats);
         }
     }
     return hipGetLastError();
@@ -1284,10 +1383,9 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, h
 hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s)
 {
     if (d.new_ > 0)
-        k_encounter<<<d.new_, kBlock, 0, s>>>(d.ework, dt, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y,
-                                               d.v0z, d.qx, d.qy, d.qz, d.vx, d.vy, d.vz, d.rc,
-                                               d.keys, d.keys_p2 < d.enc_cap ? d.keys_p2 : d.enc_cap,
-                                               d.ce, d.stats);
+        k_encounter<<<d.new_, kBlock, 0, s>>>(d.ework, dt, d.mr, d.q0x, d.q0y, d.q0z, d.v0x,
+                                               d.v0y, d.v0z, d.qx, d.qy, d.qz, d.vx, d.vy, d.vz,
+                                               d.rc, d.keys, d.enc_cap, d.ce, d.stats);
     k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats);
     return hipGetLastError();
 }

@@ -219,6 +219,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     for (double **pl : planes)
         *pl = (double *)take(nd);
     d.pk = (float4 *)take((size_t)ntot * 2 * sizeof(float4));
+    d.mr = (double4 *)take((size_t)ntot * sizeof(double4));
     d.kflag = (int *)take((size_t)ntot * sizeof(int));
     d.ce = (int *)take((size_t)ntot * sizeof(int));
     d.sys_of = (int *)take((size_t)ntot * sizeof(int));
@@ -570,6 +571,7 @@ int nb_force(nb_ctx *c)
         return r;
     if (!c->have_state)
         return set_err(c, NB_E_NOT_READY, "nb_force: no state");
+    c->have_drift = false;
     return enqueue_force(c);
 }
 
@@ -582,6 +584,7 @@ int nb_kick(nb_ctx *c, double h)
         return set_err(c, NB_E_NOT_READY, "nb_kick: no state");
     if (!std::isfinite(h))
         return set_err(c, NB_E_INVALID, "nb_kick: h not finite");
+    c->have_drift = false;
     HIP_OK(c, launch_kick(c->d, c->p, h, c->stream));
     return NB_OK;
 }
@@ -595,6 +598,7 @@ int nb_sun_drift(nb_ctx *c, double h)
         return set_err(c, NB_E_NOT_READY, "nb_sun_drift: no state");
     if (!std::isfinite(h))
         return set_err(c, NB_E_INVALID, "nb_sun_drift: h not finite");
+    c->have_drift = false;
     HIP_OK(c, launch_momentum(c->d, c->stream));
     HIP_OK(c, launch_sun_drift(c->d, h, 0, c->p, c->stream));
     return NB_OK;
@@ -689,7 +693,8 @@ int nb_step(nb_ctx *c, double dt, int nsteps, nb_stats *st)
         st->near_pairs = ds.near_pairs;
     }
     if (nsteps > 0) {
-        c->have_drift = true;
+        // the snapshot and the state no longer form a drift pair
+        c->have_drift = false;
         c->have_enc = true;
         c->last_dt = dt;
     }
@@ -774,7 +779,7 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
         return set_err(c, NB_E_NOT_READY, "nb_time_kernel: no state");
     if (!ms || reps <= 0 || which < NB_K_FORCE || which > NB_K_STEP || !std::isfinite(dt))
         return set_err(c, NB_E_INVALID, "nb_time_kernel: bad argument");
-    if (which == NB_K_ENCOUNTER && !c->have_drift)
+    if (which == NB_K_ENCOUNTER && !c->have_drift && !c->have_enc)
         return set_err(c, NB_E_NOT_READY, "nb_time_kernel: no drift before the encounter check");
     auto once = [&]() -> int {
         switch (which) {

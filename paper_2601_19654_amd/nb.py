@@ -143,12 +143,24 @@ class Context:
     """
 
     def __init__(self, off, params: nb_params | None = None, enc_cap: int = 1 << 16,
-                 stream=None, device=None):
+                 stream=None, device=None, tuned: bool = True):
         import torch
         self._torch = torch
         L = lib()
         self.params = params or default_params()
         self.off = np.ascontiguousarray(off, dtype=np.int32)
+        self.tiles = "library defaults"
+        if tuned and not (self.params.force_r or self.params.force_jchunk or self.params.enc_jchunk):
+            from . import autotune
+            try:
+                hit = autotune.lookup("fp32c" if self.params.mode == NB_FP32C else "fp64", self.off)
+            except Exception:
+                hit = None
+            if hit:
+                self.params.force_r = hit["force_r"]
+                self.params.force_jchunk = hit["force_jchunk"]
+                self.params.enc_jchunk = hit["enc_jchunk"]
+                self.tiles = "tuned"
         self.nsys = len(self.off) - 1
         self.ntot = int(self.off[-1])
         self.enc_cap = int(enc_cap)
