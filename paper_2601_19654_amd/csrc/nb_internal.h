@@ -15,10 +15,11 @@ struct RBlk {
 };
 
 // A force work item: targets [i0, i0+ni), sources [j0, j0+nj) of one system;
-// the partial sum goes to split slot `slot`.
+// the partial sum goes to split slot `slot`.  Source tiles of kBlock bodies
+// coincide with O(N) blocks; rb0 is the O(N) block index of the first one.
 struct FWork {
     int i0, ni, j0, nj;
-    int slot, sys, pad0, pad1;
+    int slot, sys, rb0, pad;
 };
 
 // An unordered-pair work item: targets [i0, i0+ni), sources [j0, j0+nj); only
@@ -45,6 +46,7 @@ struct Dev {
     // state planes (FP64, ntot each)
     double *m, *qx, *qy, *qz, *vx, *vy, *vz;
     double *ax, *ay, *az, *rc;
+    double *tile_rc2;     // per O(N) block: largest rc^2 of its bodies (set with rc)
     double *q0x, *q0y, *q0z, *v0x, *v0y, *v0z;
     float4 *pk;           // FP32C source records: 2 per body {xhi,yhi,zhi,m},{xlo,ylo,zlo,rc2}
     double4 *mr;          // per body after a drift: chord midpoint (x,y,z) and encounter reach R

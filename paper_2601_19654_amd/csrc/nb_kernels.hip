@@ -331,9 +331,11 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
                             const int *__restrict__ rb_count, const double *__restrict__ m0,
                             const double *__restrict__ part, double h, double *qx, double *qy,
                             double *qz, int rcrit, const double *__restrict__ m, double n_hill,
-                            double *__restrict__ rc, float4 *__restrict__ pk)
+                            double *__restrict__ rc, float4 *__restrict__ pk,
+                            double *__restrict__ tile_rc2)
 {
     __shared__ double sh[3 * kBlock];
+    double rc2 = 0.0;
     RBlk b = rblk[blockIdx.x];
     double c[3] = {0.0, 0.0, 0.0};
     double mm = m0[b.sys];
@@ -355,6 +357,7 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
             double r = sqrt(x * x + y * y + z * z);
             double rci = n_hill * r * cbrt(mi / (3.0 * mm));
             rc[i] = rci;
+            rc2 = rci * rci;
             if (pk) {
                 float hx = (float)x, hy = (float)y, hz = (float)z;
                 float lx = (float)(x - (double)hx), ly = (float)(y - (double)hy),
@@ -366,6 +369,20 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
                 pk[2 * (size_t)i] = make_float4(hx, hy, hz, (float)mi);
                 pk[2 * (size_t)i + 1] = make_float4(lx, ly, lz, r2);
             }
+        }
+    }
+    if (rcrit) {
+        // largest rc^2 of this block's bodies: the force kernel's per-tile zone threshold
+        for (int o = 32; o > 0; o >>= 1)
+            rc2 = fmax(rc2, __shfl_xor(rc2, o));
+        if ((threadIdx.x & 63) == 0)
+            sh[threadIdx.x >> 6] = rc2;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double r = sh[0];
+            for (int w = 1; w < kBlock / 64; ++w)
+                r = fmax(r, sh[w]);
+            tile_rc2[blockIdx.x] = r;
         }
     }
 }
@@ -521,7 +538,7 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
         fail = kepler_drift(mu, dt, x, y, z, u, v, w) != 0;
         // Encounter reach of this body over the step: chord c = Q1 - Q0 with
         // half-length rho, endpoint velocity deviations e = dt V - c with
-        // largest norm eps; R = 2 rho + eps/2 + rc (widened by 2^-20 for
+        // largest norm eps; R = 2 rho + 3 eps/4 + rc (widened by 2^-20 for
         // rounding).  Pairs whose chord midpoints are farther apart than
         // R_i + R_j cannot be flagged (see k_encounter).
         {
@@ -530,7 +547,7 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
             double ax0 = dt * v0x[i] - cx, ay0 = dt * v0y[i] - cy, az0 = dt * v0z[i] - cz;
             double ax1 = dt * u - cx, ay1 = dt * v - cy, az1 = dt * w - cz;
             double eps = sqrt(fmax(ax0 * ax0 + ay0 * ay0 + az0 * az0, ax1 * ax1 + ay1 * ay1 + az1 * az1));
-            double R = (2.0 * rho + 0.5 * eps + rc[i]) * (1.0 + 0x1p-20);
+            double R = (2.0 * rho + 0.75 * eps + rc[i]) * (1.0 + 0x1p-20);
             mr[i] = make_double4(q0x[i] + 0.5 * cx, q0y[i] + 0.5 * cy, q0z[i] + 0.5 * cz, R);
         }
         qx[i] = x;
@@ -571,32 +588,22 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
 // rc_j^2); the branch itself applies the exact pair test.
 // ----------------------------------------------------------------------------
 
-// m y^3 with y = 1/sqrt(r2): the hardware estimate y0 corrected through
-// (1 - e)^(-3/2) = 1 + 3e/2 + 15e^2/8 + O(e^3), e = 1 - r2 y0^2.
-__device__ __forceinline__ double m_rinv3(double m, double r2)
+// m y^3 with y = 1/sqrt(r2): the hardware estimate y0 (worst relative error
+// 2^-24.2 on gfx950) corrected through (1 - e)^(-3/2) = 1 + 3e/2 + O(e^2),
+// e = 1 - r2 y0^2; the dropped 15e^2/8 term is below 2.1e-14.  m15 = 1.5 m.
+__device__ __forceinline__ double m_rinv3(double m, double m15, double r2)
 {
     double y0 = __builtin_amdgcn_rsq(r2);
     double y2 = y0 * y0;
     double e = fma(-r2, y2, 1.0);
-    double c = fma(fma(1.875, e, 1.5), e, 1.0);
-    return (m * y0) * y2 * c;
+    return (y0 * y2) * fma(m15, e, m);
 }
 
-// Largest value over the block's threads (one per thread), via wave shuffles
-// and one LDS slot per wave; `sh` holds kBlock/64 doubles.  Ends with a barrier.
-__device__ __forceinline__ double block_max(double v, double *sh)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmax(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0)
-        sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    double r = sh[0];
-#pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w)
-        r = fmax(r, sh[w]);
-    return r;
-}
+// Work item layout shared by both force kernels: the block's 64*R targets are
+// the same for its kBlock/64 waves; each source tile of kBlock bodies is staged
+// in LDS and wave w takes its sources [64w, 64w+64).  The waves' sums are added
+// in wave order through LDS at the end, so results do not depend on timing.
+constexpr int kWaves = kBlock / 64;
 
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ work,
@@ -605,19 +612,20 @@ __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ wo
                                                     const double *__restrict__ qz,
                                                     const double *__restrict__ m,
                                                     const double *__restrict__ rc,
+                                                    const double *__restrict__ tile_rc2,
                                                     double *__restrict__ fpart, int ntot, int maxs,
                                                     double inner, DevStats *stats)
 {
     __shared__ double4 sj[kBlock];
-    __shared__ double src[kBlock];
-    __shared__ double smax[2][kBlock / 64];
+    __shared__ double2 sx[kBlock];                 // {1.5 m, rc}
+    __shared__ double red[kWaves - 1][3 * R][64];
     const FWork wk = work[blockIdx.x];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     double xi[R], yi[R], zi[R], rci[R], r2i[R], ax[R], ay[R], az[R];
     int near = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        int li = t + k * kBlock;
+        int li = lane + 64 * k;
         int i = wk.i0 + (li < wk.ni ? li : 0);
         xi[k] = qx[i];
         yi[k] = qy[i];
@@ -627,33 +635,34 @@ __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ wo
         ax[k] = ay[k] = az[k] = 0.0;
     }
     const int jend = wk.j0 + wk.nj;
-    int buf = 0;
-    for (int jt = wk.j0; jt < jend; jt += kBlock, buf ^= 1) {
+    int tile = wk.rb0;
+    for (int jt = wk.j0; jt < jend; jt += kBlock, ++tile) {
         const int cnt = min(kBlock, jend - jt);
         __syncthreads();
-        double r2j = 0.0;
         if (t < cnt) {
             int j = jt + t;
-            double r = rc[j];
-            sj[t] = make_double4(qx[j], qy[j], qz[j], m[j]);
-            src[t] = r;
-            r2j = r * r;
+            double mj = m[j];
+            sj[t] = make_double4(qx[j], qy[j], qz[j], mj);
+            sx[t] = make_double2(1.5 * mj, rc[j]);
         }
-        const double tmax = block_max(r2j, smax[buf]);
+        const double tmax = tile_rc2[tile];
         double thr[R];
 #pragma unroll
         for (int k = 0; k < R; ++k)
             thr[k] = fmax(r2i[k], tmax);
+        __syncthreads();
+        const int je = min(cnt, 64 * wv + 64);
 #pragma unroll 2
-        for (int jj = 0; jj < cnt; ++jj) {
+        for (int jj = 64 * wv; jj < je; ++jj) {
             const double4 J = sj[jj];
+            const double m15 = sx[jj].x;
 #pragma unroll
             for (int k = 0; k < R; ++k) {
                 double dx = J.x - xi[k], dy = J.y - yi[k], dz = J.z - zi[k];
                 double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                double s = m_rinv3(J.w, r2);
+                double s = m_rinv3(J.w, m15, r2);
                 if (r2 < thr[k]) {
-                    double rcj = src[jj];
+                    double rcj = sx[jj].y;
                     if (r2 < fmax(r2i[k], fmax(rcj * rcj, DBL_MIN))) {
                         s = J.w * changeover_w(r2, fmax(rci[k], rcj), inner);
                         ++near;
@@ -665,20 +674,36 @@ __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ wo
             }
         }
     }
+    if (wv > 0) {
 #pragma unroll
-    for (int k = 0; k < R; ++k) {
-        int li = t + k * kBlock;
-        if (li < wk.ni) {
-            int i = wk.i0 + li;
-            fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = ax[k];
-            fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = ay[k];
-            fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = az[k];
+        for (int k = 0; k < R; ++k) {
+            red[wv - 1][3 * k + 0][lane] = ax[k];
+            red[wv - 1][3 * k + 1][lane] = ay[k];
+            red[wv - 1][3 * k + 2][lane] = az[k];
+        }
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            for (int w = 0; w < kWaves - 1; ++w) {
+                ax[k] += red[w][3 * k + 0][lane];
+                ay[k] += red[w][3 * k + 1][lane];
+                az[k] += red[w][3 * k + 2][lane];
+            }
+            int li = lane + 64 * k;
+            if (li < wk.ni) {
+                int i = wk.i0 + li;
+                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = ax[k];
+                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = ay[k];
+                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = az[k];
+            }
         }
     }
     // pairs evaluated in the changeover zone (self pairs included), one atomic per wave
     for (int o = 32; o > 0; o >>= 1)
         near += __shfl_xor(near, o);
-    if ((t & 63) == 0 && near)
+    if (lane == 0 && near)
         atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
 }
 
@@ -698,20 +723,6 @@ __device__ __forceinline__ void two_sum_f(float &hi, float &lo, float t)
     lo += e;
 }
 
-__device__ __forceinline__ float block_maxf(float v, float *sh)
-{
-    for (int o = 32; o > 0; o >>= 1)
-        v = fmaxf(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0)
-        sh[threadIdx.x >> 6] = v;
-    __syncthreads();
-    float r = sh[0];
-#pragma unroll
-    for (int w = 1; w < kBlock / 64; ++w)
-        r = fmaxf(r, sh[w]);
-    return r;
-}
-
 template <int R>
 __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ work,
                                                      const float4 *__restrict__ pk,
@@ -720,14 +731,15 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
                                                      const double *__restrict__ qz,
                                                      const double *__restrict__ m,
                                                      const double *__restrict__ rc,
+                                                     const double *__restrict__ tile_rc2,
                                                      double *__restrict__ fpart, int ntot,
                                                      int maxs, double inner, DevStats *stats)
 {
     __shared__ float4 sa[kBlock];
     __shared__ float4 sb[kBlock];
-    __shared__ float smax[2][kBlock / 64];
+    __shared__ double red[kWaves - 1][3 * R][64];
     const FWork wk = work[blockIdx.x];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], r2i[R];
     float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R], tx[R], ty[R], tz[R];
     double nx[R], ny[R], nz[R];
@@ -735,7 +747,7 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
     int near = 0;
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        int li = t + k * kBlock;
+        int li = lane + 64 * k;
         int i = wk.i0 + (li < wk.ni ? li : 0);
         ii[k] = i;
         float4 A = pk[2 * (size_t)i], B = pk[2 * (size_t)i + 1];
@@ -746,26 +758,26 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
         nx[k] = ny[k] = nz[k] = 0.0;
     }
     const int jend = wk.j0 + wk.nj;
-    int buf = 0;
-    for (int jt = wk.j0; jt < jend; jt += kBlock, buf ^= 1) {
+    int tile = wk.rb0;
+    for (int jt = wk.j0; jt < jend; jt += kBlock, ++tile) {
         const int cnt = min(kBlock, jend - jt);
         __syncthreads();
-        float r2j = 0.0f;
         if (t < cnt) {
             sa[t] = pk[2 * (size_t)(jt + t)];
-            float4 B = pk[2 * (size_t)(jt + t) + 1];
-            sb[t] = B;
-            r2j = B.w;
+            sb[t] = pk[2 * (size_t)(jt + t) + 1];
         }
-        const float tmax = block_maxf(r2j, smax[buf]);
+        // widened like the per-body FP32 radii so the FP32 test stays a superset
+        const float tmax = (float)(tile_rc2[tile] * (1.0 + 0x1p-9));
         float thr[R];
 #pragma unroll
         for (int k = 0; k < R; ++k)
             thr[k] = fmaxf(r2i[k], tmax);
-        for (int jb = 0; jb < cnt; jb += kMerge) {
-            const int je = min(cnt, jb + kMerge);
+        __syncthreads();
+        const int jw = 64 * wv, je = min(cnt, jw + 64);
+        for (int jb = jw; jb < je; jb += kMerge) {
+            const int jm = min(je, jb + kMerge);
 #pragma unroll 2
-            for (int jj = jb; jj < je; ++jj) {
+            for (int jj = jb; jj < jm; ++jj) {
                 const float4 A = sa[jj];
                 const float4 B = sb[jj];
 #pragma unroll
@@ -775,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
                     float dz = (A.z - zh[k]) + (B.z - zl[k]);
                     float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     float y = __builtin_amdgcn_rsqf(r2);
-                    float s = A.w * (y * y) * y;
+                    float s = (A.w * y) * (y * y);
                     if (r2 < thr[k]) {
                         if (r2 < fmaxf(r2i[k], B.w)) {
                             // FP64 changeover pair from the FP64 state
@@ -804,19 +816,42 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
             }
         }
     }
+    double sx_[R], sy_[R], sz_[R];
 #pragma unroll
     for (int k = 0; k < R; ++k) {
-        int li = t + k * kBlock;
-        if (li < wk.ni) {
-            int i = wk.i0 + li;
-            fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = ((double)hx[k] + (double)lx[k]) + nx[k];
-            fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = ((double)hy[k] + (double)ly[k]) + ny[k];
-            fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = ((double)hz[k] + (double)lz[k]) + nz[k];
+        sx_[k] = ((double)hx[k] + (double)lx[k]) + nx[k];
+        sy_[k] = ((double)hy[k] + (double)ly[k]) + ny[k];
+        sz_[k] = ((double)hz[k] + (double)lz[k]) + nz[k];
+    }
+    if (wv > 0) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            red[wv - 1][3 * k + 0][lane] = sx_[k];
+            red[wv - 1][3 * k + 1][lane] = sy_[k];
+            red[wv - 1][3 * k + 2][lane] = sz_[k];
+        }
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            for (int w = 0; w < kWaves - 1; ++w) {
+                sx_[k] += red[w][3 * k + 0][lane];
+                sy_[k] += red[w][3 * k + 1][lane];
+                sz_[k] += red[w][3 * k + 2][lane];
+            }
+            int li = lane + 64 * k;
+            if (li < wk.ni) {
+                int i = wk.i0 + li;
+                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = sx_[k];
+                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = sy_[k];
+                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = sz_[k];
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1)
         near += __shfl_xor(near, o);
-    if ((t & 63) == 0 && near)
+    if (lane == 0 && near)
         atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
 }
 
@@ -912,12 +947,13 @@ struct EncRec {
 // Stage 1 (every pair): chord midpoints M and reaches R (from the drift).  The
 // Hermite data split into the straight-chord part |dQ0 + s dc|^2 (which the
 // cubic reproduces exactly and which is >= (D - rho_i - rho_j)^2, D = |dM|)
-// and the endpoint velocity deviations (weighted by Hermite basis functions
-// bounded by 4/27) give f(s) >= (D-P)^2 - (8/27)(D+P)E with P = rho_i + rho_j,
-// E = eps_i + eps_j; this exceeds (rc_i + rc_j)^2 >= rc_ij^2 whenever
-// D > R_i + R_j, R = 2 rho + eps/2 + rc.  So only pairs with
-// |dM|^2 <= (R_i + R_j)^2 go on.  Stage 2 (candidates): the 4/27 lower bound
-// on the full Hermite data, then the exact minimum.
+// and the endpoint velocity deviations e = dt V - c, weighted by h10(s) and
+// h11(s) with |h10| + |h11| = s(1-s) <= 1/4.  So
+// f(s) >= (D-P)^2 - (1/2)(D+P)E with P = rho_i + rho_j, E = eps_i + eps_j,
+// which exceeds (rc_i + rc_j)^2 >= rc_ij^2 whenever D > R_i + R_j with
+// R = 2 rho + 3 eps/4 + rc.  So only pairs with |dM|^2 <= (R_i + R_j)^2 go on.
+// Stage 2 (candidates): the 4/27 lower bound on the full Hermite data, then
+// the exact minimum.
 __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ work, double dt,
                                                       const double4 *__restrict__ mr,
                                                       const double *__restrict__ q0x,
@@ -1320,7 +1356,7 @@ hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, 
         return hipSuccess;
     k_sun_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, d.rpart, h, d.qx,
                                           d.qy, d.qz, rcrit, d.m, p.n_hill, d.rc,
-                                          p.mode == 1 ? d.pk : nullptr);
+                                          p.mode == 1 ? d.pk : nullptr, d.tile_rc2);
     return hipGetLastError();
 }
 
@@ -1342,28 +1378,31 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
         switch (p.force_r) {
         case 1:
             k_force32c<1><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
-                                                    d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+                                                    d.tile_rc2, d.fpart, d.ntot, d.maxs, p.inner, d.stats);
             break;
         case 4:
             k_force32c<4><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
-                                                    d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+                                                    d.tile_rc2, d.fpart, d.ntot, d.maxs, p.inner, d.stats);
             break;
         default:
             k_force32c<2><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
-                                                    d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+                                                    d.tile_rc2, d.fpart, d.ntot, d.maxs, p.inner, d.stats);
         }
     } else {
         switch (p.force_r) {
         case 1:
-            k_force64<1><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
+            k_force64<1><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc,
+                                                   d.tile_rc2, d.fpart,
                                                    d.ntot, d.maxs, p.inner, d.stats);
             break;
         case 4:
-            k_force64<4><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
+            k_force64<4><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc,
+                                                   d.tile_rc2, d.fpart,
                                                    d.ntot, d.maxs, p.inner, d.stats);
             break;
         default:
-            k_force64<2><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart,
+            k_force64<2><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.qx, d.qy, d.qz, d.m, d.rc,
+                                                   d.tile_rc2, d.fpart,
                                                    d.ntot, d.maxs, p.inner, d.stats);
         }
     }

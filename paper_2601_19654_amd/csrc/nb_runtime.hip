@@ -72,7 +72,8 @@ Params to_internal(const nb_params &q)
     p.cd = q.drag_cd;
     p.rho_p = q.drag_rho_p;
     p.force_r = q.force_r > 0 ? q.force_r : kDefaultForceR;
-    p.force_j = q.force_jchunk > 0 ? q.force_jchunk : kDefaultForceJ;
+    // source chunks are whole tiles of kBlock bodies
+    p.force_j = q.force_jchunk > 0 ? (q.force_jchunk + kBlock - 1) / kBlock * kBlock : kDefaultForceJ;
     p.enc_j = q.enc_jchunk > 0 ? q.enc_jchunk : kDefaultEncJ;
     return p;
 }
@@ -143,7 +144,7 @@ void build_tables(const Params &p, int nsys, const int32_t *off, Tables &t)
     t.dw_first.assign(nsys, 0);
     t.dw_count.assign(nsys, 0);
     t.sys_of.assign(off[nsys], 0);
-    const int TI = kBlock * p.force_r;
+    const int TI = 64 * p.force_r;
     for (int s = 0; s < nsys; ++s) {
         int a = off[s], n = off[s + 1] - off[s];
         for (int i = a; i < a + n; ++i)
@@ -161,7 +162,8 @@ void build_tables(const Params &p, int nsys, const int32_t *off, Tables &t)
             for (int k = 0; k < S; ++k) {
                 int j0 = k * p.force_j;
                 t.fwork.push_back(FWork{a + i0, std::min(TI, n - i0), a + j0,
-                                        std::min(p.force_j, n - j0), k, s, 0, 0});
+                                        std::min(p.force_j, n - j0), k, s,
+                                        t.rb_first[s] + j0 / kBlock, 0});
             }
         pair_items(a, n, p.enc_j, t.ework);
         t.dw_first[s] = (int)t.dwork.size();
@@ -239,6 +241,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.ndw = (int)t.dwork.size();
     d.dwork = (PWork *)take(t.dwork.size() * sizeof(PWork));
     d.rpart = (double *)take((size_t)d.nrb * 8 * sizeof(double));
+    d.tile_rc2 = (double *)take((size_t)std::max(d.nrb, 1) * sizeof(double));
     d.fpart = (double *)take((size_t)3 * d.maxs * ntot * sizeof(double));
     d.dpart = (double *)take((size_t)std::max(d.ndw, 1) * 4 * sizeof(double));
     d.bpart = (double *)take((size_t)std::max(d.nrb, 1) * 8 * sizeof(double));

@@ -1,0 +1,69 @@
+"""The encounter prefilter's claim, checked against the oracle's predicate.
+
+The device encounter check skips a pair when the chord midpoints of the two
+bodies are farther apart than R_i + R_j, with R = 2 rho + 3 eps/4 + rc
+(rho: half the chord Q1 - Q0; eps: the larger of |dt V0 - c|, |dt V1 - c|).
+The argument: the Hermite data split into the straight-chord quadratic
+|dQ0 + s dc|^2 >= (D - rho_i - rho_j)^2 plus the velocity deviations weighted
+by h10(s), h11(s) with |h10| + |h11| = s(1-s) <= 1/4.  Here the claim is
+tested on arbitrary (non-physical) Hermite data placed just outside the reach,
+and on Kepler arcs, with the oracle's exact minimum as the judge.
+"""
+import numpy as np
+
+import oracle
+import workloads
+
+
+def reach(q0, v0, q1, v1, rc, dt):
+    c = q1 - q0
+    rho = 0.5 * np.linalg.norm(c)
+    eps = max(np.linalg.norm(dt * v0 - c), np.linalg.norm(dt * v1 - c))
+    return 2 * rho + 0.75 * eps + rc, 0.5 * (q0 + q1)
+
+
+def _body(rng, scale):
+    q0 = rng.normal(size=3) * scale
+    v0 = rng.normal(size=3)
+    q1 = q0 + rng.normal(size=3) * scale * rng.uniform(0, 2)
+    v1 = rng.normal(size=3) * rng.uniform(0, 3)
+    return q0, v0, q1, v1
+
+
+def test_bound_holds_just_outside_the_reach():
+    rng = np.random.default_rng(2024)
+    worst = np.inf
+    for trial in range(20000):
+        dt = rng.uniform(0.01, 2.0) * rng.choice([-1, 1])
+        bi = _body(rng, rng.uniform(0.01, 1))
+        bj = list(_body(rng, rng.uniform(0.01, 1)))
+        rci, rcj = rng.uniform(0, 0.5, 2)
+        Ri, Mi = reach(*bi, rci, dt)
+        Rj, Mj = reach(*bj, rcj, dt)
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        target = Mi + u * (Ri + Rj) * (1 + rng.uniform(1e-9, 0.05))
+        shift = target - Mj
+        bj[0] = bj[0] + shift
+        bj[2] = bj[2] + shift
+        d2 = oracle.pair_min_d2(dt, *bi, *bj)
+        thr = max(rci, rcj) ** 2
+        assert d2 > thr, (trial, d2, thr)
+        worst = min(worst, (d2 - thr) / max(thr, 1e-300))
+    assert worst > 0
+
+
+def test_bound_on_kepler_arcs_of_a_dense_ring():
+    """Every flagged pair of a dense ring lies within the reach sum."""
+    w = workloads.ring(400, m=1e-7)
+    Q0, V0 = oracle.helio_to_dh(1.0, w.m, w.x, w.v)
+    rc = oracle.rcrit(1.0, w.m, Q0)
+    for dt in (0.04, 0.2, -0.1):
+        Q1, V1, _ = oracle.drift(w.G, dt, Q0, V0)
+        out = oracle.encounters(dt, Q0, V0, Q1, V1, rc)
+        R = np.empty(400); M = np.empty((400, 3))
+        for i in range(400):
+            R[i], M[i] = reach(Q0[i], V0[i], Q1[i], V1[i], rc[i], dt)
+        for i, j in zip(out["ice"], out["jce"]):
+            assert np.linalg.norm(M[j] - M[i]) <= R[i] + R[j]
+        assert out["nce"] > 0
