@@ -3,7 +3,8 @@
 
 Workload: 16384 equal-mass planetesimals (10 Earth masses in total) in a
 0.5-5 AU annulus around a solar-mass star, e ~ Rayleigh(0.01),
-i ~ Rayleigh(0.005), dt = 0.0175 yr; synthetic and seeded.
+i ~ Rayleigh(0.005), dt = 0.0021875 yr (0.0175 yr halved until an FP64 run of
+1e4 steps keeps the changeover-weighted energy within 1e-9); synthetic, seeded.
 
 A step is one whole hybrid step K S D C S F K (kick, stellar drift, Kepler
 drift, encounter check, stellar drift, critical radii + force, kick) of that
@@ -221,7 +222,7 @@ def main():
     desc = {"c1": "c1: star + 100 planetesimals, m 1e-10..1e-8 log-uniform, a 1-3 AU, dt 0.05 yr",
             "c2": "c2: star + Jupiter at 5.2 AU + 1000 planetesimals of 1e-9, a 2-10 AU, gas drag, dt 0.1 yr",
             "c3": f"c3: star + {n} equal-mass planetesimals (10 Earth masses), "
-                  "a 0.5-5 AU, e,i Rayleigh 0.01/0.005, dt 0.0175 yr",
+                  "a 0.5-5 AU, e,i Rayleigh 0.01/0.005, dt 0.0021875 yr (energy-bounded step)",
             "c4": f"c4: {w.nsys} independent systems, N_s uniform 200..4000 (sum {n}), c1 distributions, dt 0.05 yr",
             "c5": f"c5: star + {n} planetesimals of 1e-11 in a 0.9-1.1 AU ring, dt 0.04 yr"}[args.workload]
     out = {

@@ -95,6 +95,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not built: run __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime; load it first so that the library's
+        # libamdhip64.so.7 dependency resolves to the same runtime (one runtime
+        # per process: streams and device memory are shared with torch).
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)
