@@ -56,7 +56,7 @@ def run_mode(w, mode: str, steps: int, warmup: int, torch, nb):
     p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64, drag=int(w.drag))
     ctx = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0")
     tiles = {"source": ctx.tiles, "force_r": ctx.params.force_r, "force_jchunk": ctx.params.force_jchunk,
-             "enc_jchunk": ctx.params.enc_jchunk}
+             "enc_jchunk": ctx.params.enc_jchunk, "enc_algo": ctx.params.enc_algo}
     ctx.upload(w.m0, w.m, w.x, w.v)
     pairs = w.pairs()
     # warmup (untimed), also builds the step graph

@@ -87,7 +87,9 @@ typedef struct nb_params {
     int32_t force_jchunk; /* sources per force work item (0: tuned default) */
     int32_t force_r;      /* targets per lane in the force kernel: 1, 2 or 4 (0: default) */
     int32_t enc_jchunk;   /* sources per encounter work item (0: default) */
-    int32_t reserved[5];
+    int32_t enc_algo;     /* encounter check: 0 automatic, 1 every pair through a per-pair
+                             reach filter, 2 spatially sorted tiles with tile-pair culling */
+    int32_t reserved[4];
 } nb_params;
 
 typedef struct nb_stats {

@@ -76,24 +76,28 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
             if verbose:
                 print(f"[autotune] {mode} force r={r} j={j}: {ms:.4f} ms", file=sys.stderr, flush=True)
             c.close()
-    for j in ENC_J:
+    for j in ENC_J + (0,):
         if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
             continue
-        p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), enc_jchunk=j)
+        # j = 0 stands for the sorted-tile algorithm (no chunk parameter)
+        p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), enc_jchunk=j,
+                              enc_algo=2 if j == 0 else 1)
         c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False)
         c.upload(w.m0, w.m, w.x, w.v)
         c.drift(w.dt, allow_fail=True)
         ms = c.time_kernel(nb.NB_K_ENCOUNTER, reps=reps)
         res_enc[j] = ms
         if verbose:
-            print(f"[autotune] {mode} encounter j={j}: {ms:.4f} ms", file=sys.stderr, flush=True)
+            print(f"[autotune] {mode} encounter {'sorted tiles' if j == 0 else f'j={j}'}: {ms:.4f} ms",
+                  file=sys.stderr, flush=True)
         c.close()
     (r, j), fms = min(res_force.items(), key=lambda kv: kv[1])
     ej, ems = min(res_enc.items(), key=lambda kv: kv[1])
-    return {"force_r": r, "force_jchunk": j, "enc_jchunk": ej, "force_ms": round(fms, 5),
+    return {"force_r": r, "force_jchunk": j, "enc_jchunk": ej if ej else 1024, "enc_algo": 2 if ej == 0 else 1,
+            "force_ms": round(fms, 5),
             "encounter_ms": round(ems, 5), "workload": w.name, "tuned_at": time.strftime("%Y-%m-%d"),
             "force_candidates": {f"r{a}_j{b}": round(v, 5) for (a, b), v in res_force.items()},
-            "encounter_candidates": {f"j{a}": round(v, 5) for a, v in res_enc.items()}}
+            "encounter_candidates": {(f"j{a}" if a else "sorted"): round(v, 5) for a, v in res_enc.items()}}
 
 
 def main():
@@ -113,7 +117,8 @@ def main():
             best = tune(w, mode, reps=args.reps)
             cache[key(mode, w.off, a)] = best
             print(f"[autotune] {key(mode, w.off, a)} -> r={best['force_r']} j={best['force_jchunk']} "
-                  f"enc_j={best['enc_jchunk']} ({best['force_ms']:.4f} / {best['encounter_ms']:.4f} ms)",
+                  f"enc_algo={best['enc_algo']} enc_j={best['enc_jchunk']} "
+                  f"({best['force_ms']:.4f} / {best['encounter_ms']:.4f} ms)",
                   file=sys.stderr, flush=True)
             with open(args.out, "w") as f:
                 json.dump(cache, f, indent=1, sort_keys=True)

@@ -28,6 +28,29 @@ struct PWork {
     int i0, ni, j0, nj;
 };
 
+// A body's encounter record in spatially sorted order (sorted encounter check).
+struct SRec {
+    double q0[3], v0[3], q1[3], v1[3];
+    double rc;
+    int body, pad;
+};
+
+// A tile of up to 64 consecutive sorted bodies of one system; `last` is the
+// index of the system's last tile.
+struct Tile {
+    int sys, start, count, last;
+};
+
+// Bounding data of a tile: centre and radius of the chord midpoints, of the
+// chords and of the endpoint velocity deviations (dt V - chord), and the
+// largest critical radius.
+struct TileB {
+    double cm[3], sm;
+    double cc[3], sc;
+    double ce[3], se;
+    double rc, pad[3];
+};
+
 // Device statistics block (one per context).
 struct DevStats {
     long long total_nce;
@@ -37,7 +60,8 @@ struct DevStats {
     int overflow_steps;
     int cur_nce;      // count of the current encounter check
     int cur_kfail;    // failures of the current drift
-    int pad[2];
+    int cur_tp;       // tile pairs surviving the cull (sorted encounter check)
+    int pad;
 };
 
 // Device pointers of a context; every array lives in the caller's workspace.
@@ -70,6 +94,17 @@ struct Dev {
     int enc_cap;
     int *ice, *jce;       // sorted list (enc_cap)
     DevStats *stats;
+    // sorted encounter check
+    int enc_sorted;
+    double *lnr_part;     // nrb x 2: min, max of ln R (cylindrical) of chord midpoints
+    int *cell_of, *slot_of;   // ntot
+    int *cell_cnt, *cell_off; int ncell;
+    int *sys_cell_base, *sys_cell_cnt;   // nsys
+    int *ord;             // ntot: sorted position -> body
+    SRec *srec;           // ntot
+    Tile *tiles; int ntile;
+    TileB *tileb;         // ntile
+    int2 *tpairs; int tp_cap;
     int *flag;            // validation flags (4 ints)
     double *stage;        // 6 x ntot staging for host transfers / transforms
 };
@@ -79,6 +114,7 @@ struct Params {
     int mode, drag;
     double sigma0, h, cd, rho_p;
     int force_r, force_j, enc_j;
+    int enc_algo;         // 1: all pairs with the reach prefilter, 2: sorted tiles
 };
 
 // ---- launchers (nb_kernels.hip) --------------------------------------------

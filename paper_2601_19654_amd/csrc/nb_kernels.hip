@@ -16,6 +16,7 @@
 //     integer atomic per wave and is sorted afterwards.
 #include "nb_internal.h"
 
+#include <algorithm>
 #include <float.h>
 #include <math.h>
 
@@ -519,9 +520,11 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
                         double *__restrict__ v0x, double *__restrict__ v0y,
                         double *__restrict__ v0z, int *__restrict__ kflag, int *__restrict__ ce,
                         DevStats *stats, double *__restrict__ part_out,
-                        const double *__restrict__ rc, double4 *__restrict__ mr)
+                        const double *__restrict__ rc, double4 *__restrict__ mr,
+                        double *__restrict__ lnr_part)
 {
     __shared__ double sh[3 * kBlock];
+    double lnr_lo = INFINITY, lnr_hi = -INFINITY;
     RBlk b = rblk[blockIdx.x];
     int i = b.start + threadIdx.x;
     double mu = G * m0[b.sys];
@@ -548,7 +551,11 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
             double ax1 = dt * u - cx, ay1 = dt * v - cy, az1 = dt * w - cz;
             double eps = sqrt(fmax(ax0 * ax0 + ay0 * ay0 + az0 * az0, ax1 * ax1 + ay1 * ay1 + az1 * az1));
             double R = (2.0 * rho + 0.75 * eps + rc[i]) * (1.0 + 0x1p-20);
-            mr[i] = make_double4(q0x[i] + 0.5 * cx, q0y[i] + 0.5 * cy, q0z[i] + 0.5 * cz, R);
+            double mx = q0x[i] + 0.5 * cx, my = q0y[i] + 0.5 * cy;
+            mr[i] = make_double4(mx, my, q0z[i] + 0.5 * cz, R);
+            double lnr = log(fmax(sqrt(mx * mx + my * my), 1e-300));
+            lnr_lo = lnr;
+            lnr_hi = lnr;
         }
         qx[i] = x;
         qy[i] = y;
@@ -570,6 +577,28 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
     }
     if (blockIdx.x == 0 && threadIdx.x == 0)
         stats->cur_nce = 0;
+    if (lnr_part) {
+        // range of ln R over the block (the sorted encounter check bins by it)
+        for (int o = 32; o > 0; o >>= 1) {
+            lnr_lo = fmin(lnr_lo, __shfl_xor(lnr_lo, o));
+            lnr_hi = fmax(lnr_hi, __shfl_xor(lnr_hi, o));
+        }
+        if ((threadIdx.x & 63) == 0) {
+            sh[threadIdx.x >> 6] = lnr_lo;
+            sh[kBlock / 64 + (threadIdx.x >> 6)] = lnr_hi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double lo = sh[0], hi = sh[kBlock / 64];
+            for (int w = 1; w < kBlock / 64; ++w) {
+                lo = fmin(lo, sh[w]);
+                hi = fmax(hi, sh[kBlock / 64 + w]);
+            }
+            lnr_part[2 * (size_t)blockIdx.x] = lo;
+            lnr_part[2 * (size_t)blockIdx.x + 1] = hi;
+        }
+        __syncthreads();
+    }
     block_sum<3>(pv, sh);
     if (threadIdx.x == 0) {
         part_out[(size_t)blockIdx.x * 4 + 0] = pv[0];
@@ -1051,6 +1080,352 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
     }
 }
 
+// ----------------------------------------------------------------------------
+// Spatially sorted encounter check.  Each step the bodies of every system are
+// binned by the chord midpoint's cylindrical (ln R, phi) into a power-of-two
+// grid of about N_s/8 cells traversed in Morton order, counting-sorted, and
+// cut into tiles of 64 consecutive bodies.  A tile carries the centre and
+// radius of its chord midpoints M, chords c and endpoint velocity deviations
+// e = dt V - c.  For i in tile A and j in tile B the Hermite data split into
+// the chord quadratic |dM + (s - 1/2) dc|^2 and the deviations weighted by
+// |h10| + |h11| = s(1-s) <= 1/4 give f(s) >= Lmin^2 - Qmax Em / 2 with
+//   Lmin = D - sm_A - sm_B - Cm/2,  Qmax = D + sm_A + sm_B + Cm/2,
+//   D = |cm_B - cm_A|, Cm = |cc_B - cc_A| + sc_A + sc_B, Em = |ce_B - ce_A| + se_A + se_B,
+// so a tile pair whose bound exceeds max rc^2 holds no flagged pair.  Surviving
+// tile pairs are tested pair by pair exactly as in k_encounter.  The sort order
+// inside a cell depends on atomic timing; the flagged set does not (the pair
+// test is symmetric bit for bit), and the output list is sorted.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ unsigned morton2(unsigned band, int nb, unsigned pb, int np)
+{
+    unsigned code = 0;
+    int k = 0, bit = 0;
+    for (; k < nb || k < np; ++k) {
+        if (k < np)
+            code |= ((pb >> k) & 1u) << bit++;
+        if (k < nb)
+            code |= ((band >> k) & 1u) << bit++;
+    }
+    return code;
+}
+
+__global__ void k_cells(const RBlk *__restrict__ rblk, const int *__restrict__ rb_first,
+                        const int *__restrict__ rb_count, const double *__restrict__ lnr_part,
+                        const int *__restrict__ sys_cell_base, const int *__restrict__ sys_cell_cnt,
+                        const double4 *__restrict__ mr, int *__restrict__ cell_cnt,
+                        int *__restrict__ cell_of, int *__restrict__ slot_of)
+{
+    __shared__ double sh[2 * kBlock];
+    const RBlk b = rblk[blockIdx.x];
+    // ln R range of the whole system, from its blocks' partials
+    double lo = INFINITY, hi = -INFINITY;
+    for (int k = threadIdx.x; k < rb_count[b.sys]; k += kBlock) {
+        lo = fmin(lo, lnr_part[2 * (size_t)(rb_first[b.sys] + k)]);
+        hi = fmax(hi, lnr_part[2 * (size_t)(rb_first[b.sys] + k) + 1]);
+    }
+    sh[threadIdx.x] = lo;
+    sh[kBlock + threadIdx.x] = hi;
+    __syncthreads();
+    for (int st = kBlock / 2; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) {
+            sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + st]);
+            sh[kBlock + threadIdx.x] = fmax(sh[kBlock + threadIdx.x], sh[kBlock + threadIdx.x + st]);
+        }
+        __syncthreads();
+    }
+    lo = sh[0];
+    hi = sh[kBlock];
+    const int C = sys_cell_cnt[b.sys];          // power of two
+    int lc = 31 - __clz(C);
+    // bands B x phi bins P = C with square cells in (ln R, phi): B ~ sqrt(C span / 2 pi)
+    const double span = fmax(hi - lo, 0.0);
+    int lb = 0;
+    double bstar = sqrt((double)C * span / 6.283185307179586);
+    if (bstar > 1.0)
+        lb = min(lc, (int)floor(log2(bstar) + 0.5));
+    const int lp = lc - lb;
+    const int i = b.start + threadIdx.x;
+    if (i < b.end) {
+        double4 M = mr[i];
+        double R = sqrt(M.x * M.x + M.y * M.y);
+        double lnr = log(fmax(R, 1e-300));
+        unsigned band = 0, pb = 0;
+        if (span > 0.0)
+            band = (unsigned)min((1 << lb) - 1, max(0, (int)((lnr - lo) / span * (double)(1 << lb))));
+        double phi = atan2(M.y, M.x);
+        pb = (unsigned)min((1 << lp) - 1, max(0, (int)((phi + 3.141592653589793) *
+                                                      (0.15915494309189535 * (double)(1 << lp)))));
+        int cell = sys_cell_base[b.sys] + (int)morton2(band, lb, pb, lp);
+        cell_of[i] = cell;
+        slot_of[i] = atomicAdd(&cell_cnt[cell], 1);
+    }
+}
+
+// Exclusive scan of the cell counts (one workgroup), zeroing them for the next
+// step, and reset of the surviving-tile-pair counter.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_cell_scan(int *__restrict__ cell_cnt,
+                                                            int *__restrict__ cell_off, int ncell,
+                                                            DevStats *stats)
+{
+    __shared__ int part[kScanThreads];
+    const int t = threadIdx.x;
+    const int per = (ncell + kScanThreads - 1) / kScanThreads;
+    const int a = min(ncell, t * per), e = min(ncell, a + per);
+    int sum = 0;
+    for (int k = a; k < e; ++k)
+        sum += cell_cnt[k];
+    part[t] = sum;
+    __syncthreads();
+    // Hillis-Steele inclusive scan of the per-thread sums
+    for (int o = 1; o < kScanThreads; o <<= 1) {
+        int v = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int k = a; k < e; ++k) {
+        int c = cell_cnt[k];
+        cell_off[k] = run;
+        run += c;
+        cell_cnt[k] = 0;
+    }
+    if (t == 0)
+        stats->cur_tp = 0;
+}
+
+__global__ void k_scatter(const RBlk *__restrict__ rblk, const int *__restrict__ cell_of,
+                          const int *__restrict__ slot_of, const int *__restrict__ cell_off,
+                          const double *__restrict__ q0x, const double *__restrict__ q0y,
+                          const double *__restrict__ q0z, const double *__restrict__ v0x,
+                          const double *__restrict__ v0y, const double *__restrict__ v0z,
+                          const double *__restrict__ qx, const double *__restrict__ qy,
+                          const double *__restrict__ qz, const double *__restrict__ vx,
+                          const double *__restrict__ vy, const double *__restrict__ vz,
+                          const double *__restrict__ rc, int *__restrict__ ord,
+                          SRec *__restrict__ srec)
+{
+    const RBlk b = rblk[blockIdx.x];
+    const int i = b.start + threadIdx.x;
+    if (i >= b.end)
+        return;
+    const int pos = cell_off[cell_of[i]] + slot_of[i];
+    ord[pos] = i;
+    SRec r;
+    r.q0[0] = q0x[i]; r.q0[1] = q0y[i]; r.q0[2] = q0z[i];
+    r.v0[0] = v0x[i]; r.v0[1] = v0y[i]; r.v0[2] = v0z[i];
+    r.q1[0] = qx[i];  r.q1[1] = qy[i];  r.q1[2] = qz[i];
+    r.v1[0] = vx[i];  r.v1[1] = vy[i];  r.v1[2] = vz[i];
+    r.rc = rc[i];
+    r.body = i;
+    r.pad = 0;
+    srec[pos] = r;
+}
+
+// Chord midpoint M, chord c, mean deviation eb and deviation radius se of one record.
+__device__ __forceinline__ void rec_geometry(const SRec &r, double dt, double M[3], double c[3],
+                                             double eb[3], double &se)
+{
+    double s2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        c[k] = r.q1[k] - r.q0[k];
+        M[k] = r.q0[k] + 0.5 * c[k];
+        double e0 = dt * r.v0[k] - c[k], e1 = dt * r.v1[k] - c[k];
+        eb[k] = 0.5 * (e0 + e1);
+        s2 += (e0 - e1) * (e0 - e1);
+    }
+    se = 0.5 * sqrt(s2);
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+
+__device__ __forceinline__ double wave_maxd(double v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ double norm3(double x, double y, double z)
+{
+    return sqrt(x * x + y * y + z * z);
+}
+
+// One wave per tile: centres (means) and radii (maxima) of its bodies' geometry.
+__global__ __launch_bounds__(kBlock) void k_tile_bounds(const Tile *__restrict__ tiles, int ntile,
+                                                        const SRec *__restrict__ srec, double dt,
+                                                        TileB *__restrict__ tileb)
+{
+    const int tw = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (tw >= ntile)
+        return;
+    const Tile T = tiles[tw];
+    const bool on = lane < T.count;
+    double M[3] = {0, 0, 0}, c[3] = {0, 0, 0}, eb[3] = {0, 0, 0}, se = 0.0, rc = 0.0;
+    if (on) {
+        const SRec r = srec[T.start + lane];
+        rec_geometry(r, dt, M, c, eb, se);
+        rc = r.rc;
+    }
+    const double inv = 1.0 / (double)T.count;
+    double cm[3], cc[3], ce[3];
+    for (int k = 0; k < 3; ++k) {
+        cm[k] = wave_sum(M[k]) * inv;
+        cc[k] = wave_sum(c[k]) * inv;
+        ce[k] = wave_sum(eb[k]) * inv;
+    }
+    double dm = 0.0, dc = 0.0, de = 0.0;
+    if (on) {
+        dm = norm3(M[0] - cm[0], M[1] - cm[1], M[2] - cm[2]);
+        dc = norm3(c[0] - cc[0], c[1] - cc[1], c[2] - cc[2]);
+        de = norm3(eb[0] - ce[0], eb[1] - ce[1], eb[2] - ce[2]) + se;
+    }
+    // radii widened by 2^-20 to cover the rounding of the centres and norms
+    const double wf = 1.0 + 0x1p-20;
+    const double sm = wave_maxd(dm) * wf, sc = wave_maxd(dc) * wf, sde = wave_maxd(de) * wf;
+    const double rcm = wave_maxd(rc);
+    if (lane == 0) {
+        TileB B;
+        for (int k = 0; k < 3; ++k) {
+            B.cm[k] = cm[k];
+            B.cc[k] = cc[k];
+            B.ce[k] = ce[k];
+        }
+        B.sm = sm;
+        B.sc = sc;
+        B.se = sde;
+        B.rc = rcm;
+        B.pad[0] = B.pad[1] = B.pad[2] = 0.0;
+        tileb[tw] = B;
+    }
+}
+
+// True when a pair between the two bounded sets may be flagged.  The rounding
+// margin is relative to the squared scales involved.
+__device__ __forceinline__ bool may_meet(const double cmA[3], double smA, const double ccA[3],
+                                         double scA, const double ceA[3], double seA, double rcA,
+                                         const TileB &B)
+{
+    double D = norm3(B.cm[0] - cmA[0], B.cm[1] - cmA[1], B.cm[2] - cmA[2]);
+    double Cm = norm3(B.cc[0] - ccA[0], B.cc[1] - ccA[1], B.cc[2] - ccA[2]) + scA + B.sc;
+    double Em = norm3(B.ce[0] - ceA[0], B.ce[1] - ceA[1], B.ce[2] - ceA[2]) + seA + B.se;
+    double Lmin = D - smA - B.sm - 0.5 * Cm;
+    double Qmax = D + smA + B.sm + 0.5 * Cm;
+    double RC = fmax(rcA, B.rc);
+    if (!(Lmin > 0.0))
+        return true;
+    double lhs = Lmin * Lmin - 0.5 * Qmax * Em;
+    return !(lhs > RC * RC * (1.0 + 1e-6) + 1e-12 * Qmax * Qmax);
+}
+
+// One block per tile A: its threads test the tiles B >= A of the same system and
+// append the pairs that may meet.
+__global__ __launch_bounds__(kBlock) void k_tile_pairs(const Tile *__restrict__ tiles,
+                                                       const TileB *__restrict__ tileb,
+                                                       int2 *__restrict__ tpairs, int tp_cap,
+                                                       DevStats *stats)
+{
+    const int A = blockIdx.x;
+    const Tile TA = tiles[A];
+    const TileB BA = tileb[A];
+    const int lane = threadIdx.x & 63;
+    for (int b0 = A; b0 <= TA.last; b0 += kBlock) {
+        const int B = b0 + threadIdx.x;
+        const bool ok = B <= TA.last && may_meet(BA.cm, BA.sm, BA.cc, BA.sc, BA.ce, BA.se, BA.rc, tileb[B]);
+        const unsigned long long mask = __ballot(ok);
+        if (mask) {
+            const int leader = __ffsll((long long)mask) - 1;
+            int base = 0;
+            if (lane == leader)
+                base = atomicAdd(&stats->cur_tp, (int)__popcll(mask));
+            base = __shfl(base, leader);
+            if (ok) {
+                const int pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
+                if (pos < tp_cap)
+                    tpairs[pos] = make_int2(A, B);
+            }
+        }
+    }
+}
+
+// One workgroup per surviving tile pair (grid-stride over the count): each of
+// its waves holds tile A's bodies in its lanes and tests a quarter of tile B's
+// records, staged once in LDS.
+__global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ tiles,
+                                                      const TileB *__restrict__ tileb,
+                                                      const int2 *__restrict__ tpairs, int tp_cap,
+                                                      const SRec *__restrict__ srec, double dt,
+                                                      unsigned long long *__restrict__ keys,
+                                                      int cap, int *__restrict__ ce,
+                                                      DevStats *stats)
+{
+    __shared__ SRec sb[64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int npair = min(stats->cur_tp, tp_cap);
+    const double t2 = 2.0 * dt;
+    const double k427 = 4.0 / 27.0;
+    for (int p = blockIdx.x; p < npair; p += gridDim.x) {
+        const int2 AB = tpairs[p];
+        const Tile TA = tiles[AB.x], TB = tiles[AB.y];
+        __syncthreads();
+        if (threadIdx.x < TB.count)
+            sb[threadIdx.x] = srec[TB.start + threadIdx.x];
+        __syncthreads();
+        const bool on = lane < TA.count;
+        const SRec me = srec[TA.start + (on ? lane : 0)];
+        double M[3], c[3], eb[3], se;
+        rec_geometry(me, dt, M, c, eb, se);
+        const bool lane_ok = on && may_meet(M, 0.0, c, 0.0, eb, se, me.rc, tileb[AB.y]);
+        if (!__any(lane_ok))
+            continue;
+        const bool diag = AB.x == AB.y;
+        const int j1 = min(TB.count, 16 * wv + 16);
+        for (int jj = 16 * wv; jj < j1; ++jj) {
+            const SRec &J = sb[jj];
+            bool hit = false;
+            if (lane_ok && (!diag || jj > lane)) {
+                double d0x = J.q0[0] - me.q0[0], d0y = J.q0[1] - me.q0[1], d0z = J.q0[2] - me.q0[2];
+                double d1x = J.q1[0] - me.q1[0], d1y = J.q1[1] - me.q1[1], d1z = J.q1[2] - me.q1[2];
+                double e0x = J.v0[0] - me.v0[0], e0y = J.v0[1] - me.v0[1], e0z = J.v0[2] - me.v0[2];
+                double e1x = J.v1[0] - me.v1[0], e1y = J.v1[1] - me.v1[1], e1z = J.v1[2] - me.v1[2];
+                double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
+                double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
+                double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
+                double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
+                double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
+                double rcij = fmax(me.rc, J.rc);
+                double thr = rcij * rcij;
+                if (lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1)))
+                    hit = hermite_min(f0, f1, g0, g1) <= thr;
+            }
+            const unsigned long long mask = __ballot(hit);
+            if (mask) {
+                const int leader = __ffsll((long long)mask) - 1;
+                int base = 0;
+                if (lane == leader)
+                    base = atomicAdd(&stats->cur_nce, (int)__popcll(mask));
+                base = __shfl(base, leader);
+                if (hit) {
+                    const int pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
+                    const int bi = me.body, bj = J.body;
+                    const unsigned lo = (unsigned)min(bi, bj), hi = (unsigned)max(bi, bj);
+                    if (pos < cap)
+                        keys[pos] = ((unsigned long long)lo << 32) | hi;
+                    __hip_atomic_store(&ce[bi], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(&ce[bj], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+            }
+        }
+    }
+}
+
 // Sort the encounter keys (one workgroup, bitonic), split them into (ice, jce),
 // and fold the count into the run statistics.
 constexpr int kSortThreads = 1024;
@@ -1366,7 +1741,8 @@ hipError_t launch_drift(const Dev &d, const Params &p, double dt, hipStream_t s)
         return hipSuccess;
     k_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, dt, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
                                       d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
-                                      d.stats, d.rpart, d.rc, d.mr);
+                                      d.stats, d.rpart, d.rc, d.mr,
+                                      d.enc_sorted ? d.lnr_part : nullptr);
     return hipGetLastError();
 }
 
@@ -1421,6 +1797,27 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, h
 
 hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s)
 {
+    if (d.enc_sorted) {
+        if (d.nrb > 0) {
+            k_cells<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.lnr_part,
+                                              d.sys_cell_base, d.sys_cell_cnt, d.mr, d.cell_cnt,
+                                              d.cell_of, d.slot_of);
+            k_cell_scan<<<1, kScanThreads, 0, s>>>(d.cell_cnt, d.cell_off, d.ncell, d.stats);
+            k_scatter<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.cell_of, d.slot_of, d.cell_off, d.q0x,
+                                                d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.qx, d.qy, d.qz,
+                                                d.vx, d.vy, d.vz, d.rc, d.ord, d.srec);
+        }
+        if (d.ntile > 0) {
+            k_tile_bounds<<<cdiv(d.ntile, kBlock / 64), kBlock, 0, s>>>(d.tiles, d.ntile, d.srec, dt,
+                                                                         d.tileb);
+            k_tile_pairs<<<d.ntile, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.stats);
+            int grid = std::min(std::max(1, d.tp_cap), 8192);
+            k_enc_pairs<<<grid, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.srec, dt,
+                                                 d.keys, d.enc_cap, d.ce, d.stats);
+        }
+        k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats);
+        return hipGetLastError();
+    }
     if (d.new_ > 0)
         k_encounter<<<d.new_, kBlock, 0, s>>>(d.ework, dt, d.mr, d.q0x, d.q0y, d.q0z, d.v0x,
                                                d.v0y, d.v0z, d.qx, d.qy, d.qz, d.vx, d.vy, d.vz,

@@ -75,7 +75,16 @@ Params to_internal(const nb_params &q)
     // source chunks are whole tiles of kBlock bodies
     p.force_j = q.force_jchunk > 0 ? (q.force_jchunk + kBlock - 1) / kBlock * kBlock : kDefaultForceJ;
     p.enc_j = q.enc_jchunk > 0 ? q.enc_jchunk : kDefaultEncJ;
+    p.enc_algo = q.enc_algo;
     return p;
+}
+
+// Encounter algorithm: explicit choice, else sorted tiles for large totals.
+int choose_enc_algo(const Params &p, int ntot)
+{
+    if (p.enc_algo == 1 || p.enc_algo == 2)
+        return p.enc_algo;
+    return ntot >= 8192 ? 2 : 1;
 }
 
 int check_params(const nb_params *p)
@@ -90,7 +99,7 @@ int check_params(const nb_params *p)
         return NB_E_INVALID;
     if (p->force_r != 0 && p->force_r != 1 && p->force_r != 2 && p->force_r != 4)
         return NB_E_INVALID;
-    if (p->force_jchunk < 0 || p->enc_jchunk < 0)
+    if (p->force_jchunk < 0 || p->enc_jchunk < 0 || p->enc_algo < 0 || p->enc_algo > 2)
         return NB_E_INVALID;
     if (p->drag && !(p->drag_h > 0.0 && p->drag_h * p->drag_h * 3.0 < 1.0 && p->drag_rho_p > 0.0 &&
                      p->drag_sigma0 >= 0.0 && p->drag_cd >= 0.0))
@@ -120,6 +129,11 @@ struct Tables {
     std::vector<PWork> ework, dwork;
     std::vector<int> dw_first, dw_count;
     std::vector<int> sys_of;
+    // sorted encounter check
+    std::vector<int> cell_base, cell_cnt;
+    int ncell = 0;
+    std::vector<Tile> tiles;
+    long long tp_cap = 0;
 };
 
 // Unordered-pair items of one system: targets in tiles of kBlock, sources in
@@ -169,6 +183,24 @@ void build_tables(const Params &p, int nsys, const int32_t *off, Tables &t)
         t.dw_first[s] = (int)t.dwork.size();
         pair_items(a, n, p.enc_j, t.dwork);
         t.dw_count[s] = (int)t.dwork.size() - t.dw_first[s];
+    }
+    // sorted encounter check: about N_s/8 cells per system (a power of two) and
+    // tiles of 64 consecutive sorted bodies
+    t.cell_base.assign(nsys, 0);
+    t.cell_cnt.assign(nsys, 0);
+    for (int s = 0; s < nsys; ++s) {
+        int n = off[s + 1] - off[s];
+        int c = 1;
+        while (c * 8 < n)
+            c <<= 1;
+        t.cell_base[s] = t.ncell;
+        t.cell_cnt[s] = c;
+        t.ncell += c;
+        int first = (int)t.tiles.size();
+        int nt = (n + 63) / 64;
+        for (int k = 0; k < nt; ++k)
+            t.tiles.push_back(Tile{s, off[s] + 64 * k, std::min(64, n - 64 * k), first + nt - 1});
+        t.tp_cap += (long long)nt * (nt + 1) / 2;
     }
     // longest work first, so the hardware dispatcher packs the tail
     std::stable_sort(t.fwork.begin(), t.fwork.end(), [](const FWork &x, const FWork &y) {
@@ -252,6 +284,24 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.ice = (int *)take((size_t)std::max(enc_cap, 1) * sizeof(int));
     d.jce = (int *)take((size_t)std::max(enc_cap, 1) * sizeof(int));
     d.stats = (DevStats *)take(sizeof(DevStats));
+    d.enc_sorted = choose_enc_algo(p, ntot) == 2;
+    if (d.enc_sorted) {
+        d.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
+        d.cell_of = (int *)take((size_t)ntot * sizeof(int));
+        d.slot_of = (int *)take((size_t)ntot * sizeof(int));
+        d.ncell = t.ncell;
+        d.cell_cnt = (int *)take((size_t)t.ncell * sizeof(int));
+        d.cell_off = (int *)take((size_t)t.ncell * sizeof(int));
+        d.sys_cell_base = (int *)take((size_t)nsys * sizeof(int));
+        d.sys_cell_cnt = (int *)take((size_t)nsys * sizeof(int));
+        d.ord = (int *)take((size_t)ntot * sizeof(int));
+        d.srec = (SRec *)take((size_t)ntot * sizeof(SRec));
+        d.ntile = (int)t.tiles.size();
+        d.tiles = (Tile *)take(t.tiles.size() * sizeof(Tile));
+        d.tileb = (TileB *)take(t.tiles.size() * sizeof(TileB));
+        d.tp_cap = (int)std::min<long long>(t.tp_cap, 1ll << 30);
+        d.tpairs = (int2 *)take((size_t)d.tp_cap * sizeof(int2));
+    }
     d.flag = (int *)take(4 * sizeof(int));
     d.stage = (double *)take((size_t)6 * nd);
     return cur;
@@ -493,6 +543,13 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, int enc_cap, voi
     up(c->d.fwork, t.fwork.data(), t.fwork.size() * sizeof(FWork));
     up(c->d.ework, t.ework.data(), t.ework.size() * sizeof(PWork));
     up(c->d.dwork, t.dwork.data(), t.dwork.size() * sizeof(PWork));
+    if (c->d.enc_sorted) {
+        up(c->d.sys_cell_base, t.cell_base.data(), nsys * sizeof(int));
+        up(c->d.sys_cell_cnt, t.cell_cnt.data(), nsys * sizeof(int));
+        up(c->d.tiles, t.tiles.data(), t.tiles.size() * sizeof(Tile));
+        if (r == NB_OK && launch_fill_i32(c->d.cell_cnt, c->d.ncell, 0, c->stream) != hipSuccess)
+            r = set_err(c, NB_E_HIP, "nb_create: clearing the cell counts failed");
+    }
     if (r == NB_OK)
         r = reset_stats(c);
     if (r == NB_OK)

@@ -43,7 +43,8 @@ class nb_params(ctypes.Structure):
         ("drag_sigma0", ctypes.c_double), ("drag_h", ctypes.c_double),
         ("drag_cd", ctypes.c_double), ("drag_rho_p", ctypes.c_double),
         ("force_jchunk", ctypes.c_int32), ("force_r", ctypes.c_int32),
-        ("enc_jchunk", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5),
+        ("enc_jchunk", ctypes.c_int32), ("enc_algo", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -154,7 +155,8 @@ class Context:
         self.params = params or default_params()
         self.off = np.ascontiguousarray(off, dtype=np.int32)
         self.tiles = "library defaults"
-        if tuned and not (self.params.force_r or self.params.force_jchunk or self.params.enc_jchunk):
+        if tuned and not (self.params.force_r or self.params.force_jchunk or self.params.enc_jchunk
+                          or self.params.enc_algo):
             from . import autotune
             try:
                 hit = autotune.lookup("fp32c" if self.params.mode == NB_FP32C else "fp64", self.off)
@@ -164,6 +166,7 @@ class Context:
                 self.params.force_r = hit["force_r"]
                 self.params.force_jchunk = hit["force_jchunk"]
                 self.params.enc_jchunk = hit["enc_jchunk"]
+                self.params.enc_algo = hit.get("enc_algo", 0)
                 self.tiles = "tuned"
         self.nsys = len(self.off) - 1
         self.ntot = int(self.off[-1])

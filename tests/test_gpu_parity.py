@@ -148,12 +148,13 @@ def _oracle_encounters(w, Q, V, rc, dt):
     return pairs, tie, ce
 
 
+@pytest.mark.parametrize("algo", [1, 2])
 @pytest.mark.parametrize("wname", ["ring_n700", "batch_ragged", "ring_dense"])
-def test_encounter_set(wname):
+def test_encounter_set(wname, algo):
     w = workloads.ring(900, m=1e-7) if wname == "ring_dense" else CASES[wname]()
     Q, V, rc, _ = oracle_dh(w)
     pairs, tie, ce = _oracle_encounters(w, Q, V, rc, w.dt)
-    c = ctx_for(w)
+    c = ctx_for(w, enc_algo=algo)
     c.drift(w.dt)
     e = c.encounters()
     got = list(zip(e.ice.tolist(), e.jce.tolist()))
@@ -166,6 +167,24 @@ def test_encounter_set(wname):
     print(f"{wname}: {e.nce} flagged pairs, {len(tie)} in the tie band")
     if wname == "ring_dense":
         assert e.nce > 10
+
+
+@pytest.mark.parametrize("dt", [0.04, 0.2, -0.1])
+def test_encounter_algorithms_agree(dt):
+    """All-pairs and sorted-tile checks give the same list on dense rings and
+    on a ragged batch (both apply the same exact predicate)."""
+    for w in (workloads.ring(5000, m=3e-8), workloads.batch([3, 1500, 64, 65, 1, 900, 2000])):
+        outs = []
+        for algo in (1, 2):
+            c = ctx_for(w, enc_algo=algo, enc_cap=1 << 18)
+            c.drift(dt)
+            e = c.encounters()
+            outs.append(e)
+            c.close()
+        assert outs[0].nce == outs[1].nce
+        assert np.array_equal(outs[0].ice, outs[1].ice) and np.array_equal(outs[0].jce, outs[1].jce)
+        assert np.array_equal(outs[0].ce, outs[1].ce)
+        print(f"{w.name} dt={dt}: {outs[0].nce} pairs")
 
 
 def test_encounter_capacity_overflow():
@@ -196,11 +215,11 @@ def test_diagnostics(case):
 
 
 # ---------------------------------------------------------------- full steps
-@pytest.mark.parametrize("mode", [0, 1])
-def test_steps_match_oracle(case, mode):
+@pytest.mark.parametrize("mode,algo", [(0, 1), (1, 1), (0, 2)])
+def test_steps_match_oracle(case, mode, algo):
     name, w, _ = case
     k = 5
-    c = ctx_for(w, mode=mode)
+    c = ctx_for(w, mode=mode, enc_algo=algo)
     st = oracle.State.from_workload(w)
     stats = c.step(w.dt, k)
     total = 0

@@ -67,3 +67,67 @@ def test_bound_on_kepler_arcs_of_a_dense_ring():
         for i, j in zip(out["ice"], out["jce"]):
             assert np.linalg.norm(M[j] - M[i]) <= R[i] + R[j]
         assert out["nce"] > 0
+
+
+def _tile(rng, k, center_scale, spread, dt):
+    """k bodies whose midpoints, chords and velocity deviations cluster."""
+    base_q = rng.normal(size=3) * center_scale
+    base_c = rng.normal(size=3) * spread * rng.uniform(0.5, 5)
+    out = []
+    for _ in range(k):
+        q0 = base_q + rng.normal(size=3) * spread
+        c = base_c + rng.normal(size=3) * spread * 0.3
+        q1 = q0 + c
+        v0 = (c + rng.normal(size=3) * spread * 0.2) / dt
+        v1 = (c + rng.normal(size=3) * spread * 0.2) / dt
+        out.append((q0, v0, q1, v1))
+    return out
+
+
+def tile_bounds(bodies, rcs, dt):
+    """Centre/spread of chord midpoints M, chords c and velocity deviations e."""
+    M = np.array([0.5 * (b[0] + b[2]) for b in bodies])
+    C = np.array([b[2] - b[0] for b in bodies])
+    e0 = np.array([dt * b[1] - (b[2] - b[0]) for b in bodies])
+    e1 = np.array([dt * b[3] - (b[2] - b[0]) for b in bodies])
+    eb, se = 0.5 * (e0 + e1), 0.5 * np.linalg.norm(e0 - e1, axis=1)
+    CM, Cc, Ce = M.mean(0), C.mean(0), eb.mean(0)
+    return (CM, np.max(np.linalg.norm(M - CM, axis=1)), Cc, np.max(np.linalg.norm(C - Cc, axis=1)),
+            Ce, np.max(np.linalg.norm(eb - Ce, axis=1) + se), max(rcs))
+
+
+def tiles_may_meet(A, B):
+    """False only if no pair (i in A, j in B) can be flagged:
+    |L(s)| >= D - S_M - C_m/2 = Lmin, |dQ| <= D + S_M + C_m/2 = Qmax,
+    |de| <= E_m, f >= Lmin^2 - Qmax E_m / 2 (basis weights |h10| + |h11| <= 1/4)."""
+    D = np.linalg.norm(B[0] - A[0])
+    Cm = np.linalg.norm(B[2] - A[2]) + A[3] + B[3]
+    Em = np.linalg.norm(B[4] - A[4]) + A[5] + B[5]
+    Lmin = D - A[1] - B[1] - 0.5 * Cm
+    Qmax = D + A[1] + B[1] + 0.5 * Cm
+    RC = max(A[6], B[6])
+    return not (Lmin > 0 and Lmin * Lmin - 0.5 * Qmax * Em > RC * RC)
+
+
+def test_tile_pair_bound_never_drops_a_flagged_pair():
+    rng = np.random.default_rng(77)
+    checked = culled = 0
+    for trial in range(400):
+        dt = rng.uniform(0.01, 0.2)
+        spread = 10 ** rng.uniform(-3, -1)
+        A = _tile(rng, 6, 1.0, spread, dt)
+        B = _tile(rng, 6, 1.0, spread, dt)
+        # pull B towards A so that many tile pairs are near the cull boundary
+        shift = (np.mean([b[0] for b in A], 0) - np.mean([b[0] for b in B], 0)) * rng.uniform(0.5, 1.0)
+        B = [(q0 + shift, v0, q1 + shift, v1) for q0, v0, q1, v1 in B]
+        rca = rng.uniform(0, 3 * spread, 6)
+        rcb = rng.uniform(0, 3 * spread, 6)
+        ok = tiles_may_meet(tile_bounds(A, rca, dt), tile_bounds(B, rcb, dt))
+        culled += not ok
+        for a, ra in zip(A, rca):
+            for b, rb in zip(B, rcb):
+                d2 = oracle.pair_min_d2(dt, *a, *b)
+                if d2 <= max(ra, rb) ** 2:
+                    assert ok, trial
+                checked += 1
+    assert culled > 50 and checked == 400 * 36
