@@ -17,6 +17,10 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
   energy / momenta           pinned (explicit barycentric formula, invariants)
   transforms                 pinned (barycentre definition, round trip)
   step                       pinned (2nd-order convergence, reversibility, E bound)
+  close-encounter resolver   pinned (Kepler flow for a lone body, relative Kepler
+  (Bulirsch-Stoer on H0)     orbit of a bound pair, H0 energy, time reversal;
+                             the full step converges at second order to an
+                             independent Newtonian integration)
   gas drag                   parity unpinned by the paper (limits and closed form
                              of the chosen formula only)
 """
@@ -73,6 +77,12 @@ def lib():
             "orc_drag_accel": (None, [i, d, d, p, p, p, p, d, d, d, d, p]),
             "orc_kick_drag": (None, [i, d, d, d, p, p, p, p, d, d, d, d, p]),
             "orc_step": (i, [i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, p, p, p, p, i, p, p, p, p]),
+            "orc_bs_work_doubles": (i, [i]),
+            "orc_resolve_work_doubles": (i, [i]),
+            "orc_bs_h0": (i, [i, d, d, d, p, p, d, d, p, p, p]),
+            "orc_resolve": (i, [i, d, d, d, p, p, d, d, p, p, i, p, p, p, p, p, p, p, p]),
+            "orc_step_full": (i, [i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, d, p, p, p, p, i, p, p,
+                                  p, p, p, p, p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -240,6 +250,36 @@ def drag_accel(G, m0, m, Q, V, prm: Params):
     return ad
 
 
+def bs_h0(G, m0, m, rc, Q, V, tau, tol=1e-12, inner=0.1):
+    """Advance one group under H0 (Kepler + (1 - K) pair part) by tau.
+    Returns (Q, V, steps); raises on failure."""
+    m = _f64(m); rc = _f64(rc); k = len(m)
+    y = np.empty((k, 6)); y[:, :3] = _f64(Q, (-1, 3)); y[:, 3:] = _f64(V, (-1, 3))
+    y = np.ascontiguousarray(y)
+    work = np.empty(max(lib().orc_bs_work_doubles(k), 1))
+    st = ctypes.c_int()
+    if lib().orc_bs_h0(k, float(G), float(m0), float(inner), _ptr(m), _ptr(rc), float(tau), float(tol),
+                       _ptr(y), _ptr(work), ctypes.byref(st)):
+        raise RuntimeError("Bulirsch-Stoer integration failed")
+    return y[:, :3].copy(), y[:, 3:].copy(), st.value
+
+
+def resolve(G, m0, m, rc, tau, Q0, V0, ice, jce, Q, V, tol=1e-12, inner=0.1):
+    """Resolve the groups of one system's pair list (local indices).
+    Returns (Q, V, comp, nfail, ngroups, max_steps)."""
+    m = _f64(m); rc = _f64(rc); n = len(m)
+    Q0 = _f64(Q0, (-1, 3)); V0 = _f64(V0, (-1, 3))
+    Q = _f64(Q, (-1, 3)).copy(); V = _f64(V, (-1, 3)).copy()
+    ice = np.ascontiguousarray(ice, dtype=np.int32); jce = np.ascontiguousarray(jce, dtype=np.int32)
+    comp = np.empty(max(n, 1), np.int32)
+    work = np.empty(max(lib().orc_resolve_work_doubles(n), 1))
+    ng, ms = ctypes.c_int(), ctypes.c_int()
+    nf = lib().orc_resolve(n, float(G), float(m0), float(inner), _ptr(m), _ptr(rc), float(tau), float(tol),
+                           _ptr(Q0), _ptr(V0), len(ice), _ptr(ice), _ptr(jce), _ptr(Q), _ptr(V), _ptr(comp),
+                           _ptr(work), ctypes.byref(ng), ctypes.byref(ms))
+    return Q, V, comp[:n].copy(), nf, ng.value, ms.value
+
+
 # ---------------------------------------------------------------- multi-system driver
 class State:
     """Oracle state of a batch of independent systems in DH coordinates.
@@ -283,15 +323,22 @@ class State:
             self.rc[a:b] = rcrit(self.m0[s], self.m[a:b], self.Q[a:b], p.n_hill)
             self.a[a:b] = force(self.m[a:b], self.Q[a:b], self.rc[a:b], p.G, p.inner)
 
-    def step(self, tau, cap=None):
-        """One hybrid step of every system; returns the total Kepler failures.
+    def step(self, tau, cap=None, full=False, tol=1e-12):
+        """One hybrid step of every system; returns the total Kepler failures
+        (plus, with ``full``, the failed close-encounter groups).
 
-        ``self.enc`` receives, per system, the flagged pair list in global
-        indices."""
+        ``full`` resolves the flagged groups by Bulirsch-Stoer on H0 between
+        the encounter check and the second stellar drift (the full hybrid
+        method); ``self.groups`` then holds, per body, its group label (the
+        smallest member, global index) or -1.  ``self.enc`` receives, per
+        system, the flagged pair list in global indices."""
         p = self.prm
         L = lib()
         nfail = 0
         self.enc = []
+        if full:
+            self.groups = np.full(len(self.m), -1, np.int64)
+            self.ngroups = 0
         for s, (a, b) in enumerate(self.systems()):
             n = b - a
             Q = np.ascontiguousarray(self.Q[a:b]); V = np.ascontiguousarray(self.V[a:b])
@@ -303,10 +350,24 @@ class State:
             c = n * (n - 1) // 2 if cap is None else cap
             ice = np.zeros(max(c, 1), np.int32); jce = np.zeros(max(c, 1), np.int32)
             nce = ctypes.c_int()
-            nfail += L.orc_step(n, p.G, float(self.m0[s]), p.n_hill, p.inner, _ptr(m), _ptr(Q), _ptr(V),
-                                _ptr(A), _ptr(rc), float(tau), int(p.drag), p.sigma0, p.h, p.cd, p.rho_p,
-                                _ptr(Q0), _ptr(V0), _ptr(kf), _ptr(scratch), int(c), _ptr(ice), _ptr(jce),
-                                _ptr(ce), ctypes.byref(nce))
+            if full:
+                comp = np.empty(max(n, 1), np.int32)
+                work = np.empty(max(L.orc_resolve_work_doubles(n), 1))
+                bsf, ng = ctypes.c_int(), ctypes.c_int()
+                nfail += L.orc_step_full(n, p.G, float(self.m0[s]), p.n_hill, p.inner, _ptr(m), _ptr(Q),
+                                         _ptr(V), _ptr(A), _ptr(rc), float(tau), int(p.drag), p.sigma0, p.h,
+                                         p.cd, p.rho_p, float(tol), _ptr(Q0), _ptr(V0), _ptr(kf),
+                                         _ptr(scratch), int(c), _ptr(ice), _ptr(jce), _ptr(ce),
+                                         ctypes.byref(nce), _ptr(comp), _ptr(work), ctypes.byref(bsf),
+                                         ctypes.byref(ng))
+                g = comp[:n].astype(np.int64)
+                self.groups[a:b] = np.where(g >= 0, g + a, -1)
+                self.ngroups += ng.value
+            else:
+                nfail += L.orc_step(n, p.G, float(self.m0[s]), p.n_hill, p.inner, _ptr(m), _ptr(Q), _ptr(V),
+                                    _ptr(A), _ptr(rc), float(tau), int(p.drag), p.sigma0, p.h, p.cd, p.rho_p,
+                                    _ptr(Q0), _ptr(V0), _ptr(kf), _ptr(scratch), int(c), _ptr(ice), _ptr(jce),
+                                    _ptr(ce), ctypes.byref(nce))
             self.Q[a:b] = Q; self.V[a:b] = V; self.a[a:b] = A; self.rc[a:b] = rc
             self.Q0[a:b] = Q0; self.V0[a:b] = V0; self.kflag[a:b] = kf; self.ce[a:b] = ce[:n]
             k = min(nce.value, c)

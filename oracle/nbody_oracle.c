@@ -43,6 +43,7 @@
 #include <stdint.h>
 #include <string.h>
 #include <float.h>
+#include <stdlib.h>
 
 /* ------------------------------------------------------------------ */
 /* Compensated (Neumaier) accumulation                                 */
@@ -648,4 +649,294 @@ int orc_step(int n, double G, double m0, double n_hill, double inner, const doub
     else
         orc_kick(n, h, a, V);
     return nfail;
+}
+
+/* ------------------------------------------------------------------ */
+/* Close-encounter resolution, the full hybrid method (Sec. 2.1.1,     */
+/* footnote on the critical radius: inside it the interaction and the   */
+/* Kepler parts of the bodies involved are advanced by Bulirsch-Stoer;  */
+/* Sec. 3 and 3.2: that integration runs on the host after the bodies   */
+/* are restored to their state before the drift).                       */
+/*                                                                      */
+/* Readings.  Flagged pairs join bodies into groups (connected          */
+/* components of the pair graph; members in index order, groups ordered */
+/* by their smallest member).  Each group restarts from (Q0, V0) and     */
+/* follows, for the whole step tau, the flow of                          */
+/*   H0 = sum_i [m_i |V_i|^2 / 2 - G m0 m_i / |Q_i|]                    */
+/*        - sum_{i<j in the group} G m_i m_j (1 - K(r_ij)) / r_ij,       */
+/* the part of the Hamiltonian the Kepler drift leaves out inside the    */
+/* changeover zone:                                                      */
+/*   dQ_i/dt = V_i,                                                      */
+/*   dV_i/dt = -G m0 Q_i / |Q_i|^3                                       */
+/*             + sum_j G m_j [(1 - K)/r^3 + (dK/dr)/r^2] (Q_j - Q_i),    */
+/* with rc_ij = max(rc_i, rc_j) from the step's encounter check.         */
+/* Integrator: Gragg's modified midpoint rule with polynomial            */
+/* extrapolation in h^2 (Bulirsch-Stoer), substeps 2, 4, 6, ..., 16;     */
+/* error of a column = largest per-body |dQ|/|Q| or |dV|/|V| between the  */
+/* last two extrapolants; a step is taken when that error <= tol, and   */
+/* the next step length scales by 0.94 (0.65 tol/err)^(1/(2k+1)),        */
+/* clamped to [0.02, 4].                                                 */
+/* ------------------------------------------------------------------ */
+#define ORC_BS_COLS 8
+#define ORC_BS_MAXSTEPS 100000
+
+/* y holds, per member b, Q at y[6b..6b+2] and V at y[6b+3..6b+5]. */
+static void h0_deriv(int k, double G, double m0, double inner, const double *m, const double *rc,
+                     const double *y, double *dy)
+{
+    for (int b = 0; b < k; ++b) {
+        const double *q = y + 6 * b;
+        double r2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        double r = sqrt(r2);
+        double c = -G * m0 / (r2 * r);
+        nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+        ns_add(&ax, c * q[0]);
+        ns_add(&ay, c * q[1]);
+        ns_add(&az, c * q[2]);
+        for (int o = 0; o < k; ++o) {
+            if (o == b)
+                continue;
+            const double *p = y + 6 * o;
+            double dx = p[0] - q[0], dy_ = p[1] - q[1], dz = p[2] - q[2];
+            double s2 = dx * dx + dy_ * dy_ + dz * dz;
+            if (s2 == 0.0)
+                continue;
+            double s = sqrt(s2);
+            double K, dK;
+            orc_changeover(s, fmax(rc[b], rc[o]), inner, &K, &dK);
+            double w = G * m[o] * ((1.0 - K) / (s2 * s) + dK / s2);
+            ns_add(&ax, w * dx);
+            ns_add(&ay, w * dy_);
+            ns_add(&az, w * dz);
+        }
+        dy[6 * b] = y[6 * b + 3];
+        dy[6 * b + 1] = y[6 * b + 4];
+        dy[6 * b + 2] = y[6 * b + 5];
+        dy[6 * b + 3] = ns_val(&ax);
+        dy[6 * b + 4] = ns_val(&ay);
+        dy[6 * b + 5] = ns_val(&az);
+    }
+}
+
+/* Gragg's modified midpoint rule: nsub substeps of H from y0 into out.
+ * z, zp, f are scratch of 6k doubles each. */
+static void modified_midpoint(int k, double G, double m0, double inner, const double *m,
+                              const double *rc, const double *y0, double H, int nsub, double *out,
+                              double *zp, double *z, double *f)
+{
+    const int d = 6 * k;
+    double h = H / nsub;
+    h0_deriv(k, G, m0, inner, m, rc, y0, f);
+    for (int c = 0; c < d; ++c) {
+        zp[c] = y0[c];
+        z[c] = y0[c] + h * f[c];
+    }
+    for (int s = 1; s < nsub; ++s) {
+        h0_deriv(k, G, m0, inner, m, rc, z, f);
+        for (int c = 0; c < d; ++c) {
+            double zn = zp[c] + 2.0 * h * f[c];
+            zp[c] = z[c];
+            z[c] = zn;
+        }
+    }
+    h0_deriv(k, G, m0, inner, m, rc, z, f);
+    for (int c = 0; c < d; ++c)
+        out[c] = 0.5 * (z[c] + zp[c] + h * f[c]);
+}
+
+/* Largest per-body relative difference of positions and velocities. */
+static double bs_err(int k, const double *a, const double *b)
+{
+    double e = 0.0;
+    for (int i = 0; i < k; ++i) {
+        for (int part = 0; part < 2; ++part) {
+            const double *x = a + 6 * i + 3 * part, *y = b + 6 * i + 3 * part;
+            double dx = x[0] - y[0], dy = x[1] - y[1], dz = x[2] - y[2];
+            double nd = sqrt(dx * dx + dy * dy + dz * dz);
+            double nx = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+            double q = nx > 0.0 ? nd / nx : nd;
+            if (!(q <= e))
+                e = q;            /* also takes a NaN */
+        }
+    }
+    return e;
+}
+
+/* Advance one group (k members, state y in the layout above) by tau under
+ * H0 with relative tolerance tol.  work holds orc_bs_work_doubles(k)
+ * doubles.  Returns 0, or 1 when the step count limit or a non-finite
+ * state ends the integration (y is then left unchanged). */
+int orc_bs_work_doubles(int k) { return (2 * ORC_BS_COLS + 4) * 6 * k; }
+
+int orc_bs_h0(int k, double G, double m0, double inner, const double *m, const double *rc,
+              double tau, double tol, double *y, double *work, int *nsteps_out)
+{
+    const int d = 6 * k;
+    /* extrapolation tableau, two rows: prev[j] = T(c-1, j), cur[j] = T(c, j) */
+    double *prev = work, *cur = prev + ORC_BS_COLS * d;
+    double *zp = cur + ORC_BS_COLS * d, *z = zp + d, *f = z + d, *yc = f + d;
+    memcpy(yc, y, sizeof(double) * d);
+    double t = 0.0, H = tau;
+    int nsteps = 0;
+    while (t != tau) {
+        if (++nsteps > ORC_BS_MAXSTEPS)
+            return 1;
+        double rem = tau - t;
+        int last = fabs(H) >= fabs(rem);
+        if (last)
+            H = rem;
+        int accepted = 0;
+        double fac = 0.25;
+        for (int c = 0; c < ORC_BS_COLS; ++c) {
+            const int nc = 2 * (c + 1);                  /* substeps of row c */
+            modified_midpoint(k, G, m0, inner, m, rc, yc, H, nc, cur, zp, z, f);
+            for (int j = 1; j <= c; ++j) {
+                double ratio = (double)nc / (double)(2 * (c - j + 1));
+                double den = ratio * ratio - 1.0;
+                for (int e = 0; e < d; ++e)
+                    cur[j * d + e] = cur[(j - 1) * d + e] +
+                                     (cur[(j - 1) * d + e] - prev[(j - 1) * d + e]) / den;
+            }
+            if (c > 0) {
+                double err = bs_err(k, cur + c * d, cur + (c - 1) * d) / tol;
+                if (!isfinite(err))
+                    break;
+                double g = (err > 0.0) ? 0.94 * pow(0.65 / err, 1.0 / (2 * c + 1)) : 4.0;
+                if (err <= 1.0) {
+                    fac = fmin(4.0, fmax(0.02, g));
+                    memcpy(yc, cur + c * d, sizeof(double) * d);
+                    accepted = 1;
+                    break;
+                }
+                fac = fmin(0.5, fmax(0.02, g));
+            }
+            double *sw = prev;
+            prev = cur;
+            cur = sw;
+        }
+        if (accepted)
+            t = last ? tau : t + H;
+        H *= fac;
+        for (int e = 0; e < d; ++e)
+            if (!isfinite(yc[e]))
+                return 1;
+    }
+    memcpy(y, yc, sizeof(double) * d);
+    if (nsteps_out)
+        *nsteps_out = nsteps;
+    return 0;
+}
+
+/* Connected components of the pair graph over n bodies: comp[i] is the
+ * smallest member of body i's group, or -1 for a body in no pair. */
+static int find_root(int32_t *parent, int i)
+{
+    while (parent[i] != i)
+        i = parent[i];
+    return i;
+}
+
+/* Resolve every group of one system: members restart from (Q0, V0) and are
+ * advanced by tau under H0; the others keep (Q, V).  comp (n ints) receives
+ * each body's group label (its smallest member) or -1.  work holds
+ * orc_resolve_work_doubles(n) doubles.  Returns the number of groups whose
+ * integration failed; their members keep the Kepler-drifted state. */
+int orc_resolve_work_doubles(int n) { return orc_bs_work_doubles(n) + 6 * n + 2 * n; }
+
+int orc_resolve(int n, double G, double m0, double inner, const double *m, const double *rc,
+                double tau, double tol, const double *Q0, const double *V0, int nce,
+                const int32_t *ice, const int32_t *jce, double *Q, double *V, int32_t *comp,
+                double *work, int *ngroups_out, int *max_steps_out)
+{
+    for (int i = 0; i < n; ++i)
+        comp[i] = i;
+    int32_t *inpair = (int32_t *)(work + orc_bs_work_doubles(n) + 6 * n);
+    for (int i = 0; i < n; ++i)
+        inpair[i] = 0;
+    for (int p = 0; p < nce; ++p) {
+        int a = find_root(comp, ice[p]), b = find_root(comp, jce[p]);
+        inpair[ice[p]] = inpair[jce[p]] = 1;
+        if (a != b) {
+            if (a < b)
+                comp[b] = a;
+            else
+                comp[a] = b;
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        comp[i] = inpair[i] ? find_root(comp, i) : -1;
+    double *y = work + orc_bs_work_doubles(n);
+    double *gm = (double *)malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+    int *mem = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
+    int nfail = 0, ngroups = 0, maxst = 0;
+    for (int root = 0; root < n; ++root) {
+        if (comp[root] != root)
+            continue;
+        int k = 0;
+        for (int i = root; i < n; ++i)
+            if (comp[i] == root)
+                mem[k++] = i;
+        for (int b = 0; b < k; ++b) {
+            int i = mem[b];
+            memcpy(y + 6 * b, Q0 + 3 * i, 3 * sizeof(double));
+            memcpy(y + 6 * b + 3, V0 + 3 * i, 3 * sizeof(double));
+            gm[b] = m[i];
+            gm[n + b] = rc[i];
+        }
+        int st = 0;
+        int fail = orc_bs_h0(k, G, m0, inner, gm, gm + n, tau, tol, y, work, &st);
+        ++ngroups;
+        if (st > maxst)
+            maxst = st;
+        if (fail) {
+            ++nfail;
+            continue;
+        }
+        for (int b = 0; b < k; ++b) {
+            int i = mem[b];
+            memcpy(Q + 3 * i, y + 6 * b, 3 * sizeof(double));
+            memcpy(V + 3 * i, y + 6 * b + 3, 3 * sizeof(double));
+        }
+    }
+    free(gm);
+    free(mem);
+    if (ngroups_out)
+        *ngroups_out = ngroups;
+    if (max_steps_out)
+        *max_steps_out = maxst;
+    return nfail;
+}
+
+/* One step of the full hybrid method: the hot-path step with the flagged
+ * groups resolved between the encounter check and the second stellar drift.
+ * Returns Kepler failures + resolver failures (the latter also in *bsfail). */
+int orc_step_full(int n, double G, double m0, double n_hill, double inner, const double *m,
+                  double *Q, double *V, double *a, double *rc, double tau, int drag, double sigma0,
+                  double hr, double cd, double rho_p, double tol, double *Q0, double *V0,
+                  int32_t *kflag, double *scratch, int cap, int32_t *ice, int32_t *jce, int32_t *ce,
+                  int *nce, int32_t *comp, double *work, int *bsfail, int *ngroups)
+{
+    double h = 0.5 * tau;
+    if (drag)
+        orc_kick_drag(n, h, G, m0, m, Q, a, V, sigma0, hr, cd, rho_p, scratch);
+    else
+        orc_kick(n, h, a, V);
+    orc_sun_drift(n, h, m0, m, V, Q);
+    memcpy(Q0, Q, sizeof(double) * 3 * n);
+    memcpy(V0, V, sizeof(double) * 3 * n);
+    int nfail = orc_drift(n, G * m0, tau, Q, V, kflag);
+    int ntie = 0;
+    int32_t ti = 0, tj = 0;
+    orc_encounters(n, tau, Q0, V0, Q, V, rc, cap, ice, jce, ce, nce, 0.0, 0, &ti, &tj, &ntie);
+    int k = *nce < cap ? *nce : cap;
+    *bsfail = orc_resolve(n, G, m0, inner, m, rc, tau, tol, Q0, V0, k, ice, jce, Q, V, comp, work,
+                          ngroups, NULL);
+    orc_sun_drift(n, h, m0, m, V, Q);
+    orc_rcrit(n, m0, m, Q, n_hill, rc);
+    orc_force(n, G, inner, m, Q, rc, a);
+    if (drag)
+        orc_kick_drag(n, h, G, m0, m, Q, a, V, sigma0, hr, cd, rho_p, scratch);
+    else
+        orc_kick(n, h, a, V);
+    return nfail + *bsfail;
 }
