@@ -17,6 +17,9 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
   energy / momenta           pinned (explicit barycentric formula, invariants)
   transforms                 pinned (barycentre definition, round trip)
   step                       pinned (2nd-order convergence, reversibility, E bound)
+  big/small split            pinned (massless sources change no sum, big bodies
+                             do not see small ones, each small body moves as if
+                             alone with the big ones, small pairs never flagged)
   close-encounter resolver   pinned (Kepler flow for a lone body, relative Kepler
   (Bulirsch-Stoer on H0)     orbit of a bound pair, H0 energy, time reversal;
                              the full step converges at second order to an
@@ -61,6 +64,7 @@ def lib():
             "orc_changeover": (None, [d, d, d, p, p]),
             "orc_rcrit": (None, [i, d, p, p, d, p]),
             "orc_force": (None, [i, d, d, p, p, p, p]),
+            "orc_force_nb": (None, [i, i, d, d, p, p, p, p]),
             "orc_force_subset": (None, [i, d, d, p, p, p, i, p, p]),
             "orc_kick": (None, [i, d, p, p]),
             "orc_momentum": (None, [i, p, p, p]),
@@ -72,17 +76,18 @@ def lib():
             "orc_drift": (i, [i, d, d, p, p, p]),
             "orc_pair_min_d2": (d, [d, p, p, p, p, p, p, p, p]),
             "orc_encounters": (None, [i, d, p, p, p, p, p, i, p, p, p, p, d, i, p, p, p]),
-            "orc_pair_scan": (None, [i, d, p, p, p, p, p, i, d, p, p]),
+            "orc_encounters_nb": (None, [i, i, d, p, p, p, p, p, i, p, p, p, p, d, i, p, p, p]),
+            "orc_pair_scan": (None, [i, i, d, p, p, p, p, p, i, d, p, p]),
             "orc_energy": (None, [i, d, d, d, p, p, p, p, p, p, p, p]),
             "orc_drag_accel": (None, [i, d, d, p, p, p, p, d, d, d, d, p]),
             "orc_kick_drag": (None, [i, d, d, d, p, p, p, p, d, d, d, d, p]),
-            "orc_step": (i, [i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, p, p, p, p, i, p, p, p, p]),
+            "orc_step": (i, [i, i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, p, p, p, p, i, p, p, p, p]),
             "orc_bs_work_doubles": (i, [i]),
             "orc_resolve_work_doubles": (i, [i]),
             "orc_bs_h0": (i, [i, d, d, d, p, p, d, d, p, p, p]),
             "orc_resolve": (i, [i, d, d, d, p, p, d, d, p, p, i, p, p, p, p, p, p, p, p]),
-            "orc_step_full": (i, [i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, d, p, p, p, p, i, p, p,
-                                  p, p, p, p, p, p]),
+            "orc_step_full": (i, [i, i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, d, p, p, p, p, i, p,
+                                  p, p, p, p, p, p, p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -137,9 +142,12 @@ def rcrit(m0, m, Q, n_hill=3.0):
     return rc
 
 
-def force(m, Q, rc, G, inner=0.1):
+def force(m, Q, rc, G, inner=0.1, nbig=None):
+    """Interaction acceleration; with nbig, only the first nbig bodies are sources."""
     m = _f64(m); Q = _f64(Q, (-1, 3)); rc = _f64(rc); a = np.empty_like(Q)
-    lib().orc_force(len(m), float(G), float(inner), _ptr(m), _ptr(Q), _ptr(rc), _ptr(a))
+    n = len(m)
+    lib().orc_force_nb(n, n if nbig is None else int(nbig), float(G), float(inner), _ptr(m), _ptr(Q),
+                       _ptr(rc), _ptr(a))
     return a
 
 
@@ -203,8 +211,9 @@ def pair_min_d2(tau, q0i, v0i, q1i, v1i, q0j, v0j, q1j, v1j):
     return lib().orc_pair_min_d2(float(tau), *[_ptr(t) for t in args])
 
 
-def encounters(tau, Q0, V0, Q1, V1, rc, cap=None, tie=1e-10):
-    """Flagged pairs (i<j, lexicographic), per-body flags, tie-band pairs."""
+def encounters(tau, Q0, V0, Q1, V1, rc, cap=None, tie=1e-10, nbig=None):
+    """Flagged pairs (i<j, lexicographic), per-body flags, tie-band pairs.
+    With nbig, pairs of two small bodies (both >= nbig) are not tested."""
     Q0, V0, Q1, V1 = (_f64(t, (-1, 3)) for t in (Q0, V0, Q1, V1))
     rc = _f64(rc); n = len(rc)
     cap = n * (n - 1) // 2 if cap is None else cap
@@ -214,21 +223,22 @@ def encounters(tau, Q0, V0, Q1, V1, rc, cap=None, tie=1e-10):
     tie_cap = 1 << 16
     ti = np.zeros(tie_cap, np.int32); tj = np.zeros(tie_cap, np.int32)
     nce = ctypes.c_int(); ntie = ctypes.c_int()
-    lib().orc_encounters(n, float(tau), _ptr(Q0), _ptr(V0), _ptr(Q1), _ptr(V1), _ptr(rc), int(cap),
-                         _ptr(ice), _ptr(jce), _ptr(ce), ctypes.byref(nce), float(tie), tie_cap,
-                         _ptr(ti), _ptr(tj), ctypes.byref(ntie))
+    lib().orc_encounters_nb(n, n if nbig is None else int(nbig), float(tau), _ptr(Q0), _ptr(V0), _ptr(Q1),
+                            _ptr(V1), _ptr(rc), int(cap), _ptr(ice), _ptr(jce), _ptr(ce), ctypes.byref(nce),
+                            float(tie), tie_cap, _ptr(ti), _ptr(tj), ctypes.byref(ntie))
     k = min(nce.value, cap)
     t = min(ntie.value, tie_cap)
     return {"nce": nce.value, "ice": ice[:k].copy(), "jce": jce[:k].copy(), "ce": ce[:n].copy(),
             "tie": set(zip(ti[:t].tolist(), tj[:t].tolist())), "ntie": ntie.value}
 
 
-def pair_scan(tau, Q0, V0, Q1, V1, rc, i, tie=1e-10):
+def pair_scan(tau, Q0, V0, Q1, V1, rc, i, tie=1e-10, nbig=None):
     """Flags of every pair (i, j) of one system under the encounter predicate."""
     Q0, V0, Q1, V1 = (_f64(t, (-1, 3)) for t in (Q0, V0, Q1, V1))
     rc = _f64(rc); n = len(rc)
     flag = np.zeros(n, np.int32); tflag = np.zeros(n, np.int32)
-    lib().orc_pair_scan(n, float(tau), _ptr(Q0), _ptr(V0), _ptr(Q1), _ptr(V1), _ptr(rc), int(i),
+    lib().orc_pair_scan(n, n if nbig is None else int(nbig), float(tau), _ptr(Q0), _ptr(V0), _ptr(Q1),
+                        _ptr(V1), _ptr(rc), int(i),
                         float(tie), _ptr(flag), _ptr(tflag))
     return flag.astype(bool), tflag.astype(bool)
 
@@ -288,9 +298,11 @@ class State:
     force primed at construction (first-same-as-last).
     """
 
-    def __init__(self, off, m0, m, x, v, prm: Params | None = None, frame="helio"):
+    def __init__(self, off, m0, m, x, v, prm: Params | None = None, frame="helio", nbig=None):
         self.prm = prm or Params()
         self.off = np.asarray(off, dtype=np.int64)
+        # per system: bodies [off[s], off[s] + nbig[s]) are big (gravity sources)
+        self.nbig = (np.diff(self.off) if nbig is None else np.asarray(nbig, dtype=np.int64)).copy()
         self.m0 = _f64(m0).copy()
         self.m = _f64(m).copy()
         n = len(self.m)
@@ -311,7 +323,7 @@ class State:
     @classmethod
     def from_workload(cls, w, prm: Params | None = None):
         prm = prm or Params(G=w.G, drag=w.drag)
-        return cls(w.off, w.m0, w.m, w.x, w.v, prm)
+        return cls(w.off, w.m0, w.m, w.x, w.v, prm, nbig=getattr(w, "nbig", None))
 
     def systems(self):
         for s in range(len(self.m0)):
@@ -321,7 +333,7 @@ class State:
         p = self.prm
         for s, (a, b) in enumerate(self.systems()):
             self.rc[a:b] = rcrit(self.m0[s], self.m[a:b], self.Q[a:b], p.n_hill)
-            self.a[a:b] = force(self.m[a:b], self.Q[a:b], self.rc[a:b], p.G, p.inner)
+            self.a[a:b] = force(self.m[a:b], self.Q[a:b], self.rc[a:b], p.G, p.inner, nbig=self.nbig[s])
 
     def step(self, tau, cap=None, full=False, tol=1e-12):
         """One hybrid step of every system; returns the total Kepler failures
@@ -354,7 +366,7 @@ class State:
                 comp = np.empty(max(n, 1), np.int32)
                 work = np.empty(max(L.orc_resolve_work_doubles(n), 1))
                 bsf, ng = ctypes.c_int(), ctypes.c_int()
-                nfail += L.orc_step_full(n, p.G, float(self.m0[s]), p.n_hill, p.inner, _ptr(m), _ptr(Q),
+                nfail += L.orc_step_full(n, int(self.nbig[s]), p.G, float(self.m0[s]), p.n_hill, p.inner, _ptr(m), _ptr(Q),
                                          _ptr(V), _ptr(A), _ptr(rc), float(tau), int(p.drag), p.sigma0, p.h,
                                          p.cd, p.rho_p, float(tol), _ptr(Q0), _ptr(V0), _ptr(kf),
                                          _ptr(scratch), int(c), _ptr(ice), _ptr(jce), _ptr(ce),
@@ -364,7 +376,7 @@ class State:
                 self.groups[a:b] = np.where(g >= 0, g + a, -1)
                 self.ngroups += ng.value
             else:
-                nfail += L.orc_step(n, p.G, float(self.m0[s]), p.n_hill, p.inner, _ptr(m), _ptr(Q), _ptr(V),
+                nfail += L.orc_step(n, int(self.nbig[s]), p.G, float(self.m0[s]), p.n_hill, p.inner, _ptr(m), _ptr(Q), _ptr(V),
                                     _ptr(A), _ptr(rc), float(tau), int(p.drag), p.sigma0, p.h, p.cd, p.rho_p,
                                     _ptr(Q0), _ptr(V0), _ptr(kf), _ptr(scratch), int(c), _ptr(ice), _ptr(jce),
                                     _ptr(ce), ctypes.byref(nce))

@@ -106,12 +106,14 @@ void orc_rcrit(int n, double m0, const double *m, const double *Q, double n_hill
 /* gradient of the potential -G m_i m_j K(r)/r.  Coincident distinct     */
 /* bodies (r = 0) contribute nothing; the self term is skipped by index.  */
 /* ------------------------------------------------------------------ */
-void orc_force(int n, double G, double inner, const double *m, const double *Q,
-               const double *rc, double *a)
+/* Big and small bodies (Sec. 2.1): only the first nbig bodies of a system are
+ * gravity sources; the others are massless and feel the big ones only. */
+void orc_force_nb(int n, int nbig, double G, double inner, const double *m, const double *Q,
+                  const double *rc, double *a)
 {
     for (int i = 0; i < n; ++i) {
         nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
-        for (int j = 0; j < n; ++j) {
+        for (int j = 0; j < nbig; ++j) {
             if (j == i)
                 continue;
             double dx = Q[3 * j] - Q[3 * i];
@@ -134,6 +136,12 @@ void orc_force(int n, double G, double inner, const double *m, const double *Q,
         a[3 * i + 1] = ns_val(&ay);
         a[3 * i + 2] = ns_val(&az);
     }
+}
+
+void orc_force(int n, double G, double inner, const double *m, const double *Q,
+               const double *rc, double *a)
+{
+    orc_force_nb(n, n, G, inner, m, Q, rc, a);
 }
 
 /* The same sum for selected targets only (large-N sampled checks): a[k] is
@@ -457,15 +465,17 @@ double orc_pair_min_d2(double tau, const double *q0i, const double *v0i, const d
  * in *nce); ce[i] = ce[j] = 2 for flagged bodies, 0 otherwise.  Pairs whose
  * minimum lies within tie*rc_ij^2 of the threshold are reported in
  * (tie_i, tie_j) (up to tie_cap; true count in *ntie). */
-void orc_encounters(int n, double tau, const double *Q0, const double *V0, const double *Q1,
-                    const double *V1, const double *rc, int cap, int32_t *ice, int32_t *jce,
-                    int32_t *ce, int *nce, double tie, int tie_cap, int32_t *tie_i,
-                    int32_t *tie_j, int *ntie)
+/* With nbig < n the bodies from nbig on are small: two small bodies do not
+ * interact (Sec. 2.1), so only pairs with i < nbig are tested (i < j). */
+void orc_encounters_nb(int n, int nbig, double tau, const double *Q0, const double *V0,
+                       const double *Q1, const double *V1, const double *rc, int cap,
+                       int32_t *ice, int32_t *jce, int32_t *ce, int *nce, double tie,
+                       int tie_cap, int32_t *tie_i, int32_t *tie_j, int *ntie)
 {
     int cnt = 0, tcnt = 0;
     for (int i = 0; i < n; ++i)
         ce[i] = 0;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < nbig; ++i) {
         for (int j = i + 1; j < n; ++j) {
             double d2 = orc_pair_min_d2(tau, Q0 + 3 * i, V0 + 3 * i, Q1 + 3 * i, V1 + 3 * i,
                                         Q0 + 3 * j, V0 + 3 * j, Q1 + 3 * j, V1 + 3 * j);
@@ -493,17 +503,26 @@ void orc_encounters(int n, double tau, const double *Q0, const double *V0, const
     *ntie = tcnt;
 }
 
+void orc_encounters(int n, double tau, const double *Q0, const double *V0, const double *Q1,
+                    const double *V1, const double *rc, int cap, int32_t *ice, int32_t *jce,
+                    int32_t *ce, int *nce, double tie, int tie_cap, int32_t *tie_i,
+                    int32_t *tie_j, int *ntie)
+{
+    orc_encounters_nb(n, n, tau, Q0, V0, Q1, V1, rc, cap, ice, jce, ce, nce, tie, tie_cap, tie_i,
+                      tie_j, ntie);
+}
+
 /* One body i against every other body j of the system (large-N sampled
  * checks): flag[j] = 1 if the pair (min(i,j), max(i,j)) is flagged by the same
  * predicate, tie[j] = 1 if its minimum lies in the tie band. */
-void orc_pair_scan(int n, double tau, const double *Q0, const double *V0, const double *Q1,
-                   const double *V1, const double *rc, int i, double tie, int32_t *flag,
-                   int32_t *tieflag)
+void orc_pair_scan(int n, int nbig, double tau, const double *Q0, const double *V0,
+                   const double *Q1, const double *V1, const double *rc, int i, double tie,
+                   int32_t *flag, int32_t *tieflag)
 {
     for (int j = 0; j < n; ++j) {
         flag[j] = 0;
         tieflag[j] = 0;
-        if (j == i)
+        if (j == i || (i >= nbig && j >= nbig))
             continue;
         int a = i < j ? i : j, b = i < j ? j : i;
         double d2 = orc_pair_min_d2(tau, Q0 + 3 * a, V0 + 3 * a, Q1 + 3 * a, V1 + 3 * a,
@@ -624,7 +643,7 @@ void orc_kick_drag(int n, double h, double G, double m0, const double *m, const 
 /* Q0, V0 receive the pre-drift copies; the encounter outputs are those    */
 /* of orc_encounters.  Returns the number of Kepler failures.              */
 /* ------------------------------------------------------------------ */
-int orc_step(int n, double G, double m0, double n_hill, double inner, const double *m,
+int orc_step(int n, int nbig, double G, double m0, double n_hill, double inner, const double *m,
              double *Q, double *V, double *a, double *rc, double tau, int drag, double sigma0,
              double hr, double cd, double rho_p, double *Q0, double *V0, int32_t *kflag,
              double *scratch, int cap, int32_t *ice, int32_t *jce, int32_t *ce, int *nce)
@@ -640,10 +659,11 @@ int orc_step(int n, double G, double m0, double n_hill, double inner, const doub
     int nfail = orc_drift(n, G * m0, tau, Q, V, kflag);
     int ntie = 0;
     int32_t ti = 0, tj = 0;
-    orc_encounters(n, tau, Q0, V0, Q, V, rc, cap, ice, jce, ce, nce, 0.0, 0, &ti, &tj, &ntie);
+    orc_encounters_nb(n, nbig, tau, Q0, V0, Q, V, rc, cap, ice, jce, ce, nce, 0.0, 0, &ti, &tj,
+                      &ntie);
     orc_sun_drift(n, h, m0, m, V, Q);
     orc_rcrit(n, m0, m, Q, n_hill, rc);
-    orc_force(n, G, inner, m, Q, rc, a);
+    orc_force_nb(n, nbig, G, inner, m, Q, rc, a);
     if (drag)
         orc_kick_drag(n, h, G, m0, m, Q, a, V, sigma0, hr, cd, rho_p, scratch);
     else
@@ -910,7 +930,7 @@ int orc_resolve(int n, double G, double m0, double inner, const double *m, const
 /* One step of the full hybrid method: the hot-path step with the flagged
  * groups resolved between the encounter check and the second stellar drift.
  * Returns Kepler failures + resolver failures (the latter also in *bsfail). */
-int orc_step_full(int n, double G, double m0, double n_hill, double inner, const double *m,
+int orc_step_full(int n, int nbig, double G, double m0, double n_hill, double inner, const double *m,
                   double *Q, double *V, double *a, double *rc, double tau, int drag, double sigma0,
                   double hr, double cd, double rho_p, double tol, double *Q0, double *V0,
                   int32_t *kflag, double *scratch, int cap, int32_t *ice, int32_t *jce, int32_t *ce,
@@ -927,13 +947,14 @@ int orc_step_full(int n, double G, double m0, double n_hill, double inner, const
     int nfail = orc_drift(n, G * m0, tau, Q, V, kflag);
     int ntie = 0;
     int32_t ti = 0, tj = 0;
-    orc_encounters(n, tau, Q0, V0, Q, V, rc, cap, ice, jce, ce, nce, 0.0, 0, &ti, &tj, &ntie);
+    orc_encounters_nb(n, nbig, tau, Q0, V0, Q, V, rc, cap, ice, jce, ce, nce, 0.0, 0, &ti, &tj,
+                      &ntie);
     int k = *nce < cap ? *nce : cap;
     *bsfail = orc_resolve(n, G, m0, inner, m, rc, tau, tol, Q0, V0, k, ice, jce, Q, V, comp, work,
                           ngroups, NULL);
     orc_sun_drift(n, h, m0, m, V, Q);
     orc_rcrit(n, m0, m, Q, n_hill, rc);
-    orc_force(n, G, inner, m, Q, rc, a);
+    orc_force_nb(n, nbig, G, inner, m, Q, rc, a);
     if (drag)
         orc_kick_drag(n, h, G, m0, m, Q, a, V, sigma0, hr, cd, rho_p, scratch);
     else

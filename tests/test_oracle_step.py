@@ -49,7 +49,7 @@ class _Runner:
 
     def step(self, tau, k=1):
         L = self.orc.lib(); p = self.p; P = self._ptr
-        args = (self.n, p.G, self.m0, p.n_hill, p.inner, P(self.m), P(self.Q), P(self.V), P(self.a), P(self.rc),
+        args = (self.n, self.n, p.G, self.m0, p.n_hill, p.inner, P(self.m), P(self.Q), P(self.V), P(self.a), P(self.rc),
                 float(tau), int(p.drag), p.sigma0, p.h, p.cd, p.rho_p, P(self.Q0), P(self.V0), P(self.kf),
                 P(self.scr), len(self.ice), P(self.ice), P(self.jce), P(self.ce), ctypes.byref(self.nce))
         f = 0
