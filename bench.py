@@ -34,8 +34,20 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32c": 157.3}   # MI355X vector FP64 / FP32 (publ
 KERNEL_SRC = os.path.join(ROOT, "paper_2601_19654_amd", "csrc", "nb_kernels.hip")
 
 
+def force_kernel_source() -> str:
+    """Source text the force kernels are built from: the shared helpers, the
+    force section and its launcher (a change elsewhere leaves it alone)."""
+    src = open(KERNEL_SRC).read()
+    helpers = re.search(r"// small helpers\n.*?(?=\n// -{20,}\n)", src, re.S)
+    force = re.search(r"// Interaction force .*?(?=\n// -{20,}\n// Encounter check)", src, re.S)
+    launch = re.search(r"hipError_t launch_force\(.*?\n}\n", src, re.S)
+    if not (helpers and force and launch):
+        raise RuntimeError("force kernel source sections not found")
+    return helpers.group(0) + force.group(0) + launch.group(0)
+
+
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(force_kernel_source().encode()).hexdigest()[:16]
 
 
 def traffic_from_profiles(mode: str, workload: str = "c3"):
@@ -52,11 +64,13 @@ def traffic_from_profiles(mode: str, workload: str = "c3"):
     return float(t.group(1))
 
 
-def run_mode(w, mode: str, steps: int, warmup: int, torch, nb):
-    p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64, drag=int(w.drag))
-    ctx = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0")
+def run_mode(w, mode: str, steps: int, warmup: int, torch, nb, resolve: bool = False):
+    p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64, drag=int(w.drag),
+                          resolve=int(resolve))
+    ctx = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", nbig=w.nbig)
     tiles = {"source": ctx.tiles, "force_r": ctx.params.force_r, "force_jchunk": ctx.params.force_jchunk,
-             "enc_jchunk": ctx.params.enc_jchunk, "enc_algo": ctx.params.enc_algo}
+             "enc_jchunk": ctx.params.enc_jchunk, "enc_algo": ctx.params.enc_algo,
+             "step_algo": ctx.params.step_algo}
     ctx.upload(w.m0, w.m, w.x, w.v)
     pairs = w.pairs()
     # warmup (untimed), also builds the step graph
@@ -87,12 +101,12 @@ def run_mode(w, mode: str, steps: int, warmup: int, torch, nb):
     }
 
 
-def roofline(mode, pairs, force_ms):
+def roofline(mode, pairs, force_ms, workload="c3"):
     flops = FLOPS_PER_PAIR * pairs
     achieved = flops / (force_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[mode]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(mode),
+            "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(mode, workload),
             "kernel": f"k_force{'32c' if mode == 'fp32c' else '64'}",
             "kernel_ms": round(force_ms, 4), "flops_per_launch": flops,
             "flop_convention": f"{FLOPS_PER_PAIR} flops per ordered pair"}
@@ -158,15 +172,17 @@ def cpu_baseline(w, max_pairs=4e8):
         return cpu_baseline_sampled(w, max_pairs / 8)
     sizes = np.diff(w.off)
     keep, tot = [], 0
+    nbig = sizes if w.nbig is None else np.asarray(w.nbig)
     for s in range(w.nsys):
-        p = int(sizes[s]) * (int(sizes[s]) - 1)
+        p = int(nbig[s]) * (int(sizes[s]) - 1)
         if keep and tot + p > max_pairs:
             break
         keep.append(s)
         tot += p
     lo, hi = int(w.off[keep[0]]), int(w.off[keep[-1] + 1])
     sub = W.Workload(w.name, (w.off[keep[0]:keep[-1] + 2] - lo).astype(np.int32), w.m0[keep],
-                     w.m[lo:hi], w.x[lo:hi], w.v[lo:hi], w.dt, 1, G=w.G, drag=w.drag)
+                     w.m[lo:hi], w.x[lo:hi], w.v[lo:hi], w.dt, 1, G=w.G, drag=w.drag,
+                     nbig=None if w.nbig is None else np.asarray(w.nbig)[keep])
     st = oracle.State.from_workload(sub)      # includes the first force evaluation
     t0 = time.perf_counter()
     st.step(w.dt)
@@ -183,8 +199,10 @@ def main():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--modes", default="fp32c,fp64")
-    ap.add_argument("--workload", default="c3", help="c1..c5 (the headline is c3)")
+    ap.add_argument("--workload", default="c3", help="c1..c5 or bigsmall (the headline is c3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--resolve", action="store_true",
+                    help="full hybrid method: resolve close encounters on the host every step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -205,7 +223,7 @@ def main():
     for mode in modes:
         print(f"[bench] {w.name} mode {mode}: ntot={w.ntot}, warmup {args.warmup}, steps {args.steps}",
               file=sys.stderr, flush=True)
-        res[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb)
+        res[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb, resolve=args.resolve)
         print(f"[bench] mode {mode}: {res[mode]['ms_per_step']:.4f} ms/step, "
               f"force {res[mode]['force_ms']:.4f} ms, encounter {res[mode]['encounter_ms']:.4f} ms",
               file=sys.stderr, flush=True)
@@ -224,7 +242,12 @@ def main():
             "c3": f"c3: star + {n} equal-mass planetesimals (10 Earth masses), "
                   "a 0.5-5 AU, e,i Rayleigh 0.01/0.005, dt 0.0021875 yr (energy-bounded step)",
             "c4": f"c4: {w.nsys} independent systems, N_s uniform 200..4000 (sum {n}), c1 distributions, dt 0.05 yr",
-            "c5": f"c5: star + {n} planetesimals of 1e-11 in a 0.9-1.1 AU ring, dt 0.04 yr"}[args.workload]
+            "c5": f"c5: star + {n} planetesimals of 1e-11 in a 0.9-1.1 AU ring, dt 0.04 yr",
+            "bigsmall": f"bigsmall: star + {int(w.nbig[0]) if w.nbig is not None else n} Mars-mass embryos "
+                        f"(the only gravity sources) + {n - int(w.nbig[0]) if w.nbig is not None else 0} "
+                        "massless planetesimals, a 1-5 AU, dt 0.05 yr"}[args.workload]
+    if args.resolve:
+        desc += "; full hybrid method (close encounters resolved by Bulirsch-Stoer on the host)"
     out = {
         "metric": METRIC, "value": round(r["gpair_s"], 3), "unit": "Gpair/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -244,10 +267,11 @@ def main():
                      "force_gpair_s": round(pairs / (rr["force_ms"] * 1e-3) / 1e9, 2),
                      "tiles": rr["tiles"],
                      "nce_per_step": rr["stats"]["total_nce"] / args.steps,
+                     "resolved_groups_per_step": rr["stats"]["resolved_groups"] / args.steps,
                      "accel_err_vs_oracle": accel_error(w, rr["a"], rr["Q"])}
-    out["roofline"] = roofline(head, pairs, r["force_ms"])
+    out["roofline"] = roofline(head, pairs, r["force_ms"], args.workload)
     if "fp64" in res and head != "fp64":
-        out["roofline_fp64"] = roofline("fp64", pairs, res["fp64"]["force_ms"])
+        out["roofline_fp64"] = roofline("fp64", pairs, res["fp64"]["force_ms"], args.workload)
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w)
     out["kernel_source_sha256_16"] = kernel_hash()
     print(json.dumps(out), flush=True)

@@ -18,6 +18,12 @@
  *          w = K/r^3 - (dK/dr)/r^2, rc_ij = max(rc_i, rc_j), K the changeover function
  *   K(h)                                           h = dt/2
  *
+ * With nb_params.resolve = 1 (the full hybrid method), after C every group of
+ * bodies joined by flagged pairs restarts from (Q0,V0) and is advanced over dt
+ * on the host by Bulirsch-Stoer under the Kepler part plus the (1 - K)-weighted
+ * pair part (Sec. 2.1.1, critical-radius footnote; Sec. 3 and 3.2 keep this on
+ * the host), before the second S(h).
+ *
  * Conventions
  *  - Every call returns NB_OK (0) or a negative NB_E_* code; nothing throws or
  *    aborts across the ABI.  nb_strerror() names a code; nb_last_error() gives the
@@ -89,8 +95,20 @@ typedef struct nb_params {
     int32_t enc_jchunk;   /* sources per encounter work item (0: default) */
     int32_t enc_algo;     /* encounter check: 0 automatic, 1 every pair through a per-pair
                              reach filter, 2 spatially sorted tiles with tile-pair culling */
-    int32_t reserved[4];
+    int32_t step_algo;    /* nb_step: 0 automatic, 1 one launch per phase over all systems
+                             (HIP graph), 2 one persistent launch in which a workgroup owns a
+                             system for many steps (FP64 pair arithmetic; systems of at most
+                             NB_PERSISTENT_MAX_N bodies; not with resolve) */
+    int32_t resolve;      /* 0: flag close encounters only (hot-path mode); 1: the full
+                             hybrid method, every flagged group resolved on the host by
+                             Bulirsch-Stoer inside each nb_step (Sec. 2.1.1, Sec. 3.2) */
+    int32_t resolve_threads; /* host threads of the resolver (0: up to 16, by the host) */
+    int32_t reserved;     /* must be 0 */
+    double  bs_tol;       /* Bulirsch-Stoer relative tolerance (0: 1e-12) */
 } nb_params;
+
+/* largest system the persistent step launch accepts */
+#define NB_PERSISTENT_MAX_N 8192
 
 typedef struct nb_stats {
     int64_t total_nce;      /* flagged pairs summed over the steps */
@@ -98,6 +116,11 @@ typedef struct nb_stats {
     int32_t overflow_steps; /* steps whose count exceeded the list capacity */
     int64_t kepler_fail;    /* failed Kepler solves summed over the steps */
     int64_t near_pairs;     /* FP32C: pairs evaluated in FP64 near the changeover zone */
+    int64_t resolved_groups; /* resolve: groups integrated by Bulirsch-Stoer, summed */
+    int64_t resolved_bodies; /* resolve: their members, summed */
+    int32_t max_group;      /* resolve: largest group */
+    int32_t bs_fail;        /* resolve: groups whose integration failed (members keep the
+                               Kepler-drifted state) */
 } nb_stats;
 
 /* Library version. */
@@ -112,14 +135,24 @@ const char *nb_strerror(int code);
 void nb_default_params(nb_params *p);
 
 /* Bytes of device workspace a context needs for nsys systems with host offsets
- * off[0..nsys] (off[0] = 0, non-decreasing) and an encounter list of enc_cap pairs. */
-int nb_workspace_size(const nb_params *p, int nsys, const int32_t *off, int enc_cap, size_t *bytes);
+ * off[0..nsys] (off[0] = 0, non-decreasing) and an encounter list of enc_cap pairs.
+ * nbig (host, nsys entries, may be NULL = every body big): the first nbig[s]
+ * bodies of system s are big, the rest small (Sec. 2.1: only big bodies are
+ * gravity sources; small bodies are massless, feel the big ones, and two small
+ * bodies never interact, so the force costs (N_s) x nbig[s] pairs and the
+ * encounter check tests only pairs with a big member).  0 <= nbig[s] <= N_s.
+ * Gas drag needs a mass for the body size, so drag with small bodies is
+ * NB_E_INVALID. */
+int nb_workspace_size(const nb_params *p, int nsys, const int32_t *off, const int32_t *nbig,
+                      int enc_cap, size_t *bytes);
 
-/* Create a context on the current device.  workspace: device memory of at least
- * nb_workspace_size() bytes, 256-byte aligned, owned by the caller.  stream: a
- * hipStream_t (NULL = the null stream; nb_step then runs without a HIP graph). */
-int nb_create(const nb_params *p, int nsys, const int32_t *off, int enc_cap, void *workspace,
-              size_t bytes, void *stream, nb_ctx **out);
+/* Create a context on the current device.  off and nbig as for nb_workspace_size.
+ * workspace: device memory of at least nb_workspace_size() bytes, 256-byte
+ * aligned, owned by the caller.  stream: a hipStream_t (NULL = the null stream;
+ * nb_step then runs without a HIP graph).  nb_upload rejects a small body with a
+ * nonzero mass (NB_E_INVALID). */
+int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *nbig, int enc_cap,
+              void *workspace, size_t bytes, void *stream, nb_ctx **out);
 
 /* Last error message of the context (empty if none). */
 const char *nb_last_error(const nb_ctx *ctx);
@@ -164,10 +197,40 @@ int nb_get_encounters(nb_ctx *ctx, int cap, int *nce, int32_t *ice, int32_t *jce
                       int where);
 
 /* nsteps hybrid steps K S D C S F K of every system (graph-captured when the
- * stream is not NULL).  st (may be NULL) receives the run's statistics.
- * Returns NB_E_KEPLER / NB_E_CAPACITY if any step had such an event; the state
- * is still advanced. */
+ * stream is not NULL and resolve is 0).  With resolve = 1 each step
+ * synchronizes the stream after C, copies the flagged groups' members to the
+ * host, integrates them there and writes them back (only members cross PCIe).
+ * st (may be NULL) receives the run's statistics.  Returns NB_E_KEPLER /
+ * NB_E_CAPACITY if any step had such an event (with resolve, an overflowing
+ * step resolves the pairs the list holds); the state is still advanced. */
 int nb_step(nb_ctx *ctx, double dt, int nsteps, nb_stats *st);
+
+typedef struct nb_resolve_info {
+    int32_t groups;     /* groups integrated */
+    int32_t bodies;     /* their members */
+    int32_t max_group;  /* largest group */
+    int32_t failed;     /* groups whose integration failed */
+    int32_t max_steps;  /* most Bulirsch-Stoer step attempts of one group */
+} nb_resolve_info;
+
+/* Host close-encounter resolver on host arrays of one system (no GPU work;
+ * the same code nb_step runs with resolve = 1).  Sec. 2.1.1 (critical-radius
+ * footnote) and Sec. 3.2: bodies joined by the nce flagged pairs (ice[k],
+ * jce[k]), 0-based local indices, are grouped (connected components); each group
+ * restarts from (Q0,V0) and is advanced by tau under
+ *   dQ/dt = V,  dV_i/dt = -G m0 Q_i/|Q_i|^3
+ *                         + sum_j G m_j [(1-K)/r^3 + (dK/dr)/r^2] (Q_j - Q_i)
+ * (j over the group, rc_ij = max(rc_i, rc_j), changeover inner edge chg_inner
+ * rc_ij) by Bulirsch-Stoer with relative tolerance tol (0: 1e-12); its result
+ * is written to Q, V.  Other bodies keep Q, V.  Arrays are row-major n x 3 (Q0,
+ * V0, Q, V) and n (m, rc).  group[n] (may be NULL) receives each body's group
+ * label (its smallest member) or -1.  nthreads: host threads (0: up to 16).
+ * A failed group keeps Q, V and is counted in info->failed (info may be NULL).
+ * Returns NB_E_INVALID for bad sizes or indices. */
+int nb_resolve_host(int n, double G, double m0, double chg_inner, double tol, double tau,
+                    const double *m, const double *rc, const double *Q0, const double *V0,
+                    int nce, const int32_t *ice, const int32_t *jce, double *Q, double *V,
+                    int32_t *group, int nthreads, nb_resolve_info *info);
 
 /* Per system s (host arrays): E[s] total energy, EK[s] the changeover-weighted
  * energy the hot path conserves, L[3s..3s+2] = sum m Q x V, P[3s..3s+2] = sum m V.
@@ -184,7 +247,9 @@ int nb_get_rcrit(nb_ctx *ctx, double *rc, int where);
 #define NB_K_FORCE      0   /* the pair force kernel (FP64 or FP32C per the mode) */
 #define NB_K_ENCOUNTER  1   /* the encounter check plus the list sort */
 #define NB_K_DRIFT      2   /* the Kepler drift */
-#define NB_K_STEP       3   /* one whole hybrid step (all kernels of nb_step) */
+#define NB_K_STEP       3   /* whole hybrid steps, enqueued the way nb_step runs them */
+#define NB_K_FORCE_EVAL 4   /* one whole force evaluation: critical radii and source
+                               records, the force kernel and the sum of its splits */
 
 /* Measurement helper: enqueue kernel `which` alone `reps` times on the context's
  * stream between two HIP events (after one untimed launch) and return the mean

@@ -359,7 +359,9 @@ class State:
             Q0 = np.empty_like(Q); V0 = np.empty_like(V)
             kf = np.zeros(n, np.int32); ce = np.zeros(max(n, 1), np.int32)
             scratch = np.empty_like(Q)
-            c = n * (n - 1) // 2 if cap is None else cap
+            nbs = int(self.nbig[s])
+            # pairs with a big member: at most nbig (n - 1) - nbig (nbig - 1) / 2
+            c = nbs * (n - 1) - nbs * (nbs - 1) // 2 if cap is None else cap
             ice = np.zeros(max(c, 1), np.int32); jce = np.zeros(max(c, 1), np.int32)
             nce = ctypes.c_int()
             if full:

@@ -1,8 +1,8 @@
 """Tile-size search for the pair kernels, cached per (GPU arch, mode, size class).
 
 For a given batch of systems it times, with HIP events on the context's stream
-(nb_time_kernel), the force kernel over targets-per-lane x sources-per-work-item
-candidates and the encounter kernel over sources-per-work-item candidates, and
+(nb_time_kernel), the whole force evaluation (force kernel plus the sum of its
+split partials) over targets-per-lane x sources-per-work-item candidates and the encounter kernel over sources-per-work-item candidates, and
 stores the fastest choice in ``tuning.json`` under
 ``<arch>/<mode>/n<max system size, next power of two>/s<systems, next power of two>``.
 ``Context`` applies a cached entry whenever the caller leaves the tile fields at 0.
@@ -40,9 +40,14 @@ def arch() -> str:
     return name.split(":")[0]
 
 
-def key(mode: str, off, arch_name: str | None = None) -> str:
+def key(mode: str, off, arch_name: str | None = None, nbig=None) -> str:
+    """Size class: largest system and number of systems (next powers of two),
+    plus the largest big-body count when some bodies are small."""
     sizes = np.diff(np.asarray(off))
-    return f"{arch_name or arch()}/{mode}/n{_pow2(int(sizes.max()))}/s{_pow2(len(sizes))}"
+    k = f"{arch_name or arch()}/{mode}/n{_pow2(int(sizes.max()))}/s{_pow2(len(sizes))}"
+    if nbig is not None and np.any(np.asarray(nbig) < sizes):
+        k += f"/b{_pow2(int(np.max(nbig)))}"
+    return k
 
 
 def load_cache() -> dict:
@@ -52,8 +57,8 @@ def load_cache() -> dict:
     return {}
 
 
-def lookup(mode: str, off, arch_name: str | None = None):
-    return load_cache().get(key(mode, off, arch_name))
+def lookup(mode: str, off, arch_name: str | None = None, nbig=None):
+    return load_cache().get(key(mode, off, arch_name, nbig))
 
 
 def _mode_id(mode):
@@ -69,12 +74,15 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
             if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
                 continue
             p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j)
-            c = nb.Context(w.off, p, enc_cap=1 << 16, device="cuda:0", tuned=False)
+            c = nb.Context(w.off, p, enc_cap=1 << 16, device="cuda:0", tuned=False, nbig=w.nbig)
             c.upload(w.m0, w.m, w.x, w.v)
-            ms = c.time_kernel(nb.NB_K_FORCE, reps=reps)
+            # ranked by the whole force evaluation: more source chunks mean more
+            # split partials for the finalize pass to sum
+            ms = c.time_kernel(nb.NB_K_FORCE_EVAL, reps=reps)
             res_force[(r, j)] = ms
             if verbose:
-                print(f"[autotune] {mode} force r={r} j={j}: {ms:.4f} ms", file=sys.stderr, flush=True)
+                print(f"[autotune] {mode} force evaluation r={r} j={j}: {ms:.4f} ms", file=sys.stderr,
+                      flush=True)
             c.close()
     for j in ENC_J + (0,):
         if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
@@ -82,7 +90,7 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
         # j = 0 stands for the sorted-tile algorithm (no chunk parameter)
         p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), enc_jchunk=j,
                               enc_algo=2 if j == 0 else 1)
-        c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False)
+        c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False, nbig=w.nbig)
         c.upload(w.m0, w.m, w.x, w.v)
         c.drift(w.dt, allow_fail=True)
         ms = c.time_kernel(nb.NB_K_ENCOUNTER, reps=reps)
@@ -93,7 +101,21 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
         c.close()
     (r, j), fms = min(res_force.items(), key=lambda kv: kv[1])
     ej, ems = min(res_enc.items(), key=lambda kv: kv[1])
+    # whole-step launch: per-phase launches (tuned tiles) vs the persistent launch
+    res_step = {}
+    for sa in ((1, 2) if mode == "fp64" and int(np.diff(w.off).max()) <= 8192 else (1,)):
+        p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j,
+                              enc_jchunk=ej if ej else 1024, enc_algo=2 if ej == 0 else 1, step_algo=sa)
+        c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False, nbig=w.nbig)
+        c.upload(w.m0, w.m, w.x, w.v)
+        c.step(w.dt, 3, allow=(nb.NB_E_CAPACITY, nb.NB_E_KEPLER))
+        res_step[sa] = c.time_kernel(nb.NB_K_STEP, reps=max(2, reps // 2), dt=w.dt)
+        if verbose:
+            print(f"[autotune] {mode} step launch {sa}: {res_step[sa]:.4f} ms", file=sys.stderr, flush=True)
+        c.close()
+    sa, sms = min(res_step.items(), key=lambda kv: kv[1])
     return {"force_r": r, "force_jchunk": j, "enc_jchunk": ej if ej else 1024, "enc_algo": 2 if ej == 0 else 1,
+            "step_algo": sa, "step_ms": round(sms, 5), "step_candidates": {str(k): round(v, 5) for k, v in res_step.items()},
             "force_ms": round(fms, 5),
             "encounter_ms": round(ems, 5), "workload": w.name, "tuned_at": time.strftime("%Y-%m-%d"),
             "force_candidates": {f"r{a}_j{b}": round(v, 5) for (a, b), v in res_force.items()},
@@ -102,7 +124,7 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workloads", default="c1,c2,c3,c4,c5")
+    ap.add_argument("--workloads", default="c1,c2,c3,c4,c5,bigsmall")
     ap.add_argument("--modes", default="fp64,fp32c")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--out", default=CACHE)
@@ -115,9 +137,10 @@ def main():
         w = workloads.by_name(name)
         for mode in args.modes.split(","):
             best = tune(w, mode, reps=args.reps)
-            cache[key(mode, w.off, a)] = best
-            print(f"[autotune] {key(mode, w.off, a)} -> r={best['force_r']} j={best['force_jchunk']} "
-                  f"enc_algo={best['enc_algo']} enc_j={best['enc_jchunk']} "
+            k = key(mode, w.off, a, w.nbig)
+            cache[k] = best
+            print(f"[autotune] {k} -> r={best['force_r']} j={best['force_jchunk']} "
+                  f"enc_algo={best['enc_algo']} enc_j={best['enc_jchunk']} step_algo={best['step_algo']} "
                   f"({best['force_ms']:.4f} / {best['encounter_ms']:.4f} ms)",
                   file=sys.stderr, flush=True)
             with open(args.out, "w") as f:

@@ -32,7 +32,9 @@ struct PWork {
 struct SRec {
     double q0[3], v0[3], q1[3], v1[3];
     double rc;
-    int body, pad;
+    int body, big;        // global index; 1 for a big body (a gravity source)
+    double M[3], c[3];    // chord midpoint and chord Q1 - Q0
+    double e34, pad;      // 3/4 of the largest endpoint deviation (widened for rounding)
 };
 
 // A tile of up to 64 consecutive sorted bodies of one system; `last` is the
@@ -48,7 +50,14 @@ struct TileB {
     double cm[3], sm;
     double cc[3], sc;
     double ce[3], se;
-    double rc, pad[3];
+    double rc;
+    int big, pad;         // big: the tile holds at least one big body
+    double pad2[2];
+};
+
+// A system run by the persistent step launch (one workgroup each).
+struct PSys {
+    int sys, start, n, nbig;
 };
 
 // Device statistics block (one per context).
@@ -74,6 +83,7 @@ struct Dev {
     double *q0x, *q0y, *q0z, *v0x, *v0y, *v0z;
     float4 *pk;           // FP32C source records: 2 per body {xhi,yhi,zhi,m},{xlo,ylo,zlo,rc2}
     double4 *mr;          // per body after a drift: chord midpoint (x,y,z) and encounter reach R
+    double4 *cr;          // per body after a drift: chord Q1 - Q0 and 3/4 eps (widened)
     int *kflag, *ce, *sys_of;
     double *m0;           // nsys
     int *off;             // nsys+1
@@ -102,11 +112,20 @@ struct Dev {
     int *sys_cell_base, *sys_cell_cnt;   // nsys
     int *ord;             // ntot: sorted position -> body
     SRec *srec;           // ntot
+    int *scan_part;       // per chunk of 4096 cells: count sums (large grids)
     Tile *tiles; int ntile;
     TileB *tileb;         // ntile
     int2 *tpairs; int tp_cap;
+    // persistent step launch
+    PSys *psys; int npsys; int pmax_n;
+    int *step_nce; int step_chunk;   // flagged pairs per step of one launch
     int *flag;            // validation flags (4 ints)
     double *stage;        // 6 x ntot staging for host transfers / transforms
+    // close-encounter resolver (resolve = 1): member indices and their records
+    int *res_idx; double *res_buf; int res_cap;   // res_buf: 10 doubles per member
+    int *nbig;            // per system: bodies [off[s], off[s] + nbig[s]) are big
+    int force_few;        // every system has at most 256 big bodies and the targets are many:
+                          // the few-source force kernels
 };
 
 struct Params {
@@ -115,6 +134,10 @@ struct Params {
     double sigma0, h, cd, rho_p;
     int force_r, force_j, enc_j;
     int enc_algo;         // 1: all pairs with the reach prefilter, 2: sorted tiles
+    int step_algo;        // 1: per-phase launches, 2: persistent per-system launch
+    int resolve;          // 1: resolve flagged groups on the host every step
+    int resolve_threads;
+    double bs_tol;
 };
 
 // ---- launchers (nb_kernels.hip) --------------------------------------------
@@ -131,5 +154,15 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s);
 hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, hipStream_t s);
 hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s);
 hipError_t launch_diagnostics(const Dev &d, const Params &p, hipStream_t s);
+hipError_t launch_persistent_steps(const Dev &d, const Params &p, double dt, int nsteps,
+                                   hipStream_t s);
+hipError_t launch_step_stats(const Dev &d, int nsteps, hipStream_t s);
+hipError_t launch_enc_sort(const Dev &d, int accumulate, hipStream_t s);
+hipError_t launch_enc_gather(const Dev &d, hipStream_t s);
+hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s);
+// resolver transfers: members res_idx[0..k) -> res_buf (m0, m, rc, Q0, V0, pad)
+// and back from res_buf rows of 6 (Q, V; rows that are not finite are skipped)
+hipError_t launch_gather_members(const Dev &d, int k, hipStream_t s);
+hipError_t launch_scatter_members(const Dev &d, int k, hipStream_t s);
 
 }  // namespace nb

@@ -138,22 +138,28 @@ __global__ void k_fill_i32(int *p, int n, int value)
         p[i] = value;
 }
 
+// flag bit 1: a non-finite value, a negative mass or m0 <= 0; bit 2: a small
+// body (index >= off[s] + nbig[s]) with a nonzero mass.
 __global__ void k_validate(int ntot, int nsys, const double *__restrict__ m0,
                            const double *__restrict__ m, const double *__restrict__ x,
-                           const double *__restrict__ v, int *flag)
+                           const double *__restrict__ v, const int *__restrict__ sys_of,
+                           const int *__restrict__ off, const int *__restrict__ nbig, int *flag)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false;
+    int bad = 0;
     if (i < ntot) {
         double mi = m[i];
-        bad = !isfinite(mi) || mi < 0.0;
+        bad = (!isfinite(mi) || mi < 0.0) ? 1 : 0;
         for (int c = 0; c < 3; ++c)
-            bad |= !isfinite(x[(size_t)c * ntot + i]) || !isfinite(v[(size_t)c * ntot + i]);
+            bad |= (!isfinite(x[(size_t)c * ntot + i]) || !isfinite(v[(size_t)c * ntot + i])) ? 1 : 0;
+        const int s = sys_of[i];
+        if (i - off[s] >= nbig[s] && mi != 0.0)
+            bad |= 2;
     }
     if (i < nsys)
-        bad |= !(m0[i] > 0.0) || !isfinite(m0[i]);
+        bad |= (!(m0[i] > 0.0) || !isfinite(m0[i])) ? 1 : 0;
     if (bad)
-        atomicOr(flag, 1);
+        atomicOr(flag, bad);
 }
 
 // Per-block partial of sum m v (columns 0-2) and sum m (column 3).
@@ -521,7 +527,7 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
                         double *__restrict__ v0z, int *__restrict__ kflag, int *__restrict__ ce,
                         DevStats *stats, double *__restrict__ part_out,
                         const double *__restrict__ rc, double4 *__restrict__ mr,
-                        double *__restrict__ lnr_part)
+                        double4 *__restrict__ cr, double *__restrict__ lnr_part)
 {
     __shared__ double sh[3 * kBlock];
     double lnr_lo = INFINITY, lnr_hi = -INFINITY;
@@ -551,8 +557,14 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
             double ax1 = dt * u - cx, ay1 = dt * v - cy, az1 = dt * w - cz;
             double eps = sqrt(fmax(ax0 * ax0 + ay0 * ay0 + az0 * az0, ax1 * ax1 + ay1 * ay1 + az1 * az1));
             double R = (2.0 * rho + 0.75 * eps + rc[i]) * (1.0 + 0x1p-20);
-            double mx = q0x[i] + 0.5 * cx, my = q0y[i] + 0.5 * cy;
-            mr[i] = make_double4(mx, my, q0z[i] + 0.5 * cz, R);
+            double mx = q0x[i] + 0.5 * cx, my = q0y[i] + 0.5 * cy, mz = q0z[i] + 0.5 * cz;
+            mr[i] = make_double4(mx, my, mz, R);
+            // relative pair filter data: the chord and 3/4 eps, widened by 2^-20
+            // and by 2^-45 (|M| + |c|) to cover the rounding of midpoint and chord
+            // differences (see k_encounter)
+            double e34 = 0.75 * eps * (1.0 + 0x1p-20) +
+                         0x1p-45 * (sqrt(mx * mx + my * my + mz * mz) + 2.0 * rho);
+            cr[i] = make_double4(cx, cy, cz, e34);
             double lnr = log(fmax(sqrt(mx * mx + my * my), 1e-300));
             lnr_lo = lnr;
             lnr_hi = lnr;
@@ -680,9 +692,10 @@ __global__ __launch_bounds__(kBlock) void k_force64(const FWork *__restrict__ wo
         for (int k = 0; k < R; ++k)
             thr[k] = fmax(r2i[k], tmax);
         __syncthreads();
-        const int je = min(cnt, 64 * wv + 64);
+        // the waves take the tile's sources in turn (wave w: w, w + 4, ...), so a
+        // short or ragged source range still splits evenly over the 4 waves
 #pragma unroll 2
-        for (int jj = 64 * wv; jj < je; ++jj) {
+        for (int jj = wv; jj < cnt; jj += kWaves) {
             const double4 J = sj[jj];
             const double m15 = sx[jj].x;
 #pragma unroll
@@ -802,11 +815,12 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
         for (int k = 0; k < R; ++k)
             thr[k] = fmaxf(r2i[k], tmax);
         __syncthreads();
-        const int jw = 64 * wv, je = min(cnt, jw + 64);
-        for (int jb = jw; jb < je; jb += kMerge) {
-            const int jm = min(je, jb + kMerge);
+        // the waves take the tile's sources in turn (wave w: w, w + 4, ...); each
+        // run of kMerge of a wave's sources is summed in FP32, then merged
+        for (int jb = wv; jb < cnt; jb += kWaves * kMerge) {
+            const int jm = min(cnt, jb + kWaves * kMerge);
 #pragma unroll 2
-            for (int jj = jb; jj < jm; ++jj) {
+            for (int jj = jb; jj < jm; jj += kWaves) {
                 const float4 A = sa[jj];
                 const float4 B = sb[jj];
 #pragma unroll
@@ -886,6 +900,200 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
 
 // a = G * sum over the system's splits (fixed order); optionally the kick
 // V += h a and the partial sums of m V after it.
+// Few sources (every system has at most kFewMax big bodies, one split): each
+// wave owns the 64 R targets of a work item and sums over all of the system's
+// sources, held in the wave's own LDS slice; waves stride over the items and
+// restage the sources only when the system changes.  Same pair arithmetic and
+// per-target source order as the kernels above, no cross-wave reduction.
+constexpr int kFewMax = 256;
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_force64_few(const FWork *__restrict__ work, int nfw,
+                                                        const double *__restrict__ qx,
+                                                        const double *__restrict__ qy,
+                                                        const double *__restrict__ qz,
+                                                        const double *__restrict__ m,
+                                                        const double *__restrict__ rc,
+                                                        const double *__restrict__ tile_rc2,
+                                                        double *__restrict__ fpart, int ntot, int maxs,
+                                                        double inner, DevStats *stats)
+{
+    __shared__ double4 sj[kWaves][kFewMax];
+    __shared__ double2 sx[kWaves][kFewMax];     // {1.5 m, rc}
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int cached = -1, near = 0;
+    for (int it = blockIdx.x * kWaves + wv; it < nfw; it += gridDim.x * kWaves) {
+        const FWork wk = work[it];
+        if (wk.j0 != cached) {
+            for (int k = lane; k < wk.nj; k += 64) {
+                const int j = wk.j0 + k;
+                const double mj = m[j];
+                sj[wv][k] = make_double4(qx[j], qy[j], qz[j], mj);
+                sx[wv][k] = make_double2(1.5 * mj, rc[j]);
+            }
+            cached = wk.j0;
+            wave_lds_sync();
+        }
+        double xi[R], yi[R], zi[R], rci[R], r2i[R], thr[R], ax[R], ay[R], az[R];
+        const double tmax = tile_rc2[wk.rb0];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int li = lane + 64 * k;
+            const int i = wk.i0 + (li < wk.ni ? li : 0);
+            xi[k] = qx[i];
+            yi[k] = qy[i];
+            zi[k] = qz[i];
+            rci[k] = rc[i];
+            r2i[k] = fmax(rci[k] * rci[k], DBL_MIN);
+            thr[k] = fmax(r2i[k], tmax);
+            ax[k] = ay[k] = az[k] = 0.0;
+        }
+#pragma unroll 2
+        for (int jj = 0; jj < wk.nj; ++jj) {
+            const double4 J = sj[wv][jj];
+            const double m15 = sx[wv][jj].x;
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                double dx = J.x - xi[k], dy = J.y - yi[k], dz = J.z - zi[k];
+                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                double s = m_rinv3(J.w, m15, r2);
+                if (r2 < thr[k]) {
+                    double rcj = sx[wv][jj].y;
+                    if (r2 < fmax(r2i[k], fmax(rcj * rcj, DBL_MIN))) {
+                        s = J.w * changeover_w(r2, fmax(rci[k], rcj), inner);
+                        ++near;
+                    }
+                }
+                ax[k] = fma(s, dx, ax[k]);
+                ay[k] = fma(s, dy, ay[k]);
+                az[k] = fma(s, dz, az[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int li = lane + 64 * k;
+            if (li < wk.ni) {
+                const int i = wk.i0 + li;
+                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = ax[k];
+                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = ay[k];
+                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = az[k];
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        near += __shfl_xor(near, o);
+    if (lane == 0 && near)
+        atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_force32c_few(const FWork *__restrict__ work, int nfw,
+                                                         const float4 *__restrict__ pk,
+                                                         const double *__restrict__ qx,
+                                                         const double *__restrict__ qy,
+                                                         const double *__restrict__ qz,
+                                                         const double *__restrict__ m,
+                                                         const double *__restrict__ rc,
+                                                         const double *__restrict__ tile_rc2,
+                                                         double *__restrict__ fpart, int ntot,
+                                                         int maxs, double inner, DevStats *stats)
+{
+    __shared__ float4 sa[kWaves][kFewMax];
+    __shared__ float4 sb[kWaves][kFewMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int cached = -1, near = 0;
+    for (int it = blockIdx.x * kWaves + wv; it < nfw; it += gridDim.x * kWaves) {
+        const FWork wk = work[it];
+        if (wk.j0 != cached) {
+            for (int k = lane; k < wk.nj; k += 64) {
+                sa[wv][k] = pk[2 * (size_t)(wk.j0 + k)];
+                sb[wv][k] = pk[2 * (size_t)(wk.j0 + k) + 1];
+            }
+            cached = wk.j0;
+            wave_lds_sync();
+        }
+        float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], r2i[R], thr[R];
+        float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R], tx[R], ty[R], tz[R];
+        double nx[R], ny[R], nz[R];
+        int ii[R];
+        const float tmax = (float)(tile_rc2[wk.rb0] * (1.0 + 0x1p-9));
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int li = lane + 64 * k;
+            const int i = wk.i0 + (li < wk.ni ? li : 0);
+            ii[k] = i;
+            const float4 A = pk[2 * (size_t)i], B = pk[2 * (size_t)i + 1];
+            xh[k] = A.x; yh[k] = A.y; zh[k] = A.z;
+            xl[k] = B.x; yl[k] = B.y; zl[k] = B.z;
+            r2i[k] = B.w;
+            thr[k] = fmaxf(r2i[k], tmax);
+            hx[k] = hy[k] = hz[k] = lx[k] = ly[k] = lz[k] = tx[k] = ty[k] = tz[k] = 0.0f;
+            nx[k] = ny[k] = nz[k] = 0.0;
+        }
+        for (int jb = 0; jb < wk.nj; jb += kMerge) {
+            const int jm = min(wk.nj, jb + kMerge);
+#pragma unroll 2
+            for (int jj = jb; jj < jm; ++jj) {
+                const float4 A = sa[wv][jj];
+                const float4 B = sb[wv][jj];
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    float dx = (A.x - xh[k]) + (B.x - xl[k]);
+                    float dy = (A.y - yh[k]) + (B.y - yl[k]);
+                    float dz = (A.z - zh[k]) + (B.z - zl[k]);
+                    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    float y = __builtin_amdgcn_rsqf(r2);
+                    float s = (A.w * y) * (y * y);
+                    if (r2 < thr[k]) {
+                        if (r2 < fmaxf(r2i[k], B.w)) {
+                            int i = ii[k], j = wk.j0 + jj;
+                            double ex = qx[j] - qx[i], ey = qy[j] - qy[i], ez = qz[j] - qz[i];
+                            double d2 = fma(ez, ez, fma(ey, ey, ex * ex));
+                            double wgt = m[j] * changeover_w(d2, fmax(rc[i], rc[j]), inner);
+                            nx[k] = fma(wgt, ex, nx[k]);
+                            ny[k] = fma(wgt, ey, ny[k]);
+                            nz[k] = fma(wgt, ez, nz[k]);
+                            s = 0.0f;
+                            ++near;
+                        }
+                    }
+                    tx[k] = fmaf(s, dx, tx[k]);
+                    ty[k] = fmaf(s, dy, ty[k]);
+                    tz[k] = fmaf(s, dz, tz[k]);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) {
+                two_sum_f(hx[k], lx[k], tx[k]);
+                two_sum_f(hy[k], ly[k], ty[k]);
+                two_sum_f(hz[k], lz[k], tz[k]);
+                tx[k] = ty[k] = tz[k] = 0.0f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int li = lane + 64 * k;
+            if (li < wk.ni) {
+                const int i = wk.i0 + li;
+                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = ((double)hx[k] + (double)lx[k]) + nx[k];
+                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = ((double)hy[k] + (double)ly[k]) + ny[k];
+                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = ((double)hz[k] + (double)lz[k]) + nz[k];
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        near += __shfl_xor(near, o);
+    if (lane == 0 && near)
+        atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
+}
+
 __global__ void k_force_finalize(const RBlk *__restrict__ rblk, const int *__restrict__ nsplit,
                                  const double *__restrict__ fpart, int ntot, int maxs, double G,
                                  double *__restrict__ ax, double *__restrict__ ay,
@@ -981,10 +1189,19 @@ struct EncRec {
 // f(s) >= (D-P)^2 - (1/2)(D+P)E with P = rho_i + rho_j, E = eps_i + eps_j,
 // which exceeds (rc_i + rc_j)^2 >= rc_ij^2 whenever D > R_i + R_j with
 // R = 2 rho + 3 eps/4 + rc.  So only pairs with |dM|^2 <= (R_i + R_j)^2 go on.
+// Stage 1b (relative chords): the same split around the relative chord dc =
+// c_j - c_i gives f(s) >= (D - a)^2 - (1/2)(D + a)E with a = |dc|/2, which
+// exceeds rc_ij^2 whenever D > |dc| + 3E/4 + rc_ij; as (x + y)^2 <= 2x^2 + 2y^2,
+// pairs with D^2 > 2|dc|^2 + 2(3E/4 + rc_ij)^2 are dropped.  Bodies moving
+// together (neighbours on similar orbits) have short relative chords, so this
+// keeps far fewer pairs than stage 1 when steps are long.  The 3/4 eps term
+// stored per body is widened by 2^-20 and by 2^-45 (|M| + |c|) for the rounding
+// of the differences.
 // Stage 2 (candidates): the 4/27 lower bound on the full Hermite data, then
 // the exact minimum.
 __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ work, double dt,
                                                       const double4 *__restrict__ mr,
+                                                      const double4 *__restrict__ cr,
                                                       const double *__restrict__ q0x,
                                                       const double *__restrict__ q0y,
                                                       const double *__restrict__ q0z,
@@ -1003,6 +1220,7 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
                                                       DevStats *stats)
 {
     __shared__ double4 smr[kBlock];
+    __shared__ double4 scr[kBlock];
     __shared__ EncRec sj[kBlock];
     const PWork wk = work[blockIdx.x];
     const int t = threadIdx.x;
@@ -1012,6 +1230,7 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
     const bool has_i = t < wk.ni;
     const int i = wk.i0 + (has_i ? t : 0);
     const double4 Mi = mr[i];
+    const double4 Ci = cr[i];
     const double a0[3] = {q0x[i], q0y[i], q0z[i]}, b0[3] = {v0x[i], v0y[i], v0z[i]};
     const double a1[3] = {qx[i], qy[i], qz[i]}, b1[3] = {vx[i], vy[i], vz[i]};
     const double rci = rc[i];
@@ -1022,6 +1241,7 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
         if (t < cnt) {
             int j = jt + t;
             smr[t] = mr[j];
+            scr[t] = cr[j];
             EncRec r;
             r.q0[0] = q0x[j]; r.q0[1] = q0y[j]; r.q0[2] = q0z[j];
             r.v0[0] = v0x[j]; r.v0[1] = v0y[j]; r.v0[2] = v0z[j];
@@ -1041,6 +1261,16 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
             double D2 = fma(dz, dz, fma(dy, dy, dx * dx));
             double S = Mi.w + Mj.w;
             bool cand = has_i && D2 <= S * S && (!diag || j > i);
+            if (!__any(cand))
+                continue;
+            {
+                // relative chord filter
+                const double4 Cj = scr[jj];
+                double cx = Cj.x - Ci.x, cy = Cj.y - Ci.y, cz = Cj.z - Ci.z;
+                double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
+                double bb = Ci.w + Cj.w + fmax(rci, sj[jj].rc);
+                cand = cand && D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20);
+            }
             if (!__any(cand))
                 continue;
             bool hit = false;
@@ -1164,34 +1394,112 @@ __global__ void k_cells(const RBlk *__restrict__ rblk, const int *__restrict__ r
 // Exclusive scan of the cell counts (one workgroup), zeroing them for the next
 // step, and reset of the surviving-tile-pair counter.
 constexpr int kScanThreads = 1024;
+constexpr int kScanChunk = 4 * kScanThreads;   // cells per block pass, 4 per thread
+
+// Exclusive scan over the kScanThreads threads of a block; *total gets the sum.
+__device__ __forceinline__ int block_exscan(int v, int *sh, int &total)
+{
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    int x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int y = __shfl_up(x, o);
+        if (lane >= o)
+            x += y;
+    }
+    if (lane == 63)
+        sh[wv] = x;
+    __syncthreads();
+    if (t < 64) {
+        int w = t < kScanThreads / 64 ? sh[t] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            int y = __shfl_up(w, o);
+            if (lane >= o)
+                w += y;
+        }
+        if (t < kScanThreads / 64)
+            sh[32 + t] = w;               // inclusive wave totals
+    }
+    __syncthreads();
+    total = sh[32 + kScanThreads / 64 - 1];
+    const int before = wv > 0 ? sh[32 + wv - 1] : 0;
+    __syncthreads();                      // sh is reused by the next call
+    return before + x - v;
+}
+
+// Four consecutive cells of chunk `base` per thread, guarded at ncell.
+__device__ __forceinline__ void load4(const int *__restrict__ cnt, int base, int ncell, int (&c)[4])
+{
+    const int k0 = base + 4 * (int)threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        c[q] = k0 + q < ncell ? cnt[k0 + q] : 0;
+}
+
+// Exclusive scan of one chunk with a carried offset: cell_off, counts cleared.
+__device__ __forceinline__ int scan_chunk(int *__restrict__ cell_cnt, int *__restrict__ cell_off,
+                                          int base, int ncell, int carry, int *sh)
+{
+    int c[4];
+    load4(cell_cnt, base, ncell, c);
+    int tot;
+    int run = carry + block_exscan(c[0] + c[1] + c[2] + c[3], sh, tot);
+    const int k0 = base + 4 * (int)threadIdx.x;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (k0 + q < ncell) {
+            cell_off[k0 + q] = run;
+            cell_cnt[k0 + q] = 0;
+        }
+        run += c[q];
+    }
+    return tot;
+}
+
+// Counting-sort offsets: cell_off = exclusive scan of cell_cnt (all systems'
+// cells back to back), counts cleared for the next step.  One block walks
+// the cells in chunks (up to kScanSerialChunks chunks); larger grids use
+// k_scan_sums + k_scan_apply.
+constexpr int kScanSerialChunks = 16;
 __global__ __launch_bounds__(kScanThreads) void k_cell_scan(int *__restrict__ cell_cnt,
                                                             int *__restrict__ cell_off, int ncell,
                                                             DevStats *stats)
 {
-    __shared__ int part[kScanThreads];
-    const int t = threadIdx.x;
-    const int per = (ncell + kScanThreads - 1) / kScanThreads;
-    const int a = min(ncell, t * per), e = min(ncell, a + per);
-    int sum = 0;
-    for (int k = a; k < e; ++k)
-        sum += cell_cnt[k];
-    part[t] = sum;
-    __syncthreads();
-    // Hillis-Steele inclusive scan of the per-thread sums
-    for (int o = 1; o < kScanThreads; o <<= 1) {
-        int v = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
-    }
-    int run = part[t] - sum;
-    for (int k = a; k < e; ++k) {
-        int c = cell_cnt[k];
-        cell_off[k] = run;
-        run += c;
-        cell_cnt[k] = 0;
-    }
-    if (t == 0)
+    __shared__ int sh[64];
+    int carry = 0;
+    for (int base = 0; base < ncell; base += kScanChunk)
+        carry += scan_chunk(cell_cnt, cell_off, base, ncell, carry, sh);
+    if (threadIdx.x == 0)
+        stats->cur_tp = 0;
+}
+
+// Block b: sum of the counts of chunk b.
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const int *__restrict__ cell_cnt,
+                                                            int ncell, int *__restrict__ part)
+{
+    __shared__ int sh[64];
+    int c[4];
+    load4(cell_cnt, blockIdx.x * kScanChunk, ncell, c);
+    int tot;
+    (void)block_exscan(c[0] + c[1] + c[2] + c[3], sh, tot);
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = tot;
+}
+
+// Block b: exclusive offset of chunk b from the chunk sums (in order), then the
+// chunk's own scan.  Block 0 also resets the tile-pair count.
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ cell_cnt,
+                                                             int *__restrict__ cell_off, int ncell,
+                                                             const int *__restrict__ part,
+                                                             DevStats *stats)
+{
+    __shared__ int sh[64];
+    int pre = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kScanThreads)
+        pre += part[k];
+    int tot;
+    (void)block_exscan(pre, sh, tot);
+    (void)scan_chunk(cell_cnt, cell_off, blockIdx.x * kScanChunk, ncell, tot, sh);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
         stats->cur_tp = 0;
 }
 
@@ -1203,7 +1511,9 @@ __global__ void k_scatter(const RBlk *__restrict__ rblk, const int *__restrict__
                           const double *__restrict__ qx, const double *__restrict__ qy,
                           const double *__restrict__ qz, const double *__restrict__ vx,
                           const double *__restrict__ vy, const double *__restrict__ vz,
-                          const double *__restrict__ rc, int *__restrict__ ord,
+                          const double *__restrict__ rc, const double4 *__restrict__ mr,
+                          const double4 *__restrict__ cr, const int *__restrict__ off,
+                          const int *__restrict__ nbig, int *__restrict__ ord,
                           SRec *__restrict__ srec)
 {
     const RBlk b = rblk[blockIdx.x];
@@ -1219,7 +1529,12 @@ __global__ void k_scatter(const RBlk *__restrict__ rblk, const int *__restrict__
     r.v1[0] = vx[i];  r.v1[1] = vy[i];  r.v1[2] = vz[i];
     r.rc = rc[i];
     r.body = i;
-    r.pad = 0;
+    r.big = (i - off[b.sys]) < nbig[b.sys] ? 1 : 0;
+    const double4 M = mr[i], C = cr[i];
+    r.M[0] = M.x; r.M[1] = M.y; r.M[2] = M.z;
+    r.c[0] = C.x; r.c[1] = C.y; r.c[2] = C.z;
+    r.e34 = C.w;
+    r.pad = 0.0;
     srec[pos] = r;
 }
 
@@ -1269,11 +1584,14 @@ __global__ __launch_bounds__(kBlock) void k_tile_bounds(const Tile *__restrict__
     const Tile T = tiles[tw];
     const bool on = lane < T.count;
     double M[3] = {0, 0, 0}, c[3] = {0, 0, 0}, eb[3] = {0, 0, 0}, se = 0.0, rc = 0.0;
+    bool big = false;
     if (on) {
         const SRec r = srec[T.start + lane];
         rec_geometry(r, dt, M, c, eb, se);
         rc = r.rc;
+        big = r.big != 0;
     }
+    const bool any_big = __any(big);
     const double inv = 1.0 / (double)T.count;
     double cm[3], cc[3], ce[3];
     for (int k = 0; k < 3; ++k) {
@@ -1302,7 +1620,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_bounds(const Tile *__restrict__
         B.sc = sc;
         B.se = sde;
         B.rc = rcm;
-        B.pad[0] = B.pad[1] = B.pad[2] = 0.0;
+        B.big = any_big ? 1 : 0;
+        B.pad = 0;
+        B.pad2[0] = B.pad2[1] = 0.0;
         tileb[tw] = B;
     }
 }
@@ -1338,7 +1658,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_pairs(const Tile *__restrict__ 
     const int lane = threadIdx.x & 63;
     for (int b0 = A; b0 <= TA.last; b0 += kBlock) {
         const int B = b0 + threadIdx.x;
-        const bool ok = B <= TA.last && may_meet(BA.cm, BA.sm, BA.cc, BA.sc, BA.ce, BA.se, BA.rc, tileb[B]);
+        // two small bodies never interact: a pair of tiles without a big body is skipped
+        const bool ok = B <= TA.last && (BA.big || tileb[B].big) &&
+                        may_meet(BA.cm, BA.sm, BA.cc, BA.sc, BA.ce, BA.se, BA.rc, tileb[B]);
         const unsigned long long mask = __ballot(ok);
         if (mask) {
             const int leader = __ffsll((long long)mask) - 1;
@@ -1390,7 +1712,17 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
         for (int jj = 16 * wv; jj < j1; ++jj) {
             const SRec &J = sb[jj];
             bool hit = false;
-            if (lane_ok && (!diag || jj > lane)) {
+            bool cand = lane_ok && (!diag || jj > lane) && (me.big | J.big);
+            if (cand) {
+                // relative chord filter (see k_encounter)
+                const double mx = J.M[0] - me.M[0], my = J.M[1] - me.M[1], mz = J.M[2] - me.M[2];
+                const double cx = J.c[0] - me.c[0], cy = J.c[1] - me.c[1], cz = J.c[2] - me.c[2];
+                const double D2 = fma(mz, mz, fma(my, my, mx * mx));
+                const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
+                const double bb = J.e34 + me.e34 + fmax(J.rc, me.rc);
+                cand = D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20);
+            }
+            if (__any(cand) && cand) {
                 double d0x = J.q0[0] - me.q0[0], d0y = J.q0[1] - me.q0[1], d0z = J.q0[2] - me.q0[2];
                 double d1x = J.q1[0] - me.q1[0], d1y = J.q1[1] - me.q1[1], d1z = J.q1[2] - me.q1[2];
                 double e0x = J.v0[0] - me.v0[0], e0y = J.v0[1] - me.v0[1], e0z = J.v0[2] - me.v0[2];
@@ -1426,20 +1758,339 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
     }
 }
 
+// ----------------------------------------------------------------------------
+// Persistent step launch: one workgroup owns one system and runs `nsteps`
+// whole hybrid steps K S D C S F K without leaving the kernel (all phases at
+// workgroup scope, separated by workgroup barriers).  Systems are handed out
+// largest first.  FP64 pair arithmetic; every sum has a fixed order, so runs
+// are bit-reproducible (the order differs from the per-phase launches, so the
+// two paths agree to rounding, not bit for bit).
+// ----------------------------------------------------------------------------
+constexpr int kPJ = 256;    // sources staged in LDS per tile
+
+template <int NT, int W>
+__device__ __forceinline__ void pblock_sum(double (&v)[W], double *sh)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        sh[w * NT + t] = v[w];
+    __syncthreads();
+    for (int st = NT / 2; st > 0; st >>= 1) {
+        if (t < st) {
+#pragma unroll
+            for (int w = 0; w < W; ++w)
+                sh[w * NT + t] += sh[w * NT + t + st];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w)
+        v[w] = sh[w * NT];
+    __syncthreads();
+}
+
+// Sum of m V over the workgroup's system (each thread walks its own bodies).
+template <int NT>
+__device__ __forceinline__ void psys_momentum(int a, int n, const double *__restrict__ m,
+                                              const double *vx, const double *vy,
+                                              const double *vz, double (&P)[3], double *sh)
+{
+    P[0] = P[1] = P[2] = 0.0;
+    for (int i = a + (int)threadIdx.x; i < a + n; i += NT) {
+        double mi = m[i];
+        P[0] += mi * vx[i];
+        P[1] += mi * vy[i];
+        P[2] += mi * vz[i];
+    }
+    pblock_sum<NT, 3>(P, sh);
+}
+
+template <int NT>
+__device__ __forceinline__ void pkick(int a, int n, double h, double mm, const double (&P)[3],
+                                      int drag, const DragP &dp, const double *__restrict__ m,
+                                      const double *qx, const double *qy, const double *qz,
+                                      const double *ax, const double *ay, const double *az,
+                                      double *vx, double *vy, double *vz)
+{
+    for (int i = a + (int)threadIdx.x; i < a + n; i += NT) {
+        double a0 = ax[i], a1 = ay[i], a2 = az[i];
+        double u0 = vx[i], u1 = vy[i], u2 = vz[i];
+        if (drag) {
+            double d0, d1, d2;
+            drag_accel(dp, mm, m[i], qx[i], qy[i], qz[i], u0 + P[0] / mm, u1 + P[1] / mm,
+                       u2 + P[2] / mm, d0, d1, d2);
+            a0 += d0;
+            a1 += d1;
+            a2 += d2;
+        }
+        vx[i] = u0 + h * a0;
+        vy[i] = u1 + h * a1;
+        vz[i] = u2 + h * a2;
+    }
+}
+
+// Encounter record staged in LDS by the persistent launch.
+struct PRec {
+    double4 M;              // chord midpoint and reach
+    double q0[3], v0[3], q1[3], v1[3];
+    double rc, pad;
+};
+static_assert(sizeof(PRec) % sizeof(double) == 0, "PRec must be a whole number of doubles");
+
+template <int NT>
+__global__ __launch_bounds__(NT) void k_steps_persistent(
+    const PSys *__restrict__ psys, int nsteps, double dt, double G, double n_hill, double inner,
+    int drag, DragP dp, const double *__restrict__ m0, const double *__restrict__ m, double *qx,
+    double *qy, double *qz, double *vx, double *vy, double *vz, double *ax, double *ay,
+    double *az, double *rc, double *q0x, double *q0y, double *q0z, double *v0x, double *v0y,
+    double *v0z, int *kflag, int *ce, double4 *mr, unsigned long long *keys, int cap,
+    DevStats *stats, int *step_nce)
+{
+    // one LDS buffer, viewed per phase: block sums, encounter tile, force tile
+    constexpr int kRecWords = (int)(sizeof(PRec) / sizeof(double));
+    constexpr int kWords = (3 * NT > kPJ * kRecWords ? 3 * NT : kPJ * kRecWords);
+    static_assert(kWords >= 2 * 4 * kPJ, "force tile must fit the buffer");
+    __shared__ double lds[kWords];
+    double *sh = lds;
+    PRec *se = reinterpret_cast<PRec *>(lds);
+    double4 *sj = reinterpret_cast<double4 *>(lds);
+    double4 *sx = reinterpret_cast<double4 *>(lds) + kPJ;
+    const PSys S = psys[blockIdx.x];
+    const int a = S.start, n = S.n, nb = S.nbig, t = threadIdx.x, lane = t & 63;
+    const int wave0 = t & ~63;             // first thread index of this wave
+    const double mm = m0[S.sys], mu = G * mm, h = 0.5 * dt;
+    const double t2 = 2.0 * dt, k427 = 4.0 / 27.0;
+    for (int step = 0; step < nsteps; ++step) {
+        const bool last = step == nsteps - 1;
+        double P[3] = {0.0, 0.0, 0.0};
+        // K(h); with drag the heliocentric velocity needs the current sum m V
+        if (drag)
+            psys_momentum<NT>(a, n, m, vx, vy, vz, P, sh);
+        pkick<NT>(a, n, h, mm, P, drag, dp, m, qx, qy, qz, ax, ay, az, vx, vy, vz);
+        // S(h)
+        psys_momentum<NT>(a, n, m, vx, vy, vz, P, sh);
+        for (int i = a + t; i < a + n; i += NT) {
+            qx[i] += h * P[0] / mm;
+            qy[i] += h * P[1] / mm;
+            qz[i] += h * P[2] / mm;
+        }
+        // D(dt): snapshot, drift, failure flags, encounter reach, cleared flags
+        int nf = 0;
+        for (int i = a + t; i < a + n; i += NT) {
+            double x = qx[i], y = qy[i], z = qz[i], u = vx[i], v = vy[i], w = vz[i];
+            q0x[i] = x; q0y[i] = y; q0z[i] = z;
+            v0x[i] = u; v0y[i] = v; v0z[i] = w;
+            const double x0 = x, y0 = y, z0 = z, u0 = u, v0 = v, w0 = w;
+            const bool fail = kepler_drift(mu, dt, x, y, z, u, v, w) != 0;
+            nf += fail;
+            qx[i] = x; qy[i] = y; qz[i] = z;
+            vx[i] = u; vy[i] = v; vz[i] = w;
+            kflag[i] = fail ? 1 : 0;
+            ce[i] = 0;
+            double cx = x - x0, cy = y - y0, cz = z - z0;
+            double rho = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
+            double ex0 = dt * u0 - cx, ey0 = dt * v0 - cy, ez0 = dt * w0 - cz;
+            double ex1 = dt * u - cx, ey1 = dt * v - cy, ez1 = dt * w - cz;
+            double eps = sqrt(fmax(ex0 * ex0 + ey0 * ey0 + ez0 * ez0, ex1 * ex1 + ey1 * ey1 + ez1 * ez1));
+            double R = (2.0 * rho + 0.75 * eps + rc[i]) * (1.0 + 0x1p-20);
+            mr[i] = make_double4(x0 + 0.5 * cx, y0 + 0.5 * cy, z0 + 0.5 * cz, R);
+        }
+        for (int o = 32; o > 0; o >>= 1)
+            nf += __shfl_xor(nf, o);
+        if (lane == 0 && nf)
+            atomicAdd((unsigned long long *)&stats->kepler_fail, (unsigned long long)nf);
+        double P2[3];
+        psys_momentum<NT>(a, n, m, vx, vy, vz, P2, sh);   // also orders the drift's writes
+        // C: ordered pairs (i, j) with i < j tested when i + j is even, i > j when
+        // odd, so each unordered pair is tested once and every thread sees all j.
+        for (int i0 = 0; i0 < n; i0 += NT) {
+            const bool vi = i0 + t < n;
+            const bool wave_on = i0 + wave0 < n;
+            const int i = a + (vi ? i0 + t : 0);
+            const double4 Mi = mr[i];
+            const double a0[3] = {q0x[i], q0y[i], q0z[i]}, b0[3] = {v0x[i], v0y[i], v0z[i]};
+            const double a1[3] = {qx[i], qy[i], qz[i]}, b1[3] = {vx[i], vy[i], vz[i]};
+            const double rci = rc[i];
+            for (int j0 = 0; j0 < n; j0 += kPJ) {
+                const int cnt = min(kPJ, n - j0);
+                __syncthreads();
+                for (int k = t; k < cnt; k += NT) {
+                    const int j = a + j0 + k;
+                    PRec r;
+                    r.M = mr[j];
+                    r.q0[0] = q0x[j]; r.q0[1] = q0y[j]; r.q0[2] = q0z[j];
+                    r.v0[0] = v0x[j]; r.v0[1] = v0y[j]; r.v0[2] = v0z[j];
+                    r.q1[0] = qx[j];  r.q1[1] = qy[j];  r.q1[2] = qz[j];
+                    r.v1[0] = vx[j];  r.v1[1] = vy[j];  r.v1[2] = vz[j];
+                    r.rc = rc[j];
+                    r.pad = 0.0;
+                    se[k] = r;
+                }
+                __syncthreads();
+                if (!wave_on)
+                    continue;
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const int j = a + j0 + jj;
+                    const PRec &J = se[jj];
+                    double dx = J.M.x - Mi.x, dy = J.M.y - Mi.y, dz = J.M.z - Mi.z;
+                    double D2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    double Sr = Mi.w + J.M.w;
+                    // two small bodies (both at or past a + nb) never interact
+                    bool mine = vi && j != i && ((i < j) == (((i + j) & 1) == 0)) &&
+                                min(i, j) < a + nb;
+                    bool cand = mine && D2 <= Sr * Sr;
+                    if (!__any(cand))
+                        continue;
+                    bool hit = false;
+                    if (cand) {
+                        double d0x = J.q0[0] - a0[0], d0y = J.q0[1] - a0[1], d0z = J.q0[2] - a0[2];
+                        double d1x = J.q1[0] - a1[0], d1y = J.q1[1] - a1[1], d1z = J.q1[2] - a1[2];
+                        double e0x = J.v0[0] - b0[0], e0y = J.v0[1] - b0[1], e0z = J.v0[2] - b0[2];
+                        double e1x = J.v1[0] - b1[0], e1y = J.v1[1] - b1[1], e1z = J.v1[2] - b1[2];
+                        double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
+                        double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
+                        double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
+                        double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
+                        double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
+                        double rcij = fmax(rci, J.rc);
+                        double thr = rcij * rcij;
+                        if (lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1)))
+                            hit = hermite_min(f0, f1, g0, g1) <= thr;
+                    }
+                    const unsigned long long mask = __ballot(hit);
+                    if (mask) {
+                        const int leader = __ffsll((long long)mask) - 1;
+                        if (lane == leader)
+                            atomicAdd(&step_nce[step], (int)__popcll(mask));
+                        if (last) {
+                            int base = 0;
+                            if (lane == leader)
+                                base = atomicAdd(&stats->cur_nce, (int)__popcll(mask));
+                            base = __shfl(base, leader);
+                            if (hit) {
+                                const int pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
+                                const unsigned lo = (unsigned)min(i, j), hi = (unsigned)max(i, j);
+                                if (pos < cap)
+                                    keys[pos] = ((unsigned long long)lo << 32) | hi;
+                            }
+                        }
+                        if (hit) {
+                            __hip_atomic_store(&ce[i], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            __hip_atomic_store(&ce[j], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // S(h) and the critical radii at the new positions
+        for (int i = a + t; i < a + n; i += NT) {
+            double x = qx[i] + h * P2[0] / mm, y = qy[i] + h * P2[1] / mm, z = qz[i] + h * P2[2] / mm;
+            qx[i] = x;
+            qy[i] = y;
+            qz[i] = z;
+            rc[i] = n_hill * sqrt(x * x + y * y + z * z) * cbrt(m[i] / (3.0 * mm));
+        }
+        __syncthreads();
+        // F: each thread sums its targets over every big source, tile by tile in order
+        for (int i0 = 0; i0 < n; i0 += NT) {
+            const bool vi = i0 + t < n;
+            const bool wave_on = i0 + wave0 < n;
+            const int i = a + (vi ? i0 + t : 0);
+            const double xi = qx[i], yi = qy[i], zi = qz[i], rci = rc[i];
+            const double r2i = fmax(rci * rci, DBL_MIN);
+            double sx0 = 0.0, sy0 = 0.0, sz0 = 0.0;
+            for (int j0 = 0; j0 < nb; j0 += kPJ) {
+                const int cnt = min(kPJ, nb - j0);
+                __syncthreads();
+                for (int k = t; k < cnt; k += NT) {
+                    const int j = a + j0 + k;
+                    const double mj = m[j], rj = rc[j];
+                    sj[k] = make_double4(qx[j], qy[j], qz[j], mj);
+                    sx[k] = make_double4(1.5 * mj, rj, fmax(rj * rj, DBL_MIN), 0.0);
+                }
+                __syncthreads();
+                if (!wave_on)
+                    continue;
+#pragma unroll 2
+                for (int jj = 0; jj < cnt; ++jj) {
+                    const double4 J = sj[jj];
+                    const double4 X = sx[jj];
+                    double dx = J.x - xi, dy = J.y - yi, dz = J.z - zi;
+                    double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                    double w = m_rinv3(J.w, X.x, r2);
+                    if (r2 < fmax(r2i, X.z))
+                        w = J.w * changeover_w(r2, fmax(rci, X.y), inner);
+                    sx0 = fma(w, dx, sx0);
+                    sy0 = fma(w, dy, sy0);
+                    sz0 = fma(w, dz, sz0);
+                }
+            }
+            if (vi) {
+                ax[i] = G * sx0;
+                ay[i] = G * sy0;
+                az[i] = G * sz0;
+            }
+        }
+        __syncthreads();
+        // K(h)
+        if (drag)
+            psys_momentum<NT>(a, n, m, vx, vy, vz, P, sh);
+        pkick<NT>(a, n, h, mm, P, drag, dp, m, qx, qy, qz, ax, ay, az, vx, vy, vz);
+        __syncthreads();
+    }
+}
+
+// Per-step counts of one persistent launch into the run statistics (one workgroup).
+__global__ __launch_bounds__(kBlock) void k_step_stats(int *__restrict__ step_nce, int nsteps,
+                                                       int cap, DevStats *stats)
+{
+    __shared__ long long st[kBlock];
+    __shared__ int mx[kBlock], ov[kBlock];
+    long long tot = 0;
+    int mxv = 0, ovc = 0;
+    for (int k = threadIdx.x; k < nsteps; k += kBlock) {
+        int c = step_nce[k];
+        tot += c;
+        mxv = max(mxv, c);
+        ovc += c > cap;
+        step_nce[k] = 0;
+    }
+    st[threadIdx.x] = tot;
+    mx[threadIdx.x] = mxv;
+    ov[threadIdx.x] = ovc;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            st[threadIdx.x] += st[threadIdx.x + o];
+            mx[threadIdx.x] = max(mx[threadIdx.x], mx[threadIdx.x + o]);
+            ov[threadIdx.x] += ov[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        stats->total_nce += st[0];
+        stats->max_nce = max(stats->max_nce, mx[0]);
+        stats->overflow_steps += ov[0];
+    }
+}
+
 // Sort the encounter keys (one workgroup, bitonic), split them into (ice, jce),
 // and fold the count into the run statistics.
 constexpr int kSortThreads = 1024;
-constexpr int kSortLds = 8192;
+constexpr int kSortLds = 16384;  // 128 KiB of keys in LDS
 
 __global__ __launch_bounds__(kSortThreads) void k_enc_sort(unsigned long long *keys, int keys_p2,
                                                            int cap, int *__restrict__ ice,
-                                                           int *__restrict__ jce, DevStats *stats)
+                                                           int *__restrict__ jce, DevStats *stats,
+                                                           int accumulate)
 {
     __shared__ unsigned long long sk[kSortLds];
     const int t = threadIdx.x;
     const int count = stats->cur_nce;
     const int n = min(count, cap);
-    if (t == 0) {
+    if (t == 0 && accumulate) {
         stats->total_nce += count;
         if (count > stats->max_nce)
             stats->max_nce = count;
@@ -1646,6 +2297,74 @@ __global__ void k_diag_final(int nsys, const int *__restrict__ rb_first,
 // ----------------------------------------------------------------------------
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
+// Resolver transfers: one thread per member.
+__global__ __launch_bounds__(kBlock) void k_gather_members(
+    const int *__restrict__ idx, int k, const int *__restrict__ sys_of,
+    const double *__restrict__ m0, const double *__restrict__ m, const double *__restrict__ rc,
+    const double *__restrict__ q0x, const double *__restrict__ q0y, const double *__restrict__ q0z,
+    const double *__restrict__ v0x, const double *__restrict__ v0y, const double *__restrict__ v0z,
+    double *__restrict__ out)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= k)
+        return;
+    const int i = idx[t];
+    double *o = out + 10 * (size_t)t;
+    o[0] = m0[sys_of[i]];
+    o[1] = m[i];
+    o[2] = rc[i];
+    o[3] = q0x[i];
+    o[4] = q0y[i];
+    o[5] = q0z[i];
+    o[6] = v0x[i];
+    o[7] = v0y[i];
+    o[8] = v0z[i];
+    o[9] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scatter_members(
+    const int *__restrict__ idx, int k, const double *__restrict__ in, double *qx, double *qy,
+    double *qz, double *vx, double *vy, double *vz)
+{
+    const int t = blockIdx.x * kBlock + threadIdx.x;
+    if (t >= k)
+        return;
+    const double *r = in + 6 * (size_t)t;
+    const double a = r[0], b = r[1], c = r[2], u = r[3], v = r[4], w = r[5];
+    if (!isfinite(a + b + c + u + v + w))
+        return;                       // a failed group keeps the drifted state
+    const int i = idx[t];
+    qx[i] = a;
+    qy[i] = b;
+    qz[i] = c;
+    vx[i] = u;
+    vy[i] = v;
+    vz[i] = w;
+}
+
+hipError_t launch_gather_members(const Dev &d, int k, hipStream_t s)
+{
+    if (k <= 0)
+        return hipSuccess;
+    if (k > d.res_cap)
+        return hipErrorInvalidValue;
+    k_gather_members<<<cdiv(k, kBlock), kBlock, 0, s>>>(d.res_idx, k, d.sys_of, d.m0, d.m, d.rc,
+                                                         d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z,
+                                                         d.res_buf);
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter_members(const Dev &d, int k, hipStream_t s)
+{
+    if (k <= 0)
+        return hipSuccess;
+    if (k > d.res_cap)
+        return hipErrorInvalidValue;
+    k_scatter_members<<<cdiv(k, kBlock), kBlock, 0, s>>>(d.res_idx, k, d.res_buf, d.qx, d.qy,
+                                                          d.qz, d.vx, d.vy, d.vz);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s)
 {
     if (n <= 0)
@@ -1658,7 +2377,8 @@ hipError_t launch_validate(const Dev &d, const double *m0, const double *m, cons
                            const double *v, hipStream_t s)
 {
     int n = d.ntot > d.nsys ? d.ntot : d.nsys;
-    k_validate<<<cdiv(n, kBlock), kBlock, 0, s>>>(d.ntot, d.nsys, m0, m, x, v, d.flag);
+    k_validate<<<cdiv(n, kBlock), kBlock, 0, s>>>(d.ntot, d.nsys, m0, m, x, v, d.sys_of, d.off,
+                                                   d.nbig, d.flag);
     return hipGetLastError();
 }
 
@@ -1741,7 +2461,7 @@ hipError_t launch_drift(const Dev &d, const Params &p, double dt, hipStream_t s)
         return hipSuccess;
     k_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, dt, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
                                       d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
-                                      d.stats, d.rpart, d.rc, d.mr,
+                                      d.stats, d.rpart, d.rc, d.mr, d.cr,
                                       d.enc_sorted ? d.lnr_part : nullptr);
     return hipGetLastError();
 }
@@ -1750,6 +2470,32 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
 {
     if (d.nfw == 0)
         return hipSuccess;
+    if (d.force_few) {
+        // waves stride over the items; about 8 workgroups per CU
+        const int grid = std::min(cdiv(d.nfw, kWaves), 2048);
+#define NB_FEW_ARGS d.fwork, d.nfw, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart, d.ntot, d.maxs, \
+                    p.inner, d.stats
+#define NB_FEW32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart, d.ntot, \
+                      d.maxs, p.inner, d.stats
+        if (p.mode == 1) {
+            if (p.force_r == 1)
+                k_force32c_few<1><<<grid, kBlock, 0, s>>>(NB_FEW32_ARGS);
+            else if (p.force_r == 4)
+                k_force32c_few<4><<<grid, kBlock, 0, s>>>(NB_FEW32_ARGS);
+            else
+                k_force32c_few<2><<<grid, kBlock, 0, s>>>(NB_FEW32_ARGS);
+        } else {
+            if (p.force_r == 1)
+                k_force64_few<1><<<grid, kBlock, 0, s>>>(NB_FEW_ARGS);
+            else if (p.force_r == 4)
+                k_force64_few<4><<<grid, kBlock, 0, s>>>(NB_FEW_ARGS);
+            else
+                k_force64_few<2><<<grid, kBlock, 0, s>>>(NB_FEW_ARGS);
+        }
+#undef NB_FEW_ARGS
+#undef NB_FEW32_ARGS
+        return hipGetLastError();
+    }
     if (p.mode == 1) {
         switch (p.force_r) {
         case 1:
@@ -1795,18 +2541,36 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, h
     return hipGetLastError();
 }
 
-hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s)
+// Encounter check in two parts.  The gather part bins the drift records and
+// copies them into the sorted record array (sorted algorithm only); the test
+// part reads nothing but those copies, the list buffers and the flags, so it
+// may run beside the next S(h) and force pass.  The direct algorithm reads the
+// state planes and has an empty gather part.
+hipError_t launch_enc_gather(const Dev &d, hipStream_t s)
+{
+    if (d.enc_sorted && d.nrb > 0) {
+        k_cells<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.lnr_part,
+                                          d.sys_cell_base, d.sys_cell_cnt, d.mr, d.cell_cnt,
+                                          d.cell_of, d.slot_of);
+        const int nchunk = cdiv(d.ncell, kScanChunk);
+        if (nchunk <= kScanSerialChunks) {
+            k_cell_scan<<<1, kScanThreads, 0, s>>>(d.cell_cnt, d.cell_off, d.ncell, d.stats);
+        } else {
+            k_scan_sums<<<nchunk, kScanThreads, 0, s>>>(d.cell_cnt, d.ncell, d.scan_part);
+            k_scan_apply<<<nchunk, kScanThreads, 0, s>>>(d.cell_cnt, d.cell_off, d.ncell,
+                                                         d.scan_part, d.stats);
+        }
+        k_scatter<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.cell_of, d.slot_of, d.cell_off, d.q0x,
+                                            d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.qx, d.qy, d.qz,
+                                            d.vx, d.vy, d.vz, d.rc, d.mr, d.cr, d.off, d.nbig, d.ord,
+                                            d.srec);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
 {
     if (d.enc_sorted) {
-        if (d.nrb > 0) {
-            k_cells<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.lnr_part,
-                                              d.sys_cell_base, d.sys_cell_cnt, d.mr, d.cell_cnt,
-                                              d.cell_of, d.slot_of);
-            k_cell_scan<<<1, kScanThreads, 0, s>>>(d.cell_cnt, d.cell_off, d.ncell, d.stats);
-            k_scatter<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.cell_of, d.slot_of, d.cell_off, d.q0x,
-                                                d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.qx, d.qy, d.qz,
-                                                d.vx, d.vy, d.vz, d.rc, d.ord, d.srec);
-        }
         if (d.ntile > 0) {
             k_tile_bounds<<<cdiv(d.ntile, kBlock / 64), kBlock, 0, s>>>(d.tiles, d.ntile, d.srec, dt,
                                                                          d.tileb);
@@ -1815,14 +2579,52 @@ hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s)
             k_enc_pairs<<<grid, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.srec, dt,
                                                  d.keys, d.enc_cap, d.ce, d.stats);
         }
-        k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats);
-        return hipGetLastError();
-    }
-    if (d.new_ > 0)
-        k_encounter<<<d.new_, kBlock, 0, s>>>(d.ework, dt, d.mr, d.q0x, d.q0y, d.q0z, d.v0x,
+    } else if (d.new_ > 0) {
+        k_encounter<<<d.new_, kBlock, 0, s>>>(d.ework, dt, d.mr, d.cr, d.q0x, d.q0y, d.q0z, d.v0x,
                                                d.v0y, d.v0z, d.qx, d.qy, d.qz, d.vx, d.vy, d.vz,
                                                d.rc, d.keys, d.enc_cap, d.ce, d.stats);
-    k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats);
+    }
+    k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s)
+{
+    hipError_t e = launch_enc_gather(d, s);
+    return e != hipSuccess ? e : launch_enc_test(d, dt, s);
+}
+
+hipError_t launch_enc_sort(const Dev &d, int accumulate, hipStream_t s)
+{
+    k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats,
+                                          accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_persistent_steps(const Dev &d, const Params &p, double dt, int nsteps,
+                                   hipStream_t s)
+{
+    if (d.npsys == 0 || nsteps <= 0)
+        return hipSuccess;
+    // workgroup size from the largest system (psys[0] after the largest-first order)
+#define NB_PERSIST_ARGS                                                                         \
+    d.psys, nsteps, dt, p.G, p.n_hill, p.inner, p.drag, drag_params(p), d.m0, d.m, d.qx, d.qy, \
+        d.qz, d.vx, d.vy, d.vz, d.ax, d.ay, d.az, d.rc, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y,     \
+        d.v0z, d.kflag, d.ce, d.mr, d.keys, d.enc_cap, d.stats, d.step_nce
+    // (512 threads at most: 8 waves keep the full register budget without spills)
+    if (d.pmax_n <= 128)
+        k_steps_persistent<128><<<d.npsys, 128, 0, s>>>(NB_PERSIST_ARGS);
+    else if (d.pmax_n <= 256)
+        k_steps_persistent<256><<<d.npsys, 256, 0, s>>>(NB_PERSIST_ARGS);
+    else
+        k_steps_persistent<512><<<d.npsys, 512, 0, s>>>(NB_PERSIST_ARGS);
+#undef NB_PERSIST_ARGS
+    return hipGetLastError();
+}
+
+hipError_t launch_step_stats(const Dev &d, int nsteps, hipStream_t s)
+{
+    k_step_stats<<<1, kBlock, 0, s>>>(d.step_nce, nsteps, d.enc_cap, d.stats);
     return hipGetLastError();
 }
 

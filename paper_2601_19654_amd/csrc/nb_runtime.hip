@@ -4,12 +4,16 @@
 // the caller's workspace.
 #include "nb.h"
 #include "nb_internal.h"
+#include "nb_resolve.h"
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace nb;
@@ -24,9 +28,20 @@ struct nb_ctx {
     bool have_state = false, have_drift = false, have_enc = false;
     double last_dt = 0.0;
     hipGraphExec_t gexec = nullptr;
+    // second stream on which the sorted encounter test overlaps S(h) and the force
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     double graph_dt = 0.0;
     int graph_steps = 0;
     std::string err;
+    // close-encounter resolver (resolve = 1)
+    std::unique_ptr<WorkerPool> pool;
+    Groups groups;
+    std::vector<int32_t> h_ice, h_jce;
+    std::vector<Member> h_in;
+    std::vector<double> h_out;
+    long long res_groups = 0, res_bodies = 0;
+    int res_max_group = 0, res_fail = 0;
 };
 
 namespace {
@@ -76,15 +91,49 @@ Params to_internal(const nb_params &q)
     p.force_j = q.force_jchunk > 0 ? (q.force_jchunk + kBlock - 1) / kBlock * kBlock : kDefaultForceJ;
     p.enc_j = q.enc_jchunk > 0 ? q.enc_jchunk : kDefaultEncJ;
     p.enc_algo = q.enc_algo;
+    p.step_algo = q.step_algo;
+    p.resolve = q.resolve;
+    p.resolve_threads = q.resolve_threads;
+    p.bs_tol = q.bs_tol > 0.0 ? q.bs_tol : 1e-12;
     return p;
 }
 
-// Encounter algorithm: explicit choice, else sorted tiles for large totals.
-int choose_enc_algo(const Params &p, int ntot)
+int resolver_threads(int requested)
+{
+    if (requested > 0)
+        return requested;
+    const unsigned hw = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(hw, 16u));
+}
+
+// Step launch: explicit choice, else the persistent per-system launch for FP64
+// batches whose systems are all small enough and numerous (or tiny).
+int choose_step_algo(const Params &p, int nsys, const int32_t *off)
+{
+    int nmax = 0;
+    for (int s = 0; s < nsys; ++s)
+        nmax = std::max(nmax, off[s + 1] - off[s]);
+    bool fits = nmax <= NB_PERSISTENT_MAX_N && p.mode == NB_FP64 && !p.resolve;
+    if (p.step_algo == 2)
+        return fits ? 2 : 1;
+    if (p.step_algo == 1)
+        return 1;
+    return fits && (nmax <= 2048 || nsys >= 64) ? 2 : 1;
+}
+
+// Encounter algorithm: explicit choice, else sorted tiles when bodies have
+// many candidate partners on average (tested pairs per body >= 512); with few
+// big bodies or small systems every pair through the filters is cheaper.
+int choose_enc_algo(const Params &p, int nsys, const int32_t *off, const int32_t *nbig)
 {
     if (p.enc_algo == 1 || p.enc_algo == 2)
         return p.enc_algo;
-    return ntot >= 8192 ? 2 : 1;
+    long long pairs = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const long long n = off[s + 1] - off[s], nb = nbig ? nbig[s] : n;
+        pairs += nb * (n - 1) - nb * (nb - 1) / 2;
+    }
+    return pairs >= 512ll * std::max(off[nsys], 1) ? 2 : 1;
 }
 
 int check_params(const nb_params *p)
@@ -99,7 +148,11 @@ int check_params(const nb_params *p)
         return NB_E_INVALID;
     if (p->force_r != 0 && p->force_r != 1 && p->force_r != 2 && p->force_r != 4)
         return NB_E_INVALID;
-    if (p->force_jchunk < 0 || p->enc_jchunk < 0 || p->enc_algo < 0 || p->enc_algo > 2)
+    if (p->force_jchunk < 0 || p->enc_jchunk < 0 || p->enc_algo < 0 || p->enc_algo > 2 ||
+        p->step_algo < 0 || p->step_algo > 2)
+        return NB_E_INVALID;
+    if ((p->resolve != 0 && p->resolve != 1) || p->resolve_threads < 0 || p->reserved != 0 ||
+        !(p->bs_tol >= 0.0 && p->bs_tol < 1.0) || (p->resolve && p->step_algo == 2))
         return NB_E_INVALID;
     if (p->drag && !(p->drag_h > 0.0 && p->drag_h * p->drag_h * 3.0 < 1.0 && p->drag_rho_p > 0.0 &&
                      p->drag_sigma0 >= 0.0 && p->drag_cd >= 0.0))
@@ -107,16 +160,26 @@ int check_params(const nb_params *p)
     return NB_OK;
 }
 
-int check_offsets(int nsys, const int32_t *off)
+int check_offsets(int nsys, const int32_t *off, const int32_t *nbig)
 {
     if (nsys <= 0 || !off || off[0] != 0)
         return NB_E_INVALID;
     for (int s = 0; s < nsys; ++s)
-        if (off[s + 1] < off[s])
+        if (off[s + 1] < off[s] || (nbig && (nbig[s] < 0 || nbig[s] > off[s + 1] - off[s])))
             return NB_E_INVALID;
     if (off[nsys] <= 0)
         return NB_E_INVALID;
     return NB_OK;
+}
+
+bool has_small(int nsys, const int32_t *off, const int32_t *nbig)
+{
+    if (!nbig)
+        return false;
+    for (int s = 0; s < nsys; ++s)
+        if (nbig[s] < off[s + 1] - off[s])
+            return true;
+    return false;
 }
 
 // Host-side tables of a context.
@@ -134,14 +197,19 @@ struct Tables {
     int ncell = 0;
     std::vector<Tile> tiles;
     long long tp_cap = 0;
+    bool enc_sorted = false;
+    bool force_few = false;
+    // persistent step launch: systems largest first
+    std::vector<PSys> psys;
 };
 
-// Unordered-pair items of one system: targets in tiles of kBlock, sources in
+// Unordered pair items (i < j) of one system with i < nb (the big bodies: pairs
+// of two small bodies do not interact): targets in tiles of kBlock, sources in
 // chunks of J; an item exists when some source index exceeds some target index.
-void pair_items(int a, int n, int J, std::vector<PWork> &out)
+void pair_items(int a, int n, int nb, int J, std::vector<PWork> &out)
 {
-    for (int i0 = 0; i0 < n; i0 += kBlock) {
-        int ni = std::min(kBlock, n - i0);
+    for (int i0 = 0; i0 < nb; i0 += kBlock) {
+        int ni = std::min(kBlock, nb - i0);
         for (int j0 = 0; j0 < n; j0 += J) {
             int nj = std::min(J, n - j0);
             if (j0 + nj - 1 > i0)
@@ -150,8 +218,9 @@ void pair_items(int a, int n, int J, std::vector<PWork> &out)
     }
 }
 
-void build_tables(const Params &p, int nsys, const int32_t *off, Tables &t)
+void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *nbig, Tables &t)
 {
+    t.enc_sorted = choose_enc_algo(p, nsys, off, nbig) == 2;
     t.rb_first.assign(nsys, 0);
     t.rb_count.assign(nsys, 0);
     t.nsplit.assign(nsys, 0);
@@ -169,20 +238,30 @@ void build_tables(const Params &p, int nsys, const int32_t *off, Tables &t)
         t.rb_count[s] = (int)t.rblk.size() - t.rb_first[s];
         if (n == 0)
             continue;
-        int S = (n + p.force_j - 1) / p.force_j;
+        // sources are the big bodies [a, a + nb) only (Sec. 2.1)
+        const int nb = nbig ? nbig[s] : n;
+        int S = (nb + p.force_j - 1) / p.force_j;
         t.nsplit[s] = S;
         t.maxs = std::max(t.maxs, S);
         for (int i0 = 0; i0 < n; i0 += TI)
             for (int k = 0; k < S; ++k) {
                 int j0 = k * p.force_j;
                 t.fwork.push_back(FWork{a + i0, std::min(TI, n - i0), a + j0,
-                                        std::min(p.force_j, n - j0), k, s,
+                                        std::min(p.force_j, nb - j0), k, s,
                                         t.rb_first[s] + j0 / kBlock, 0});
             }
-        pair_items(a, n, p.enc_j, t.ework);
+        pair_items(a, n, nb, p.enc_j, t.ework);
         t.dw_first[s] = (int)t.dwork.size();
-        pair_items(a, n, p.enc_j, t.dwork);
+        pair_items(a, n, nb, p.enc_j, t.dwork);
         t.dw_count[s] = (int)t.dwork.size() - t.dw_first[s];
+    }
+    // few-source force kernels: every system's sources fit one LDS slice (and one
+    // split), and there are enough target tiles (>= 1024) to fill the GPU by waves
+    {
+        int maxnb = 0;
+        for (int s = 0; s < nsys; ++s)
+            maxnb = std::max(maxnb, nbig ? nbig[s] : off[s + 1] - off[s]);
+        t.force_few = maxnb <= 256 && maxnb <= p.force_j && t.fwork.size() >= 1024;
     }
     // sorted encounter check: about N_s/8 cells per system (a power of two) and
     // tiles of 64 consecutive sorted bodies
@@ -202,6 +281,12 @@ void build_tables(const Params &p, int nsys, const int32_t *off, Tables &t)
             t.tiles.push_back(Tile{s, off[s] + 64 * k, std::min(64, n - 64 * k), first + nt - 1});
         t.tp_cap += (long long)nt * (nt + 1) / 2;
     }
+    for (int s = 0; s < nsys; ++s)
+        if (off[s + 1] > off[s])
+            t.psys.push_back(PSys{s, off[s], off[s + 1] - off[s],
+                                  nbig ? nbig[s] : off[s + 1] - off[s]});
+    std::stable_sort(t.psys.begin(), t.psys.end(),
+                     [](const PSys &x, const PSys &y) { return x.n > y.n; });
     // longest work first, so the hardware dispatcher packs the tail
     std::stable_sort(t.fwork.begin(), t.fwork.end(), [](const FWork &x, const FWork &y) {
         return (long long)x.ni * x.nj > (long long)y.ni * y.nj;
@@ -254,9 +339,11 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
         *pl = (double *)take(nd);
     d.pk = (float4 *)take((size_t)ntot * 2 * sizeof(float4));
     d.mr = (double4 *)take((size_t)ntot * sizeof(double4));
+    d.cr = (double4 *)take((size_t)ntot * sizeof(double4));
     d.kflag = (int *)take((size_t)ntot * sizeof(int));
     d.ce = (int *)take((size_t)ntot * sizeof(int));
     d.sys_of = (int *)take((size_t)ntot * sizeof(int));
+    d.nbig = (int *)take((size_t)nsys * sizeof(int));
     d.m0 = (double *)take((size_t)nsys * sizeof(double));
     d.off = (int *)take((size_t)(nsys + 1) * sizeof(int));
     // nsplit, then diagnostic item ranges (dw_first, dw_count) right after it
@@ -284,7 +371,13 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.ice = (int *)take((size_t)std::max(enc_cap, 1) * sizeof(int));
     d.jce = (int *)take((size_t)std::max(enc_cap, 1) * sizeof(int));
     d.stats = (DevStats *)take(sizeof(DevStats));
-    d.enc_sorted = choose_enc_algo(p, ntot) == 2;
+    d.step_chunk = 256;
+    d.step_nce = (int *)take((size_t)d.step_chunk * sizeof(int));
+    d.npsys = (int)t.psys.size();
+    d.pmax_n = t.psys.empty() ? 0 : t.psys[0].n;
+    d.psys = (PSys *)take(t.psys.size() * sizeof(PSys));
+    d.enc_sorted = t.enc_sorted;
+    d.force_few = t.force_few ? 1 : 0;
     if (d.enc_sorted) {
         d.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
         d.cell_of = (int *)take((size_t)ntot * sizeof(int));
@@ -292,6 +385,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
         d.ncell = t.ncell;
         d.cell_cnt = (int *)take((size_t)t.ncell * sizeof(int));
         d.cell_off = (int *)take((size_t)t.ncell * sizeof(int));
+        d.scan_part = (int *)take((size_t)(t.ncell / 4096 + 1) * sizeof(int));
         d.sys_cell_base = (int *)take((size_t)nsys * sizeof(int));
         d.sys_cell_cnt = (int *)take((size_t)nsys * sizeof(int));
         d.ord = (int *)take((size_t)ntot * sizeof(int));
@@ -304,6 +398,12 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     }
     d.flag = (int *)take(4 * sizeof(int));
     d.stage = (double *)take((size_t)6 * nd);
+    if (p.resolve) {
+        // every member of a resolved group is in a listed pair
+        d.res_cap = (int)std::min<long long>(ntot, 2ll * std::max(enc_cap, 1));
+        d.res_idx = (int *)take((size_t)d.res_cap * sizeof(int));
+        d.res_buf = (double *)take((size_t)d.res_cap * 10 * sizeof(double));
+    }
     return cur;
 }
 
@@ -344,7 +444,8 @@ int enqueue_force(nb_ctx *c)
 }
 
 // One hybrid step K(h) S(h) D(dt) C S(h) [rc, F] K(h).
-int enqueue_step(nb_ctx *c, double dt)
+// K(h) S(h) D(dt) C of a step.
+int enqueue_step_head(nb_ctx *c, double dt)
 {
     const double h = 0.5 * dt;
     const Dev &d = c->d;
@@ -352,6 +453,14 @@ int enqueue_step(nb_ctx *c, double dt)
     HIP_OK(c, launch_sun_drift(d, h, 0, c->p, c->stream));
     HIP_OK(c, launch_drift(d, c->p, dt, c->stream));
     HIP_OK(c, launch_encounters(d, dt, c->stream));
+    return NB_OK;
+}
+
+// S(h), critical radii, F, K(h) of a step.
+int enqueue_step_tail(nb_ctx *c, double dt)
+{
+    const double h = 0.5 * dt;
+    const Dev &d = c->d;
     HIP_OK(c, launch_sun_drift(d, h, 1, c->p, c->stream));
     HIP_OK(c, launch_force(d, c->p, c->stream));
     if (c->p.drag) {
@@ -361,6 +470,85 @@ int enqueue_step(nb_ctx *c, double dt)
         HIP_OK(c, launch_force_finalize(d, c->p, h, c->stream));
     }
     return NB_OK;
+}
+
+int enqueue_step(nb_ctx *c, double dt)
+{
+    if (c->side && c->d.enc_sorted) {
+        // fork after the records are copied into the sorted array: the test part
+        // of the encounter check runs beside S(h), the force and its finalize
+        const double h = 0.5 * dt;
+        const Dev &d = c->d;
+        HIP_OK(c, launch_kick(d, c->p, h, c->stream));
+        HIP_OK(c, launch_sun_drift(d, h, 0, c->p, c->stream));
+        HIP_OK(c, launch_drift(d, c->p, dt, c->stream));
+        HIP_OK(c, launch_enc_gather(d, c->stream));
+        HIP_OK(c, hipEventRecord(c->ev_fork, c->stream));
+        HIP_OK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
+        HIP_OK(c, launch_enc_test(d, dt, c->side));
+        HIP_OK(c, hipEventRecord(c->ev_join, c->side));
+        int r = enqueue_step_tail(c, dt);
+        if (r)
+            return r;
+        HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+        return NB_OK;
+    }
+    int r = enqueue_step_head(c, dt);
+    return r ? r : enqueue_step_tail(c, dt);
+}
+
+// Between C and the second S(h) of the full method: read the sorted pair list
+// of this step, group it, bring the members' pre-drift records to the host,
+// integrate every group there and write the results back.
+int resolve_step(nb_ctx *c, double dt)
+{
+    Dev &d = c->d;
+    DevStats ds;
+    HIP_OK(c, hipMemcpyAsync(&ds, d.stats, sizeof ds, hipMemcpyDeviceToHost, c->stream));
+    int r = sync(c);
+    if (r)
+        return r;
+    const int npairs = std::min(ds.cur_nce, d.enc_cap);
+    if (npairs <= 0)
+        return NB_OK;
+    c->h_ice.resize(npairs);
+    c->h_jce.resize(npairs);
+    HIP_OK(c, hipMemcpyAsync(c->h_ice.data(), d.ice, npairs * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->h_jce.data(), d.jce, npairs * sizeof(int32_t),
+                             hipMemcpyDeviceToHost, c->stream));
+    if ((r = sync(c)))
+        return r;
+    for (int k = 0; k < npairs; ++k)
+        if (c->h_ice[k] < 0 || c->h_ice[k] >= c->ntot || c->h_jce[k] < 0 ||
+            c->h_jce[k] >= c->ntot)
+            return set_err(c, NB_E_HIP, "resolver: pair %d has an index out of range", k);
+    build_groups(npairs, c->h_ice.data(), c->h_jce.data(), c->groups);
+    const int k = (int)c->groups.body.size();
+    if (k > d.res_cap)
+        return set_err(c, NB_E_HIP, "resolver: %d members exceed the capacity %d", k, d.res_cap);
+    c->h_in.resize(k);
+    c->h_out.resize((size_t)6 * k);
+    HIP_OK(c, hipMemcpyAsync(d.res_idx, c->groups.body.data(), k * sizeof(int32_t),
+                             hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, launch_gather_members(d, k, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->h_in.data(), d.res_buf, k * sizeof(Member), hipMemcpyDeviceToHost,
+                             c->stream));
+    if ((r = sync(c)))
+        return r;
+    if (!c->pool && resolver_threads(c->p.resolve_threads) > 1)
+        c->pool.reset(new WorkerPool(resolver_threads(c->p.resolve_threads)));
+    ResolveTotals t = resolve_groups(c->groups, c->h_in.data(), c->h_out.data(), c->p.G,
+                                     c->p.inner, dt, c->p.bs_tol, c->pool.get());
+    c->res_groups += t.groups;
+    c->res_bodies += t.bodies;
+    c->res_max_group = std::max(c->res_max_group, t.max_group);
+    c->res_fail += t.failed;
+    HIP_OK(c, hipMemcpyAsync(d.res_buf, c->h_out.data(), (size_t)6 * k * sizeof(double),
+                             hipMemcpyHostToDevice, c->stream));
+    HIP_OK(c, launch_scatter_members(d, k, c->stream));
+    // h_out must stay intact until the copy has been read
+    return sync(c);
 }
 
 void drop_graph(nb_ctx *c)
@@ -399,6 +587,49 @@ int build_graph(nb_ctx *c, double dt, int steps)
     return NB_OK;
 }
 
+// nsteps whole steps on the context's stream, by the context's step launch.
+int enqueue_steps(nb_ctx *c, double dt, int nsteps)
+{
+    int r = NB_OK;
+    int done = 0;
+    if (c->p.resolve) {
+        // the host takes part in every step: direct launches, no graph
+        for (; done < nsteps; ++done) {
+            if ((r = enqueue_step_head(c, dt)) || (r = resolve_step(c, dt)) ||
+                (r = enqueue_step_tail(c, dt)))
+                return r;
+        }
+        return NB_OK;
+    }
+    if (c->p.step_algo == 2) {
+        // persistent per-system launches of at most step_chunk steps each
+        while (done < nsteps) {
+            int k = std::min(nsteps - done, c->d.step_chunk);
+            HIP_OK(c, launch_fill_i32(&c->d.stats->cur_nce, 1, 0, c->stream));
+            HIP_OK(c, launch_persistent_steps(c->d, c->p, dt, k, c->stream));
+            HIP_OK(c, launch_step_stats(c->d, k, c->stream));
+            done += k;
+        }
+        if (nsteps > 0)
+            HIP_OK(c, launch_enc_sort(c->d, 0, c->stream));
+        return NB_OK;
+    }
+    if (c->stream && nsteps > 0) {
+        int g = std::min(nsteps, kMaxGraphSteps);
+        if (!c->gexec || c->graph_dt != dt || c->graph_steps != g)
+            if ((r = build_graph(c, dt, g)))
+                return r;
+        while (nsteps - done >= c->graph_steps) {
+            HIP_OK(c, hipGraphLaunch(c->gexec, c->stream));
+            done += c->graph_steps;
+        }
+    }
+    for (; done < nsteps; ++done)
+        if ((r = enqueue_step(c, dt)))
+            return r;
+    return NB_OK;
+}
+
 int copy_list(nb_ctx *c, int cap, int *nce, int32_t *ice, int32_t *jce, int32_t *ce, int where)
 {
     DevStats st;
@@ -425,6 +656,21 @@ int copy_list(nb_ctx *c, int cap, int *nce, int32_t *ice, int32_t *jce, int32_t 
         return set_err(c, NB_E_CAPACITY, "encounter count %d exceeds capacity %d", count,
                        std::min(cap, c->enc_cap));
     return NB_OK;
+}
+
+// Free what the context owns (graph, side stream, events) and the context.
+void release(nb_ctx *c)
+{
+    drop_graph(c);
+    if (c->side) {
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamDestroy(c->side);
+    }
+    if (c->ev_fork)
+        (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join)
+        (void)hipEventDestroy(c->ev_join);
+    delete c;
 }
 
 int enter(nb_ctx *c)
@@ -482,25 +728,28 @@ void nb_default_params(nb_params *p)
     p->drag_rho_p = 2.0 / (msun_g / (au_cm * au_cm * au_cm));
 }
 
-int nb_workspace_size(const nb_params *p, int nsys, const int32_t *off, int enc_cap, size_t *bytes)
+int nb_workspace_size(const nb_params *p, int nsys, const int32_t *off, const int32_t *nbig,
+                      int enc_cap, size_t *bytes)
 {
-    if (!bytes || check_params(p) || check_offsets(nsys, off) || enc_cap < 0)
+    if (!bytes || check_params(p) || check_offsets(nsys, off, nbig) || enc_cap < 0 ||
+        (p->drag && has_small(nsys, off, nbig)))
         return NB_E_INVALID;
     Params q = to_internal(*p);
     Tables t;
-    build_tables(q, nsys, off, t);
+    build_tables(q, nsys, off, nbig, t);
     Dev d{};
     *bytes = carve(q, nsys, off[nsys], enc_cap, t, nullptr, d);
     return NB_OK;
 }
 
-int nb_create(const nb_params *p, int nsys, const int32_t *off, int enc_cap, void *workspace,
-              size_t bytes, void *stream, nb_ctx **out)
+int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *nbig, int enc_cap,
+              void *workspace, size_t bytes, void *stream, nb_ctx **out)
 {
     if (!out)
         return NB_E_INVALID;
     *out = nullptr;
-    if (check_params(p) || check_offsets(nsys, off) || enc_cap < 0)
+    if (check_params(p) || check_offsets(nsys, off, nbig) || enc_cap < 0 ||
+        (p->drag && has_small(nsys, off, nbig)))
         return NB_E_INVALID;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
         return NB_E_WORKSPACE;
@@ -516,7 +765,7 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, int enc_cap, voi
         return NB_E_HIP;
     }
     Tables t;
-    build_tables(c->p, nsys, off, t);
+    build_tables(c->p, nsys, off, nbig, t);
     size_t need = carve(c->p, nsys, c->ntot, enc_cap, t, nullptr, c->d);
     if (bytes < need) {
         delete c;
@@ -535,6 +784,10 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, int enc_cap, voi
             r = copy(c, dst, src, n);
     };
     up(c->d.off, off, (nsys + 1) * sizeof(int));
+    std::vector<int> nb(nsys);
+    for (int s = 0; s < nsys; ++s)
+        nb[s] = nbig ? nbig[s] : off[s + 1] - off[s];
+    up(c->d.nbig, nb.data(), nsys * sizeof(int));
     up(c->d.nsplit, ranges.data(), ranges.size() * sizeof(int));
     up(c->d.rb_first, t.rb_first.data(), nsys * sizeof(int));
     up(c->d.rb_count, t.rb_count.data(), nsys * sizeof(int));
@@ -543,6 +796,10 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, int enc_cap, voi
     up(c->d.fwork, t.fwork.data(), t.fwork.size() * sizeof(FWork));
     up(c->d.ework, t.ework.data(), t.ework.size() * sizeof(PWork));
     up(c->d.dwork, t.dwork.data(), t.dwork.size() * sizeof(PWork));
+    up(c->d.psys, t.psys.data(), t.psys.size() * sizeof(PSys));
+    c->p.step_algo = choose_step_algo(c->p, nsys, off);
+    if (r == NB_OK && launch_fill_i32(c->d.step_nce, c->d.step_chunk, 0, c->stream) != hipSuccess)
+        r = set_err(c, NB_E_HIP, "nb_create: clearing the step counters failed");
     if (c->d.enc_sorted) {
         up(c->d.sys_cell_base, t.cell_base.data(), nsys * sizeof(int));
         up(c->d.sys_cell_cnt, t.cell_cnt.data(), nsys * sizeof(int));
@@ -554,8 +811,15 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, int enc_cap, voi
         r = reset_stats(c);
     if (r == NB_OK)
         r = sync(c);
+    if (r == NB_OK && c->stream && c->d.enc_sorted) {
+        // default priority, like every stream here
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+            r = set_err(c, NB_E_HIP, "nb_create: side stream or events");
+    }
     if (r != NB_OK) {
-        delete c;
+        release(c);
         return r;
     }
     *out = c;
@@ -589,9 +853,13 @@ int nb_upload(nb_ctx *c, const double *m0, const double *m, const double *x, con
     int bad = 0;
     if ((r = read_int(c, c->d.flag, &bad)))
         return r;
-    if (bad) {
+    if (bad & 1) {
         c->have_state = false;
         return set_err(c, NB_E_NONFINITE, "nb_upload: non-finite value, negative mass or m0 <= 0");
+    }
+    if (bad & 2) {
+        c->have_state = false;
+        return set_err(c, NB_E_INVALID, "nb_upload: a small body has a nonzero mass");
     }
     HIP_OK(c, launch_to_dh(c->d, xs, vs, frame, c->stream));
     if ((r = enqueue_force(c)))
@@ -727,20 +995,10 @@ int nb_step(nb_ctx *c, double dt, int nsteps, nb_stats *st)
         return set_err(c, NB_E_INVALID, "nb_step: bad argument");
     if ((r = reset_stats(c)))
         return r;
-    int done = 0;
-    if (c->stream && nsteps > 0) {
-        int g = std::min(nsteps, kMaxGraphSteps);
-        if (!c->gexec || c->graph_dt != dt || c->graph_steps != g)
-            if ((r = build_graph(c, dt, g)))
-                return r;
-        while (nsteps - done >= c->graph_steps) {
-            HIP_OK(c, hipGraphLaunch(c->gexec, c->stream));
-            done += c->graph_steps;
-        }
-    }
-    for (; done < nsteps; ++done)
-        if ((r = enqueue_step(c, dt)))
-            return r;
+    c->res_groups = c->res_bodies = 0;
+    c->res_max_group = c->res_fail = 0;
+    if ((r = enqueue_steps(c, dt, nsteps)))
+        return r;
     DevStats ds;
     HIP_OK(c, hipMemcpyAsync(&ds, c->d.stats, sizeof ds, hipMemcpyDeviceToHost, c->stream));
     if ((r = sync(c)))
@@ -751,6 +1009,10 @@ int nb_step(nb_ctx *c, double dt, int nsteps, nb_stats *st)
         st->overflow_steps = ds.overflow_steps;
         st->kepler_fail = ds.kepler_fail;
         st->near_pairs = ds.near_pairs;
+        st->resolved_groups = c->res_groups;
+        st->resolved_bodies = c->res_bodies;
+        st->max_group = c->res_max_group;
+        st->bs_fail = c->res_fail;
     }
     if (nsteps > 0) {
         // the snapshot and the state no longer form a drift pair
@@ -837,7 +1099,7 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
         return r;
     if (!c->have_state)
         return set_err(c, NB_E_NOT_READY, "nb_time_kernel: no state");
-    if (!ms || reps <= 0 || which < NB_K_FORCE || which > NB_K_STEP || !std::isfinite(dt))
+    if (!ms || reps <= 0 || which < NB_K_FORCE || which > NB_K_FORCE_EVAL || !std::isfinite(dt))
         return set_err(c, NB_E_INVALID, "nb_time_kernel: bad argument");
     if (which == NB_K_ENCOUNTER && !c->have_drift && !c->have_enc)
         return set_err(c, NB_E_NOT_READY, "nb_time_kernel: no drift before the encounter check");
@@ -847,13 +1109,19 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
             HIP_OK(c, launch_force(c->d, c->p, c->stream));
             return NB_OK;
         case NB_K_ENCOUNTER:
+            // each check starts from an empty list, as after a drift
+            HIP_OK(c, launch_fill_i32(&c->d.stats->cur_nce, 1, 0, c->stream));
             HIP_OK(c, launch_encounters(c->d, c->last_dt, c->stream));
             return NB_OK;
         case NB_K_DRIFT:
             HIP_OK(c, launch_drift(c->d, c->p, dt, c->stream));
             return NB_OK;
+        case NB_K_FORCE_EVAL:
+            return enqueue_force(c);
         default:
-            return enqueue_step(c, dt);
+            // as many steps as the timed call replays per graph, so that the
+            // graph it launches is built here, outside the timed region
+            return enqueue_steps(c, dt, std::min(reps, kMaxGraphSteps));
         }
     };
     if ((r = once()))
@@ -865,8 +1133,11 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
         return set_err(c, NB_E_HIP, "hipEventCreate failed");
     }
     hipError_t he = hipEventRecord(e0, c->stream);
-    for (int k = 0; k < reps && r == NB_OK && he == hipSuccess; ++k)
-        r = once();
+    if (which == NB_K_STEP)
+        r = enqueue_steps(c, dt, reps);     // the way nb_step runs them
+    else
+        for (int k = 0; k < reps && r == NB_OK && he == hipSuccess; ++k)
+            r = once();
     if (he == hipSuccess)
         he = hipEventRecord(e1, c->stream);
     if (he == hipSuccess)
@@ -888,6 +1159,75 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
     return NB_OK;
 }
 
+int nb_resolve_host(int n, double G, double m0, double chg_inner, double tol, double tau,
+                    const double *m, const double *rc, const double *Q0, const double *V0,
+                    int nce, const int32_t *ice, const int32_t *jce, double *Q, double *V,
+                    int32_t *group, int nthreads, nb_resolve_info *info)
+{
+    if (n < 0 || nce < 0 || nthreads < 0 || !(G > 0.0) || !(m0 > 0.0) ||
+        !(chg_inner >= 0.0 && chg_inner < 1.0) || !(tol >= 0.0 && tol < 1.0) ||
+        !std::isfinite(tau))
+        return NB_E_INVALID;
+    if (n > 0 && (!m || !rc || !Q0 || !V0 || !Q || !V))
+        return NB_E_INVALID;
+    if (nce > 0 && (!ice || !jce))
+        return NB_E_INVALID;
+    for (int k = 0; k < nce; ++k)
+        if (ice[k] < 0 || ice[k] >= n || jce[k] < 0 || jce[k] >= n || ice[k] == jce[k])
+            return NB_E_INVALID;
+    Groups g;
+    build_groups(nce, ice, jce, g);
+    const int k = (int)g.body.size();
+    std::vector<Member> in(k);
+    for (int e = 0; e < k; ++e) {
+        const int i = g.body[e];
+        Member &mb = in[e];
+        mb.m0 = m0;
+        mb.m = m[i];
+        mb.rc = rc[i];
+        for (int c = 0; c < 3; ++c) {
+            mb.q[c] = Q0[3 * i + c];
+            mb.v[c] = V0[3 * i + c];
+        }
+        mb.pad = 0.0;
+    }
+    std::vector<double> out((size_t)6 * k);
+    std::unique_ptr<WorkerPool> pool;
+    const int nt = resolver_threads(nthreads);
+    if (nt > 1 && g.count() > 1)
+        pool.reset(new WorkerPool(std::min(nt, g.count())));
+    ResolveTotals t = resolve_groups(g, in.data(), out.data(), G, chg_inner, tau,
+                                     tol > 0.0 ? tol : 1e-12, pool.get());
+    for (int e = 0; e < k; ++e) {
+        const double *o = out.data() + 6 * (size_t)e;
+        bool ok = true;
+        for (int c = 0; c < 6; ++c)
+            ok = ok && std::isfinite(o[c]);
+        if (!ok)
+            continue;
+        const int i = g.body[e];
+        for (int c = 0; c < 3; ++c) {
+            Q[3 * i + c] = o[c];
+            V[3 * i + c] = o[3 + c];
+        }
+    }
+    if (group) {
+        for (int i = 0; i < n; ++i)
+            group[i] = -1;
+        for (int gi = 0; gi < g.count(); ++gi)
+            for (int e = g.start[gi]; e < g.start[gi + 1]; ++e)
+                group[g.body[e]] = g.body[g.start[gi]];
+    }
+    if (info) {
+        info->groups = t.groups;
+        info->bodies = t.bodies;
+        info->max_group = t.max_group;
+        info->failed = t.failed;
+        info->max_steps = t.max_steps;
+    }
+    return NB_OK;
+}
+
 int nb_destroy(nb_ctx *c)
 {
     if (!c)
@@ -897,8 +1237,7 @@ int nb_destroy(nb_ctx *c)
         (void)hipStreamSynchronize(c->stream);
     else
         (void)hipDeviceSynchronize();
-    drop_graph(c);
-    delete c;
+    release(c);
     return NB_OK;
 }
 

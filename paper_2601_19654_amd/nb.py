@@ -34,6 +34,7 @@ NB_K_FORCE = 0
 NB_K_ENCOUNTER = 1
 NB_K_DRIFT = 2
 NB_K_STEP = 3
+NB_K_FORCE_EVAL = 4
 
 
 class nb_params(ctypes.Structure):
@@ -44,7 +45,9 @@ class nb_params(ctypes.Structure):
         ("drag_cd", ctypes.c_double), ("drag_rho_p", ctypes.c_double),
         ("force_jchunk", ctypes.c_int32), ("force_r", ctypes.c_int32),
         ("enc_jchunk", ctypes.c_int32), ("enc_algo", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("step_algo", ctypes.c_int32), ("resolve", ctypes.c_int32),
+        ("resolve_threads", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("bs_tol", ctypes.c_double),
     ]
 
 
@@ -52,7 +55,16 @@ class nb_stats(ctypes.Structure):
     _fields_ = [
         ("total_nce", ctypes.c_int64), ("max_nce", ctypes.c_int32),
         ("overflow_steps", ctypes.c_int32), ("kepler_fail", ctypes.c_int64),
-        ("near_pairs", ctypes.c_int64),
+        ("near_pairs", ctypes.c_int64), ("resolved_groups", ctypes.c_int64),
+        ("resolved_bodies", ctypes.c_int64), ("max_group", ctypes.c_int32),
+        ("bs_fail", ctypes.c_int32),
+    ]
+
+
+class nb_resolve_info(ctypes.Structure):
+    _fields_ = [
+        ("groups", ctypes.c_int32), ("bodies", ctypes.c_int32), ("max_group", ctypes.c_int32),
+        ("failed", ctypes.c_int32), ("max_steps", ctypes.c_int32),
     ]
 
 
@@ -70,8 +82,8 @@ SIGNATURES = {
     "nb_version": (_I, [_P, _P]),
     "nb_strerror": (ctypes.c_char_p, [_I]),
     "nb_default_params": (None, [_P]),
-    "nb_workspace_size": (_I, [_P, _I, _P, _I, _P]),
-    "nb_create": (_I, [_P, _I, _P, _I, _P, _S, _P, _P]),
+    "nb_workspace_size": (_I, [_P, _I, _P, _P, _I, _P]),
+    "nb_create": (_I, [_P, _I, _P, _P, _I, _P, _S, _P, _P]),
     "nb_last_error": (ctypes.c_char_p, [_P]),
     "nb_upload": (_I, [_P, _P, _P, _P, _P, _I, _I]),
     "nb_download": (_I, [_P, _P, _P, _I, _I]),
@@ -86,6 +98,7 @@ SIGNATURES = {
     "nb_get_accel": (_I, [_P, _P, _I]),
     "nb_get_rcrit": (_I, [_P, _P, _I]),
     "nb_time_kernel": (_I, [_P, _I, _I, _D, _P]),
+    "nb_resolve_host": (_I, [_I, _D, _D, _D, _D, _D, _P, _P, _P, _P, _I, _P, _P, _P, _P, _P, _I, _P]),
     "nb_destroy": (_I, [_P]),
 }
 
@@ -140,6 +153,23 @@ class Encounters:
     ce: np.ndarray
 
 
+def resolve_host(G, m0, m, rc, tau, Q0, V0, ice, jce, Q, V, tol=0.0, inner=0.1, nthreads=0):
+    """Host close-encounter resolver on one system's host arrays (n x 3 rows,
+    local pair indices).  Returns (Q, V, group, info dict)."""
+    m = _f64(m); rc = _f64(rc); n = len(m)
+    Q0 = _f64(Q0).reshape(n, 3); V0 = _f64(V0).reshape(n, 3)
+    Q = _f64(Q).reshape(n, 3).copy(); V = _f64(V).reshape(n, 3).copy()
+    ice = np.ascontiguousarray(ice, dtype=np.int32); jce = np.ascontiguousarray(jce, dtype=np.int32)
+    group = np.empty(max(n, 1), np.int32)
+    info = nb_resolve_info()
+    code = lib().nb_resolve_host(n, float(G), float(m0), float(inner), float(tol), float(tau), _addr(m), _addr(rc),
+                                 _addr(Q0), _addr(V0), len(ice), _addr(ice), _addr(jce), _addr(Q), _addr(V),
+                                 _addr(group), int(nthreads), ctypes.byref(info))
+    if code != NB_OK:
+        raise NbError(code, "nb_resolve_host")
+    return Q, V, group[:n].copy(), {k: getattr(info, k) for k, _ in nb_resolve_info._fields_}
+
+
 class Context:
     """One nb_ctx: workspace and stream from PyTorch, every call into libnbody.
 
@@ -148,18 +178,22 @@ class Context:
     """
 
     def __init__(self, off, params: nb_params | None = None, enc_cap: int = 1 << 16,
-                 stream=None, device=None, tuned: bool = True):
+                 stream=None, device=None, tuned: bool = True, nbig=None):
         import torch
         self._torch = torch
         L = lib()
         self.params = params or default_params()
         self.off = np.ascontiguousarray(off, dtype=np.int32)
+        # per system: the first nbig[s] bodies are big (gravity sources); None = all
+        self.nbig = None if nbig is None else np.ascontiguousarray(nbig, dtype=np.int32)
+        nbig_p = None if self.nbig is None else _addr(self.nbig)
         self.tiles = "library defaults"
         if tuned and not (self.params.force_r or self.params.force_jchunk or self.params.enc_jchunk
-                          or self.params.enc_algo):
+                          or self.params.enc_algo or self.params.step_algo):
             from . import autotune
             try:
-                hit = autotune.lookup("fp32c" if self.params.mode == NB_FP32C else "fp64", self.off)
+                hit = autotune.lookup("fp32c" if self.params.mode == NB_FP32C else "fp64", self.off,
+                                      nbig=self.nbig)
             except Exception:
                 hit = None
             if hit:
@@ -167,19 +201,21 @@ class Context:
                 self.params.force_jchunk = hit["force_jchunk"]
                 self.params.enc_jchunk = hit["enc_jchunk"]
                 self.params.enc_algo = hit.get("enc_algo", 0)
+                # the persistent launch cannot hand groups to the host resolver
+                self.params.step_algo = 0 if self.params.resolve else hit.get("step_algo", 0)
                 self.tiles = "tuned"
         self.nsys = len(self.off) - 1
         self.ntot = int(self.off[-1])
         self.enc_cap = int(enc_cap)
         nbytes = ctypes.c_size_t()
-        self._check(L.nb_workspace_size(ctypes.byref(self.params), self.nsys, _addr(self.off),
+        self._check(L.nb_workspace_size(ctypes.byref(self.params), self.nsys, _addr(self.off), nbig_p,
                                         self.enc_cap, ctypes.byref(nbytes)), "nb_workspace_size")
         self.device = torch.device(device or "cuda")
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         self.workspace = torch.empty(max(int(nbytes.value), 256), dtype=torch.uint8, device=self.device)
         self.ctx = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            self._check(L.nb_create(ctypes.byref(self.params), self.nsys, _addr(self.off), self.enc_cap,
+            self._check(L.nb_create(ctypes.byref(self.params), self.nsys, _addr(self.off), nbig_p, self.enc_cap,
                                     _addr(self.workspace), nbytes.value,
                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)),
                         "nb_create")

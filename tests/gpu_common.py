@@ -10,7 +10,7 @@ U = 2.0 ** -53
 def ctx_for(w, mode=0, enc_cap=1 << 16, **kw):
     from paper_2601_19654_amd import nb
     p = nb.default_params(G=w.G, mode=mode, drag=int(w.drag), **kw)
-    c = nb.Context(w.off, p, enc_cap=enc_cap, device="cuda:0")
+    c = nb.Context(w.off, p, enc_cap=enc_cap, device="cuda:0", nbig=getattr(w, "nbig", None))
     c.upload(w.m0, w.m, w.x, w.v)
     return c
 
@@ -18,6 +18,11 @@ def ctx_for(w, mode=0, enc_cap=1 << 16, **kw):
 def systems(w):
     for s in range(w.nsys):
         yield s, int(w.off[s]), int(w.off[s + 1])
+
+
+def nbig_of(w, s):
+    nb = getattr(w, "nbig", None)
+    return int(w.off[s + 1] - w.off[s]) if nb is None else int(nb[s])
 
 
 def oracle_dh(w):
@@ -28,7 +33,7 @@ def oracle_dh(w):
             continue
         Q[lo:hi], V[lo:hi] = oracle.helio_to_dh(w.m0[s], w.m[lo:hi], w.x[lo:hi], w.v[lo:hi])
         rc[lo:hi] = oracle.rcrit(w.m0[s], w.m[lo:hi], Q[lo:hi])
-        a[lo:hi] = oracle.force(w.m[lo:hi], Q[lo:hi], rc[lo:hi], w.G)
+        a[lo:hi] = oracle.force(w.m[lo:hi], Q[lo:hi], rc[lo:hi], w.G, nbig=nbig_of(w, s))
     return Q, V, rc, a
 
 

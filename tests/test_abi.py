@@ -43,12 +43,14 @@ def test_version_status_defaults(nb):
     assert abs(p.drag_sigma0 - 1.1252e-4) < 1e-7
 
 
-def _wsize(nb, off, enc_cap=1024, **kw):
+def _wsize(nb, off, enc_cap=1024, nbig=None, **kw):
     p = nb.default_params(**kw)
     off = np.ascontiguousarray(off, dtype=np.int32)
+    nb_arr = None if nbig is None else np.ascontiguousarray(nbig, dtype=np.int32)
     n = ctypes.c_size_t()
-    rc = nb.lib().nb_workspace_size(ctypes.byref(p), len(off) - 1,
-                                    off.ctypes.data_as(ctypes.c_void_p), enc_cap, ctypes.byref(n))
+    rc = nb.lib().nb_workspace_size(ctypes.byref(p), len(off) - 1, off.ctypes.data_as(ctypes.c_void_p),
+                                    None if nb_arr is None else nb_arr.ctypes.data_as(ctypes.c_void_p),
+                                    enc_cap, ctypes.byref(n))
     return rc, n.value
 
 
@@ -66,15 +68,28 @@ def test_workspace_size_and_validation(nb):
     assert _wsize(nb, [0, 10], force_r=3)[0] == nb.NB_E_INVALID
     assert _wsize(nb, [0, 10], G=-1.0)[0] == nb.NB_E_INVALID
     assert _wsize(nb, [0, 10], enc_cap=-1)[0] == nb.NB_E_INVALID
-
+    # big/small split: 0 <= nbig[s] <= N_s; no drag with small bodies
+    assert _wsize(nb, [0, 400, 1000], nbig=[400, 10])[0] == 0
+    assert _wsize(nb, [0, 400, 1000], nbig=[400, 0])[0] == 0
+    assert _wsize(nb, [0, 400, 1000], nbig=[401, 10])[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 400, 1000], nbig=[-1, 10])[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 400, 1000], nbig=[400, 10], drag=1)[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 400, 1000], nbig=[400, 600], drag=1)[0] == 0
+    # resolver parameters
+    assert _wsize(nb, [0, 10], resolve=2)[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 10], resolve=1, step_algo=2)[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 10], resolve=1, bs_tol=-1.0)[0] == nb.NB_E_INVALID
+    rc, plain = _wsize(nb, [0, 1000])
+    rc, full = _wsize(nb, [0, 1000], resolve=1)
+    assert rc == 0 and full > plain
 
 def test_create_rejects_bad_workspace(nb):
     p = nb.default_params()
     off = np.array([0, 10], dtype=np.int32)
     ctx = ctypes.c_void_p()
-    rc = nb.lib().nb_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.c_void_p), 16, None, 0,
+    rc = nb.lib().nb_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.c_void_p), None, 16, None, 0,
                             None, ctypes.byref(ctx))
     assert rc == nb.NB_E_WORKSPACE and not ctx.value
-    rc = nb.lib().nb_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.c_void_p), 16,
+    rc = nb.lib().nb_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.c_void_p), None, 16,
                             ctypes.c_void_p(0x1001), 1 << 20, None, ctypes.byref(ctx))
     assert rc == nb.NB_E_WORKSPACE

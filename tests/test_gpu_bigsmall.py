@@ -1,0 +1,123 @@
+"""GPU parity of the big/small split (Sec. 2.1: only the first nbig[s] bodies
+of a system are gravity sources; small bodies are massless and two small
+bodies never interact) against the oracle with the same split."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from gpu_common import (U, accel_error, ctx_for, enc_compare, nbig_of, oracle_dh, pair_scale,
+                        rel_rows, systems)
+
+pytestmark = pytest.mark.gpu
+
+nb = pytest.importorskip("paper_2601_19654_amd.nb")
+
+
+def _ragged():
+    """Systems with nbig = N, a few, 0, and a tile-straddling count."""
+    sizes = [50, 300, 1, 700, 40]
+    nbig = [50, 7, 0, 65, 0]
+    w = workloads.batch(sizes, cfg_id=12)
+    m = w.m.copy()
+    for s, lo, hi in systems(w):
+        m[lo + nbig[s]:hi] = 0.0
+    w.m = m
+    w.nbig = np.array(nbig, np.int32)
+    return w
+
+
+CASES = {
+    "disk_20x3000": lambda: workloads.bigsmall(20, 3000),
+    "ring_16x2000": lambda: workloads.bigsmall(16, 2000, a_lo=0.97, a_hi=1.03, m_big=3e-6),
+    "ragged": _ragged,
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def case(request):
+    w = CASES[request.param]()
+    return request.param, w, oracle_dh(w)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_force(case, mode):
+    name, w, (Q, V, rc, a_ref) = case
+    c = ctx_for(w, mode=mode)
+    a = c.accel()
+    bar = 1e-12 if mode == 0 else 4e-6
+    for s, lo, hi in systems(w):
+        if nbig_of(w, s) == 0 or hi - lo < 2:
+            assert np.all(a[lo:hi] == 0.0), (name, s)
+            continue
+        A = pair_scale(w.m[lo:hi], Q[lo:hi], w.G)
+        err = accel_error(a[lo:hi], a_ref[lo:hi], A)
+        assert err <= bar, (name, s, err)
+
+
+@pytest.mark.parametrize("algo", [1, 2])
+def test_encounters(case, algo):
+    name, w, (Q, V, rc, a_ref) = case
+    c = ctx_for(w, enc_algo=algo)
+    c.drift(w.dt)
+    e = c.encounters()
+    x1, v1 = c.download(nb.NB_DH)
+    total = 0
+    for s, lo, hi in systems(w):
+        if hi == lo:
+            continue
+        Q1, V1, _ = oracle.drift(w.G * w.m0[s], w.dt, Q[lo:hi], V[lo:hi])
+        ref = oracle.encounters(w.dt, Q[lo:hi], V[lo:hi], Q1, V1, rc[lo:hi], nbig=nbig_of(w, s))
+        gpu = [(i - lo, j - lo) for i, j in zip(e.ice.tolist(), e.jce.tolist()) if lo <= i < hi]
+        assert not enc_compare(gpu, zip(ref["ice"].tolist(), ref["jce"].tolist()), ref["tie"]), (name, s)
+        total += ref["nce"]
+        # no pair of two small bodies is ever reported
+        assert all(i < nbig_of(w, s) for i, _ in gpu)
+    if name == "ring_16x2000":
+        assert total > 0
+
+
+@pytest.mark.parametrize("mode,step_algo,resolve", [(0, 1, 0), (1, 1, 0), (0, 2, 0), (0, 1, 1)])
+def test_steps_match_oracle(case, mode, step_algo, resolve):
+    name, w, _ = case
+    k = 5
+    c = ctx_for(w, mode=mode, step_algo=step_algo, resolve=resolve)
+    stats = c.step(w.dt, k)
+    x, v = c.download(nb.NB_DH)
+    st = oracle.State.from_workload(w)
+    total = 0
+    for _ in range(k):
+        st.step(w.dt, full=bool(resolve))
+        total += sum(e[0] for e in st.enc)
+    tol = 1e-11 if mode == 0 else 1e-7
+    if resolve:
+        st14 = oracle.State.from_workload(w)
+        for _ in range(k):
+            st14.step(w.dt, full=True, tol=1e-14)
+        tol = 3 * (rel_rows(st.Q, st14.Q) + tol)
+    assert rel_rows(x, st.Q) <= tol, (name, rel_rows(x, st.Q), tol)
+    assert rel_rows(v, st.V) <= tol * 10, (name, rel_rows(v, st.V))
+    if mode == 0:
+        assert stats["total_nce"] == total
+
+
+def test_big_bodies_ignore_small_ones():
+    w = workloads.bigsmall(20, 3000)
+    big = workloads.Workload("big", np.array([0, 20], np.int32), w.m0, w.m[:20], w.x[:20], w.v[:20], w.dt, 10)
+    c1 = ctx_for(w)
+    c2 = ctx_for(big)
+    c1.step(w.dt, 10)
+    c2.step(w.dt, 10)
+    x1, v1 = c1.download(nb.NB_DH)
+    x2, v2 = c2.download(nb.NB_DH)
+    assert rel_rows(x1[:20], x2) <= 1e-13 and rel_rows(v1[:20], v2) <= 1e-12
+
+
+def test_upload_rejects_massive_small_body():
+    w = workloads.bigsmall(20, 300)
+    m = w.m.copy()
+    m[25] = 1e-12
+    c = nb.Context(w.off, nb.default_params(G=w.G), device="cuda:0", nbig=w.nbig)
+    with pytest.raises(nb.NbError) as e:
+        c.upload(w.m0, m, w.x, w.v)
+    assert e.value.code == nb.NB_E_INVALID

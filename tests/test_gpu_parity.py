@@ -215,11 +215,11 @@ def test_diagnostics(case):
 
 
 # ---------------------------------------------------------------- full steps
-@pytest.mark.parametrize("mode,algo", [(0, 1), (1, 1), (0, 2)])
-def test_steps_match_oracle(case, mode, algo):
+@pytest.mark.parametrize("mode,algo,step_algo", [(0, 1, 1), (1, 1, 1), (0, 2, 1), (0, 0, 2)])
+def test_steps_match_oracle(case, mode, algo, step_algo):
     name, w, _ = case
     k = 5
-    c = ctx_for(w, mode=mode, enc_algo=algo)
+    c = ctx_for(w, mode=mode, enc_algo=algo, step_algo=step_algo)
     st = oracle.State.from_workload(w)
     stats = c.step(w.dt, k)
     total = 0
@@ -237,9 +237,10 @@ def test_steps_match_oracle(case, mode, algo):
         assert sorted(zip(e.ice.tolist(), e.jce.tolist())) == sorted(ref)
 
 
-def test_step_with_drag():
+@pytest.mark.parametrize("step_algo", [1, 2])
+def test_step_with_drag(step_algo):
     w = workloads.c2(400)
-    c = ctx_for(w)
+    c = ctx_for(w, step_algo=step_algo)
     st = oracle.State.from_workload(w)
     c.step(w.dt, 3)
     for _ in range(3):
@@ -249,11 +250,32 @@ def test_step_with_drag():
     assert rel_rows(v, st.V) <= 1e-10
 
 
-def test_graph_replays_match_direct_steps():
+def test_step_launches_agree():
+    """The per-phase launches and the persistent launch follow the same step
+    with different summation orders: equal to rounding over 40 steps, same
+    encounter statistics."""
+    w = workloads.batch([5, 300, 1700, 64, 1, 2048, 900])
+    outs = []
+    for step_algo in (1, 2):
+        c = ctx_for(w, step_algo=step_algo)
+        st = c.step(w.dt, 40)
+        x, v = c.download(nb.NB_DH)
+        e = c.last_encounters()
+        outs.append((x, v, st, e))
+        c.close()
+    assert rel_rows(outs[0][0], outs[1][0]) <= 1e-11
+    assert rel_rows(outs[0][1], outs[1][1]) <= 1e-10
+    assert outs[0][2]["total_nce"] == outs[1][2]["total_nce"]
+    assert outs[0][2]["max_nce"] == outs[1][2]["max_nce"]
+    assert np.array_equal(outs[0][3].ice, outs[1][3].ice) and np.array_equal(outs[0][3].jce, outs[1][3].jce)
+
+
+@pytest.mark.parametrize("step_algo", [1, 2])
+def test_graph_replays_match_direct_steps(step_algo):
     """nb_step replays a captured graph; chunks of steps must equal one call."""
     w = workloads.batch([300, 700, 41])
-    a = ctx_for(w)
-    b = ctx_for(w)
+    a = ctx_for(w, step_algo=step_algo)
+    b = ctx_for(w, step_algo=step_algo)
     a.step(w.dt, 20)
     for _ in range(20):
         b.step(w.dt, 1)
@@ -262,14 +284,36 @@ def test_graph_replays_match_direct_steps():
     assert np.array_equal(xa, xb) and np.array_equal(va, vb)
 
 
-def test_bitwise_determinism():
+@pytest.mark.parametrize("enc_algo", [1, 2])
+def test_bitwise_determinism(enc_algo):
     w = workloads.ring(1200, m=3e-8)
     outs = []
     for _ in range(2):
-        c = ctx_for(w, mode=nb.NB_FP32C)
+        c = ctx_for(w, mode=nb.NB_FP32C, enc_algo=enc_algo)
         c.step(w.dt, 4)
         outs.append((*c.download(nb.NB_DH), c.accel(), c.last_encounters().ice))
         c.close()
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)
+
+
+def test_overlapped_encounter_branch_matches_serial_steps():
+    """With the sorted encounter check, the test part runs on a second stream
+    beside S(h) and the force (graph branches); a context on the null stream
+    runs every phase in order on one stream.  Same state, same lists, same
+    statistics after 21 steps (graph replays plus a direct remainder)."""
+    import torch
+    w = workloads.ring(2000, m=3e-8)
+    p = nb.default_params(G=w.G, enc_algo=2)
+    serial = nb.Context(w.off, p, device="cuda:0", stream=torch.cuda.default_stream(torch.device("cuda:0")))
+    serial.upload(w.m0, w.m, w.x, w.v)
+    forked = ctx_for(w, enc_algo=2)
+    outs = []
+    for c in (serial, forked):
+        st = c.step(w.dt, 21)
+        e = c.last_encounters()
+        outs.append((*c.download(nb.NB_DH), e.ice, e.jce, st["total_nce"], st["max_nce"]))
+    assert outs[1][4] > 0
     for u, v in zip(*outs):
         assert np.array_equal(u, v)
 
@@ -332,3 +376,93 @@ def test_device_pointer_upload_and_download():
     torch.cuda.synchronize()
     assert np.array_equal(xd.cpu().numpy().T, w.x)
     assert rel_rows(vd.cpu().numpy().T, w.v) <= 8 * U
+
+
+# ---------------------------------------------------------------- full hybrid method
+def _oracle_full(w, steps, tol):
+    st = oracle.State.from_workload(w)
+    groups = bodies = 0
+    for _ in range(steps):
+        st.step(w.dt, full=True, tol=tol)
+        groups += st.ngroups
+        bodies += int(np.sum(st.groups >= 0))
+    return st, groups, bodies
+
+
+FULL_CASES = {
+    "ring_n700": lambda: workloads.ring(700, m=3e-8),
+    "batch_ragged": lambda: workloads.batch([1, 2, 3, 17, 0, 257, 600, 1031]),
+    "ring_batch": lambda: workloads.batch([300, 5, 450], cfg_id=8, a_lo=0.98, a_hi=1.02),
+}
+
+
+@pytest.mark.parametrize("name", list(FULL_CASES))
+@pytest.mark.parametrize("mode", [0, 1])
+def test_full_steps_match_oracle(name, mode):
+    """nb_step with resolve = 1 against the oracle's full step over 5 steps.
+    Bar: the resolver's own global error (oracle at tol 1e-12 against 1e-14)
+    plus the hot-path bar of the mode (1e-11 FP64, 1e-7 FP32C)."""
+    w = FULL_CASES[name]()
+    k = 5
+    print(f"[full] {name} mode={mode}", flush=True)
+    c = ctx_for(w, mode=mode, resolve=1)
+    stats = c.step(w.dt, k)
+    x, v = c.download(nb.NB_DH)
+    st, groups, bodies = _oracle_full(w, k, 1e-12)
+    st14, _, _ = _oracle_full(w, k, 1e-14)
+    hot = 1e-11 if mode == 0 else 1e-7
+    eq = rel_rows(st.Q, st14.Q) + hot
+    ev = rel_rows(st.V, st14.V) + 10 * hot
+    assert rel_rows(x, st.Q) <= 3 * eq, (name, rel_rows(x, st.Q), eq)
+    assert rel_rows(v, st.V) <= 3 * ev, (name, rel_rows(v, st.V), ev)
+    assert stats["bs_fail"] == 0
+    if mode == 0:
+        assert stats["resolved_groups"] == groups and stats["resolved_bodies"] == bodies
+    if name != "batch_ragged":
+        assert groups > 0
+
+
+def test_full_steps_differ_from_hot_path_and_are_deterministic():
+    w = FULL_CASES["ring_n700"]()
+    outs = []
+    for resolve in (1, 1, 0):
+        c = ctx_for(w, resolve=resolve)
+        st = c.step(w.dt, 5)
+        outs.append((c.download(nb.NB_DH), st))
+        c.close()
+    (x1, v1), s1 = outs[0]
+    (x2, v2), s2 = outs[1]
+    (x0, v0), s0 = outs[2]
+    assert np.array_equal(x1, x2) and np.array_equal(v1, v2)
+    assert s1["resolved_groups"] > 0 and s0["resolved_groups"] == 0
+    assert rel_rows(x1, x0) > 1e-9
+
+
+def test_full_mode_rejects_persistent_launch():
+    w = workloads.c1(100)
+    p = nb.default_params(G=w.G, resolve=1, step_algo=2)
+    with pytest.raises(nb.NbError):
+        nb.Context(w.off, p, device="cuda:0")
+
+
+def test_full_mode_resolves_a_close_encounter():
+    """Two bodies inside each other's changeover zone: the GPU full step and
+    the oracle's full step agree through the encounter (20 steps)."""
+    G = workloads.G_AU_MSUN_YR
+    m = np.array([3e-6, 1e-7])
+
+    def circ(r, th):
+        vv = np.sqrt(G / r)
+        return [r * np.cos(th), r * np.sin(th), 0.0], [-vv * np.sin(th), vv * np.cos(th), 0.0]
+    xa, va = circ(1.0, 0.0)
+    xb, vb = circ(1.02, 0.06)
+    w = workloads.Workload("pair", np.array([0, 2], np.int32), np.array([1.0]), m, np.array([xa, xb]),
+                           np.array([va, vb]), 0.02, 20)
+    c = ctx_for(w, resolve=1)
+    stats = c.step(w.dt, 20)
+    x, v = c.download(nb.NB_DH)
+    st, groups, _ = _oracle_full(w, 20, 1e-12)
+    st14, _, _ = _oracle_full(w, 20, 1e-14)
+    assert groups >= 10 and stats["resolved_groups"] == groups
+    eq = rel_rows(st.Q, st14.Q) + 1e-11
+    assert rel_rows(x, st.Q) <= 3 * eq, (rel_rows(x, st.Q), eq)

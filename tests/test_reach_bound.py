@@ -131,3 +131,74 @@ def test_tile_pair_bound_never_drops_a_flagged_pair():
                     assert ok, trial
                 checked += 1
     assert culled > 50 and checked == 400 * 36
+
+
+def relative_bound_culls(bi, bj, rci, rcj, dt):
+    """The pair filter on relative chords: with dM the midpoint difference, dc
+    the chord difference, E = eps_i + eps_j and b = 3E/4 + max(rc_i, rc_j), a pair
+    with |dM|^2 > 2 |dc|^2 + 2 b^2 cannot be flagged.  (Hermite data = relative
+    chord quadratic, >= (D - |dc|/2)^2, plus deviations weighted by
+    |h10| + |h11| <= 1/4; D > |dc| + 3E/4 + rc suffices, and
+    (|dc| + b)^2 <= 2 |dc|^2 + 2 b^2.)"""
+    def parts(q0, v0, q1, v1):
+        c = q1 - q0
+        eps = max(np.linalg.norm(dt * v0 - c), np.linalg.norm(dt * v1 - c))
+        return 0.5 * (q0 + q1), c, eps
+    Mi, ci, ei = parts(*bi)
+    Mj, cj, ej = parts(*bj)
+    D2 = np.sum((Mj - Mi) ** 2)
+    C2 = np.sum((cj - ci) ** 2)
+    b = 0.75 * (ei + ej) + max(rci, rcj)
+    return D2 > 2 * C2 + 2 * b * b
+
+
+def test_relative_chord_bound_holds_just_outside():
+    rng = np.random.default_rng(4242)
+    for trial in range(20000):
+        dt = rng.uniform(0.01, 2.0) * rng.choice([-1, 1])
+        bi = _body(rng, rng.uniform(0.01, 1))
+        bj = list(_body(rng, rng.uniform(0.01, 1)))
+        # often co-moving: j's chord close to i's
+        if rng.uniform() < 0.5:
+            bj[2] = bj[0] + (bi[2] - bi[0]) + rng.normal(size=3) * 1e-3
+        rci, rcj = rng.uniform(0, 0.5, 2)
+        # put j's midpoint just beyond the filter radius along a random direction
+        c_i, c_j = bi[2] - bi[0], bj[2] - bj[0]
+        eps = lambda b: max(np.linalg.norm(dt * b[1] - (b[2] - b[0])), np.linalg.norm(dt * b[3] - (b[2] - b[0])))
+        b = 0.75 * (eps(bi) + eps(bj)) + max(rci, rcj)
+        radius = np.sqrt(2 * np.sum((c_j - c_i) ** 2) + 2 * b * b) * (1 + rng.uniform(1e-9, 0.05))
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        Mi = 0.5 * (bi[0] + bi[2])
+        shift = Mi + u * radius - 0.5 * (bj[0] + bj[2])
+        bj[0] = bj[0] + shift
+        bj[2] = bj[2] + shift
+        assert relative_bound_culls(bi, bj, rci, rcj, dt)
+        d2 = oracle.pair_min_d2(dt, *bi, *bj)
+        assert d2 > max(rci, rcj) ** 2, (trial, d2)
+
+
+def test_relative_chord_bound_on_ring_arcs():
+    """Every flagged pair of a dense ring passes the relative filter, and the
+    filter keeps far fewer pairs than the per-body reach."""
+    w = workloads.ring(400, m=1e-7)
+    Q0, V0 = oracle.helio_to_dh(1.0, w.m, w.x, w.v)
+    rc = oracle.rcrit(1.0, w.m, Q0)
+    for dt in (0.04, 0.2):
+        Q1, V1, _ = oracle.drift(w.G, dt, Q0, V0)
+        out = oracle.encounters(dt, Q0, V0, Q1, V1, rc)
+        for i, j in zip(out["ice"], out["jce"]):
+            assert not relative_bound_culls((Q0[i], V0[i], Q1[i], V1[i]), (Q0[j], V0[j], Q1[j], V1[j]),
+                                            rc[i], rc[j], dt)
+        if dt != 0.04:
+            continue                # at dt = 0.2 a chord spans the ring: both keep every pair
+        kept_rel = kept_reach = 0
+        R = np.empty(400); M = np.empty((400, 3))
+        for i in range(400):
+            R[i], M[i] = reach(Q0[i], V0[i], Q1[i], V1[i], rc[i], dt)
+        for i in range(0, 400, 7):
+            for j in range(i + 1, 400):
+                kept_reach += np.linalg.norm(M[j] - M[i]) <= R[i] + R[j]
+                kept_rel += not relative_bound_culls((Q0[i], V0[i], Q1[i], V1[i]), (Q0[j], V0[j], Q1[j], V1[j]),
+                                                     rc[i], rc[j], dt)
+        assert kept_rel < 0.5 * kept_reach, (kept_rel, kept_reach)

@@ -26,6 +26,12 @@ orbital distributions of the five benchmark configurations:
   c5  star + 131072 bodies of 1e-11 in a 0.9-1.1 AU ring, e ~ Rayleigh(0.005),
       i ~ Rayleigh(0.0025); dt = 0.04 yr, 2000 steps.
 
+Big and small bodies (Sec. 2.1: only big bodies are gravity sources; small
+bodies are massless planetesimals; production runs have N_big of 1-100 and
+N_small of 1e4-1e6): ``bigsmall`` draws N_big Mars-mass embryos (3.2e-7) and
+N_small massless bodies, both with a ~ U[1,5], e ~ Rayleigh(0.01),
+i ~ Rayleigh(0.005); dt = 0.05 yr.  The big bodies come first in each system.
+
 Random stream: numpy ``default_rng(SeedSequence(20260119, spawn_key=(cfg, s)))``
 per system s; draw order m, a, e, i, Omega, omega, M as length-N vectors.
 Elements are converted with mu_i = G (m0 + m_i).
@@ -65,6 +71,7 @@ class Workload:
     G: float = G_AU_MSUN_YR
     drag: bool = False
     meta: dict = field(default_factory=dict)
+    nbig: np.ndarray | None = None   # per system: the first nbig[s] bodies are big (None: all)
 
     @property
     def nsys(self) -> int:
@@ -78,9 +85,11 @@ class Workload:
         return np.diff(self.off)
 
     def pairs(self) -> int:
-        """Ordered pair interactions per force evaluation, sum of N_s (N_s - 1)."""
+        """Ordered pair interactions per force evaluation: sum of N_s (N_s - 1),
+        or with big bodies only as sources, sum of nbig_s (N_s - 1)."""
         n = self.sizes().astype(np.int64)
-        return int(np.sum(n * (n - 1)))
+        nb = n if self.nbig is None else np.asarray(self.nbig, dtype=np.int64)
+        return int(np.sum(nb * np.maximum(n - 1, 0)))
 
 
 def _rng(cfg_id: int, sys_index: int) -> np.random.Generator:
@@ -208,6 +217,24 @@ def batch(sizes, cfg_id: int = 6, a_lo=1.0, a_hi=3.0) -> Workload:
     return _pack(f"batch{list(sizes)}", systems, 0.05, 10)
 
 
+M_MARS = 3.227151e-7       # Msun
+
+
+def bigsmall(n_big: int = 100, n_small: int = 1 << 20, nsys: int = 1, cfg_id: int = 9,
+             a_lo: float = 1.0, a_hi: float = 5.0, m_big: float = M_MARS) -> Workload:
+    """Big embryos plus massless small bodies (nsys identical-size systems)."""
+    systems, nbig = [], []
+    for s in range(nsys):
+        rng = _rng(cfg_id, s)
+        mb, xb, vb = _disk(rng, n_big, m_big, a_lo, a_hi, 0.01, 0.005)
+        ms, xs, vs = _disk(rng, n_small, 0.0, a_lo, a_hi, 0.01, 0.005)
+        systems.append((1.0, np.concatenate([mb, ms]), np.concatenate([xb, xs]), np.concatenate([vb, vs])))
+        nbig.append(n_big)
+    w = _pack(f"bigsmall{n_big}x{n_small}", systems, 0.05, 1000)
+    w.nbig = np.array(nbig, dtype=np.int32)
+    return w
+
+
 def ring(n: int, seed_sys: int = 0, m: float = 1e-11, a_lo=0.9, a_hi=1.1) -> Workload:
     """A c5-like dense ring of any size (encounter-rich tests)."""
     rng = _rng(5, 1000 + seed_sys)
@@ -216,4 +243,4 @@ def ring(n: int, seed_sys: int = 0, m: float = 1e-11, a_lo=0.9, a_hi=1.1) -> Wor
 
 
 def by_name(name: str) -> Workload:
-    return {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}[name]()
+    return {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5, "bigsmall": bigsmall}[name]()
