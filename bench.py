@@ -69,8 +69,7 @@ def run_mode(w, mode: str, steps: int, warmup: int, torch, nb, resolve: bool = F
                           resolve=int(resolve))
     ctx = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", nbig=w.nbig)
     tiles = {"source": ctx.tiles, "force_r": ctx.params.force_r, "force_jchunk": ctx.params.force_jchunk,
-             "enc_jchunk": ctx.params.enc_jchunk, "enc_algo": ctx.params.enc_algo,
-             "step_algo": ctx.params.step_algo}
+             "enc_jchunk": ctx.params.enc_jchunk, **ctx.choices()}
     ctx.upload(w.m0, w.m, w.x, w.v)
     pairs = w.pairs()
     # warmup (untimed), also builds the step graph
@@ -101,15 +100,23 @@ def run_mode(w, mode: str, steps: int, warmup: int, torch, nb, resolve: bool = F
     }
 
 
-def roofline(mode, pairs, force_ms, workload="c3"):
+KERNEL_SUFFIX = {1: "", 2: "_sym", 3: "_few"}
+
+
+def roofline(mode, pairs, force_ms, workload="c3", force_algo=1):
+    """Algorithmic flops (20 per ordered pair interaction, N_s (N_s - 1) or
+    N_s nbig_s per system) over the measured force-kernel duration.  The
+    symmetric kernel evaluates each unordered pair once for both bodies, so it
+    delivers the same interactions with half the pair evaluations."""
     flops = FLOPS_PER_PAIR * pairs
     achieved = flops / (force_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[mode]
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": traffic_from_profiles(mode, workload),
-            "kernel": f"k_force{'32c' if mode == 'fp32c' else '64'}",
+            "kernel": f"k_force{'32c' if mode == 'fp32c' else '64'}{KERNEL_SUFFIX.get(force_algo, '')}",
             "kernel_ms": round(force_ms, 4), "flops_per_launch": flops,
-            "flop_convention": f"{FLOPS_PER_PAIR} flops per ordered pair"}
+            "flop_convention": f"{FLOPS_PER_PAIR} flops per ordered pair interaction"
+                               + (" (each unordered pair evaluated once)" if force_algo == 2 else "")}
 
 
 def accel_error(w, a_gpu, Q, sample=64, seed=1):
@@ -269,9 +276,10 @@ def main():
                      "nce_per_step": rr["stats"]["total_nce"] / args.steps,
                      "resolved_groups_per_step": rr["stats"]["resolved_groups"] / args.steps,
                      "accel_err_vs_oracle": accel_error(w, rr["a"], rr["Q"])}
-    out["roofline"] = roofline(head, pairs, r["force_ms"], args.workload)
+    out["roofline"] = roofline(head, pairs, r["force_ms"], args.workload, r["tiles"]["force_algo"])
     if "fp64" in res and head != "fp64":
-        out["roofline_fp64"] = roofline("fp64", pairs, res["fp64"]["force_ms"], args.workload)
+        out["roofline_fp64"] = roofline("fp64", pairs, res["fp64"]["force_ms"], args.workload,
+                                        res["fp64"]["tiles"]["force_algo"])
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w)
     out["kernel_source_sha256_16"] = kernel_hash()
     print(json.dumps(out), flush=True)

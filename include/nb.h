@@ -103,7 +103,9 @@ typedef struct nb_params {
                              hybrid method, every flagged group resolved on the host by
                              Bulirsch-Stoer inside each nb_step (Sec. 2.1.1, Sec. 3.2) */
     int32_t resolve_threads; /* host threads of the resolver (0: up to 16, by the host) */
-    int32_t reserved;     /* must be 0 */
+    int32_t force_algo;   /* force: 0 automatic, 1 every ordered pair (i, j) evaluated,
+                             2 each unordered pair once and applied to both bodies (tile pairs;
+                             every body big); automatic takes 2 where it applies */
     double  bs_tol;       /* Bulirsch-Stoer relative tolerance (0: 1e-12) */
 } nb_params;
 
@@ -115,7 +117,8 @@ typedef struct nb_stats {
     int32_t max_nce;        /* largest per-step count */
     int32_t overflow_steps; /* steps whose count exceeded the list capacity */
     int64_t kepler_fail;    /* failed Kepler solves summed over the steps */
-    int64_t near_pairs;     /* FP32C: pairs evaluated in FP64 near the changeover zone */
+    int64_t near_pairs;     /* pair evaluations inside the changeover zone (in FP64 for FP32C);
+                               with symmetric tile pairs one evaluation serves both bodies */
     int64_t resolved_groups; /* resolve: groups integrated by Bulirsch-Stoer, summed */
     int64_t resolved_bodies; /* resolve: their members, summed */
     int32_t max_group;      /* resolve: largest group */
@@ -257,6 +260,12 @@ int nb_get_rcrit(nb_ctx *ctx, double *rc, int where);
  * and NB_K_STEP advance it by dt per launch; NB_K_ENCOUNTER overwrites the last
  * encounter list (with the dt of the last drift or step). */
 int nb_time_kernel(nb_ctx *ctx, int which, int reps, double dt, double *ms_per_launch);
+
+/* The algorithms the context resolved its automatic choices to (any pointer may
+ * be NULL): force 1 (ordered pairs), 2 (symmetric tile pairs) or 3 (few-source
+ * kernels); encounter check 1 (direct) or 2 (sorted tiles); step launch 1
+ * (per phase) or 2 (persistent). */
+int nb_get_choices(const nb_ctx *ctx, int32_t *force_algo, int32_t *enc_algo, int32_t *step_algo);
 
 /* Release the context (not the workspace). */
 int nb_destroy(nb_ctx *ctx);

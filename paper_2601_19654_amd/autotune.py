@@ -69,21 +69,25 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
     """Time every candidate on workload w; returns the best entry (not saved)."""
     from . import nb
     res_force, res_enc = {}, {}
-    for r in FORCE_R:
-        for j in FORCE_J:
-            if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
-                continue
-            p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j)
-            c = nb.Context(w.off, p, enc_cap=1 << 16, device="cuda:0", tuned=False, nbig=w.nbig)
-            c.upload(w.m0, w.m, w.x, w.v)
-            # ranked by the whole force evaluation: more source chunks mean more
-            # split partials for the finalize pass to sum
-            ms = c.time_kernel(nb.NB_K_FORCE_EVAL, reps=reps)
-            res_force[(r, j)] = ms
-            if verbose:
-                print(f"[autotune] {mode} force evaluation r={r} j={j}: {ms:.4f} ms", file=sys.stderr,
-                      flush=True)
-            c.close()
+    all_big = w.nbig is None or np.all(np.asarray(w.nbig) == np.diff(w.off))
+    for fa in ((1, 2) if all_big else (1,)):
+        for r in FORCE_R:
+            # the symmetric tile pairs have no source-chunk parameter
+            for j in (FORCE_J if fa == 1 else (1024,)):
+                if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
+                    continue
+                p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j,
+                                      force_algo=fa)
+                c = nb.Context(w.off, p, enc_cap=1 << 16, device="cuda:0", tuned=False, nbig=w.nbig)
+                c.upload(w.m0, w.m, w.x, w.v)
+                # ranked by the whole force evaluation: more source chunks mean more
+                # split partials for the finalize pass to sum
+                ms = c.time_kernel(nb.NB_K_FORCE_EVAL, reps=reps)
+                res_force[(fa, r, j)] = ms
+                if verbose:
+                    print(f"[autotune] {mode} force evaluation algo={fa} r={r} j={j}: {ms:.4f} ms",
+                          file=sys.stderr, flush=True)
+                c.close()
     for j in ENC_J + (0,):
         if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
             continue
@@ -99,13 +103,14 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
             print(f"[autotune] {mode} encounter {'sorted tiles' if j == 0 else f'j={j}'}: {ms:.4f} ms",
                   file=sys.stderr, flush=True)
         c.close()
-    (r, j), fms = min(res_force.items(), key=lambda kv: kv[1])
+    (fa, r, j), fms = min(res_force.items(), key=lambda kv: kv[1])
     ej, ems = min(res_enc.items(), key=lambda kv: kv[1])
     # whole-step launch: per-phase launches (tuned tiles) vs the persistent launch
     res_step = {}
     for sa in ((1, 2) if mode == "fp64" and int(np.diff(w.off).max()) <= 8192 else (1,)):
         p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j,
-                              enc_jchunk=ej if ej else 1024, enc_algo=2 if ej == 0 else 1, step_algo=sa)
+                              force_algo=fa, enc_jchunk=ej if ej else 1024, enc_algo=2 if ej == 0 else 1,
+                              step_algo=sa)
         c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False, nbig=w.nbig)
         c.upload(w.m0, w.m, w.x, w.v)
         c.step(w.dt, 3, allow=(nb.NB_E_CAPACITY, nb.NB_E_KEPLER))
@@ -114,11 +119,12 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
             print(f"[autotune] {mode} step launch {sa}: {res_step[sa]:.4f} ms", file=sys.stderr, flush=True)
         c.close()
     sa, sms = min(res_step.items(), key=lambda kv: kv[1])
-    return {"force_r": r, "force_jchunk": j, "enc_jchunk": ej if ej else 1024, "enc_algo": 2 if ej == 0 else 1,
+    return {"force_algo": fa, "force_r": r, "force_jchunk": j, "enc_jchunk": ej if ej else 1024,
+            "enc_algo": 2 if ej == 0 else 1,
             "step_algo": sa, "step_ms": round(sms, 5), "step_candidates": {str(k): round(v, 5) for k, v in res_step.items()},
             "force_ms": round(fms, 5),
             "encounter_ms": round(ems, 5), "workload": w.name, "tuned_at": time.strftime("%Y-%m-%d"),
-            "force_candidates": {f"r{a}_j{b}": round(v, 5) for (a, b), v in res_force.items()},
+            "force_candidates": {f"a{f}_r{a}_j{b}": round(v, 5) for (f, a, b), v in res_force.items()},
             "encounter_candidates": {(f"j{a}" if a else "sorted"): round(v, 5) for a, v in res_enc.items()}}
 
 
@@ -139,7 +145,7 @@ def main():
             best = tune(w, mode, reps=args.reps)
             k = key(mode, w.off, a, w.nbig)
             cache[k] = best
-            print(f"[autotune] {k} -> r={best['force_r']} j={best['force_jchunk']} "
+            print(f"[autotune] {k} -> force_algo={best['force_algo']} r={best['force_r']} j={best['force_jchunk']} "
                   f"enc_algo={best['enc_algo']} enc_j={best['enc_jchunk']} step_algo={best['step_algo']} "
                   f"({best['force_ms']:.4f} / {best['encounter_ms']:.4f} ms)",
                   file=sys.stderr, flush=True)

@@ -81,6 +81,9 @@ struct Dev {
     double *ax, *ay, *az, *rc;
     double *tile_rc2;     // per O(N) block: largest rc^2 of its bodies (set with rc)
     double *q0x, *q0y, *q0z, *v0x, *v0y, *v0z;
+    // after a drift: copies of Q1, V1 and the critical radii for the encounter
+    // check, so that it can run beside the next S(h), force and kick
+    double *q1x, *q1y, *q1z, *v1x, *v1y, *v1z, *rc1;
     float4 *pk;           // FP32C source records: 2 per body {xhi,yhi,zhi,m},{xlo,ylo,zlo,rc2}
     double4 *mr;          // per body after a drift: chord midpoint (x,y,z) and encounter reach R
     double4 *cr;          // per body after a drift: chord Q1 - Q0 and 3/4 eps (widened)
@@ -121,11 +124,13 @@ struct Dev {
     int *step_nce; int step_chunk;   // flagged pairs per step of one launch
     int *flag;            // validation flags (4 ints)
     double *stage;        // 6 x ntot staging for host transfers / transforms
-    // close-encounter resolver (resolve = 1): member indices and their records
-    int *res_idx; double *res_buf; int res_cap;   // res_buf: 10 doubles per member
+    // close-encounter resolver (resolve = 1): records of both ends of up to res_cap
+    // listed pairs (20 doubles per pair) and result rows (7 doubles per member)
+    double *res_buf; double *res_rows; int res_cap;
     int *nbig;            // per system: bodies [off[s], off[s] + nbig[s]) are big
     int force_few;        // every system has at most 256 big bodies and the targets are many:
                           // the few-source force kernels
+    int force_sym;        // every body big: work items are unordered tile pairs
 };
 
 struct Params {
@@ -135,6 +140,7 @@ struct Params {
     int force_r, force_j, enc_j;
     int enc_algo;         // 1: all pairs with the reach prefilter, 2: sorted tiles
     int step_algo;        // 1: per-phase launches, 2: persistent per-system launch
+    int force_algo;       // 0 automatic, 1 ordered pairs, 2 symmetric tile pairs
     int resolve;          // 1: resolve flagged groups on the host every step
     int resolve_threads;
     double bs_tol;
@@ -160,9 +166,9 @@ hipError_t launch_step_stats(const Dev &d, int nsteps, hipStream_t s);
 hipError_t launch_enc_sort(const Dev &d, int accumulate, hipStream_t s);
 hipError_t launch_enc_gather(const Dev &d, hipStream_t s);
 hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s);
-// resolver transfers: members res_idx[0..k) -> res_buf (m0, m, rc, Q0, V0, pad)
-// and back from res_buf rows of 6 (Q, V; rows that are not finite are skipped)
-hipError_t launch_gather_members(const Dev &d, int k, hipStream_t s);
+// resolver transfers: both ends of listed pairs [k0, k0 + n) -> res_buf (per end
+// m0, m, rc, Q0, V0, index); res_rows (index, Q, V; rows not finite skipped) -> state
+hipError_t launch_gather_pairs(const Dev &d, int k0, int n, hipStream_t s);
 hipError_t launch_scatter_members(const Dev &d, int k, hipStream_t s);
 
 }  // namespace nb

@@ -527,7 +527,11 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
                         double *__restrict__ v0z, int *__restrict__ kflag, int *__restrict__ ce,
                         DevStats *stats, double *__restrict__ part_out,
                         const double *__restrict__ rc, double4 *__restrict__ mr,
-                        double4 *__restrict__ cr, double *__restrict__ lnr_part)
+                        double4 *__restrict__ cr, double *__restrict__ lnr_part,
+                        double *__restrict__ q1x, double *__restrict__ q1y,
+                        double *__restrict__ q1z, double *__restrict__ v1x,
+                        double *__restrict__ v1y, double *__restrict__ v1z,
+                        double *__restrict__ rc1)
 {
     __shared__ double sh[3 * kBlock];
     double lnr_lo = INFINITY, lnr_hi = -INFINITY;
@@ -575,6 +579,13 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
         vx[i] = u;
         vy[i] = v;
         vz[i] = w;
+        q1x[i] = x;
+        q1y[i] = y;
+        q1z[i] = z;
+        v1x[i] = u;
+        v1y[i] = v;
+        v1z[i] = w;
+        rc1[i] = rc[i];
         kflag[i] = fail ? 1 : 0;
         ce[i] = 0;
         double mi = m[i];
@@ -1087,6 +1098,359 @@ __global__ __launch_bounds__(kBlock) void k_force32c_few(const FWork *__restrict
                 fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = ((double)hz[k] + (double)lz[k]) + nz[k];
             }
         }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        near += __shfl_xor(near, o);
+    if (lane == 0 && near)
+        atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
+}
+
+// Symmetric pairs (every body big): each unordered pair is evaluated once and
+// applied to both bodies, a_i += m_j q d and a_j -= m_i q d with the mass-free
+// weight q = K/r^3 - K'/r^2 (Newtonian q = 1/r^3 refined from the hardware
+// estimate as in m_rinv3).  A work item is a pair of tiles (I <= J) of T = 64 R
+// bodies of one system, owned by one wave: the lanes hold R targets of tile I,
+// tile J sits in the wave's LDS slice together with its accumulators.  At step
+// k of sub-tile t, lane L pairs with source 64 t + ((L + k) mod 64), so the 64
+// lanes touch 64 different sources and update their accumulators without
+// atomics.  Item (I, J) writes tile I's sums to split slot J and tile J's sums
+// to slot I (both to slot I on the diagonal, where only i < j is taken), so
+// every body receives exactly one partial per tile of its system, summed in
+// slot order by the finalize pass.
+__device__ __forceinline__ double rinv3(double r2)
+{
+    const double y0 = __builtin_amdgcn_rsq(r2);
+    const double y2 = y0 * y0;
+    const double e = fma(-r2, y2, 1.0);
+    return (y0 * y2) * fma(1.5, e, 1.0);
+}
+
+template <int R, bool DIAG>
+__device__ __forceinline__ void sym_tile64(const double4 *__restrict__ sj, const double2 *__restrict__ sx,
+                                           double4 *__restrict__ sacc, int lane, double inner,
+                                           const double (&xi)[R], const double (&yi)[R],
+                                           const double (&zi)[R], const double (&mi)[R],
+                                           const double (&rci)[R], const double (&r2i)[R],
+                                           const double (&thr)[R], double (&ax)[R], double (&ay)[R],
+                                           double (&az)[R], int &near)
+{
+#pragma unroll 1
+    for (int t = 0; t < R; ++t) {
+        // Lanes update each other's accumulators from step to step: the next
+        // step's loads must stay after this step's store (LDS operations of a
+        // wave complete in issue order, so program order is enough); sources
+        // are read-only and prefetched one step ahead.
+        int jj = 64 * t + lane;
+        double4 J = sj[jj];
+#pragma unroll 1
+        for (int k = 0; k < 64; ++k) {
+            double4 a = sacc[jj];
+            double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double dx = J.x - xi[r], dy = J.y - yi[r], dz = J.z - zi[r];
+                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                double q = rinv3(r2);
+                if (r2 < thr[r]) {
+                    const double rcj = sx[jj].x;
+                    if (r2 < fmax(r2i[r], fmax(rcj * rcj, DBL_MIN))) {
+                        q = changeover_w(r2, fmax(rci[r], rcj), inner);
+                        ++near;
+                    }
+                }
+                if (DIAG)
+                    q = (64 * r + lane < jj) ? q : 0.0;
+                const double wi = J.w * q, wj = mi[r] * q;
+                ax[r] = fma(wi, dx, ax[r]);
+                ay[r] = fma(wi, dy, ay[r]);
+                az[r] = fma(wi, dz, az[r]);
+                jx = fma(-wj, dx, jx);
+                jy = fma(-wj, dy, jy);
+                jz = fma(-wj, dz, jz);
+            }
+            const int jn = 64 * t + ((lane + k + 1) & 63);
+            const double4 Jn = sj[jn];
+            a.x += jx;
+            a.y += jy;
+            a.z += jz;
+            sacc[jj] = a;
+            __asm__ __volatile__("" ::: "memory");
+            jj = jn;
+            J = Jn;
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict__ work, int nitems,
+                                                        const double *__restrict__ qx,
+                                                        const double *__restrict__ qy,
+                                                        const double *__restrict__ qz,
+                                                        const double *__restrict__ m,
+                                                        const double *__restrict__ rc,
+                                                        const double *__restrict__ tile_rc2,
+                                                        double *__restrict__ fpart, int ntot, int maxs,
+                                                        double inner, DevStats *stats)
+{
+    constexpr int T = 64 * R;
+    __shared__ double4 sj[kWaves][T];       // x, y, z, m of tile J
+    __shared__ double2 sx[kWaves][T];       // rc of tile J
+    __shared__ double4 sacc[kWaves][T];     // tile J's sums
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int near = 0;
+    for (int it = blockIdx.x * kWaves + wv; it < nitems; it += gridDim.x * kWaves) {
+        const FWork wk = work[it];
+        const bool diag = wk.i0 == wk.j0;
+        for (int k = lane; k < T; k += 64) {
+            // sources past the tile end: massless copies of its first body
+            const int j = wk.j0 + (k < wk.nj ? k : 0);
+            sj[wv][k] = make_double4(qx[j], qy[j], qz[j], k < wk.nj ? m[j] : 0.0);
+            sx[wv][k] = make_double2(k < wk.nj ? rc[j] : 0.0, 0.0);
+            sacc[wv][k] = make_double4(0.0, 0.0, 0.0, 0.0);
+        }
+        wave_lds_sync();
+        double xi[R], yi[R], zi[R], mi[R], rci[R], r2i[R], thr[R], ax[R], ay[R], az[R];
+        const double tmax = tile_rc2[wk.rb0];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int li = 64 * r + lane;
+            const bool ok = li < wk.ni;
+            const int i = wk.i0 + (ok ? li : 0);
+            xi[r] = qx[i];
+            yi[r] = qy[i];
+            zi[r] = qz[i];
+            // targets past the tile end are massless: they add nothing to tile J
+            mi[r] = ok ? m[i] : 0.0;
+            rci[r] = rc[i];
+            r2i[r] = fmax(rci[r] * rci[r], DBL_MIN);
+            thr[r] = fmax(r2i[r], tmax);
+            ax[r] = ay[r] = az[r] = 0.0;
+        }
+        if (diag)
+            sym_tile64<R, true>(sj[wv], sx[wv], sacc[wv], lane, inner, xi, yi, zi, mi, rci, r2i, thr,
+                                ax, ay, az, near);
+        else
+            sym_tile64<R, false>(sj[wv], sx[wv], sacc[wv], lane, inner, xi, yi, zi, mi, rci, r2i, thr,
+                                 ax, ay, az, near);
+        wave_lds_sync();
+        // tile I to slot J (on the diagonal together with tile J's sums of the same bodies)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int li = 64 * r + lane;
+            if (li < wk.ni) {
+                double sx_ = ax[r], sy_ = ay[r], sz_ = az[r];
+                if (diag) {
+                    const double4 a = sacc[wv][li];
+                    sx_ += a.x;
+                    sy_ += a.y;
+                    sz_ += a.z;
+                }
+                const int i = wk.i0 + li;
+                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = sx_;
+                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = sy_;
+                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = sz_;
+            }
+        }
+        if (!diag) {
+            // tile J to slot I
+            for (int k = lane; k < wk.nj; k += 64) {
+                const double4 a = sacc[wv][k];
+                const int j = wk.j0 + k;
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = a.x;
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = a.y;
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = a.z;
+            }
+        }
+        wave_lds_sync();
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        near += __shfl_xor(near, o);
+    if (lane == 0 && near)
+        atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
+}
+
+// FP32C form of the symmetric tile pairs: FP32 pair terms from the hi/lo
+// records; tile I's sums in FP32 runs of 32 steps merged by two-sum, tile J's
+// contributions (summed over the R targets in FP32) added in FP64 in LDS;
+// changeover pairs in FP64 from the FP64 state for both bodies.
+template <int R, bool DIAG>
+__device__ __forceinline__ void sym_tile32c(const float4 *__restrict__ sa, const float4 *__restrict__ sb,
+                                            double4 *__restrict__ sacc, int lane, int ni, int nj,
+                                            int j0, double inner, const double *__restrict__ qx,
+                                            const double *__restrict__ qy, const double *__restrict__ qz,
+                                            const double *__restrict__ m, const double *__restrict__ rc,
+                                            const int (&ii)[R], const float (&xh)[R], const float (&yh)[R],
+                                            const float (&zh)[R], const float (&xl)[R], const float (&yl)[R],
+                                            const float (&zl)[R], const float (&mi)[R], const float (&r2i)[R],
+                                            const float (&thr)[R], float (&hx)[R], float (&hy)[R],
+                                            float (&hz)[R], float (&lx)[R], float (&ly)[R], float (&lz)[R],
+                                            double (&nx)[R], double (&ny)[R], double (&nz)[R], int &near)
+{
+#pragma unroll 1
+    for (int t = 0; t < R; ++t) {
+#pragma unroll 1
+        for (int half = 0; half < 2; ++half) {
+            float tx[R], ty[R], tz[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                tx[r] = ty[r] = tz[r] = 0.0f;
+            // see sym_tile64 for the order of the accumulator updates
+            int jj = 64 * t + ((lane + 32 * half) & 63);
+            float4 A = sa[jj], B = sb[jj];
+#pragma unroll 1
+            for (int kk = 0; kk < 32; ++kk) {
+                double4 a = sacc[jj];
+                float jx = 0.0f, jy = 0.0f, jz = 0.0f;
+                double ex_ = 0.0, ey_ = 0.0, ez_ = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool on = !DIAG || (64 * r + lane < jj);
+                    float dx = (A.x - xh[r]) + (B.x - xl[r]);
+                    float dy = (A.y - yh[r]) + (B.y - yl[r]);
+                    float dz = (A.z - zh[r]) + (B.z - zl[r]);
+                    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    float y = __builtin_amdgcn_rsqf(r2);
+                    float q = y * (y * y);
+                    if (r2 < thr[r] && on && jj < nj) {
+                        if (r2 < fmaxf(r2i[r], B.w)) {
+                            // FP64 changeover pair from the FP64 state, both bodies
+                            const int i = ii[r], j = j0 + jj;
+                            const double gx = qx[j] - qx[i], gy = qy[j] - qy[i], gz = qz[j] - qz[i];
+                            const double d2 = fma(gz, gz, fma(gy, gy, gx * gx));
+                            const double wgt = changeover_w(d2, fmax(rc[i], rc[j]), inner);
+                            const double wi = m[j] * wgt;
+                            const double wj = (64 * r + lane < ni ? m[i] : 0.0) * wgt;
+                            nx[r] = fma(wi, gx, nx[r]);
+                            ny[r] = fma(wi, gy, ny[r]);
+                            nz[r] = fma(wi, gz, nz[r]);
+                            ex_ = fma(-wj, gx, ex_);
+                            ey_ = fma(-wj, gy, ey_);
+                            ez_ = fma(-wj, gz, ez_);
+                            q = 0.0f;
+                            ++near;
+                        }
+                    }
+                    q = on ? q : 0.0f;
+                    const float wi = A.w * q, wj = mi[r] * q;
+                    tx[r] = fmaf(wi, dx, tx[r]);
+                    ty[r] = fmaf(wi, dy, ty[r]);
+                    tz[r] = fmaf(wi, dz, tz[r]);
+                    jx = fmaf(-wj, dx, jx);
+                    jy = fmaf(-wj, dy, jy);
+                    jz = fmaf(-wj, dz, jz);
+                }
+                const int jn = 64 * t + ((lane + 32 * half + kk + 1) & 63);
+                const float4 An = sa[jn], Bn = sb[jn];
+                a.x += (double)jx + ex_;
+                a.y += (double)jy + ey_;
+                a.z += (double)jz + ez_;
+                sacc[jj] = a;
+                __asm__ __volatile__("" ::: "memory");
+                jj = jn;
+                A = An;
+                B = Bn;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                two_sum_f(hx[r], lx[r], tx[r]);
+                two_sum_f(hy[r], ly[r], ty[r]);
+                two_sum_f(hz[r], lz[r], tz[r]);
+            }
+        }
+    }
+}
+
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict__ work, int nitems,
+                                                         const float4 *__restrict__ pk,
+                                                         const double *__restrict__ qx,
+                                                         const double *__restrict__ qy,
+                                                         const double *__restrict__ qz,
+                                                         const double *__restrict__ m,
+                                                         const double *__restrict__ rc,
+                                                         const double *__restrict__ tile_rc2,
+                                                         double *__restrict__ fpart, int ntot,
+                                                         int maxs, double inner, DevStats *stats)
+{
+    constexpr int T = 64 * R;
+    __shared__ float4 sa[kWaves][T];
+    __shared__ float4 sb[kWaves][T];
+    __shared__ double4 sacc[kWaves][T];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int near = 0;
+    for (int it = blockIdx.x * kWaves + wv; it < nitems; it += gridDim.x * kWaves) {
+        const FWork wk = work[it];
+        const bool diag = wk.i0 == wk.j0;
+        for (int k = lane; k < T; k += 64) {
+            const int j = wk.j0 + (k < wk.nj ? k : 0);
+            float4 A = pk[2 * (size_t)j], B = pk[2 * (size_t)j + 1];
+            if (k >= wk.nj) {
+                A.w = 0.0f;             // massless copy of the tile's first body
+                B.w = 0.0f;
+            }
+            sa[wv][k] = A;
+            sb[wv][k] = B;
+            sacc[wv][k] = make_double4(0.0, 0.0, 0.0, 0.0);
+        }
+        wave_lds_sync();
+        float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], mi[R], r2i[R], thr[R];
+        float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
+        double nx[R], ny[R], nz[R];
+        int ii[R];
+        const float tmax = (float)(tile_rc2[wk.rb0] * (1.0 + 0x1p-9));
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int li = 64 * r + lane;
+            const bool ok = li < wk.ni;
+            const int i = wk.i0 + (ok ? li : 0);
+            ii[r] = i;
+            const float4 A = pk[2 * (size_t)i], B = pk[2 * (size_t)i + 1];
+            xh[r] = A.x; yh[r] = A.y; zh[r] = A.z;
+            xl[r] = B.x; yl[r] = B.y; zl[r] = B.z;
+            mi[r] = ok ? A.w : 0.0f;
+            r2i[r] = B.w;
+            thr[r] = fmaxf(r2i[r], tmax);
+            hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
+            nx[r] = ny[r] = nz[r] = 0.0;
+        }
+        if (diag)
+            sym_tile32c<R, true>(sa[wv], sb[wv], sacc[wv], lane, wk.ni, wk.nj, wk.j0, inner, qx, qy, qz,
+                                 m, rc, ii, xh, yh, zh, xl, yl, zl, mi, r2i, thr, hx, hy, hz, lx, ly, lz,
+                                 nx, ny, nz, near);
+        else
+            sym_tile32c<R, false>(sa[wv], sb[wv], sacc[wv], lane, wk.ni, wk.nj, wk.j0, inner, qx, qy,
+                                  qz, m, rc, ii, xh, yh, zh, xl, yl, zl, mi, r2i, thr, hx, hy, hz, lx,
+                                  ly, lz, nx, ny, nz, near);
+        wave_lds_sync();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int li = 64 * r + lane;
+            if (li < wk.ni) {
+                double sx_ = ((double)hx[r] + (double)lx[r]) + nx[r];
+                double sy_ = ((double)hy[r] + (double)ly[r]) + ny[r];
+                double sz_ = ((double)hz[r] + (double)lz[r]) + nz[r];
+                if (diag) {
+                    const double4 a = sacc[wv][li];
+                    sx_ += a.x;
+                    sy_ += a.y;
+                    sz_ += a.z;
+                }
+                const int i = wk.i0 + li;
+                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = sx_;
+                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = sy_;
+                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = sz_;
+            }
+        }
+        if (!diag) {
+            for (int k = lane; k < wk.nj; k += 64) {
+                const double4 a = sacc[wv][k];
+                const int j = wk.j0 + k;
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = a.x;
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = a.y;
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = a.z;
+            }
+        }
+        wave_lds_sync();
     }
     for (int o = 32; o > 0; o >>= 1)
         near += __shfl_xor(near, o);
@@ -2297,43 +2661,53 @@ __global__ void k_diag_final(int nsys, const int *__restrict__ rb_first,
 // ----------------------------------------------------------------------------
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
-// Resolver transfers: one thread per member.
-__global__ __launch_bounds__(kBlock) void k_gather_members(
-    const int *__restrict__ idx, int k, const int *__restrict__ sys_of,
+// Resolver transfers.  k_gather_pairs packs both ends of listed pairs
+// [k0, k0 + n) (n capped by the step's count and the list): per pair two
+// records of 10 doubles (m0, m, rc, Q0, V0, body index); k_scatter_members
+// writes rows of 7 doubles (body index, Q, V) back, skipping rows that are not
+// finite (a failed group keeps its drifted state).
+__global__ __launch_bounds__(kBlock) void k_gather_pairs(
+    const int *__restrict__ ice, const int *__restrict__ jce, int k0, int n, int cap,
+    const DevStats *__restrict__ stats, const int *__restrict__ sys_of,
     const double *__restrict__ m0, const double *__restrict__ m, const double *__restrict__ rc,
     const double *__restrict__ q0x, const double *__restrict__ q0y, const double *__restrict__ q0z,
     const double *__restrict__ v0x, const double *__restrict__ v0y, const double *__restrict__ v0z,
     double *__restrict__ out)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= k)
+    const int k = k0 + t;
+    if (t >= n || k >= min(stats->cur_nce, cap))
         return;
-    const int i = idx[t];
-    double *o = out + 10 * (size_t)t;
-    o[0] = m0[sys_of[i]];
-    o[1] = m[i];
-    o[2] = rc[i];
-    o[3] = q0x[i];
-    o[4] = q0y[i];
-    o[5] = q0z[i];
-    o[6] = v0x[i];
-    o[7] = v0y[i];
-    o[8] = v0z[i];
-    o[9] = 0.0;
+    const int body[2] = {ice[k], jce[k]};
+    for (int e = 0; e < 2; ++e) {
+        const int i = body[e];
+        double *o = out + 20 * (size_t)t + 10 * e;
+        o[0] = m0[sys_of[i]];
+        o[1] = m[i];
+        o[2] = rc[i];
+        o[3] = q0x[i];
+        o[4] = q0y[i];
+        o[5] = q0z[i];
+        o[6] = v0x[i];
+        o[7] = v0y[i];
+        o[8] = v0z[i];
+        o[9] = (double)i;
+    }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scatter_members(
-    const int *__restrict__ idx, int k, const double *__restrict__ in, double *qx, double *qy,
-    double *qz, double *vx, double *vy, double *vz)
+__global__ __launch_bounds__(kBlock) void k_scatter_members(const double *__restrict__ rows, int k,
+                                                            int ntot, double *qx, double *qy,
+                                                            double *qz, double *vx, double *vy,
+                                                            double *vz)
 {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     if (t >= k)
         return;
-    const double *r = in + 6 * (size_t)t;
-    const double a = r[0], b = r[1], c = r[2], u = r[3], v = r[4], w = r[5];
-    if (!isfinite(a + b + c + u + v + w))
-        return;                       // a failed group keeps the drifted state
-    const int i = idx[t];
+    const double *r = rows + 7 * (size_t)t;
+    const double a = r[1], b = r[2], c = r[3], u = r[4], v = r[5], w = r[6];
+    const int i = (int)r[0];
+    if (!isfinite(a + b + c + u + v + w) || i < 0 || i >= ntot)
+        return;
     qx[i] = a;
     qy[i] = b;
     qz[i] = c;
@@ -2342,15 +2716,15 @@ __global__ __launch_bounds__(kBlock) void k_scatter_members(
     vz[i] = w;
 }
 
-hipError_t launch_gather_members(const Dev &d, int k, hipStream_t s)
+hipError_t launch_gather_pairs(const Dev &d, int k0, int n, hipStream_t s)
 {
-    if (k <= 0)
+    if (n <= 0)
         return hipSuccess;
-    if (k > d.res_cap)
+    if (n > d.res_cap)
         return hipErrorInvalidValue;
-    k_gather_members<<<cdiv(k, kBlock), kBlock, 0, s>>>(d.res_idx, k, d.sys_of, d.m0, d.m, d.rc,
-                                                         d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z,
-                                                         d.res_buf);
+    k_gather_pairs<<<cdiv(n, kBlock), kBlock, 0, s>>>(d.ice, d.jce, k0, n, d.enc_cap, d.stats, d.sys_of,
+                                                       d.m0, d.m, d.rc, d.q0x, d.q0y, d.q0z, d.v0x,
+                                                       d.v0y, d.v0z, d.res_buf);
     return hipGetLastError();
 }
 
@@ -2358,10 +2732,10 @@ hipError_t launch_scatter_members(const Dev &d, int k, hipStream_t s)
 {
     if (k <= 0)
         return hipSuccess;
-    if (k > d.res_cap)
+    if (k > 2 * d.res_cap)
         return hipErrorInvalidValue;
-    k_scatter_members<<<cdiv(k, kBlock), kBlock, 0, s>>>(d.res_idx, k, d.res_buf, d.qx, d.qy,
-                                                          d.qz, d.vx, d.vy, d.vz);
+    k_scatter_members<<<cdiv(k, kBlock), kBlock, 0, s>>>(d.res_rows, k, d.ntot, d.qx, d.qy, d.qz,
+                                                          d.vx, d.vy, d.vz);
     return hipGetLastError();
 }
 
@@ -2462,7 +2836,8 @@ hipError_t launch_drift(const Dev &d, const Params &p, double dt, hipStream_t s)
     k_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, dt, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
                                       d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
                                       d.stats, d.rpart, d.rc, d.mr, d.cr,
-                                      d.enc_sorted ? d.lnr_part : nullptr);
+                                      d.enc_sorted ? d.lnr_part : nullptr, d.q1x, d.q1y, d.q1z,
+                                      d.v1x, d.v1y, d.v1z, d.rc1);
     return hipGetLastError();
 }
 
@@ -2470,6 +2845,31 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
 {
     if (d.nfw == 0)
         return hipSuccess;
+    if (d.force_sym) {
+        const int grid = std::min(cdiv(d.nfw, kWaves), 4096);
+#define NB_SYM_ARGS d.fwork, d.nfw, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart, d.ntot, d.maxs, \
+                    p.inner, d.stats
+#define NB_SYM32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart, d.ntot, \
+                      d.maxs, p.inner, d.stats
+        if (p.mode == 1) {
+            if (p.force_r == 1)
+                k_force32c_sym<1><<<grid, kBlock, 0, s>>>(NB_SYM32_ARGS);
+            else if (p.force_r == 4)
+                k_force32c_sym<4><<<grid, kBlock, 0, s>>>(NB_SYM32_ARGS);
+            else
+                k_force32c_sym<2><<<grid, kBlock, 0, s>>>(NB_SYM32_ARGS);
+        } else {
+            if (p.force_r == 1)
+                k_force64_sym<1><<<grid, kBlock, 0, s>>>(NB_SYM_ARGS);
+            else if (p.force_r == 4)
+                k_force64_sym<4><<<grid, kBlock, 0, s>>>(NB_SYM_ARGS);
+            else
+                k_force64_sym<2><<<grid, kBlock, 0, s>>>(NB_SYM_ARGS);
+        }
+#undef NB_SYM_ARGS
+#undef NB_SYM32_ARGS
+        return hipGetLastError();
+    }
     if (d.force_few) {
         // waves stride over the items; about 8 workgroups per CU
         const int grid = std::min(cdiv(d.nfw, kWaves), 2048);
@@ -2541,11 +2941,11 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, h
     return hipGetLastError();
 }
 
-// Encounter check in two parts.  The gather part bins the drift records and
-// copies them into the sorted record array (sorted algorithm only); the test
-// part reads nothing but those copies, the list buffers and the flags, so it
-// may run beside the next S(h) and force pass.  The direct algorithm reads the
-// state planes and has an empty gather part.
+// Encounter check in two parts: the gather part bins the drift records and
+// copies them into the sorted record array (sorted algorithm only), the test
+// part tests pairs.  Both read only what the drift wrote (Q0, V0, the Q1, V1
+// and rc copies, the midpoint and chord records), so the whole check may run
+// beside the next S(h), force and kick.
 hipError_t launch_enc_gather(const Dev &d, hipStream_t s)
 {
     if (d.enc_sorted && d.nrb > 0) {
@@ -2561,9 +2961,9 @@ hipError_t launch_enc_gather(const Dev &d, hipStream_t s)
                                                          d.scan_part, d.stats);
         }
         k_scatter<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.cell_of, d.slot_of, d.cell_off, d.q0x,
-                                            d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.qx, d.qy, d.qz,
-                                            d.vx, d.vy, d.vz, d.rc, d.mr, d.cr, d.off, d.nbig, d.ord,
-                                            d.srec);
+                                            d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.q1x, d.q1y, d.q1z,
+                                            d.v1x, d.v1y, d.v1z, d.rc1, d.mr, d.cr, d.off, d.nbig,
+                                            d.ord, d.srec);
     }
     return hipGetLastError();
 }
@@ -2581,8 +2981,8 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
         }
     } else if (d.new_ > 0) {
         k_encounter<<<d.new_, kBlock, 0, s>>>(d.ework, dt, d.mr, d.cr, d.q0x, d.q0y, d.q0z, d.v0x,
-                                               d.v0y, d.v0z, d.qx, d.qy, d.qz, d.vx, d.vy, d.vz,
-                                               d.rc, d.keys, d.enc_cap, d.ce, d.stats);
+                                               d.v0y, d.v0z, d.q1x, d.q1y, d.q1z, d.v1x, d.v1y,
+                                               d.v1z, d.rc1, d.keys, d.enc_cap, d.ce, d.stats);
     }
     k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats, 1);
     return hipGetLastError();

@@ -34,10 +34,16 @@ struct nb_ctx {
     double graph_dt = 0.0;
     int graph_steps = 0;
     std::string err;
-    // close-encounter resolver (resolve = 1)
+    // close-encounter resolver (resolve = 1): pinned staging of the step's count
+    // and pair records (host reads), result rows (host writes; the next step's
+    // synchronisation orders their reuse after the copy)
     std::unique_ptr<WorkerPool> pool;
     Groups groups;
+    DevStats *h_stats = nullptr;
+    double *h_pairs = nullptr, *h_rows = nullptr;
+    int res_k = 256;                 // pairs copied with the count (adapts to the counts seen)
     std::vector<int32_t> h_ice, h_jce;
+    std::vector<std::pair<int32_t, int32_t>> h_ends;   // (body, record) of every pair end
     std::vector<Member> h_in;
     std::vector<double> h_out;
     long long res_groups = 0, res_bodies = 0;
@@ -92,6 +98,7 @@ Params to_internal(const nb_params &q)
     p.enc_j = q.enc_jchunk > 0 ? q.enc_jchunk : kDefaultEncJ;
     p.enc_algo = q.enc_algo;
     p.step_algo = q.step_algo;
+    p.force_algo = q.force_algo;
     p.resolve = q.resolve;
     p.resolve_threads = q.resolve_threads;
     p.bs_tol = q.bs_tol > 0.0 ? q.bs_tol : 1e-12;
@@ -151,7 +158,8 @@ int check_params(const nb_params *p)
     if (p->force_jchunk < 0 || p->enc_jchunk < 0 || p->enc_algo < 0 || p->enc_algo > 2 ||
         p->step_algo < 0 || p->step_algo > 2)
         return NB_E_INVALID;
-    if ((p->resolve != 0 && p->resolve != 1) || p->resolve_threads < 0 || p->reserved != 0 ||
+    if ((p->resolve != 0 && p->resolve != 1) || p->resolve_threads < 0 || p->force_algo < 0 ||
+        p->force_algo > 2 ||
         !(p->bs_tol >= 0.0 && p->bs_tol < 1.0) || (p->resolve && p->step_algo == 2))
         return NB_E_INVALID;
     if (p->drag && !(p->drag_h > 0.0 && p->drag_h * p->drag_h * 3.0 < 1.0 && p->drag_rho_p > 0.0 &&
@@ -199,6 +207,7 @@ struct Tables {
     long long tp_cap = 0;
     bool enc_sorted = false;
     bool force_few = false;
+    bool force_sym = false;
     // persistent step launch: systems largest first
     std::vector<PSys> psys;
 };
@@ -221,6 +230,8 @@ void pair_items(int a, int n, int nb, int J, std::vector<PWork> &out)
 void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *nbig, Tables &t)
 {
     t.enc_sorted = choose_enc_algo(p, nsys, off, nbig) == 2;
+    // symmetric tile pairs: every body big (automatic or asked for)
+    t.force_sym = p.force_algo != 1 && !has_small(nsys, off, nbig);
     t.rb_first.assign(nsys, 0);
     t.rb_count.assign(nsys, 0);
     t.nsplit.assign(nsys, 0);
@@ -240,16 +251,29 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
             continue;
         // sources are the big bodies [a, a + nb) only (Sec. 2.1)
         const int nb = nbig ? nbig[s] : n;
-        int S = (nb + p.force_j - 1) / p.force_j;
-        t.nsplit[s] = S;
-        t.maxs = std::max(t.maxs, S);
-        for (int i0 = 0; i0 < n; i0 += TI)
-            for (int k = 0; k < S; ++k) {
-                int j0 = k * p.force_j;
-                t.fwork.push_back(FWork{a + i0, std::min(TI, n - i0), a + j0,
-                                        std::min(p.force_j, nb - j0), k, s,
-                                        t.rb_first[s] + j0 / kBlock, 0});
-            }
+        if (t.force_sym) {
+            // unordered tile pairs (I <= J) of TI bodies; tile I's sums go to slot J,
+            // tile J's to slot I (the item's pad field)
+            const int nt = (n + TI - 1) / TI;
+            t.nsplit[s] = nt;
+            t.maxs = std::max(t.maxs, nt);
+            for (int I = 0; I < nt; ++I)
+                for (int J = I; J < nt; ++J)
+                    t.fwork.push_back(FWork{a + I * TI, std::min(TI, n - I * TI), a + J * TI,
+                                            std::min(TI, n - J * TI), J, s,
+                                            t.rb_first[s] + (J * TI) / kBlock, I});
+        } else {
+            int S = (nb + p.force_j - 1) / p.force_j;
+            t.nsplit[s] = S;
+            t.maxs = std::max(t.maxs, S);
+            for (int i0 = 0; i0 < n; i0 += TI)
+                for (int k = 0; k < S; ++k) {
+                    int j0 = k * p.force_j;
+                    t.fwork.push_back(FWork{a + i0, std::min(TI, n - i0), a + j0,
+                                            std::min(p.force_j, nb - j0), k, s,
+                                            t.rb_first[s] + j0 / kBlock, 0});
+                }
+        }
         pair_items(a, n, nb, p.enc_j, t.ework);
         t.dw_first[s] = (int)t.dwork.size();
         pair_items(a, n, nb, p.enc_j, t.dwork);
@@ -261,7 +285,7 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
         int maxnb = 0;
         for (int s = 0; s < nsys; ++s)
             maxnb = std::max(maxnb, nbig ? nbig[s] : off[s + 1] - off[s]);
-        t.force_few = maxnb <= 256 && maxnb <= p.force_j && t.fwork.size() >= 1024;
+        t.force_few = !t.force_sym && maxnb <= 256 && maxnb <= p.force_j && t.fwork.size() >= 1024;
     }
     // sorted encounter check: about N_s/8 cells per system (a power of two) and
     // tiles of 64 consecutive sorted bodies
@@ -333,8 +357,9 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     const size_t nd = (size_t)ntot * sizeof(double);
     d.ntot = ntot;
     d.nsys = nsys;
-    double **planes[] = {&d.m,  &d.qx, &d.qy, &d.qz, &d.vx,  &d.vy,  &d.vz,  &d.ax, &d.ay,
-                         &d.az, &d.rc, &d.q0x, &d.q0y, &d.q0z, &d.v0x, &d.v0y, &d.v0z};
+    double **planes[] = {&d.m,   &d.qx,  &d.qy,  &d.qz,  &d.vx,  &d.vy,  &d.vz,  &d.ax,
+                         &d.ay,  &d.az,  &d.rc,  &d.q0x, &d.q0y, &d.q0z, &d.v0x, &d.v0y,
+                         &d.v0z, &d.q1x, &d.q1y, &d.q1z, &d.v1x, &d.v1y, &d.v1z, &d.rc1};
     for (double **pl : planes)
         *pl = (double *)take(nd);
     d.pk = (float4 *)take((size_t)ntot * 2 * sizeof(float4));
@@ -378,6 +403,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.psys = (PSys *)take(t.psys.size() * sizeof(PSys));
     d.enc_sorted = t.enc_sorted;
     d.force_few = t.force_few ? 1 : 0;
+    d.force_sym = t.force_sym ? 1 : 0;
     if (d.enc_sorted) {
         d.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
         d.cell_of = (int *)take((size_t)ntot * sizeof(int));
@@ -399,10 +425,10 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.flag = (int *)take(4 * sizeof(int));
     d.stage = (double *)take((size_t)6 * nd);
     if (p.resolve) {
-        // every member of a resolved group is in a listed pair
-        d.res_cap = (int)std::min<long long>(ntot, 2ll * std::max(enc_cap, 1));
-        d.res_idx = (int *)take((size_t)d.res_cap * sizeof(int));
-        d.res_buf = (double *)take((size_t)d.res_cap * 10 * sizeof(double));
+        // every member of a resolved group is an end of a listed pair
+        d.res_cap = std::max(enc_cap, 1);
+        d.res_buf = (double *)take((size_t)d.res_cap * 20 * sizeof(double));
+        d.res_rows = (double *)take((size_t)d.res_cap * 2 * 7 * sizeof(double));
     }
     return cur;
 }
@@ -474,18 +500,17 @@ int enqueue_step_tail(nb_ctx *c, double dt)
 
 int enqueue_step(nb_ctx *c, double dt)
 {
-    if (c->side && c->d.enc_sorted) {
-        // fork after the records are copied into the sorted array: the test part
-        // of the encounter check runs beside S(h), the force and its finalize
+    if (c->side) {
+        // fork after the drift: the encounter check reads only the drift's
+        // snapshots (Q0, V0, Q1, V1, rc) and runs beside S(h), the force and K(h)
         const double h = 0.5 * dt;
         const Dev &d = c->d;
         HIP_OK(c, launch_kick(d, c->p, h, c->stream));
         HIP_OK(c, launch_sun_drift(d, h, 0, c->p, c->stream));
         HIP_OK(c, launch_drift(d, c->p, dt, c->stream));
-        HIP_OK(c, launch_enc_gather(d, c->stream));
         HIP_OK(c, hipEventRecord(c->ev_fork, c->stream));
         HIP_OK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-        HIP_OK(c, launch_enc_test(d, dt, c->side));
+        HIP_OK(c, launch_encounters(d, dt, c->side));
         HIP_OK(c, hipEventRecord(c->ev_join, c->side));
         int r = enqueue_step_tail(c, dt);
         if (r)
@@ -497,45 +522,71 @@ int enqueue_step(nb_ctx *c, double dt)
     return r ? r : enqueue_step_tail(c, dt);
 }
 
-// Between C and the second S(h) of the full method: read the sorted pair list
-// of this step, group it, bring the members' pre-drift records to the host,
-// integrate every group there and write the results back.
+// Between C and the second S(h) of the full method.  The device packs both ends
+// of the step's listed pairs (the first res_k of them, more on a second pass);
+// one synchronisation brings the count and those records to the host, which
+// groups the pairs, integrates every group and sends (index, Q, V) rows back to
+// a scatter kernel; the rest of the step is enqueued without waiting.
 int resolve_step(nb_ctx *c, double dt)
 {
     Dev &d = c->d;
-    DevStats ds;
-    HIP_OK(c, hipMemcpyAsync(&ds, d.stats, sizeof ds, hipMemcpyDeviceToHost, c->stream));
+    const int kcap = d.res_cap;
+    if (!c->h_stats) {
+        HIP_OK(c, hipHostMalloc((void **)&c->h_stats, sizeof(DevStats), hipHostMallocDefault));
+        HIP_OK(c, hipHostMalloc((void **)&c->h_pairs, (size_t)kcap * 20 * sizeof(double),
+                                hipHostMallocDefault));
+        HIP_OK(c, hipHostMalloc((void **)&c->h_rows, (size_t)kcap * 2 * 7 * sizeof(double),
+                                hipHostMallocDefault));
+    }
+    int K = std::min(c->res_k, kcap);
+    HIP_OK(c, launch_gather_pairs(d, 0, K, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->h_stats, d.stats, sizeof(DevStats), hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipMemcpyAsync(c->h_pairs, d.res_buf, (size_t)K * 20 * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
     int r = sync(c);
     if (r)
         return r;
-    const int npairs = std::min(ds.cur_nce, d.enc_cap);
+    const int npairs = std::min(c->h_stats->cur_nce, d.enc_cap);
+    if (npairs > K) {
+        // more pairs than expected: gather and copy the rest
+        HIP_OK(c, launch_gather_pairs(d, K, npairs - K, c->stream));
+        HIP_OK(c, hipMemcpyAsync(c->h_pairs + (size_t)K * 20, d.res_buf,
+                                 (size_t)(npairs - K) * 20 * sizeof(double), hipMemcpyDeviceToHost,
+                                 c->stream));
+        if ((r = sync(c)))
+            return r;
+    }
+    // next step's prefetch: twice this count, at least 256 pairs
+    int nk = 256;
+    while (nk < 2 * npairs && nk < kcap)
+        nk <<= 1;
+    c->res_k = nk;
     if (npairs <= 0)
         return NB_OK;
     c->h_ice.resize(npairs);
     c->h_jce.resize(npairs);
-    HIP_OK(c, hipMemcpyAsync(c->h_ice.data(), d.ice, npairs * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, c->stream));
-    HIP_OK(c, hipMemcpyAsync(c->h_jce.data(), d.jce, npairs * sizeof(int32_t),
-                             hipMemcpyDeviceToHost, c->stream));
-    if ((r = sync(c)))
-        return r;
-    for (int k = 0; k < npairs; ++k)
-        if (c->h_ice[k] < 0 || c->h_ice[k] >= c->ntot || c->h_jce[k] < 0 ||
-            c->h_jce[k] >= c->ntot)
+    c->h_ends.resize(2 * (size_t)npairs);
+    for (int k = 0; k < npairs; ++k) {
+        const double *rec = c->h_pairs + 20 * (size_t)k;
+        const double bi = rec[9], bj = rec[19];
+        if (!(bi >= 0.0 && bi < c->ntot && bj >= 0.0 && bj < c->ntot))
             return set_err(c, NB_E_HIP, "resolver: pair %d has an index out of range", k);
+        c->h_ice[k] = (int32_t)bi;
+        c->h_jce[k] = (int32_t)bj;
+        c->h_ends[2 * (size_t)k] = {c->h_ice[k], 2 * k};
+        c->h_ends[2 * (size_t)k + 1] = {c->h_jce[k], 2 * k + 1};
+    }
+    std::sort(c->h_ends.begin(), c->h_ends.end());
     build_groups(npairs, c->h_ice.data(), c->h_jce.data(), c->groups);
     const int k = (int)c->groups.body.size();
-    if (k > d.res_cap)
-        return set_err(c, NB_E_HIP, "resolver: %d members exceed the capacity %d", k, d.res_cap);
     c->h_in.resize(k);
     c->h_out.resize((size_t)6 * k);
-    HIP_OK(c, hipMemcpyAsync(d.res_idx, c->groups.body.data(), k * sizeof(int32_t),
-                             hipMemcpyHostToDevice, c->stream));
-    HIP_OK(c, launch_gather_members(d, k, c->stream));
-    HIP_OK(c, hipMemcpyAsync(c->h_in.data(), d.res_buf, k * sizeof(Member), hipMemcpyDeviceToHost,
-                             c->stream));
-    if ((r = sync(c)))
-        return r;
+    for (int e = 0; e < k; ++e) {
+        const int32_t b = c->groups.body[e];
+        auto it = std::lower_bound(c->h_ends.begin(), c->h_ends.end(), std::make_pair(b, (int32_t)-1));
+        std::memcpy(&c->h_in[e], c->h_pairs + 10 * (size_t)it->second, sizeof(Member));
+        c->h_in[e].pad = 0.0;
+    }
     if (!c->pool && resolver_threads(c->p.resolve_threads) > 1)
         c->pool.reset(new WorkerPool(resolver_threads(c->p.resolve_threads)));
     ResolveTotals t = resolve_groups(c->groups, c->h_in.data(), c->h_out.data(), c->p.G,
@@ -544,11 +595,15 @@ int resolve_step(nb_ctx *c, double dt)
     c->res_bodies += t.bodies;
     c->res_max_group = std::max(c->res_max_group, t.max_group);
     c->res_fail += t.failed;
-    HIP_OK(c, hipMemcpyAsync(d.res_buf, c->h_out.data(), (size_t)6 * k * sizeof(double),
+    for (int e = 0; e < k; ++e) {
+        double *row = c->h_rows + 7 * (size_t)e;
+        row[0] = (double)c->groups.body[e];
+        std::memcpy(row + 1, c->h_out.data() + 6 * (size_t)e, 6 * sizeof(double));
+    }
+    HIP_OK(c, hipMemcpyAsync(d.res_rows, c->h_rows, (size_t)k * 7 * sizeof(double),
                              hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, launch_scatter_members(d, k, c->stream));
-    // h_out must stay intact until the copy has been read
-    return sync(c);
+    return NB_OK;
 }
 
 void drop_graph(nb_ctx *c)
@@ -670,6 +725,12 @@ void release(nb_ctx *c)
         (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join)
         (void)hipEventDestroy(c->ev_join);
+    if (c->h_stats)
+        (void)hipHostFree(c->h_stats);
+    if (c->h_pairs)
+        (void)hipHostFree(c->h_pairs);
+    if (c->h_rows)
+        (void)hipHostFree(c->h_rows);
     delete c;
 }
 
@@ -811,7 +872,7 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *n
         r = reset_stats(c);
     if (r == NB_OK)
         r = sync(c);
-    if (r == NB_OK && c->stream && c->d.enc_sorted) {
+    if (r == NB_OK && c->stream) {
         // default priority, like every stream here
         if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
@@ -1225,6 +1286,19 @@ int nb_resolve_host(int n, double G, double m0, double chg_inner, double tol, do
         info->failed = t.failed;
         info->max_steps = t.max_steps;
     }
+    return NB_OK;
+}
+
+int nb_get_choices(const nb_ctx *c, int32_t *force_algo, int32_t *enc_algo, int32_t *step_algo)
+{
+    if (!c)
+        return NB_E_INVALID;
+    if (force_algo)
+        *force_algo = c->d.force_sym ? 2 : (c->d.force_few ? 3 : 1);
+    if (enc_algo)
+        *enc_algo = c->d.enc_sorted ? 2 : 1;
+    if (step_algo)
+        *step_algo = c->p.step_algo;
     return NB_OK;
 }
 

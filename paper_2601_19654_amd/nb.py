@@ -46,7 +46,7 @@ class nb_params(ctypes.Structure):
         ("force_jchunk", ctypes.c_int32), ("force_r", ctypes.c_int32),
         ("enc_jchunk", ctypes.c_int32), ("enc_algo", ctypes.c_int32),
         ("step_algo", ctypes.c_int32), ("resolve", ctypes.c_int32),
-        ("resolve_threads", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("resolve_threads", ctypes.c_int32), ("force_algo", ctypes.c_int32),
         ("bs_tol", ctypes.c_double),
     ]
 
@@ -99,6 +99,7 @@ SIGNATURES = {
     "nb_get_rcrit": (_I, [_P, _P, _I]),
     "nb_time_kernel": (_I, [_P, _I, _I, _D, _P]),
     "nb_resolve_host": (_I, [_I, _D, _D, _D, _D, _D, _P, _P, _P, _P, _I, _P, _P, _P, _P, _P, _I, _P]),
+    "nb_get_choices": (_I, [_P, _P, _P, _P]),
     "nb_destroy": (_I, [_P]),
 }
 
@@ -189,7 +190,7 @@ class Context:
         nbig_p = None if self.nbig is None else _addr(self.nbig)
         self.tiles = "library defaults"
         if tuned and not (self.params.force_r or self.params.force_jchunk or self.params.enc_jchunk
-                          or self.params.enc_algo or self.params.step_algo):
+                          or self.params.enc_algo or self.params.step_algo or self.params.force_algo):
             from . import autotune
             try:
                 hit = autotune.lookup("fp32c" if self.params.mode == NB_FP32C else "fp64", self.off,
@@ -197,6 +198,7 @@ class Context:
             except Exception:
                 hit = None
             if hit:
+                self.params.force_algo = hit.get("force_algo", 0)
                 self.params.force_r = hit["force_r"]
                 self.params.force_jchunk = hit["force_jchunk"]
                 self.params.enc_jchunk = hit["enc_jchunk"]
@@ -321,6 +323,14 @@ class Context:
         self._check(lib().nb_time_kernel(self.ctx, int(which), int(reps), float(dt), ctypes.byref(ms)),
                     "nb_time_kernel")
         return ms.value
+
+    def choices(self):
+        """Resolved algorithms: force (1 ordered, 2 symmetric, 3 few sources),
+        encounter check (1 direct, 2 sorted), step launch (1 per phase, 2 persistent)."""
+        f, e, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        self._check(lib().nb_get_choices(self.ctx, ctypes.byref(f), ctypes.byref(e), ctypes.byref(st)),
+                    "nb_get_choices")
+        return {"force_algo": f.value, "enc_algo": e.value, "step_algo": st.value}
 
     def close(self):
         if getattr(self, "ctx", None):

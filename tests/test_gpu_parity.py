@@ -40,9 +40,12 @@ def case(request):
 
 # ---------------------------------------------------------------- force
 @pytest.mark.parametrize("r,jchunk", [(2, 0), (1, 256), (4, 512)])
-def test_force_fp64(case, r, jchunk):
+@pytest.mark.parametrize("force_algo", [1, 2])
+def test_force_fp64(case, r, jchunk, force_algo):
+    """force_algo 1: every ordered pair; 2: each unordered pair once, applied to
+    both bodies (tile pairs of 64 r bodies, ragged tails, diagonal tiles)."""
     name, w, (Q, V, rc, a_ref) = case
-    c = ctx_for(w, mode=nb.NB_FP64, force_r=r, force_jchunk=jchunk)
+    c = ctx_for(w, mode=nb.NB_FP64, force_r=r, force_jchunk=jchunk, force_algo=force_algo)
     a = c.accel()
     rc_g = c.rcrit()
     # cbrt and sqrt differ between the device library and glibc by about an ulp each
@@ -57,9 +60,10 @@ def test_force_fp64(case, r, jchunk):
 
 
 @pytest.mark.parametrize("r,jchunk", [(2, 0), (1, 256), (4, 512)])
-def test_force_fp32c(case, r, jchunk):
+@pytest.mark.parametrize("force_algo", [1, 2])
+def test_force_fp32c(case, r, jchunk, force_algo):
     name, w, (Q, V, rc, a_ref) = case
-    c = ctx_for(w, mode=nb.NB_FP32C, force_r=r, force_jchunk=jchunk)
+    c = ctx_for(w, mode=nb.NB_FP32C, force_r=r, force_jchunk=jchunk, force_algo=force_algo)
     a = c.accel()
     worst = 0.0
     for s, lo, hi in systems(w):
@@ -67,7 +71,7 @@ def test_force_fp32c(case, r, jchunk):
             continue
         A = pair_scale(w.m[lo:hi], Q[lo:hi], w.G)
         worst = max(worst, accel_error(a[lo:hi], a_ref[lo:hi], A))
-    print(f"FP32C force error {name} r={r} j={jchunk}: {worst:.3e} A_i")
+    print(f"FP32C force error {name} r={r} j={jchunk} algo={force_algo}: {worst:.3e} A_i")
     assert worst <= 4e-6, (name, worst)
 
 
@@ -215,11 +219,12 @@ def test_diagnostics(case):
 
 
 # ---------------------------------------------------------------- full steps
-@pytest.mark.parametrize("mode,algo,step_algo", [(0, 1, 1), (1, 1, 1), (0, 2, 1), (0, 0, 2)])
-def test_steps_match_oracle(case, mode, algo, step_algo):
+@pytest.mark.parametrize("mode,algo,step_algo,force_algo", [(0, 1, 1, 0), (1, 1, 1, 0), (0, 2, 1, 0),
+                                                            (0, 0, 2, 0), (0, 1, 1, 1)])
+def test_steps_match_oracle(case, mode, algo, step_algo, force_algo):
     name, w, _ = case
     k = 5
-    c = ctx_for(w, mode=mode, enc_algo=algo, step_algo=step_algo)
+    c = ctx_for(w, mode=mode, enc_algo=algo, step_algo=step_algo, force_algo=force_algo)
     st = oracle.State.from_workload(w)
     stats = c.step(w.dt, k)
     total = 0
@@ -297,17 +302,18 @@ def test_bitwise_determinism(enc_algo):
         assert np.array_equal(u, v)
 
 
-def test_overlapped_encounter_branch_matches_serial_steps():
-    """With the sorted encounter check, the test part runs on a second stream
-    beside S(h) and the force (graph branches); a context on the null stream
-    runs every phase in order on one stream.  Same state, same lists, same
-    statistics after 21 steps (graph replays plus a direct remainder)."""
+@pytest.mark.parametrize("enc_algo", [1, 2])
+def test_overlapped_encounter_branch_matches_serial_steps(enc_algo):
+    """On a context with a stream the encounter check runs on a second stream
+    beside S(h), the force and K(h) (graph branches); a context on the null
+    stream runs every phase in order on one stream.  Same state, same lists,
+    same statistics after 21 steps (graph replays plus a direct remainder)."""
     import torch
     w = workloads.ring(2000, m=3e-8)
-    p = nb.default_params(G=w.G, enc_algo=2)
+    p = nb.default_params(G=w.G, enc_algo=enc_algo)
     serial = nb.Context(w.off, p, device="cuda:0", stream=torch.cuda.default_stream(torch.device("cuda:0")))
     serial.upload(w.m0, w.m, w.x, w.v)
-    forked = ctx_for(w, enc_algo=2)
+    forked = ctx_for(w, enc_algo=enc_algo)
     outs = []
     for c in (serial, forked):
         st = c.step(w.dt, 21)
@@ -466,3 +472,19 @@ def test_full_mode_resolves_a_close_encounter():
     assert groups >= 10 and stats["resolved_groups"] == groups
     eq = rel_rows(st.Q, st14.Q) + 1e-11
     assert rel_rows(x, st.Q) <= 3 * eq, (rel_rows(x, st.Q), eq)
+
+
+def test_resolved_choices():
+    """nb_get_choices reports what the automatic choices resolved to."""
+    ring = workloads.ring(2000, m=3e-8)
+    c = ctx_for(ring)
+    ch = c.choices()
+    assert ch["force_algo"] == 2 and ch["enc_algo"] in (1, 2) and ch["step_algo"] in (1, 2)
+    assert ctx_for(ring, force_algo=1).choices()["force_algo"] == 1
+    assert ctx_for(ring, enc_algo=2).choices()["enc_algo"] == 2
+    assert ctx_for(ring, resolve=1).choices()["step_algo"] == 1
+    bs = workloads.bigsmall(50, 140000)
+    chb = ctx_for(bs, force_r=1).choices()
+    assert chb["force_algo"] == 3 and chb["enc_algo"] == 1      # few sources, few partners
+    small = workloads.bigsmall(20, 3000)
+    assert ctx_for(small).choices()["force_algo"] == 1           # too few target tiles
