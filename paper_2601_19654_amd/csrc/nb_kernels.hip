@@ -1125,9 +1125,16 @@ __device__ __forceinline__ double rinv3(double r2)
     return (y0 * y2) * fma(1.5, e, 1.0);
 }
 
-template <int R, bool DIAG>
-__device__ __forceinline__ void sym_tile64(const double4 *__restrict__ sj, const double2 *__restrict__ sx,
-                                           double4 *__restrict__ sacc, int lane, double inner,
+// Tile J of one wave in LDS, one array per component (consecutive lanes touch
+// consecutive 8-byte words: no bank conflicts for the rotating accesses).
+template <int T>
+struct SymTile64 {
+    double x[T], y[T], z[T], m[T], rc[T];
+    double ax[T], ay[T], az[T];        // tile J's sums
+};
+
+template <int R, bool DIAG, int T>
+__device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, double inner,
                                            const double (&xi)[R], const double (&yi)[R],
                                            const double (&zi)[R], const double (&mi)[R],
                                            const double (&rci)[R], const double (&r2i)[R],
@@ -1137,22 +1144,24 @@ __device__ __forceinline__ void sym_tile64(const double4 *__restrict__ sj, const
 #pragma unroll 1
     for (int t = 0; t < R; ++t) {
         // Lanes update each other's accumulators from step to step: the next
-        // step's loads must stay after this step's store (LDS operations of a
+        // step's loads must stay after this step's stores (LDS operations of a
         // wave complete in issue order, so program order is enough); sources
-        // are read-only and prefetched one step ahead.
+        // are read-only and read one step ahead.
         int jj = 64 * t + lane;
-        double4 J = sj[jj];
+        double jxs = L.x[jj], jys = L.y[jj], jzs = L.z[jj], jms = L.m[jj];
 #pragma unroll 1
         for (int k = 0; k < 64; ++k) {
-            double4 a = sacc[jj];
+            double a0 = L.ax[jj], a1 = L.ay[jj], a2 = L.az[jj];
+            const int jn = 64 * t + ((lane + k + 1) & 63);
+            const double xn = L.x[jn], yn = L.y[jn], zn = L.z[jn], mn = L.m[jn];
             double jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double dx = J.x - xi[r], dy = J.y - yi[r], dz = J.z - zi[r];
+                const double dx = jxs - xi[r], dy = jys - yi[r], dz = jzs - zi[r];
                 const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 double q = rinv3(r2);
                 if (r2 < thr[r]) {
-                    const double rcj = sx[jj].x;
+                    const double rcj = L.rc[jj];
                     if (r2 < fmax(r2i[r], fmax(rcj * rcj, DBL_MIN))) {
                         q = changeover_w(r2, fmax(rci[r], rcj), inner);
                         ++near;
@@ -1160,7 +1169,7 @@ __device__ __forceinline__ void sym_tile64(const double4 *__restrict__ sj, const
                 }
                 if (DIAG)
                     q = (64 * r + lane < jj) ? q : 0.0;
-                const double wi = J.w * q, wj = mi[r] * q;
+                const double wi = jms * q, wj = mi[r] * q;
                 ax[r] = fma(wi, dx, ax[r]);
                 ay[r] = fma(wi, dy, ay[r]);
                 az[r] = fma(wi, dz, az[r]);
@@ -1168,15 +1177,15 @@ __device__ __forceinline__ void sym_tile64(const double4 *__restrict__ sj, const
                 jy = fma(-wj, dy, jy);
                 jz = fma(-wj, dz, jz);
             }
-            const int jn = 64 * t + ((lane + k + 1) & 63);
-            const double4 Jn = sj[jn];
-            a.x += jx;
-            a.y += jy;
-            a.z += jz;
-            sacc[jj] = a;
+            L.ax[jj] = a0 + jx;
+            L.ay[jj] = a1 + jy;
+            L.az[jj] = a2 + jz;
             __asm__ __volatile__("" ::: "memory");
             jj = jn;
-            J = Jn;
+            jxs = xn;
+            jys = yn;
+            jzs = zn;
+            jms = mn;
         }
     }
 }
@@ -1193,20 +1202,24 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
                                                         double inner, DevStats *stats)
 {
     constexpr int T = 64 * R;
-    __shared__ double4 sj[kWaves][T];       // x, y, z, m of tile J
-    __shared__ double2 sx[kWaves][T];       // rc of tile J
-    __shared__ double4 sacc[kWaves][T];     // tile J's sums
+    __shared__ SymTile64<T> tl[kWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    SymTile64<T> &L = tl[wv];
     int near = 0;
     for (int it = blockIdx.x * kWaves + wv; it < nitems; it += gridDim.x * kWaves) {
         const FWork wk = work[it];
         const bool diag = wk.i0 == wk.j0;
         for (int k = lane; k < T; k += 64) {
-            // sources past the tile end: massless copies of its first body
-            const int j = wk.j0 + (k < wk.nj ? k : 0);
-            sj[wv][k] = make_double4(qx[j], qy[j], qz[j], k < wk.nj ? m[j] : 0.0);
-            sx[wv][k] = make_double2(k < wk.nj ? rc[j] : 0.0, 0.0);
-            sacc[wv][k] = make_double4(0.0, 0.0, 0.0, 0.0);
+            // sources past the tile end: massless and far away (r^2 ~ 1e300, so
+            // their weight underflows to 0 instead of meeting a target at r = 0)
+            const bool ok = k < wk.nj;
+            const int j = wk.j0 + (ok ? k : 0);
+            L.x[k] = ok ? qx[j] : 1e150;
+            L.y[k] = ok ? qy[j] : 1e150;
+            L.z[k] = ok ? qz[j] : 1e150;
+            L.m[k] = ok ? m[j] : 0.0;
+            L.rc[k] = ok ? rc[j] : 0.0;
+            L.ax[k] = L.ay[k] = L.az[k] = 0.0;
         }
         wave_lds_sync();
         double xi[R], yi[R], zi[R], mi[R], rci[R], r2i[R], thr[R], ax[R], ay[R], az[R];
@@ -1227,11 +1240,9 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
             ax[r] = ay[r] = az[r] = 0.0;
         }
         if (diag)
-            sym_tile64<R, true>(sj[wv], sx[wv], sacc[wv], lane, inner, xi, yi, zi, mi, rci, r2i, thr,
-                                ax, ay, az, near);
+            sym_tile64<R, true, T>(L, lane, inner, xi, yi, zi, mi, rci, r2i, thr, ax, ay, az, near);
         else
-            sym_tile64<R, false>(sj[wv], sx[wv], sacc[wv], lane, inner, xi, yi, zi, mi, rci, r2i, thr,
-                                 ax, ay, az, near);
+            sym_tile64<R, false, T>(L, lane, inner, xi, yi, zi, mi, rci, r2i, thr, ax, ay, az, near);
         wave_lds_sync();
         // tile I to slot J (on the diagonal together with tile J's sums of the same bodies)
 #pragma unroll
@@ -1240,10 +1251,9 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
             if (li < wk.ni) {
                 double sx_ = ax[r], sy_ = ay[r], sz_ = az[r];
                 if (diag) {
-                    const double4 a = sacc[wv][li];
-                    sx_ += a.x;
-                    sy_ += a.y;
-                    sz_ += a.z;
+                    sx_ += L.ax[li];
+                    sy_ += L.ay[li];
+                    sz_ += L.az[li];
                 }
                 const int i = wk.i0 + li;
                 fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = sx_;
@@ -1254,11 +1264,10 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
         if (!diag) {
             // tile J to slot I
             for (int k = lane; k < wk.nj; k += 64) {
-                const double4 a = sacc[wv][k];
                 const int j = wk.j0 + k;
-                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = a.x;
-                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = a.y;
-                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = a.z;
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = L.ax[k];
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = L.ay[k];
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = L.az[k];
             }
         }
         wave_lds_sync();
@@ -1273,10 +1282,17 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
 // records; tile I's sums in FP32 runs of 32 steps merged by two-sum, tile J's
 // contributions (summed over the R targets in FP32) added in FP64 in LDS;
 // changeover pairs in FP64 from the FP64 state for both bodies.
-template <int R, bool DIAG>
-__device__ __forceinline__ void sym_tile32c(const float4 *__restrict__ sa, const float4 *__restrict__ sb,
-                                            double4 *__restrict__ sacc, int lane, int ni, int nj,
-                                            int j0, double inner, const double *__restrict__ qx,
+// Tile J of one wave in LDS for the FP32C form: (hi, lo) of each coordinate,
+// (mass, widened rc^2) and the FP64 sums, one 8-byte word per lane and array.
+template <int T>
+struct SymTile32 {
+    float2 x[T], y[T], z[T], mr[T];
+    double ax[T], ay[T], az[T];
+};
+
+template <int R, bool DIAG, int T>
+__device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int ni, int nj, int j0,
+                                            double inner, const double *__restrict__ qx,
                                             const double *__restrict__ qy, const double *__restrict__ qz,
                                             const double *__restrict__ m, const double *__restrict__ rc,
                                             const int (&ii)[R], const float (&xh)[R], const float (&yh)[R],
@@ -1296,23 +1312,25 @@ __device__ __forceinline__ void sym_tile32c(const float4 *__restrict__ sa, const
                 tx[r] = ty[r] = tz[r] = 0.0f;
             // see sym_tile64 for the order of the accumulator updates
             int jj = 64 * t + ((lane + 32 * half) & 63);
-            float4 A = sa[jj], B = sb[jj];
+            float2 X = L.x[jj], Y = L.y[jj], Z = L.z[jj], MR = L.mr[jj];
 #pragma unroll 1
             for (int kk = 0; kk < 32; ++kk) {
-                double4 a = sacc[jj];
+                const double a0 = L.ax[jj], a1 = L.ay[jj], a2 = L.az[jj];
+                const int jn = 64 * t + ((lane + 32 * half + kk + 1) & 63);
+                const float2 Xn = L.x[jn], Yn = L.y[jn], Zn = L.z[jn], MRn = L.mr[jn];
                 float jx = 0.0f, jy = 0.0f, jz = 0.0f;
                 double ex_ = 0.0, ey_ = 0.0, ez_ = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const bool on = !DIAG || (64 * r + lane < jj);
-                    float dx = (A.x - xh[r]) + (B.x - xl[r]);
-                    float dy = (A.y - yh[r]) + (B.y - yl[r]);
-                    float dz = (A.z - zh[r]) + (B.z - zl[r]);
+                    float dx = (X.x - xh[r]) + (X.y - xl[r]);
+                    float dy = (Y.x - yh[r]) + (Y.y - yl[r]);
+                    float dz = (Z.x - zh[r]) + (Z.y - zl[r]);
                     float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     float y = __builtin_amdgcn_rsqf(r2);
                     float q = y * (y * y);
                     if (r2 < thr[r] && on && jj < nj) {
-                        if (r2 < fmaxf(r2i[r], B.w)) {
+                        if (r2 < fmaxf(r2i[r], MR.y)) {
                             // FP64 changeover pair from the FP64 state, both bodies
                             const int i = ii[r], j = j0 + jj;
                             const double gx = qx[j] - qx[i], gy = qy[j] - qy[i], gz = qz[j] - qz[i];
@@ -1331,7 +1349,7 @@ __device__ __forceinline__ void sym_tile32c(const float4 *__restrict__ sa, const
                         }
                     }
                     q = on ? q : 0.0f;
-                    const float wi = A.w * q, wj = mi[r] * q;
+                    const float wi = MR.x * q, wj = mi[r] * q;
                     tx[r] = fmaf(wi, dx, tx[r]);
                     ty[r] = fmaf(wi, dy, ty[r]);
                     tz[r] = fmaf(wi, dz, tz[r]);
@@ -1339,16 +1357,15 @@ __device__ __forceinline__ void sym_tile32c(const float4 *__restrict__ sa, const
                     jy = fmaf(-wj, dy, jy);
                     jz = fmaf(-wj, dz, jz);
                 }
-                const int jn = 64 * t + ((lane + 32 * half + kk + 1) & 63);
-                const float4 An = sa[jn], Bn = sb[jn];
-                a.x += (double)jx + ex_;
-                a.y += (double)jy + ey_;
-                a.z += (double)jz + ez_;
-                sacc[jj] = a;
+                L.ax[jj] = a0 + ((double)jx + ex_);
+                L.ay[jj] = a1 + ((double)jy + ey_);
+                L.az[jj] = a2 + ((double)jz + ez_);
                 __asm__ __volatile__("" ::: "memory");
                 jj = jn;
-                A = An;
-                B = Bn;
+                X = Xn;
+                Y = Yn;
+                Z = Zn;
+                MR = MRn;
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -1373,24 +1390,27 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
                                                          int maxs, double inner, DevStats *stats)
 {
     constexpr int T = 64 * R;
-    __shared__ float4 sa[kWaves][T];
-    __shared__ float4 sb[kWaves][T];
-    __shared__ double4 sacc[kWaves][T];
+    __shared__ SymTile32<T> tl[kWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    SymTile32<T> &L = tl[wv];
     int near = 0;
     for (int it = blockIdx.x * kWaves + wv; it < nitems; it += gridDim.x * kWaves) {
         const FWork wk = work[it];
         const bool diag = wk.i0 == wk.j0;
         for (int k = lane; k < T; k += 64) {
-            const int j = wk.j0 + (k < wk.nj ? k : 0);
-            float4 A = pk[2 * (size_t)j], B = pk[2 * (size_t)j + 1];
-            if (k >= wk.nj) {
-                A.w = 0.0f;             // massless copy of the tile's first body
-                B.w = 0.0f;
+            // sources past the tile end: massless and far away (r^2 ~ 1e36, so the
+            // weight underflows to 0 instead of meeting a target at r = 0)
+            if (k < wk.nj) {
+                const float4 A = pk[2 * (size_t)(wk.j0 + k)], B = pk[2 * (size_t)(wk.j0 + k) + 1];
+                L.x[k] = make_float2(A.x, B.x);
+                L.y[k] = make_float2(A.y, B.y);
+                L.z[k] = make_float2(A.z, B.z);
+                L.mr[k] = make_float2(A.w, B.w);
+            } else {
+                L.x[k] = L.y[k] = L.z[k] = make_float2(1e18f, 0.0f);
+                L.mr[k] = make_float2(0.0f, 0.0f);
             }
-            sa[wv][k] = A;
-            sb[wv][k] = B;
-            sacc[wv][k] = make_double4(0.0, 0.0, 0.0, 0.0);
+            L.ax[k] = L.ay[k] = L.az[k] = 0.0;
         }
         wave_lds_sync();
         float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], mi[R], r2i[R], thr[R];
@@ -1414,13 +1434,11 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
             nx[r] = ny[r] = nz[r] = 0.0;
         }
         if (diag)
-            sym_tile32c<R, true>(sa[wv], sb[wv], sacc[wv], lane, wk.ni, wk.nj, wk.j0, inner, qx, qy, qz,
-                                 m, rc, ii, xh, yh, zh, xl, yl, zl, mi, r2i, thr, hx, hy, hz, lx, ly, lz,
-                                 nx, ny, nz, near);
+            sym_tile32c<R, true, T>(L, lane, wk.ni, wk.nj, wk.j0, inner, qx, qy, qz, m, rc, ii, xh, yh, zh,
+                                    xl, yl, zl, mi, r2i, thr, hx, hy, hz, lx, ly, lz, nx, ny, nz, near);
         else
-            sym_tile32c<R, false>(sa[wv], sb[wv], sacc[wv], lane, wk.ni, wk.nj, wk.j0, inner, qx, qy,
-                                  qz, m, rc, ii, xh, yh, zh, xl, yl, zl, mi, r2i, thr, hx, hy, hz, lx,
-                                  ly, lz, nx, ny, nz, near);
+            sym_tile32c<R, false, T>(L, lane, wk.ni, wk.nj, wk.j0, inner, qx, qy, qz, m, rc, ii, xh, yh, zh,
+                                     xl, yl, zl, mi, r2i, thr, hx, hy, hz, lx, ly, lz, nx, ny, nz, near);
         wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -1430,10 +1448,9 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
                 double sy_ = ((double)hy[r] + (double)ly[r]) + ny[r];
                 double sz_ = ((double)hz[r] + (double)lz[r]) + nz[r];
                 if (diag) {
-                    const double4 a = sacc[wv][li];
-                    sx_ += a.x;
-                    sy_ += a.y;
-                    sz_ += a.z;
+                    sx_ += L.ax[li];
+                    sy_ += L.ay[li];
+                    sz_ += L.az[li];
                 }
                 const int i = wk.i0 + li;
                 fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = sx_;
@@ -1443,11 +1460,10 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
         }
         if (!diag) {
             for (int k = lane; k < wk.nj; k += 64) {
-                const double4 a = sacc[wv][k];
                 const int j = wk.j0 + k;
-                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = a.x;
-                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = a.y;
-                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = a.z;
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = L.ax[k];
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = L.ay[k];
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = L.az[k];
             }
         }
         wave_lds_sync();

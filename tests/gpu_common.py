@@ -52,7 +52,9 @@ def pair_scale(m, Q, G, idx=None, chunk=2048):
 
 
 def accel_error(a_gpu, a_ref, A):
-    """max over targets of max-component |error| / A_i."""
+    """max over targets of max-component |error| / A_i (inf if any value is not finite)."""
+    if not np.all(np.isfinite(a_gpu)):
+        return float("inf")
     return float(np.max(np.max(np.abs(a_gpu - a_ref), axis=1) / A))
 
 
