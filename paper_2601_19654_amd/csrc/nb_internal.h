@@ -98,7 +98,10 @@ struct Dev {
     PWork *ework; int new_;
     PWork *dwork; int ndw;
     // scratch
-    double *rpart;        // nrb x 4: per-block partial sums (sum m v, or sum m v + sum m)
+    double *rpart;        // nrb x 8: per-block sums of m V, first half after a kick (or from
+                          // the momentum kernel), second half after a drift (and, with gas
+                          // drag, before a kick)
+    double *rpart_drift() const { return rpart + (size_t)nrb * 4; }
     double *fpart;        // 3 x maxs x ntot force partials
     double *dpart;        // ndw x 4 double-double pair sums (E pair, EK pair)
     double *bpart;        // nrb x 16 body partial sums for diagnostics
@@ -152,12 +155,21 @@ hipError_t launch_validate(const Dev &d, const double *m0, const double *m, cons
                            const double *v, hipStream_t s);
 hipError_t launch_to_dh(const Dev &d, const double *x, const double *v, int frame, hipStream_t s);
 hipError_t launch_from_dh(const Dev &d, double *x, double *v, int frame, hipStream_t s);
-hipError_t launch_momentum(const Dev &d, hipStream_t s);
+// per-block sums of m V into part (rpart or rpart_drift())
+hipError_t launch_momentum(const Dev &d, double *part, hipStream_t s);
 hipError_t launch_kick(const Dev &d, const Params &p, double h, hipStream_t s);
-hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, hipStream_t s);
-hipError_t launch_drift(const Dev &d, const Params &p, double dt, hipStream_t s);
+// S(h) from the per-block sums of m V in `part`; rcrit: also the critical radii
+// (and the FP32C records and per-block largest rc^2)
+hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, const double *part,
+                            hipStream_t s);
+// the drift D(dt), preceded by S(sun_h) from the sums after the kick (sun_h = 0: no
+// sun drift); writes the sums after the drift to rpart_drift()
+hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h, hipStream_t s);
 hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s);
-hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, hipStream_t s);
+// a from the split partials; kick_h != 0: then `kicks` kicks V += kick_h a (and the
+// sums of m V after them into rpart)
+hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, int kicks,
+                                 hipStream_t s);
 hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s);
 hipError_t launch_diagnostics(const Dev &d, const Params &p, hipStream_t s);
 hipError_t launch_persistent_steps(const Dev &d, const Params &p, double dt, int nsteps,

@@ -98,7 +98,7 @@ __device__ __forceinline__ void system_sum(const double *__restrict__ part, int 
 // Changeover weight w = K/r^3 - (dK/dr)/r^2 for a pair at squared distance r2
 // with pair critical radius rc (inner edge `inner` rc).  K = 0 below the inner
 // edge, 1 beyond rc and y^2/(2y^2-2y+1) in between, y = (r - inner rc)/((1-inner) rc).
-__device__ __noinline__ double changeover_w(double r2, double rc, double inner)
+__device__ __forceinline__ double changeover_w_inl(double r2, double rc, double inner)
 {
     if (!(r2 > 0.0))
         return 0.0;
@@ -114,6 +114,12 @@ __device__ __noinline__ double changeover_w(double r2, double rc, double inner)
     double K = y * y / q;
     double dK = 2.0 * y * (1.0 - y) / (q * q * width);
     return (K / r - dK) / r2;
+}
+
+// Out of line: the pair loops call it only for the rare pairs inside rc.
+__device__ __noinline__ double changeover_w(double r2, double rc, double inner)
+{
+    return changeover_w_inl(r2, rc, inner);
 }
 
 // K itself (diagnostics).
@@ -308,9 +314,10 @@ __global__ void k_kick(const RBlk *__restrict__ rblk, double h, const double *__
             a1 += d1;
             a2 += d2;
         }
-        u0 += h * a0;
-        u1 += h * a1;
-        u2 += h * a2;
+        // fused multiply-add, as in k_force_finalize: two kicks there equal two here
+        u0 = fma(h, a0, u0);
+        u1 = fma(h, a1, u1);
+        u2 = fma(h, a2, u2);
         vx[i] = u0;
         vy[i] = u1;
         vz[i] = u2;
@@ -531,7 +538,9 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
                         double *__restrict__ q1x, double *__restrict__ q1y,
                         double *__restrict__ q1z, double *__restrict__ v1x,
                         double *__restrict__ v1y, double *__restrict__ v1z,
-                        double *__restrict__ rc1)
+                        double *__restrict__ rc1, const double *__restrict__ part_in,
+                        double sun_h, const int *__restrict__ rb_first,
+                        const int *__restrict__ rb_count)
 {
     __shared__ double sh[3 * kBlock];
     double lnr_lo = INFINITY, lnr_hi = -INFINITY;
@@ -540,8 +549,20 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
     double mu = G * m0[b.sys];
     bool fail = false;
     double pv[3] = {0.0, 0.0, 0.0};
+    // the sun drift S(sun_h) that precedes the drift, from the per-block sums of
+    // m V in part_in (same arithmetic as k_sun_drift)
+    double sd[3] = {0.0, 0.0, 0.0};
+    if (sun_h != 0.0) {
+        double P[3];
+        system_sum<3>(part_in, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        const double mm = m0[b.sys];
+        sd[0] = sun_h * P[0] / mm;
+        sd[1] = sun_h * P[1] / mm;
+        sd[2] = sun_h * P[2] / mm;
+    }
     if (i < b.end) {
-        double x = qx[i], y = qy[i], z = qz[i], u = vx[i], v = vy[i], w = vz[i];
+        double x = qx[i] + sd[0], y = qy[i] + sd[1], z = qz[i] + sd[2];
+        double u = vx[i], v = vy[i], w = vz[i];
         q0x[i] = x;
         q0y[i] = y;
         q0z[i] = z;
@@ -909,8 +930,6 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
         atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
 }
 
-// a = G * sum over the system's splits (fixed order); optionally the kick
-// V += h a and the partial sums of m V after it.
 // Few sources (every system has at most kFewMax big bodies, one split): each
 // wave owns the 64 R targets of a work item and sums over all of the system's
 // sources, held in the wave's own LDS slice; waves stride over the items and
@@ -1125,50 +1144,84 @@ __device__ __forceinline__ double rinv3(double r2)
     return (y0 * y2) * fma(1.5, e, 1.0);
 }
 
+// Largest value over the wave, returned in a scalar register (every lane active).
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o));
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// max of two non-negative finite floats through their bit patterns (one
+// integer instruction, no NaN handling needed)
+__device__ __forceinline__ float max_nonneg(float a, float b)
+{
+    return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
+}
+
+__device__ __forceinline__ float wave_max_nonneg(float v)
+{
+    for (int o = 32; o > 0; o >>= 1)
+        v = max_nonneg(v, __shfl_xor(v, o));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // Tile J of one wave in LDS, one array per component (consecutive lanes touch
 // consecutive 8-byte words: no bank conflicts for the rotating accesses).
 template <int T>
 struct SymTile64 {
-    double x[T], y[T], z[T], m[T], rc[T];
+    double x[T], y[T], z[T], m[T];
+    double r2[T];                      // max(rc^2, DBL_MIN)
+    double rc[T];
     double ax[T], ay[T], az[T];        // tile J's sums
 };
 
 template <int R, bool DIAG, int T>
-__device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, double inner,
-                                           const double (&xi)[R], const double (&yi)[R],
-                                           const double (&zi)[R], const double (&mi)[R],
-                                           const double (&rci)[R], const double (&r2i)[R],
-                                           const double (&thr)[R], double (&ax)[R], double (&ay)[R],
-                                           double (&az)[R], int &near)
+__device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, int ni, double inner,
+                                           const double *__restrict__ rc, const double (&xi)[R],
+                                           const double (&yi)[R], const double (&zi)[R],
+                                           const double (&mi)[R], double tmi, double (&ax)[R],
+                                           double (&ay)[R], double (&az)[R], int &near)
 {
 #pragma unroll 1
     for (int t = 0; t < R; ++t) {
-        // Lanes update each other's accumulators from step to step: the next
-        // step's loads must stay after this step's stores (LDS operations of a
-        // wave complete in issue order, so program order is enough); sources
-        // are read-only and read one step ahead.
+        // Step k: lane L pairs its targets with source L xor k of sub-tile t,
+        // so the lanes of a step touch distinct sources and each lane meets
+        // every source once in 64 steps.  The sums a step reads were written by
+        // another lane one step earlier: LDS operations of a wave complete in
+        // issue order, and the compiler barrier keeps the read after that
+        // write.  Sources are read-only and read one step ahead.
         int jj = 64 * t + lane;
+        // the largest rc^2 of the wave's targets and of the sub-tile's sources:
+        // one compare per pair outside the rare branch
+        const double thr = fmax(tmi, wave_max(L.r2[jj]));
         double jxs = L.x[jj], jys = L.y[jj], jzs = L.z[jj], jms = L.m[jj];
 #pragma unroll 1
         for (int k = 0; k < 64; ++k) {
-            double a0 = L.ax[jj], a1 = L.ay[jj], a2 = L.az[jj];
-            const int jn = 64 * t + ((lane + k + 1) & 63);
+            const int jn = 64 * t + (lane ^ ((k + 1) & 63));
             const double xn = L.x[jn], yn = L.y[jn], zn = L.z[jn], mn = L.m[jn];
-            double jx = 0.0, jy = 0.0, jz = 0.0;
+            double jx = L.ax[jj], jy = L.ay[jj], jz = L.az[jj];
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double dx = jxs - xi[r], dy = jys - yi[r], dz = jzs - zi[r];
                 const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 double q = rinv3(r2);
-                if (r2 < thr[r]) {
-                    const double rcj = L.rc[jj];
-                    if (r2 < fmax(r2i[r], fmax(rcj * rcj, DBL_MIN))) {
-                        q = changeover_w(r2, fmax(rci[r], rcj), inner);
+                const bool on = !DIAG || (64 * r + lane < jj);
+                if (r2 < thr && on) {
+                    // rare: the target's rc from memory (a padded target is a copy
+                    // of body i0)
+                    const int li = 64 * r + lane;
+                    const double rci = rc[i0 + (li < ni ? li : 0)];
+                    if (r2 < fmax(fmax(rci * rci, DBL_MIN), L.r2[jj])) {
+                        q = changeover_w(r2, fmax(rci, L.rc[jj]), inner);
                         ++near;
                     }
                 }
                 if (DIAG)
-                    q = (64 * r + lane < jj) ? q : 0.0;
+                    q = on ? q : 0.0;
                 const double wi = jms * q, wj = mi[r] * q;
                 ax[r] = fma(wi, dx, ax[r]);
                 ay[r] = fma(wi, dy, ay[r]);
@@ -1177,9 +1230,9 @@ __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, double inn
                 jy = fma(-wj, dy, jy);
                 jz = fma(-wj, dz, jz);
             }
-            L.ax[jj] = a0 + jx;
-            L.ay[jj] = a1 + jy;
-            L.az[jj] = a2 + jz;
+            L.ax[jj] = jx;
+            L.ay[jj] = jy;
+            L.az[jj] = jz;
             __asm__ __volatile__("" ::: "memory");
             jj = jn;
             jxs = xn;
@@ -1197,7 +1250,6 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
                                                         const double *__restrict__ qz,
                                                         const double *__restrict__ m,
                                                         const double *__restrict__ rc,
-                                                        const double *__restrict__ tile_rc2,
                                                         double *__restrict__ fpart, int ntot, int maxs,
                                                         double inner, DevStats *stats)
 {
@@ -1218,12 +1270,14 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
             L.y[k] = ok ? qy[j] : 1e150;
             L.z[k] = ok ? qz[j] : 1e150;
             L.m[k] = ok ? m[j] : 0.0;
-            L.rc[k] = ok ? rc[j] : 0.0;
+            const double rcj = ok ? rc[j] : 0.0;
+            L.rc[k] = rcj;
+            L.r2[k] = fmax(rcj * rcj, DBL_MIN);
             L.ax[k] = L.ay[k] = L.az[k] = 0.0;
         }
         wave_lds_sync();
-        double xi[R], yi[R], zi[R], mi[R], rci[R], r2i[R], thr[R], ax[R], ay[R], az[R];
-        const double tmax = tile_rc2[wk.rb0];
+        double xi[R], yi[R], zi[R], mi[R], ax[R], ay[R], az[R];
+        double tmi = DBL_MIN;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int li = 64 * r + lane;
@@ -1234,15 +1288,16 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
             zi[r] = qz[i];
             // targets past the tile end are massless: they add nothing to tile J
             mi[r] = ok ? m[i] : 0.0;
-            rci[r] = rc[i];
-            r2i[r] = fmax(rci[r] * rci[r], DBL_MIN);
-            thr[r] = fmax(r2i[r], tmax);
+            tmi = fmax(tmi, rc[i] * rc[i]);
             ax[r] = ay[r] = az[r] = 0.0;
         }
+        tmi = wave_max(tmi);
         if (diag)
-            sym_tile64<R, true, T>(L, lane, inner, xi, yi, zi, mi, rci, r2i, thr, ax, ay, az, near);
+            sym_tile64<R, true, T>(L, lane, wk.i0, wk.ni, inner, rc, xi, yi, zi, mi, tmi, ax, ay, az,
+                                   near);
         else
-            sym_tile64<R, false, T>(L, lane, inner, xi, yi, zi, mi, rci, r2i, thr, ax, ay, az, near);
+            sym_tile64<R, false, T>(L, lane, wk.i0, wk.ni, inner, rc, xi, yi, zi, mi, tmi, ax, ay, az,
+                                    near);
         wave_lds_sync();
         // tile I to slot J (on the diagonal together with tile J's sums of the same bodies)
 #pragma unroll
@@ -1278,78 +1333,130 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
         atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
 }
 
-// FP32C form of the symmetric tile pairs: FP32 pair terms from the hi/lo
-// records; tile I's sums in FP32 runs of 32 steps merged by two-sum, tile J's
-// contributions (summed over the R targets in FP32) added in FP64 in LDS;
-// changeover pairs in FP64 from the FP64 state for both bodies.
-// Tile J of one wave in LDS for the FP32C form: (hi, lo) of each coordinate,
-// (mass, widened rc^2) and the FP64 sums, one 8-byte word per lane and array.
+// FP32C form of the symmetric tile pairs.  Pair terms in FP32 from the hi/lo
+// records.  Tile I's sums: FP32 runs of half a sub-tile round (32 steps)
+// merged by two-sum into a (hi, lo) pair per target.  Tile J's sums: an FP32
+// run sum per source in LDS over the same 32 steps, added to the source's FP64
+// total when the run ends.  Changeover pairs in FP64 from the FP64 state: the
+// target's part goes straight to its split partial (read back and added when
+// the item ends), the source's part to its FP64 total.
 template <int T>
 struct SymTile32 {
-    float2 x[T], y[T], z[T], mr[T];
-    double ax[T], ay[T], az[T];
+    float4 a[T];                    // hi parts and mass
+    float4 b[T];                    // lo parts and widened rc^2
+    float4 run[T];                  // current FP32 run sums of tile J (x, y, z, -)
+    double ax[T], ay[T], az[T];     // FP64 totals of tile J (consecutive planes)
 };
 
+// The rare branch of the FP32C pair loop, out of line so that it adds nothing
+// to the loop: target li of the item (body i0 + li, or a padded copy of body i0
+// when li >= ni) against source jj (body j0 + jj) at FP32 squared distance r2.
+// Unless r2 is inside the pair's widened critical radius it returns false.
+// Otherwise the pair is evaluated in FP64 from the FP64 state: m_j w (Q_j - Q_i)
+// goes to the target's split partial at fp[i], fp[plane + i], fp[2 plane + i]
+// (stored when `first`, else added; nothing for a padded target) and
+// -m_i w (Q_j - Q_i) to source jj's FP64 totals tot[jj], tot[T + jj],
+// tot[2 T + jj]; it returns true.
+__device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4 *__restrict__ pk,
+                                               int i0, int li, int ni, int j0, int jj, int T,
+                                               double *tot, double *fp, size_t plane, bool first,
+                                               const double *__restrict__ qx,
+                                               const double *__restrict__ qy,
+                                               const double *__restrict__ qz,
+                                               const double *__restrict__ m,
+                                               const double *__restrict__ rc, double inner)
+{
+    const bool ok = li < ni;
+    const int i = i0 + (ok ? li : 0);
+    if (!(r2 < max_nonneg(pk[2 * (size_t)i + 1].w, r2j)))
+        return false;
+    const int j = j0 + jj;
+    const double gx = qx[j] - qx[i], gy = qy[j] - qy[i], gz = qz[j] - qz[i];
+    const double d2 = fma(gz, gz, fma(gy, gy, gx * gx));
+    const double w = changeover_w_inl(d2, fmax(rc[i], rc[j]), inner);
+    if (ok) {
+        const double wi = m[j] * w;
+        if (first) {
+            fp[i] = wi * gx;
+            fp[plane + i] = wi * gy;
+            fp[2 * plane + i] = wi * gz;
+        } else {
+            fp[i] = fma(wi, gx, fp[i]);
+            fp[plane + i] = fma(wi, gy, fp[plane + i]);
+            fp[2 * plane + i] = fma(wi, gz, fp[2 * plane + i]);
+        }
+        const double wj = m[i] * w;
+        tot[jj] = fma(-wj, gx, tot[jj]);
+        tot[T + jj] = fma(-wj, gy, tot[T + jj]);
+        tot[2 * T + jj] = fma(-wj, gz, tot[2 * T + jj]);
+    }
+    return true;
+}
+
 template <int R, bool DIAG, int T>
-__device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int ni, int nj, int j0,
-                                            double inner, const double *__restrict__ qx,
-                                            const double *__restrict__ qy, const double *__restrict__ qz,
-                                            const double *__restrict__ m, const double *__restrict__ rc,
-                                            const int (&ii)[R], const float (&xh)[R], const float (&yh)[R],
-                                            const float (&zh)[R], const float (&xl)[R], const float (&yl)[R],
-                                            const float (&zl)[R], const float (&mi)[R], const float (&r2i)[R],
-                                            const float (&thr)[R], float (&hx)[R], float (&hy)[R],
-                                            float (&hz)[R], float (&lx)[R], float (&ly)[R], float (&lz)[R],
-                                            double (&nx)[R], double (&ny)[R], double (&nz)[R], int &near)
+__device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, int ni, int j0,
+                                            double *fp, size_t plane, double inner,
+                                            const float4 *__restrict__ pk,
+                                            const double *__restrict__ qx,
+                                            const double *__restrict__ qy,
+                                            const double *__restrict__ qz,
+                                            const double *__restrict__ m,
+                                            const double *__restrict__ rc, const float (&xh)[R],
+                                            const float (&yh)[R], const float (&zh)[R],
+                                            const float (&xl)[R], const float (&yl)[R],
+                                            const float (&zl)[R], const float (&mi)[R], float tmi,
+                                            float (&hx)[R], float (&hy)[R], float (&hz)[R],
+                                            float (&lx)[R], float (&ly)[R], float (&lz)[R],
+                                            int &rare, int &near)
 {
 #pragma unroll 1
     for (int t = 0; t < R; ++t) {
+        // the largest widened rc^2 of the wave's targets and of the sub-tile's
+        // sources: one compare per pair outside the rare branch
+        const float thr = max_nonneg(tmi, wave_max_nonneg(L.b[64 * t + lane].w));
 #pragma unroll 1
         for (int half = 0; half < 2; ++half) {
             float tx[R], ty[R], tz[R];
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 tx[r] = ty[r] = tz[r] = 0.0f;
-            // see sym_tile64 for the order of the accumulator updates
-            int jj = 64 * t + ((lane + 32 * half) & 63);
-            float2 X = L.x[jj], Y = L.y[jj], Z = L.z[jj], MR = L.mr[jj];
-#pragma unroll 1
+            // Step k: lane L pairs its targets with source L xor k of sub-tile t,
+            // so the lanes of a step touch distinct sources and each lane meets
+            // every source once in 64 steps.  The run sum a step reads was
+            // written by another lane one step earlier: LDS operations of a
+            // wave complete in issue order, and the compiler barrier keeps the
+            // read after that write.  Source records are read-only and fetched
+            // one step ahead.
+            const int k0 = 32 * half;
+            int jj = 64 * t + (lane ^ k0);
+            float4 A = L.a[jj], B = L.b[jj];
+#pragma unroll 2
             for (int kk = 0; kk < 32; ++kk) {
-                const double a0 = L.ax[jj], a1 = L.ay[jj], a2 = L.az[jj];
-                const int jn = 64 * t + ((lane + 32 * half + kk + 1) & 63);
-                const float2 Xn = L.x[jn], Yn = L.y[jn], Zn = L.z[jn], MRn = L.mr[jn];
-                float jx = 0.0f, jy = 0.0f, jz = 0.0f;
-                double ex_ = 0.0, ey_ = 0.0, ez_ = 0.0;
+                const int jn = 64 * t + (lane ^ ((k0 + kk + 1) & 63));
+                const float4 An = L.a[jn], Bn = L.b[jn];
+                const float4 S = L.run[jj];
+                float jx = S.x, jy = S.y, jz = S.z;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const bool on = !DIAG || (64 * r + lane < jj);
-                    float dx = (X.x - xh[r]) + (X.y - xl[r]);
-                    float dy = (Y.x - yh[r]) + (Y.y - yl[r]);
-                    float dz = (Z.x - zh[r]) + (Z.y - zl[r]);
-                    float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    float y = __builtin_amdgcn_rsqf(r2);
+                    const float dx = (A.x - xh[r]) + (B.x - xl[r]);
+                    const float dy = (A.y - yh[r]) + (B.y - yl[r]);
+                    const float dz = (A.z - zh[r]) + (B.z - zl[r]);
+                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                    const float y = __builtin_amdgcn_rsqf(r2);
                     float q = y * (y * y);
-                    if (r2 < thr[r] && on && jj < nj) {
-                        if (r2 < fmaxf(r2i[r], MR.y)) {
-                            // FP64 changeover pair from the FP64 state, both bodies
-                            const int i = ii[r], j = j0 + jj;
-                            const double gx = qx[j] - qx[i], gy = qy[j] - qy[i], gz = qz[j] - qz[i];
-                            const double d2 = fma(gz, gz, fma(gy, gy, gx * gx));
-                            const double wgt = changeover_w(d2, fmax(rc[i], rc[j]), inner);
-                            const double wi = m[j] * wgt;
-                            const double wj = (64 * r + lane < ni ? m[i] : 0.0) * wgt;
-                            nx[r] = fma(wi, gx, nx[r]);
-                            ny[r] = fma(wi, gy, ny[r]);
-                            nz[r] = fma(wi, gz, nz[r]);
-                            ex_ = fma(-wj, gx, ex_);
-                            ey_ = fma(-wj, gy, ey_);
-                            ez_ = fma(-wj, gz, ez_);
+                    const bool on = !DIAG || (64 * r + lane < jj);
+                    if (r2 < thr && on) {
+                        if (changeover_pair32(r2, L.b[jj].w, pk, i0, 64 * r + lane, ni, j0, jj, T,
+                                              L.ax, fp, plane, !((rare >> r) & 1), qx, qy, qz, m,
+                                              rc, inner)) {
+                            rare |= 1 << r;
                             q = 0.0f;
                             ++near;
                         }
                     }
-                    q = on ? q : 0.0f;
-                    const float wi = MR.x * q, wj = mi[r] * q;
+                    if (DIAG)
+                        q = on ? q : 0.0f;
+                    const float wi = A.w * q, wj = mi[r] * q;
                     tx[r] = fmaf(wi, dx, tx[r]);
                     ty[r] = fmaf(wi, dy, ty[r]);
                     tz[r] = fmaf(wi, dz, tz[r]);
@@ -1357,15 +1464,11 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int ni, i
                     jy = fmaf(-wj, dy, jy);
                     jz = fmaf(-wj, dz, jz);
                 }
-                L.ax[jj] = a0 + ((double)jx + ex_);
-                L.ay[jj] = a1 + ((double)jy + ey_);
-                L.az[jj] = a2 + ((double)jz + ez_);
+                L.run[jj] = make_float4(jx, jy, jz, 0.0f);
                 __asm__ __volatile__("" ::: "memory");
                 jj = jn;
-                X = Xn;
-                Y = Yn;
-                Z = Zn;
-                MR = MRn;
+                A = An;
+                B = Bn;
             }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -1373,6 +1476,15 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int ni, i
                 two_sum_f(hy[r], ly[r], ty[r]);
                 two_sum_f(hz[r], lz[r], tz[r]);
             }
+            // end of the run: every source of sub-tile t had its 32 steps; lane
+            // L moves source 64 t + L's run sum into its FP64 total
+            const int js = 64 * t + lane;
+            const float4 S = L.run[js];
+            L.ax[js] += (double)S.x;
+            L.ay[js] += (double)S.y;
+            L.az[js] += (double)S.z;
+            L.run[js] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            __asm__ __volatile__("" ::: "memory");
         }
     }
 }
@@ -1385,7 +1497,6 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
                                                          const double *__restrict__ qz,
                                                          const double *__restrict__ m,
                                                          const double *__restrict__ rc,
-                                                         const double *__restrict__ tile_rc2,
                                                          double *__restrict__ fpart, int ntot,
                                                          int maxs, double inner, DevStats *stats)
 {
@@ -1393,6 +1504,7 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
     __shared__ SymTile32<T> tl[kWaves];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     SymTile32<T> &L = tl[wv];
+    const size_t plane = (size_t)maxs * ntot;
     int near = 0;
     for (int it = blockIdx.x * kWaves + wv; it < nitems; it += gridDim.x * kWaves) {
         const FWork wk = work[it];
@@ -1401,61 +1513,66 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
             // sources past the tile end: massless and far away (r^2 ~ 1e36, so the
             // weight underflows to 0 instead of meeting a target at r = 0)
             if (k < wk.nj) {
-                const float4 A = pk[2 * (size_t)(wk.j0 + k)], B = pk[2 * (size_t)(wk.j0 + k) + 1];
-                L.x[k] = make_float2(A.x, B.x);
-                L.y[k] = make_float2(A.y, B.y);
-                L.z[k] = make_float2(A.z, B.z);
-                L.mr[k] = make_float2(A.w, B.w);
+                L.a[k] = pk[2 * (size_t)(wk.j0 + k)];
+                L.b[k] = pk[2 * (size_t)(wk.j0 + k) + 1];
             } else {
-                L.x[k] = L.y[k] = L.z[k] = make_float2(1e18f, 0.0f);
-                L.mr[k] = make_float2(0.0f, 0.0f);
+                L.a[k] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+                L.b[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
+            L.run[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             L.ax[k] = L.ay[k] = L.az[k] = 0.0;
         }
         wave_lds_sync();
-        float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], mi[R], r2i[R], thr[R];
+        float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], mi[R];
         float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
-        double nx[R], ny[R], nz[R];
-        int ii[R];
-        const float tmax = (float)(tile_rc2[wk.rb0] * (1.0 + 0x1p-9));
+        float tmi = 0.0f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int li = 64 * r + lane;
             const bool ok = li < wk.ni;
             const int i = wk.i0 + (ok ? li : 0);
-            ii[r] = i;
             const float4 A = pk[2 * (size_t)i], B = pk[2 * (size_t)i + 1];
             xh[r] = A.x; yh[r] = A.y; zh[r] = A.z;
             xl[r] = B.x; yl[r] = B.y; zl[r] = B.z;
+            // targets past the tile end are massless: they add nothing to tile J
             mi[r] = ok ? A.w : 0.0f;
-            r2i[r] = B.w;
-            thr[r] = fmaxf(r2i[r], tmax);
+            tmi = max_nonneg(tmi, B.w);
             hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
-            nx[r] = ny[r] = nz[r] = 0.0;
         }
+        tmi = wave_max_nonneg(tmi);
+        // bit r: target r's split partial already holds FP64 changeover terms
+        int rare = 0;
+        double *fp = fpart + (size_t)wk.slot * ntot;
         if (diag)
-            sym_tile32c<R, true, T>(L, lane, wk.ni, wk.nj, wk.j0, inner, qx, qy, qz, m, rc, ii, xh, yh, zh,
-                                    xl, yl, zl, mi, r2i, thr, hx, hy, hz, lx, ly, lz, nx, ny, nz, near);
+            sym_tile32c<R, true, T>(L, lane, wk.i0, wk.ni, wk.j0, fp, plane, inner, pk, qx, qy, qz, m,
+                                    rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx, hy, hz, lx, ly, lz, rare,
+                                    near);
         else
-            sym_tile32c<R, false, T>(L, lane, wk.ni, wk.nj, wk.j0, inner, qx, qy, qz, m, rc, ii, xh, yh, zh,
-                                     xl, yl, zl, mi, r2i, thr, hx, hy, hz, lx, ly, lz, nx, ny, nz, near);
+            sym_tile32c<R, false, T>(L, lane, wk.i0, wk.ni, wk.j0, fp, plane, inner, pk, qx, qy, qz,
+                                     m, rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx, hy, hz, lx, ly, lz,
+                                     rare, near);
         wave_lds_sync();
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int li = 64 * r + lane;
             if (li < wk.ni) {
-                double sx_ = ((double)hx[r] + (double)lx[r]) + nx[r];
-                double sy_ = ((double)hy[r] + (double)ly[r]) + ny[r];
-                double sz_ = ((double)hz[r] + (double)lz[r]) + nz[r];
+                const int i = wk.i0 + li;
+                double sx_ = (double)hx[r] + (double)lx[r];
+                double sy_ = (double)hy[r] + (double)ly[r];
+                double sz_ = (double)hz[r] + (double)lz[r];
+                if ((rare >> r) & 1) {
+                    sx_ += fp[i];
+                    sy_ += fp[plane + i];
+                    sz_ += fp[2 * plane + i];
+                }
                 if (diag) {
                     sx_ += L.ax[li];
                     sy_ += L.ay[li];
                     sz_ += L.az[li];
                 }
-                const int i = wk.i0 + li;
-                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = sx_;
-                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = sy_;
-                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = sz_;
+                fp[i] = sx_;
+                fp[plane + i] = sy_;
+                fp[2 * plane + i] = sz_;
             }
         }
         if (!diag) {
@@ -1474,23 +1591,66 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
         atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
 }
 
-__global__ void k_force_finalize(const RBlk *__restrict__ rblk, const int *__restrict__ nsplit,
-                                 const double *__restrict__ fpart, int ntot, int maxs, double G,
-                                 double *__restrict__ ax, double *__restrict__ ay,
-                                 double *__restrict__ az, double h, const double *__restrict__ m,
-                                 double *vx, double *vy, double *vz, double *__restrict__ part_out)
+// a = G * sum over the system's splits (fixed order); optionally `kicks` (1 or
+// 2) kicks V += h a, rounded as that many k_kick launches, and the partial sums
+// of m V after them.  The split partials of a
+// block's bodies are read by kFinGroups thread groups,
+// group g taking slots [g ns / G, (g + 1) ns / G) in order; the group sums are
+// added in group order (fixed summation order, several loads in flight per body).
+constexpr int kFinGroups = 4;
+
+__global__ __launch_bounds__(kBlock * kFinGroups) void k_force_finalize(
+    const RBlk *__restrict__ rblk, const int *__restrict__ nsplit, const double *__restrict__ fpart,
+    int ntot, int maxs, double G, double *__restrict__ ax, double *__restrict__ ay,
+    double *__restrict__ az, double h, int kicks, const double *__restrict__ m, double *vx,
+    double *vy, double *vz, double *__restrict__ part_out)
 {
+    __shared__ double gs[kFinGroups - 1][3][kBlock];
     __shared__ double sh[3 * kBlock];
-    RBlk b = rblk[blockIdx.x];
-    int ns = nsplit[b.sys];
-    int i = b.start + threadIdx.x;
-    double pv[3] = {0.0, 0.0, 0.0};
+    const RBlk b = rblk[blockIdx.x];
+    const int ns = nsplit[b.sys];
+    const int t = threadIdx.x % kBlock, g = threadIdx.x / kBlock;
+    const int i = b.start + t;
+    const int k0 = g * ns / kFinGroups, k1 = (g + 1) * ns / kFinGroups;
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     if (i < b.end) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        for (int k = 0; k < ns; ++k) {
-            s0 += fpart[((size_t)0 * maxs + k) * ntot + i];
-            s1 += fpart[((size_t)1 * maxs + k) * ntot + i];
-            s2 += fpart[((size_t)2 * maxs + k) * ntot + i];
+        const double *px = fpart + i, *py = px + (size_t)maxs * ntot, *pz = py + (size_t)maxs * ntot;
+        int k = k0;
+        // eight slots' loads in flight, then added in slot order
+        for (; k + 8 <= k1; k += 8) {
+            double ux[8], uy[8], uz[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                ux[u] = px[(size_t)(k + u) * ntot];
+                uy[u] = py[(size_t)(k + u) * ntot];
+                uz[u] = pz[(size_t)(k + u) * ntot];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                s0 += ux[u];
+                s1 += uy[u];
+                s2 += uz[u];
+            }
+        }
+        for (; k < k1; ++k) {
+            s0 += px[(size_t)k * ntot];
+            s1 += py[(size_t)k * ntot];
+            s2 += pz[(size_t)k * ntot];
+        }
+    }
+    if (g > 0) {
+        gs[g - 1][0][t] = s0;
+        gs[g - 1][1][t] = s1;
+        gs[g - 1][2][t] = s2;
+    }
+    __syncthreads();
+    double pv[3] = {0.0, 0.0, 0.0};
+    if (g == 0 && i < b.end) {
+#pragma unroll
+        for (int q = 0; q < kFinGroups - 1; ++q) {
+            s0 += gs[q][0][t];
+            s1 += gs[q][1][t];
+            s2 += gs[q][2][t];
         }
         s0 *= G;
         s1 *= G;
@@ -1500,7 +1660,12 @@ __global__ void k_force_finalize(const RBlk *__restrict__ rblk, const int *__res
         az[i] = s2;
         if (h != 0.0) {
             double mi = m[i];
-            double u0 = vx[i] + h * s0, u1 = vy[i] + h * s1, u2 = vz[i] + h * s2;
+            double u0 = fma(h, s0, vx[i]), u1 = fma(h, s1, vy[i]), u2 = fma(h, s2, vz[i]);
+            if (kicks == 2) {
+                u0 = fma(h, s0, u0);
+                u1 = fma(h, s1, u1);
+                u2 = fma(h, s2, u2);
+            }
             vx[i] = u0;
             vy[i] = u1;
             vz[i] = u2;
@@ -1510,11 +1675,25 @@ __global__ void k_force_finalize(const RBlk *__restrict__ rblk, const int *__res
         }
     }
     if (part_out) {
-        block_sum<3>(pv, sh);
+        // the block's m V sums over group 0's threads, same tree as block_sum
+        if (g == 0) {
+#pragma unroll
+            for (int w = 0; w < 3; ++w)
+                sh[w * kBlock + t] = pv[w];
+        }
+        __syncthreads();
+        for (int st = kBlock / 2; st > 0; st >>= 1) {
+            if (g == 0 && t < st) {
+#pragma unroll
+                for (int w = 0; w < 3; ++w)
+                    sh[w * kBlock + t] += sh[w * kBlock + t + st];
+            }
+            __syncthreads();
+        }
         if (threadIdx.x == 0) {
-            part_out[(size_t)blockIdx.x * 4 + 0] = pv[0];
-            part_out[(size_t)blockIdx.x * 4 + 1] = pv[1];
-            part_out[(size_t)blockIdx.x * 4 + 2] = pv[2];
+            part_out[(size_t)blockIdx.x * 4 + 0] = sh[0];
+            part_out[(size_t)blockIdx.x * 4 + 1] = sh[kBlock];
+            part_out[(size_t)blockIdx.x * 4 + 2] = sh[2 * kBlock];
             part_out[(size_t)blockIdx.x * 4 + 3] = 0.0;
         }
     }
@@ -2797,11 +2976,11 @@ hipError_t launch_from_dh(const Dev &d, double *x, double *v, int frame, hipStre
     return hipGetLastError();
 }
 
-hipError_t launch_momentum(const Dev &d, hipStream_t s)
+hipError_t launch_momentum(const Dev &d, double *part, hipStream_t s)
 {
     if (d.nrb == 0)
         return hipSuccess;
-    k_partial_mv<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m, d.vx, d.vy, d.vz, d.rpart);
+    k_partial_mv<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m, d.vx, d.vy, d.vz, part);
     return hipGetLastError();
 }
 
@@ -2820,7 +2999,7 @@ hipError_t launch_kick(const Dev &d, const Params &p, double h, hipStream_t s)
 {
     if (d.nrb == 0)
         return hipSuccess;
-    double *part_b = d.rpart + (size_t)d.nrb * 4;
+    double *part_b = d.rpart_drift();
     if (p.drag) {
         // partial sums of m V before the kick, for the heliocentric velocity
         k_partial_mv<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m, d.vx, d.vy, d.vz, part_b);
@@ -2835,25 +3014,27 @@ hipError_t launch_kick(const Dev &d, const Params &p, double h, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, hipStream_t s)
+hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, const double *part,
+                            hipStream_t s)
 {
     if (d.nrb == 0)
         return hipSuccess;
-    k_sun_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, d.rpart, h, d.qx,
+    k_sun_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, part, h, d.qx,
                                           d.qy, d.qz, rcrit, d.m, p.n_hill, d.rc,
                                           p.mode == 1 ? d.pk : nullptr, d.tile_rc2);
     return hipGetLastError();
 }
 
-hipError_t launch_drift(const Dev &d, const Params &p, double dt, hipStream_t s)
+hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h, hipStream_t s)
 {
     if (d.nrb == 0)
         return hipSuccess;
     k_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, dt, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
                                       d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
-                                      d.stats, d.rpart, d.rc, d.mr, d.cr,
+                                      d.stats, d.rpart_drift(), d.rc, d.mr, d.cr,
                                       d.enc_sorted ? d.lnr_part : nullptr, d.q1x, d.q1y, d.q1z,
-                                      d.v1x, d.v1y, d.v1z, d.rc1);
+                                      d.v1x, d.v1y, d.v1z, d.rc1, d.rpart, sun_h, d.rb_first,
+                                      d.rb_count);
     return hipGetLastError();
 }
 
@@ -2863,9 +3044,9 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
         return hipSuccess;
     if (d.force_sym) {
         const int grid = std::min(cdiv(d.nfw, kWaves), 4096);
-#define NB_SYM_ARGS d.fwork, d.nfw, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart, d.ntot, d.maxs, \
+#define NB_SYM_ARGS d.fwork, d.nfw, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart, d.ntot, d.maxs, \
                     p.inner, d.stats
-#define NB_SYM32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart, d.ntot, \
+#define NB_SYM32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart, d.ntot, \
                       d.maxs, p.inner, d.stats
         if (p.mode == 1) {
             if (p.force_r == 1)
@@ -2947,13 +3128,14 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, hipStream_t s)
+hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, int kicks,
+                                 hipStream_t s)
 {
     if (d.nrb == 0)
         return hipSuccess;
-    k_force_finalize<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.nsplit, d.fpart, d.ntot, d.maxs, p.G, d.ax,
-                                               d.ay, d.az, kick_h, d.m, d.vx, d.vy, d.vz,
-                                               kick_h != 0.0 ? d.rpart : nullptr);
+    k_force_finalize<<<d.nrb, kBlock * kFinGroups, 0, s>>>(
+        d.rblk, d.nsplit, d.fpart, d.ntot, d.maxs, p.G, d.ax, d.ay, d.az, kick_h, kicks, d.m, d.vx,
+        d.vy, d.vz, kick_h != 0.0 ? d.rpart : nullptr);
     return hipGetLastError();
 }
 

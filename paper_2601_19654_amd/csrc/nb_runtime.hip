@@ -463,63 +463,87 @@ int reset_stats(nb_ctx *c)
 // Critical radii (and FP32 source records), then the force at the current Q.
 int enqueue_force(nb_ctx *c)
 {
-    HIP_OK(c, launch_sun_drift(c->d, 0.0, 1, c->p, c->stream));
+    HIP_OK(c, launch_sun_drift(c->d, 0.0, 1, c->p, c->d.rpart, c->stream));
     HIP_OK(c, launch_force(c->d, c->p, c->stream));
-    HIP_OK(c, launch_force_finalize(c->d, c->p, 0.0, c->stream));
+    HIP_OK(c, launch_force_finalize(c->d, c->p, 0.0, 1, c->stream));
     return NB_OK;
 }
 
-// One hybrid step K(h) S(h) D(dt) C S(h) [rc, F] K(h).
-// K(h) S(h) D(dt) C of a step.
-int enqueue_step_head(nb_ctx *c, double dt)
+// One hybrid step K(h) S(h) D(dt) C S(h) [rc, F] K(h).  In a run of steps the
+// closing K(h) of one step and the opening K(h) of the next are one launch that
+// kicks twice (rounded as two kicks): only the run's first step opens with a
+// kick launch (`first`), only its last closes with a single kick (`last`).  Not
+// with gas drag, whose kick depends on V and the heliocentric correction.
+bool merged_kicks(const nb_ctx *c)
+{
+    return !c->p.drag;
+}
+
+// K(h) S(h) D(dt) C of a step (S(h) inside the drift launch).
+int enqueue_step_head(nb_ctx *c, double dt, bool first)
 {
     const double h = 0.5 * dt;
     const Dev &d = c->d;
-    HIP_OK(c, launch_kick(d, c->p, h, c->stream));
-    HIP_OK(c, launch_sun_drift(d, h, 0, c->p, c->stream));
-    HIP_OK(c, launch_drift(d, c->p, dt, c->stream));
+    if (first)
+        HIP_OK(c, launch_kick(d, c->p, h, c->stream));
+    HIP_OK(c, launch_drift(d, c->p, dt, h, c->stream));
     HIP_OK(c, launch_encounters(d, dt, c->stream));
     return NB_OK;
 }
 
-// S(h), critical radii, F, K(h) of a step.
-int enqueue_step_tail(nb_ctx *c, double dt)
+// S(h), critical radii, F, K(h) of a step (and the next step's K(h) unless `last`).
+int enqueue_step_tail(nb_ctx *c, double dt, bool last)
 {
     const double h = 0.5 * dt;
     const Dev &d = c->d;
-    HIP_OK(c, launch_sun_drift(d, h, 1, c->p, c->stream));
+    HIP_OK(c, launch_sun_drift(d, h, 1, c->p, d.rpart_drift(), c->stream));
     HIP_OK(c, launch_force(d, c->p, c->stream));
     if (c->p.drag) {
-        HIP_OK(c, launch_force_finalize(d, c->p, 0.0, c->stream));
+        HIP_OK(c, launch_force_finalize(d, c->p, 0.0, 1, c->stream));
         HIP_OK(c, launch_kick(d, c->p, h, c->stream));
     } else {
-        HIP_OK(c, launch_force_finalize(d, c->p, h, c->stream));
+        HIP_OK(c, launch_force_finalize(d, c->p, h, last ? 1 : 2, c->stream));
     }
     return NB_OK;
 }
 
-int enqueue_step(nb_ctx *c, double dt)
+int enqueue_step(nb_ctx *c, double dt, bool first, bool last)
 {
     if (c->side) {
         // fork after the drift: the encounter check reads only the drift's
-        // snapshots (Q0, V0, Q1, V1, rc) and runs beside S(h), the force and K(h)
+        // snapshots (Q0, V0, Q1, V1, rc) and runs beside S(h), the force and K(h).
+        // The rest of the step is enqueued (and, under capture, recorded) before
+        // the branch, so that the step's own chain keeps the stream's queue and
+        // only the branch and the join cross queues.
         const double h = 0.5 * dt;
         const Dev &d = c->d;
-        HIP_OK(c, launch_kick(d, c->p, h, c->stream));
-        HIP_OK(c, launch_sun_drift(d, h, 0, c->p, c->stream));
-        HIP_OK(c, launch_drift(d, c->p, dt, c->stream));
+        if (first)
+            HIP_OK(c, launch_kick(d, c->p, h, c->stream));
+        HIP_OK(c, launch_drift(d, c->p, dt, h, c->stream));
         HIP_OK(c, hipEventRecord(c->ev_fork, c->stream));
+        int r = enqueue_step_tail(c, dt, last);
+        if (r)
+            return r;
         HIP_OK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
         HIP_OK(c, launch_encounters(d, dt, c->side));
         HIP_OK(c, hipEventRecord(c->ev_join, c->side));
-        int r = enqueue_step_tail(c, dt);
-        if (r)
-            return r;
         HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
         return NB_OK;
     }
-    int r = enqueue_step_head(c, dt);
-    return r ? r : enqueue_step_tail(c, dt);
+    int r = enqueue_step_head(c, dt, first);
+    return r ? r : enqueue_step_tail(c, dt, last);
+}
+
+// A run of `steps` steps (kicks merged between them).
+int enqueue_run(nb_ctx *c, double dt, int steps)
+{
+    const bool merge = merged_kicks(c);
+    for (int k = 0; k < steps; ++k) {
+        int r = enqueue_step(c, dt, k == 0 || !merge, k == steps - 1 || !merge);
+        if (r)
+            return r;
+    }
+    return NB_OK;
 }
 
 // Between C and the second S(h) of the full method.  The device packs both ends
@@ -603,6 +627,8 @@ int resolve_step(nb_ctx *c, double dt)
     HIP_OK(c, hipMemcpyAsync(d.res_rows, c->h_rows, (size_t)k * 7 * sizeof(double),
                              hipMemcpyHostToDevice, c->stream));
     HIP_OK(c, launch_scatter_members(d, k, c->stream));
+    // the second S(h) takes the momentum of the resolved velocities
+    HIP_OK(c, launch_momentum(d, d.rpart_drift(), c->stream));
     return NB_OK;
 }
 
@@ -620,9 +646,7 @@ int build_graph(nb_ctx *c, double dt, int steps)
     drop_graph(c);
     hipGraph_t g = nullptr;
     HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-    int rc = NB_OK;
-    for (int k = 0; k < steps && rc == NB_OK; ++k)
-        rc = enqueue_step(c, dt);
+    int rc = enqueue_run(c, dt, steps);
     hipError_t e = hipStreamEndCapture(c->stream, &g);
     if (rc != NB_OK) {
         if (g)
@@ -650,8 +674,8 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
     if (c->p.resolve) {
         // the host takes part in every step: direct launches, no graph
         for (; done < nsteps; ++done) {
-            if ((r = enqueue_step_head(c, dt)) || (r = resolve_step(c, dt)) ||
-                (r = enqueue_step_tail(c, dt)))
+            if ((r = enqueue_step_head(c, dt, true)) || (r = resolve_step(c, dt)) ||
+                (r = enqueue_step_tail(c, dt, true)))
                 return r;
         }
         return NB_OK;
@@ -679,9 +703,13 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
             done += c->graph_steps;
         }
     }
-    for (; done < nsteps; ++done)
-        if ((r = enqueue_step(c, dt)))
+    // direct launches: runs of the graph's length, then the remainder
+    while (done < nsteps) {
+        const int g = std::min(nsteps - done, kMaxGraphSteps);
+        if ((r = enqueue_run(c, dt, g)))
             return r;
+        done += g;
+    }
     return NB_OK;
 }
 
@@ -988,8 +1016,8 @@ int nb_sun_drift(nb_ctx *c, double h)
     if (!std::isfinite(h))
         return set_err(c, NB_E_INVALID, "nb_sun_drift: h not finite");
     c->have_drift = false;
-    HIP_OK(c, launch_momentum(c->d, c->stream));
-    HIP_OK(c, launch_sun_drift(c->d, h, 0, c->p, c->stream));
+    HIP_OK(c, launch_momentum(c->d, c->d.rpart, c->stream));
+    HIP_OK(c, launch_sun_drift(c->d, h, 0, c->p, c->d.rpart, c->stream));
     return NB_OK;
 }
 
@@ -1003,7 +1031,7 @@ int nb_drift(nb_ctx *c, double dt, int *nfail)
     if (!std::isfinite(dt))
         return set_err(c, NB_E_INVALID, "nb_drift: dt not finite");
     HIP_OK(c, launch_fill_i32(&c->d.stats->cur_kfail, 1, 0, c->stream));
-    HIP_OK(c, launch_drift(c->d, c->p, dt, c->stream));
+    HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->stream));
     int nf = 0;
     if ((r = read_int(c, &c->d.stats->cur_kfail, &nf)))
         return r;
@@ -1175,7 +1203,7 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
             HIP_OK(c, launch_encounters(c->d, c->last_dt, c->stream));
             return NB_OK;
         case NB_K_DRIFT:
-            HIP_OK(c, launch_drift(c->d, c->p, dt, c->stream));
+            HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->stream));
             return NB_OK;
         case NB_K_FORCE_EVAL:
             return enqueue_force(c);
