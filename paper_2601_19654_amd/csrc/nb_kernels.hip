@@ -2204,19 +2204,21 @@ __device__ __forceinline__ bool may_meet(const double cmA[3], double smA, const 
     return !(lhs > RC * RC * (1.0 + 1e-6) + 1e-12 * Qmax * Qmax);
 }
 
-// One block per tile A: its threads test the tiles B >= A of the same system and
-// append the pairs that may meet.
-__global__ __launch_bounds__(kBlock) void k_tile_pairs(const Tile *__restrict__ tiles,
+// One wave per tile A (four per workgroup): its lanes test the tiles B >= A of
+// the same system, 64 at a time, and append the pairs that may meet.
+__global__ __launch_bounds__(kBlock) void k_tile_pairs(const Tile *__restrict__ tiles, int ntile,
                                                        const TileB *__restrict__ tileb,
                                                        int2 *__restrict__ tpairs, int tp_cap,
                                                        DevStats *stats)
 {
-    const int A = blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int A = blockIdx.x * kWaves + (threadIdx.x >> 6);
+    if (A >= ntile)
+        return;
     const Tile TA = tiles[A];
     const TileB BA = tileb[A];
-    const int lane = threadIdx.x & 63;
-    for (int b0 = A; b0 <= TA.last; b0 += kBlock) {
-        const int B = b0 + threadIdx.x;
+    for (int b0 = A; b0 <= TA.last; b0 += 64) {
+        const int B = b0 + lane;
         // two small bodies never interact: a pair of tiles without a big body is skipped
         const bool ok = B <= TA.last && (BA.big || tileb[B].big) &&
                         may_meet(BA.cm, BA.sm, BA.cc, BA.sc, BA.ce, BA.se, BA.rc, tileb[B]);
@@ -3172,7 +3174,8 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
         if (d.ntile > 0) {
             k_tile_bounds<<<cdiv(d.ntile, kBlock / 64), kBlock, 0, s>>>(d.tiles, d.ntile, d.srec, dt,
                                                                          d.tileb);
-            k_tile_pairs<<<d.ntile, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.stats);
+            k_tile_pairs<<<cdiv(d.ntile, kWaves), kBlock, 0, s>>>(d.tiles, d.ntile, d.tileb, d.tpairs,
+                                                                   d.tp_cap, d.stats);
             int grid = std::min(std::max(1, d.tp_cap), 8192);
             k_enc_pairs<<<grid, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.srec, dt,
                                                  d.keys, d.enc_cap, d.ce, d.stats);
