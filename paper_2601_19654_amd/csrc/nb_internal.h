@@ -122,6 +122,7 @@ struct Dev {
     Tile *tiles; int ntile;
     TileB *tileb;         // ntile
     int2 *tpairs; int tp_cap;
+    int2 *units; int nunit;   // culling units: tile A against tiles [b0, b0 + 64) (B >= A)
     // persistent step launch
     PSys *psys; int npsys; int pmax_n;
     int *step_nce; int step_chunk;   // flagged pairs per step of one launch

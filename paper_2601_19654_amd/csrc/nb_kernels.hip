@@ -2204,37 +2204,63 @@ __device__ __forceinline__ bool may_meet(const double cmA[3], double smA, const 
     return !(lhs > RC * RC * (1.0 + 1e-6) + 1e-12 * Qmax * Qmax);
 }
 
-// One wave per tile A (four per workgroup): its lanes test the tiles B >= A of
-// the same system, 64 at a time, and append the pairs that may meet.
-__global__ __launch_bounds__(kBlock) void k_tile_pairs(const Tile *__restrict__ tiles, int ntile,
-                                                       const TileB *__restrict__ tileb,
-                                                       int2 *__restrict__ tpairs, int tp_cap,
-                                                       DevStats *stats)
+// One wave per culling unit (tile A against tiles [b0, b0 + 64) of the same
+// system with B >= A; kTpWaves units per workgroup): its lanes test one tile B
+// each and the pairs that may meet are appended.  The survivors are counted
+// first and the workgroup reserves its whole range with one atomic (a counter
+// that every wave of the grid hits is a serial point), then the test is
+// repeated to write the pairs.
+constexpr int kTpWaves = 16;
+
+__device__ __forceinline__ bool tile_pair_kept(const Tile &TA, const TileB &BA,
+                                               const TileB *__restrict__ tileb, int B)
 {
-    const int lane = threadIdx.x & 63;
-    const int A = blockIdx.x * kWaves + (threadIdx.x >> 6);
-    if (A >= ntile)
-        return;
-    const Tile TA = tiles[A];
-    const TileB BA = tileb[A];
-    for (int b0 = A; b0 <= TA.last; b0 += 64) {
-        const int B = b0 + lane;
-        // two small bodies never interact: a pair of tiles without a big body is skipped
-        const bool ok = B <= TA.last && (BA.big || tileb[B].big) &&
-                        may_meet(BA.cm, BA.sm, BA.cc, BA.sc, BA.ce, BA.se, BA.rc, tileb[B]);
-        const unsigned long long mask = __ballot(ok);
-        if (mask) {
-            const int leader = __ffsll((long long)mask) - 1;
-            int base = 0;
-            if (lane == leader)
-                base = atomicAdd(&stats->cur_tp, (int)__popcll(mask));
-            base = __shfl(base, leader);
-            if (ok) {
-                const int pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
-                if (pos < tp_cap)
-                    tpairs[pos] = make_int2(A, B);
-            }
+    // two small bodies never interact: a pair of tiles without a big body is skipped
+    return B <= TA.last && (BA.big || tileb[B].big) &&
+           may_meet(BA.cm, BA.sm, BA.cc, BA.sc, BA.ce, BA.se, BA.rc, tileb[B]);
+}
+
+__global__ __launch_bounds__(64 * kTpWaves) void k_tile_pairs(const Tile *__restrict__ tiles,
+                                                             const int2 *__restrict__ units,
+                                                             int nunit,
+                                                             const TileB *__restrict__ tileb,
+                                                             int2 *__restrict__ tpairs, int tp_cap,
+                                                             DevStats *stats)
+{
+    __shared__ int wcount[kTpWaves];
+    __shared__ int wbase[kTpWaves];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int u = blockIdx.x * kTpWaves + wv;
+    const bool has = u < nunit;
+    int A = 0, B = 0;
+    bool ok = false;
+    if (has) {
+        const int2 U = units[u];
+        A = U.x;
+        B = U.y + lane;
+        const Tile TA = tiles[A];
+        const TileB BA = tileb[A];
+        ok = tile_pair_kept(TA, BA, tileb, B);
+    }
+    const unsigned long long mask = __ballot(ok);
+    if (lane == 0)
+        wcount[wv] = (int)__popcll(mask);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int w = 0; w < kTpWaves; ++w) {
+            wbase[w] = tot;
+            tot += wcount[w];
         }
+        const int base = tot ? atomicAdd(&stats->cur_tp, tot) : 0;
+        for (int w = 0; w < kTpWaves; ++w)
+            wbase[w] += base;
+    }
+    __syncthreads();
+    if (ok) {
+        const int p = wbase[wv] + (int)__popcll(mask & ((1ull << lane) - 1ull));
+        if (p < tp_cap)
+            tpairs[p] = make_int2(A, B);
     }
 }
 
@@ -3174,8 +3200,8 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
         if (d.ntile > 0) {
             k_tile_bounds<<<cdiv(d.ntile, kBlock / 64), kBlock, 0, s>>>(d.tiles, d.ntile, d.srec, dt,
                                                                          d.tileb);
-            k_tile_pairs<<<cdiv(d.ntile, kWaves), kBlock, 0, s>>>(d.tiles, d.ntile, d.tileb, d.tpairs,
-                                                                   d.tp_cap, d.stats);
+            k_tile_pairs<<<cdiv(d.nunit, kTpWaves), 64 * kTpWaves, 0, s>>>(
+                d.tiles, d.units, d.nunit, d.tileb, d.tpairs, d.tp_cap, d.stats);
             int grid = std::min(std::max(1, d.tp_cap), 8192);
             k_enc_pairs<<<grid, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.srec, dt,
                                                  d.keys, d.enc_cap, d.ce, d.stats);

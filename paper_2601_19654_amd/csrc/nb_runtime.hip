@@ -205,6 +205,7 @@ struct Tables {
     int ncell = 0;
     std::vector<Tile> tiles;
     long long tp_cap = 0;
+    std::vector<int2> units;    // sorted check: (tile A, first of 64 tiles B >= A) culling units
     bool enc_sorted = false;
     bool force_few = false;
     bool force_sym = false;
@@ -304,6 +305,9 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
         for (int k = 0; k < nt; ++k)
             t.tiles.push_back(Tile{s, off[s] + 64 * k, std::min(64, n - 64 * k), first + nt - 1});
         t.tp_cap += (long long)nt * (nt + 1) / 2;
+        for (int A = first; A < first + nt; ++A)
+            for (int b0 = A; b0 < first + nt; b0 += 64)
+                t.units.push_back(make_int2(A, b0));
     }
     for (int s = 0; s < nsys; ++s)
         if (off[s + 1] > off[s])
@@ -421,6 +425,8 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
         d.tileb = (TileB *)take(t.tiles.size() * sizeof(TileB));
         d.tp_cap = (int)std::min<long long>(t.tp_cap, 1ll << 30);
         d.tpairs = (int2 *)take((size_t)d.tp_cap * sizeof(int2));
+        d.nunit = (int)t.units.size();
+        d.units = (int2 *)take(t.units.size() * sizeof(int2));
     }
     d.flag = (int *)take(4 * sizeof(int));
     d.stage = (double *)take((size_t)6 * nd);
@@ -893,6 +899,7 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *n
         up(c->d.sys_cell_base, t.cell_base.data(), nsys * sizeof(int));
         up(c->d.sys_cell_cnt, t.cell_cnt.data(), nsys * sizeof(int));
         up(c->d.tiles, t.tiles.data(), t.tiles.size() * sizeof(Tile));
+        up(c->d.units, t.units.data(), t.units.size() * sizeof(int2));
         if (r == NB_OK && launch_fill_i32(c->d.cell_cnt, c->d.ncell, 0, c->stream) != hipSuccess)
             r = set_err(c, NB_E_HIP, "nb_create: clearing the cell counts failed");
     }
