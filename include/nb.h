@@ -94,7 +94,9 @@ typedef struct nb_params {
     int32_t force_r;      /* targets per lane in the force kernel: 1, 2 or 4 (0: default) */
     int32_t enc_jchunk;   /* sources per encounter work item (0: default) */
     int32_t enc_algo;     /* encounter check: 0 automatic, 1 every pair through a per-pair
-                             reach filter, 2 spatially sorted tiles with tile-pair culling */
+                             reach filter, 2 spatially sorted tiles with tile-pair culling,
+                             3 every body against the big bodies of its system (at most 256
+                             big bodies per system; automatic when some bodies are small) */
     int32_t step_algo;    /* nb_step: 0 automatic, 1 one launch per phase over all systems
                              (HIP graph), 2 one persistent launch in which a workgroup owns a
                              system for many steps (FP64 pair arithmetic; systems of at most
@@ -263,7 +265,8 @@ int nb_time_kernel(nb_ctx *ctx, int which, int reps, double dt, double *ms_per_l
 
 /* The algorithms the context resolved its automatic choices to (any pointer may
  * be NULL): force 1 (ordered pairs), 2 (symmetric tile pairs) or 3 (few-source
- * kernels); encounter check 1 (direct) or 2 (sorted tiles); step launch 1
+ * kernels); encounter check 1 (direct), 2 (sorted tiles) or 3 (big bodies only as
+ * partners); step launch 1
  * (per phase) or 2 (persistent). */
 int nb_get_choices(const nb_ctx *ctx, int32_t *force_algo, int32_t *enc_algo, int32_t *step_algo);
 

@@ -88,29 +88,32 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
                     print(f"[autotune] {mode} force evaluation algo={fa} r={r} j={j}: {ms:.4f} ms",
                           file=sys.stderr, flush=True)
                 c.close()
-    for j in ENC_J + (0,):
-        if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
-            continue
-        # j = 0 stands for the sorted-tile algorithm (no chunk parameter)
-        p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), enc_jchunk=j,
-                              enc_algo=2 if j == 0 else 1)
+    # encounter candidates: (1, j) direct with source chunks of j, (2, 0) sorted
+    # tiles, (3, 0) every body against its system's big bodies (some small
+    # bodies, at most 256 big bodies per system)
+    sizes = np.diff(w.off)
+    nbig = sizes if w.nbig is None else np.asarray(w.nbig)
+    enc_cands = [(1, j) for j in ENC_J if j <= max(256, _pow2(int(sizes.max()))) * 2] + [(2, 0)]
+    if np.any(nbig < sizes) and int(nbig.max()) <= 256:
+        enc_cands.append((3, 0))
+    for ea, j in enc_cands:
+        p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), enc_jchunk=j or 1024,
+                              enc_algo=ea)
         c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False, nbig=w.nbig)
         c.upload(w.m0, w.m, w.x, w.v)
         c.drift(w.dt, allow_fail=True)
         ms = c.time_kernel(nb.NB_K_ENCOUNTER, reps=reps)
-        res_enc[j] = ms
+        res_enc[(ea, j)] = ms
         if verbose:
-            print(f"[autotune] {mode} encounter {'sorted tiles' if j == 0 else f'j={j}'}: {ms:.4f} ms",
-                  file=sys.stderr, flush=True)
+            print(f"[autotune] {mode} encounter algo={ea} j={j}: {ms:.4f} ms", file=sys.stderr, flush=True)
         c.close()
     (fa, r, j), fms = min(res_force.items(), key=lambda kv: kv[1])
-    ej, ems = min(res_enc.items(), key=lambda kv: kv[1])
+    (ea, ej), ems = min(res_enc.items(), key=lambda kv: kv[1])
     # whole-step launch: per-phase launches (tuned tiles) vs the persistent launch
     res_step = {}
     for sa in ((1, 2) if mode == "fp64" and int(np.diff(w.off).max()) <= 8192 else (1,)):
         p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j,
-                              force_algo=fa, enc_jchunk=ej if ej else 1024, enc_algo=2 if ej == 0 else 1,
-                              step_algo=sa)
+                              force_algo=fa, enc_jchunk=ej or 1024, enc_algo=ea, step_algo=sa)
         c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False, nbig=w.nbig)
         c.upload(w.m0, w.m, w.x, w.v)
         c.step(w.dt, 3, allow=(nb.NB_E_CAPACITY, nb.NB_E_KEPLER))
@@ -119,13 +122,13 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
             print(f"[autotune] {mode} step launch {sa}: {res_step[sa]:.4f} ms", file=sys.stderr, flush=True)
         c.close()
     sa, sms = min(res_step.items(), key=lambda kv: kv[1])
-    return {"force_algo": fa, "force_r": r, "force_jchunk": j, "enc_jchunk": ej if ej else 1024,
-            "enc_algo": 2 if ej == 0 else 1,
+    return {"force_algo": fa, "force_r": r, "force_jchunk": j, "enc_jchunk": ej or 1024,
+            "enc_algo": ea,
             "step_algo": sa, "step_ms": round(sms, 5), "step_candidates": {str(k): round(v, 5) for k, v in res_step.items()},
             "force_ms": round(fms, 5),
             "encounter_ms": round(ems, 5), "workload": w.name, "tuned_at": time.strftime("%Y-%m-%d"),
             "force_candidates": {f"a{f}_r{a}_j{b}": round(v, 5) for (f, a, b), v in res_force.items()},
-            "encounter_candidates": {(f"j{a}" if a else "sorted"): round(v, 5) for a, v in res_enc.items()}}
+            "encounter_candidates": {f"a{a}_j{b}": round(v, 5) for (a, b), v in res_enc.items()}}
 
 
 def main():

@@ -112,6 +112,7 @@ struct Dev {
     DevStats *stats;
     // sorted encounter check
     int enc_sorted;
+    int enc_few;          // few big bodies: each body against its system's big bodies
     double *lnr_part;     // nrb x 2: min, max of ln R (cylindrical) of chord midpoints
     int *cell_of, *slot_of;   // ntot
     int *cell_cnt, *cell_off; int ncell;
@@ -142,7 +143,8 @@ struct Params {
     int mode, drag;
     double sigma0, h, cd, rho_p;
     int force_r, force_j, enc_j;
-    int enc_algo;         // 1: all pairs with the reach prefilter, 2: sorted tiles
+    int enc_algo;         // 1: all pairs with the reach prefilter, 2: sorted tiles,
+                          // 3: each body against its system's big bodies (at most kBlock)
     int step_algo;        // 1: per-phase launches, 2: persistent per-system launch
     int force_algo;       // 0 automatic, 1 ordered pairs, 2 symmetric tile pairs
     int resolve;          // 1: resolve flagged groups on the host every step

@@ -1869,6 +1869,119 @@ __global__ __launch_bounds__(kBlock) void k_encounter(const PWork *__restrict__ 
     }
 }
 
+// Few big bodies (every system has at most kBlock big bodies; small bodies are
+// massless and never meet each other): one lane per body j of an O(N) block,
+// tested against the big bodies i < j of its system, which the block stages in
+// LDS once.  Same two-stage pair test as k_encounter, so the same pairs are
+// flagged.
+__global__ __launch_bounds__(kBlock) void k_encounter_few(const RBlk *__restrict__ rblk,
+                                                          const int *__restrict__ off,
+                                                          const int *__restrict__ nbig, double dt,
+                                                          const double4 *__restrict__ mr,
+                                                          const double4 *__restrict__ cr,
+                                                          const double *__restrict__ q0x,
+                                                          const double *__restrict__ q0y,
+                                                          const double *__restrict__ q0z,
+                                                          const double *__restrict__ v0x,
+                                                          const double *__restrict__ v0y,
+                                                          const double *__restrict__ v0z,
+                                                          const double *__restrict__ qx,
+                                                          const double *__restrict__ qy,
+                                                          const double *__restrict__ qz,
+                                                          const double *__restrict__ vx,
+                                                          const double *__restrict__ vy,
+                                                          const double *__restrict__ vz,
+                                                          const double *__restrict__ rc,
+                                                          unsigned long long *__restrict__ keys,
+                                                          int cap, int *__restrict__ ce,
+                                                          DevStats *stats)
+{
+    __shared__ double4 smr[kBlock];
+    __shared__ double4 scr[kBlock];
+    __shared__ EncRec si[kBlock];
+    const RBlk b = rblk[blockIdx.x];
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int a = off[b.sys], nb = min(nbig[b.sys], kBlock);
+    const double t2 = 2.0 * dt;
+    const double k427 = 4.0 / 27.0;
+    // the system's big bodies
+    if (t < nb) {
+        const int i = a + t;
+        smr[t] = mr[i];
+        scr[t] = cr[i];
+        EncRec r;
+        r.q0[0] = q0x[i]; r.q0[1] = q0y[i]; r.q0[2] = q0z[i];
+        r.v0[0] = v0x[i]; r.v0[1] = v0y[i]; r.v0[2] = v0z[i];
+        r.q1[0] = qx[i];  r.q1[1] = qy[i];  r.q1[2] = qz[i];
+        r.v1[0] = vx[i];  r.v1[1] = vy[i];  r.v1[2] = vz[i];
+        r.rc = rc[i];
+        r.pad = 0.0;
+        si[t] = r;
+    }
+    __syncthreads();
+    const bool has_j = b.start + t < b.end;
+    const int j = b.start + (has_j ? t : 0);
+    const int ni = has_j ? min(nb, j - a) : 0;     // big bodies i < j
+    const double4 Mj = mr[j];
+    const double4 Cj = cr[j];
+    const double a0[3] = {q0x[j], q0y[j], q0z[j]}, b0[3] = {v0x[j], v0y[j], v0z[j]};
+    const double a1[3] = {qx[j], qy[j], qz[j]}, b1[3] = {vx[j], vy[j], vz[j]};
+    const double rcj = rc[j];
+    for (int ii = 0; ii < nb; ++ii) {
+        const double4 Mi = smr[ii];
+        const double dx = Mj.x - Mi.x, dy = Mj.y - Mi.y, dz = Mj.z - Mi.z;
+        const double D2 = fma(dz, dz, fma(dy, dy, dx * dx));
+        const double S = Mi.w + Mj.w;
+        bool cand = ii < ni && D2 <= S * S;
+        if (!__any(cand))
+            continue;
+        {
+            // relative chord filter
+            const double4 Ci = scr[ii];
+            const double cx = Cj.x - Ci.x, cy = Cj.y - Ci.y, cz = Cj.z - Ci.z;
+            const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
+            const double bb = Ci.w + Cj.w + fmax(si[ii].rc, rcj);
+            cand = cand && D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20);
+        }
+        if (!__any(cand))
+            continue;
+        bool hit = false;
+        if (cand) {
+            const EncRec &I = si[ii];
+            const double d0x = a0[0] - I.q0[0], d0y = a0[1] - I.q0[1], d0z = a0[2] - I.q0[2];
+            const double d1x = a1[0] - I.q1[0], d1y = a1[1] - I.q1[1], d1z = a1[2] - I.q1[2];
+            const double e0x = b0[0] - I.v0[0], e0y = b0[1] - I.v0[1], e0z = b0[2] - I.v0[2];
+            const double e1x = b1[0] - I.v1[0], e1y = b1[1] - I.v1[1], e1z = b1[2] - I.v1[2];
+            const double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
+            const double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
+            const double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
+            const double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
+            const double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
+            const double rcij = fmax(I.rc, rcj);
+            const double thr = rcij * rcij;
+            if (lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1)))
+                hit = hermite_min(f0, f1, g0, g1) <= thr;
+        }
+        const unsigned long long mask = __ballot(hit);
+        if (mask) {
+            const int leader = __ffsll((long long)mask) - 1;
+            int base = 0;
+            if (lane == leader)
+                base = atomicAdd(&stats->cur_nce, (int)__popcll(mask));
+            base = __shfl(base, leader);
+            if (hit) {
+                const int i = a + ii;
+                const int pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
+                if (pos < cap)
+                    keys[pos] = ((unsigned long long)(unsigned)i << 32) | (unsigned)j;
+                __hip_atomic_store(&ce[i], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(&ce[j], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
 // ----------------------------------------------------------------------------
 // Spatially sorted encounter check.  Each step the bodies of every system are
 // binned by the chord midpoint's cylindrical (ln R, phi) into a power-of-two
@@ -2210,7 +2323,7 @@ __device__ __forceinline__ bool may_meet(const double cmA[3], double smA, const 
 // first and the workgroup reserves its whole range with one atomic (a counter
 // that every wave of the grid hits is a serial point), then the test is
 // repeated to write the pairs.
-constexpr int kTpWaves = 16;
+constexpr int kTpWaves = 4;
 
 __device__ __forceinline__ bool tile_pair_kept(const Tile &TA, const TileB &BA,
                                                const TileB *__restrict__ tileb, int B)
@@ -3206,6 +3319,12 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
             k_enc_pairs<<<grid, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.srec, dt,
                                                  d.keys, d.enc_cap, d.ce, d.stats);
         }
+    } else if (d.enc_few) {
+        if (d.nrb > 0)
+            k_encounter_few<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.off, d.nbig, dt, d.mr, d.cr, d.q0x,
+                                                      d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.q1x,
+                                                      d.q1y, d.q1z, d.v1x, d.v1y, d.v1z, d.rc1,
+                                                      d.keys, d.enc_cap, d.ce, d.stats);
     } else if (d.new_ > 0) {
         k_encounter<<<d.new_, kBlock, 0, s>>>(d.ework, dt, d.mr, d.cr, d.q0x, d.q0y, d.q0z, d.v0x,
                                                d.v0y, d.v0z, d.q1x, d.q1y, d.q1z, d.v1x, d.v1y,

@@ -131,10 +131,24 @@ int choose_step_algo(const Params &p, int nsys, const int32_t *off)
 // Encounter algorithm: explicit choice, else sorted tiles when bodies have
 // many candidate partners on average (tested pairs per body >= 512); with few
 // big bodies or small systems every pair through the filters is cheaper.
+bool has_small(int nsys, const int32_t *off, const int32_t *nbig);
+
+int max_big(int nsys, const int32_t *off, const int32_t *nbig)
+{
+    int mb = 0;
+    for (int s = 0; s < nsys; ++s)
+        mb = std::max(mb, nbig ? nbig[s] : off[s + 1] - off[s]);
+    return mb;
+}
+
 int choose_enc_algo(const Params &p, int nsys, const int32_t *off, const int32_t *nbig)
 {
-    if (p.enc_algo == 1 || p.enc_algo == 2)
+    if (p.enc_algo >= 1 && p.enc_algo <= 3)
         return p.enc_algo;
+    // small bodies and at most kBlock big bodies per system: every body against
+    // the big bodies of its system
+    if (has_small(nsys, off, nbig) && max_big(nsys, off, nbig) <= kBlock)
+        return 3;
     long long pairs = 0;
     for (int s = 0; s < nsys; ++s) {
         const long long n = off[s + 1] - off[s], nb = nbig ? nbig[s] : n;
@@ -155,7 +169,7 @@ int check_params(const nb_params *p)
         return NB_E_INVALID;
     if (p->force_r != 0 && p->force_r != 1 && p->force_r != 2 && p->force_r != 4)
         return NB_E_INVALID;
-    if (p->force_jchunk < 0 || p->enc_jchunk < 0 || p->enc_algo < 0 || p->enc_algo > 2 ||
+    if (p->force_jchunk < 0 || p->enc_jchunk < 0 || p->enc_algo < 0 || p->enc_algo > 3 ||
         p->step_algo < 0 || p->step_algo > 2)
         return NB_E_INVALID;
     if ((p->resolve != 0 && p->resolve != 1) || p->resolve_threads < 0 || p->force_algo < 0 ||
@@ -207,6 +221,7 @@ struct Tables {
     long long tp_cap = 0;
     std::vector<int2> units;    // sorted check: (tile A, first of 64 tiles B >= A) culling units
     bool enc_sorted = false;
+    bool enc_few = false;
     bool force_few = false;
     bool force_sym = false;
     // persistent step launch: systems largest first
@@ -231,6 +246,7 @@ void pair_items(int a, int n, int nb, int J, std::vector<PWork> &out)
 void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *nbig, Tables &t)
 {
     t.enc_sorted = choose_enc_algo(p, nsys, off, nbig) == 2;
+    t.enc_few = choose_enc_algo(p, nsys, off, nbig) == 3;
     // symmetric tile pairs: every body big (automatic or asked for)
     t.force_sym = p.force_algo != 1 && !has_small(nsys, off, nbig);
     t.rb_first.assign(nsys, 0);
@@ -406,6 +422,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.pmax_n = t.psys.empty() ? 0 : t.psys[0].n;
     d.psys = (PSys *)take(t.psys.size() * sizeof(PSys));
     d.enc_sorted = t.enc_sorted;
+    d.enc_few = t.enc_few ? 1 : 0;
     d.force_few = t.force_few ? 1 : 0;
     d.force_sym = t.force_sym ? 1 : 0;
     if (d.enc_sorted) {
@@ -827,7 +844,8 @@ int nb_workspace_size(const nb_params *p, int nsys, const int32_t *off, const in
                       int enc_cap, size_t *bytes)
 {
     if (!bytes || check_params(p) || check_offsets(nsys, off, nbig) || enc_cap < 0 ||
-        (p->drag && has_small(nsys, off, nbig)))
+        (p->drag && has_small(nsys, off, nbig)) ||
+        (p->enc_algo == 3 && max_big(nsys, off, nbig) > kBlock))
         return NB_E_INVALID;
     Params q = to_internal(*p);
     Tables t;
@@ -844,7 +862,8 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *n
         return NB_E_INVALID;
     *out = nullptr;
     if (check_params(p) || check_offsets(nsys, off, nbig) || enc_cap < 0 ||
-        (p->drag && has_small(nsys, off, nbig)))
+        (p->drag && has_small(nsys, off, nbig)) ||
+        (p->enc_algo == 3 && max_big(nsys, off, nbig) > kBlock))
         return NB_E_INVALID;
     if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
         return NB_E_WORKSPACE;
@@ -1331,7 +1350,7 @@ int nb_get_choices(const nb_ctx *c, int32_t *force_algo, int32_t *enc_algo, int3
     if (force_algo)
         *force_algo = c->d.force_sym ? 2 : (c->d.force_few ? 3 : 1);
     if (enc_algo)
-        *enc_algo = c->d.enc_sorted ? 2 : 1;
+        *enc_algo = c->d.enc_sorted ? 2 : (c->d.enc_few ? 3 : 1);
     if (step_algo)
         *step_algo = c->p.step_algo;
     return NB_OK;

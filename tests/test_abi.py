@@ -82,6 +82,10 @@ def test_workspace_size_and_validation(nb):
     rc, plain = _wsize(nb, [0, 1000])
     rc, full = _wsize(nb, [0, 1000], resolve=1)
     assert rc == 0 and full > plain
+    # encounter check against the big bodies only: at most 256 big bodies per system
+    assert _wsize(nb, [0, 1000], nbig=[100], enc_algo=3)[0] == 0
+    assert _wsize(nb, [0, 1000], enc_algo=3)[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 1000], enc_algo=4)[0] == nb.NB_E_INVALID
 
 def test_create_rejects_bad_workspace(nb):
     p = nb.default_params()

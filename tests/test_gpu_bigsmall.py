@@ -55,7 +55,7 @@ def test_force(case, mode):
         assert err <= bar, (name, s, err)
 
 
-@pytest.mark.parametrize("algo", [1, 2])
+@pytest.mark.parametrize("algo", [1, 2, 3])
 def test_encounters(case, algo):
     name, w, (Q, V, rc, a_ref) = case
     c = ctx_for(w, enc_algo=algo)
@@ -121,3 +121,19 @@ def test_upload_rejects_massive_small_body():
     with pytest.raises(nb.NbError) as e:
         c.upload(w.m0, m, w.x, w.v)
     assert e.value.code == nb.NB_E_INVALID
+
+
+def test_few_big_encounter_check_matches_direct_at_size():
+    """100 big bodies and 2^18 small ones: the check that runs every body against
+    its system's big bodies flags exactly the pairs of the direct check."""
+    w = workloads.bigsmall(100, 1 << 18)
+    outs = []
+    for algo in (1, 3):
+        c = ctx_for(w, enc_algo=algo, enc_cap=1 << 18)
+        c.drift(w.dt)
+        e = c.encounters()
+        outs.append((e.ice.copy(), e.jce.copy(), e.ce.copy()))
+        c.close()
+    assert len(outs[0][0]) > 0
+    for u, v in zip(*outs):
+        assert np.array_equal(u, v)

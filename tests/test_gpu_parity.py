@@ -488,6 +488,6 @@ def test_resolved_choices():
     assert ctx_for(ring, resolve=1).choices()["step_algo"] == 1
     bs = workloads.bigsmall(50, 140000)
     chb = ctx_for(bs, force_r=1).choices()
-    assert chb["force_algo"] == 3 and chb["enc_algo"] == 1      # few sources, few partners
+    assert chb["force_algo"] == 3 and chb["enc_algo"] == 3      # few sources, few partners
     small = workloads.bigsmall(20, 3000)
     assert ctx_for(small).choices()["force_algo"] == 1           # too few target tiles
