@@ -7,7 +7,7 @@ The argument: the Hermite data split into the straight-chord quadratic
 |dQ0 + s dc|^2 >= (D - rho_i - rho_j)^2 plus the velocity deviations weighted
 by h10(s), h11(s) with |h10| + |h11| = s(1-s) <= 1/4.  Here the claim is
 tested on arbitrary (non-physical) Hermite data placed just outside the reach,
-and on Kepler arcs, with the oracle's exact minimum as the judge.
+and on Kepler arcs, with the oracle's exact minimum as the reference.
 """
 import numpy as np
 
