@@ -73,6 +73,16 @@ struct DevStats {
     int pad;
 };
 
+// What a drift leaves for the encounter check (snapshots, copies, chord
+// records); a context keeps two sets so that the check of one step can run
+// beside the next step.
+struct Snap {
+    double *q0x, *q0y, *q0z, *v0x, *v0y, *v0z;
+    double *q1x, *q1y, *q1z, *v1x, *v1y, *v1z, *rc1;
+    double4 *mr, *cr;
+    double *lnr_part;
+};
+
 // Device pointers of a context; every array lives in the caller's workspace.
 struct Dev {
     int ntot, nsys;
@@ -136,6 +146,26 @@ struct Dev {
     int force_few;        // every system has at most 256 big bodies and the targets are many:
                           // the few-source force kernels
     int force_sym;        // every body big: work items are unordered tile pairs
+    Snap alt;             // the second set of drift outputs
+
+    Snap snap() const
+    {
+        return Snap{q0x, q0y, q0z, v0x, v0y, v0z, q1x, q1y, q1z, v1x, v1y, v1z, rc1, mr, cr, lnr_part};
+    }
+    // this context with the drift outputs of set `parity` (0: the first set)
+    Dev with_snap(int parity) const
+    {
+        Dev e = *this;
+        if (parity) {
+            const Snap a = alt;
+            e.q0x = a.q0x; e.q0y = a.q0y; e.q0z = a.q0z;
+            e.v0x = a.v0x; e.v0y = a.v0y; e.v0z = a.v0z;
+            e.q1x = a.q1x; e.q1y = a.q1y; e.q1z = a.q1z;
+            e.v1x = a.v1x; e.v1y = a.v1y; e.v1z = a.v1z;
+            e.rc1 = a.rc1; e.mr = a.mr; e.cr = a.cr; e.lnr_part = a.lnr_part;
+        }
+        return e;
+    }
 };
 
 struct Params {

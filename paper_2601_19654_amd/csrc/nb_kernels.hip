@@ -608,7 +608,6 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
         v1z[i] = w;
         rc1[i] = rc[i];
         kflag[i] = fail ? 1 : 0;
-        ce[i] = 0;
         double mi = m[i];
         pv[0] = mi * u;
         pv[1] = mi * v;
@@ -619,8 +618,6 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
         atomicAdd((unsigned long long *)&stats->kepler_fail, (unsigned long long)__popcll(mask));
         atomicAdd(&stats->cur_kfail, (int)__popcll(mask));
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        stats->cur_nce = 0;
     if (lnr_part) {
         // range of ln R over the block (the sorted encounter check bins by it)
         for (int o = 32; o > 0; o >>= 1) {
@@ -3336,7 +3333,13 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
 
 hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s)
 {
-    hipError_t e = launch_enc_gather(d, s);
+    // an empty list and no flags (the check may run beside the next drift, so
+    // the drift does not clear them)
+    hipError_t e = launch_fill_i32(&d.stats->cur_nce, 1, 0, s);
+    if (e == hipSuccess)
+        e = launch_fill_i32(d.ce, d.ntot, 0, s);
+    if (e == hipSuccess)
+        e = launch_enc_gather(d, s);
     return e != hipSuccess ? e : launch_enc_test(d, dt, s);
 }
 

@@ -30,7 +30,9 @@ struct nb_ctx {
     hipGraphExec_t gexec = nullptr;
     // second stream on which the sorted encounter test overlaps S(h) and the force
     hipStream_t side = nullptr;
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // one fork and one join event per set of drift outputs
+    hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join[2] = {nullptr, nullptr};
+    int snap = 0;         // the set of drift outputs the latest drift wrote
     double graph_dt = 0.0;
     int graph_steps = 0;
     std::string err;
@@ -385,6 +387,16 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.pk = (float4 *)take((size_t)ntot * 2 * sizeof(float4));
     d.mr = (double4 *)take((size_t)ntot * sizeof(double4));
     d.cr = (double4 *)take((size_t)ntot * sizeof(double4));
+    {
+        // the second set of drift outputs
+        double **alt[] = {&d.alt.q0x, &d.alt.q0y, &d.alt.q0z, &d.alt.v0x, &d.alt.v0y,
+                          &d.alt.v0z, &d.alt.q1x, &d.alt.q1y, &d.alt.q1z, &d.alt.v1x,
+                          &d.alt.v1y, &d.alt.v1z, &d.alt.rc1};
+        for (double **pl : alt)
+            *pl = (double *)take(nd);
+        d.alt.mr = (double4 *)take((size_t)ntot * sizeof(double4));
+        d.alt.cr = (double4 *)take((size_t)ntot * sizeof(double4));
+    }
     d.kflag = (int *)take((size_t)ntot * sizeof(int));
     d.ce = (int *)take((size_t)ntot * sizeof(int));
     d.sys_of = (int *)take((size_t)ntot * sizeof(int));
@@ -427,6 +439,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.force_sym = t.force_sym ? 1 : 0;
     if (d.enc_sorted) {
         d.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
+        d.alt.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
         d.cell_of = (int *)take((size_t)ntot * sizeof(int));
         d.slot_of = (int *)take((size_t)ntot * sizeof(int));
         d.ncell = t.ncell;
@@ -502,7 +515,8 @@ bool merged_kicks(const nb_ctx *c)
     return !c->p.drag;
 }
 
-// K(h) S(h) D(dt) C of a step (S(h) inside the drift launch).
+// K(h) S(h) D(dt) C of a step (S(h) inside the drift launch), the drift's
+// outputs in set 0.
 int enqueue_step_head(nb_ctx *c, double dt, bool first)
 {
     const double h = 0.5 * dt;
@@ -511,6 +525,7 @@ int enqueue_step_head(nb_ctx *c, double dt, bool first)
         HIP_OK(c, launch_kick(d, c->p, h, c->stream));
     HIP_OK(c, launch_drift(d, c->p, dt, h, c->stream));
     HIP_OK(c, launch_encounters(d, dt, c->stream));
+    c->snap = 0;
     return NB_OK;
 }
 
@@ -530,42 +545,42 @@ int enqueue_step_tail(nb_ctx *c, double dt, bool last)
     return NB_OK;
 }
 
-int enqueue_step(nb_ctx *c, double dt, bool first, bool last)
-{
-    if (c->side) {
-        // fork after the drift: the encounter check reads only the drift's
-        // snapshots (Q0, V0, Q1, V1, rc) and runs beside S(h), the force and K(h).
-        // The rest of the step is enqueued (and, under capture, recorded) before
-        // the branch, so that the step's own chain keeps the stream's queue and
-        // only the branch and the join cross queues.
-        const double h = 0.5 * dt;
-        const Dev &d = c->d;
-        if (first)
-            HIP_OK(c, launch_kick(d, c->p, h, c->stream));
-        HIP_OK(c, launch_drift(d, c->p, dt, h, c->stream));
-        HIP_OK(c, hipEventRecord(c->ev_fork, c->stream));
-        int r = enqueue_step_tail(c, dt, last);
-        if (r)
-            return r;
-        HIP_OK(c, hipStreamWaitEvent(c->side, c->ev_fork, 0));
-        HIP_OK(c, launch_encounters(d, dt, c->side));
-        HIP_OK(c, hipEventRecord(c->ev_join, c->side));
-        HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-        return NB_OK;
-    }
-    int r = enqueue_step_head(c, dt, first);
-    return r ? r : enqueue_step_tail(c, dt, last);
-}
-
-// A run of `steps` steps (kicks merged between them).
+// A run of `steps` steps (kicks merged between them).  On a context with a
+// stream the encounter check of a step runs on a second stream (graph branches
+// under capture) beside the rest of that step and the next one: the drifts
+// write the two sets of drift outputs in turn, and a drift waits only for the
+// check that read its set two steps earlier; the run ends with a join.  The
+// step's own chain is enqueued (recorded) before the branch, so that it keeps
+// the stream's hardware queue and only the branch and the joins cross queues.
 int enqueue_run(nb_ctx *c, double dt, int steps)
 {
     const bool merge = merged_kicks(c);
+    const double h = 0.5 * dt;
     for (int k = 0; k < steps; ++k) {
-        int r = enqueue_step(c, dt, k == 0 || !merge, k == steps - 1 || !merge);
-        if (r)
+        const bool first = k == 0 || !merge, last = k == steps - 1 || !merge;
+        int r;
+        if (!c->side) {
+            if ((r = enqueue_step_head(c, dt, first)) || (r = enqueue_step_tail(c, dt, last)))
+                return r;
+            continue;
+        }
+        const int par = k & 1;
+        const Dev d = c->d.with_snap(par);
+        if (k >= 2)
+            HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join[par], 0));
+        if (first)
+            HIP_OK(c, launch_kick(d, c->p, h, c->stream));
+        HIP_OK(c, launch_drift(d, c->p, dt, h, c->stream));
+        HIP_OK(c, hipEventRecord(c->ev_fork[par], c->stream));
+        if ((r = enqueue_step_tail(c, dt, last)))
             return r;
+        HIP_OK(c, hipStreamWaitEvent(c->side, c->ev_fork[par], 0));
+        HIP_OK(c, launch_encounters(d, dt, c->side));
+        HIP_OK(c, hipEventRecord(c->ev_join[par], c->side));
+        c->snap = par;
     }
+    if (c->side && steps > 0)
+        HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join[(steps - 1) & 1], 0));
     return NB_OK;
 }
 
@@ -586,7 +601,7 @@ int resolve_step(nb_ctx *c, double dt)
                                 hipHostMallocDefault));
     }
     int K = std::min(c->res_k, kcap);
-    HIP_OK(c, launch_gather_pairs(d, 0, K, c->stream));
+    HIP_OK(c, launch_gather_pairs(d.with_snap(c->snap), 0, K, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->h_stats, d.stats, sizeof(DevStats), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->h_pairs, d.res_buf, (size_t)K * 20 * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
@@ -596,7 +611,7 @@ int resolve_step(nb_ctx *c, double dt)
     const int npairs = std::min(c->h_stats->cur_nce, d.enc_cap);
     if (npairs > K) {
         // more pairs than expected: gather and copy the rest
-        HIP_OK(c, launch_gather_pairs(d, K, npairs - K, c->stream));
+        HIP_OK(c, launch_gather_pairs(d.with_snap(c->snap), K, npairs - K, c->stream));
         HIP_OK(c, hipMemcpyAsync(c->h_pairs + (size_t)K * 20, d.res_buf,
                                  (size_t)(npairs - K) * 20 * sizeof(double), hipMemcpyDeviceToHost,
                                  c->stream));
@@ -705,6 +720,7 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
     }
     if (c->p.step_algo == 2) {
         // persistent per-system launches of at most step_chunk steps each
+        c->snap = 0;
         while (done < nsteps) {
             int k = std::min(nsteps - done, c->d.step_chunk);
             HIP_OK(c, launch_fill_i32(&c->d.stats->cur_nce, 1, 0, c->stream));
@@ -772,10 +788,12 @@ void release(nb_ctx *c)
         (void)hipStreamSynchronize(c->side);
         (void)hipStreamDestroy(c->side);
     }
-    if (c->ev_fork)
-        (void)hipEventDestroy(c->ev_fork);
-    if (c->ev_join)
-        (void)hipEventDestroy(c->ev_join);
+    for (int k = 0; k < 2; ++k) {
+        if (c->ev_fork[k])
+            (void)hipEventDestroy(c->ev_fork[k]);
+        if (c->ev_join[k])
+            (void)hipEventDestroy(c->ev_join[k]);
+    }
     if (c->h_stats)
         (void)hipHostFree(c->h_stats);
     if (c->h_pairs)
@@ -929,8 +947,10 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *n
     if (r == NB_OK && c->stream) {
         // default priority, like every stream here
         if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+            hipEventCreateWithFlags(&c->ev_fork[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join[0], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_fork[1], hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&c->ev_join[1], hipEventDisableTiming) != hipSuccess)
             r = set_err(c, NB_E_HIP, "nb_create: side stream or events");
     }
     if (r != NB_OK) {
@@ -1058,6 +1078,7 @@ int nb_drift(nb_ctx *c, double dt, int *nfail)
         return set_err(c, NB_E_INVALID, "nb_drift: dt not finite");
     HIP_OK(c, launch_fill_i32(&c->d.stats->cur_kfail, 1, 0, c->stream));
     HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->stream));
+    c->snap = 0;
     int nf = 0;
     if ((r = read_int(c, &c->d.stats->cur_kfail, &nf)))
         return r;
@@ -1081,7 +1102,7 @@ int nb_encounters(nb_ctx *c, int cap, int *nce, int32_t *ice, int32_t *jce, int3
         return set_err(c, NB_E_INVALID, "nb_encounters: bad argument");
     HIP_OK(c, launch_fill_i32(c->d.ce, c->ntot, 0, c->stream));
     HIP_OK(c, launch_fill_i32(&c->d.stats->cur_nce, 1, 0, c->stream));
-    HIP_OK(c, launch_encounters(c->d, c->last_dt, c->stream));
+    HIP_OK(c, launch_encounters(c->d.with_snap(c->snap), c->last_dt, c->stream));
     c->have_enc = true;
     return copy_list(c, cap, nce, ice, jce, ce, where);
 }
@@ -1226,10 +1247,11 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
         case NB_K_ENCOUNTER:
             // each check starts from an empty list, as after a drift
             HIP_OK(c, launch_fill_i32(&c->d.stats->cur_nce, 1, 0, c->stream));
-            HIP_OK(c, launch_encounters(c->d, c->last_dt, c->stream));
+            HIP_OK(c, launch_encounters(c->d.with_snap(c->snap), c->last_dt, c->stream));
             return NB_OK;
         case NB_K_DRIFT:
             HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->stream));
+            c->snap = 0;
             return NB_OK;
         case NB_K_FORCE_EVAL:
             return enqueue_force(c);
