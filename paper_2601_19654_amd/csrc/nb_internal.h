@@ -108,10 +108,13 @@ struct Dev {
     PWork *ework; int new_;
     PWork *dwork; int ndw;
     // scratch
-    double *rpart;        // nrb x 8: per-block sums of m V, first half after a kick (or from
-                          // the momentum kernel), second half after a drift (and, with gas
-                          // drag, before a kick)
+    double *rpart;        // 3 x nrb x 4: per-block sums of m V.  First: after a kick (or
+                          // from the momentum kernel); rpart_drift(): after a drift (and,
+                          // with gas drag, before a kick); rpart_prev(): see below
     double *rpart_drift() const { return rpart + (size_t)nrb * 4; }
+    // a copy of the last drift's sums taken by the second S(h): the momentum
+    // before the next kicks, which leave it unchanged (the pair forces cancel)
+    double *rpart_prev() const { return rpart + (size_t)nrb * 8; }
     double *fpart;        // 3 x maxs x ntot force partials
     double *dpart;        // ndw x 4 double-double pair sums (E pair, EK pair)
     double *bpart;        // nrb x 16 body partial sums for diagnostics
@@ -194,10 +197,11 @@ hipError_t launch_kick(const Dev &d, const Params &p, double h, hipStream_t s);
 // S(h) from the per-block sums of m V in `part`; rcrit: also the critical radii
 // (and the FP32C records and per-block largest rc^2)
 hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, const double *part,
-                            hipStream_t s);
+                            double *copy_to, hipStream_t s);
 // the drift D(dt), preceded by S(sun_h) from the sums after the kick (sun_h = 0: no
 // sun drift); writes the sums after the drift to rpart_drift()
-hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h, hipStream_t s);
+hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h,
+                        const double *part_in, hipStream_t s);
 hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s);
 // a from the split partials; kick_h != 0: then `kicks` kicks V += kick_h a (and the
 // sums of m V after them into rpart)

@@ -346,8 +346,12 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
                             const double *__restrict__ part, double h, double *qx, double *qy,
                             double *qz, int rcrit, const double *__restrict__ m, double n_hill,
                             double *__restrict__ rc, float4 *__restrict__ pk,
-                            double *__restrict__ tile_rc2)
+                            double *__restrict__ tile_rc2, double *__restrict__ copy_to)
 {
+    // copy_to: this block's entry of `part` is copied there (nothing else reads
+    // that array during the launch)
+    if (copy_to && threadIdx.x < 4)
+        copy_to[(size_t)blockIdx.x * 4 + threadIdx.x] = part[(size_t)blockIdx.x * 4 + threadIdx.x];
     __shared__ double sh[3 * kBlock];
     double rc2 = 0.0;
     RBlk b = rblk[blockIdx.x];
@@ -1588,32 +1592,32 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
         atomicAdd((unsigned long long *)&stats->near_pairs, (unsigned long long)near);
 }
 
-// a = G * sum over the system's splits (fixed order); optionally `kicks` (1 or
-// 2) kicks V += h a, rounded as that many k_kick launches, and the partial sums
-// of m V after them.  The split partials of a
-// block's bodies are read by kFinGroups thread groups,
-// group g taking slots [g ns / G, (g + 1) ns / G) in order; the group sums are
-// added in group order (fixed summation order, several loads in flight per body).
-constexpr int kFinGroups = 4;
+// a = G * sum over the body's split partials (fixed order); optionally `kicks`
+// (1 or 2) kicks V += h a, rounded as that many k_kick launches.  A workgroup of
+// kFinThreads threads takes B = kFinThreads / nsl bodies: thread group g (B
+// threads) reads slice g of every body's partials (slots [g ns / nsl, (g + 1) ns
+// / nsl) in order, eight loads in flight per lane), and the slice sums are added
+// in slice order.  nsl (a power of two, at most 16) follows the largest split
+// count, so that few-split systems do not leave most threads idle.  The sums of
+// m V are not needed after it: the next S(h) takes the momentum from before the
+// kicks.
+constexpr int kFinThreads = 1024;
 
-__global__ __launch_bounds__(kBlock * kFinGroups) void k_force_finalize(
-    const RBlk *__restrict__ rblk, const int *__restrict__ nsplit, const double *__restrict__ fpart,
-    int ntot, int maxs, double G, double *__restrict__ ax, double *__restrict__ ay,
-    double *__restrict__ az, double h, int kicks, const double *__restrict__ m, double *vx,
-    double *vy, double *vz, double *__restrict__ part_out)
+__global__ __launch_bounds__(kFinThreads) void k_force_finalize(
+    const int *__restrict__ sys_of, const int *__restrict__ nsplit, const double *__restrict__ fpart,
+    int ntot, int maxs, int nsl, double G, double *__restrict__ ax, double *__restrict__ ay,
+    double *__restrict__ az, double h, int kicks, double *vx, double *vy, double *vz)
 {
-    __shared__ double gs[kFinGroups - 1][3][kBlock];
-    __shared__ double sh[3 * kBlock];
-    const RBlk b = rblk[blockIdx.x];
-    const int ns = nsplit[b.sys];
-    const int t = threadIdx.x % kBlock, g = threadIdx.x / kBlock;
-    const int i = b.start + t;
-    const int k0 = g * ns / kFinGroups, k1 = (g + 1) * ns / kFinGroups;
+    __shared__ double gs[3 * kFinThreads];
+    const int B = kFinThreads / nsl;
+    const int t = threadIdx.x % B, g = threadIdx.x / B;
+    const int i = blockIdx.x * B + t;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    if (i < b.end) {
+    if (i < ntot) {
+        const int ns = nsplit[sys_of[i]];
+        const int k0 = g * ns / nsl, k1 = (g + 1) * ns / nsl;
         const double *px = fpart + i, *py = px + (size_t)maxs * ntot, *pz = py + (size_t)maxs * ntot;
         int k = k0;
-        // eight slots' loads in flight, then added in slot order
         for (; k + 8 <= k1; k += 8) {
             double ux[8], uy[8], uz[8];
 #pragma unroll
@@ -1636,18 +1640,18 @@ __global__ __launch_bounds__(kBlock * kFinGroups) void k_force_finalize(
         }
     }
     if (g > 0) {
-        gs[g - 1][0][t] = s0;
-        gs[g - 1][1][t] = s1;
-        gs[g - 1][2][t] = s2;
+        double *o = gs + (size_t)(g - 1) * 3 * B;
+        o[t] = s0;
+        o[B + t] = s1;
+        o[2 * B + t] = s2;
     }
     __syncthreads();
-    double pv[3] = {0.0, 0.0, 0.0};
-    if (g == 0 && i < b.end) {
-#pragma unroll
-        for (int q = 0; q < kFinGroups - 1; ++q) {
-            s0 += gs[q][0][t];
-            s1 += gs[q][1][t];
-            s2 += gs[q][2][t];
+    if (g == 0 && i < ntot) {
+        for (int q = 0; q < nsl - 1; ++q) {
+            const double *o = gs + (size_t)q * 3 * B;
+            s0 += o[t];
+            s1 += o[B + t];
+            s2 += o[2 * B + t];
         }
         s0 *= G;
         s1 *= G;
@@ -1656,7 +1660,6 @@ __global__ __launch_bounds__(kBlock * kFinGroups) void k_force_finalize(
         ay[i] = s1;
         az[i] = s2;
         if (h != 0.0) {
-            double mi = m[i];
             double u0 = fma(h, s0, vx[i]), u1 = fma(h, s1, vy[i]), u2 = fma(h, s2, vz[i]);
             if (kicks == 2) {
                 u0 = fma(h, s0, u0);
@@ -1666,32 +1669,6 @@ __global__ __launch_bounds__(kBlock * kFinGroups) void k_force_finalize(
             vx[i] = u0;
             vy[i] = u1;
             vz[i] = u2;
-            pv[0] = mi * u0;
-            pv[1] = mi * u1;
-            pv[2] = mi * u2;
-        }
-    }
-    if (part_out) {
-        // the block's m V sums over group 0's threads, same tree as block_sum
-        if (g == 0) {
-#pragma unroll
-            for (int w = 0; w < 3; ++w)
-                sh[w * kBlock + t] = pv[w];
-        }
-        __syncthreads();
-        for (int st = kBlock / 2; st > 0; st >>= 1) {
-            if (g == 0 && t < st) {
-#pragma unroll
-                for (int w = 0; w < 3; ++w)
-                    sh[w * kBlock + t] += sh[w * kBlock + t + st];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) {
-            part_out[(size_t)blockIdx.x * 4 + 0] = sh[0];
-            part_out[(size_t)blockIdx.x * 4 + 1] = sh[kBlock];
-            part_out[(size_t)blockIdx.x * 4 + 2] = sh[2 * kBlock];
-            part_out[(size_t)blockIdx.x * 4 + 3] = 0.0;
         }
     }
 }
@@ -3153,17 +3130,18 @@ hipError_t launch_kick(const Dev &d, const Params &p, double h, hipStream_t s)
 }
 
 hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, const double *part,
-                            hipStream_t s)
+                            double *copy_to, hipStream_t s)
 {
     if (d.nrb == 0)
         return hipSuccess;
     k_sun_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, part, h, d.qx,
                                           d.qy, d.qz, rcrit, d.m, p.n_hill, d.rc,
-                                          p.mode == 1 ? d.pk : nullptr, d.tile_rc2);
+                                          p.mode == 1 ? d.pk : nullptr, d.tile_rc2, copy_to);
     return hipGetLastError();
 }
 
-hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h, hipStream_t s)
+hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h,
+                        const double *part_in, hipStream_t s)
 {
     if (d.nrb == 0)
         return hipSuccess;
@@ -3171,7 +3149,7 @@ hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h, 
                                       d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
                                       d.stats, d.rpart_drift(), d.rc, d.mr, d.cr,
                                       d.enc_sorted ? d.lnr_part : nullptr, d.q1x, d.q1y, d.q1z,
-                                      d.v1x, d.v1y, d.v1z, d.rc1, d.rpart, sun_h, d.rb_first,
+                                      d.v1x, d.v1y, d.v1z, d.rc1, part_in, sun_h, d.rb_first,
                                       d.rb_count);
     return hipGetLastError();
 }
@@ -3269,11 +3247,15 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
 hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, int kicks,
                                  hipStream_t s)
 {
-    if (d.nrb == 0)
+    if (d.ntot == 0)
         return hipSuccess;
-    k_force_finalize<<<d.nrb, kBlock * kFinGroups, 0, s>>>(
-        d.rblk, d.nsplit, d.fpart, d.ntot, d.maxs, p.G, d.ax, d.ay, d.az, kick_h, kicks, d.m, d.vx,
-        d.vy, d.vz, kick_h != 0.0 ? d.rpart : nullptr);
+    // eight slots per slice at the largest split count
+    int nsl = 1;
+    while (nsl < 16 && nsl * 8 < d.maxs)
+        nsl *= 2;
+    k_force_finalize<<<cdiv(d.ntot, kFinThreads / nsl), kFinThreads, 0, s>>>(
+        d.sys_of, d.nsplit, d.fpart, d.ntot, d.maxs, nsl, p.G, d.ax, d.ay, d.az, kick_h, kicks,
+        d.vx, d.vy, d.vz);
     return hipGetLastError();
 }
 

@@ -33,6 +33,8 @@ struct nb_ctx {
     // one fork and one join event per set of drift outputs
     hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join[2] = {nullptr, nullptr};
     int snap = 0;         // the set of drift outputs the latest drift wrote
+    // rpart_prev() holds the momentum of the current V (kept by the steps)
+    bool mom_valid = false;
     double graph_dt = 0.0;
     int graph_steps = 0;
     std::string err;
@@ -416,7 +418,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.ework = (PWork *)take(t.ework.size() * sizeof(PWork));
     d.ndw = (int)t.dwork.size();
     d.dwork = (PWork *)take(t.dwork.size() * sizeof(PWork));
-    d.rpart = (double *)take((size_t)d.nrb * 8 * sizeof(double));
+    d.rpart = (double *)take((size_t)d.nrb * 12 * sizeof(double));
     d.tile_rc2 = (double *)take((size_t)std::max(d.nrb, 1) * sizeof(double));
     d.fpart = (double *)take((size_t)3 * d.maxs * ntot * sizeof(double));
     d.dpart = (double *)take((size_t)std::max(d.ndw, 1) * 4 * sizeof(double));
@@ -499,7 +501,7 @@ int reset_stats(nb_ctx *c)
 // Critical radii (and FP32 source records), then the force at the current Q.
 int enqueue_force(nb_ctx *c)
 {
-    HIP_OK(c, launch_sun_drift(c->d, 0.0, 1, c->p, c->d.rpart, c->stream));
+    HIP_OK(c, launch_sun_drift(c->d, 0.0, 1, c->p, c->d.rpart, nullptr, c->stream));
     HIP_OK(c, launch_force(c->d, c->p, c->stream));
     HIP_OK(c, launch_force_finalize(c->d, c->p, 0.0, 1, c->stream));
     return NB_OK;
@@ -508,8 +510,12 @@ int enqueue_force(nb_ctx *c)
 // One hybrid step K(h) S(h) D(dt) C S(h) [rc, F] K(h).  In a run of steps the
 // closing K(h) of one step and the opening K(h) of the next are one launch that
 // kicks twice (rounded as two kicks): only the run's first step opens with a
-// kick launch (`first`), only its last closes with a single kick (`last`).  Not
-// with gas drag, whose kick depends on V and the heliocentric correction.
+// kick launch (`first`), only its last closes with a single kick (`last`).  The
+// first S(h) takes P from the momentum before the kicks (rpart_prev(), kept by
+// the previous second S(h), or summed at the start of a call): the kicks leave
+// it unchanged, the pair forces cancelling in the sum.  Not with gas drag, whose
+// kick depends on V and changes P: there each step kicks on its own and its
+// S(h) takes P after the kick.
 bool merged_kicks(const nb_ctx *c)
 {
     return !c->p.drag;
@@ -523,7 +529,7 @@ int enqueue_step_head(nb_ctx *c, double dt, bool first)
     const Dev &d = c->d;
     if (first)
         HIP_OK(c, launch_kick(d, c->p, h, c->stream));
-    HIP_OK(c, launch_drift(d, c->p, dt, h, c->stream));
+    HIP_OK(c, launch_drift(d, c->p, dt, h, merged_kicks(c) ? d.rpart_prev() : d.rpart, c->stream));
     HIP_OK(c, launch_encounters(d, dt, c->stream));
     c->snap = 0;
     return NB_OK;
@@ -534,7 +540,8 @@ int enqueue_step_tail(nb_ctx *c, double dt, bool last)
 {
     const double h = 0.5 * dt;
     const Dev &d = c->d;
-    HIP_OK(c, launch_sun_drift(d, h, 1, c->p, d.rpart_drift(), c->stream));
+    HIP_OK(c, launch_sun_drift(d, h, 1, c->p, d.rpart_drift(),
+                               merged_kicks(c) ? d.rpart_prev() : nullptr, c->stream));
     HIP_OK(c, launch_force(d, c->p, c->stream));
     if (c->p.drag) {
         HIP_OK(c, launch_force_finalize(d, c->p, 0.0, 1, c->stream));
@@ -570,7 +577,7 @@ int enqueue_run(nb_ctx *c, double dt, int steps)
             HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join[par], 0));
         if (first)
             HIP_OK(c, launch_kick(d, c->p, h, c->stream));
-        HIP_OK(c, launch_drift(d, c->p, dt, h, c->stream));
+        HIP_OK(c, launch_drift(d, c->p, dt, h, merge ? d.rpart_prev() : d.rpart, c->stream));
         HIP_OK(c, hipEventRecord(c->ev_fork[par], c->stream));
         if ((r = enqueue_step_tail(c, dt, last)))
             return r;
@@ -709,6 +716,11 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
 {
     int r = NB_OK;
     int done = 0;
+    if (c->p.step_algo != 2 && merged_kicks(c) && !c->mom_valid && nsteps > 0) {
+        // the first S(h) takes P from the momentum before the kicks
+        HIP_OK(c, launch_momentum(c->d, c->d.rpart_prev(), c->stream));
+        c->mom_valid = true;
+    }
     if (c->p.resolve) {
         // the host takes part in every step: direct launches, no graph
         for (; done < nsteps; ++done) {
@@ -721,6 +733,7 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
     if (c->p.step_algo == 2) {
         // persistent per-system launches of at most step_chunk steps each
         c->snap = 0;
+        c->mom_valid = false;
         while (done < nsteps) {
             int k = std::min(nsteps - done, c->d.step_chunk);
             HIP_OK(c, launch_fill_i32(&c->d.stats->cur_nce, 1, 0, c->stream));
@@ -1003,6 +1016,7 @@ int nb_upload(nb_ctx *c, const double *m0, const double *m, const double *x, con
         return r;
     c->have_state = true;
     c->have_drift = false;
+    c->mom_valid = false;
     c->have_enc = false;
     return NB_OK;
 }
@@ -1048,6 +1062,7 @@ int nb_kick(nb_ctx *c, double h)
     if (!std::isfinite(h))
         return set_err(c, NB_E_INVALID, "nb_kick: h not finite");
     c->have_drift = false;
+    c->mom_valid = false;
     HIP_OK(c, launch_kick(c->d, c->p, h, c->stream));
     return NB_OK;
 }
@@ -1063,7 +1078,7 @@ int nb_sun_drift(nb_ctx *c, double h)
         return set_err(c, NB_E_INVALID, "nb_sun_drift: h not finite");
     c->have_drift = false;
     HIP_OK(c, launch_momentum(c->d, c->d.rpart, c->stream));
-    HIP_OK(c, launch_sun_drift(c->d, h, 0, c->p, c->d.rpart, c->stream));
+    HIP_OK(c, launch_sun_drift(c->d, h, 0, c->p, c->d.rpart, nullptr, c->stream));
     return NB_OK;
 }
 
@@ -1077,7 +1092,7 @@ int nb_drift(nb_ctx *c, double dt, int *nfail)
     if (!std::isfinite(dt))
         return set_err(c, NB_E_INVALID, "nb_drift: dt not finite");
     HIP_OK(c, launch_fill_i32(&c->d.stats->cur_kfail, 1, 0, c->stream));
-    HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->stream));
+    HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->d.rpart, c->stream));
     c->snap = 0;
     int nf = 0;
     if ((r = read_int(c, &c->d.stats->cur_kfail, &nf)))
@@ -1085,6 +1100,7 @@ int nb_drift(nb_ctx *c, double dt, int *nfail)
     if (nfail)
         *nfail = nf;
     c->have_drift = true;
+    c->mom_valid = false;
     c->last_dt = dt;
     if (nf > 0)
         return set_err(c, NB_E_KEPLER, "nb_drift: %d bodies failed to converge", nf);
@@ -1250,7 +1266,7 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
             HIP_OK(c, launch_encounters(c->d.with_snap(c->snap), c->last_dt, c->stream));
             return NB_OK;
         case NB_K_DRIFT:
-            HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->stream));
+            HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->d.rpart, c->stream));
             c->snap = 0;
             return NB_OK;
         case NB_K_FORCE_EVAL:
@@ -1290,6 +1306,7 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
         return set_err(c, NB_E_HIP, "timing events: %s", hipGetErrorString(he));
     *ms = (double)t / reps;
     if (which == NB_K_DRIFT || which == NB_K_STEP) {
+        c->mom_valid = false;
         c->have_drift = true;
         c->last_dt = dt;
     }
