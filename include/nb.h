@@ -250,7 +250,7 @@ int nb_get_rcrit(nb_ctx *ctx, double *rc, int where);
 
 /* Kernels that nb_time_kernel can time. */
 #define NB_K_FORCE      0   /* the pair force kernel (FP64 or FP32C per the mode) */
-#define NB_K_ENCOUNTER  1   /* the encounter check plus the list sort */
+#define NB_K_ENCOUNTER  1   /* the encounter check (the list is sorted when read) */
 #define NB_K_DRIFT      2   /* the Kepler drift */
 #define NB_K_STEP       3   /* whole hybrid steps, enqueued the way nb_step runs them */
 #define NB_K_FORCE_EVAL 4   /* one whole force evaluation: critical radii and source

@@ -2750,10 +2750,24 @@ __global__ __launch_bounds__(kBlock) void k_step_stats(int *__restrict__ step_nc
     }
 }
 
-// Sort the encounter keys (one workgroup, bitonic), split them into (ice, jce),
-// and fold the count into the run statistics.
+// Sort the encounter keys (one workgroup, bitonic) and split them into (ice,
+// jce); `accumulate`: also fold the count into the run statistics.
 constexpr int kSortThreads = 1024;
 constexpr int kSortLds = 16384;  // 128 KiB of keys in LDS
+
+// The check's totals: count, largest count and overflowing checks.  The list
+// itself stays in append order until it is read (k_enc_sort).
+__global__ void k_enc_count(int cap, DevStats *stats)
+{
+    if (threadIdx.x == 0) {
+        const int count = stats->cur_nce;
+        stats->total_nce += count;
+        if (count > stats->max_nce)
+            stats->max_nce = count;
+        if (count > cap)
+            stats->overflow_steps += 1;
+    }
+}
 
 __global__ __launch_bounds__(kSortThreads) void k_enc_sort(unsigned long long *keys, int keys_p2,
                                                            int cap, int *__restrict__ ice,
@@ -3309,7 +3323,7 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
                                                d.v0y, d.v0z, d.q1x, d.q1y, d.q1z, d.v1x, d.v1y,
                                                d.v1z, d.rc1, d.keys, d.enc_cap, d.ce, d.stats);
     }
-    k_enc_sort<<<1, kSortThreads, 0, s>>>(d.keys, d.keys_p2, d.enc_cap, d.ice, d.jce, d.stats, 1);
+    k_enc_count<<<1, 64, 0, s>>>(d.enc_cap, d.stats);
     return hipGetLastError();
 }
 

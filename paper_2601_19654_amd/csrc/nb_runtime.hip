@@ -608,6 +608,8 @@ int resolve_step(nb_ctx *c, double dt)
                                 hipHostMallocDefault));
     }
     int K = std::min(c->res_k, kcap);
+    // the list in (i, j) order, so that the groups do not depend on the append order
+    HIP_OK(c, launch_enc_sort(d, 0, c->stream));
     HIP_OK(c, launch_gather_pairs(d.with_snap(c->snap), 0, K, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->h_stats, d.stats, sizeof(DevStats), hipMemcpyDeviceToHost, c->stream));
     HIP_OK(c, hipMemcpyAsync(c->h_pairs, d.res_buf, (size_t)K * 20 * sizeof(double),
@@ -767,6 +769,8 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
 
 int copy_list(nb_ctx *c, int cap, int *nce, int32_t *ice, int32_t *jce, int32_t *ce, int where)
 {
+    // the latest check's list, put in (i, j) order as it is read
+    HIP_OK(c, launch_enc_sort(c->d, 0, c->stream));
     DevStats st;
     HIP_OK(c, hipMemcpyAsync(&st, c->d.stats, sizeof st, hipMemcpyDeviceToHost, c->stream));
     int r = sync(c);
