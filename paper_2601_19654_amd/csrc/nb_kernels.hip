@@ -17,6 +17,8 @@
 #include "nb_internal.h"
 
 #include <algorithm>
+#include <cstddef>
+#include <cstdint>
 #include <float.h>
 #include <math.h>
 
@@ -1170,15 +1172,56 @@ __device__ __forceinline__ float wave_max_nonneg(float v)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
+// LDS addresses as 32-bit integers, for the rotating source index of the
+// symmetric kernels: with a tile array aligned to 64 elements, the address of
+// element 64 t + (lane xor k) is that of element 64 t + lane with k times the
+// element size xored in.
+typedef float lds_v4f __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) lds_v4f lds_float4;
+typedef __attribute__((address_space(3))) double lds_double;
+
+__device__ __forceinline__ uint32_t lds_addr(float4 *p)
+{
+    return (uint32_t)(uintptr_t)(lds_float4 *)p;
+}
+
+__device__ __forceinline__ uint32_t lds_addr(double *p)
+{
+    return (uint32_t)(uintptr_t)(lds_double *)p;
+}
+
+__device__ __forceinline__ float4 lds_ld4(uint32_t a)
+{
+    const lds_v4f v = *(const lds_float4 *)(uintptr_t)a;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+__device__ __forceinline__ void lds_st4(uint32_t a, float4 v)
+{
+    *(lds_float4 *)(uintptr_t)a = lds_v4f{v.x, v.y, v.z, v.w};
+}
+
+__device__ __forceinline__ double lds_ld8(uint32_t a)
+{
+    return *(const lds_double *)(uintptr_t)a;
+}
+
+__device__ __forceinline__ void lds_st8(uint32_t a, double v)
+{
+    *(lds_double *)(uintptr_t)a = v;
+}
+
 // Tile J of one wave in LDS, one array per component (consecutive lanes touch
 // consecutive 8-byte words: no bank conflicts for the rotating accesses).
 template <int T>
-struct SymTile64 {
+struct alignas(512) SymTile64 {
     double x[T], y[T], z[T], m[T];
     double r2[T];                      // max(rc^2, DBL_MIN)
     double rc[T];
     double ax[T], ay[T], az[T];        // tile J's sums
 };
+static_assert(offsetof(SymTile64<64>, m) == 8 * 3 * 64 && offsetof(SymTile64<64>, ax) == 8 * 6 * 64,
+              "SymTile64 layout");
 
 template <int R, bool DIAG, int T>
 __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, int ni, double inner,
@@ -1195,16 +1238,21 @@ __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, in
         // another lane one step earlier: LDS operations of a wave complete in
         // issue order, and the compiler barrier keeps the read after that
         // write.  Sources are read-only and read one step ahead.
-        int jj = 64 * t + lane;
         // the largest rc^2 of the wave's targets and of the sub-tile's sources:
         // one compare per pair outside the rare branch
-        const double thr = fmax(tmi, wave_max(L.r2[jj]));
-        double jxs = L.x[jj], jys = L.y[jj], jzs = L.z[jj], jms = L.m[jj];
+        const double thr = fmax(tmi, wave_max(L.r2[64 * t + lane]));
+        // LDS address of x[64 t + lane]; the other arrays at fixed offsets
+        const uint32_t self = lds_addr(&L.x[64 * t + lane]);
+        uint32_t ac = self;
+        double jxs = lds_ld8(ac), jys = lds_ld8(ac + 8 * T), jzs = lds_ld8(ac + 16 * T),
+               jms = lds_ld8(ac + 24 * T);
 #pragma unroll 1
         for (int k = 0; k < 64; ++k) {
-            const int jn = 64 * t + (lane ^ ((k + 1) & 63));
-            const double xn = L.x[jn], yn = L.y[jn], zn = L.z[jn], mn = L.m[jn];
-            double jx = L.ax[jj], jy = L.ay[jj], jz = L.az[jj];
+            const int jj = 64 * t + (lane ^ k);
+            const uint32_t an = self ^ (uint32_t)(((k + 1) & 63) << 3);
+            const double xn = lds_ld8(an), yn = lds_ld8(an + 8 * T), zn = lds_ld8(an + 16 * T),
+                         mn = lds_ld8(an + 24 * T);
+            double jx = lds_ld8(ac + 48 * T), jy = lds_ld8(ac + 56 * T), jz = lds_ld8(ac + 64 * T);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double dx = jxs - xi[r], dy = jys - yi[r], dz = jzs - zi[r];
@@ -1231,11 +1279,11 @@ __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, in
                 jy = fma(-wj, dy, jy);
                 jz = fma(-wj, dz, jz);
             }
-            L.ax[jj] = jx;
-            L.ay[jj] = jy;
-            L.az[jj] = jz;
+            lds_st8(ac + 48 * T, jx);
+            lds_st8(ac + 56 * T, jy);
+            lds_st8(ac + 64 * T, jz);
             __asm__ __volatile__("" ::: "memory");
-            jj = jn;
+            ac = an;
             jxs = xn;
             jys = yn;
             jzs = zn;
@@ -1341,17 +1389,26 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
 // total when the run ends.  Changeover pairs in FP64 from the FP64 state: the
 // target's part goes straight to its split partial (read back and added when
 // the item ends), the source's part to its FP64 total.
+// Aligned to 1024 bytes, so that the LDS address of a[64 t + (lane xor k)]
+// is that of a[64 t + lane] with 16 k xored in (k < 64): one VALU per step
+// addresses a[], b[] and run[] (fixed offsets 16 T and 32 T from a[]).
 template <int T>
-struct SymTile32 {
+struct alignas(1024) SymTile32 {
     float4 a[T];                    // hi parts and mass
     float4 b[T];                    // lo parts and widened rc^2
     float4 run[T];                  // current FP32 run sums of tile J (x, y, z, -)
     double ax[T], ay[T], az[T];     // FP64 totals of tile J (consecutive planes)
 };
+static_assert(offsetof(SymTile32<64>, b) == 16 * 64 && offsetof(SymTile32<64>, run) == 32 * 64,
+              "SymTile32 layout");
+static_assert(offsetof(SymTile32<128>, b) == 16 * 128 && offsetof(SymTile32<128>, run) == 32 * 128,
+              "SymTile32 layout");
 
 // The rare branch of the FP32C pair loop, out of line so that it adds nothing
 // to the loop: target li of the item (body i0 + li, or a padded copy of body i0
-// when li >= ni) against source jj (body j0 + jj) at FP32 squared distance r2.
+// when li >= ni) against source jj (body j0 + jj, found from the LDS addresses
+// of its record, ja, and of the tile's first record, a0) at FP32 squared
+// distance r2.
 // Unless r2 is inside the pair's widened critical radius it returns false.
 // Otherwise the pair is evaluated in FP64 from the FP64 state: m_j w (Q_j - Q_i)
 // goes to the target's split partial at fp[i], fp[plane + i], fp[2 plane + i]
@@ -1359,7 +1416,8 @@ struct SymTile32 {
 // -m_i w (Q_j - Q_i) to source jj's FP64 totals tot[jj], tot[T + jj],
 // tot[2 T + jj]; it returns true.
 __device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4 *__restrict__ pk,
-                                               int i0, int li, int ni, int j0, int jj, int T,
+                                               int i0, int li, int ni, int j0, uint32_t ja,
+                                               uint32_t a0, int T,
                                                double *tot, double *fp, size_t plane, bool first,
                                                const double *__restrict__ qx,
                                                const double *__restrict__ qy,
@@ -1371,6 +1429,7 @@ __device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4
     const int i = i0 + (ok ? li : 0);
     if (!(r2 < max_nonneg(pk[2 * (size_t)i + 1].w, r2j)))
         return false;
+    const int jj = (int)((ja - a0) >> 4);
     const int j = j0 + jj;
     const double gx = qx[j] - qx[i], gy = qy[j] - qy[i], gz = qz[j] - qz[i];
     const double d2 = fma(gz, gz, fma(gy, gy, gx * gx));
@@ -1429,13 +1488,15 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
             // read after that write.  Source records are read-only and fetched
             // one step ahead.
             const int k0 = 32 * half;
-            int jj = 64 * t + (lane ^ k0);
-            float4 A = L.a[jj], B = L.b[jj];
+            const uint32_t a0 = lds_addr(&L.a[0]);
+            const uint32_t self = lds_addr(&L.a[64 * t + lane]);
+            uint32_t ac = self ^ (uint32_t)(k0 << 4);
+            float4 A = lds_ld4(ac), B = lds_ld4(ac + 16 * T);
 #pragma unroll 2
             for (int kk = 0; kk < 32; ++kk) {
-                const int jn = 64 * t + (lane ^ ((k0 + kk + 1) & 63));
-                const float4 An = L.a[jn], Bn = L.b[jn];
-                const float4 S = L.run[jj];
+                const uint32_t an = self ^ (uint32_t)(((k0 + kk + 1) & 63) << 4);
+                const float4 An = lds_ld4(an), Bn = lds_ld4(an + 16 * T);
+                const float4 S = lds_ld4(ac + 32 * T);
                 float jx = S.x, jy = S.y, jz = S.z;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -1445,9 +1506,9 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                     const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                     const float y = __builtin_amdgcn_rsqf(r2);
                     float q = y * (y * y);
-                    const bool on = !DIAG || (64 * r + lane < jj);
+                    const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
                     if (r2 < thr && on) {
-                        if (changeover_pair32(r2, L.b[jj].w, pk, i0, 64 * r + lane, ni, j0, jj, T,
+                        if (changeover_pair32(r2, B.w, pk, i0, 64 * r + lane, ni, j0, ac, a0, T,
                                               L.ax, fp, plane, !((rare >> r) & 1), qx, qy, qz, m,
                                               rc, inner)) {
                             rare |= 1 << r;
@@ -1465,9 +1526,9 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                     jy = fmaf(-wj, dy, jy);
                     jz = fmaf(-wj, dz, jz);
                 }
-                L.run[jj] = make_float4(jx, jy, jz, 0.0f);
+                lds_st4(ac + 32 * T, make_float4(jx, jy, jz, 0.0f));
                 __asm__ __volatile__("" ::: "memory");
-                jj = jn;
+                ac = an;
                 A = An;
                 B = Bn;
             }
