@@ -1196,9 +1196,18 @@ __device__ __forceinline__ float4 lds_ld4(uint32_t a)
     return make_float4(v.x, v.y, v.z, v.w);
 }
 
-__device__ __forceinline__ void lds_st4(uint32_t a, float4 v)
+// x, y, z of a 16-byte record (the fourth word is neither read nor written)
+typedef float lds_v3f __attribute__((ext_vector_type(3)));
+typedef __attribute__((address_space(3))) lds_v3f lds_float3;
+
+__device__ __forceinline__ lds_v3f lds_ld3(uint32_t a)
 {
-    *(lds_float4 *)(uintptr_t)a = lds_v4f{v.x, v.y, v.z, v.w};
+    return *(const lds_float3 *)(uintptr_t)a;
+}
+
+__device__ __forceinline__ void lds_st3(uint32_t a, float x, float y, float z)
+{
+    *(lds_float3 *)(uintptr_t)a = lds_v3f{x, y, z};
 }
 
 __device__ __forceinline__ double lds_ld8(uint32_t a)
@@ -1496,7 +1505,7 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
             for (int kk = 0; kk < 32; ++kk) {
                 const uint32_t an = self ^ (uint32_t)(((k0 + kk + 1) & 63) << 4);
                 const float4 An = lds_ld4(an), Bn = lds_ld4(an + 16 * T);
-                const float4 S = lds_ld4(ac + 32 * T);
+                const lds_v3f S = lds_ld3(ac + 32 * T);
                 float jx = S.x, jy = S.y, jz = S.z;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -1526,7 +1535,7 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                     jy = fmaf(-wj, dy, jy);
                     jz = fmaf(-wj, dz, jz);
                 }
-                lds_st4(ac + 32 * T, make_float4(jx, jy, jz, 0.0f));
+                lds_st3(ac + 32 * T, jx, jy, jz);
                 __asm__ __volatile__("" ::: "memory");
                 ac = an;
                 A = An;
