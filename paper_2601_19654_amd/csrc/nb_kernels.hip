@@ -1229,7 +1229,8 @@ struct alignas(512) SymTile64 {
     double rc[T];
     double ax[T], ay[T], az[T];        // tile J's sums
 };
-static_assert(offsetof(SymTile64<64>, m) == 8 * 3 * 64 && offsetof(SymTile64<64>, ax) == 8 * 6 * 64,
+static_assert(offsetof(SymTile64<64>, m) == 8 * 3 * 64 && offsetof(SymTile64<64>, r2) == 8 * 4 * 64 &&
+                  offsetof(SymTile64<64>, rc) == 8 * 5 * 64 && offsetof(SymTile64<64>, ax) == 8 * 6 * 64,
               "SymTile64 layout");
 
 template <int R, bool DIAG, int T>
@@ -1255,9 +1256,8 @@ __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, in
         uint32_t ac = self;
         double jxs = lds_ld8(ac), jys = lds_ld8(ac + 8 * T), jzs = lds_ld8(ac + 16 * T),
                jms = lds_ld8(ac + 24 * T);
-#pragma unroll 1
+#pragma unroll 2
         for (int k = 0; k < 64; ++k) {
-            const int jj = 64 * t + (lane ^ k);
             const uint32_t an = self ^ (uint32_t)(((k + 1) & 63) << 3);
             const double xn = lds_ld8(an), yn = lds_ld8(an + 8 * T), zn = lds_ld8(an + 16 * T),
                          mn = lds_ld8(an + 24 * T);
@@ -1267,14 +1267,14 @@ __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, in
                 const double dx = jxs - xi[r], dy = jys - yi[r], dz = jzs - zi[r];
                 const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
                 double q = rinv3(r2);
-                const bool on = !DIAG || (64 * r + lane < jj);
+                const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ k));
                 if (r2 < thr && on) {
                     // rare: the target's rc from memory (a padded target is a copy
-                    // of body i0)
+                    // of body i0), the source's rc^2 and rc from its LDS record
                     const int li = 64 * r + lane;
                     const double rci = rc[i0 + (li < ni ? li : 0)];
-                    if (r2 < fmax(fmax(rci * rci, DBL_MIN), L.r2[jj])) {
-                        q = changeover_w(r2, fmax(rci, L.rc[jj]), inner);
+                    if (r2 < fmax(fmax(rci * rci, DBL_MIN), lds_ld8(ac + 32 * T))) {
+                        q = changeover_w(r2, fmax(rci, lds_ld8(ac + 40 * T)), inner);
                         ++near;
                     }
                 }
