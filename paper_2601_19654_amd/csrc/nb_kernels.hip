@@ -59,26 +59,32 @@ __device__ __forceinline__ double rsqrt64_acc(double x)
     return fma(0.5 * y, e, y);
 }
 
-// Deterministic block-wide sum of W doubles per thread (fixed tree).
+// Deterministic block-wide sum of W doubles per thread (kBlock threads, fixed
+// order): each wave's 64 values by an xor-shuffle butterfly (both lanes of a
+// pair add the same two values, so every lane ends with the same bits), then
+// the wave sums in wave order.  Every thread returns the block's sums.
 template <int W>
 __device__ __forceinline__ void block_sum(double (&v)[W], double *sh)
 {
-    const int t = threadIdx.x;
+    constexpr int NW = kBlock / 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
 #pragma unroll
     for (int w = 0; w < W; ++w)
-        sh[w * kBlock + t] = v[w];
-    __syncthreads();
-    for (int st = kBlock / 2; st > 0; st >>= 1) {
-        if (t < st) {
+        for (int o = 32; o > 0; o >>= 1)
+            v[w] += __shfl_xor(v[w], o);
+    if (lane == 0) {
 #pragma unroll
-            for (int w = 0; w < W; ++w)
-                sh[w * kBlock + t] += sh[w * kBlock + t + st];
-        }
-        __syncthreads();
+        for (int w = 0; w < W; ++w)
+            sh[w * NW + wv] = v[w];
     }
+    __syncthreads();
 #pragma unroll
-    for (int w = 0; w < W; ++w)
-        v[w] = sh[w * kBlock];
+    for (int w = 0; w < W; ++w) {
+        double t = sh[w * NW];
+        for (int q = 1; q < NW; ++q)
+            t += sh[w * NW + q];
+        v[w] = t;
+    }
     __syncthreads();
 }
 
