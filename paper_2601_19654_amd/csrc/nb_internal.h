@@ -105,6 +105,7 @@ struct Dev {
     // tables
     RBlk *rblk;  int nrb;
     FWork *fwork; int nfw; int maxs;
+    int ns_all;           // the split count of every system with bodies, if they all share it; else 0
     PWork *ework; int new_;
     PWork *dwork; int ndw;
     // scratch

@@ -1681,16 +1681,25 @@ constexpr int kFinThreads = 1024;
 
 __global__ __launch_bounds__(kFinThreads) void k_force_finalize(
     const int *__restrict__ sys_of, const int *__restrict__ nsplit, const double *__restrict__ fpart,
-    int ntot, int maxs, int nsl, double G, double *__restrict__ ax, double *__restrict__ ay,
-    double *__restrict__ az, double h, int kicks, double *vx, double *vy, double *vz)
+    int ntot, int maxs, int ns_all, int nsl, double G, double *__restrict__ ax,
+    double *__restrict__ ay, double *__restrict__ az, double h, int kicks, double *vx, double *vy,
+    double *vz)
 {
     __shared__ double gs[3 * kFinThreads];
     const int B = kFinThreads / nsl;
     const int t = threadIdx.x % B, g = threadIdx.x / B;
     const int i = blockIdx.x * B + t;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    // the velocities to kick, fetched while the partials load
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    if (g == 0 && i < ntot && h != 0.0) {
+        v0 = vx[i];
+        v1 = vy[i];
+        v2 = vz[i];
+    }
     if (i < ntot) {
-        const int ns = nsplit[sys_of[i]];
+        // ns_all != 0: every system has that split count
+        const int ns = ns_all ? ns_all : nsplit[sys_of[i]];
         const int k0 = g * ns / nsl, k1 = (g + 1) * ns / nsl;
         const double *px = fpart + i, *py = px + (size_t)maxs * ntot, *pz = py + (size_t)maxs * ntot;
         int k = k0;
@@ -1736,7 +1745,7 @@ __global__ __launch_bounds__(kFinThreads) void k_force_finalize(
         ay[i] = s1;
         az[i] = s2;
         if (h != 0.0) {
-            double u0 = fma(h, s0, vx[i]), u1 = fma(h, s1, vy[i]), u2 = fma(h, s2, vz[i]);
+            double u0 = fma(h, s0, v0), u1 = fma(h, s1, v1), u2 = fma(h, s2, v2);
             if (kicks == 2) {
                 u0 = fma(h, s0, u0);
                 u1 = fma(h, s1, u1);
@@ -3344,8 +3353,8 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, i
     while (nsl < 16 && nsl * 8 < d.maxs)
         nsl *= 2;
     k_force_finalize<<<cdiv(d.ntot, kFinThreads / nsl), kFinThreads, 0, s>>>(
-        d.sys_of, d.nsplit, d.fpart, d.ntot, d.maxs, nsl, p.G, d.ax, d.ay, d.az, kick_h, kicks,
-        d.vx, d.vy, d.vz);
+        d.sys_of, d.nsplit, d.fpart, d.ntot, d.maxs, d.ns_all, nsl, p.G, d.ax, d.ay, d.az, kick_h,
+        kicks, d.vx, d.vy, d.vz);
     return hipGetLastError();
 }
 

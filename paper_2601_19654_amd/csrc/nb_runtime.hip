@@ -414,6 +414,10 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.nfw = (int)t.fwork.size();
     d.fwork = (FWork *)take(t.fwork.size() * sizeof(FWork));
     d.maxs = t.maxs;
+    d.ns_all = t.maxs;
+    for (int s = 0; s < nsys; ++s)
+        if (t.rb_count[s] > 0 && t.nsplit[s] != t.maxs)
+            d.ns_all = 0;
     d.new_ = (int)t.ework.size();
     d.ework = (PWork *)take(t.ework.size() * sizeof(PWork));
     d.ndw = (int)t.dwork.size();
