@@ -363,6 +363,11 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
     __shared__ double sh[3 * kBlock];
     double rc2 = 0.0;
     RBlk b = rblk[blockIdx.x];
+    const int i = b.start + threadIdx.x;
+    const bool on = i < b.end;
+    // the body's position, loaded while the system's momentum is summed
+    const double x0 = on ? qx[i] : 0.0, y0 = on ? qy[i] : 0.0, z0 = on ? qz[i] : 0.0;
+    const double mi = on && rcrit ? m[i] : 0.0;
     double c[3] = {0.0, 0.0, 0.0};
     double mm = m0[b.sys];
     if (h != 0.0) {
@@ -372,14 +377,12 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
         c[1] = h * P[1] / mm;
         c[2] = h * P[2] / mm;
     }
-    int i = b.start + threadIdx.x;
-    if (i < b.end) {
-        double x = qx[i] + c[0], y = qy[i] + c[1], z = qz[i] + c[2];
+    if (on) {
+        double x = x0 + c[0], y = y0 + c[1], z = z0 + c[2];
         qx[i] = x;
         qy[i] = y;
         qz[i] = z;
         if (rcrit) {
-            double mi = m[i];
             double r = sqrt(x * x + y * y + z * z);
             double rci = n_hill * r * cbrt(mi / (3.0 * mm));
             rc[i] = rci;
@@ -558,6 +561,11 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
     double lnr_lo = INFINITY, lnr_hi = -INFINITY;
     RBlk b = rblk[blockIdx.x];
     int i = b.start + threadIdx.x;
+    const bool on = i < b.end;
+    // the body's state, loaded while the system's momentum is summed
+    const double xs = on ? qx[i] : 0.0, ys = on ? qy[i] : 0.0, zs = on ? qz[i] : 0.0;
+    const double us = on ? vx[i] : 0.0, vs = on ? vy[i] : 0.0, ws = on ? vz[i] : 0.0;
+    const double rci = on ? rc[i] : 0.0, mi = on ? m[i] : 0.0;
     double mu = G * m0[b.sys];
     bool fail = false;
     double pv[3] = {0.0, 0.0, 0.0};
@@ -572,9 +580,10 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
         sd[1] = sun_h * P[1] / mm;
         sd[2] = sun_h * P[2] / mm;
     }
-    if (i < b.end) {
-        double x = qx[i] + sd[0], y = qy[i] + sd[1], z = qz[i] + sd[2];
-        double u = vx[i], v = vy[i], w = vz[i];
+    if (on) {
+        double x = xs + sd[0], y = ys + sd[1], z = zs + sd[2];
+        double u = us, v = vs, w = ws;
+        const double sx = x, sy = y, sz = z;
         q0x[i] = x;
         q0y[i] = y;
         q0z[i] = z;
@@ -588,13 +597,13 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
         // rounding).  Pairs whose chord midpoints are farther apart than
         // R_i + R_j cannot be flagged (see k_encounter).
         {
-            double cx = x - q0x[i], cy = y - q0y[i], cz = z - q0z[i];
+            double cx = x - sx, cy = y - sy, cz = z - sz;
             double rho = 0.5 * sqrt(cx * cx + cy * cy + cz * cz);
-            double ax0 = dt * v0x[i] - cx, ay0 = dt * v0y[i] - cy, az0 = dt * v0z[i] - cz;
+            double ax0 = dt * us - cx, ay0 = dt * vs - cy, az0 = dt * ws - cz;
             double ax1 = dt * u - cx, ay1 = dt * v - cy, az1 = dt * w - cz;
             double eps = sqrt(fmax(ax0 * ax0 + ay0 * ay0 + az0 * az0, ax1 * ax1 + ay1 * ay1 + az1 * az1));
-            double R = (2.0 * rho + 0.75 * eps + rc[i]) * (1.0 + 0x1p-20);
-            double mx = q0x[i] + 0.5 * cx, my = q0y[i] + 0.5 * cy, mz = q0z[i] + 0.5 * cz;
+            double R = (2.0 * rho + 0.75 * eps + rci) * (1.0 + 0x1p-20);
+            double mx = sx + 0.5 * cx, my = sy + 0.5 * cy, mz = sz + 0.5 * cz;
             mr[i] = make_double4(mx, my, mz, R);
             // relative pair filter data: the chord and 3/4 eps, widened by 2^-20
             // and by 2^-45 (|M| + |c|) to cover the rounding of midpoint and chord
@@ -618,9 +627,8 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
         v1x[i] = u;
         v1y[i] = v;
         v1z[i] = w;
-        rc1[i] = rc[i];
+        rc1[i] = rci;
         kflag[i] = fail ? 1 : 0;
-        double mi = m[i];
         pv[0] = mi * u;
         pv[1] = mi * v;
         pv[2] = mi * w;
