@@ -1276,24 +1276,41 @@ __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, in
             const double xn = lds_ld8(an), yn = lds_ld8(an + 8 * T), zn = lds_ld8(an + 16 * T),
                          mn = lds_ld8(an + 24 * T);
             double jx = lds_ld8(ac + 48 * T), jy = lds_ld8(ac + 56 * T), jz = lds_ld8(ac + 64 * T);
+            // the R pairs' geometry first, then one branch for the rare ones,
+            // so that the R chains share one basic block
+            double dxr[R], dyr[R], dzr[R], r2r[R], qr[R];
+            bool cand = false;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double dx = jxs - xi[r], dy = jys - yi[r], dz = jzs - zi[r];
-                const double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-                double q = rinv3(r2);
+                dxr[r] = jxs - xi[r];
+                dyr[r] = jys - yi[r];
+                dzr[r] = jzs - zi[r];
+                r2r[r] = fma(dzr[r], dzr[r], fma(dyr[r], dyr[r], dxr[r] * dxr[r]));
+                qr[r] = rinv3(r2r[r]);
                 const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ k));
-                if (r2 < thr && on) {
-                    // rare: the target's rc from memory (a padded target is a copy
-                    // of body i0), the source's rc^2 and rc from its LDS record
-                    const int li = 64 * r + lane;
-                    const double rci = rc[i0 + (li < ni ? li : 0)];
-                    if (r2 < fmax(fmax(rci * rci, DBL_MIN), lds_ld8(ac + 32 * T))) {
-                        q = changeover_w(r2, fmax(rci, lds_ld8(ac + 40 * T)), inner);
-                        ++near;
+                cand |= r2r[r] < thr && on;
+                if (DIAG)
+                    qr[r] = on ? qr[r] : 0.0;
+            }
+            if (cand) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ k));
+                    if (r2r[r] < thr && on) {
+                        // rare: the target's rc from memory (a padded target is a copy
+                        // of body i0), the source's rc^2 and rc from its LDS record
+                        const int li = 64 * r + lane;
+                        const double rci = rc[i0 + (li < ni ? li : 0)];
+                        if (r2r[r] < fmax(fmax(rci * rci, DBL_MIN), lds_ld8(ac + 32 * T))) {
+                            qr[r] = changeover_w(r2r[r], fmax(rci, lds_ld8(ac + 40 * T)), inner);
+                            ++near;
+                        }
                     }
                 }
-                if (DIAG)
-                    q = on ? q : 0.0;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double dx = dxr[r], dy = dyr[r], dz = dzr[r], q = qr[r];
                 const double wi = jms * q, wj = mi[r] * q;
                 ax[r] = fma(wi, dx, ax[r]);
                 ay[r] = fma(wi, dy, ay[r]);
@@ -1521,26 +1538,40 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                 const float4 An = lds_ld4(an), Bn = lds_ld4(an + 16 * T);
                 const lds_v3f S = lds_ld3(ac + 32 * T);
                 float jx = S.x, jy = S.y, jz = S.z;
+                // the R pairs' geometry first, then one branch for the rare
+                // ones, so that the R chains share one basic block
+                float dxr[R], dyr[R], dzr[R], r2r[R], qr[R];
+                bool cand = false;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    const float dx = (A.x - xh[r]) + (B.x - xl[r]);
-                    const float dy = (A.y - yh[r]) + (B.y - yl[r]);
-                    const float dz = (A.z - zh[r]) + (B.z - zl[r]);
-                    const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-                    const float y = __builtin_amdgcn_rsqf(r2);
-                    float q = y * (y * y);
+                    dxr[r] = (A.x - xh[r]) + (B.x - xl[r]);
+                    dyr[r] = (A.y - yh[r]) + (B.y - yl[r]);
+                    dzr[r] = (A.z - zh[r]) + (B.z - zl[r]);
+                    r2r[r] = fmaf(dzr[r], dzr[r], fmaf(dyr[r], dyr[r], dxr[r] * dxr[r]));
+                    const float y = __builtin_amdgcn_rsqf(r2r[r]);
+                    qr[r] = y * (y * y);
                     const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
-                    if (r2 < thr && on) {
-                        if (changeover_pair32(r2, B.w, pk, i0, 64 * r + lane, ni, j0, ac, a0, T,
+                    cand |= r2r[r] < thr && on;
+                    if (DIAG)
+                        qr[r] = on ? qr[r] : 0.0f;
+                }
+                if (cand) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
+                        if (r2r[r] < thr && on &&
+                            changeover_pair32(r2r[r], B.w, pk, i0, 64 * r + lane, ni, j0, ac, a0, T,
                                               L.ax, fp, plane, !((rare >> r) & 1), qx, qy, qz, m,
                                               rc, inner)) {
                             rare |= 1 << r;
-                            q = 0.0f;
+                            qr[r] = 0.0f;
                             ++near;
                         }
                     }
-                    if (DIAG)
-                        q = on ? q : 0.0f;
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float dx = dxr[r], dy = dyr[r], dz = dzr[r], q = qr[r];
                     const float wi = A.w * q, wj = mi[r] * q;
                     tx[r] = fmaf(wi, dx, tx[r]);
                     ty[r] = fmaf(wi, dy, ty[r]);
