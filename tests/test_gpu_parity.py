@@ -242,7 +242,10 @@ def test_steps_match_oracle(case, mode, algo, step_algo, force_algo):
         assert stats["total_nce"] == total
         e = c.last_encounters()
         ref = [(int(i), int(j)) for (_, ii, jj) in st.enc for i, j in zip(ii, jj)]
-        assert sorted(zip(e.ice.tolist(), e.jce.tolist())) == sorted(ref)
+        got = list(zip(e.ice.tolist(), e.jce.tolist()))
+        # the last step's list, put in (i, j) order when it is read
+        assert got == sorted(got)
+        assert got == sorted(ref)
 
 
 @pytest.mark.parametrize("step_algo", [1, 2])
