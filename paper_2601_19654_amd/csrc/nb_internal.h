@@ -116,6 +116,9 @@ struct Dev {
     // a copy of the last drift's sums taken by the second S(h): the momentum
     // before the next kicks, which leave it unchanged (the pair forces cancel)
     double *rpart_prev() const { return rpart + (size_t)nrb * 8; }
+    double *ptot;         // nsys x 4: per-system sums of m V for the stellar drifts
+    int sys_total;        // some system has more than 64 blocks: its momentum is summed once
+                          // per stellar drift into ptot instead of by each of its blocks
     double *fpart;        // 3 x maxs x ntot force partials
     double *dpart;        // ndw x 4 double-double pair sums (E pair, EK pair)
     double *bpart;        // nrb x 16 body partial sums for diagnostics

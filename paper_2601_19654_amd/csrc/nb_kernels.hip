@@ -103,6 +103,20 @@ __device__ __forceinline__ void system_sum(const double *__restrict__ part, int 
     block_sum<W>(out, sh);
 }
 
+// Per-system sums of the first three columns of the per-block partials (one
+// workgroup per system, the same order as an inline system_sum), for systems with
+// so many blocks that every block summing them again would read the partials
+// quadratically often.
+__global__ void k_sys_total(const int *__restrict__ rb_first, const int *__restrict__ rb_count,
+                            const double *__restrict__ part, double *__restrict__ tot)
+{
+    __shared__ double sh[3 * kBlock];
+    double P[3];
+    system_sum<3>(part, 4, rb_first[blockIdx.x], rb_count[blockIdx.x], P, sh);
+    if (threadIdx.x < 3)
+        tot[(size_t)blockIdx.x * 4 + threadIdx.x] = P[threadIdx.x];
+}
+
 // Changeover weight w = K/r^3 - (dK/dr)/r^2 for a pair at squared distance r2
 // with pair critical radius rc (inner edge `inner` rc).  K = 0 below the inner
 // edge, 1 beyond rc and y^2/(2y^2-2y+1) in between, y = (r - inner rc)/((1-inner) rc).
@@ -354,7 +368,8 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
                             const double *__restrict__ part, double h, double *qx, double *qy,
                             double *qz, int rcrit, const double *__restrict__ m, double n_hill,
                             double *__restrict__ rc, float4 *__restrict__ pk,
-                            double *__restrict__ tile_rc2, double *__restrict__ copy_to)
+                            double *__restrict__ tile_rc2, double *__restrict__ copy_to,
+                            const double *__restrict__ ptot)
 {
     // copy_to: this block's entry of `part` is copied there (nothing else reads
     // that array during the launch)
@@ -371,8 +386,15 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
     double c[3] = {0.0, 0.0, 0.0};
     double mm = m0[b.sys];
     if (h != 0.0) {
+        // the system's momentum: precomputed per system (ptot) or summed here
         double P[3];
-        system_sum<3>(part, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        if (ptot) {
+            P[0] = ptot[(size_t)b.sys * 4];
+            P[1] = ptot[(size_t)b.sys * 4 + 1];
+            P[2] = ptot[(size_t)b.sys * 4 + 2];
+        } else {
+            system_sum<3>(part, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        }
         c[0] = h * P[0] / mm;
         c[1] = h * P[1] / mm;
         c[2] = h * P[2] / mm;
@@ -555,7 +577,7 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
                         double *__restrict__ v1y, double *__restrict__ v1z,
                         double *__restrict__ rc1, const double *__restrict__ part_in,
                         double sun_h, const int *__restrict__ rb_first,
-                        const int *__restrict__ rb_count)
+                        const int *__restrict__ rb_count, const double *__restrict__ ptot)
 {
     __shared__ double sh[3 * kBlock];
     double lnr_lo = INFINITY, lnr_hi = -INFINITY;
@@ -573,8 +595,15 @@ __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict_
     // m V in part_in (same arithmetic as k_sun_drift)
     double sd[3] = {0.0, 0.0, 0.0};
     if (sun_h != 0.0) {
+        // the system's momentum: precomputed per system (ptot) or summed here
         double P[3];
-        system_sum<3>(part_in, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        if (ptot) {
+            P[0] = ptot[(size_t)b.sys * 4];
+            P[1] = ptot[(size_t)b.sys * 4 + 1];
+            P[2] = ptot[(size_t)b.sys * 4 + 2];
+        } else {
+            system_sum<3>(part_in, 4, rb_first[b.sys], rb_count[b.sys], P, sh);
+        }
         const double mm = m0[b.sys];
         sd[0] = sun_h * P[0] / mm;
         sd[1] = sun_h * P[1] / mm;
@@ -3272,9 +3301,13 @@ hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, 
 {
     if (d.nrb == 0)
         return hipSuccess;
+    const bool pre = h != 0.0 && d.sys_total;
+    if (pre)
+        k_sys_total<<<d.nsys, kBlock, 0, s>>>(d.rb_first, d.rb_count, part, d.ptot);
     k_sun_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, part, h, d.qx,
                                           d.qy, d.qz, rcrit, d.m, p.n_hill, d.rc,
-                                          p.mode == 1 ? d.pk : nullptr, d.tile_rc2, copy_to);
+                                          p.mode == 1 ? d.pk : nullptr, d.tile_rc2, copy_to,
+                                          pre ? d.ptot : nullptr);
     return hipGetLastError();
 }
 
@@ -3283,12 +3316,15 @@ hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h,
 {
     if (d.nrb == 0)
         return hipSuccess;
+    const bool pre = sun_h != 0.0 && d.sys_total;
+    if (pre)
+        k_sys_total<<<d.nsys, kBlock, 0, s>>>(d.rb_first, d.rb_count, part_in, d.ptot);
     k_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, dt, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
                                       d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
                                       d.stats, d.rpart_drift(), d.rc, d.mr, d.cr,
                                       d.enc_sorted ? d.lnr_part : nullptr, d.q1x, d.q1y, d.q1z,
                                       d.v1x, d.v1y, d.v1z, d.rc1, part_in, sun_h, d.rb_first,
-                                      d.rb_count);
+                                      d.rb_count, pre ? d.ptot : nullptr);
     return hipGetLastError();
 }
 

@@ -424,6 +424,11 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.dwork = (PWork *)take(t.dwork.size() * sizeof(PWork));
     d.rpart = (double *)take((size_t)d.nrb * 12 * sizeof(double));
     d.tile_rc2 = (double *)take((size_t)std::max(d.nrb, 1) * sizeof(double));
+    d.ptot = (double *)take((size_t)std::max(nsys, 1) * 4 * sizeof(double));
+    d.sys_total = 0;
+    for (int s = 0; s < nsys; ++s)
+        if (t.rb_count[s] > 64)
+            d.sys_total = 1;
     d.fpart = (double *)take((size_t)3 * d.maxs * ntot * sizeof(double));
     d.dpart = (double *)take((size_t)std::max(d.ndw, 1) * 4 * sizeof(double));
     d.bpart = (double *)take((size_t)std::max(d.nrb, 1) * 8 * sizeof(double));
