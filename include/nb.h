@@ -197,7 +197,9 @@ int nb_encounters(nb_ctx *ctx, int cap, int *nce, int32_t *ice, int32_t *jce, in
                   int where);
 
 /* Read the list of the last encounter check (by nb_encounters or the last step
- * of nb_step) without recomputing it. */
+ * of nb_step) without recomputing it; the same layout as nb_encounters (the
+ * list is put in (i,j) order as it is read, the check itself appends in an
+ * arbitrary order). */
 int nb_get_encounters(nb_ctx *ctx, int cap, int *nce, int32_t *ice, int32_t *jce, int32_t *ce,
                       int where);
 
