@@ -103,20 +103,6 @@ __device__ __forceinline__ void system_sum(const double *__restrict__ part, int 
     block_sum<W>(out, sh);
 }
 
-// Per-system sums of the first three columns of the per-block partials (one
-// workgroup per system, the same order as an inline system_sum), for systems with
-// so many blocks that every block summing them again would read the partials
-// quadratically often.
-__global__ void k_sys_total(const int *__restrict__ rb_first, const int *__restrict__ rb_count,
-                            const double *__restrict__ part, double *__restrict__ tot)
-{
-    __shared__ double sh[3 * kBlock];
-    double P[3];
-    system_sum<3>(part, 4, rb_first[blockIdx.x], rb_count[blockIdx.x], P, sh);
-    if (threadIdx.x < 3)
-        tot[(size_t)blockIdx.x * 4 + threadIdx.x] = P[threadIdx.x];
-}
-
 // Changeover weight w = K/r^3 - (dK/dr)/r^2 for a pair at squared distance r2
 // with pair critical radius rc (inner edge `inner` rc).  K = 0 below the inner
 // edge, 1 beyond rc and y^2/(2y^2-2y+1) in between, y = (r - inner rc)/((1-inner) rc).
@@ -356,6 +342,20 @@ __global__ void k_kick(const RBlk *__restrict__ rblk, double h, const double *__
             part_out[(size_t)blockIdx.x * 4 + 3] = 0.0;
         }
     }
+}
+
+// Per-system sums of the first three columns of the per-block partials (one
+// workgroup per system, the same order as an inline system_sum), for systems with
+// so many blocks that every block summing them again would read the partials
+// quadratically often.
+__global__ void k_sys_total(const int *__restrict__ rb_first, const int *__restrict__ rb_count,
+                            const double *__restrict__ part, double *__restrict__ tot)
+{
+    __shared__ double sh[3 * kBlock];
+    double P[3];
+    system_sum<3>(part, 4, rb_first[blockIdx.x], rb_count[blockIdx.x], P, sh);
+    if (threadIdx.x < 3)
+        tot[(size_t)blockIdx.x * 4 + threadIdx.x] = P[threadIdx.x];
 }
 
 // ----------------------------------------------------------------------------
