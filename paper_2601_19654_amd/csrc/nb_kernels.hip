@@ -344,6 +344,11 @@ __global__ void k_kick(const RBlk *__restrict__ rblk, double h, const double *__
     }
 }
 
+// ----------------------------------------------------------------------------
+// Stellar drift Q += h P/m0 (Hamiltonian block loops 2-3), optionally followed
+// by the critical radius rc = n_hill |Q| (m/(3 m0))^(1/3) (Sec. 2.1.1) and the
+// FP32 hi/lo source records of the FP32C force.
+// ----------------------------------------------------------------------------
 // Per-system sums of the first three columns of the per-block partials (one
 // workgroup per system, the same order as an inline system_sum), for systems with
 // so many blocks that every block summing them again would read the partials
@@ -358,11 +363,6 @@ __global__ void k_sys_total(const int *__restrict__ rb_first, const int *__restr
         tot[(size_t)blockIdx.x * 4 + threadIdx.x] = P[threadIdx.x];
 }
 
-// ----------------------------------------------------------------------------
-// Stellar drift Q += h P/m0 (Hamiltonian block loops 2-3), optionally followed
-// by the critical radius rc = n_hill |Q| (m/(3 m0))^(1/3) (Sec. 2.1.1) and the
-// FP32 hi/lo source records of the FP32C force.
-// ----------------------------------------------------------------------------
 __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict__ rb_first,
                             const int *__restrict__ rb_count, const double *__restrict__ m0,
                             const double *__restrict__ part, double h, double *qx, double *qy,
