@@ -2536,19 +2536,19 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
             continue;
         const bool diag = AB.x == AB.y;
         const int j1 = min(TB.count, 16 * wv + 16);
+#pragma unroll 4
         for (int jj = 16 * wv; jj < j1; ++jj) {
             const SRec &J = sb[jj];
             bool hit = false;
-            bool cand = lane_ok && (!diag || jj > lane) && (me.big | J.big);
-            if (cand) {
-                // relative chord filter (see k_encounter)
-                const double mx = J.M[0] - me.M[0], my = J.M[1] - me.M[1], mz = J.M[2] - me.M[2];
-                const double cx = J.c[0] - me.c[0], cy = J.c[1] - me.c[1], cz = J.c[2] - me.c[2];
-                const double D2 = fma(mz, mz, fma(my, my, mx * mx));
-                const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
-                const double bb = J.e34 + me.e34 + fmax(J.rc, me.rc);
-                cand = D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20);
-            }
+            // relative chord filter (see k_encounter), evaluated by every lane
+            // without a branch (the source record is one broadcast read)
+            const double mx = J.M[0] - me.M[0], my = J.M[1] - me.M[1], mz = J.M[2] - me.M[2];
+            const double cx = J.c[0] - me.c[0], cy = J.c[1] - me.c[1], cz = J.c[2] - me.c[2];
+            const double D2 = fma(mz, mz, fma(my, my, mx * mx));
+            const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
+            const double bb = J.e34 + me.e34 + fmax(J.rc, me.rc);
+            const bool cand = lane_ok & (!diag | (jj > lane)) & ((me.big | J.big) != 0) &
+                              (D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20));
             if (__any(cand) && cand) {
                 double d0x = J.q0[0] - me.q0[0], d0y = J.q0[1] - me.q0[1], d0z = J.q0[2] - me.q0[2];
                 double d1x = J.q1[0] - me.q1[0], d1y = J.q1[1] - me.q1[1], d1z = J.q1[2] - me.q1[2];
