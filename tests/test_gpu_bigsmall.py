@@ -101,6 +101,28 @@ def test_steps_match_oracle(case, mode, step_algo, resolve):
         assert stats["total_nce"] == total
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_steps_match_oracle_many_blocks(mode):
+    """One system of 20 big and 20000 small bodies (79 blocks of 256): the stellar
+    drifts take the system momentum from the per-system sum; three steps against
+    the oracle."""
+    w = workloads.bigsmall(20, 20000)
+    k = 3
+    c = ctx_for(w, mode=mode)
+    stats = c.step(w.dt, k)
+    x, v = c.download(nb.NB_DH)
+    st = oracle.State.from_workload(w)
+    total = 0
+    for _ in range(k):
+        st.step(w.dt)
+        total += sum(e[0] for e in st.enc)
+    tol = 1e-11 if mode == 0 else 1e-7
+    assert rel_rows(x, st.Q) <= tol, rel_rows(x, st.Q)
+    assert rel_rows(v, st.V) <= tol * 10, rel_rows(v, st.V)
+    if mode == 0:
+        assert stats["total_nce"] == total
+
+
 def test_big_bodies_ignore_small_ones():
     w = workloads.bigsmall(20, 3000)
     big = workloads.Workload("big", np.array([0, 20], np.int32), w.m0, w.m[:20], w.x[:20], w.v[:20], w.dt, 10)
