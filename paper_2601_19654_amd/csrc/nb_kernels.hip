@@ -2536,7 +2536,6 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
             continue;
         const bool diag = AB.x == AB.y;
         const int j1 = min(TB.count, 16 * wv + 16);
-#pragma unroll 4
         for (int jj = 16 * wv; jj < j1; ++jj) {
             const SRec &J = sb[jj];
             bool hit = false;
