@@ -561,14 +561,15 @@ __device__ int kepler_drift(double mu, double dt, double &x, double &y, double &
     return 0;
 }
 
-// Snapshot, drift, failure flags and counters, encounter flags cleared, and the
-// partial sums of m V after the drift (for the second stellar drift).
+// Snapshot, drift, failure flags and counters, the encounter check's records,
+// and the partial sums of m V after the drift (for the second stellar drift).
+// The check clears its own list and flags, since it may run beside the next drift.
 __global__ void k_drift(const RBlk *__restrict__ rblk, const double *__restrict__ m0, double G,
                         double dt, const double *__restrict__ m, double *qx, double *qy,
                         double *qz, double *vx, double *vy, double *vz, double *__restrict__ q0x,
                         double *__restrict__ q0y, double *__restrict__ q0z,
                         double *__restrict__ v0x, double *__restrict__ v0y,
-                        double *__restrict__ v0z, int *__restrict__ kflag, int *__restrict__ ce,
+                        double *__restrict__ v0z, int *__restrict__ kflag,
                         DevStats *stats, double *__restrict__ part_out,
                         const double *__restrict__ rc, double4 *__restrict__ mr,
                         double4 *__restrict__ cr, double *__restrict__ lnr_part,
@@ -3319,7 +3320,7 @@ hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h,
     if (pre)
         k_sys_total<<<d.nsys, kBlock, 0, s>>>(d.rb_first, d.rb_count, part_in, d.ptot);
     k_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, dt, d.m, d.qx, d.qy, d.qz, d.vx, d.vy,
-                                      d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag, d.ce,
+                                      d.vz, d.q0x, d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.kflag,
                                       d.stats, d.rpart_drift(), d.rc, d.mr, d.cr,
                                       d.enc_sorted ? d.lnr_part : nullptr, d.q1x, d.q1y, d.q1z,
                                       d.v1x, d.v1y, d.v1z, d.rc1, part_in, sun_h, d.rb_first,
