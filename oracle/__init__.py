@@ -39,62 +39,82 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nbody_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# the same source built with OpenMP (targets, bodies and encounter rows split over
+# threads, results bit-identical): the threaded CPU baseline only
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99"]
 
 
+def _stale(path: str) -> bool:
+    return not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC)
+
+
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C99, no contraction, no fast math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the oracle with gcc (plain C99, no contraction, no fast math),
+    serial and with OpenMP."""
+    for path, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or _stale(path):
+            tmp = path + ".tmp"
+            subprocess.check_call(["gcc", *CFLAGS, *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, path)
     return _LIB
 
 
 _lib = None
+_lib_omp = None
 
 
-def lib():
-    global _lib
+def lib(threads: bool = False):
+    """The serial oracle (threads=True: the OpenMP build of the same source)."""
+    global _lib, _lib_omp
+    if threads:
+        if _lib_omp is None:
+            build(force=False)
+            _lib_omp = _load(_LIB_OMP)
+        return _lib_omp
     if _lib is None:
         build(force=False)
-        L = ctypes.CDLL(_LIB)
-        d, i, p = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
-        sig = {
-            "orc_changeover": (None, [d, d, d, p, p]),
-            "orc_rcrit": (None, [i, d, p, p, d, p]),
-            "orc_force": (None, [i, d, d, p, p, p, p]),
-            "orc_force_nb": (None, [i, i, d, d, p, p, p, p]),
-            "orc_force_subset": (None, [i, d, d, p, p, p, i, p, p]),
-            "orc_kick": (None, [i, d, p, p]),
-            "orc_momentum": (None, [i, p, p, p]),
-            "orc_sun_drift": (None, [i, d, d, p, p, p]),
-            "orc_helio_to_dh": (None, [i, d, p, p, p, p, p]),
-            "orc_dh_to_helio": (None, [i, d, p, p, p, p, p]),
-            "orc_stumpff": (None, [d, p]),
-            "orc_kepler_drift": (i, [d, d, p, p]),
-            "orc_drift": (i, [i, d, d, p, p, p]),
-            "orc_pair_min_d2": (d, [d, p, p, p, p, p, p, p, p]),
-            "orc_encounters": (None, [i, d, p, p, p, p, p, i, p, p, p, p, d, i, p, p, p]),
-            "orc_encounters_nb": (None, [i, i, d, p, p, p, p, p, i, p, p, p, p, d, i, p, p, p]),
-            "orc_pair_scan": (None, [i, i, d, p, p, p, p, p, i, d, p, p]),
-            "orc_energy": (None, [i, d, d, d, p, p, p, p, p, p, p, p]),
-            "orc_drag_accel": (None, [i, d, d, p, p, p, p, d, d, d, d, p]),
-            "orc_kick_drag": (None, [i, d, d, d, p, p, p, p, d, d, d, d, p]),
-            "orc_step": (i, [i, i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, p, p, p, p, i, p, p, p, p]),
-            "orc_bs_work_doubles": (i, [i]),
-            "orc_resolve_work_doubles": (i, [i]),
-            "orc_bs_h0": (i, [i, d, d, d, p, p, d, d, p, p, p]),
-            "orc_resolve": (i, [i, d, d, d, p, p, d, d, p, p, i, p, p, p, p, p, p, p, p]),
-            "orc_step_full": (i, [i, i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, d, p, p, p, p, i, p,
-                                  p, p, p, p, p, p, p]),
-        }
-        for name, (res, args) in sig.items():
-            f = getattr(L, name)
-            f.restype = res
-            f.argtypes = args
-        _lib = L
+        _lib = _load(_LIB)
     return _lib
+
+
+def _load(path):
+    L = ctypes.CDLL(path)
+    d, i, p = ctypes.c_double, ctypes.c_int, ctypes.c_void_p
+    sig = {
+        "orc_changeover": (None, [d, d, d, p, p]),
+        "orc_rcrit": (None, [i, d, p, p, d, p]),
+        "orc_force": (None, [i, d, d, p, p, p, p]),
+        "orc_force_nb": (None, [i, i, d, d, p, p, p, p]),
+        "orc_force_subset": (None, [i, i, d, d, p, p, p, i, p, p]),
+        "orc_kick": (None, [i, d, p, p]),
+        "orc_momentum": (None, [i, p, p, p]),
+        "orc_sun_drift": (None, [i, d, d, p, p, p]),
+        "orc_helio_to_dh": (None, [i, d, p, p, p, p, p]),
+        "orc_dh_to_helio": (None, [i, d, p, p, p, p, p]),
+        "orc_stumpff": (None, [d, p]),
+        "orc_kepler_drift": (i, [d, d, p, p]),
+        "orc_drift": (i, [i, d, d, p, p, p]),
+        "orc_pair_min_d2": (d, [d, p, p, p, p, p, p, p, p]),
+        "orc_encounters": (None, [i, d, p, p, p, p, p, i, p, p, p, p, d, i, p, p, p]),
+        "orc_encounters_nb": (None, [i, i, d, p, p, p, p, p, i, p, p, p, p, d, i, p, p, p]),
+        "orc_pair_scan": (None, [i, i, d, p, p, p, p, p, i, d, p, p]),
+        "orc_energy": (None, [i, d, d, d, p, p, p, p, p, p, p, p]),
+        "orc_drag_accel": (None, [i, d, d, p, p, p, p, d, d, d, d, p]),
+        "orc_kick_drag": (None, [i, d, d, d, p, p, p, p, d, d, d, d, p]),
+        "orc_step": (i, [i, i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, p, p, p, p, i, p, p, p, p]),
+        "orc_bs_work_doubles": (i, [i]),
+        "orc_resolve_work_doubles": (i, [i]),
+        "orc_bs_h0": (i, [i, d, d, d, p, p, d, d, p, p, p]),
+        "orc_resolve": (i, [i, d, d, d, p, p, d, d, p, p, i, p, p, p, p, p, p, p, p]),
+        "orc_step_full": (i, [i, i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, d, p, p, p, p, i, p,
+                              p, p, p, p, p, p, p]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    return L
 
 
 def _f64(a, shape=None):
@@ -151,12 +171,15 @@ def force(m, Q, rc, G, inner=0.1, nbig=None):
     return a
 
 
-def force_subset(m, Q, rc, G, idx, inner=0.1):
-    """Accelerations of the targets idx only (same definition as force)."""
+def force_subset(m, Q, rc, G, idx, inner=0.1, nbig=None):
+    """Accelerations of the targets idx only (the same per-target sum as force)."""
     m = _f64(m); Q = _f64(Q, (-1, 3)); rc = _f64(rc)
     idx = np.ascontiguousarray(idx, dtype=np.int32); a = np.empty((len(idx), 3))
-    lib().orc_force_subset(len(m), float(G), float(inner), _ptr(m), _ptr(Q), _ptr(rc), len(idx),
-                           _ptr(idx), _ptr(a))
+    n = len(m)
+    if len(idx) and (idx.min() < 0 or idx.max() >= n):
+        raise IndexError("force_subset: target index out of range")
+    lib().orc_force_subset(n, n if nbig is None else int(nbig), float(G), float(inner), _ptr(m), _ptr(Q),
+                           _ptr(rc), len(idx), _ptr(idx), _ptr(a))
     return a
 
 
@@ -298,8 +321,11 @@ class State:
     force primed at construction (first-same-as-last).
     """
 
-    def __init__(self, off, m0, m, x, v, prm: Params | None = None, frame="helio", nbig=None):
+    def __init__(self, off, m0, m, x, v, prm: Params | None = None, frame="helio", nbig=None,
+                 threads: bool = False):
         self.prm = prm or Params()
+        # threads: steps run in the OpenMP build of the oracle (same results)
+        self.threads = bool(threads)
         self.off = np.asarray(off, dtype=np.int64)
         # per system: bodies [off[s], off[s] + nbig[s]) are big (gravity sources)
         self.nbig = (np.diff(self.off) if nbig is None else np.asarray(nbig, dtype=np.int64)).copy()
@@ -321,9 +347,9 @@ class State:
         self.prime()
 
     @classmethod
-    def from_workload(cls, w, prm: Params | None = None):
+    def from_workload(cls, w, prm: Params | None = None, threads: bool = False):
         prm = prm or Params(G=w.G, drag=w.drag)
-        return cls(w.off, w.m0, w.m, w.x, w.v, prm, nbig=getattr(w, "nbig", None))
+        return cls(w.off, w.m0, w.m, w.x, w.v, prm, nbig=getattr(w, "nbig", None), threads=threads)
 
     def systems(self):
         for s in range(len(self.m0)):
@@ -331,9 +357,13 @@ class State:
 
     def prime(self):
         p = self.prm
+        L = lib(self.threads)
         for s, (a, b) in enumerate(self.systems()):
             self.rc[a:b] = rcrit(self.m0[s], self.m[a:b], self.Q[a:b], p.n_hill)
-            self.a[a:b] = force(self.m[a:b], self.Q[a:b], self.rc[a:b], p.G, p.inner, nbig=self.nbig[s])
+            m = np.ascontiguousarray(self.m[a:b]); Q = np.ascontiguousarray(self.Q[a:b])
+            rc = np.ascontiguousarray(self.rc[a:b]); acc = np.empty((b - a, 3))
+            L.orc_force_nb(b - a, int(self.nbig[s]), p.G, p.inner, _ptr(m), _ptr(Q), _ptr(rc), _ptr(acc))
+            self.a[a:b] = acc
 
     def step(self, tau, cap=None, full=False, tol=1e-12):
         """One hybrid step of every system; returns the total Kepler failures
@@ -345,7 +375,7 @@ class State:
         smallest member, global index) or -1.  ``self.enc`` receives, per
         system, the flagged pair list in global indices."""
         p = self.prm
-        L = lib()
+        L = lib(self.threads)
         nfail = 0
         self.enc = []
         if full:

@@ -107,35 +107,48 @@ void orc_rcrit(int n, double m0, const double *m, const double *Q, double n_hill
 /* bodies (r = 0) contribute nothing; the self term is skipped by index.  */
 /* ------------------------------------------------------------------ */
 /* Big and small bodies (Sec. 2.1): only the first nbig bodies of a system are
- * gravity sources; the others are massless and feel the big ones only. */
+ * gravity sources; the others are massless and feel the big ones only.
+ * The acceleration of one target i: the sum over sources j < nbig, j != i,
+ * in index order. */
+static void force_target(int i, int nbig, double G, double inner, const double *m,
+                         const double *Q, const double *rc, double *ai)
+{
+    nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+    for (int j = 0; j < nbig; ++j) {
+        if (j == i)
+            continue;
+        double dx = Q[3 * j] - Q[3 * i];
+        double dy = Q[3 * j + 1] - Q[3 * i + 1];
+        double dz = Q[3 * j + 2] - Q[3 * i + 2];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 == 0.0)
+            continue;
+        double r = sqrt(r2);
+        double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
+        double K, dK;
+        orc_changeover(r, rcij, inner, &K, &dK);
+        double w = K / (r2 * r) - dK / r2;
+        double f = G * m[j] * w;
+        ns_add(&ax, f * dx);
+        ns_add(&ay, f * dy);
+        ns_add(&az, f * dz);
+    }
+    ai[0] = ns_val(&ax);
+    ai[1] = ns_val(&ay);
+    ai[2] = ns_val(&az);
+}
+
+/* Every target of the system.  Targets are independent, so the OpenMP build
+ * (the threaded CPU baseline) splits them over threads with bit-identical
+ * results. */
 void orc_force_nb(int n, int nbig, double G, double inner, const double *m, const double *Q,
                   const double *rc, double *a)
 {
-    for (int i = 0; i < n; ++i) {
-        nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
-        for (int j = 0; j < nbig; ++j) {
-            if (j == i)
-                continue;
-            double dx = Q[3 * j] - Q[3 * i];
-            double dy = Q[3 * j + 1] - Q[3 * i + 1];
-            double dz = Q[3 * j + 2] - Q[3 * i + 2];
-            double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 == 0.0)
-                continue;
-            double r = sqrt(r2);
-            double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
-            double K, dK;
-            orc_changeover(r, rcij, inner, &K, &dK);
-            double w = K / (r2 * r) - dK / r2;
-            double f = G * m[j] * w;
-            ns_add(&ax, f * dx);
-            ns_add(&ay, f * dy);
-            ns_add(&az, f * dz);
-        }
-        a[3 * i] = ns_val(&ax);
-        a[3 * i + 1] = ns_val(&ay);
-        a[3 * i + 2] = ns_val(&az);
-    }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int i = 0; i < n; ++i)
+        force_target(i, nbig, G, inner, m, Q, rc, a + 3 * i);
 }
 
 void orc_force(int n, double G, double inner, const double *m, const double *Q,
@@ -146,35 +159,12 @@ void orc_force(int n, double G, double inner, const double *m, const double *Q,
 
 /* The same sum for selected targets only (large-N sampled checks): a[k] is
  * the acceleration of body idx[k]. */
-void orc_force_subset(int n, double G, double inner, const double *m, const double *Q,
+void orc_force_subset(int n, int nbig, double G, double inner, const double *m, const double *Q,
                       const double *rc, int k, const int32_t *idx, double *a)
 {
-    for (int t = 0; t < k; ++t) {
-        int i = idx[t];
-        nsum ax = {0, 0}, ay = {0, 0}, az = {0, 0};
-        for (int j = 0; j < n; ++j) {
-            if (j == i)
-                continue;
-            double dx = Q[3 * j] - Q[3 * i];
-            double dy = Q[3 * j + 1] - Q[3 * i + 1];
-            double dz = Q[3 * j + 2] - Q[3 * i + 2];
-            double r2 = dx * dx + dy * dy + dz * dz;
-            if (r2 == 0.0)
-                continue;
-            double r = sqrt(r2);
-            double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
-            double K, dK;
-            orc_changeover(r, rcij, inner, &K, &dK);
-            double w = K / (r2 * r) - dK / r2;
-            double f = G * m[j] * w;
-            ns_add(&ax, f * dx);
-            ns_add(&ay, f * dy);
-            ns_add(&az, f * dz);
-        }
-        a[3 * t] = ns_val(&ax);
-        a[3 * t + 1] = ns_val(&ay);
-        a[3 * t + 2] = ns_val(&az);
-    }
+    (void)n;
+    for (int t = 0; t < k; ++t)
+        force_target(idx[t], nbig, G, inner, m, Q, rc, a + 3 * t);
 }
 
 /* Interaction kick (Sec. 3.1, Hamiltonian block loop 1): V += h a. */
@@ -391,6 +381,9 @@ int orc_kepler_drift(double mu, double tau, double *q, double *v)
 int orc_drift(int n, double mu, double tau, double *Q, double *V, int32_t *flag)
 {
     int nfail = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : nfail)
+#endif
     for (int i = 0; i < n; ++i) {
         int f = orc_kepler_drift(mu, tau, Q + 3 * i, V + 3 * i);
         if (flag)
@@ -460,13 +453,28 @@ double orc_pair_min_d2(double tau, const double *q0i, const double *v0i, const d
     return fmin > 0.0 ? fmin : 0.0;
 }
 
+/* The pair (i, j), i < j: its minimum squared separation over the step and
+ * the threshold rc_ij^2, rc_ij = max(rc_i, rc_j).  Flagged iff d2 <= thr. */
+static void pair_test(int i, int j, double tau, const double *Q0, const double *V0,
+                      const double *Q1, const double *V1, const double *rc, double *d2,
+                      double *thr)
+{
+    *d2 = orc_pair_min_d2(tau, Q0 + 3 * i, V0 + 3 * i, Q1 + 3 * i, V1 + 3 * i, Q0 + 3 * j,
+                          V0 + 3 * j, Q1 + 3 * j, V1 + 3 * j);
+    double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
+    *thr = rcij * rcij;
+}
+
 /* All unordered pairs i<j of one system.  Flagged pairs go to (ice, jce) in
  * (i, j) lexicographic order (up to cap entries; the true count is returned
  * in *nce); ce[i] = ce[j] = 2 for flagged bodies, 0 otherwise.  Pairs whose
  * minimum lies within tie*rc_ij^2 of the threshold are reported in
- * (tie_i, tie_j) (up to tie_cap; true count in *ntie). */
-/* With nbig < n the bodies from nbig on are small: two small bodies do not
- * interact (Sec. 2.1), so only pairs with i < nbig are tested (i < j). */
+ * (tie_i, tie_j) (up to tie_cap; true count in *ntie).
+ * With nbig < n the bodies from nbig on are small: two small bodies do not
+ * interact (Sec. 2.1), so only pairs with i < nbig are tested (i < j).
+ * Rows i are independent: the OpenMP build tests them on several threads and
+ * appends each row's hits in row order (an ordered section), so the list is
+ * the same as the serial one. */
 void orc_encounters_nb(int n, int nbig, double tau, const double *Q0, const double *V0,
                        const double *Q1, const double *V1, const double *rc, int cap,
                        int32_t *ice, int32_t *jce, int32_t *ce, int *nce, double tie,
@@ -475,29 +483,44 @@ void orc_encounters_nb(int n, int nbig, double tau, const double *Q0, const doub
     int cnt = 0, tcnt = 0;
     for (int i = 0; i < n; ++i)
         ce[i] = 0;
-    for (int i = 0; i < nbig; ++i) {
-        for (int j = i + 1; j < n; ++j) {
-            double d2 = orc_pair_min_d2(tau, Q0 + 3 * i, V0 + 3 * i, Q1 + 3 * i, V1 + 3 * i,
-                                        Q0 + 3 * j, V0 + 3 * j, Q1 + 3 * j, V1 + 3 * j);
-            double rcij = rc[i] > rc[j] ? rc[i] : rc[j];
-            double thr = rcij * rcij;
-            if (d2 <= thr) {
-                if (cnt < cap) {
-                    ice[cnt] = i;
-                    jce[cnt] = j;
-                }
-                ++cnt;
-                ce[i] = 2;
-                ce[j] = 2;
+#ifdef _OPENMP
+#pragma omp parallel
+#endif
+    {
+        /* one row's hits (2 bits per source: flagged, in the tie band) */
+        unsigned char *row = (unsigned char *)malloc(n > 0 ? (size_t)n : 1);
+#ifdef _OPENMP
+#pragma omp for ordered schedule(static, 1)
+#endif
+        for (int i = 0; i < nbig; ++i) {
+            for (int j = i + 1; j < n; ++j) {
+                double d2, thr;
+                pair_test(i, j, tau, Q0, V0, Q1, V1, rc, &d2, &thr);
+                row[j] = (unsigned char)((d2 <= thr ? 1 : 0) | (fabs(d2 - thr) <= tie * thr ? 2 : 0));
             }
-            if (fabs(d2 - thr) <= tie * thr) {
-                if (tcnt < tie_cap) {
-                    tie_i[tcnt] = i;
-                    tie_j[tcnt] = j;
+#ifdef _OPENMP
+#pragma omp ordered
+#endif
+            for (int j = i + 1; j < n; ++j) {
+                if (row[j] & 1) {
+                    if (cnt < cap) {
+                        ice[cnt] = i;
+                        jce[cnt] = j;
+                    }
+                    ++cnt;
+                    ce[i] = 2;
+                    ce[j] = 2;
                 }
-                ++tcnt;
+                if (row[j] & 2) {
+                    if (tcnt < tie_cap) {
+                        tie_i[tcnt] = i;
+                        tie_j[tcnt] = j;
+                    }
+                    ++tcnt;
+                }
             }
         }
+        free(row);
     }
     *nce = cnt;
     *ntie = tcnt;
@@ -524,11 +547,8 @@ void orc_pair_scan(int n, int nbig, double tau, const double *Q0, const double *
         tieflag[j] = 0;
         if (j == i || (i >= nbig && j >= nbig))
             continue;
-        int a = i < j ? i : j, b = i < j ? j : i;
-        double d2 = orc_pair_min_d2(tau, Q0 + 3 * a, V0 + 3 * a, Q1 + 3 * a, V1 + 3 * a,
-                                    Q0 + 3 * b, V0 + 3 * b, Q1 + 3 * b, V1 + 3 * b);
-        double rcij = rc[a] > rc[b] ? rc[a] : rc[b];
-        double thr = rcij * rcij;
+        double d2, thr;
+        pair_test(i < j ? i : j, i < j ? j : i, tau, Q0, V0, Q1, V1, rc, &d2, &thr);
         flag[j] = d2 <= thr;
         tieflag[j] = fabs(d2 - thr) <= tie * thr;
     }

@@ -161,7 +161,7 @@ def test_few_source_force(mode, tol, r):
     c = ctx_for(w, mode=mode, force_r=r)
     a = c.accel()
     idx = _sample(w.ntot, 2000, 17, np.arange(50))
-    ref = oracle.force_subset(w.m, Q, rc, w.G, idx)
+    ref = oracle.force_subset(w.m, Q, rc, w.G, idx, nbig=int(w.nbig[0]))
     A = pair_scale(w.m, Q, w.G, idx, chunk=256)
     err = float(np.max(np.max(np.abs(a[idx] - ref), axis=1) / A))
     print(f"few sources mode {mode} r {r}: accel error {err:.3e} A_i")
