@@ -8,10 +8,14 @@ i ~ Rayleigh(0.005), dt = 0.0021875 yr (0.0175 yr halved until an FP64 run of
 
 A step is one whole hybrid step K S D C S F K (kick, stellar drift, Kepler
 drift, encounter check, stellar drift, critical radii + force, kick) of that
-system, replayed from a captured HIP graph; the state stays resident in HBM.
-Prints one JSON line: Gpair/s = N(N-1) x steps / wall time of the timed steps
-(FP32C pair arithmetic as the headline, FP64 alongside), steps/s, the force
-kernel against its roofline, and the CPU oracle timed on a bounded sample.
+system, replayed from captured HIP graphs built before the timed region; the
+state stays resident in HBM.  Prints one JSON line: Gpair/s = N(N-1) x steps /
+device time of the timed steps (HIP events on the context's stream; FP32C pair
+arithmetic as the headline, FP64 alongside), steps/s, the median of 5 further
+timed calls, the energy error of each line over 1e4 steps (E_K for the hot
+path, E for the full method with encounters resolved on the host), the force
+kernel against its roofline, and the CPU oracle (median of 5 steps, serial and
+OpenMP).
 """
 from __future__ import annotations
 
@@ -64,7 +68,19 @@ def traffic_from_profiles(mode: str, workload: str = "c3"):
     return float(t.group(1))
 
 
-def run_mode(w, mode: str, steps: int, warmup: int, torch, nb, resolve: bool = False):
+def _dev_ms(ctx, torch, fn):
+    """Device milliseconds of fn() between two HIP events on the context's stream."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(ctx.stream)
+    out = fn()
+    e1.record(ctx.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1), out
+
+
+def run_mode(w, mode: str, steps: int, warmup: int, torch, nb, resolve: bool = False,
+             energy_steps: int = 0):
     p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64, drag=int(w.drag),
                           resolve=int(resolve))
     ctx = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", nbig=w.nbig)
@@ -72,32 +88,63 @@ def run_mode(w, mode: str, steps: int, warmup: int, torch, nb, resolve: bool = F
              "enc_jchunk": ctx.params.enc_jchunk, **ctx.choices()}
     ctx.upload(w.m0, w.m, w.x, w.v)
     pairs = w.pairs()
-    # warmup (untimed), also builds the step graph
+    allow = (nb.NB_E_CAPACITY, nb.NB_E_KEPLER)
+    # warm-up steps (untimed), then the captured runs the timed call replays
+    # are built before the timed region (nb_prepare runs no step)
     if warmup > 0:
         ctx.step_async(w.dt, warmup)
-    # timed region: exactly `steps` steps of one nb_step call
+    ctx.prepare(w.dt, steps)
+    # timed region: exactly `steps` steps of one nb_step call, device time from
+    # HIP events on the context's stream, host wall time beside it
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
-    ev0.record(ctx.stream)
-    stats = ctx.step(w.dt, steps, allow=(nb.NB_E_CAPACITY, nb.NB_E_KEPLER))
-    ev1.record(ctx.stream)
+    dev_ms, stats = _dev_ms(ctx, torch, lambda: ctx.step(w.dt, steps, allow=allow))
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    dev_ms = ev0.elapsed_time(ev1)
-    # per-kernel timing with HIP events on the context's stream
-    force_ms = ctx.time_kernel(nb.NB_K_FORCE, reps=20)
-    enc_ms = ctx.time_kernel(nb.NB_K_ENCOUNTER, reps=10)
+    # replay protocol: 3 warm-up replays of the same call, then the median of 5
+    for _ in range(3):
+        ctx.step_async(w.dt, steps)
+    reps = sorted(_dev_ms(ctx, torch, lambda: ctx.step_async(w.dt, steps))[0] for _ in range(5))
+    # per-kernel timing with HIP events on the context's stream (after the steps:
+    # the force at the current state, the check on the last step's drift)
+    force_ms = ctx.time_kernel(nb.NB_K_FORCE, reps=100)
+    enc_ms = ctx.time_kernel(nb.NB_K_ENCOUNTER, reps=20) if not resolve else None
     a_gpu = ctx.accel()
     x, v = ctx.download(nb.NB_DH)
     ctx.close()
-    return {
-        "wall_s": wall, "device_ms": dev_ms, "ms_per_step": 1e3 * wall / steps,
-        "gpair_s": pairs * steps / wall / 1e9, "steps_per_s": steps / wall,
+    out = {
+        "wall_s": wall, "device_ms": dev_ms, "ms_per_step": dev_ms / steps,
+        "wall_ms_per_step": 1e3 * wall / steps,
+        "replay_median_ms_per_step": reps[2] / steps,
+        "replay_ms_per_step": [round(r / steps, 5) for r in reps],
+        "gpair_s": pairs * steps / (dev_ms * 1e-3) / 1e9, "steps_per_s": steps / (dev_ms * 1e-3),
         "force_ms": force_ms, "encounter_ms": enc_ms, "stats": stats,
         "a": a_gpu, "Q": x, "tiles": tiles,
     }
+    if energy_steps > 0:
+        out["energy"] = energy_run(w, mode, energy_steps, nb, resolve)
+    return out
+
+
+def energy_run(w, mode, steps, nb, resolve, every=100, bound=1e-9):
+    """Relative errors of E and E_K over `steps` steps from the upload state,
+    sampled every `every` steps (FP64 diagnostics on the device)."""
+    p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64, drag=int(w.drag),
+                          resolve=int(resolve))
+    c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", nbig=w.nbig)
+    c.upload(w.m0, w.m, w.x, w.v)
+    d0 = c.diagnostics()
+    dE = dEK = 0.0
+    for k in range(0, steps, every):
+        c.step(w.dt, min(every, steps - k), allow=(nb.NB_E_CAPACITY, nb.NB_E_KEPLER))
+        d = c.diagnostics()
+        dE = max(dE, float(np.max(np.abs((d["E"] - d0["E"]) / d0["E"]))))
+        dEK = max(dEK, float(np.max(np.abs((d["EK"] - d0["EK"]) / d0["EK"]))))
+    c.close()
+    return {"steps": steps, "dt": w.dt, "max_rel_dE": dE, "max_rel_dEK": dEK, "bound": bound,
+            "meets_dE": dE <= bound, "meets_dEK": dEK <= bound,
+            "conserved": "E (whole Hamiltonian, encounters resolved)" if resolve
+            else "E_K (changeover-weighted; flagged encounters are not resolved on the hot path)"}
 
 
 KERNEL_SUFFIX = {1: "", 2: "_sym", 3: "_few"}
@@ -169,9 +216,22 @@ def cpu_baseline_sampled(w, max_pairs):
             "steps_per_s": round(1.0 / step, 6)}
 
 
-def cpu_baseline(w, max_pairs=4e8):
-    """Full hybrid steps of the same workload by the CPU oracle (1 thread),
-    on as many whole systems as fit about max_pairs pair interactions."""
+def _omp_threads():
+    """Threads the OpenMP build of the oracle runs with (its runtime's own count)."""
+    import ctypes
+    import oracle
+    oracle.lib(threads=True)
+    try:
+        return int(ctypes.CDLL(oracle._LIB_OMP).omp_get_max_threads())
+    except (OSError, AttributeError):
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(w, max_pairs=4e8, steps=5):
+    """Full hybrid steps of the same workload by the CPU oracle: the median of
+    `steps` timed steps on 1 thread, and beside it the median of the same steps
+    by the OpenMP build of the oracle (bit-identical results), on as many whole
+    systems as fit about max_pairs pair interactions."""
     import oracle
     import workloads as W
     oracle.build(force=False)
@@ -190,14 +250,48 @@ def cpu_baseline(w, max_pairs=4e8):
     sub = W.Workload(w.name, (w.off[keep[0]:keep[-1] + 2] - lo).astype(np.int32), w.m0[keep],
                      w.m[lo:hi], w.x[lo:hi], w.v[lo:hi], w.dt, 1, G=w.G, drag=w.drag,
                      nbig=None if w.nbig is None else np.asarray(w.nbig)[keep])
-    st = oracle.State.from_workload(sub)      # includes the first force evaluation
-    t0 = time.perf_counter()
-    st.step(w.dt)
-    dt = time.perf_counter() - t0
+
+    def median_step(threads):
+        st = oracle.State.from_workload(sub, threads=threads)   # includes the first force evaluation
+        ts = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            st.step(w.dt)
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts)), st
+
+    t1, st1 = median_step(False)
+    tn, stn = median_step(True)
+    same = bool(np.array_equal(st1.Q, stn.Q) and np.array_equal(st1.V, stn.V))
+    nthr = _omp_threads()
     what = f"{len(keep)} of {w.nsys} systems" if w.nsys > 1 else f"the N={w.ntot} system"
-    return {"value": round(sub.pairs() / dt / 1e9, 5), "unit": "Gpair/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 full hybrid step of {what} (FP64, serial), {dt:.2f} s",
-            "steps_per_s": round(1.0 / dt, 5) if w.nsys == 1 else None}
+    return {"value": round(sub.pairs() / t1 / 1e9, 5), "unit": "Gpair/s", "cores": 1, "kind": "oracle",
+            "sample": f"median of {steps} full hybrid steps of {what} (FP64, serial): {t1:.3f} s per step",
+            "steps_per_s": round(1.0 / t1, 5) if w.nsys == 1 else None,
+            "oracle_omp": {"value": round(sub.pairs() / tn / 1e9, 5), "unit": "Gpair/s", "cores": nthr,
+                           "kind": "oracle-OMP", "s_per_step": round(tn, 4),
+                           "sample": f"median of {steps} steps of the OpenMP build ({nthr} threads; "
+                                     f"targets, bodies and encounter rows split over threads)",
+                           "bit_identical_to_serial": same}}
+
+
+def mode_line(w, rr, steps, pairs):
+    """The per-mode summary of a run_mode result."""
+    out = {"gpair_s": round(rr["gpair_s"], 3), "steps_per_s": round(rr["steps_per_s"], 3),
+           "ms_per_step": round(rr["ms_per_step"], 5),
+           "wall_ms_per_step": round(rr["wall_ms_per_step"], 5),
+           "replay_median_ms_per_step": round(rr["replay_median_ms_per_step"], 5),
+           "replay_ms_per_step": rr["replay_ms_per_step"],
+           "force_kernel_ms": round(rr["force_ms"], 5),
+           "encounter_kernel_ms": None if rr["encounter_ms"] is None else round(rr["encounter_ms"], 5),
+           "force_gpair_s": round(pairs / (rr["force_ms"] * 1e-3) / 1e9, 2),
+           "tiles": rr["tiles"],
+           "nce_per_step": rr["stats"]["total_nce"] / steps,
+           "resolved_groups_per_step": rr["stats"]["resolved_groups"] / steps,
+           "accel_err_vs_oracle": accel_error(w, rr["a"], rr["Q"])}
+    if "energy" in rr:
+        out["energy"] = rr["energy"]
+    return out
 
 
 def main():
@@ -209,7 +303,13 @@ def main():
     ap.add_argument("--workload", default="c3", help="c1..c5 or bigsmall (the headline is c3)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--resolve", action="store_true",
-                    help="full hybrid method: resolve close encounters on the host every step")
+                    help="full hybrid method on the headline lines: resolve close encounters on "
+                         "the host every step")
+    ap.add_argument("--energy-steps", type=int, default=None,
+                    help="steps of the energy-error run of every line (default: 10000 for c3, "
+                         "else 0 = none)")
+    ap.add_argument("--no-full-method", action="store_true",
+                    help="skip the full-method lines (c3 adds them by default)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -225,15 +325,27 @@ def main():
     nb.lib()
 
     w = workloads.by_name(args.workload)
+    energy_steps = args.energy_steps if args.energy_steps is not None else (10000 if w.name == "c3" else 0)
+    full_lines = w.name == "c3" and not args.resolve and not args.no_full_method
     modes = [m for m in args.modes.split(",") if m]
-    res = {}
+    res, full = {}, {}
     for mode in modes:
         print(f"[bench] {w.name} mode {mode}: ntot={w.ntot}, warmup {args.warmup}, steps {args.steps}",
               file=sys.stderr, flush=True)
-        res[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb, resolve=args.resolve)
-        print(f"[bench] mode {mode}: {res[mode]['ms_per_step']:.4f} ms/step, "
-              f"force {res[mode]['force_ms']:.4f} ms, encounter {res[mode]['encounter_ms']:.4f} ms",
+        res[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb, resolve=args.resolve,
+                             energy_steps=energy_steps)
+        enc = res[mode]["encounter_ms"]
+        print(f"[bench] mode {mode}: {res[mode]['ms_per_step']:.4f} ms/step (replay median "
+              f"{res[mode]['replay_median_ms_per_step']:.4f}, wall {res[mode]['wall_ms_per_step']:.4f}), "
+              f"force {res[mode]['force_ms']:.4f} ms, encounter {enc if enc is None else round(enc, 4)} ms"
+              + (f", energy {res[mode]['energy']}" if "energy" in res[mode] else ""),
               file=sys.stderr, flush=True)
+        if full_lines:
+            full[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb, resolve=True,
+                                  energy_steps=energy_steps)
+            print(f"[bench] full method {mode}: {full[mode]['ms_per_step']:.4f} ms/step"
+                  + (f", energy {full[mode]['energy']}" if "energy" in full[mode] else ""),
+                  file=sys.stderr, flush=True)
     if args.copy_probe:
         src = torch.empty(256 << 20, dtype=torch.uint8, device="cuda:0")
         dst = torch.empty_like(src)
@@ -265,17 +377,15 @@ def main():
         "config": {"workload": desc, "n_bodies": n, "n_systems": w.nsys, "pairs_per_step": pairs,
                    "mode": head, "tiles": r["tiles"], "parallelism": "single GPU"},
         "steps_per_s": round(r["steps_per_s"], 3),
+        "timing": "value and ms_per_step: device time (HIP events on the context's stream) of the "
+                  "one timed nb_step call of exactly `steps` steps, its captured runs built "
+                  "beforehand; wall_ms_per_step: host time of that call; replay_median_ms_per_step: "
+                  "median of 5 further timed calls after 3 warm-up calls",
     }
     for mode, rr in res.items():
-        out[mode] = {"gpair_s": round(rr["gpair_s"], 3), "steps_per_s": round(rr["steps_per_s"], 3),
-                     "ms_per_step": round(rr["ms_per_step"], 5),
-                     "force_kernel_ms": round(rr["force_ms"], 5),
-                     "encounter_kernel_ms": round(rr["encounter_ms"], 5),
-                     "force_gpair_s": round(pairs / (rr["force_ms"] * 1e-3) / 1e9, 2),
-                     "tiles": rr["tiles"],
-                     "nce_per_step": rr["stats"]["total_nce"] / args.steps,
-                     "resolved_groups_per_step": rr["stats"]["resolved_groups"] / args.steps,
-                     "accel_err_vs_oracle": accel_error(w, rr["a"], rr["Q"])}
+        out[mode] = mode_line(w, rr, args.steps, pairs)
+    if full:
+        out["full_method"] = {mode: mode_line(w, rr, args.steps, pairs) for mode, rr in full.items()}
     out["roofline"] = roofline(head, pairs, r["force_ms"], args.workload, r["tiles"]["force_algo"])
     if "fp64" in res and head != "fp64":
         out["roofline_fp64"] = roofline("fp64", pairs, res["fp64"]["force_ms"], args.workload,

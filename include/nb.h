@@ -52,7 +52,7 @@ extern "C" {
 #endif
 
 #define NB_VERSION_MAJOR 0
-#define NB_VERSION_MINOR 1
+#define NB_VERSION_MINOR 2
 
 /* status codes */
 #define NB_OK            0
@@ -109,6 +109,15 @@ typedef struct nb_params {
                              2 each unordered pair once and applied to both bodies (tile pairs;
                              every body big); automatic takes 2 where it applies */
     double  bs_tol;       /* Bulirsch-Stoer relative tolerance (0: 1e-12) */
+    const char *autotune_path; /* tuning table written by the autotuner (text; NULL: none).
+                             When every tile and algorithm field above (force_jchunk,
+                             force_r, enc_jchunk, enc_algo, step_algo, force_algo) is 0,
+                             nb_workspace_size and nb_create take them from the table's
+                             entry for this GPU, mode and size class (largest system and
+                             system count, and the largest big-body count when some
+                             bodies are small, each rounded up to a power of two); a
+                             class the table lacks keeps the defaults.  An unreadable
+                             file is NB_E_INVALID.  Read during the call only. */
 } nb_params;
 
 /* largest system the persistent step launch accepts */
@@ -212,6 +221,15 @@ int nb_get_encounters(nb_ctx *ctx, int cap, int *nce, int32_t *ice, int32_t *jce
  * step resolves the pairs the list holds); the state is still advanced. */
 int nb_step(nb_ctx *ctx, double dt, int nsteps, nb_stats *st);
 
+/* Capture, ahead of time, the HIP graphs that nb_step(ctx, dt, nsteps) replays
+ * (runs of 8 steps and one run of the remainder, kept per run length for one
+ * dt; a new dt replaces them), so that the nb_step call itself only launches
+ * them.  Runs no step and leaves the state alone.  Does nothing (NB_OK) without
+ * a stream, with resolve = 1 or with the persistent step launch.  An
+ * implementation aid for timing and for callers that must not capture inside
+ * their loop; not a step of the method. */
+int nb_prepare(nb_ctx *ctx, double dt, int nsteps);
+
 typedef struct nb_resolve_info {
     int32_t groups;     /* groups integrated */
     int32_t bodies;     /* their members */
@@ -271,6 +289,11 @@ int nb_time_kernel(nb_ctx *ctx, int which, int reps, double dt, double *ms_per_l
  * partners); step launch 1
  * (per phase) or 2 (persistent). */
 int nb_get_choices(const nb_ctx *ctx, int32_t *force_algo, int32_t *enc_algo, int32_t *step_algo);
+
+/* The parameters the context runs with (tile and algorithm fields after the
+ * tuning table and the automatic choices of nb_create; autotune_path NULL);
+ * *tuned (may be NULL) = 1 if they came from the tuning table. */
+int nb_get_params(const nb_ctx *ctx, nb_params *out, int32_t *tuned);
 
 /* Release the context (not the workspace). */
 int nb_destroy(nb_ctx *ctx);

@@ -3,9 +3,10 @@
 For a given batch of systems it times, with HIP events on the context's stream
 (nb_time_kernel), the whole force evaluation (force kernel plus the sum of its
 split partials) over targets-per-lane x sources-per-work-item candidates and the encounter kernel over sources-per-work-item candidates, and
-stores the fastest choice in ``tuning.json`` under
-``<arch>/<mode>/n<max system size, next power of two>/s<systems, next power of two>``.
-``Context`` applies a cached entry whenever the caller leaves the tile fields at 0.
+stores the fastest choice in ``tuning.json`` (with every candidate's time) under
+``<arch>/<mode>/n<max system size, next power of two>/s<systems, next power of two>``,
+and the chosen fields in ``tuning.tsv``, the table the library itself reads
+(``nb_params.autotune_path``) whenever the caller leaves the tile fields at 0.
 
     python -m paper_2601_19654_amd.autotune --workloads c1,c2,c3,c4,c5
 """
@@ -50,15 +51,26 @@ def key(mode: str, off, arch_name: str | None = None, nbig=None) -> str:
     return k
 
 
+TABLE = os.path.join(PKG, "tuning.tsv")
+TABLE_FIELDS = ("force_algo", "force_r", "force_jchunk", "enc_algo", "enc_jchunk", "step_algo")
+
+
+def write_table(cache: dict, path: str = TABLE) -> None:
+    """The table the library reads (nb_params.autotune_path): one line per size
+    class, the key then the six chosen fields."""
+    lines = ["# key " + " ".join(TABLE_FIELDS) + "  (written by autotune.py from tuning.json)"]
+    for k in sorted(cache):
+        e = cache[k]
+        lines.append(k + " " + " ".join(str(int(e.get(f, 0))) for f in TABLE_FIELDS))
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def load_cache() -> dict:
     if os.path.exists(CACHE):
         with open(CACHE) as f:
             return json.load(f)
     return {}
-
-
-def lookup(mode: str, off, arch_name: str | None = None, nbig=None):
-    return load_cache().get(key(mode, off, arch_name, nbig))
 
 
 def _mode_id(mode):
@@ -172,6 +184,7 @@ def main():
                   file=sys.stderr, flush=True)
             with open(args.out, "w") as f:
                 json.dump(cache, f, indent=1, sort_keys=True)
+            write_table(cache, os.path.join(os.path.dirname(os.path.abspath(args.out)), "tuning.tsv"))
 
 
 if __name__ == "__main__":

@@ -401,9 +401,13 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
     }
     if (on) {
         double x = x0 + c[0], y = y0 + c[1], z = z0 + c[2];
-        qx[i] = x;
-        qy[i] = y;
-        qz[i] = z;
+        // with h = 0 (critical radii only) Q is left as it is: the positions
+        // may then be a caller's read-only input
+        if (h != 0.0) {
+            qx[i] = x;
+            qy[i] = y;
+            qz[i] = z;
+        }
         if (rcrit) {
             double r = sqrt(x * x + y * y + z * z);
             double rci = n_hill * r * cbrt(mi / (3.0 * mm));
@@ -414,9 +418,11 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
                 float lx = (float)(x - (double)hx), ly = (float)(y - (double)hy),
                       lz = (float)(z - (double)hz);
                 // squared radius widened by 2^-9 so the FP32 zone test is a superset of
-                // the FP64 one; never below FLT_MIN so coincident bodies take the FP64 path
+                // the FP64 one; never below 2^-80, so that pairs closer than 2^-40 (where
+                // the FP32 weight r^-3 would overflow: massless bodies have rc = 0, and
+                // 0 * inf is NaN) and coincident bodies take the FP64 path
                 float r2 = (float)(rci * rci * (1.0 + 0x1p-9));
-                r2 = fmaxf(r2, FLT_MIN);
+                r2 = fmaxf(r2, 0x1p-80f);
                 pk[2 * (size_t)i] = make_float4(hx, hy, hz, (float)mi);
                 pk[2 * (size_t)i + 1] = make_float4(lx, ly, lz, r2);
             }

@@ -20,14 +20,23 @@ using namespace nb;
 
 struct nb_ctx {
     Params p;
+    bool tuned = false;   // tile and algorithm fields taken from the tuning table
     int nsys = 0, ntot = 0, enc_cap = 0;
     int device = 0;
     hipStream_t stream = nullptr;
     Dev d{};
     std::vector<int> off;
     bool have_state = false, have_drift = false, have_enc = false;
+    // the drift outputs of set `snap` hold the last drift or per-phase step
+    // (the persistent step launch does not write them)
+    bool snap_valid = false;
     double last_dt = 0.0;
-    hipGraphExec_t gexec = nullptr;
+    // captured runs of steps, one per length (1 .. kMaxGraphSteps) for one dt
+    struct Graph {
+        int steps;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
     // second stream on which the sorted encounter test overlaps S(h) and the force
     hipStream_t side = nullptr;
     // one fork and one join event per set of drift outputs
@@ -36,7 +45,6 @@ struct nb_ctx {
     // rpart_prev() holds the momentum of the current V (kept by the steps)
     bool mom_valid = false;
     double graph_dt = 0.0;
-    int graph_steps = 0;
     std::string err;
     // close-encounter resolver (resolve = 1): pinned staging of the step's count
     // and pair records (host reads), result rows (host writes; the next step's
@@ -115,6 +123,74 @@ int resolver_threads(int requested)
         return requested;
     const unsigned hw = std::thread::hardware_concurrency();
     return (int)std::max(1u, std::min(hw, 16u));
+}
+
+int next_pow2(int n);
+
+// Tuning table (written by the autotuner): one line per size class,
+//   <arch>/<fp64|fp32c>/n<N>/s<S>[/b<B>] force_algo force_r force_jchunk enc_algo enc_jchunk step_algo
+// with N the largest system and S the number of systems rounded up to powers of
+// two, and B (only when some bodies are small) the largest big-body count, also
+// rounded up; '#' starts a comment.  When every tile and algorithm field of the
+// parameters is 0 and the table has the context's class, its fields are used.
+// Returns NB_E_INVALID if the file cannot be read, NB_OK otherwise (a class not
+// in the table leaves the defaults).
+int apply_tuning(const nb_params &u, int nsys, const int32_t *off, const int32_t *nbig, Params &q,
+                 bool *tuned, std::string *why)
+{
+    *tuned = false;
+    if (!u.autotune_path || u.force_r || u.force_jchunk || u.enc_jchunk || u.enc_algo ||
+        u.step_algo || u.force_algo)
+        return NB_OK;
+    FILE *f = std::fopen(u.autotune_path, "r");
+    if (!f) {
+        if (why)
+            *why = std::string("cannot read the tuning table ") + u.autotune_path;
+        return NB_E_INVALID;
+    }
+    int dev = 0;
+    hipDeviceProp_t prop;
+    std::string arch = "unknown";
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        arch = prop.gcnArchName;
+        arch = arch.substr(0, arch.find(':'));
+    }
+    int nmax = 0, bmax = 0;
+    bool small = false;
+    for (int s = 0; s < nsys; ++s) {
+        const int n = off[s + 1] - off[s], b = nbig ? nbig[s] : n;
+        nmax = std::max(nmax, n);
+        bmax = std::max(bmax, b);
+        small = small || b < n;
+    }
+    std::string key = arch + (q.mode == NB_FP32C ? "/fp32c" : "/fp64") + "/n" +
+                      std::to_string(next_pow2(std::max(nmax, 1))) + "/s" +
+                      std::to_string(next_pow2(nsys));
+    if (small)
+        key += "/b" + std::to_string(next_pow2(std::max(bmax, 1)));
+    char line[512], k[256];
+    int fa, fr, fj, ea, ej, sa;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#')
+            continue;
+        if (std::sscanf(line, "%255s %d %d %d %d %d %d", k, &fa, &fr, &fj, &ea, &ej, &sa) != 7 ||
+            key != k)
+            continue;
+        if (fa < 0 || fa > 2 || (fr != 1 && fr != 2 && fr != 4) || fj <= 0 || ea < 0 || ea > 3 ||
+            ej <= 0 || sa < 0 || sa > 2)
+            break;     // a malformed entry is ignored
+        q.force_algo = fa;
+        q.force_r = fr;
+        q.force_j = (fj + kBlock - 1) / kBlock * kBlock;
+        q.enc_algo = ea;
+        q.enc_j = ej;
+        // the persistent launch cannot hand groups to the host resolver
+        q.step_algo = q.resolve ? 0 : sa;
+        *tuned = true;
+        break;
+    }
+    std::fclose(f);
+    return NB_OK;
 }
 
 // Step launch: explicit choice, else the persistent per-system launch for FP64
@@ -690,20 +766,30 @@ int resolve_step(nb_ctx *c, double dt)
 
 void drop_graph(nb_ctx *c)
 {
-    if (c->gexec) {
-        (void)hipGraphExecDestroy(c->gexec);
-        c->gexec = nullptr;
-    }
-    c->graph_steps = 0;
+    for (auto &g : c->graphs)
+        (void)hipGraphExecDestroy(g.exec);
+    c->graphs.clear();
 }
 
-int build_graph(nb_ctx *c, double dt, int steps)
+// The captured run of `steps` steps for this dt: from the cache, else captured
+// and instantiated now (a new dt drops the runs of the old one).
+int graph_for(nb_ctx *c, double dt, int steps, hipGraphExec_t *out)
 {
-    drop_graph(c);
+    if (!c->graphs.empty() && c->graph_dt != dt)
+        drop_graph(c);
+    for (auto &g : c->graphs)
+        if (g.steps == steps) {
+            *out = g.exec;
+            return NB_OK;
+        }
     hipGraph_t g = nullptr;
+    // capturing runs nothing: the set of drift outputs of the last step run
+    // stays what it was
+    const int snap = c->snap;
     HIP_OK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     int rc = enqueue_run(c, dt, steps);
     hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->snap = snap;
     if (rc != NB_OK) {
         if (g)
             (void)hipGraphDestroy(g);
@@ -711,15 +797,23 @@ int build_graph(nb_ctx *c, double dt, int steps)
     }
     if (e != hipSuccess)
         return set_err(c, NB_E_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
-    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
-    if (e != hipSuccess) {
-        c->gexec = nullptr;
+    if (e != hipSuccess)
         return set_err(c, NB_E_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    }
     c->graph_dt = dt;
-    c->graph_steps = steps;
+    c->graphs.push_back({steps, x});
+    *out = x;
     return NB_OK;
+}
+
+// How nb_step splits nsteps steps into captured runs: full runs of
+// kMaxGraphSteps, then one run of the remainder.
+void graph_lengths(int nsteps, int *full, int *rest)
+{
+    *full = nsteps / kMaxGraphSteps;
+    *rest = nsteps % kMaxGraphSteps;
 }
 
 // nsteps whole steps on the context's stream, by the context's step launch.
@@ -738,6 +832,7 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
             if ((r = enqueue_step_head(c, dt, true)) || (r = resolve_step(c, dt)) ||
                 (r = enqueue_step_tail(c, dt, true)))
                 return r;
+            c->snap_valid = true;
         }
         return NB_OK;
     }
@@ -752,27 +847,42 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
             HIP_OK(c, launch_step_stats(c->d, k, c->stream));
             done += k;
         }
-        if (nsteps > 0)
+        if (nsteps > 0) {
             HIP_OK(c, launch_enc_sort(c->d, 0, c->stream));
+            // the persistent launch keeps its drift outputs in registers and LDS
+            c->snap_valid = false;
+        }
         return NB_OK;
     }
     if (c->stream && nsteps > 0) {
-        int g = std::min(nsteps, kMaxGraphSteps);
-        if (!c->gexec || c->graph_dt != dt || c->graph_steps != g)
-            if ((r = build_graph(c, dt, g)))
+        // captured runs: full runs of kMaxGraphSteps, then the remainder
+        int full, rest;
+        graph_lengths(nsteps, &full, &rest);
+        hipGraphExec_t gx = nullptr;
+        if (full > 0 && (r = graph_for(c, dt, kMaxGraphSteps, &gx)))
+            return r;
+        for (int k = 0; k < full; ++k)
+            HIP_OK(c, hipGraphLaunch(gx, c->stream));
+        if (rest > 0) {
+            if ((r = graph_for(c, dt, rest, &gx)))
                 return r;
-        while (nsteps - done >= c->graph_steps) {
-            HIP_OK(c, hipGraphLaunch(c->gexec, c->stream));
-            done += c->graph_steps;
+            HIP_OK(c, hipGraphLaunch(gx, c->stream));
         }
+        // a run's steps write the two sets of drift outputs in turn, from set 0
+        c->snap = ((rest > 0 ? rest : kMaxGraphSteps) - 1) & 1;
+        c->snap_valid = true;
+        return NB_OK;
     }
-    // direct launches: runs of the graph's length, then the remainder
+    // no stream (the null stream cannot be captured): direct launches in runs
+    // of kMaxGraphSteps, then the remainder
     while (done < nsteps) {
         const int g = std::min(nsteps - done, kMaxGraphSteps);
         if ((r = enqueue_run(c, dt, g)))
             return r;
         done += g;
     }
+    if (nsteps > 0)
+        c->snap_valid = true;
     return NB_OK;
 }
 
@@ -892,6 +1002,11 @@ int nb_workspace_size(const nb_params *p, int nsys, const int32_t *off, const in
         (p->enc_algo == 3 && max_big(nsys, off, nbig) > kBlock))
         return NB_E_INVALID;
     Params q = to_internal(*p);
+    bool tuned = false;
+    if (apply_tuning(*p, nsys, off, nbig, q, &tuned, nullptr))
+        return NB_E_INVALID;
+    if (q.enc_algo == 3 && max_big(nsys, off, nbig) > kBlock)
+        q.enc_algo = 0;
     Tables t;
     build_tables(q, nsys, off, nbig, t);
     Dev d{};
@@ -913,6 +1028,15 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *n
         return NB_E_WORKSPACE;
     nb_ctx *c = new nb_ctx();
     c->p = to_internal(*p);
+    {
+        std::string why;
+        if (apply_tuning(*p, nsys, off, nbig, c->p, &c->tuned, &why)) {
+            delete c;
+            return NB_E_INVALID;
+        }
+        if (c->p.enc_algo == 3 && max_big(nsys, off, nbig) > kBlock)
+            c->p.enc_algo = 0;
+    }
     c->nsys = nsys;
     c->ntot = off[nsys];
     c->enc_cap = enc_cap;
@@ -1029,6 +1153,7 @@ int nb_upload(nb_ctx *c, const double *m0, const double *m, const double *x, con
         return r;
     c->have_state = true;
     c->have_drift = false;
+    c->snap_valid = false;
     c->mom_valid = false;
     c->have_enc = false;
     return NB_OK;
@@ -1113,6 +1238,7 @@ int nb_drift(nb_ctx *c, double dt, int *nfail)
     if (nfail)
         *nfail = nf;
     c->have_drift = true;
+    c->snap_valid = true;
     c->mom_valid = false;
     c->last_dt = dt;
     if (nf > 0)
@@ -1193,6 +1319,27 @@ int nb_step(nb_ctx *c, double dt, int nsteps, nb_stats *st)
     return NB_OK;
 }
 
+int nb_prepare(nb_ctx *c, double dt, int nsteps)
+{
+    int r = enter(c);
+    if (r)
+        return r;
+    if (!std::isfinite(dt) || nsteps < 0)
+        return set_err(c, NB_E_INVALID, "nb_prepare: bad argument");
+    // only captured runs are prepared: not without a stream, with the host
+    // resolver or with the persistent launch
+    if (!c->stream || c->p.resolve || c->p.step_algo == 2 || nsteps == 0)
+        return NB_OK;
+    int full, rest;
+    hipGraphExec_t gx;
+    graph_lengths(nsteps, &full, &rest);
+    if (full > 0 && (r = graph_for(c, dt, kMaxGraphSteps, &gx)))
+        return r;
+    if (rest > 0 && (r = graph_for(c, dt, rest, &gx)))
+        return r;
+    return NB_OK;
+}
+
 int nb_diagnostics(nb_ctx *c, double *E, double *EK, double *L, double *P)
 {
     int r = enter(c);
@@ -1266,8 +1413,10 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
         return set_err(c, NB_E_NOT_READY, "nb_time_kernel: no state");
     if (!ms || reps <= 0 || which < NB_K_FORCE || which > NB_K_FORCE_EVAL || !std::isfinite(dt))
         return set_err(c, NB_E_INVALID, "nb_time_kernel: bad argument");
-    if (which == NB_K_ENCOUNTER && !c->have_drift && !c->have_enc)
-        return set_err(c, NB_E_NOT_READY, "nb_time_kernel: no drift before the encounter check");
+    if (which == NB_K_ENCOUNTER && !c->snap_valid)
+        return set_err(c, NB_E_NOT_READY,
+                       "nb_time_kernel: no drift outputs for the encounter check (no drift or "
+                       "per-phase step since the upload, or the last steps ran persistent)");
     auto once = [&]() -> int {
         switch (which) {
         case NB_K_FORCE:
@@ -1281,13 +1430,23 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
         case NB_K_DRIFT:
             HIP_OK(c, launch_drift(c->d, c->p, dt, 0.0, c->d.rpart, c->stream));
             c->snap = 0;
+            c->snap_valid = true;
             return NB_OK;
         case NB_K_FORCE_EVAL:
             return enqueue_force(c);
         default:
-            // as many steps as the timed call replays per graph, so that the
-            // graph it launches is built here, outside the timed region
-            return enqueue_steps(c, dt, std::min(reps, kMaxGraphSteps));
+            // the runs the timed call replays, captured here, outside the timed
+            // region (one untimed step)
+            if (c->stream && !c->p.resolve && c->p.step_algo != 2) {
+                int full, rest, r2;
+                hipGraphExec_t gx;
+                graph_lengths(reps, &full, &rest);
+                if (full > 0 && (r2 = graph_for(c, dt, kMaxGraphSteps, &gx)))
+                    return r2;
+                if (rest > 0 && (r2 = graph_for(c, dt, rest, &gx)))
+                    return r2;
+            }
+            return enqueue_steps(c, dt, 1);
         }
     };
     if ((r = once()))
@@ -1318,9 +1477,16 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
     if (he != hipSuccess)
         return set_err(c, NB_E_HIP, "timing events: %s", hipGetErrorString(he));
     *ms = (double)t / reps;
-    if (which == NB_K_DRIFT || which == NB_K_STEP) {
+    if (which == NB_K_DRIFT) {
         c->mom_valid = false;
         c->have_drift = true;
+        c->last_dt = dt;
+    }
+    if (which == NB_K_STEP) {
+        // as after nb_step: the list of the last step can be read, and the
+        // encounter check can be timed on its drift outputs (per-phase steps)
+        c->have_drift = false;
+        c->have_enc = true;
         c->last_dt = dt;
     }
     return NB_OK;
@@ -1405,6 +1571,36 @@ int nb_get_choices(const nb_ctx *c, int32_t *force_algo, int32_t *enc_algo, int3
         *enc_algo = c->d.enc_sorted ? 2 : (c->d.enc_few ? 3 : 1);
     if (step_algo)
         *step_algo = c->p.step_algo;
+    return NB_OK;
+}
+
+int nb_get_params(const nb_ctx *c, nb_params *out, int32_t *tuned)
+{
+    if (!c || !out)
+        return NB_E_INVALID;
+    std::memset(out, 0, sizeof *out);
+    const Params &p = c->p;
+    out->G = p.G;
+    out->n_hill = p.n_hill;
+    out->chg_inner = p.inner;
+    out->mode = p.mode;
+    out->drag = p.drag;
+    out->drag_sigma0 = p.sigma0;
+    out->drag_h = p.h;
+    out->drag_cd = p.cd;
+    out->drag_rho_p = p.rho_p;
+    out->force_jchunk = p.force_j;
+    out->force_r = p.force_r;
+    out->enc_jchunk = p.enc_j;
+    out->enc_algo = p.enc_algo;
+    out->step_algo = p.step_algo;
+    out->resolve = p.resolve;
+    out->resolve_threads = p.resolve_threads;
+    out->force_algo = p.force_algo;
+    out->bs_tol = p.bs_tol;
+    out->autotune_path = nullptr;
+    if (tuned)
+        *tuned = c->tuned ? 1 : 0;
     return NB_OK;
 }
 

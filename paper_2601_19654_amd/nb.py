@@ -15,6 +15,8 @@ import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libnbody.so")
+# tile and algorithm choices per GPU, mode and size class (written by autotune.py)
+TUNING_TABLE = os.path.join(_PKG, "tuning.tsv")
 
 NB_OK = 0
 NB_E_INVALID = -1
@@ -47,7 +49,7 @@ class nb_params(ctypes.Structure):
         ("enc_jchunk", ctypes.c_int32), ("enc_algo", ctypes.c_int32),
         ("step_algo", ctypes.c_int32), ("resolve", ctypes.c_int32),
         ("resolve_threads", ctypes.c_int32), ("force_algo", ctypes.c_int32),
-        ("bs_tol", ctypes.c_double),
+        ("bs_tol", ctypes.c_double), ("autotune_path", ctypes.c_char_p),
     ]
 
 
@@ -94,12 +96,14 @@ SIGNATURES = {
     "nb_encounters": (_I, [_P, _I, _P, _P, _P, _P, _I]),
     "nb_get_encounters": (_I, [_P, _I, _P, _P, _P, _P, _I]),
     "nb_step": (_I, [_P, _D, _I, _P]),
+    "nb_prepare": (_I, [_P, _D, _I]),
     "nb_diagnostics": (_I, [_P, _P, _P, _P, _P]),
     "nb_get_accel": (_I, [_P, _P, _I]),
     "nb_get_rcrit": (_I, [_P, _P, _I]),
     "nb_time_kernel": (_I, [_P, _I, _I, _D, _P]),
     "nb_resolve_host": (_I, [_I, _D, _D, _D, _D, _D, _P, _P, _P, _P, _I, _P, _P, _P, _P, _P, _I, _P]),
     "nb_get_choices": (_I, [_P, _P, _P, _P]),
+    "nb_get_params": (_I, [_P, _P, _P]),
     "nb_destroy": (_I, [_P]),
 }
 
@@ -183,29 +187,18 @@ class Context:
         import torch
         self._torch = torch
         L = lib()
-        self.params = params or default_params()
+        # a copy: the caller's parameters are not modified
+        self.params = nb_params.from_buffer_copy(params) if params is not None else default_params()
         self.off = np.ascontiguousarray(off, dtype=np.int32)
         # per system: the first nbig[s] bodies are big (gravity sources); None = all
         self.nbig = None if nbig is None else np.ascontiguousarray(nbig, dtype=np.int32)
         nbig_p = None if self.nbig is None else _addr(self.nbig)
-        self.tiles = "library defaults"
-        if tuned and not (self.params.force_r or self.params.force_jchunk or self.params.enc_jchunk
-                          or self.params.enc_algo or self.params.step_algo or self.params.force_algo):
-            from . import autotune
-            try:
-                hit = autotune.lookup("fp32c" if self.params.mode == NB_FP32C else "fp64", self.off,
-                                      nbig=self.nbig)
-            except Exception:
-                hit = None
-            if hit:
-                self.params.force_algo = hit.get("force_algo", 0)
-                self.params.force_r = hit["force_r"]
-                self.params.force_jchunk = hit["force_jchunk"]
-                self.params.enc_jchunk = hit["enc_jchunk"]
-                self.params.enc_algo = hit.get("enc_algo", 0)
-                # the persistent launch cannot hand groups to the host resolver
-                self.params.step_algo = 0 if self.params.resolve else hit.get("step_algo", 0)
-                self.tiles = "tuned"
+        # tuned: the library takes the tile and algorithm fields left at 0 from
+        # the package's tuning table for this GPU, mode and size class
+        self._tuning_path = None
+        if tuned and not self.params.autotune_path and os.path.exists(TUNING_TABLE):
+            self._tuning_path = TUNING_TABLE.encode()
+            self.params.autotune_path = self._tuning_path
         self.nsys = len(self.off) - 1
         self.ntot = int(self.off[-1])
         self.enc_cap = int(enc_cap)
@@ -221,6 +214,11 @@ class Context:
                                     _addr(self.workspace), nbytes.value,
                                     ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.ctx)),
                         "nb_create")
+        # the parameters the library runs with (tuned or default tiles)
+        eff, tun = nb_params(), ctypes.c_int32()
+        self._check(L.nb_get_params(self.ctx, ctypes.byref(eff), ctypes.byref(tun)), "nb_get_params")
+        self.params = eff
+        self.tiles = "tuned" if tun.value else "library defaults"
 
     def _check(self, code, what, allow=()):
         if code != NB_OK and code not in allow:
@@ -293,6 +291,10 @@ class Context:
         self._check(lib().nb_step(self.ctx, float(dt), int(nsteps), ctypes.byref(st)), "nb_step",
                     allow=allow)
         return {k: getattr(st, k) for k, _ in nb_stats._fields_}
+
+    def prepare(self, dt, nsteps):
+        """Capture the HIP graphs a step(dt, nsteps) call replays, running nothing."""
+        self._check(lib().nb_prepare(self.ctx, float(dt), int(nsteps)), "nb_prepare")
 
     def step_async(self, dt, nsteps=1):
         """nb_step without the statistics argument (still synchronizes at the end)."""

@@ -35,7 +35,7 @@ def test_every_declared_symbol_is_exported(nb):
 
 
 def test_version_status_defaults(nb):
-    assert nb.version() == (0, 1)
+    assert nb.version() == (0, 2)
     assert nb.strerror(nb.NB_E_CAPACITY).startswith("encounter")
     p = nb.default_params()
     assert abs(p.G - (0.01720209895 * 365.25) ** 2) < 1e-14
@@ -97,3 +97,43 @@ def test_create_rejects_bad_workspace(nb):
     rc = nb.lib().nb_create(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.c_void_p), None, 16,
                             ctypes.c_void_p(0x1001), 1 << 20, None, ctypes.byref(ctx))
     assert rc == nb.NB_E_WORKSPACE
+
+
+def test_tuning_table_read_by_the_library(nb, tmp_path):
+    """nb_params.autotune_path: the library itself applies the table's entry for
+    the GPU, mode and size class when the tile fields are 0 (on this host there
+    is no GPU, so the class's architecture is 'unknown')."""
+    off = [0, 1000]
+    t = tmp_path / "tuning.tsv"
+    t.write_text("# key force_algo force_r force_jchunk enc_algo enc_jchunk step_algo\n"
+                 "unknown/fp64/n1024/s1 1 4 256 1 512 1\n"
+                 "unknown/fp32c/n1024/s1 2 1 1024 2 1024 1\n")
+    path = str(t).encode()
+    rc, tuned = _wsize(nb, off, autotune_path=path)
+    rc2, explicit = _wsize(nb, off, force_algo=1, force_r=4, force_jchunk=256, enc_algo=1, enc_jchunk=512,
+                           step_algo=1)
+    rc3, default = _wsize(nb, off)
+    assert rc == rc2 == rc3 == 0
+    assert tuned == explicit != default
+    rc, tuned32 = _wsize(nb, off, mode=nb.NB_FP32C, autotune_path=path)
+    rc2, explicit32 = _wsize(nb, off, mode=nb.NB_FP32C, force_algo=2, force_r=1, enc_algo=2)
+    assert rc == rc2 == 0 and tuned32 == explicit32
+    # a class the table lacks keeps the defaults; an explicit field turns the table off
+    assert _wsize(nb, [0, 3000], autotune_path=path)[1] == _wsize(nb, [0, 3000])[1]
+    assert _wsize(nb, off, force_r=2, autotune_path=path)[1] == _wsize(nb, off, force_r=2)[1]
+    # an unreadable table is an error
+    assert _wsize(nb, off, autotune_path=str(tmp_path / "missing.tsv").encode())[0] == nb.NB_E_INVALID
+
+
+def test_package_tuning_table_matches_the_autotuner_cache():
+    from paper_2601_19654_amd import autotune
+    cache = autotune.load_cache()
+    rows = {}
+    for line in open(autotune.TABLE):
+        if line.startswith("#"):
+            continue
+        k, *vals = line.split()
+        rows[k] = [int(v) for v in vals]
+    assert set(rows) == set(cache)
+    for k, vals in rows.items():
+        assert vals == [int(cache[k][f]) for f in autotune.TABLE_FIELDS], k

@@ -45,7 +45,7 @@ def test_force(case, mode):
     name, w, (Q, V, rc, a_ref) = case
     c = ctx_for(w, mode=mode)
     a = c.accel()
-    bar = 1e-12 if mode == 0 else 4e-6
+    bar = 1e-12 if mode == 0 else 1e-6
     for s, lo, hi in systems(w):
         if nbig_of(w, s) == 0 or hi - lo < 2:
             assert np.all(a[lo:hi] == 0.0), (name, s)

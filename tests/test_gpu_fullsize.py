@@ -43,7 +43,7 @@ def c3():
     return w, Q, V, rc
 
 
-@pytest.mark.parametrize("mode,tol", [(0, 1e-12), (1, 4e-6)])
+@pytest.mark.parametrize("mode,tol", [(0, 1e-12), (1, 1e-6)])
 def test_c3_force_sampled(c3, mode, tol):
     w, Q, V, rc = c3
     c = ctx_for(w, mode=mode)
@@ -84,7 +84,7 @@ def test_c5_max_size():
     w = workloads.c5()
     Q, V = oracle.helio_to_dh(w.m0[0], w.m, w.x, w.v)
     rc = oracle.rcrit(w.m0[0], w.m, Q)
-    for mode, tol in ((1, 4e-6), (0, 1e-12)):
+    for mode, tol in ((1, 1e-6), (0, 1e-12)):
         c = ctx_for(w, mode=mode, enc_cap=1 << 18)
         a = c.accel()
         idx = _sample(w.ntot, 12, 21, _near_targets(Q, rc, 4))
@@ -150,7 +150,7 @@ def test_ring_600k_sorted_encounters_multi_block_scan():
         assert not ((want ^ have) - tie), i
 
 
-@pytest.mark.parametrize("mode,tol", [(0, 1e-12), (1, 4e-6)])
+@pytest.mark.parametrize("mode,tol", [(0, 1e-12), (1, 1e-6)])
 @pytest.mark.parametrize("r", [1, 2])
 def test_few_source_force(mode, tol, r):
     """50 big bodies and 140 000 massless ones: enough target tiles for the
