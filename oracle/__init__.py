@@ -24,6 +24,11 @@ Parity status per function (pins live in ``tests/test_oracle_*.py``):
   (Bulirsch-Stoer on H0)     orbit of a bound pair, H0 energy, time reversal;
                              the full step converges at second order to an
                              independent Newtonian integration)
+  collisions, star impacts,  pinned (sphere mass, pericentre distance of the
+  ejections, compaction      generating elements and dense arc sampling, mass,
+                             momentum and barycentre conservation, unchanged
+                             heliocentric motion of the rest, order kept)
+  sampled force / pair scan  pinned (bit-equal to the full routines' rows)
   gas drag                   parity unpinned by the paper (limits and closed form
                              of the chosen formula only)
 """
@@ -109,6 +114,10 @@ def _load(path):
         "orc_resolve": (i, [i, d, d, d, p, p, d, d, p, p, i, p, p, p, p, p, p, p, p]),
         "orc_step_full": (i, [i, i, d, d, d, d, p, p, p, p, p, d, i, d, d, d, d, d, p, p, p, p, i, p,
                               p, p, p, p, p, p, p]),
+        "orc_phys_radius": (None, [i, p, d, p]),
+        "orc_star_min": (d, [d, d, p, p, p, p]),
+        "orc_events": (None, [i, d, p, p, p, p, p, p, p, p, d, i, p, p, d, d, d, p, p]),
+        "orc_compact": (i, [i, p, p, p, p, p, p, p, p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -313,6 +322,48 @@ def resolve(G, m0, m, rc, tau, Q0, V0, ice, jce, Q, V, tol=1e-12, inner=0.1):
     return Q, V, comp[:n].copy(), nf, ng.value, ms.value
 
 
+def phys_radius(m, rho):
+    """Physical radii from mass and one bulk density."""
+    m = _f64(m); R = np.empty(len(m))
+    lib().orc_phys_radius(len(m), _ptr(m), float(rho), _ptr(R))
+    return R
+
+
+def star_min(mu, tau, q0, v0, q1, v1):
+    """Closest approach to the star along one drift arc of duration tau."""
+    a = [_f64(t, (3,)) for t in (q0, v0, q1, v1)]
+    return lib().orc_star_min(float(mu), float(tau), *[_ptr(t) for t in a])
+
+
+LOST_STAR, LOST_MERGED, LOST_EJECTED = 1, 2, 3
+
+
+def events(G, m0, m, Q, V, Q0, V0, Q1, V1, tau, ice, jce, rho, r_star, r_eject=0.0):
+    """Star impacts, collisions and ejections of one step of one system (local
+    pair indices).  Returns (m0, m, Q, V, lost, counts) with counts = (star
+    impacts, colliding pairs, bodies merged away, ejections)."""
+    m = _f64(m).copy(); Q = _f64(Q, (-1, 3)).copy(); V = _f64(V, (-1, 3)).copy()
+    Q0, V0, Q1, V1 = (_f64(t, (-1, 3)) for t in (Q0, V0, Q1, V1))
+    ice = np.ascontiguousarray(ice, dtype=np.int32); jce = np.ascontiguousarray(jce, dtype=np.int32)
+    n = len(m)
+    mm0 = ctypes.c_double(float(m0))
+    lost = np.zeros(max(n, 1), np.int32); ev = np.zeros(4, np.int32)
+    lib().orc_events(n, float(G), ctypes.byref(mm0), _ptr(m), _ptr(Q), _ptr(V), _ptr(Q0), _ptr(V0), _ptr(Q1),
+                     _ptr(V1), float(tau), len(ice), _ptr(ice), _ptr(jce), float(rho), float(r_star),
+                     float(r_eject), _ptr(lost), _ptr(ev))
+    return mm0.value, m, Q, V, lost[:n].copy(), tuple(int(e) for e in ev)
+
+
+def compact(lost, m, Q, V):
+    """The kept bodies (lost == 0) in order, and their old indices."""
+    lost = np.ascontiguousarray(lost, dtype=np.int32); m = _f64(m)
+    Q = _f64(Q, (-1, 3)); V = _f64(V, (-1, 3)); n = len(m)
+    mo = np.empty(max(n, 1)); Qo = np.empty((max(n, 1), 3)); Vo = np.empty((max(n, 1), 3))
+    idx = np.empty(max(n, 1), np.int32)
+    k = lib().orc_compact(n, _ptr(lost), _ptr(m), _ptr(Q), _ptr(V), _ptr(mo), _ptr(Qo), _ptr(Vo), _ptr(idx))
+    return mo[:k].copy(), Qo[:k].copy(), Vo[:k].copy(), idx[:k].copy()
+
+
 # ---------------------------------------------------------------- multi-system driver
 class State:
     """Oracle state of a batch of independent systems in DH coordinates.
@@ -417,6 +468,43 @@ class State:
             k = min(nce.value, c)
             self.enc.append((nce.value, ice[:k] + a, jce[:k] + a))
         return nfail
+
+    def events(self, tau, rho, r_star, r_eject=0.0):
+        """Star impacts, collisions and ejections after the last step (its
+        drift arcs and flagged pairs), applied to every system in place
+        (Sec. 2.1.1-2.1.2).  Sets self.lost (per body) and returns the summed
+        counts (star impacts, colliding pairs, bodies merged away, ejections)."""
+        self.lost = np.zeros(len(self.m), np.int32)
+        tot = np.zeros(4, np.int64)
+        for s, (a, b) in enumerate(self.systems()):
+            if b == a:
+                continue
+            # the step's drift arc, recomputed by the same routine from its start
+            q1, v1, _ = drift(self.prm.G * self.m0[s], tau, self.Q0[a:b], self.V0[a:b])
+            nce, ii, jj = self.enc[s]
+            m0, m, Q, V, lost, ev = events(self.prm.G, self.m0[s], self.m[a:b], self.Q[a:b], self.V[a:b],
+                                           self.Q0[a:b], self.V0[a:b], q1, v1, tau, ii - a, jj - a, rho,
+                                           r_star, r_eject)
+            self.m0[s] = m0; self.m[a:b] = m; self.Q[a:b] = Q; self.V[a:b] = V; self.lost[a:b] = lost
+            tot += ev
+        return tuple(int(t) for t in tot)
+
+    def compacted(self):
+        """A new state without the lost bodies (mxx_elim), its critical radii
+        and force computed again (mce_init).  Returns (state, old index of every
+        kept body)."""
+        off = [0]
+        ms, Qs, Vs, idx, nbig = [], [], [], [], []
+        for s, (a, b) in enumerate(self.systems()):
+            mk, Qk, Vk, ik = compact(self.lost[a:b], self.m[a:b], self.Q[a:b], self.V[a:b])
+            ms.append(mk); Qs.append(Qk); Vs.append(Vk); idx.append(ik + a)
+            off.append(off[-1] + len(mk))
+            # big bodies stay first: the kept ones among the first nbig
+            nbig.append(int(np.sum(ik < self.nbig[s])))
+        cat = lambda xs, shape: np.concatenate(xs) if xs else np.zeros(shape)  # noqa: E731
+        st = State(np.array(off), self.m0, cat(ms, 0), cat(Qs, (0, 3)), cat(Vs, (0, 3)), self.prm, frame="dh",
+                   nbig=nbig, threads=self.threads)
+        return st, cat(idx, 0).astype(np.int64)
 
     def energy(self):
         p = self.prm

@@ -981,3 +981,229 @@ int orc_step_full(int n, int nbig, double G, double m0, double n_hill, double in
         orc_kick(n, h, a, V);
     return nfail + *bsfail;
 }
+
+/* ------------------------------------------------------------------ */
+/* Collisions, star impacts, ejections and the removal of lost bodies    */
+/* (Sec. 2.1.1: physical radii from mce_init, mxx_elim; Sec. 2.1.2:      */
+/* mce_coll for planet-planet and planet-star collisions, ejections      */
+/* checked every 200 yr for bodies beyond 400 AU).  The paper names the  */
+/* events and their schedule, not their arithmetic; the readings used:    */
+/*  - physical radius R = (3 m/(4 pi rho))^(1/3), one bulk density rho;    */
+/*  - star impact: the body's Kepler arc of the step's drift comes within  */
+/*    r_star of the star; the impactors' mass joins the star, whose        */
+/*    centre moves to the centre of mass of star and impactors (so every   */
+/*    other heliocentric position shifts by minus that displacement);      */
+/*  - collision: a flagged pair of the step whose minimum separation over  */
+/*    the step (the encounter predicate's Hermite minimum) is at most      */
+/*    R_i + R_j; bodies joined by colliding pairs merge perfectly into the */
+/*    smallest index: summed mass, mass-weighted position and velocity;    */
+/*  - ejection: heliocentric distance beyond r_eject; the body leaves, and */
+/*    the barycentric velocities of the rest follow the new barycentre.    */
+/* ------------------------------------------------------------------ */
+void orc_phys_radius(int n, const double *m, double rho, double *R)
+{
+    const double pi = 3.14159265358979323846;
+    for (int i = 0; i < n; ++i)
+        R[i] = cbrt(3.0 * m[i] / (4.0 * pi * rho));
+}
+
+/* Closest approach to the star along the Kepler arc of duration tau from
+ * (q0, v0) to (q1, v1) (mu = G m0): the smaller end distance, or the
+ * pericentre distance q = h^2 / (mu (1 + e)) when the arc passes a pericentre.
+ * Bound orbits: the arc covers the mean anomalies from M0 to M0 + n tau, and a
+ * pericentre lies at every multiple of 2 pi; unbound orbits have one
+ * pericentre, where the radial velocity turns from inward to outward. */
+double orc_star_min(double mu, double tau, const double *q0, const double *v0, const double *q1,
+                    const double *v1)
+{
+    const double pi = 3.14159265358979323846;
+    double r0 = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2]);
+    double r1 = sqrt(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2]);
+    double rmin = r0 < r1 ? r0 : r1;
+    double eta0 = q0[0] * v0[0] + q0[1] * v0[1] + q0[2] * v0[2];
+    double eta1 = q1[0] * v1[0] + q1[1] * v1[1] + q1[2] * v1[2];
+    double hx = q0[1] * v0[2] - q0[2] * v0[1];
+    double hy = q0[2] * v0[0] - q0[0] * v0[2];
+    double hz = q0[0] * v0[1] - q0[1] * v0[0];
+    double h2 = hx * hx + hy * hy + hz * hz;
+    double v2 = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
+    double alpha = 2.0 / r0 - v2 / mu;                  /* 1/a */
+    double ecosE = 1.0 - r0 * alpha;
+    double e2 = 1.0 - h2 * alpha / mu;
+    double e = sqrt(e2 > 0.0 ? e2 : 0.0);
+    int passed;
+    if (alpha > 0.0) {
+        /* eccentric anomaly E0 and mean anomaly M0 = E0 - e sin E0 at the start */
+        double esinE = eta0 * sqrt(alpha / mu);
+        double E0 = atan2(esinE, ecosE);
+        double M0 = E0 - esinE;
+        double M1 = M0 + sqrt(mu * alpha * alpha * alpha) * tau;
+        double lo = M0 < M1 ? M0 : M1, hi = M0 < M1 ? M1 : M0;
+        /* a multiple of 2 pi in [lo, hi] */
+        passed = floor(hi / (2.0 * pi)) * (2.0 * pi) >= lo;
+    } else {
+        passed = tau >= 0.0 ? (eta0 < 0.0 && eta1 >= 0.0) : (eta1 < 0.0 && eta0 >= 0.0);
+    }
+    if (passed) {
+        double q = h2 / (mu * (1.0 + e));
+        if (q < rmin)
+            rmin = q;
+    }
+    return rmin;
+}
+
+/* The events of one step of one system, applied in this order: star impacts,
+ * collisions (among the step's flagged pairs ice/jce, i < j, of bodies not
+ * lost to the star), ejections (r_eject > 0).  (Q0,V0), (Q1,V1): the step's
+ * drift arcs; Q, V: the state at the end of the step (changed in place), m and
+ * *m0 likewise.  lost[i] = 0 kept, 1 star impact, 2 merged into another body,
+ * 3 ejected; lost bodies get m = 0.  Counts in ev[4]: star impacts, colliding
+ * pairs, bodies merged away, ejections. */
+void orc_events(int n, double G, double *m0, double *m, double *Q, double *V, const double *Q0,
+                const double *V0, const double *Q1, const double *V1, double tau, int nce,
+                const int32_t *ice, const int32_t *jce, double rho, double r_star, double r_eject,
+                int32_t *lost, int32_t *ev)
+{
+    for (int k = 0; k < 4; ++k)
+        ev[k] = 0;
+    for (int i = 0; i < n; ++i)
+        lost[i] = 0;
+    /* 1. star impacts: all of one step's impactors join the star together */
+    nsum ms = {0, 0}, sx = {0, 0}, sy = {0, 0}, sz = {0, 0};
+    for (int i = 0; i < n; ++i) {
+        if (orc_star_min(G * *m0, tau, Q0 + 3 * i, V0 + 3 * i, Q1 + 3 * i, V1 + 3 * i) <= r_star) {
+            lost[i] = 1;
+            ++ev[0];
+            ns_add(&ms, m[i]);
+            ns_add(&sx, m[i] * Q[3 * i]);
+            ns_add(&sy, m[i] * Q[3 * i + 1]);
+            ns_add(&sz, m[i] * Q[3 * i + 2]);
+        }
+    }
+    if (ev[0] > 0) {
+        double mnew = *m0 + ns_val(&ms);
+        double s[3] = {ns_val(&sx) / mnew, ns_val(&sy) / mnew, ns_val(&sz) / mnew};
+        for (int i = 0; i < n; ++i) {
+            if (lost[i]) {
+                m[i] = 0.0;
+                continue;
+            }
+            for (int c = 0; c < 3; ++c)
+                Q[3 * i + c] -= s[c];
+        }
+        *m0 = mnew;
+    }
+    /* 2. collisions: connected components of the colliding pairs merge into
+     * their smallest member */
+    int32_t *parent = (int32_t *)malloc(sizeof(int32_t) * (n > 0 ? n : 1));
+    double *R = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+    orc_phys_radius(n, m, rho, R);
+    for (int i = 0; i < n; ++i)
+        parent[i] = i;
+    for (int p = 0; p < nce; ++p) {
+        int i = ice[p], j = jce[p];
+        if (lost[i] || lost[j])
+            continue;
+        double d2 = orc_pair_min_d2(tau, Q0 + 3 * i, V0 + 3 * i, Q1 + 3 * i, V1 + 3 * i,
+                                    Q0 + 3 * j, V0 + 3 * j, Q1 + 3 * j, V1 + 3 * j);
+        double rr = R[i] + R[j];
+        if (d2 <= rr * rr) {
+            ++ev[1];
+            int a = find_root(parent, i), b = find_root(parent, j);
+            if (a != b) {
+                if (a < b)
+                    parent[b] = a;
+                else
+                    parent[a] = b;
+            }
+        }
+    }
+    for (int root = 0; root < n; ++root) {
+        if (lost[root] || find_root(parent, root) != root)
+            continue;
+        int members = 0;
+        nsum mm = {0, 0}, px = {0, 0}, py = {0, 0}, pz = {0, 0}, vx = {0, 0}, vy = {0, 0},
+             vz = {0, 0};
+        for (int i = root; i < n; ++i) {
+            if (lost[i] || find_root(parent, i) != root)
+                continue;
+            ++members;
+            ns_add(&mm, m[i]);
+            ns_add(&px, m[i] * Q[3 * i]);
+            ns_add(&py, m[i] * Q[3 * i + 1]);
+            ns_add(&pz, m[i] * Q[3 * i + 2]);
+            ns_add(&vx, m[i] * V[3 * i]);
+            ns_add(&vy, m[i] * V[3 * i + 1]);
+            ns_add(&vz, m[i] * V[3 * i + 2]);
+        }
+        if (members < 2)
+            continue;
+        double M = ns_val(&mm);
+        if (M > 0.0) {
+            Q[3 * root] = ns_val(&px) / M;
+            Q[3 * root + 1] = ns_val(&py) / M;
+            Q[3 * root + 2] = ns_val(&pz) / M;
+            V[3 * root] = ns_val(&vx) / M;
+            V[3 * root + 1] = ns_val(&vy) / M;
+            V[3 * root + 2] = ns_val(&vz) / M;
+        }
+        m[root] = M;
+        for (int i = root + 1; i < n; ++i)
+            if (!lost[i] && find_root(parent, i) == root) {
+                lost[i] = 2;
+                m[i] = 0.0;
+                ++ev[2];
+            }
+    }
+    free(parent);
+    free(R);
+    /* 3. ejections: the ejected bodies' momentum leaves with them */
+    if (r_eject > 0.0) {
+        nsum mt = {0, 0}, me = {0, 0}, ex = {0, 0}, ey = {0, 0}, ez = {0, 0};
+        ns_add(&mt, *m0);
+        for (int i = 0; i < n; ++i) {
+            if (lost[i])
+                continue;
+            ns_add(&mt, m[i]);
+            double r = sqrt(Q[3 * i] * Q[3 * i] + Q[3 * i + 1] * Q[3 * i + 1] +
+                            Q[3 * i + 2] * Q[3 * i + 2]);
+            if (r > r_eject) {
+                lost[i] = 3;
+                ++ev[3];
+                ns_add(&me, m[i]);
+                ns_add(&ex, m[i] * V[3 * i]);
+                ns_add(&ey, m[i] * V[3 * i + 1]);
+                ns_add(&ez, m[i] * V[3 * i + 2]);
+            }
+        }
+        if (ev[3] > 0) {
+            double rest = ns_val(&mt) - ns_val(&me);
+            double dv[3] = {ns_val(&ex) / rest, ns_val(&ey) / rest, ns_val(&ez) / rest};
+            for (int i = 0; i < n; ++i) {
+                if (lost[i] == 3)
+                    m[i] = 0.0;
+                else if (!lost[i])
+                    for (int c = 0; c < 3; ++c)
+                        V[3 * i + c] += dv[c];
+            }
+        }
+    }
+}
+
+/* Removal of lost bodies (mxx_elim): the kept bodies in their order; index[k]
+ * is the old index of kept body k.  Returns the number kept. */
+int orc_compact(int n, const int32_t *lost, const double *m, const double *Q, const double *V,
+                double *m_out, double *Q_out, double *V_out, int32_t *index)
+{
+    int k = 0;
+    for (int i = 0; i < n; ++i) {
+        if (lost[i])
+            continue;
+        m_out[k] = m[i];
+        memcpy(Q_out + 3 * k, Q + 3 * i, 3 * sizeof(double));
+        memcpy(V_out + 3 * k, V + 3 * i, 3 * sizeof(double));
+        index[k] = i;
+        ++k;
+    }
+    return k;
+}

@@ -35,6 +35,13 @@ int orc_step_full(int n, int nbig, double G, double m0, double n_hill, double in
                   int32_t *kflag, double *scratch, int cap, int32_t *ice, int32_t *jce, int32_t *ce,
                   int *nce, int32_t *comp, double *work, int *bsfail, int *ngroups);
 
+void orc_events(int n, double G, double *m0, double *m, double *Q, double *V, const double *Q0,
+                const double *V0, const double *Q1, const double *V1, double tau, int nce,
+                const int32_t *ice, const int32_t *jce, double rho, double r_star, double r_eject,
+                int32_t *lost, int32_t *ev);
+int orc_compact(int n, const int32_t *lost, const double *m, const double *Q, const double *V,
+                double *m_out, double *Q_out, double *V_out, int32_t *index);
+
 static uint64_t lcg = 12345;
 static double unif(void)
 {
@@ -100,6 +107,21 @@ static int run(int n, int nbig, int cap, int drag, int full)
     orc_pair_scan(nn, nbig < nn ? nbig : nn, tau, Q0, V0, Q1, V1, rc, nn - 1, 1e-6, fl, tf);
     double E, EK, L[3], P[3];
     orc_energy(n, G, m0, 0.1, m, Q, V, rc, &E, &EK, L, P);
+    /* collisions among the listed pairs (a low density: large bodies), star
+     * impacts and ejections, then the compaction */
+    {
+        int32_t ev[4], *lost = malloc(sizeof(int32_t) * nn);
+        double mm0 = m0, *mo = malloc(sizeof(double) * nn), *Qo = malloc(sizeof(double) * 3 * nn);
+        double *Vo = malloc(sizeof(double) * 3 * nn);
+        int32_t *io = malloc(sizeof(int32_t) * nn);
+        int k = nce < cap ? nce : cap;
+        orc_events(nn, G, &mm0, m, Q1, V1, Q0, V0, Q1, V1, tau, k, ice, jce, 0.1, 0.999, 1.005,
+                   lost, ev);
+        int kept = orc_compact(nn, lost, m, Q1, V1, mo, Qo, Vo, io);
+        printf("events: star %d, colliding pairs %d, merged %d, ejected %d, kept %d\n", ev[0],
+               ev[1], ev[2], ev[3], kept);
+        free(lost); free(mo); free(Qo); free(Vo); free(io);
+    }
     printf("n=%d nbig=%d cap=%d drag=%d full=%d: %d flagged, E=%.6e\n", n, nbig, cap, drag, full,
            total, E);
     free(m); free(Q); free(V); free(a); free(rc); free(Q0); free(V0); free(sc); free(kf);
