@@ -257,6 +257,62 @@ int nb_resolve_host(int n, double G, double m0, double chg_inner, double tol, do
                     int nce, const int32_t *ice, const int32_t *jce, double *Q, double *V,
                     int32_t *group, int nthreads, nb_resolve_info *info);
 
+/* Collisions, star impacts and ejections after a step (Sec. 2.1.1: physical
+ * radii, removal of lost bodies; Sec. 2.1.2: planet-planet and planet-star
+ * collisions, ejections of distant bodies, checked by the paper every 200 yr
+ * beyond 400 AU).  The paper gives no arithmetic for them; the readings:
+ *  - physical radius R = (3 m/(4 pi rho))^(1/3) from one bulk density rho;
+ *  - star impact (r_star > 0): the Kepler arc of the last drift comes within
+ *    r_star of the star (the nearer end, or the pericentre distance when the
+ *    arc passes a pericentre); the impactors' mass joins m0 and the star moves
+ *    to the centre of mass of star and impactors, so every other body's
+ *    heliocentric position shifts by minus that displacement;
+ *  - collision: a listed pair of the last encounter check, neither member lost
+ *    to the star, whose minimum separation over the step (the encounter
+ *    predicate's Hermite minimum) is at most R_i + R_j; bodies joined by
+ *    colliding pairs merge into their smallest index: summed mass,
+ *    mass-weighted position and velocity;
+ *  - ejection (r_eject > 0): a body farther than r_eject from the star leaves
+ *    with its momentum; the barycentric velocities of the rest change by
+ *    sum m_e V_e / (m0 + sum m - sum m_e).
+ * Applied in that order to the state after the last step (nb_step, or nb_drift
+ * followed by nb_encounters); NB_E_NOT_READY otherwise (also after the
+ * persistent step launch, which keeps no drift arcs).  Lost bodies keep their
+ * slot with m = 0 until nb_compact; lost[ntot] (may be NULL; host or device per
+ * `where`) receives 0 kept, 1 star impact, 2 merged away, 3 ejected.  When a
+ * body was lost the critical radii and the force are computed again.
+ * NB_E_CAPACITY if the list had overflowed (only the kept pairs are tested).
+ * Collisions are tested by one workgroup, quadratic in the members of colliding
+ * pairs: meant for a few per call. */
+typedef struct nb_event_params {
+    double rho;      /* bulk density of the bodies (mass / length^3), > 0 */
+    double r_star;   /* star radius (0: no star impacts) */
+    double r_eject;  /* ejection distance from the star (0: no ejections) */
+} nb_event_params;
+
+typedef struct nb_event_counts {
+    int32_t star;     /* bodies that fell into their star */
+    int32_t collide;  /* colliding pairs */
+    int32_t merged;   /* bodies merged into another one */
+    int32_t ejected;  /* bodies ejected */
+} nb_event_counts;
+
+int nb_events(nb_ctx *ctx, const nb_event_params *ep, nb_event_counts *counts, int32_t *lost,
+              int where);
+
+/* Remove the bodies nb_events marked lost (the paper's removal of lost bodies,
+ * Sec. 2.1.1), keeping the order of the rest in every system, and continue with
+ * the smaller arrays in the same workspace: the work tables are rebuilt for the
+ * new offsets, the critical radii and the force computed again (a new upload of
+ * the kept state).  The kept bodies among a system's first nbig stay its big
+ * bodies.  Outputs (host or device per `where`, each may be NULL): off_out[nsys+1]
+ * the new offsets, nbig_out[nsys] the new big-body counts, index[new ntot] the
+ * old index of every kept body.  NB_E_NOT_READY without nb_events on the current
+ * state; NB_E_WORKSPACE if the new layout needs more workspace than the context
+ * has (possible only when an automatic algorithm choice changes with the sizes):
+ * the context is then left as it was. */
+int nb_compact(nb_ctx *ctx, int32_t *off_out, int32_t *nbig_out, int32_t *index, int where);
+
 /* Per system s (host arrays): E[s] total energy, EK[s] the changeover-weighted
  * energy the hot path conserves, L[3s..3s+2] = sum m Q x V, P[3s..3s+2] = sum m V.
  * Any pointer may be NULL.  Returns NB_E_NONFINITE if a value is not finite. */

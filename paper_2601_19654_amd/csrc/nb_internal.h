@@ -145,7 +145,17 @@ struct Dev {
     PSys *psys; int npsys; int pmax_n;
     int *step_nce; int step_chunk;   // flagged pairs per step of one launch
     int *flag;            // validation flags (4 ints)
-    double *stage;        // 6 x ntot staging for host transfers / transforms
+    double *stage;        // 7 x ntot staging for host transfers, transforms and the compaction
+    // collisions, star impacts, ejections and compaction
+    int *lost;            // ntot: 0 kept, 1 star impact, 2 merged away, 3 ejected
+    int *evroot;          // ntot: union-find parents of colliding bodies
+    int *evflag;          // max(enc_cap, nrb): colliding-pair flags, then kept counts per block
+    int *evmem;           // 2 enc_cap: members of colliding pairs
+    int *evcnt;           // 4: star impacts, colliding pairs, bodies merged away, ejections
+    int *cmp_pos;         // nrb + 1: first kept slot of every block, then the kept total
+    int *evidx;           // ntot: old index of every kept body
+    double *evpart;       // nrb x 8 per-block event sums
+    double *evsys;        // nsys x 8 per-system shift (star impact) or dv (ejection), count
     // close-encounter resolver (resolve = 1): records of both ends of up to res_cap
     // listed pairs (20 doubles per pair) and result rows (7 doubles per member)
     double *res_buf; double *res_rows; int res_cap;
@@ -213,6 +223,12 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, i
                                  hipStream_t s);
 hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s);
 hipError_t launch_diagnostics(const Dev &d, const Params &p, hipStream_t s);
+// star impacts, collisions among the listed pairs, ejections (r_eject > 0) of
+// the last step (drift arcs of d.snap(), the sorted list), applied in place
+hipError_t launch_events(const Dev &d, const Params &p, double tau, double rho, double r_star,
+                         double r_eject, hipStream_t s);
+// kept bodies (lost == 0) in order: out = 7 planes of ntot (m, Q, V), idx = old index
+hipError_t launch_compact(const Dev &d, double *out, int *idx, hipStream_t s);
 hipError_t launch_persistent_steps(const Dev &d, const Params &p, double dt, int nsteps,
                                    hipStream_t s);
 hipError_t launch_step_stats(const Dev &d, int nsteps, hipStream_t s);

@@ -3539,6 +3539,450 @@ hipError_t launch_step_stats(const Dev &d, int nsteps, hipStream_t s)
     return hipGetLastError();
 }
 
+// ----------------------------------------------------------------------------
+// Collisions, star impacts, ejections and the removal of lost bodies (Sec.
+// 2.1.1: physical radii, removal of lost bodies from the arrays; Sec. 2.1.2:
+// planet-planet and planet-star collisions, ejections of bodies far from the
+// star).  The paper gives the events and their schedule, not their arithmetic;
+// the readings: physical radius R = (3 m/(4 pi rho))^(1/3); a star impact when
+// the step's Kepler arc comes within r_star of the star (its mass joins the
+// star, whose centre moves to the centre of mass of star and impactors); a
+// collision when a flagged pair's minimum separation over the step (the
+// encounter predicate's Hermite minimum) is at most R_i + R_j, bodies joined
+// by colliding pairs merging perfectly into the smallest index; an ejection
+// beyond r_eject, the body leaving with its momentum.  Applied in that order,
+// on the state at the end of the step.  Lost bodies keep their slot with
+// m = 0 and a nonzero flag until the compaction.
+// ----------------------------------------------------------------------------
+// Closest approach to the star along the Kepler arc of duration tau from
+// (q0, v0) to (q1, v1), mu = G m0: the nearer end, or the pericentre distance
+// h^2/(mu (1 + e)) when the arc passes a pericentre (bound orbits: a multiple
+// of 2 pi between the mean anomalies at the ends; unbound orbits: the radial
+// velocity changes sign from inward to outward along the direction of time).
+__device__ double star_min_dist(double mu, double tau, const double (&q0)[3], const double (&v0)[3],
+                                const double (&q1)[3], const double (&v1)[3])
+{
+    const double r0 = sqrt(q0[0] * q0[0] + q0[1] * q0[1] + q0[2] * q0[2]);
+    const double r1 = sqrt(q1[0] * q1[0] + q1[1] * q1[1] + q1[2] * q1[2]);
+    double rmin = fmin(r0, r1);
+    const double eta0 = q0[0] * v0[0] + q0[1] * v0[1] + q0[2] * v0[2];
+    const double eta1 = q1[0] * v1[0] + q1[1] * v1[1] + q1[2] * v1[2];
+    const double hx = q0[1] * v0[2] - q0[2] * v0[1];
+    const double hy = q0[2] * v0[0] - q0[0] * v0[2];
+    const double hz = q0[0] * v0[1] - q0[1] * v0[0];
+    const double h2 = hx * hx + hy * hy + hz * hz;
+    const double vv = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
+    const double alpha = 2.0 / r0 - vv / mu;        // 1/a
+    const double e2 = 1.0 - h2 * alpha / mu;
+    const double e = sqrt(fmax(e2, 0.0));
+    bool passed;
+    if (alpha > 0.0) {
+        const double twopi = 6.283185307179586;
+        const double esinE = eta0 * sqrt(alpha / mu), ecosE = 1.0 - r0 * alpha;
+        const double M0 = atan2(esinE, ecosE) - esinE;
+        const double M1 = M0 + sqrt(mu * alpha * alpha * alpha) * tau;
+        const double lo = fmin(M0, M1), hi = fmax(M0, M1);
+        passed = floor(hi / twopi) * twopi >= lo;
+    } else {
+        passed = tau >= 0.0 ? (eta0 < 0.0 && eta1 >= 0.0) : (eta1 < 0.0 && eta0 >= 0.0);
+    }
+    if (passed)
+        rmin = fmin(rmin, h2 / (mu * (1.0 + e)));
+    return rmin;
+}
+
+// Star impacts, per body: lost = 1 when the arc reaches r_star (r_star > 0);
+// every flag cleared otherwise and every union-find parent set to the body.
+// Per-block sums of the impactors' m, m Q and count into part (8 per block).
+__global__ void k_ev_star(const RBlk *__restrict__ rblk, const double *__restrict__ m0, double G,
+                          double tau, Snap a, const double *__restrict__ m,
+                          const double *__restrict__ qx, const double *__restrict__ qy,
+                          const double *__restrict__ qz, double r_star, int *__restrict__ lost,
+                          int *__restrict__ root, double *__restrict__ part)
+{
+    __shared__ double sh[8 * kBlock / 64];
+    const RBlk b = rblk[blockIdx.x];
+    const int i = b.start + threadIdx.x;
+    double w[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < b.end) {
+        int flag = 0;
+        if (r_star > 0.0) {
+            const double q0[3] = {a.q0x[i], a.q0y[i], a.q0z[i]}, v0[3] = {a.v0x[i], a.v0y[i], a.v0z[i]};
+            const double q1[3] = {a.q1x[i], a.q1y[i], a.q1z[i]}, v1[3] = {a.v1x[i], a.v1y[i], a.v1z[i]};
+            flag = star_min_dist(G * m0[b.sys], tau, q0, v0, q1, v1) <= r_star;
+        }
+        lost[i] = flag;
+        root[i] = i;
+        if (flag) {
+            const double mi = m[i];
+            w[0] = mi;
+            w[1] = mi * qx[i];
+            w[2] = mi * qy[i];
+            w[3] = mi * qz[i];
+            w[4] = 1.0;
+        }
+    }
+    block_sum<5>(w, sh);
+    if (threadIdx.x < 5)
+        part[(size_t)blockIdx.x * 8 + threadIdx.x] = w[threadIdx.x];
+}
+
+// One workgroup per system: the impactors join the star (m0 += their mass) and
+// the star's centre moves to the centre of mass of star and impactors; the
+// shift is kept in sys[8 s .. 8 s + 2] for the bodies.  cnt[0] += impacts.
+__global__ void k_ev_star_sys(const int *__restrict__ rb_first, const int *__restrict__ rb_count,
+                              const double *__restrict__ part, double *__restrict__ m0,
+                              double *__restrict__ sys, int *__restrict__ cnt)
+{
+    __shared__ double sh[8 * kBlock / 64];
+    double t[5];
+    system_sum<5>(part + 0, 8, rb_first[blockIdx.x], rb_count[blockIdx.x], t, sh);
+    if (threadIdx.x == 0) {
+        double *o = sys + (size_t)blockIdx.x * 8;
+        o[0] = o[1] = o[2] = 0.0;
+        const int k = (int)t[4];
+        if (k > 0) {
+            const double mnew = m0[blockIdx.x] + t[0];
+            o[0] = t[1] / mnew;
+            o[1] = t[2] / mnew;
+            o[2] = t[3] / mnew;
+            m0[blockIdx.x] = mnew;
+            atomicAdd(&cnt[0], k);
+        }
+        o[3] = (double)k;
+    }
+}
+
+// Impactors lose their mass; every other body of a system with impacts moves
+// by minus the star's shift (its heliocentric position is relative to the star).
+__global__ void k_ev_star_apply(const RBlk *__restrict__ rblk, const double *__restrict__ sys,
+                                const int *__restrict__ lost, double *__restrict__ m,
+                                double *__restrict__ qx, double *__restrict__ qy,
+                                double *__restrict__ qz)
+{
+    const RBlk b = rblk[blockIdx.x];
+    const int i = b.start + threadIdx.x;
+    if (i >= b.end)
+        return;
+    const double *o = sys + (size_t)b.sys * 8;
+    if (o[3] == 0.0)
+        return;
+    if (lost[i]) {
+        m[i] = 0.0;
+    } else {
+        qx[i] -= o[0];
+        qy[i] -= o[1];
+        qz[i] -= o[2];
+    }
+}
+
+__device__ int uf_find(int *root, int i)
+{
+    while (root[i] != i)
+        i = root[i];
+    return i;
+}
+
+// Collisions among the step's listed pairs (sorted by (i, j); pairs with a
+// lost member are skipped).  Every thread tests pairs: the Hermite minimum of
+// the step's arcs against (R_i + R_j)^2.  Then thread 0 joins colliding pairs
+// (union-find, the smaller root wins), lists the members in index order and
+// merges every group into its smallest member: summed mass, mass-weighted
+// position and velocity (compensated sums in index order); the others get
+// lost = 2 and m = 0.  One workgroup; collisions are rare, and the member
+// list is ordered by insertion (quadratic in the members of colliding pairs).
+__global__ __launch_bounds__(kBlock) void k_ev_collide(
+    const DevStats *__restrict__ stats, int cap, const int *__restrict__ ice,
+    const int *__restrict__ jce, double tau, Snap a, double rho, int *__restrict__ lost,
+    int *__restrict__ root, int *__restrict__ pflag, int *__restrict__ mem, double *m, double *qx,
+    double *qy, double *qz, double *vx, double *vy, double *vz, int *__restrict__ cnt)
+{
+    const int nce = min(stats->cur_nce, cap);
+    const double k3 = 3.0 / (4.0 * 3.141592653589793 * rho);
+    const double t2 = 2.0 * tau;
+    for (int p = threadIdx.x; p < nce; p += blockDim.x) {
+        const int i = ice[p], j = jce[p];
+        int hit = 0;
+        if (!lost[i] && !lost[j]) {
+            const double d0x = a.q0x[j] - a.q0x[i], d0y = a.q0y[j] - a.q0y[i], d0z = a.q0z[j] - a.q0z[i];
+            const double d1x = a.q1x[j] - a.q1x[i], d1y = a.q1y[j] - a.q1y[i], d1z = a.q1z[j] - a.q1z[i];
+            const double e0x = a.v0x[j] - a.v0x[i], e0y = a.v0y[j] - a.v0y[i], e0z = a.v0z[j] - a.v0z[i];
+            const double e1x = a.v1x[j] - a.v1x[i], e1y = a.v1y[j] - a.v1y[i], e1z = a.v1z[j] - a.v1z[i];
+            const double f0 = d0x * d0x + d0y * d0y + d0z * d0z;
+            const double f1 = d1x * d1x + d1y * d1y + d1z * d1z;
+            const double g0 = t2 * (d0x * e0x + d0y * e0y + d0z * e0z);
+            const double g1 = t2 * (d1x * e1x + d1y * e1y + d1z * e1z);
+            const double rr = cbrt(k3 * m[i]) + cbrt(k3 * m[j]);
+            hit = hermite_min(f0, f1, g0, g1) <= rr * rr;
+        }
+        pflag[p] = hit;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
+    int ncoll = 0, nm = 0;
+    for (int p = 0; p < nce; ++p) {
+        if (!pflag[p])
+            continue;
+        ++ncoll;
+        const int i = ice[p], j = jce[p];
+        const int ra = uf_find(root, i), rb = uf_find(root, j);
+        if (ra != rb) {
+            if (ra < rb)
+                root[rb] = ra;
+            else
+                root[ra] = rb;
+        }
+        // members in increasing index order, each once
+        for (int e = 0; e < 2; ++e) {
+            const int b = e ? j : i;
+            int k = nm;
+            while (k > 0 && mem[k - 1] > b)
+                --k;
+            if (k > 0 && mem[k - 1] == b)
+                continue;
+            for (int q = nm; q > k; --q)
+                mem[q] = mem[q - 1];
+            mem[k] = b;
+            ++nm;
+        }
+    }
+    int merged = 0;
+    for (int e = 0; e < nm; ++e) {
+        const int r = mem[e];
+        if (uf_find(root, r) != r)
+            continue;
+        dd sm{0, 0}, px{0, 0}, py{0, 0}, pz{0, 0}, ux{0, 0}, uy{0, 0}, uz{0, 0};
+        for (int f = e; f < nm; ++f) {
+            const int b = mem[f];
+            if (uf_find(root, b) != r)
+                continue;
+            const double mb = m[b];
+            dd_add(sm, mb);
+            dd_add(px, mb * qx[b]);
+            dd_add(py, mb * qy[b]);
+            dd_add(pz, mb * qz[b]);
+            dd_add(ux, mb * vx[b]);
+            dd_add(uy, mb * vy[b]);
+            dd_add(uz, mb * vz[b]);
+        }
+        const double M = sm.hi + sm.lo;
+        if (M > 0.0) {
+            qx[r] = (px.hi + px.lo) / M;
+            qy[r] = (py.hi + py.lo) / M;
+            qz[r] = (pz.hi + pz.lo) / M;
+            vx[r] = (ux.hi + ux.lo) / M;
+            vy[r] = (uy.hi + uy.lo) / M;
+            vz[r] = (uz.hi + uz.lo) / M;
+        }
+        m[r] = M;
+        for (int f = e + 1; f < nm; ++f) {
+            const int b = mem[f];
+            if (uf_find(root, b) == r) {
+                lost[b] = 2;
+                m[b] = 0.0;
+                ++merged;
+            }
+        }
+    }
+    cnt[1] += ncoll;
+    cnt[2] += merged;
+}
+
+// Ejections, per body not lost: lost = 3 beyond r_eject.  Per-block sums of
+// the mass of the bodies not lost before this check, of the ejected mass, of
+// the ejected momentum and of the count.
+__global__ void k_ev_eject(const RBlk *__restrict__ rblk, double r_eject, int *__restrict__ lost,
+                           const double *__restrict__ m, const double *__restrict__ qx,
+                           const double *__restrict__ qy, const double *__restrict__ qz,
+                           const double *__restrict__ vx, const double *__restrict__ vy,
+                           const double *__restrict__ vz, double *__restrict__ part)
+{
+    __shared__ double sh[8 * kBlock / 64];
+    const RBlk b = rblk[blockIdx.x];
+    const int i = b.start + threadIdx.x;
+    double w[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (i < b.end && !lost[i]) {
+        const double mi = m[i];
+        w[0] = mi;
+        const double r = sqrt(qx[i] * qx[i] + qy[i] * qy[i] + qz[i] * qz[i]);
+        if (r > r_eject) {
+            lost[i] = 3;
+            w[1] = mi;
+            w[2] = mi * vx[i];
+            w[3] = mi * vy[i];
+            w[4] = mi * vz[i];
+            w[5] = 1.0;
+        }
+    }
+    block_sum<6>(w, sh);
+    if (threadIdx.x < 6)
+        part[(size_t)blockIdx.x * 8 + threadIdx.x] = w[threadIdx.x];
+}
+
+// One workgroup per system: the ejected momentum leaves, so the barycentric
+// velocities of the rest change by dv = sum m_e V_e / (m0 + sum m - sum m_e).
+__global__ void k_ev_eject_sys(const int *__restrict__ rb_first, const int *__restrict__ rb_count,
+                               const double *__restrict__ part, const double *__restrict__ m0,
+                               double *__restrict__ sys, int *__restrict__ cnt)
+{
+    __shared__ double sh[8 * kBlock / 64];
+    double t[6];
+    system_sum<6>(part, 8, rb_first[blockIdx.x], rb_count[blockIdx.x], t, sh);
+    if (threadIdx.x == 0) {
+        double *o = sys + (size_t)blockIdx.x * 8;
+        const int k = (int)t[5];
+        o[0] = o[1] = o[2] = 0.0;
+        if (k > 0) {
+            const double rest = (m0[blockIdx.x] + t[0]) - t[1];
+            o[0] = t[2] / rest;
+            o[1] = t[3] / rest;
+            o[2] = t[4] / rest;
+            atomicAdd(&cnt[3], k);
+        }
+        o[3] = (double)k;
+    }
+}
+
+__global__ void k_ev_eject_apply(const RBlk *__restrict__ rblk, const double *__restrict__ sys,
+                                 const int *__restrict__ lost, double *__restrict__ m,
+                                 double *__restrict__ vx, double *__restrict__ vy,
+                                 double *__restrict__ vz)
+{
+    const RBlk b = rblk[blockIdx.x];
+    const int i = b.start + threadIdx.x;
+    if (i >= b.end)
+        return;
+    const double *o = sys + (size_t)b.sys * 8;
+    if (o[3] == 0.0)
+        return;
+    const int f = lost[i];
+    if (f == 3) {
+        m[i] = 0.0;
+    } else if (f == 0) {
+        vx[i] += o[0];
+        vy[i] += o[1];
+        vz[i] += o[2];
+    }
+}
+
+// Order-preserving compaction of the bodies with lost == 0: per-block kept
+// counts, their exclusive scan over all blocks (systems are contiguous, so
+// the scan is also each system's), then every kept body to its place.
+__global__ void k_cmp_count(const RBlk *__restrict__ rblk, const int *__restrict__ lost,
+                            int *__restrict__ kept)
+{
+    __shared__ int sh[kBlock / 64];
+    const RBlk b = rblk[blockIdx.x];
+    const int i = b.start + threadIdx.x;
+    const int k = __popcll(__ballot(i < b.end && lost[i] == 0));
+    if ((threadIdx.x & 63) == 0)
+        sh[threadIdx.x >> 6] = k;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kBlock / 64; ++w)
+            t += sh[w];
+        kept[blockIdx.x] = t;
+    }
+}
+
+// pos[b] = kept[0] + ... + kept[b-1], pos[n] = the total (one workgroup).
+__global__ void k_cmp_scan(int n, const int *__restrict__ kept, int *__restrict__ pos)
+{
+    __shared__ int sh[kBlock];
+    int carry = 0;
+    for (int b0 = 0; b0 < n; b0 += kBlock) {
+        const int b = b0 + threadIdx.x;
+        const int v = b < n ? kept[b] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        // inclusive Hillis-Steele scan of the chunk
+        for (int o = 1; o < kBlock; o <<= 1) {
+            const int t = threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (b < n)
+            pos[b] = carry + sh[threadIdx.x] - v;
+        carry += sh[kBlock - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        pos[n] = carry;
+}
+
+// out: 7 planes of ntot (m, Q, V); idx[k] = the old index of kept body k.
+__global__ void k_cmp_scatter(const RBlk *__restrict__ rblk, const int *__restrict__ lost,
+                              const int *__restrict__ pos, int ntot, const double *__restrict__ m,
+                              const double *__restrict__ qx, const double *__restrict__ qy,
+                              const double *__restrict__ qz, const double *__restrict__ vx,
+                              const double *__restrict__ vy, const double *__restrict__ vz,
+                              double *__restrict__ out, int *__restrict__ idx)
+{
+    __shared__ int sh[kBlock / 64];
+    const RBlk b = rblk[blockIdx.x];
+    const int i = b.start + threadIdx.x;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool keep = i < b.end && lost[i] == 0;
+    const unsigned long long mask = __ballot(keep);
+    if (lane == 0)
+        sh[wv] = __popcll(mask);
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wv; ++w)
+        before += sh[w];
+    if (!keep)
+        return;
+    const int o = pos[blockIdx.x] + before + (int)__popcll(mask & ((1ull << lane) - 1ull));
+    const size_t n = (size_t)ntot;
+    out[o] = m[i];
+    out[n + o] = qx[i];
+    out[2 * n + o] = qy[i];
+    out[3 * n + o] = qz[i];
+    out[4 * n + o] = vx[i];
+    out[5 * n + o] = vy[i];
+    out[6 * n + o] = vz[i];
+    idx[o] = i;
+}
+
+hipError_t launch_events(const Dev &d, const Params &p, double tau, double rho, double r_star,
+                         double r_eject, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    const Snap a = d.snap();
+    k_fill_i32<<<1, 64, 0, s>>>(d.evcnt, 4, 0);
+    k_ev_star<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.m0, p.G, tau, a, d.m, d.qx, d.qy, d.qz, r_star,
+                                        d.lost, d.evroot, d.evpart);
+    k_ev_star_sys<<<d.nsys, kBlock, 0, s>>>(d.rb_first, d.rb_count, d.evpart, d.m0, d.evsys,
+                                             d.evcnt);
+    k_ev_star_apply<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.evsys, d.lost, d.m, d.qx, d.qy, d.qz);
+    k_ev_collide<<<1, kBlock, 0, s>>>(d.stats, d.enc_cap, d.ice, d.jce, tau, a, rho, d.lost,
+                                       d.evroot, d.evflag, d.evmem, d.m, d.qx, d.qy, d.qz, d.vx,
+                                       d.vy, d.vz, d.evcnt);
+    if (r_eject > 0.0) {
+        k_ev_eject<<<d.nrb, kBlock, 0, s>>>(d.rblk, r_eject, d.lost, d.m, d.qx, d.qy, d.qz, d.vx,
+                                             d.vy, d.vz, d.evpart);
+        k_ev_eject_sys<<<d.nsys, kBlock, 0, s>>>(d.rb_first, d.rb_count, d.evpart, d.m0, d.evsys,
+                                                  d.evcnt);
+        k_ev_eject_apply<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.evsys, d.lost, d.m, d.vx, d.vy, d.vz);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const Dev &d, double *out, int *idx, hipStream_t s)
+{
+    if (d.nrb == 0)
+        return hipSuccess;
+    k_cmp_count<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.lost, d.evflag);
+    k_cmp_scan<<<1, kBlock, 0, s>>>(d.nrb, d.evflag, d.cmp_pos);
+    k_cmp_scatter<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.lost, d.cmp_pos, d.ntot, d.m, d.qx, d.qy,
+                                            d.qz, d.vx, d.vy, d.vz, out, idx);
+    return hipGetLastError();
+}
+
 hipError_t launch_diagnostics(const Dev &d, const Params &p, hipStream_t s)
 {
     if (d.ndw > 0)

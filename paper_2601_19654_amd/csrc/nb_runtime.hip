@@ -25,8 +25,13 @@ struct nb_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     Dev d{};
-    std::vector<int> off;
+    std::vector<int> off, nbig, rb_first;
+    // the caller's workspace (the layout is carved again when bodies are removed)
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
     bool have_state = false, have_drift = false, have_enc = false;
+    // nb_events ran on the current state: its lost flags are what nb_compact removes
+    bool have_events = false;
     // the drift outputs of set `snap` hold the last drift or per-phase step
     // (the persistent step launch does not write them)
     bool snap_valid = false;
@@ -323,12 +328,32 @@ void pair_items(int a, int n, int nb, int J, std::vector<PWork> &out)
     }
 }
 
+// Split partials of the symmetric force: 3 doubles per body and tile of TI
+// bodies of its system (quadratic in the system size).
+constexpr long long kSymPartialMax = 4ll << 30;
+// Most source chunks per system of the ordered force (its partials: 3 doubles
+// per body and chunk).
+constexpr int kMaxOrderedSplits = 64;
+
+long long sym_partial_bytes(int nsys, const int32_t *off, int TI)
+{
+    long long b = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const long long n = off[s + 1] - off[s];
+        b += 24 * n * ((n + TI - 1) / TI);
+    }
+    return b;
+}
+
 void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *nbig, Tables &t)
 {
     t.enc_sorted = choose_enc_algo(p, nsys, off, nbig) == 2;
     t.enc_few = choose_enc_algo(p, nsys, off, nbig) == 3;
-    // symmetric tile pairs: every body big (automatic or asked for)
-    t.force_sym = p.force_algo != 1 && !has_small(nsys, off, nbig);
+    // symmetric tile pairs: every body big (asked for, or automatic while their
+    // split partials, 3 doubles per body and tile of its system, stay within
+    // kSymPartialMax; beyond that the ordered pairs' partials are bounded)
+    t.force_sym = p.force_algo != 1 && !has_small(nsys, off, nbig) &&
+                  (p.force_algo == 2 || sym_partial_bytes(nsys, off, 64 * p.force_r) <= kSymPartialMax);
     t.rb_first.assign(nsys, 0);
     t.rb_count.assign(nsys, 0);
     t.nsplit.assign(nsys, 0);
@@ -360,14 +385,19 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
                                             std::min(TI, n - J * TI), J, s,
                                             t.rb_first[s] + (J * TI) / kBlock, I});
         } else {
-            int S = (nb + p.force_j - 1) / p.force_j;
+            // source chunks of J bodies, widened (whole O(N) blocks) so that a
+            // system has at most kMaxOrderedSplits of them
+            int J = p.force_j;
+            if ((nb + J - 1) / J > kMaxOrderedSplits)
+                J = ((nb + kMaxOrderedSplits - 1) / kMaxOrderedSplits + kBlock - 1) / kBlock * kBlock;
+            int S = (nb + J - 1) / J;
             t.nsplit[s] = S;
             t.maxs = std::max(t.maxs, S);
             for (int i0 = 0; i0 < n; i0 += TI)
                 for (int k = 0; k < S; ++k) {
-                    int j0 = k * p.force_j;
+                    int j0 = k * J;
                     t.fwork.push_back(FWork{a + i0, std::min(TI, n - i0), a + j0,
-                                            std::min(p.force_j, nb - j0), k, s,
+                                            std::min(J, nb - j0), k, s,
                                             t.rb_first[s] + j0 / kBlock, 0});
                 }
         }
@@ -546,7 +576,16 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
         d.units = (int2 *)take(t.units.size() * sizeof(int2));
     }
     d.flag = (int *)take(4 * sizeof(int));
-    d.stage = (double *)take((size_t)6 * nd);
+    d.stage = (double *)take((size_t)7 * nd);
+    d.lost = (int *)take((size_t)ntot * sizeof(int));
+    d.evroot = (int *)take((size_t)ntot * sizeof(int));
+    d.evflag = (int *)take((size_t)std::max(std::max(enc_cap, d.nrb), 1) * sizeof(int));
+    d.evmem = (int *)take((size_t)2 * std::max(enc_cap, 1) * sizeof(int));
+    d.evcnt = (int *)take(4 * sizeof(int));
+    d.cmp_pos = (int *)take((size_t)(d.nrb + 1) * sizeof(int));
+    d.evidx = (int *)take((size_t)std::max(ntot, 1) * sizeof(int));
+    d.evpart = (double *)take((size_t)std::max(d.nrb, 1) * 8 * sizeof(double));
+    d.evsys = (double *)take((size_t)std::max(nsys, 1) * 8 * sizeof(double));
     if (p.resolve) {
         // every member of a resolved group is an end of a listed pair
         d.res_cap = std::max(enc_cap, 1);
@@ -939,6 +978,73 @@ void release(nb_ctx *c)
     delete c;
 }
 
+// Work tables and workspace layout for systems with offsets off and big-body
+// counts nbig (NULL: all big) in the context's workspace, and the device copies
+// of the tables; the state itself is not set.  Used at creation and again when
+// lost bodies are removed.
+int setup_layout(nb_ctx *c, int nsys, const int32_t *off, const int32_t *nbig)
+{
+    Tables t;
+    build_tables(c->p, nsys, off, nbig, t);
+    Dev d{};
+    const size_t need = carve(c->p, nsys, off[nsys], c->enc_cap, t, nullptr, d);
+    if (c->ws_bytes < need)
+        return set_err(c, NB_E_WORKSPACE, "workspace of %zu bytes, %zu needed", c->ws_bytes, need);
+    drop_graph(c);
+    c->nsys = nsys;
+    c->ntot = off[nsys];
+    c->off.assign(off, off + nsys + 1);
+    c->nbig.resize(nsys);
+    for (int s = 0; s < nsys; ++s)
+        c->nbig[s] = nbig ? nbig[s] : off[s + 1] - off[s];
+    c->rb_first = t.rb_first;
+    c->d = Dev{};
+    carve(c->p, nsys, c->ntot, c->enc_cap, t, (char *)c->ws, c->d);
+    std::vector<int> ranges(3 * (size_t)nsys);
+    for (int s = 0; s < nsys; ++s) {
+        ranges[s] = t.nsplit[s];
+        ranges[nsys + s] = t.dw_first[s];
+        ranges[2 * nsys + s] = t.dw_count[s];
+    }
+    int r = NB_OK;
+    auto up = [&](void *dst, const void *src, size_t n) {
+        if (r == NB_OK && n)
+            r = copy(c, dst, src, n);
+    };
+    up(c->d.off, off, (nsys + 1) * sizeof(int));
+    up(c->d.nbig, c->nbig.data(), nsys * sizeof(int));
+    up(c->d.nsplit, ranges.data(), ranges.size() * sizeof(int));
+    up(c->d.rb_first, t.rb_first.data(), nsys * sizeof(int));
+    up(c->d.rb_count, t.rb_count.data(), nsys * sizeof(int));
+    up(c->d.sys_of, t.sys_of.data(), t.sys_of.size() * sizeof(int));
+    up(c->d.rblk, t.rblk.data(), t.rblk.size() * sizeof(RBlk));
+    up(c->d.fwork, t.fwork.data(), t.fwork.size() * sizeof(FWork));
+    up(c->d.ework, t.ework.data(), t.ework.size() * sizeof(PWork));
+    up(c->d.dwork, t.dwork.data(), t.dwork.size() * sizeof(PWork));
+    up(c->d.psys, t.psys.data(), t.psys.size() * sizeof(PSys));
+    c->p.step_algo = choose_step_algo(c->p, nsys, off);
+    if (r == NB_OK && launch_fill_i32(c->d.step_nce, c->d.step_chunk, 0, c->stream) != hipSuccess)
+        r = set_err(c, NB_E_HIP, "clearing the step counters failed");
+    if (r == NB_OK && c->ntot > 0 && launch_fill_i32(c->d.lost, c->ntot, 0, c->stream) != hipSuccess)
+        r = set_err(c, NB_E_HIP, "clearing the lost flags failed");
+    if (c->d.enc_sorted) {
+        up(c->d.sys_cell_base, t.cell_base.data(), nsys * sizeof(int));
+        up(c->d.sys_cell_cnt, t.cell_cnt.data(), nsys * sizeof(int));
+        up(c->d.tiles, t.tiles.data(), t.tiles.size() * sizeof(Tile));
+        up(c->d.units, t.units.data(), t.units.size() * sizeof(int2));
+        if (r == NB_OK && launch_fill_i32(c->d.cell_cnt, c->d.ncell, 0, c->stream) != hipSuccess)
+            r = set_err(c, NB_E_HIP, "clearing the cell counts failed");
+    }
+    if (r == NB_OK)
+        r = reset_stats(c);
+    if (r == NB_OK)
+        r = sync(c);
+    c->have_state = c->have_drift = c->have_enc = c->snap_valid = c->mom_valid = false;
+    c->have_events = false;
+    c->snap = 0;
+    return r;
+}
+
 int enter(nb_ctx *c)
 {
     if (!c)
@@ -1037,63 +1143,19 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *n
         if (c->p.enc_algo == 3 && max_big(nsys, off, nbig) > kBlock)
             c->p.enc_algo = 0;
     }
-    c->nsys = nsys;
-    c->ntot = off[nsys];
     c->enc_cap = enc_cap;
-    c->off.assign(off, off + nsys + 1);
     c->stream = (hipStream_t)stream;
+    c->ws = workspace;
+    c->ws_bytes = bytes;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return NB_E_HIP;
     }
-    Tables t;
-    build_tables(c->p, nsys, off, nbig, t);
-    size_t need = carve(c->p, nsys, c->ntot, enc_cap, t, nullptr, c->d);
-    if (bytes < need) {
+    int r = setup_layout(c, nsys, off, nbig);
+    if (r == NB_E_WORKSPACE) {
         delete c;
-        return NB_E_WORKSPACE;
+        return r;
     }
-    carve(c->p, nsys, c->ntot, enc_cap, t, (char *)workspace, c->d);
-    std::vector<int> ranges(3 * (size_t)nsys);
-    for (int s = 0; s < nsys; ++s) {
-        ranges[s] = t.nsplit[s];
-        ranges[nsys + s] = t.dw_first[s];
-        ranges[2 * nsys + s] = t.dw_count[s];
-    }
-    int r = NB_OK;
-    auto up = [&](void *dst, const void *src, size_t n) {
-        if (r == NB_OK && n)
-            r = copy(c, dst, src, n);
-    };
-    up(c->d.off, off, (nsys + 1) * sizeof(int));
-    std::vector<int> nb(nsys);
-    for (int s = 0; s < nsys; ++s)
-        nb[s] = nbig ? nbig[s] : off[s + 1] - off[s];
-    up(c->d.nbig, nb.data(), nsys * sizeof(int));
-    up(c->d.nsplit, ranges.data(), ranges.size() * sizeof(int));
-    up(c->d.rb_first, t.rb_first.data(), nsys * sizeof(int));
-    up(c->d.rb_count, t.rb_count.data(), nsys * sizeof(int));
-    up(c->d.sys_of, t.sys_of.data(), t.sys_of.size() * sizeof(int));
-    up(c->d.rblk, t.rblk.data(), t.rblk.size() * sizeof(RBlk));
-    up(c->d.fwork, t.fwork.data(), t.fwork.size() * sizeof(FWork));
-    up(c->d.ework, t.ework.data(), t.ework.size() * sizeof(PWork));
-    up(c->d.dwork, t.dwork.data(), t.dwork.size() * sizeof(PWork));
-    up(c->d.psys, t.psys.data(), t.psys.size() * sizeof(PSys));
-    c->p.step_algo = choose_step_algo(c->p, nsys, off);
-    if (r == NB_OK && launch_fill_i32(c->d.step_nce, c->d.step_chunk, 0, c->stream) != hipSuccess)
-        r = set_err(c, NB_E_HIP, "nb_create: clearing the step counters failed");
-    if (c->d.enc_sorted) {
-        up(c->d.sys_cell_base, t.cell_base.data(), nsys * sizeof(int));
-        up(c->d.sys_cell_cnt, t.cell_cnt.data(), nsys * sizeof(int));
-        up(c->d.tiles, t.tiles.data(), t.tiles.size() * sizeof(Tile));
-        up(c->d.units, t.units.data(), t.units.size() * sizeof(int2));
-        if (r == NB_OK && launch_fill_i32(c->d.cell_cnt, c->d.ncell, 0, c->stream) != hipSuccess)
-            r = set_err(c, NB_E_HIP, "nb_create: clearing the cell counts failed");
-    }
-    if (r == NB_OK)
-        r = reset_stats(c);
-    if (r == NB_OK)
-        r = sync(c);
     if (r == NB_OK && c->stream) {
         // default priority, like every stream here
         if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
@@ -1156,6 +1218,7 @@ int nb_upload(nb_ctx *c, const double *m0, const double *m, const double *x, con
     c->snap_valid = false;
     c->mom_valid = false;
     c->have_enc = false;
+    c->have_events = false;
     return NB_OK;
 }
 
@@ -1559,6 +1622,107 @@ int nb_resolve_host(int n, double G, double m0, double chg_inner, double tol, do
         info->max_steps = t.max_steps;
     }
     return NB_OK;
+}
+
+int nb_events(nb_ctx *c, const nb_event_params *ep, nb_event_counts *counts, int32_t *lost,
+              int where)
+{
+    int r = enter(c);
+    if (r)
+        return r;
+    if (!ep || !(ep->rho > 0.0) || !std::isfinite(ep->rho) || !(ep->r_star >= 0.0) ||
+        !(ep->r_eject >= 0.0) || !std::isfinite(ep->r_star) || !std::isfinite(ep->r_eject) ||
+        (where != NB_HOST && where != NB_DEVICE))
+        return set_err(c, NB_E_INVALID, "nb_events: bad argument");
+    if (!c->have_state || !c->snap_valid || !c->have_enc)
+        return set_err(c, NB_E_NOT_READY,
+                       "nb_events: needs the drift arcs and the encounter list of the last step");
+    // the pairs in (i, j) order: the groups do not depend on the append order
+    HIP_OK(c, launch_enc_sort(c->d, 0, c->stream));
+    HIP_OK(c, launch_events(c->d.with_snap(c->snap), c->p, c->last_dt, ep->rho, ep->r_star,
+                            ep->r_eject, c->stream));
+    int cnt[4] = {0, 0, 0, 0};
+    DevStats st;
+    HIP_OK(c, hipMemcpyAsync(cnt, c->d.evcnt, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(c, hipMemcpyAsync(&st, c->d.stats, sizeof st, hipMemcpyDeviceToHost, c->stream));
+    if (lost && (r = copy(c, lost, c->d.lost, (size_t)c->ntot * sizeof(int))))
+        return r;
+    if ((r = sync(c)))
+        return r;
+    if (counts) {
+        counts->star = cnt[0];
+        counts->collide = cnt[1];
+        counts->merged = cnt[2];
+        counts->ejected = cnt[3];
+    }
+    c->have_events = true;
+    if (cnt[0] + cnt[2] + cnt[3] > 0) {
+        // masses, star masses, positions or velocities changed: new critical
+        // radii and force (first-same-as-last), momentum summed again
+        if ((r = enqueue_force(c)) || (r = sync(c)))
+            return r;
+        c->have_drift = c->have_enc = c->snap_valid = c->mom_valid = false;
+    }
+    if (st.cur_nce > c->enc_cap)
+        return set_err(c, NB_E_CAPACITY, "nb_events: %d listed pairs, only %d kept", st.cur_nce,
+                       c->enc_cap);
+    return NB_OK;
+}
+
+int nb_compact(nb_ctx *c, int32_t *off_out, int32_t *nbig_out, int32_t *index, int where)
+{
+    int r = enter(c);
+    if (r)
+        return r;
+    if (where != NB_HOST && where != NB_DEVICE)
+        return set_err(c, NB_E_INVALID, "nb_compact: bad argument");
+    if (!c->have_state || !c->have_events)
+        return set_err(c, NB_E_NOT_READY, "nb_compact: no nb_events on the current state");
+    const int n = c->ntot, nsys = c->nsys;
+    if ((r = sync(c)))
+        return r;
+    double *out = c->d.stage;
+    HIP_OK(c, launch_compact(c->d, out, c->d.evidx, c->stream));
+    std::vector<int> pos(c->d.nrb + 1, 0);
+    if ((r = copy(c, pos.data(), c->d.cmp_pos, pos.size() * sizeof(int))))
+        return r;
+    if ((r = sync(c)))
+        return r;
+    const int kept = n > 0 ? pos[c->d.nrb] : 0;
+    std::vector<int32_t> noff(nsys + 1, 0), nbig(nsys, 0), idx(kept);
+    std::vector<double> st7((size_t)7 * kept), m0(nsys);
+    // a system's first block (for a system without bodies: the next system's)
+    for (int s = 0; s < nsys; ++s)
+        noff[s] = n > 0 ? pos[c->rb_first[s]] : 0;
+    noff[nsys] = kept;
+    for (int k = 0; k < 7; ++k)
+        if (kept && (r = copy(c, st7.data() + (size_t)k * kept, out + (size_t)k * n,
+                              (size_t)kept * sizeof(double))))
+            return r;
+    if (kept && (r = copy(c, idx.data(), c->d.evidx, (size_t)kept * sizeof(int))))
+        return r;
+    if ((r = copy(c, m0.data(), c->d.m0, (size_t)nsys * sizeof(double))) || (r = sync(c)))
+        return r;
+    // big bodies stay first in every system: the kept ones among the first nbig
+    for (int s = 0; s < nsys; ++s)
+        for (int k = noff[s]; k < noff[s + 1]; ++k)
+            nbig[s] += idx[k] < c->off[s] + c->nbig[s];
+    if (kept < n) {
+        if ((r = setup_layout(c, nsys, noff.data(), nbig.data())))
+            return r;
+        // the kept state again (DH), with new critical radii and force
+        if ((r = nb_upload(c, m0.data(), st7.data(), st7.data() + (size_t)kept,
+                           st7.data() + (size_t)4 * kept, NB_DH, NB_HOST)))
+            return r;
+    }
+    c->have_events = false;
+    if (off_out && (r = copy(c, off_out, noff.data(), (nsys + 1) * sizeof(int32_t))))
+        return r;
+    if (nbig_out && (r = copy(c, nbig_out, nbig.data(), nsys * sizeof(int32_t))))
+        return r;
+    if (index && (r = copy(c, index, idx.data(), (size_t)kept * sizeof(int32_t))))
+        return r;
+    return sync(c);
 }
 
 int nb_get_choices(const nb_ctx *c, int32_t *force_algo, int32_t *enc_algo, int32_t *step_algo)

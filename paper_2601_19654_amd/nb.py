@@ -70,6 +70,15 @@ class nb_resolve_info(ctypes.Structure):
     ]
 
 
+class nb_event_params(ctypes.Structure):
+    _fields_ = [("rho", ctypes.c_double), ("r_star", ctypes.c_double), ("r_eject", ctypes.c_double)]
+
+
+class nb_event_counts(ctypes.Structure):
+    _fields_ = [("star", ctypes.c_int32), ("collide", ctypes.c_int32), ("merged", ctypes.c_int32),
+                ("ejected", ctypes.c_int32)]
+
+
 class NbError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{msg} (status {code})")
@@ -105,6 +114,8 @@ SIGNATURES = {
     "nb_get_choices": (_I, [_P, _P, _P, _P]),
     "nb_get_params": (_I, [_P, _P, _P]),
     "nb_destroy": (_I, [_P]),
+    "nb_events": (_I, [_P, _P, _P, _P, _I]),
+    "nb_compact": (_I, [_P, _P, _P, _P, _I]),
 }
 
 
@@ -300,6 +311,30 @@ class Context:
         """nb_step without the statistics argument (still synchronizes at the end)."""
         return self._check(lib().nb_step(self.ctx, float(dt), int(nsteps), None), "nb_step",
                            allow=(NB_E_CAPACITY, NB_E_KEPLER))
+
+    # ------------------------------------------------------------ events
+    def events(self, rho, r_star=0.0, r_eject=0.0, allow_overflow=False):
+        """Star impacts, collisions and ejections of the last step; returns
+        (counts dict, lost flags per body)."""
+        ep = nb_event_params(float(rho), float(r_star), float(r_eject))
+        cnt = nb_event_counts()
+        lost = np.zeros(max(self.ntot, 1), np.int32)
+        self._check(lib().nb_events(self.ctx, ctypes.byref(ep), ctypes.byref(cnt), _addr(lost), NB_HOST),
+                    "nb_events", allow=(NB_E_CAPACITY,) if allow_overflow else ())
+        return {k: getattr(cnt, k) for k, _ in nb_event_counts._fields_}, lost[:self.ntot]
+
+    def compact(self):
+        """Remove the lost bodies; returns the old index of every kept body and
+        updates off, ntot and nbig."""
+        off = np.zeros(self.nsys + 1, np.int32)
+        nbig = np.zeros(max(self.nsys, 1), np.int32)
+        idx = np.zeros(max(self.ntot, 1), np.int32)
+        self._check(lib().nb_compact(self.ctx, _addr(off), _addr(nbig), _addr(idx), NB_HOST), "nb_compact")
+        self.off = off
+        self.ntot = int(off[-1])
+        if self.nbig is not None:
+            self.nbig = nbig[:self.nsys].copy()
+        return idx[:self.ntot].copy()
 
     # ------------------------------------------------------------ outputs
     def diagnostics(self):

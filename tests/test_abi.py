@@ -137,3 +137,22 @@ def test_package_tuning_table_matches_the_autotuner_cache():
     assert set(rows) == set(cache)
     for k, vals in rows.items():
         assert vals == [int(cache[k][f]) for f in autotune.TABLE_FIELDS], k
+
+
+def test_workspace_stays_bounded_for_millions_of_bodies(nb):
+    """The symmetric force's split partials grow as N^2/T; beyond 4 GiB of them
+    the automatic choice takes ordered pairs with at most 64 source chunks, so
+    the workspace grows about linearly: 2^21 bodies in one system fit in a few
+    GiB of the 288 GB of HBM (the sorted encounter check's tile-pair list is
+    the largest part there)."""
+    p = nb.default_params()
+    sizes = {}
+    for n in (131072, 600000, 1 << 21):
+        off = np.array([0, n], np.int32)
+        b = ctypes.c_size_t()
+        assert nb.lib().nb_workspace_size(ctypes.byref(p), 1, off.ctypes.data_as(ctypes.c_void_p), None,
+                                          1 << 18, ctypes.byref(b)) == nb.NB_OK
+        sizes[n] = b.value
+    assert sizes[600000] < 4 << 30
+    assert sizes[1 << 21] < 16 << 30
+
