@@ -310,6 +310,8 @@ def main():
                          "else 0 = none)")
     ap.add_argument("--no-full-method", action="store_true",
                     help="skip the full-method lines (c3 adds them by default)")
+    ap.add_argument("--log", default=None,
+                    help="also append the result line to this JSON-lines run log")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -393,6 +395,9 @@ def main():
     out["cpu_baseline"] = None if args.no_cpu_baseline else cpu_baseline(w)
     out["kernel_source_sha256_16"] = kernel_hash()
     print(json.dumps(out), flush=True)
+    if args.log:
+        with open(args.log, "a") as f:
+            f.write(json.dumps({"kind": "bench", "time": time.strftime("%Y-%m-%dT%H:%M:%S"), **out}) + "\n")
 
 
 if __name__ == "__main__":

@@ -52,7 +52,7 @@ extern "C" {
 #endif
 
 #define NB_VERSION_MAJOR 0
-#define NB_VERSION_MINOR 2
+#define NB_VERSION_MINOR 3
 
 /* status codes */
 #define NB_OK            0
@@ -97,10 +97,11 @@ typedef struct nb_params {
                              reach filter, 2 spatially sorted tiles with tile-pair culling,
                              3 every body against the big bodies of its system (at most 256
                              big bodies per system; automatic when some bodies are small) */
-    int32_t step_algo;    /* nb_step: 0 automatic, 1 one launch per phase over all systems
-                             (HIP graph), 2 one persistent launch in which a workgroup owns a
-                             system for many steps (FP64 pair arithmetic; systems of at most
-                             NB_PERSISTENT_MAX_N bodies; not with resolve) */
+    int32_t step_algo;    /* nb_step: 0 automatic (the tuning table's choice, else 1), 1 one
+                             launch per phase over all systems (HIP graph), 2 one persistent
+                             launch in which a workgroup owns a system for many steps (FP64
+                             pair arithmetic; systems of at most NB_PERSISTENT_MAX_N bodies; not
+                             with resolve; keeps no drift arcs for nb_encounters or nb_events) */
     int32_t resolve;      /* 0: flag close encounters only (hot-path mode); 1: the full
                              hybrid method, every flagged group resolved on the host by
                              Bulirsch-Stoer inside each nb_step (Sec. 2.1.1, Sec. 3.2) */
@@ -110,14 +111,18 @@ typedef struct nb_params {
                              every body big); automatic takes 2 where it applies */
     double  bs_tol;       /* Bulirsch-Stoer relative tolerance (0: 1e-12) */
     const char *autotune_path; /* tuning table written by the autotuner (text; NULL: none).
-                             When every tile and algorithm field above (force_jchunk,
-                             force_r, enc_jchunk, enc_algo, step_algo, force_algo) is 0,
+                             When every tile and algorithm field (force_jchunk, force_r,
+                             enc_jchunk, enc_algo, step_algo, force_algo, force_g) is 0,
                              nb_workspace_size and nb_create take them from the table's
                              entry for this GPU, mode and size class (largest system and
                              system count, and the largest big-body count when some
                              bodies are small, each rounded up to a power of two); a
                              class the table lacks keeps the defaults.  An unreadable
                              file is NB_E_INVALID.  Read during the call only. */
+    int32_t force_g;      /* symmetric force: tiles of 64 force_r bodies per super-tile, 1, 2
+                             or 4 (0: automatic, the widest that still gives 2048 work
+                             items).  A body receives one partial sum per super-tile of
+                             its system, so wider super-tiles write fewer partials. */
 } nb_params;
 
 /* largest system the persistent step launch accepts */

@@ -25,6 +25,7 @@ CACHE = os.path.join(PKG, "tuning.json")
 
 FORCE_R = (1, 2, 4)
 FORCE_J = (256, 512, 1024, 2048, 4096)
+FORCE_G = (1, 2, 4)          # super-tile widths of the symmetric force
 ENC_J = (256, 512, 1024, 2048, 4096)
 
 
@@ -52,12 +53,12 @@ def key(mode: str, off, arch_name: str | None = None, nbig=None) -> str:
 
 
 TABLE = os.path.join(PKG, "tuning.tsv")
-TABLE_FIELDS = ("force_algo", "force_r", "force_jchunk", "enc_algo", "enc_jchunk", "step_algo")
+TABLE_FIELDS = ("force_algo", "force_r", "force_jchunk", "enc_algo", "enc_jchunk", "step_algo", "force_g")
 
 
 def write_table(cache: dict, path: str = TABLE) -> None:
     """The table the library reads (nb_params.autotune_path): one line per size
-    class, the key then the six chosen fields."""
+    class, the key then the seven chosen fields (force_g 0: the automatic width)."""
     lines = ["# key " + " ".join(TABLE_FIELDS) + "  (written by autotune.py from tuning.json)"]
     for k in sorted(cache):
         e = cache[k]
@@ -84,20 +85,21 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
     all_big = w.nbig is None or np.all(np.asarray(w.nbig) == np.diff(w.off))
     for fa in ((1, 2) if all_big else (1,)):
         for r in FORCE_R:
-            # the symmetric tile pairs have no source-chunk parameter
-            for j in (FORCE_J if fa == 1 else (1024,)):
+            # the symmetric tile pairs have no source-chunk parameter, but a
+            # super-tile width (tiles per workgroup)
+            for j, g in ([(j, 0) for j in FORCE_J] if fa == 1 else [(1024, g) for g in FORCE_G]):
                 if j > max(256, _pow2(int(np.diff(w.off).max()))) * 2:
                     continue
                 p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j,
-                                      force_algo=fa)
+                                      force_algo=fa, force_g=g)
                 c = nb.Context(w.off, p, enc_cap=1 << 16, device="cuda:0", tuned=False, nbig=w.nbig)
                 c.upload(w.m0, w.m, w.x, w.v)
-                # ranked by the whole force evaluation: more source chunks mean more
-                # split partials for the finalize pass to sum
+                # ranked by the whole force evaluation: more source chunks or
+                # narrower super-tiles mean more split partials for the finalize
                 ms = c.time_kernel(nb.NB_K_FORCE_EVAL, reps=reps)
-                res_force[(fa, r, j)] = ms
+                res_force[(fa, r, j, g)] = ms
                 if verbose:
-                    print(f"[autotune] {mode} force evaluation algo={fa} r={r} j={j}: {ms:.4f} ms",
+                    print(f"[autotune] {mode} force evaluation algo={fa} r={r} j={j} g={g}: {ms:.4f} ms",
                           file=sys.stderr, flush=True)
                 c.close()
     # encounter candidates: (1, j) direct with source chunks of j, (2, 0) sorted
@@ -119,12 +121,12 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
         if verbose:
             print(f"[autotune] {mode} encounter algo={ea} j={j}: {ms:.4f} ms", file=sys.stderr, flush=True)
         c.close()
-    (fa, r, j), fms = min(res_force.items(), key=lambda kv: kv[1])
+    (fa, r, j, g), fms = min(res_force.items(), key=lambda kv: kv[1])
     (ea, ej), ems = min(res_enc.items(), key=lambda kv: kv[1])
 
-    def step_ms(fa_, r_, j_, sa):
+    def step_ms(fa_, r_, j_, g_, sa):
         p = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r_, force_jchunk=j_,
-                              force_algo=fa_, enc_jchunk=ej or 1024, enc_algo=ea, step_algo=sa)
+                              force_algo=fa_, force_g=g_, enc_jchunk=ej or 1024, enc_algo=ea, step_algo=sa)
         c = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", tuned=False, nbig=w.nbig)
         c.upload(w.m0, w.m, w.x, w.v)
         c.step(w.dt, 3, allow=(nb.NB_E_CAPACITY, nb.NB_E_KEPLER))
@@ -140,24 +142,25 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
         for k in near:
             res_near[k] = step_ms(*k, 1)
             if verbose:
-                print(f"[autotune] {mode} step with force algo={k[0]} r={k[1]} j={k[2]}: {res_near[k]:.4f} ms",
-                      file=sys.stderr, flush=True)
-        fa, r, j = min(res_near.items(), key=lambda kv: kv[1])[0]
-        fms = res_force[(fa, r, j)]
+                print(f"[autotune] {mode} step with force algo={k[0]} r={k[1]} j={k[2]} g={k[3]}: "
+                      f"{res_near[k]:.4f} ms", file=sys.stderr, flush=True)
+        fa, r, j, g = min(res_near.items(), key=lambda kv: kv[1])[0]
+        fms = res_force[(fa, r, j, g)]
     # whole-step launch: per-phase launches (tuned tiles) vs the persistent launch
     res_step = {}
     for sa in ((1, 2) if mode == "fp64" and int(np.diff(w.off).max()) <= 8192 else (1,)):
-        res_step[sa] = res_near[(fa, r, j)] if sa == 1 and (fa, r, j) in res_near else step_ms(fa, r, j, sa)
+        res_step[sa] = (res_near[(fa, r, j, g)] if sa == 1 and (fa, r, j, g) in res_near
+                        else step_ms(fa, r, j, g, sa))
         if verbose:
             print(f"[autotune] {mode} step launch {sa}: {res_step[sa]:.4f} ms", file=sys.stderr, flush=True)
     sa, sms = min(res_step.items(), key=lambda kv: kv[1])
-    return {"force_algo": fa, "force_r": r, "force_jchunk": j, "enc_jchunk": ej or 1024,
+    return {"force_algo": fa, "force_r": r, "force_jchunk": j, "force_g": g, "enc_jchunk": ej or 1024,
             "enc_algo": ea,
             "step_algo": sa, "step_ms": round(sms, 5), "step_candidates": {str(k): round(v, 5) for k, v in res_step.items()},
             "force_ms": round(fms, 5),
             "encounter_ms": round(ems, 5), "workload": w.name, "tuned_at": time.strftime("%Y-%m-%d"),
-            "force_candidates": {f"a{f}_r{a}_j{b}": round(v, 5) for (f, a, b), v in res_force.items()},
-            "near_tie_steps": {f"a{f}_r{a}_j{b}": round(v, 5) for (f, a, b), v in res_near.items()},
+            "force_candidates": {f"a{f}_r{a}_j{b}_g{h}": round(v, 5) for (f, a, b, h), v in res_force.items()},
+            "near_tie_steps": {f"a{f}_r{a}_j{b}_g{h}": round(v, 5) for (f, a, b, h), v in res_near.items()},
             "encounter_candidates": {f"a{a}_j{b}": round(v, 5) for (a, b), v in res_enc.items()}}
 
 

@@ -162,7 +162,8 @@ struct Dev {
     int *nbig;            // per system: bodies [off[s], off[s] + nbig[s]) are big
     int force_few;        // every system has at most 256 big bodies and the targets are many:
                           // the few-source force kernels
-    int force_sym;        // every body big: work items are unordered tile pairs
+    int force_sym;        // every body big: work items are unordered pairs of super-tiles
+    int sym_g;            // tiles per super-tile (1, 2 or 4; the symmetric kernels' waves)
     Snap alt;             // the second set of drift outputs
 
     Snap snap() const
@@ -194,6 +195,7 @@ struct Params {
                           // 3: each body against its system's big bodies (at most kBlock)
     int step_algo;        // 1: per-phase launches, 2: persistent per-system launch
     int force_algo;       // 0 automatic, 1 ordered pairs, 2 symmetric tile pairs
+    int force_g;          // symmetric force: tiles per super-tile (0 automatic, 1, 2, 4)
     int resolve;          // 1: resolve flagged groups on the host every step
     int resolve_threads;
     double bs_tol;

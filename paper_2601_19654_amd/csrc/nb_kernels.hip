@@ -1180,15 +1180,20 @@ __global__ __launch_bounds__(kBlock) void k_force32c_few(const FWork *__restrict
 // Symmetric pairs (every body big): each unordered pair is evaluated once and
 // applied to both bodies, a_i += m_j q d and a_j -= m_i q d with the mass-free
 // weight q = K/r^3 - K'/r^2 (Newtonian q = 1/r^3 refined from the hardware
-// estimate as in m_rinv3).  A work item is a pair of tiles (I <= J) of T = 64 R
-// bodies of one system, owned by one wave: the lanes hold R targets of tile I,
-// tile J sits in the wave's LDS slice together with its accumulators.  At step
-// k of sub-tile t, lane L pairs with source 64 t + ((L + k) mod 64), so the 64
-// lanes touch 64 different sources and update their accumulators without
-// atomics.  Item (I, J) writes tile I's sums to split slot J and tile J's sums
-// to slot I (both to slot I on the diagonal, where only i < j is taken), so
-// every body receives exactly one partial per tile of its system, summed in
-// slot order by the finalize pass.
+// estimate as in m_rinv3).  Bodies of a system form tiles of T = 64 R and
+// super-tiles of G tiles.  A work item is a pair of super-tiles (I <= J),
+// owned by a workgroup of G waves: wave w holds the R targets per lane of tile
+// w of I in registers, the G tiles of J sit in LDS together with their
+// accumulators, and in round k wave w meets tile (w + k) mod G of J, so that no
+// two waves update one source tile at once.  Within a tile pair, at step k of
+// sub-tile t, lane L pairs with source 64 t + (L xor k), so the 64 lanes touch
+// 64 different sources and update their accumulators without atomics.  Item
+// (I, J) writes super-tile I's sums to split slot J and super-tile J's sums to
+// slot I (both to slot I on the diagonal, where each pair is met once), so
+// every body receives exactly one partial per super-tile of its system, summed
+// in slot order by the finalize pass: G times fewer partials than tiles, in a
+// fixed order whatever the schedule.  The register budget keeps three waves
+// per SIMD (two at R = 4), as with one wave per work item.
 __device__ __forceinline__ double rinv3(double r2)
 {
     const double y0 = __builtin_amdgcn_rsq(r2);
@@ -1368,8 +1373,8 @@ __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, in
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict__ work, int nitems,
+template <int R, int G>
+__global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force64_sym(const FWork *__restrict__ work, int nitems,
                                                         const double *__restrict__ qx,
                                                         const double *__restrict__ qy,
                                                         const double *__restrict__ qz,
@@ -1379,78 +1384,93 @@ __global__ __launch_bounds__(kBlock) void k_force64_sym(const FWork *__restrict_
                                                         double inner, DevStats *stats)
 {
     constexpr int T = 64 * R;
-    __shared__ SymTile64<T> tl[kWaves];
+    __shared__ SymTile64<T> tl[G];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    SymTile64<T> &L = tl[wv];
     int near = 0;
-    for (int it = blockIdx.x * kWaves + wv; it < nitems; it += gridDim.x * kWaves) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const FWork wk = work[it];
         const bool diag = wk.i0 == wk.j0;
-        for (int k = lane; k < T; k += 64) {
-            // sources past the tile end: massless and far away (r^2 ~ 1e300, so
+        // the G source tiles of super-tile J (nj real records from j0)
+        for (int k = threadIdx.x; k < G * T; k += 64 * G) {
+            SymTile64<T> &S = tl[k / T];
+            const int e = k % T;
+            // sources past the end: massless and far away (r^2 ~ 1e300, so
             // their weight underflows to 0 instead of meeting a target at r = 0)
             const bool ok = k < wk.nj;
             const int j = wk.j0 + (ok ? k : 0);
-            L.x[k] = ok ? qx[j] : 1e150;
-            L.y[k] = ok ? qy[j] : 1e150;
-            L.z[k] = ok ? qz[j] : 1e150;
-            L.m[k] = ok ? m[j] : 0.0;
+            S.x[e] = ok ? qx[j] : 1e150;
+            S.y[e] = ok ? qy[j] : 1e150;
+            S.z[e] = ok ? qz[j] : 1e150;
+            S.m[e] = ok ? m[j] : 0.0;
             const double rcj = ok ? rc[j] : 0.0;
-            L.rc[k] = rcj;
-            L.r2[k] = fmax(rcj * rcj, DBL_MIN);
-            L.ax[k] = L.ay[k] = L.az[k] = 0.0;
+            S.rc[e] = rcj;
+            S.r2[e] = fmax(rcj * rcj, DBL_MIN);
+            S.ax[e] = S.ay[e] = S.az[e] = 0.0;
         }
-        wave_lds_sync();
+        __syncthreads();
+        // this wave's target tile: tni bodies from ti0 (none when tni <= 0)
+        const int ti0 = wk.i0 + wv * T;
+        const int tni = min(T, wk.ni - wv * T);
         double xi[R], yi[R], zi[R], mi[R], ax[R], ay[R], az[R];
         double tmi = DBL_MIN;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int li = 64 * r + lane;
-            const bool ok = li < wk.ni;
-            const int i = wk.i0 + (ok ? li : 0);
+            const bool ok = li < tni;
+            const int i = ok ? ti0 + li : wk.i0;
             xi[r] = qx[i];
             yi[r] = qy[i];
             zi[r] = qz[i];
-            // targets past the tile end are massless: they add nothing to tile J
+            // targets past the tile end are massless: they add nothing to the sources
             mi[r] = ok ? m[i] : 0.0;
             tmi = fmax(tmi, rc[i] * rc[i]);
             ax[r] = ay[r] = az[r] = 0.0;
         }
         tmi = wave_max(tmi);
-        if (diag)
-            sym_tile64<R, true, T>(L, lane, wk.i0, wk.ni, inner, rc, xi, yi, zi, mi, tmi, ax, ay, az,
-                                   near);
-        else
-            sym_tile64<R, false, T>(L, lane, wk.i0, wk.ni, inner, rc, xi, yi, zi, mi, tmi, ax, ay, az,
-                                    near);
-        wave_lds_sync();
-        // tile I to slot J (on the diagonal together with tile J's sums of the same bodies)
+        // rounds as in the FP32C kernel: wave w meets source tile (w + k) mod G
+        const int nr = diag ? G / 2 + 1 : G;
+        for (int k = 0; k < nr; ++k) {
+            const int s = (wv + k) % G;
+            const bool go = tni > 0 && s * T < wk.nj && !(diag && 2 * k == G && wv >= G / 2);
+            if (go) {
+                if (diag && k == 0)
+                    sym_tile64<R, true, T>(tl[s], lane, ti0, tni, inner, rc, xi, yi, zi, mi, tmi,
+                                           ax, ay, az, near);
+                else
+                    sym_tile64<R, false, T>(tl[s], lane, ti0, tni, inner, rc, xi, yi, zi, mi, tmi,
+                                            ax, ay, az, near);
+            }
+            __syncthreads();
+        }
+        // super-tile I's sums to slot J (on the diagonal together with the same
+        // bodies' sums as sources)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int li = 64 * r + lane;
-            if (li < wk.ni) {
+            if (li < tni) {
                 double sx_ = ax[r], sy_ = ay[r], sz_ = az[r];
                 if (diag) {
-                    sx_ += L.ax[li];
-                    sy_ += L.ay[li];
-                    sz_ += L.az[li];
+                    sx_ += tl[wv].ax[li];
+                    sy_ += tl[wv].ay[li];
+                    sz_ += tl[wv].az[li];
                 }
-                const int i = wk.i0 + li;
+                const int i = ti0 + li;
                 fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = sx_;
                 fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = sy_;
                 fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = sz_;
             }
         }
         if (!diag) {
-            // tile J to slot I
-            for (int k = lane; k < wk.nj; k += 64) {
-                const int j = wk.j0 + k;
-                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = L.ax[k];
-                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = L.ay[k];
-                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = L.az[k];
+            // super-tile J's sums to slot I
+            for (int k = threadIdx.x; k < wk.nj; k += 64 * G) {
+                const SymTile64<T> &S = tl[k / T];
+                const int e = k % T, j = wk.j0 + k;
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = S.ax[e];
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = S.ay[e];
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = S.az[e];
             }
         }
-        wave_lds_sync();
+        __syncthreads();
     }
     for (int o = 32; o > 0; o >>= 1)
         near += __shfl_xor(near, o);
@@ -1641,8 +1661,8 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
     }
 }
 
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict__ work, int nitems,
+template <int R, int G>
+__global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const FWork *__restrict__ work, int nitems,
                                                          const float4 *__restrict__ pk,
                                                          const double *__restrict__ qx,
                                                          const double *__restrict__ qy,
@@ -1653,40 +1673,45 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
                                                          int maxs, double inner, DevStats *stats)
 {
     constexpr int T = 64 * R;
-    __shared__ SymTile32<T> tl[kWaves];
+    __shared__ SymTile32<T> tl[G];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    SymTile32<T> &L = tl[wv];
     const size_t plane = (size_t)maxs * ntot;
     int near = 0;
-    for (int it = blockIdx.x * kWaves + wv; it < nitems; it += gridDim.x * kWaves) {
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
         const FWork wk = work[it];
         const bool diag = wk.i0 == wk.j0;
-        for (int k = lane; k < T; k += 64) {
-            // sources past the tile end: massless and far away (r^2 ~ 1e36, so the
+        // the G source tiles of super-tile J (nj real records from j0)
+        for (int k = threadIdx.x; k < G * T; k += 64 * G) {
+            SymTile32<T> &S = tl[k / T];
+            const int e = k % T;
+            // sources past the end: massless and far away (r^2 ~ 1e36, so the
             // weight underflows to 0 instead of meeting a target at r = 0)
             if (k < wk.nj) {
-                L.a[k] = pk[2 * (size_t)(wk.j0 + k)];
-                L.b[k] = pk[2 * (size_t)(wk.j0 + k) + 1];
+                S.a[e] = pk[2 * (size_t)(wk.j0 + k)];
+                S.b[e] = pk[2 * (size_t)(wk.j0 + k) + 1];
             } else {
-                L.a[k] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
-                L.b[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                S.a[e] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+                S.b[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
-            L.run[k] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            L.ax[k] = L.ay[k] = L.az[k] = 0.0;
+            S.run[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            S.ax[e] = S.ay[e] = S.az[e] = 0.0;
         }
-        wave_lds_sync();
+        __syncthreads();
+        // this wave's target tile: tni bodies from ti0 (none when tni <= 0)
+        const int ti0 = wk.i0 + wv * T;
+        const int tni = min(T, wk.ni - wv * T);
         float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], mi[R];
         float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
         float tmi = 0.0f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int li = 64 * r + lane;
-            const bool ok = li < wk.ni;
-            const int i = wk.i0 + (ok ? li : 0);
+            const bool ok = li < tni;
+            const int i = ok ? ti0 + li : wk.i0;
             const float4 A = pk[2 * (size_t)i], B = pk[2 * (size_t)i + 1];
             xh[r] = A.x; yh[r] = A.y; zh[r] = A.z;
             xl[r] = B.x; yl[r] = B.y; zl[r] = B.z;
-            // targets past the tile end are massless: they add nothing to tile J
+            // targets past the tile end are massless: they add nothing to the sources
             mi[r] = ok ? A.w : 0.0f;
             tmi = max_nonneg(tmi, B.w);
             hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
@@ -1695,20 +1720,35 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
         // bit r: target r's split partial already holds FP64 changeover terms
         int rare = 0;
         double *fp = fpart + (size_t)wk.slot * ntot;
-        if (diag)
-            sym_tile32c<R, true, T>(L, lane, wk.i0, wk.ni, wk.j0, fp, plane, inner, pk, qx, qy, qz, m,
-                                    rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx, hy, hz, lx, ly, lz, rare,
-                                    near);
-        else
-            sym_tile32c<R, false, T>(L, lane, wk.i0, wk.ni, wk.j0, fp, plane, inner, pk, qx, qy, qz,
-                                     m, rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx, hy, hz, lx, ly, lz,
-                                     rare, near);
-        wave_lds_sync();
+        // Round k: wave w pairs its target tile with source tile (w + k) mod G, so
+        // that the waves of a round update distinct source tiles.  Off the
+        // diagonal G rounds cover the G x G tile pairs.  On the diagonal (I = J)
+        // round 0 takes the pairs inside each tile, rounds 1 .. G/2 - 1 every
+        // other tile pair once, and round G/2 (even G) only its first G/2 waves,
+        // whose partners the other half would meet again.
+        const int nr = diag ? G / 2 + 1 : G;
+        for (int k = 0; k < nr; ++k) {
+            const int s = (wv + k) % G;
+            const bool go = tni > 0 && s * T < wk.nj && !(diag && 2 * k == G && wv >= G / 2);
+            if (go) {
+                if (diag && k == 0)
+                    sym_tile32c<R, true, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, fp, plane, inner,
+                                            pk, qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi,
+                                            hx, hy, hz, lx, ly, lz, rare, near);
+                else
+                    sym_tile32c<R, false, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, fp, plane,
+                                             inner, pk, qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl,
+                                             mi, tmi, hx, hy, hz, lx, ly, lz, rare, near);
+            }
+            __syncthreads();
+        }
+        // super-tile I's sums to slot J (on the diagonal together with the same
+        // bodies' sums as sources)
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int li = 64 * r + lane;
-            if (li < wk.ni) {
-                const int i = wk.i0 + li;
+            if (li < tni) {
+                const int i = ti0 + li;
                 double sx_ = (double)hx[r] + (double)lx[r];
                 double sy_ = (double)hy[r] + (double)ly[r];
                 double sz_ = (double)hz[r] + (double)lz[r];
@@ -1718,9 +1758,9 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
                     sz_ += fp[2 * plane + i];
                 }
                 if (diag) {
-                    sx_ += L.ax[li];
-                    sy_ += L.ay[li];
-                    sz_ += L.az[li];
+                    sx_ += tl[wv].ax[li];
+                    sy_ += tl[wv].ay[li];
+                    sz_ += tl[wv].az[li];
                 }
                 fp[i] = sx_;
                 fp[plane + i] = sy_;
@@ -1728,14 +1768,16 @@ __global__ __launch_bounds__(kBlock) void k_force32c_sym(const FWork *__restrict
             }
         }
         if (!diag) {
-            for (int k = lane; k < wk.nj; k += 64) {
-                const int j = wk.j0 + k;
-                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = L.ax[k];
-                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = L.ay[k];
-                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = L.az[k];
+            // super-tile J's sums to slot I
+            for (int k = threadIdx.x; k < wk.nj; k += 64 * G) {
+                const SymTile32<T> &S = tl[k / T];
+                const int e = k % T, j = wk.j0 + k;
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = S.ax[e];
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = S.ay[e];
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = S.az[e];
             }
         }
-        wave_lds_sync();
+        __syncthreads();
     }
     for (int o = 32; o > 0; o >>= 1)
         near += __shfl_xor(near, o);
@@ -3339,26 +3381,37 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
     if (d.nfw == 0)
         return hipSuccess;
     if (d.force_sym) {
-        const int grid = std::min(cdiv(d.nfw, kWaves), 4096);
+        // one workgroup of G waves per super-tile pair
+        const int grid = std::min(d.nfw, 1 << 22);
 #define NB_SYM_ARGS d.fwork, d.nfw, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart, d.ntot, d.maxs, \
                     p.inner, d.stats
 #define NB_SYM32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart, d.ntot, \
                       d.maxs, p.inner, d.stats
-        if (p.mode == 1) {
-            if (p.force_r == 1)
-                k_force32c_sym<1><<<grid, kBlock, 0, s>>>(NB_SYM32_ARGS);
-            else if (p.force_r == 4)
-                k_force32c_sym<4><<<grid, kBlock, 0, s>>>(NB_SYM32_ARGS);
-            else
-                k_force32c_sym<2><<<grid, kBlock, 0, s>>>(NB_SYM32_ARGS);
-        } else {
-            if (p.force_r == 1)
-                k_force64_sym<1><<<grid, kBlock, 0, s>>>(NB_SYM_ARGS);
-            else if (p.force_r == 4)
-                k_force64_sym<4><<<grid, kBlock, 0, s>>>(NB_SYM_ARGS);
-            else
-                k_force64_sym<2><<<grid, kBlock, 0, s>>>(NB_SYM_ARGS);
-        }
+#define NB_SYM_G(R_)                                                                          \
+    do {                                                                                      \
+        if (p.mode == 1) {                                                                    \
+            if (d.sym_g == 4)                                                                 \
+                k_force32c_sym<R_, 4><<<grid, 256, 0, s>>>(NB_SYM32_ARGS);                    \
+            else if (d.sym_g == 2)                                                            \
+                k_force32c_sym<R_, 2><<<grid, 128, 0, s>>>(NB_SYM32_ARGS);                    \
+            else                                                                              \
+                k_force32c_sym<R_, 1><<<grid, 64, 0, s>>>(NB_SYM32_ARGS);                     \
+        } else {                                                                              \
+            if (d.sym_g == 4)                                                                 \
+                k_force64_sym<R_, 4><<<grid, 256, 0, s>>>(NB_SYM_ARGS);                       \
+            else if (d.sym_g == 2)                                                            \
+                k_force64_sym<R_, 2><<<grid, 128, 0, s>>>(NB_SYM_ARGS);                       \
+            else                                                                              \
+                k_force64_sym<R_, 1><<<grid, 64, 0, s>>>(NB_SYM_ARGS);                        \
+        }                                                                                     \
+    } while (0)
+        if (p.force_r == 1)
+            NB_SYM_G(1);
+        else if (p.force_r == 4)
+            NB_SYM_G(4);
+        else
+            NB_SYM_G(2);
+#undef NB_SYM_G
 #undef NB_SYM_ARGS
 #undef NB_SYM32_ARGS
         return hipGetLastError();

@@ -116,6 +116,7 @@ Params to_internal(const nb_params &q)
     p.enc_algo = q.enc_algo;
     p.step_algo = q.step_algo;
     p.force_algo = q.force_algo;
+    p.force_g = q.force_g;
     p.resolve = q.resolve;
     p.resolve_threads = q.resolve_threads;
     p.bs_tol = q.bs_tol > 0.0 ? q.bs_tol : 1e-12;
@@ -133,7 +134,7 @@ int resolver_threads(int requested)
 int next_pow2(int n);
 
 // Tuning table (written by the autotuner): one line per size class,
-//   <arch>/<fp64|fp32c>/n<N>/s<S>[/b<B>] force_algo force_r force_jchunk enc_algo enc_jchunk step_algo
+//   <arch>/<fp64|fp32c>/n<N>/s<S>[/b<B>] force_algo force_r force_jchunk enc_algo enc_jchunk step_algo [force_g]
 // with N the largest system and S the number of systems rounded up to powers of
 // two, and B (only when some bodies are small) the largest big-body count, also
 // rounded up; '#' starts a comment.  When every tile and algorithm field of the
@@ -145,7 +146,7 @@ int apply_tuning(const nb_params &u, int nsys, const int32_t *off, const int32_t
 {
     *tuned = false;
     if (!u.autotune_path || u.force_r || u.force_jchunk || u.enc_jchunk || u.enc_algo ||
-        u.step_algo || u.force_algo)
+        u.step_algo || u.force_algo || u.force_g)
         return NB_OK;
     FILE *f = std::fopen(u.autotune_path, "r");
     if (!f) {
@@ -174,17 +175,20 @@ int apply_tuning(const nb_params &u, int nsys, const int32_t *off, const int32_t
     if (small)
         key += "/b" + std::to_string(next_pow2(std::max(bmax, 1)));
     char line[512], k[256];
-    int fa, fr, fj, ea, ej, sa;
+    int fa, fr, fj, ea, ej, sa, fg;
     while (std::fgets(line, sizeof line, f)) {
         if (line[0] == '#')
             continue;
-        if (std::sscanf(line, "%255s %d %d %d %d %d %d", k, &fa, &fr, &fj, &ea, &ej, &sa) != 7 ||
-            key != k)
+        // the super-tile width (eighth field) may be absent: automatic
+        fg = 0;
+        const int nf = std::sscanf(line, "%255s %d %d %d %d %d %d %d", k, &fa, &fr, &fj, &ea, &ej, &sa, &fg);
+        if (nf < 7 || key != k)
             continue;
         if (fa < 0 || fa > 2 || (fr != 1 && fr != 2 && fr != 4) || fj <= 0 || ea < 0 || ea > 3 ||
-            ej <= 0 || sa < 0 || sa > 2)
+            ej <= 0 || sa < 0 || sa > 2 || (fg != 0 && fg != 1 && fg != 2 && fg != 4))
             break;     // a malformed entry is ignored
         q.force_algo = fa;
+        q.force_g = fg;
         q.force_r = fr;
         q.force_j = (fj + kBlock - 1) / kBlock * kBlock;
         q.enc_algo = ea;
@@ -198,19 +202,17 @@ int apply_tuning(const nb_params &u, int nsys, const int32_t *off, const int32_t
     return NB_OK;
 }
 
-// Step launch: explicit choice, else the persistent per-system launch for FP64
-// batches whose systems are all small enough and numerous (or tiny).
+// Step launch: the persistent per-system launch when asked for (or chosen by
+// the tuning table) and applicable, else one launch per phase.  It is not an
+// automatic choice: it won only for a single system of about 100 bodies, and it
+// keeps no drift arcs for nb_encounters / nb_events after a run.
 int choose_step_algo(const Params &p, int nsys, const int32_t *off)
 {
     int nmax = 0;
     for (int s = 0; s < nsys; ++s)
         nmax = std::max(nmax, off[s + 1] - off[s]);
     bool fits = nmax <= NB_PERSISTENT_MAX_N && p.mode == NB_FP64 && !p.resolve;
-    if (p.step_algo == 2)
-        return fits ? 2 : 1;
-    if (p.step_algo == 1)
-        return 1;
-    return fits && (nmax <= 2048 || nsys >= 64) ? 2 : 1;
+    return p.step_algo == 2 && fits ? 2 : 1;
 }
 
 // Encounter algorithm: explicit choice, else sorted tiles when bodies have
@@ -309,6 +311,7 @@ struct Tables {
     bool enc_few = false;
     bool force_few = false;
     bool force_sym = false;
+    int sym_g = 1;        // tiles per super-tile of the symmetric force
     // persistent step launch: systems largest first
     std::vector<PSys> psys;
 };
@@ -328,9 +331,12 @@ void pair_items(int a, int n, int nb, int J, std::vector<PWork> &out)
     }
 }
 
-// Split partials of the symmetric force: 3 doubles per body and tile of TI
-// bodies of its system (quadratic in the system size).
+// Split partials of the symmetric force: 3 doubles per body and super-tile of
+// TI bodies of its system (quadratic in the system size).
 constexpr long long kSymPartialMax = 4ll << 30;
+// Work items (super-tile pairs, one workgroup each) the automatic super-tile
+// width keeps at least: 8 workgroups per compute unit of the MI355X.
+constexpr long long kSymMinItems = 2048;
 // Most source chunks per system of the ordered force (its partials: 3 doubles
 // per body and chunk).
 constexpr int kMaxOrderedSplits = 64;
@@ -345,6 +351,29 @@ long long sym_partial_bytes(int nsys, const int32_t *off, int TI)
     return b;
 }
 
+long long sym_items(int nsys, const int32_t *off, int TI)
+{
+    long long c = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const long long nt = (off[s + 1] - off[s] + TI - 1) / TI;
+        c += nt * (nt + 1) / 2;
+    }
+    return c;
+}
+
+// Tiles per super-tile of the symmetric force: the one asked for, else the
+// widest of 4, 2 that still gives kSymMinItems work items, else 1.
+int sym_width(const Params &p, int nsys, const int32_t *off)
+{
+    if (p.force_g == 1 || p.force_g == 2 || p.force_g == 4)
+        return p.force_g;
+    const int T = 64 * p.force_r;
+    for (int g = 4; g > 1; g /= 2)
+        if (sym_items(nsys, off, g * T) >= kSymMinItems)
+            return g;
+    return 1;
+}
+
 void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *nbig, Tables &t)
 {
     t.enc_sorted = choose_enc_algo(p, nsys, off, nbig) == 2;
@@ -352,8 +381,10 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
     // symmetric tile pairs: every body big (asked for, or automatic while their
     // split partials, 3 doubles per body and tile of its system, stay within
     // kSymPartialMax; beyond that the ordered pairs' partials are bounded)
+    t.sym_g = sym_width(p, nsys, off);
     t.force_sym = p.force_algo != 1 && !has_small(nsys, off, nbig) &&
-                  (p.force_algo == 2 || sym_partial_bytes(nsys, off, 64 * p.force_r) <= kSymPartialMax);
+                  (p.force_algo == 2 ||
+                   sym_partial_bytes(nsys, off, t.sym_g * 64 * p.force_r) <= kSymPartialMax);
     t.rb_first.assign(nsys, 0);
     t.rb_count.assign(nsys, 0);
     t.nsplit.assign(nsys, 0);
@@ -374,16 +405,17 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
         // sources are the big bodies [a, a + nb) only (Sec. 2.1)
         const int nb = nbig ? nbig[s] : n;
         if (t.force_sym) {
-            // unordered tile pairs (I <= J) of TI bodies; tile I's sums go to slot J,
-            // tile J's to slot I (the item's pad field)
-            const int nt = (n + TI - 1) / TI;
+            // unordered pairs (I <= J) of super-tiles of ST bodies; super-tile I's
+            // sums go to slot J, super-tile J's to slot I (the item's pad field)
+            const int ST = t.sym_g * TI;
+            const int nt = (n + ST - 1) / ST;
             t.nsplit[s] = nt;
             t.maxs = std::max(t.maxs, nt);
             for (int I = 0; I < nt; ++I)
                 for (int J = I; J < nt; ++J)
-                    t.fwork.push_back(FWork{a + I * TI, std::min(TI, n - I * TI), a + J * TI,
-                                            std::min(TI, n - J * TI), J, s,
-                                            t.rb_first[s] + (J * TI) / kBlock, I});
+                    t.fwork.push_back(FWork{a + I * ST, std::min(ST, n - I * ST), a + J * ST,
+                                            std::min(ST, n - J * ST), J, s,
+                                            t.rb_first[s] + (J * ST) / kBlock, I});
         } else {
             // source chunks of J bodies, widened (whole O(N) blocks) so that a
             // system has at most kMaxOrderedSplits of them
@@ -554,6 +586,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.enc_few = t.enc_few ? 1 : 0;
     d.force_few = t.force_few ? 1 : 0;
     d.force_sym = t.force_sym ? 1 : 0;
+    d.sym_g = t.sym_g;
     if (d.enc_sorted) {
         d.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
         d.alt.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
@@ -1761,6 +1794,7 @@ int nb_get_params(const nb_ctx *c, nb_params *out, int32_t *tuned)
     out->resolve = p.resolve;
     out->resolve_threads = p.resolve_threads;
     out->force_algo = p.force_algo;
+    out->force_g = c->d.force_sym ? c->d.sym_g : p.force_g;
     out->bs_tol = p.bs_tol;
     out->autotune_path = nullptr;
     if (tuned)

@@ -50,6 +50,7 @@ class nb_params(ctypes.Structure):
         ("step_algo", ctypes.c_int32), ("resolve", ctypes.c_int32),
         ("resolve_threads", ctypes.c_int32), ("force_algo", ctypes.c_int32),
         ("bs_tol", ctypes.c_double), ("autotune_path", ctypes.c_char_p),
+        ("force_g", ctypes.c_int32),
     ]
 
 
@@ -363,11 +364,13 @@ class Context:
 
     def choices(self):
         """Resolved algorithms: force (1 ordered, 2 symmetric, 3 few sources),
-        encounter check (1 direct, 2 sorted), step launch (1 per phase, 2 persistent)."""
+        encounter check (1 direct, 2 sorted), step launch (1 per phase, 2 persistent),
+        and the symmetric force's super-tile width."""
         f, e, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         self._check(lib().nb_get_choices(self.ctx, ctypes.byref(f), ctypes.byref(e), ctypes.byref(st)),
                     "nb_get_choices")
-        return {"force_algo": f.value, "enc_algo": e.value, "step_algo": st.value}
+        return {"force_algo": f.value, "enc_algo": e.value, "step_algo": st.value,
+                "force_g": int(self.params.force_g)}
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -66,7 +66,8 @@ def _events_workload(nbig_small=True):
 
 
 def _ctx(w, mode):
-    p = nb.default_params(G=w.G, mode=mode)
+    # the per-phase step launch: the persistent one keeps no drift arcs for nb_events
+    p = nb.default_params(G=w.G, mode=mode, step_algo=1)
     c = nb.Context(w.off, p, enc_cap=1 << 12, device="cuda:0", nbig=w.nbig)
     c.upload(w.m0, w.m, w.x, w.v)
     return c
@@ -94,9 +95,13 @@ def test_events_and_compaction_match_oracle(mode, tol_a):
     assert lost[505] == 3 and lost[510] == 3
     x, v = c.download(nb.NB_DH)
     keep = lost == 0
-    # the kept bodies after the events (star shift, mergers, ejection dv)
-    assert rel_rows(x[keep], st.Q[keep]) <= 1e-13
-    assert rel_rows(v[keep], st.V[keep]) <= 1e-13
+    # the kept bodies after the events (star shift, mergers, ejection dv); one
+    # step carries the force's error through two half kicks and the drift
+    # (FP32C: far pairs in FP32, <= 1e-6 of A_i; changeover pairs in FP64;
+    # measured 3e-13 relative)
+    tol1 = 1e-13 if mode == 0 else 1e-10
+    assert rel_rows(x[keep], st.Q[keep]) <= tol1
+    assert rel_rows(v[keep], st.V[keep]) <= tol1
     # compaction
     idx = c.compact()
     new, idx_ref = st.compacted()
@@ -104,7 +109,7 @@ def test_events_and_compaction_match_oracle(mode, tol_a):
     assert np.array_equal(c.off, new.off.astype(np.int32))
     assert np.array_equal(c.nbig, new.nbig.astype(np.int32))
     x, v = c.download(nb.NB_DH)
-    assert rel_rows(x, new.Q) <= 1e-13 and rel_rows(v, new.V) <= 1e-13
+    assert rel_rows(x, new.Q) <= tol1 and rel_rows(v, new.V) <= tol1
     a = c.accel()
     for s, (lo, hi) in enumerate(new.systems()):
         A = pair_scale(new.m[lo:hi], new.Q[lo:hi], G)

@@ -78,6 +78,30 @@ def test_force_fp32c(case, r, jchunk, force_algo):
     assert worst <= 1e-6, (name, worst)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("r", [1, 2, 4])
+@pytest.mark.parametrize("g", [1, 2, 4])
+def test_force_super_tiles(case, mode, r, g):
+    """Symmetric force with super-tiles of g tiles of 64 r bodies (one
+    workgroup of g waves per super-tile pair, rotating over the source tiles):
+    ragged super-tiles with empty tiles, diagonal super-tiles, every width and
+    tile size, both precisions."""
+    name, w, (Q, V, rc, a_ref) = case
+    c = ctx_for(w, mode=mode, force_r=r, force_algo=2, force_g=g)
+    ch = c.choices()
+    assert ch["force_algo"] == 2 and ch["force_g"] == g, ch
+    a = c.accel()
+    assert np.all(np.isfinite(a)), name
+    bar = 1e-12 if mode == 0 else 1e-6
+    for s, lo, hi in systems(w):
+        if hi - lo < 2:
+            assert np.all(a[lo:hi] == 0.0)
+            continue
+        A = pair_scale(w.m[lo:hi], Q[lo:hi], w.G)
+        err = accel_error(a[lo:hi], a_ref[lo:hi], A)
+        assert err <= bar, (name, s, mode, r, g, err)
+
+
 # ---------------------------------------------------------------- O(N) phases
 def test_transforms_kick_sun_drift(case):
     name, w, (Q, V, rc, a_ref) = case
