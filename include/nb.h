@@ -356,6 +356,33 @@ int nb_get_choices(const nb_ctx *ctx, int32_t *force_algo, int32_t *enc_algo, in
  * *tuned (may be NULL) = 1 if they came from the tuning table. */
 int nb_get_params(const nb_ctx *ctx, nb_params *out, int32_t *tuned);
 
+/* Force evaluation without a context, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The same computation as nb_upload (frame NB_DH) followed
+ * by nb_force and nb_get_accel on a context with the same parameters, for one
+ * system: critical radii rc_i = n_hill |x_i| (m_i/(3 m0))^(1/3), then
+ * a_i = G sum_j m_j w(r_ij; rc_ij) (x_j - x_i) by the symmetric force kernels
+ * (every body big), equal bit for bit to that context's result.
+ *   p: G, n_hill, chg_inner, mode, force_r (0, 1, 2, 4), force_g (0, 1, 2, 4) and
+ *      force_algo (0 or 2) are used; the other fields are ignored.
+ *   n: bodies, 0 <= n <= NB_NOALLOC_MAX_N.  m0: the star's mass (> 0).
+ *   m[n], x[3n] (plane-major DH positions), a[3n] (output, plane-major, G
+ *      included): device pointers owned by the caller; m and x are only read.
+ *   stream: hipStream_t (NULL: the null stream); the call only enqueues work.
+ * Nothing is allocated: the work tables, critical radii, source records and
+ * partial sums live in a static device array of NB_NOALLOC_SCRATCH_MB MiB that
+ * every GPU the library runs on holds until the process ends.  Every call on a
+ * GPU uses that GPU's one array, so calls that overlap on one GPU (other streams,
+ * other host threads) race; successive calls on one stream are ordered.  Inputs
+ * are not checked for finite values.  Returns NB_E_WORKSPACE when n exceeds
+ * NB_NOALLOC_MAX_N or the layout for the asked force_r / force_g does not fit the
+ * array (the automatic widths fit up to NB_NOALLOC_MAX_N), NB_E_INVALID for other
+ * bad arguments, NB_E_HIP if a launch fails. */
+#define NB_NOALLOC_MAX_N 16384
+#define NB_NOALLOC_SCRATCH_MB 32
+int nb_force_noalloc(const nb_params *p, int n, double m0, const double *m, const double *x,
+                     double *a, void *stream);
+
 /* Release the context (not the workspace). */
 int nb_destroy(nb_ctx *ctx);
 

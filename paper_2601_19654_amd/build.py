@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libnbody.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("nb_kernels.hip", "nb_runtime.hip", "nb_resolve.cpp")]
+SOURCES = [os.path.join(CSRC, f) for f in ("nb_kernels.hip", "nb_runtime.hip", "nb_noalloc.hip",
+                                            "nb_resolve.cpp")]
 HEADERS = [os.path.join(ROOT, "include", "nb.h"), os.path.join(CSRC, "nb_internal.h"),
            os.path.join(CSRC, "nb_resolve.h")]
 ARCH = "gfx950"

@@ -219,6 +219,9 @@ hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, 
 hipError_t launch_drift(const Dev &d, const Params &p, double dt, double sun_h,
                         const double *part_in, hipStream_t s);
 hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s);
+// tables of a single system of d.ntot bodies (O(N) blocks, m0, super-tile pairs of
+// ST bodies, nt super-tiles) and a cleared statistics block, written on the device
+hipError_t launch_single_tables(const Dev &d, int ST, int nt, double m0, hipStream_t s);
 // a from the split partials; kick_h != 0: then `kicks` kicks V += kick_h a (and the
 // sums of m V after them into rpart)
 hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, int kicks,

@@ -3264,6 +3264,43 @@ hipError_t launch_scatter_members(const Dev &d, int k, hipStream_t s)
     return hipGetLastError();
 }
 
+// Tables of one system of n bodies for a force evaluation without a context:
+// the O(N) blocks, the star's mass and the symmetric force's super-tile pairs
+// (I <= J of nt super-tiles of ST bodies, row I's items from I nt - I (I - 1) / 2,
+// in the layout the context's tables use; the order of the items does not
+// change the sums, which the finalize takes in slot order).  Also clears the
+// statistics block.
+__global__ void k_single_tables(int n, int ST, int nt, double m0v, RBlk *__restrict__ rblk, int nrb,
+                                double *__restrict__ m0, FWork *__restrict__ fw,
+                                DevStats *__restrict__ stats)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < nrb)
+        rblk[t] = RBlk{0, t * kBlock, min(n, (t + 1) * kBlock), 0};
+    if (t == 0) {
+        m0[0] = m0v;
+        *stats = DevStats{};
+    }
+    if (t < nt * nt) {
+        const int I = t / nt, J = t % nt;
+        if (J >= I) {
+            const int at = I * nt - I * (I - 1) / 2 + (J - I);
+            fw[at] = FWork{I * ST, min(ST, n - I * ST), J * ST, min(ST, n - J * ST), J, 0,
+                           (J * ST) / kBlock, I};
+        }
+    }
+}
+
+hipError_t launch_single_tables(const Dev &d, int ST, int nt, double m0v, hipStream_t s)
+{
+    const int total = std::max(d.nrb, nt * nt);
+    if (total <= 0)
+        return hipSuccess;
+    k_single_tables<<<cdiv(total, kBlock), kBlock, 0, s>>>(d.ntot, ST, nt, m0v, d.rblk, d.nrb, d.m0,
+                                                           d.fwork, d.stats);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_i32(int *p, int n, int value, hipStream_t s)
 {
     if (n <= 0)

@@ -117,6 +117,7 @@ SIGNATURES = {
     "nb_destroy": (_I, [_P]),
     "nb_events": (_I, [_P, _P, _P, _P, _I]),
     "nb_compact": (_I, [_P, _P, _P, _P, _I]),
+    "nb_force_noalloc": (_I, [_P, _I, _D, _P, _P, _P, _P]),
 }
 
 
@@ -137,6 +138,27 @@ def lib():
             f.argtypes = args
         _lib = L
     return _lib
+
+
+NOALLOC_MAX_N = 16384     # include/nb.h: NB_NOALLOC_MAX_N
+
+
+def force_noalloc(params: nb_params, n: int, m0: float, m, x, a, stream=None, check=True) -> int:
+    """nb_force_noalloc on device tensors m[n], x[3, n], a[3, n] (float64,
+    contiguous) on the current device; enqueued on `stream` (a torch stream, or
+    torch's current stream).  Returns the status (raises on an error when check)."""
+    import torch
+    for t in (m, x, a):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("force_noalloc takes contiguous float64 device tensors")
+    if m.numel() < n or x.numel() < 3 * n or a.numel() < 3 * n:
+        raise ValueError("force_noalloc: arrays shorter than n")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    code = lib().nb_force_noalloc(ctypes.byref(params), int(n), float(m0), _addr(m), _addr(x), _addr(a),
+                                  ctypes.c_void_p(s.cuda_stream))
+    if check and code != NB_OK:
+        raise NbError(code, "nb_force_noalloc")
+    return code
 
 
 def strerror(code: int) -> str:
