@@ -96,7 +96,12 @@ typedef struct nb_params {
     int32_t enc_algo;     /* encounter check: 0 automatic, 1 every pair through a per-pair
                              reach filter, 2 spatially sorted tiles with tile-pair culling,
                              3 every body against the big bodies of its system (at most 256
-                             big bodies per system; automatic when some bodies are small) */
+                             big bodies per system; automatic when some bodies are small),
+                             4 in nb_step the check of 2 done inside the force pass, which
+                             then runs over the sorted order (Sec. 3.1 force and encounter
+                             blocks in one tile loop; FP32C, every body big, resolve 0 and
+                             the symmetric force, else 2; nb_encounters and nb_force run as
+                             with 2) */
     int32_t step_algo;    /* nb_step: 0 automatic (the tuning table's choice, else 1), 1 one
                              launch per phase over all systems (HIP graph), 2 one persistent
                              launch in which a workgroup owns a system for many steps (FP64
@@ -120,9 +125,10 @@ typedef struct nb_params {
                              class the table lacks keeps the defaults.  An unreadable
                              file is NB_E_INVALID.  Read during the call only. */
     int32_t force_g;      /* symmetric force: tiles of 64 force_r bodies per super-tile, 1, 2
-                             or 4 (0: automatic, the widest that still gives 2048 work
-                             items).  A body receives one partial sum per super-tile of
-                             its system, so wider super-tiles write fewer partials. */
+                             or 4 (0: automatic, 4 when that gives at least 8192 work items,
+                             else 2 when that gives 2048, else 1).  A body receives one
+                             partial sum per super-tile of its system, so wider super-tiles
+                             write fewer partials. */
 } nb_params;
 
 /* largest system the persistent step launch accepts */
@@ -183,16 +189,22 @@ const char *nb_last_error(const nb_ctx *ctx);
 int nb_upload(nb_ctx *ctx, const double *m0, const double *m, const double *x,
               const double *v, int frame, int where);
 
-/* Copy the state out: x, v plane-major [3*ntot] in frame NB_HELIO or NB_DH. */
+/* Copy the state out: x, v plane-major [3*ntot] in frame NB_HELIO or NB_DH (the
+ * DH -> heliocentric change v = V + P/m0 of Sec. 2.1.1's coordinate footnote;
+ * the paper copies x and v back to the host every step, Sec. 3.2). */
 int nb_download(nb_ctx *ctx, double *x, double *v, int frame, int where);
 
-/* Recompute critical radii and the interaction acceleration a at the current Q. */
+/* Recompute critical radii (Sec. 2.1.1, Hill-radius footnotes) and the interaction
+ * acceleration a at the current Q (Sec. 3.1, force block loop 2: the
+ * changeover-weighted pair sum of the header's formula). */
 int nb_force(nb_ctx *ctx);
 
-/* Interaction kick with the current a: V += h a (plus drag if enabled). */
+/* Interaction kick with the current a: V += h a (Sec. 3.1, Hamiltonian block loop
+ * 1), plus the gas drag of force block loop 5 if enabled. */
 int nb_kick(nb_ctx *ctx, double h);
 
-/* Stellar-motion drift: Q += h P / m0 per system. */
+/* Stellar-motion drift: Q += h P / m0 per system, P = sum m V (Sec. 3.1,
+ * Hamiltonian block loops 2-3). */
 int nb_sun_drift(nb_ctx *ctx, double h);
 
 /* Snapshot (Q0,V0) <- (Q,V), then Kepler-drift every body for dt (dt may be
@@ -323,7 +335,8 @@ int nb_compact(nb_ctx *ctx, int32_t *off_out, int32_t *nbig_out, int32_t *index,
  * Any pointer may be NULL.  Returns NB_E_NONFINITE if a value is not finite. */
 int nb_diagnostics(nb_ctx *ctx, double *E, double *EK, double *L, double *P);
 
-/* Copy the last interaction acceleration a (G included, drag excluded), plane-major. */
+/* Copy the last interaction acceleration a (G included, drag excluded), plane-major
+ * (the force block's output, Sec. 3.1 loop 2). */
 int nb_get_accel(nb_ctx *ctx, double *a, int where);
 
 /* Copy the current critical radii rc[ntot]. */
@@ -336,6 +349,9 @@ int nb_get_rcrit(nb_ctx *ctx, double *rc, int where);
 #define NB_K_STEP       3   /* whole hybrid steps, enqueued the way nb_step runs them */
 #define NB_K_FORCE_EVAL 4   /* one whole force evaluation: critical radii and source
                                records, the force kernel and the sum of its splits */
+#define NB_K_FORCE_FUSED 5  /* enc_algo 4: the force pass with the encounter test in it,
+                               on the sorted order of the last per-phase step (its list
+                               is made again once after the timed launches) */
 
 /* Measurement helper: enqueue kernel `which` alone `reps` times on the context's
  * stream between two HIP events (after one untimed launch) and return the mean
@@ -346,8 +362,8 @@ int nb_time_kernel(nb_ctx *ctx, int which, int reps, double dt, double *ms_per_l
 
 /* The algorithms the context resolved its automatic choices to (any pointer may
  * be NULL): force 1 (ordered pairs), 2 (symmetric tile pairs) or 3 (few-source
- * kernels); encounter check 1 (direct), 2 (sorted tiles) or 3 (big bodies only as
- * partners); step launch 1
+ * kernels); encounter check 1 (direct), 2 (sorted tiles), 3 (big bodies only as
+ * partners) or 4 (sorted tiles inside the force pass); step launch 1
  * (per phase) or 2 (persistent). */
 int nb_get_choices(const nb_ctx *ctx, int32_t *force_algo, int32_t *enc_algo, int32_t *step_algo);
 

@@ -146,6 +146,25 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
                       f"{res_near[k]:.4f} ms", file=sys.stderr, flush=True)
         fa, r, j, g = min(res_near.items(), key=lambda kv: kv[1])[0]
         fms = res_force[(fa, r, j, g)]
+    # the encounter test inside the force pass (FP32C, every body big, symmetric
+    # force): only a whole step compares it with the separate check
+    if mode == "fp32c" and all_big and fa == 2 and ea == 2:
+        base = res_near.get((fa, r, j, g)) or step_ms(fa, r, j, g, 1)
+        p4 = nb.default_params(G=w.G, mode=_mode_id(mode), drag=int(w.drag), force_r=r, force_jchunk=j,
+                               force_algo=fa, force_g=g, enc_jchunk=ej or 1024, enc_algo=4, step_algo=1)
+        c = nb.Context(w.off, p4, enc_cap=1 << 18, device="cuda:0", tuned=False, nbig=w.nbig)
+        c.upload(w.m0, w.m, w.x, w.v)
+        c.step(w.dt, 3, allow=(nb.NB_E_CAPACITY, nb.NB_E_KEPLER))
+        fused = c.time_kernel(nb.NB_K_STEP, reps=max(2, reps // 2), dt=w.dt)
+        c.close()
+        res_enc[(4, 0)] = fused
+        if verbose:
+            print(f"[autotune] {mode} step with the check in the force pass: {fused:.4f} ms "
+                  f"(separate: {base:.4f} ms)", file=sys.stderr, flush=True)
+        # the step time of the chosen check (the per-phase launch's entry below)
+        res_near[(fa, r, j, g)] = min(base, fused)
+        if fused < base:
+            ea = 4
     # whole-step launch: per-phase launches (tuned tiles) vs the persistent launch
     res_step = {}
     for sa in ((1, 2) if mode == "fp64" and int(np.diff(w.off).max()) <= 8192 else (1,)):

@@ -9,6 +9,10 @@ namespace nb {
 
 constexpr int kBlock = 256;      // threads of every O(N) kernel and of the pair kernels
 
+// Work items the automatic super-tile width g of the symmetric force needs (one
+// workgroup of g waves per item): 2048 for g = 2, 8192 for g = 4.
+constexpr long long kSymMinItems(int g) { return g >= 4 ? 8192 : 2048; }
+
 // A block of an O(N) kernel: bodies [start, end) of one system (end - start <= kBlock).
 struct RBlk {
     int sys, start, end, pad;
@@ -141,6 +145,11 @@ struct Dev {
     TileB *tileb;         // ntile
     int2 *tpairs; int tp_cap;
     int2 *units; int nunit;   // culling units: tile A against tiles [b0, b0 + 64) (B >= A)
+    int *tile_first;      // nsys: first tile of every system
+    // force and encounter check in one pass over the sorted order (FP32C,
+    // every body big): per sorted position an FP32 midpoint and widened reach
+    int enc_fused;
+    float4 *em;
     // persistent step launch
     PSys *psys; int npsys; int pmax_n;
     int *step_nce; int step_chunk;   // flagged pairs per step of one launch
@@ -224,8 +233,10 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s);
 hipError_t launch_single_tables(const Dev &d, int ST, int nt, double m0, hipStream_t s);
 // a from the split partials; kick_h != 0: then `kicks` kicks V += kick_h a (and the
 // sums of m V after them into rpart)
+// ord: partials by sorted position (the fused pass); enc_count: also the
+// statistics of the encounter list the fused pass wrote
 hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, int kicks,
-                                 hipStream_t s);
+                                 hipStream_t s, const int *ord = nullptr, bool enc_count = false);
 hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s);
 hipError_t launch_diagnostics(const Dev &d, const Params &p, hipStream_t s);
 // star impacts, collisions among the listed pairs, ejections (r_eject > 0) of
@@ -239,6 +250,12 @@ hipError_t launch_persistent_steps(const Dev &d, const Params &p, double dt, int
 hipError_t launch_step_stats(const Dev &d, int nsteps, hipStream_t s);
 hipError_t launch_enc_sort(const Dev &d, int accumulate, hipStream_t s);
 hipError_t launch_enc_gather(const Dev &d, hipStream_t s);
+// fused mode, before the force: an empty list and no flags, the sorted order
+// and records of the last drift, and the tile bounds
+hipError_t launch_enc_prepare(const Dev &d, double dt, hipStream_t s);
+// fused mode: the force and the encounter test in one pass, then (count != 0) the
+// list's count
+hipError_t launch_force_fused(const Dev &d, const Params &p, double dt, int count, hipStream_t s);
 hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s);
 // resolver transfers: both ends of listed pairs [k0, k0 + n) -> res_buf (per end
 // m0, m, rc, Q0, V0, index); res_rows (index, Q, V; rows not finite skipped) -> state

@@ -1501,16 +1501,17 @@ static_assert(offsetof(SymTile32<128>, b) == 16 * 128 && offsetof(SymTile32<128>
               "SymTile32 layout");
 
 // The rare branch of the FP32C pair loop, out of line so that it adds nothing
-// to the loop: target li of the item (body i0 + li, or a padded copy of body i0
-// when li >= ni) against source jj (body j0 + jj, found from the LDS addresses
-// of its record, ja, and of the tile's first record, a0) at FP32 squared
-// distance r2.
+// to the loop: target li of the item (position i0 + li, or a padded copy of
+// position i0 when li >= ni) against source jj (position j0 + jj, found from the
+// LDS addresses of its record, ja, and of the tile's first record, a0) at FP32
+// squared distance r2.  Positions are body indices, or with a sorted order
+// (ord != nullptr) the bodies ord[position].
 // Unless r2 is inside the pair's widened critical radius it returns false.
 // Otherwise the pair is evaluated in FP64 from the FP64 state: m_j w (Q_j - Q_i)
 // goes to the target's split partial at fp[i], fp[plane + i], fp[2 plane + i]
-// (stored when `first`, else added; nothing for a padded target) and
-// -m_i w (Q_j - Q_i) to source jj's FP64 totals tot[jj], tot[T + jj],
-// tot[2 T + jj]; it returns true.
+// (i its position; stored when `first`, else added; nothing for a padded
+// target) and -m_i w (Q_j - Q_i) to source jj's FP64 totals tot[jj],
+// tot[T + jj], tot[2 T + jj]; it returns true.
 __device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4 *__restrict__ pk,
                                                int i0, int li, int ni, int j0, uint32_t ja,
                                                uint32_t a0, int T,
@@ -1519,19 +1520,21 @@ __device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4
                                                const double *__restrict__ qy,
                                                const double *__restrict__ qz,
                                                const double *__restrict__ m,
-                                               const double *__restrict__ rc, double inner)
+                                               const double *__restrict__ rc, double inner,
+                                               const int *__restrict__ ord)
 {
     const bool ok = li < ni;
     const int i = i0 + (ok ? li : 0);
-    if (!(r2 < max_nonneg(pk[2 * (size_t)i + 1].w, r2j)))
+    const int bi = ord ? ord[i] : i;
+    if (!(r2 < max_nonneg(pk[2 * (size_t)bi + 1].w, r2j)))
         return false;
     const int jj = (int)((ja - a0) >> 4);
-    const int j = j0 + jj;
-    const double gx = qx[j] - qx[i], gy = qy[j] - qy[i], gz = qz[j] - qz[i];
+    const int bj = ord ? ord[j0 + jj] : j0 + jj;
+    const double gx = qx[bj] - qx[bi], gy = qy[bj] - qy[bi], gz = qz[bj] - qz[bi];
     const double d2 = fma(gz, gz, fma(gy, gy, gx * gx));
-    const double w = changeover_w_inl(d2, fmax(rc[i], rc[j]), inner);
+    const double w = changeover_w_inl(d2, fmax(rc[bi], rc[bj]), inner);
     if (ok) {
-        const double wi = m[j] * w;
+        const double wi = m[bj] * w;
         if (first) {
             fp[i] = wi * gx;
             fp[plane + i] = wi * gy;
@@ -1541,7 +1544,7 @@ __device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4
             fp[plane + i] = fma(wi, gy, fp[plane + i]);
             fp[2 * plane + i] = fma(wi, gz, fp[2 * plane + i]);
         }
-        const double wj = m[i] * w;
+        const double wj = m[bi] * w;
         tot[jj] = fma(-wj, gx, tot[jj]);
         tot[T + jj] = fma(-wj, gy, tot[T + jj]);
         tot[2 * T + jj] = fma(-wj, gz, tot[2 * T + jj]);
@@ -1549,7 +1552,48 @@ __device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4
     return true;
 }
 
-template <int R, bool DIAG, int T>
+// What the FP32C pair loop needs for the encounter test fused into it (sorted
+// order): the sorted records, the step, and the list and flags to append to.
+struct EncCtx {
+    const SRec *srec;
+    double dt;
+    unsigned long long *keys;
+    int cap;
+    int *ce;
+    DevStats *stats;
+};
+
+// Relative-chord filter and exact encounter test of two sorted positions, with
+// the append of a flagged pair (defined with the encounter check).
+__device__ __noinline__ void enc_candidate(const SRec *__restrict__ srec, double dt,
+                                           unsigned long long *keys, int cap, int *ce,
+                                           DevStats *stats, int pi, int pj);
+
+// The tile of 64 R sources with, after the FP32C fields, each source's
+// encounter record: chord midpoint M and reach R widened for FP32 (x, y, z, R').
+// The FP32C tile is a member, not a base: a base's tail padding may hold the
+// derived members, while a member object keeps its whole size, so em[] starts
+// exactly sizeof(SymTile32<T>) bytes after the tile's first record.
+template <int T>
+struct alignas(1024) SymTile32E {
+    SymTile32<T> t;
+    float4 em[T];
+};
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winvalid-offsetof"
+static_assert(offsetof(SymTile32E<64>, em) == sizeof(SymTile32<64>) &&
+                  offsetof(SymTile32E<128>, em) == sizeof(SymTile32<128>) &&
+                  offsetof(SymTile32E<256>, em) == sizeof(SymTile32<256>),
+              "SymTile32E: em[] right after the FP32C tile");
+#pragma clang diagnostic pop
+
+// ENC: the encounter test fused in (sorted order).  Target r of sub-tile t is
+// tested against the sources when bit t R + r of `live` is set (the tile pair
+// survived the culling): its FP32 midpoint distance against the widened reaches
+// (emi[r] and the source's em), and the pairs that pass go to the exact test.
+// The source records are read from the LDS tile at a fixed offset past the
+// FP32C fields (em of SymTile32E).
+template <int R, bool DIAG, int T, bool ENC = false>
 __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, int ni, int j0,
                                             double *fp, size_t plane, double inner,
                                             const float4 *__restrict__ pk,
@@ -1563,13 +1607,17 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                                             const float (&zl)[R], const float (&mi)[R], float tmi,
                                             float (&hx)[R], float (&hy)[R], float (&hz)[R],
                                             float (&lx)[R], float (&ly)[R], float (&lz)[R],
-                                            int &rare, int &near)
+                                            int &rare, int &near, const int *__restrict__ ord,
+                                            const EncCtx &ec, const float4 (&emi)[R],
+                                            unsigned live)
 {
 #pragma unroll 1
     for (int t = 0; t < R; ++t) {
         // the largest widened rc^2 of the wave's targets and of the sub-tile's
         // sources: one compare per pair outside the rare branch
         const float thr = max_nonneg(tmi, wave_max_nonneg(L.b[64 * t + lane].w));
+        // targets of this wave that meet sub-tile t in a tile pair the culling kept
+        const unsigned livet = ENC ? (live >> (t * R)) & ((1u << R) - 1u) : 0u;
 #pragma unroll 1
         for (int half = 0; half < 2; ++half) {
             float tx[R], ty[R], tz[R];
@@ -1611,18 +1659,38 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                     if (DIAG)
                         qr[r] = on ? qr[r] : 0.0f;
                 }
-                if (cand) {
+                // fused encounter test: midpoint distance against the summed
+                // reaches, in FP32 (padded targets and sources carry NaN
+                // midpoints and never pass)
+                bool encr[R] = {};
+                bool ecand = false;
+                if (ENC && livet) {
+                    const float4 E = lds_ld4(ac + (uint32_t)sizeof(SymTile32<T>));
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float ex = E.x - emi[r].x, ey = E.y - emi[r].y, ez = E.z - emi[r].z;
+                        const float D2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                        const float Sr = E.w + emi[r].w;
+                        const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
+                        encr[r] = ((livet >> r) & 1u) && on && D2 <= Sr * Sr;
+                        ecand |= encr[r];
+                    }
+                }
+                if (cand || ecand) {
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
                         if (r2r[r] < thr && on &&
                             changeover_pair32(r2r[r], B.w, pk, i0, 64 * r + lane, ni, j0, ac, a0, T,
                                               L.ax, fp, plane, !((rare >> r) & 1), qx, qy, qz, m,
-                                              rc, inner)) {
+                                              rc, inner, ord)) {
                             rare |= 1 << r;
                             qr[r] = 0.0f;
                             ++near;
                         }
+                        if (ENC && encr[r])
+                            enc_candidate(ec.srec, ec.dt, ec.keys, ec.cap, ec.ce, ec.stats,
+                                          i0 + 64 * r + lane, j0 + (int)((ac - a0) >> 4));
                     }
                 }
 #pragma unroll
@@ -1720,6 +1788,8 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
         // bit r: target r's split partial already holds FP64 changeover terms
         int rare = 0;
         double *fp = fpart + (size_t)wk.slot * ntot;
+        const EncCtx noenc{};
+        float4 noem[R];
         // Round k: wave w pairs its target tile with source tile (w + k) mod G, so
         // that the waves of a round update distinct source tiles.  Off the
         // diagonal G rounds cover the G x G tile pairs.  On the diagonal (I = J)
@@ -1734,11 +1804,13 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
                 if (diag && k == 0)
                     sym_tile32c<R, true, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, fp, plane, inner,
                                             pk, qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi,
-                                            hx, hy, hz, lx, ly, lz, rare, near);
+                                            hx, hy, hz, lx, ly, lz, rare, near, nullptr, noenc,
+                                            noem, 0u);
                 else
                     sym_tile32c<R, false, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, fp, plane,
                                              inner, pk, qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl,
-                                             mi, tmi, hx, hy, hz, lx, ly, lz, rare, near);
+                                             mi, tmi, hx, hy, hz, lx, ly, lz, rare, near, nullptr,
+                                             noenc, noem, 0u);
             }
             __syncthreads();
         }
@@ -1800,19 +1872,31 @@ __global__ __launch_bounds__(kFinThreads) void k_force_finalize(
     const int *__restrict__ sys_of, const int *__restrict__ nsplit, const double *__restrict__ fpart,
     int ntot, int maxs, int ns_all, int nsl, double G, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double h, int kicks, double *vx, double *vy,
-    double *vz)
+    double *vz, const int *__restrict__ ord, int count_cap, DevStats *stats)
 {
     __shared__ double gs[3 * kFinThreads];
+    // count_cap >= 0: also the encounter list's statistics (as k_enc_count), for
+    // the check that ran inside the force pass before this launch
+    if (count_cap >= 0 && blockIdx.x == 0 && threadIdx.x == 0) {
+        const int count = stats->cur_nce;
+        stats->total_nce += count;
+        if (count > stats->max_nce)
+            stats->max_nce = count;
+        if (count > count_cap)
+            stats->overflow_steps += 1;
+    }
     const int B = kFinThreads / nsl;
     const int t = threadIdx.x % B, g = threadIdx.x / B;
+    // i: the partials' position; bi: the body (the sorted order maps them)
     const int i = blockIdx.x * B + t;
+    const int bi = ord && i < ntot ? ord[i] : i;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
     // the velocities to kick, fetched while the partials load
     double v0 = 0.0, v1 = 0.0, v2 = 0.0;
     if (g == 0 && i < ntot && h != 0.0) {
-        v0 = vx[i];
-        v1 = vy[i];
-        v2 = vz[i];
+        v0 = vx[bi];
+        v1 = vy[bi];
+        v2 = vz[bi];
     }
     if (i < ntot) {
         // ns_all != 0: every system has that split count
@@ -1858,9 +1942,9 @@ __global__ __launch_bounds__(kFinThreads) void k_force_finalize(
         s0 *= G;
         s1 *= G;
         s2 *= G;
-        ax[i] = s0;
-        ay[i] = s1;
-        az[i] = s2;
+        ax[bi] = s0;
+        ay[bi] = s1;
+        az[bi] = s2;
         if (h != 0.0) {
             double u0 = fma(h, s0, v0), u1 = fma(h, s1, v1), u2 = fma(h, s2, v2);
             if (kicks == 2) {
@@ -1868,9 +1952,9 @@ __global__ __launch_bounds__(kFinThreads) void k_force_finalize(
                 u1 = fma(h, s1, u1);
                 u2 = fma(h, s2, u2);
             }
-            vx[i] = u0;
-            vy[i] = u1;
-            vz[i] = u2;
+            vx[bi] = u0;
+            vy[bi] = u1;
+            vz[bi] = u2;
         }
     }
 }
@@ -2170,9 +2254,9 @@ __global__ __launch_bounds__(kBlock) void k_encounter_few(const RBlk *__restrict
 //   Lmin = D - sm_A - sm_B - Cm/2,  Qmax = D + sm_A + sm_B + Cm/2,
 //   D = |cm_B - cm_A|, Cm = |cc_B - cc_A| + sc_A + sc_B, Em = |ce_B - ce_A| + se_A + se_B,
 // so a tile pair whose bound exceeds max rc^2 holds no flagged pair.  Surviving
-// tile pairs are tested pair by pair exactly as in k_encounter.  The sort order
-// inside a cell depends on atomic timing; the flagged set does not (the pair
-// test is symmetric bit for bit), and the output list is sorted.
+// tile pairs are tested pair by pair exactly as in k_encounter.  The bodies of
+// a cell are put in index order after the binning, so the sorted order does
+// not depend on the timing of its atomics; the output list is sorted.
 // ----------------------------------------------------------------------------
 __device__ __forceinline__ unsigned morton2(unsigned band, int nb, unsigned pb, int np)
 {
@@ -2191,7 +2275,7 @@ __global__ void k_cells(const RBlk *__restrict__ rblk, const int *__restrict__ r
                         const int *__restrict__ rb_count, const double *__restrict__ lnr_part,
                         const int *__restrict__ sys_cell_base, const int *__restrict__ sys_cell_cnt,
                         const double4 *__restrict__ mr, int *__restrict__ cell_cnt,
-                        int *__restrict__ cell_of, int *__restrict__ slot_of)
+                        int *__restrict__ cell_of, int *__restrict__ slot_of, int *__restrict__ ce)
 {
     __shared__ double sh[2 * kBlock];
     const RBlk b = rblk[blockIdx.x];
@@ -2236,6 +2320,8 @@ __global__ void k_cells(const RBlk *__restrict__ rblk, const int *__restrict__ r
         int cell = sys_cell_base[b.sys] + (int)morton2(band, lb, pb, lp);
         cell_of[i] = cell;
         slot_of[i] = atomicAdd(&cell_cnt[cell], 1);
+        // no encounter flag yet (the check of this drift sets them)
+        ce[i] = 0;
     }
 }
 
@@ -2316,8 +2402,10 @@ __global__ __launch_bounds__(kScanThreads) void k_cell_scan(int *__restrict__ ce
     int carry = 0;
     for (int base = 0; base < ncell; base += kScanChunk)
         carry += scan_chunk(cell_cnt, cell_off, base, ncell, carry, sh);
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
         stats->cur_tp = 0;
+        stats->cur_nce = 0;
+    }
 }
 
 // Block b: sum of the counts of chunk b.
@@ -2347,29 +2435,76 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ c
     int tot;
     (void)block_exscan(pre, sh, tot);
     (void)scan_chunk(cell_cnt, cell_off, blockIdx.x * kScanChunk, ncell, tot, sh);
-    if (blockIdx.x == 0 && threadIdx.x == 0)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         stats->cur_tp = 0;
+        stats->cur_nce = 0;
+    }
 }
 
+// Sorted position of every body: its cell's offset plus the slot the binning
+// took (the order inside a cell follows the atomics' timing until
+// k_cell_order puts it in index order).
 __global__ void k_scatter(const RBlk *__restrict__ rblk, const int *__restrict__ cell_of,
                           const int *__restrict__ slot_of, const int *__restrict__ cell_off,
-                          const double *__restrict__ q0x, const double *__restrict__ q0y,
-                          const double *__restrict__ q0z, const double *__restrict__ v0x,
-                          const double *__restrict__ v0y, const double *__restrict__ v0z,
-                          const double *__restrict__ qx, const double *__restrict__ qy,
-                          const double *__restrict__ qz, const double *__restrict__ vx,
-                          const double *__restrict__ vy, const double *__restrict__ vz,
-                          const double *__restrict__ rc, const double4 *__restrict__ mr,
-                          const double4 *__restrict__ cr, const int *__restrict__ off,
-                          const int *__restrict__ nbig, int *__restrict__ ord,
-                          SRec *__restrict__ srec)
+                          int *__restrict__ ord)
 {
     const RBlk b = rblk[blockIdx.x];
     const int i = b.start + threadIdx.x;
     if (i >= b.end)
         return;
-    const int pos = cell_off[cell_of[i]] + slot_of[i];
-    ord[pos] = i;
+    ord[cell_off[cell_of[i]] + slot_of[i]] = i;
+}
+
+// The bodies of every cell in index order, so that the sorted order, its tiles
+// and the tile pairs are the same from run to run.  One wave per cell: a body's
+// new slot is the number of smaller indices in its cell.  A cell of more than
+// kCellSortMax bodies keeps the binning's order (its set is still right).
+constexpr int kCellSortMax = 512;
+
+__global__ __launch_bounds__(kBlock) void k_cell_order(const int *__restrict__ cell_off, int ncell,
+                                                       int ntot, int *__restrict__ ord)
+{
+    __shared__ int sb[kBlock / 64][kCellSortMax];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int c = blockIdx.x * (kBlock / 64) + wv;
+    int start = 0, k = 0;
+    if (c < ncell) {
+        start = cell_off[c];
+        k = (c + 1 < ncell ? cell_off[c + 1] : ntot) - start;
+    }
+    const bool go = k > 1 && k <= kCellSortMax;
+    if (go)
+        for (int e = lane; e < k; e += 64)
+            sb[wv][e] = ord[start + e];
+    __syncthreads();
+    if (go)
+        for (int e = lane; e < k; e += 64) {
+            const int me = sb[wv][e];
+            int rank = 0;
+            for (int q = 0; q < k; ++q)
+                rank += sb[wv][q] < me;
+            ord[start + rank] = me;
+        }
+}
+
+// The sorted records, position by position, from the drift outputs.
+__global__ void k_srec(int ntot, const int *__restrict__ ord, const int *__restrict__ sys_of,
+                       const double *__restrict__ q0x, const double *__restrict__ q0y,
+                       const double *__restrict__ q0z, const double *__restrict__ v0x,
+                       const double *__restrict__ v0y, const double *__restrict__ v0z,
+                       const double *__restrict__ qx, const double *__restrict__ qy,
+                       const double *__restrict__ qz, const double *__restrict__ vx,
+                       const double *__restrict__ vy, const double *__restrict__ vz,
+                       const double *__restrict__ rc, const double4 *__restrict__ mr,
+                       const double4 *__restrict__ cr, const int *__restrict__ off,
+                       const int *__restrict__ nbig, SRec *__restrict__ srec,
+                       float4 *__restrict__ em)
+{
+    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+    if (pos >= ntot)
+        return;
+    const int i = ord[pos];
+    const int sy = sys_of[i];
     SRec r;
     r.q0[0] = q0x[i]; r.q0[1] = q0y[i]; r.q0[2] = q0z[i];
     r.v0[0] = v0x[i]; r.v0[1] = v0y[i]; r.v0[2] = v0z[i];
@@ -2377,13 +2512,20 @@ __global__ void k_scatter(const RBlk *__restrict__ rblk, const int *__restrict__
     r.v1[0] = vx[i];  r.v1[1] = vy[i];  r.v1[2] = vz[i];
     r.rc = rc[i];
     r.body = i;
-    r.big = (i - off[b.sys]) < nbig[b.sys] ? 1 : 0;
+    r.big = (i - off[sy]) < nbig[sy] ? 1 : 0;
     const double4 M = mr[i], C = cr[i];
     r.M[0] = M.x; r.M[1] = M.y; r.M[2] = M.z;
     r.c[0] = C.x; r.c[1] = C.y; r.c[2] = C.z;
     r.e34 = C.w;
     r.pad = 0.0;
     srec[pos] = r;
+    if (em) {
+        // FP32 midpoint and reach for the fused test: the reach widened by
+        // 2^-21 |M|_1 for the FP32 rounding of the midpoints and their
+        // differences, and by 2^-18 relative for that of the distance and sums
+        const double w = (M.w + 0x1p-21 * (fabs(M.x) + fabs(M.y) + fabs(M.z))) * (1.0 + 0x1p-18);
+        em[pos] = make_float4((float)M.x, (float)M.y, (float)M.z, (float)w);
+    }
 }
 
 // Chord midpoint M, chord c, mean deviation eb and deviation radius se of one record.
@@ -2631,6 +2773,194 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
             }
         }
     }
+}
+
+// ----------------------------------------------------------------------------
+// Force and encounter check in one pass over spatially sorted tiles (FP32C,
+// every body big).  The symmetric force runs over super-tile pairs of sorted
+// positions (sources and targets gathered through the sorted order, split
+// partials by position, mapped back to bodies by the finalize).  In every
+// round the wave bounds the tile pairs of its target sub-tiles and the source
+// sub-tiles with the culling lemma of the sorted check (may_meet on the tiles
+// of 64); where a tile pair may hold a flagged pair, each pair of it also gets
+// the FP32 midpoint-reach filter, and the pairs it passes the relative-chord
+// filter and the exact Hermite test in FP64 from the sorted records.  Each
+// unordered pair is met once, so each flagged pair is appended once.
+// ----------------------------------------------------------------------------
+__device__ __noinline__ void enc_candidate(const SRec *__restrict__ srec, double dt,
+                                           unsigned long long *keys, int cap, int *ce,
+                                           DevStats *stats, int pi, int pj)
+{
+    const SRec &I = srec[pi];
+    const SRec &J = srec[pj];
+    // relative chord filter (see k_encounter)
+    const double mx = J.M[0] - I.M[0], my = J.M[1] - I.M[1], mz = J.M[2] - I.M[2];
+    const double cx = J.c[0] - I.c[0], cy = J.c[1] - I.c[1], cz = J.c[2] - I.c[2];
+    const double D2 = fma(mz, mz, fma(my, my, mx * mx));
+    const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
+    const double bb = J.e34 + I.e34 + fmax(J.rc, I.rc);
+    if (!(D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20)))
+        return;
+    const double t2 = 2.0 * dt, k427 = 4.0 / 27.0;
+    const double d0x = J.q0[0] - I.q0[0], d0y = J.q0[1] - I.q0[1], d0z = J.q0[2] - I.q0[2];
+    const double d1x = J.q1[0] - I.q1[0], d1y = J.q1[1] - I.q1[1], d1z = J.q1[2] - I.q1[2];
+    const double e0x = J.v0[0] - I.v0[0], e0y = J.v0[1] - I.v0[1], e0z = J.v0[2] - I.v0[2];
+    const double e1x = J.v1[0] - I.v1[0], e1y = J.v1[1] - I.v1[1], e1z = J.v1[2] - I.v1[2];
+    const double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
+    const double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
+    const double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
+    const double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
+    const double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
+    const double rcij = fmax(I.rc, J.rc);
+    const double thr = rcij * rcij;
+    if (!(lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1))))
+        return;
+    if (!(hermite_min(f0, f1, g0, g1) <= thr))
+        return;
+    const int pos = atomicAdd(&stats->cur_nce, 1);
+    const int bi = I.body, bj = J.body;
+    const unsigned lo = (unsigned)min(bi, bj), hi = (unsigned)max(bi, bj);
+    if (pos < cap)
+        keys[pos] = ((unsigned long long)lo << 32) | hi;
+    __hip_atomic_store(&ce[bi], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ce[bj], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Tile of 64 sorted positions holding position p of system sy.
+__device__ __forceinline__ int tile_of(const int *__restrict__ tile_first, const int *__restrict__ off,
+                                       int sy, int p)
+{
+    return tile_first[sy] + (p - off[sy]) / 64;
+}
+
+template <int R, int G>
+__global__ __launch_bounds__(64 * G, R == 4 ? 1 : 2) void k_force32c_fused(
+    const FWork *__restrict__ work, int nitems, const int *__restrict__ ord,
+    const float4 *__restrict__ pk, const float4 *__restrict__ em, const TileB *__restrict__ tileb,
+    const int *__restrict__ tile_first, const int *__restrict__ off, const double *__restrict__ qx,
+    const double *__restrict__ qy, const double *__restrict__ qz, const double *__restrict__ m,
+    const double *__restrict__ rc, double *__restrict__ fpart, int ntot, int maxs, double inner,
+    EncCtx ec)
+{
+    constexpr int T = 64 * R;
+    __shared__ SymTile32E<T> tl[G];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const size_t plane = (size_t)maxs * ntot;
+    const float qnan = __int_as_float(0x7fc00000);
+    int near = 0;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const FWork wk = work[it];
+        const bool diag = wk.i0 == wk.j0;
+        // the G source tiles of super-tile J, gathered through the sorted order
+        for (int k = threadIdx.x; k < G * T; k += 64 * G) {
+            SymTile32<T> &S = tl[k / T].t;
+            const int e = k % T;
+            if (k < wk.nj) {
+                const int b = ord[wk.j0 + k];
+                S.a[e] = pk[2 * (size_t)b];
+                S.b[e] = pk[2 * (size_t)b + 1];
+                tl[k / T].em[e] = em[wk.j0 + k];
+            } else {
+                S.a[e] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
+                S.b[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                tl[k / T].em[e] = make_float4(qnan, qnan, qnan, 0.0f);
+            }
+            S.run[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            S.ax[e] = S.ay[e] = S.az[e] = 0.0;
+        }
+        __syncthreads();
+        const int ti0 = wk.i0 + wv * T;
+        const int tni = min(T, wk.ni - wv * T);
+        float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], mi[R];
+        float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
+        float4 emi[R];
+        float tmi = 0.0f;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int li = 64 * r + lane;
+            const bool ok = li < tni;
+            const int b = ord[ok ? ti0 + li : wk.i0];
+            const float4 A = pk[2 * (size_t)b], B = pk[2 * (size_t)b + 1];
+            xh[r] = A.x; yh[r] = A.y; zh[r] = A.z;
+            xl[r] = B.x; yl[r] = B.y; zl[r] = B.z;
+            mi[r] = ok ? A.w : 0.0f;
+            tmi = max_nonneg(tmi, B.w);
+            emi[r] = ok ? em[ti0 + li] : make_float4(qnan, qnan, qnan, 0.0f);
+            hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
+        }
+        tmi = wave_max_nonneg(tmi);
+        int rare = 0;
+        double *fp = fpart + (size_t)wk.slot * ntot;
+        const int nr = diag ? G / 2 + 1 : G;
+        for (int k = 0; k < nr; ++k) {
+            const int s = (wv + k) % G;
+            const bool go = tni > 0 && s * T < wk.nj && !(diag && 2 * k == G && wv >= G / 2);
+            if (go) {
+                // tile pairs (target sub-tile r, source sub-tile t) that may hold
+                // a flagged pair: bit t R + r
+                const int sj0 = wk.j0 + s * T, snj = min(T, wk.nj - s * T);
+                unsigned live = 0u;
+                for (int r = 0; r < R; ++r) {
+                    if (64 * r >= tni)
+                        continue;
+                    const TileB A = tileb[tile_of(tile_first, off, wk.sys, ti0 + 64 * r)];
+                    for (int t = 0; t < R; ++t)
+                        if (64 * t < snj &&
+                            may_meet(A.cm, A.sm, A.cc, A.sc, A.ce, A.se, A.rc,
+                                     tileb[tile_of(tile_first, off, wk.sys, sj0 + 64 * t)]))
+                            live |= 1u << (t * R + r);
+                }
+                if (diag && k == 0)
+                    sym_tile32c<R, true, T, true>(tl[s].t, lane, ti0, tni, sj0, fp, plane, inner, pk,
+                                                  qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi,
+                                                  tmi, hx, hy, hz, lx, ly, lz, rare, near, ord, ec,
+                                                  emi, live);
+                else
+                    sym_tile32c<R, false, T, true>(tl[s].t, lane, ti0, tni, sj0, fp, plane, inner, pk,
+                                                   qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi,
+                                                   tmi, hx, hy, hz, lx, ly, lz, rare, near, ord, ec,
+                                                   emi, live);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int li = 64 * r + lane;
+            if (li < tni) {
+                const int i = ti0 + li;
+                double sx_ = (double)hx[r] + (double)lx[r];
+                double sy_ = (double)hy[r] + (double)ly[r];
+                double sz_ = (double)hz[r] + (double)lz[r];
+                if ((rare >> r) & 1) {
+                    sx_ += fp[i];
+                    sy_ += fp[plane + i];
+                    sz_ += fp[2 * plane + i];
+                }
+                if (diag) {
+                    sx_ += tl[wv].t.ax[li];
+                    sy_ += tl[wv].t.ay[li];
+                    sz_ += tl[wv].t.az[li];
+                }
+                fp[i] = sx_;
+                fp[plane + i] = sy_;
+                fp[2 * plane + i] = sz_;
+            }
+        }
+        if (!diag) {
+            for (int k = threadIdx.x; k < wk.nj; k += 64 * G) {
+                const SymTile32<T> &S = tl[k / T].t;
+                const int e = k % T, j = wk.j0 + k;
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = S.ax[e];
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = S.ay[e];
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = S.az[e];
+            }
+        }
+        __syncthreads();
+    }
+    for (int o = 32; o > 0; o >>= 1)
+        near += __shfl_xor(near, o);
+    if (lane == 0 && near)
+        atomicAdd((unsigned long long *)&ec.stats->near_pairs, (unsigned long long)near);
 }
 
 // ----------------------------------------------------------------------------
@@ -3515,7 +3845,7 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
 }
 
 hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, int kicks,
-                                 hipStream_t s)
+                                 hipStream_t s, const int *ord, bool enc_count)
 {
     if (d.ntot == 0)
         return hipSuccess;
@@ -3525,7 +3855,7 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, i
         nsl *= 2;
     k_force_finalize<<<cdiv(d.ntot, kFinThreads / nsl), kFinThreads, 0, s>>>(
         d.sys_of, d.nsplit, d.fpart, d.ntot, d.maxs, d.ns_all, nsl, p.G, d.ax, d.ay, d.az, kick_h,
-        kicks, d.vx, d.vy, d.vz);
+        kicks, d.vx, d.vy, d.vz, ord, enc_count ? d.enc_cap : -1, d.stats);
     return hipGetLastError();
 }
 
@@ -3539,7 +3869,7 @@ hipError_t launch_enc_gather(const Dev &d, hipStream_t s)
     if (d.enc_sorted && d.nrb > 0) {
         k_cells<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.lnr_part,
                                           d.sys_cell_base, d.sys_cell_cnt, d.mr, d.cell_cnt,
-                                          d.cell_of, d.slot_of);
+                                          d.cell_of, d.slot_of, d.ce);
         const int nchunk = cdiv(d.ncell, kScanChunk);
         if (nchunk <= kScanSerialChunks) {
             k_cell_scan<<<1, kScanThreads, 0, s>>>(d.cell_cnt, d.cell_off, d.ncell, d.stats);
@@ -3548,10 +3878,12 @@ hipError_t launch_enc_gather(const Dev &d, hipStream_t s)
             k_scan_apply<<<nchunk, kScanThreads, 0, s>>>(d.cell_cnt, d.cell_off, d.ncell,
                                                          d.scan_part, d.stats);
         }
-        k_scatter<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.cell_of, d.slot_of, d.cell_off, d.q0x,
-                                            d.q0y, d.q0z, d.v0x, d.v0y, d.v0z, d.q1x, d.q1y, d.q1z,
-                                            d.v1x, d.v1y, d.v1z, d.rc1, d.mr, d.cr, d.off, d.nbig,
-                                            d.ord, d.srec);
+        k_scatter<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.cell_of, d.slot_of, d.cell_off, d.ord);
+        k_cell_order<<<cdiv(d.ncell, kBlock / 64), kBlock, 0, s>>>(d.cell_off, d.ncell, d.ntot, d.ord);
+        k_srec<<<cdiv(d.ntot, kBlock), kBlock, 0, s>>>(d.ntot, d.ord, d.sys_of, d.q0x, d.q0y, d.q0z,
+                                                       d.v0x, d.v0y, d.v0z, d.q1x, d.q1y, d.q1z,
+                                                       d.v1x, d.v1y, d.v1z, d.rc1, d.mr, d.cr, d.off,
+                                                       d.nbig, d.srec, d.enc_fused ? d.em : nullptr);
     }
     return hipGetLastError();
 }
@@ -3580,6 +3912,46 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
                                                d.v1z, d.rc1, d.keys, d.enc_cap, d.ce, d.stats);
     }
     k_enc_count<<<1, 64, 0, s>>>(d.enc_cap, d.stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_enc_prepare(const Dev &d, double dt, hipStream_t s)
+{
+    // the binning clears the flags, the cell scan the list count
+    hipError_t e = launch_enc_gather(d, s);
+    if (e == hipSuccess && d.ntile > 0)
+        k_tile_bounds<<<cdiv(d.ntile, kBlock / 64), kBlock, 0, s>>>(d.tiles, d.ntile, d.srec, dt,
+                                                                     d.tileb);
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_force_fused(const Dev &d, const Params &p, double dt, int count, hipStream_t s)
+{
+    if (d.nfw > 0) {
+        const int grid = std::min(d.nfw, 1 << 22);
+        const EncCtx ec{d.srec, dt, d.keys, d.enc_cap, d.ce, d.stats};
+#define NB_FUSED_ARGS d.fwork, d.nfw, d.ord, d.pk, d.em, d.tileb, d.tile_first, d.off, d.qx, d.qy, \
+                      d.qz, d.m, d.rc, d.fpart, d.ntot, d.maxs, p.inner, ec
+#define NB_FUSED_G(R_)                                                                        \
+    do {                                                                                      \
+        if (d.sym_g == 4)                                                                     \
+            k_force32c_fused<R_, 4><<<grid, 256, 0, s>>>(NB_FUSED_ARGS);                      \
+        else if (d.sym_g == 2)                                                                \
+            k_force32c_fused<R_, 2><<<grid, 128, 0, s>>>(NB_FUSED_ARGS);                      \
+        else                                                                                  \
+            k_force32c_fused<R_, 1><<<grid, 64, 0, s>>>(NB_FUSED_ARGS);                       \
+    } while (0)
+        if (p.force_r == 1)
+            NB_FUSED_G(1);
+        else if (p.force_r == 4)
+            NB_FUSED_G(4);
+        else
+            NB_FUSED_G(2);
+#undef NB_FUSED_G
+#undef NB_FUSED_ARGS
+    }
+    if (count)
+        k_enc_count<<<1, 64, 0, s>>>(d.enc_cap, d.stats);
     return hipGetLastError();
 }
 

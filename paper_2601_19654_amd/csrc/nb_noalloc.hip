@@ -73,14 +73,14 @@ int nb_force_noalloc(const nb_params *p, int n, double m0, const double *m, cons
     q.mode = p->mode;
     q.force_r = p->force_r ? p->force_r : 2;
     q.force_algo = 2;
-    // super-tile width: asked for, or the widest that still gives 2048 work items
+    // super-tile width: asked for, or chosen as nb_create chooses it
     const int T = 64 * q.force_r;
     int g = p->force_g;
     if (!g) {
         g = 1;
         for (int w = 4; w > 1 && g == 1; w /= 2) {
             const long long nt = (n + (long long)w * T - 1) / ((long long)w * T);
-            if (nt * (nt + 1) / 2 >= 2048)
+            if (nt * (nt + 1) / 2 >= kSymMinItems(w))
                 g = w;
         }
     }

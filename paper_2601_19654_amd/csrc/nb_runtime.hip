@@ -184,7 +184,7 @@ int apply_tuning(const nb_params &u, int nsys, const int32_t *off, const int32_t
         const int nf = std::sscanf(line, "%255s %d %d %d %d %d %d %d", k, &fa, &fr, &fj, &ea, &ej, &sa, &fg);
         if (nf < 7 || key != k)
             continue;
-        if (fa < 0 || fa > 2 || (fr != 1 && fr != 2 && fr != 4) || fj <= 0 || ea < 0 || ea > 3 ||
+        if (fa < 0 || fa > 2 || (fr != 1 && fr != 2 && fr != 4) || fj <= 0 || ea < 0 || ea > 4 ||
             ej <= 0 || sa < 0 || sa > 2 || (fg != 0 && fg != 1 && fg != 2 && fg != 4))
             break;     // a malformed entry is ignored
         q.force_algo = fa;
@@ -230,6 +230,10 @@ int max_big(int nsys, const int32_t *off, const int32_t *nbig)
 
 int choose_enc_algo(const Params &p, int nsys, const int32_t *off, const int32_t *nbig)
 {
+    // 4: the sorted check fused into the symmetric force pass, where it applies
+    // (FP32C, every body big, the hot-path mode); else the sorted check alone
+    if (p.enc_algo == 4)
+        return p.mode == NB_FP32C && !p.resolve && !has_small(nsys, off, nbig) ? 4 : 2;
     if (p.enc_algo >= 1 && p.enc_algo <= 3)
         return p.enc_algo;
     // small bodies and at most kBlock big bodies per system: every body against
@@ -256,7 +260,7 @@ int check_params(const nb_params *p)
         return NB_E_INVALID;
     if (p->force_r != 0 && p->force_r != 1 && p->force_r != 2 && p->force_r != 4)
         return NB_E_INVALID;
-    if (p->force_jchunk < 0 || p->enc_jchunk < 0 || p->enc_algo < 0 || p->enc_algo > 3 ||
+    if (p->force_jchunk < 0 || p->enc_jchunk < 0 || p->enc_algo < 0 || p->enc_algo > 4 ||
         p->step_algo < 0 || p->step_algo > 2)
         return NB_E_INVALID;
     if ((p->resolve != 0 && p->resolve != 1) || p->resolve_threads < 0 || p->force_algo < 0 ||
@@ -309,6 +313,8 @@ struct Tables {
     std::vector<int2> units;    // sorted check: (tile A, first of 64 tiles B >= A) culling units
     bool enc_sorted = false;
     bool enc_few = false;
+    bool enc_fused = false;   // sorted check inside the symmetric force pass
+    std::vector<int> tile_first;
     bool force_few = false;
     bool force_sym = false;
     int sym_g = 1;        // tiles per super-tile of the symmetric force
@@ -334,9 +340,7 @@ void pair_items(int a, int n, int nb, int J, std::vector<PWork> &out)
 // Split partials of the symmetric force: 3 doubles per body and super-tile of
 // TI bodies of its system (quadratic in the system size).
 constexpr long long kSymPartialMax = 4ll << 30;
-// Work items (super-tile pairs, one workgroup each) the automatic super-tile
-// width keeps at least: 8 workgroups per compute unit of the MI355X.
-constexpr long long kSymMinItems = 2048;
+
 // Most source chunks per system of the ordered force (its partials: 3 doubles
 // per body and chunk).
 constexpr int kMaxOrderedSplits = 64;
@@ -362,22 +366,27 @@ long long sym_items(int nsys, const int32_t *off, int TI)
 }
 
 // Tiles per super-tile of the symmetric force: the one asked for, else the
-// widest of 4, 2 that still gives kSymMinItems work items, else 1.
+// widest whose work items (super-tile pairs, one workgroup each) reach
+// kSymMinItems(g): measured, a width of 2 pays from about 8 workgroups per
+// compute unit (16384 bodies) and one of 4 from about 32 (131072 bodies, where
+// it also beats 2; not at 256 systems of 200-4000 bodies).
 int sym_width(const Params &p, int nsys, const int32_t *off)
 {
     if (p.force_g == 1 || p.force_g == 2 || p.force_g == 4)
         return p.force_g;
     const int T = 64 * p.force_r;
     for (int g = 4; g > 1; g /= 2)
-        if (sym_items(nsys, off, g * T) >= kSymMinItems)
+        if (sym_items(nsys, off, g * T) >= kSymMinItems(g))
             return g;
     return 1;
 }
 
 void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *nbig, Tables &t)
 {
-    t.enc_sorted = choose_enc_algo(p, nsys, off, nbig) == 2;
-    t.enc_few = choose_enc_algo(p, nsys, off, nbig) == 3;
+    const int ea = choose_enc_algo(p, nsys, off, nbig);
+    t.enc_sorted = ea == 2 || ea == 4;
+    t.enc_few = ea == 3;
+    t.enc_fused = ea == 4;
     // symmetric tile pairs: every body big (asked for, or automatic while their
     // split partials, 3 doubles per body and tile of its system, stay within
     // kSymPartialMax; beyond that the ordered pairs' partials are bounded)
@@ -385,6 +394,8 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
     t.force_sym = p.force_algo != 1 && !has_small(nsys, off, nbig) &&
                   (p.force_algo == 2 ||
                    sym_partial_bytes(nsys, off, t.sym_g * 64 * p.force_r) <= kSymPartialMax);
+    // the fused pass is the symmetric force's: without it, the sorted check alone
+    t.enc_fused = t.enc_fused && t.force_sym;
     t.rb_first.assign(nsys, 0);
     t.rb_count.assign(nsys, 0);
     t.nsplit.assign(nsys, 0);
@@ -459,6 +470,7 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
         t.cell_cnt[s] = c;
         t.ncell += c;
         int first = (int)t.tiles.size();
+        t.tile_first.push_back(first);
         int nt = (n + 63) / 64;
         for (int k = 0; k < nt; ++k)
             t.tiles.push_back(Tile{s, off[s] + 64 * k, std::min(64, n - 64 * k), first + nt - 1});
@@ -607,7 +619,10 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
         d.tpairs = (int2 *)take((size_t)d.tp_cap * sizeof(int2));
         d.nunit = (int)t.units.size();
         d.units = (int2 *)take(t.units.size() * sizeof(int2));
+        d.tile_first = (int *)take((size_t)nsys * sizeof(int));
     }
+    d.enc_fused = t.enc_fused ? 1 : 0;
+    d.em = t.enc_fused ? (float4 *)take((size_t)ntot * sizeof(float4)) : nullptr;
     d.flag = (int *)take(4 * sizeof(int));
     d.stage = (double *)take((size_t)7 * nd);
     d.lost = (int *)take((size_t)ntot * sizeof(int));
@@ -687,7 +702,11 @@ int enqueue_step_head(nb_ctx *c, double dt, bool first)
     if (first)
         HIP_OK(c, launch_kick(d, c->p, h, c->stream));
     HIP_OK(c, launch_drift(d, c->p, dt, h, merged_kicks(c) ? d.rpart_prev() : d.rpart, c->stream));
-    HIP_OK(c, launch_encounters(d, dt, c->stream));
+    // fused: the sorted order and tile bounds now, the pair test inside the force pass
+    if (d.enc_fused)
+        HIP_OK(c, launch_enc_prepare(d, dt, c->stream));
+    else
+        HIP_OK(c, launch_encounters(d, dt, c->stream));
     c->snap = 0;
     return NB_OK;
 }
@@ -699,12 +718,19 @@ int enqueue_step_tail(nb_ctx *c, double dt, bool last)
     const Dev &d = c->d;
     HIP_OK(c, launch_sun_drift(d, h, 1, c->p, d.rpart_drift(),
                                merged_kicks(c) ? d.rpart_prev() : nullptr, c->stream));
-    HIP_OK(c, launch_force(d, c->p, c->stream));
+    // fused: the force over the sorted order with the encounter test in it; its
+    // partials are by sorted position, which the finalize maps back to bodies
+    const bool fz = d.enc_fused;
+    const int *ord = fz ? d.ord : nullptr;
+    if (fz)
+        HIP_OK(c, launch_force_fused(d, c->p, dt, 0, c->stream));
+    else
+        HIP_OK(c, launch_force(d, c->p, c->stream));
     if (c->p.drag) {
-        HIP_OK(c, launch_force_finalize(d, c->p, 0.0, 1, c->stream));
+        HIP_OK(c, launch_force_finalize(d, c->p, 0.0, 1, c->stream, ord, fz));
         HIP_OK(c, launch_kick(d, c->p, h, c->stream));
     } else {
-        HIP_OK(c, launch_force_finalize(d, c->p, h, last ? 1 : 2, c->stream));
+        HIP_OK(c, launch_force_finalize(d, c->p, h, last ? 1 : 2, c->stream, ord, fz));
     }
     return NB_OK;
 }
@@ -723,7 +749,7 @@ int enqueue_run(nb_ctx *c, double dt, int steps)
     for (int k = 0; k < steps; ++k) {
         const bool first = k == 0 || !merge, last = k == steps - 1 || !merge;
         int r;
-        if (!c->side) {
+        if (!c->side || c->d.enc_fused) {
             if ((r = enqueue_step_head(c, dt, first)) || (r = enqueue_step_tail(c, dt, last)))
                 return r;
             continue;
@@ -743,7 +769,7 @@ int enqueue_run(nb_ctx *c, double dt, int steps)
         HIP_OK(c, hipEventRecord(c->ev_join[par], c->side));
         c->snap = par;
     }
-    if (c->side && steps > 0)
+    if (c->side && !c->d.enc_fused && steps > 0)
         HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join[(steps - 1) & 1], 0));
     return NB_OK;
 }
@@ -1065,6 +1091,7 @@ int setup_layout(nb_ctx *c, int nsys, const int32_t *off, const int32_t *nbig)
         up(c->d.sys_cell_cnt, t.cell_cnt.data(), nsys * sizeof(int));
         up(c->d.tiles, t.tiles.data(), t.tiles.size() * sizeof(Tile));
         up(c->d.units, t.units.data(), t.units.size() * sizeof(int2));
+        up(c->d.tile_first, t.tile_first.data(), nsys * sizeof(int));
         if (r == NB_OK && launch_fill_i32(c->d.cell_cnt, c->d.ncell, 0, c->stream) != hipSuccess)
             r = set_err(c, NB_E_HIP, "clearing the cell counts failed");
     }
@@ -1507,8 +1534,12 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
         return r;
     if (!c->have_state)
         return set_err(c, NB_E_NOT_READY, "nb_time_kernel: no state");
-    if (!ms || reps <= 0 || which < NB_K_FORCE || which > NB_K_FORCE_EVAL || !std::isfinite(dt))
+    if (!ms || reps <= 0 || which < NB_K_FORCE || which > NB_K_FORCE_FUSED || !std::isfinite(dt))
         return set_err(c, NB_E_INVALID, "nb_time_kernel: bad argument");
+    if (which == NB_K_FORCE_FUSED && !(c->d.enc_fused && c->snap_valid && c->have_enc))
+        return set_err(c, NB_E_NOT_READY,
+                       "nb_time_kernel: the fused force pass needs enc_algo 4 and a per-phase "
+                       "step before it");
     if (which == NB_K_ENCOUNTER && !c->snap_valid)
         return set_err(c, NB_E_NOT_READY,
                        "nb_time_kernel: no drift outputs for the encounter check (no drift or "
@@ -1530,6 +1561,10 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
             return NB_OK;
         case NB_K_FORCE_EVAL:
             return enqueue_force(c);
+        case NB_K_FORCE_FUSED:
+            // the force pass alone (its appends run past the list's count)
+            HIP_OK(c, launch_force_fused(c->d, c->p, c->last_dt, 0, c->stream));
+            return NB_OK;
         default:
             // the runs the timed call replays, captured here, outside the timed
             // region (one untimed step)
@@ -1573,6 +1608,13 @@ int nb_time_kernel(nb_ctx *c, int which, int reps, double dt, double *ms)
     if (he != hipSuccess)
         return set_err(c, NB_E_HIP, "timing events: %s", hipGetErrorString(he));
     *ms = (double)t / reps;
+    if (which == NB_K_FORCE_FUSED) {
+        // the last step's list again, from an empty one
+        HIP_OK(c, launch_enc_prepare(c->d, c->last_dt, c->stream));
+        HIP_OK(c, launch_force_fused(c->d, c->p, c->last_dt, 1, c->stream));
+        if ((r = sync(c)))
+            return r;
+    }
     if (which == NB_K_DRIFT) {
         c->mom_valid = false;
         c->have_drift = true;
@@ -1765,7 +1807,7 @@ int nb_get_choices(const nb_ctx *c, int32_t *force_algo, int32_t *enc_algo, int3
     if (force_algo)
         *force_algo = c->d.force_sym ? 2 : (c->d.force_few ? 3 : 1);
     if (enc_algo)
-        *enc_algo = c->d.enc_sorted ? 2 : (c->d.enc_few ? 3 : 1);
+        *enc_algo = c->d.enc_fused ? 4 : (c->d.enc_sorted ? 2 : (c->d.enc_few ? 3 : 1));
     if (step_algo)
         *step_algo = c->p.step_algo;
     return NB_OK;

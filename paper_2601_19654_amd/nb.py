@@ -37,6 +37,7 @@ NB_K_ENCOUNTER = 1
 NB_K_DRIFT = 2
 NB_K_STEP = 3
 NB_K_FORCE_EVAL = 4
+NB_K_FORCE_FUSED = 5
 
 
 class nb_params(ctypes.Structure):

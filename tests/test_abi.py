@@ -85,7 +85,7 @@ def test_workspace_size_and_validation(nb):
     # encounter check against the big bodies only: at most 256 big bodies per system
     assert _wsize(nb, [0, 1000], nbig=[100], enc_algo=3)[0] == 0
     assert _wsize(nb, [0, 1000], enc_algo=3)[0] == nb.NB_E_INVALID
-    assert _wsize(nb, [0, 1000], enc_algo=4)[0] == nb.NB_E_INVALID
+    assert _wsize(nb, [0, 1000], enc_algo=5)[0] == nb.NB_E_INVALID
 
 def test_create_rejects_bad_workspace(nb):
     p = nb.default_params()

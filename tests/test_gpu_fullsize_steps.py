@@ -13,6 +13,9 @@ every one of three steps:
   * the first 64 systems of the 256-system batch (N_s from 200 to 4000, the
     largest system setting the split count, longest work first), FP32C.
 
+Both FP32C cases also run with the encounter test inside the force pass over
+the sorted order (enc_algo 4).
+
 Bars: every body's Q and V within 1e-11 (FP64) or 1e-7 (FP32C) relative, the
 accelerations within 1e-12 A_i (FP64) or 1e-6 A_i (FP32C), the flagged-pair
 count of every step equal to the oracle's, and the last step's list equal to
@@ -59,8 +62,10 @@ def _sampled_scale(w, Q, nsample=512, seed=3):
     return np.concatenate(idx), np.concatenate(A)
 
 
-def _compare_steps(w, mode, ref, qtol, atol):
-    c = ctx_for(w, mode=mode, enc_cap=1 << 18)
+def _compare_steps(w, mode, ref, qtol, atol, enc_algo=0):
+    c = ctx_for(w, mode=mode, enc_cap=1 << 18, enc_algo=enc_algo)
+    if enc_algo == 4:
+        assert c.choices()["enc_algo"] == 4
     print(f"[{w.name}] mode {mode} choices {c.choices()} tiles {c.tiles}", flush=True)
     for k in range(STEPS):
         # one step per call: the run of one step is itself captured and replayed
@@ -81,9 +86,9 @@ def _compare_steps(w, mode, ref, qtol, atol):
     c.close()
 
 
-def _compare_run(w, mode, ref, qtol):
+def _compare_run(w, mode, ref, qtol, enc_algo=0):
     """The same three steps as one nb_step call (a captured run of three steps)."""
-    c = ctx_for(w, mode=mode, enc_cap=1 << 18)
+    c = ctx_for(w, mode=mode, enc_cap=1 << 18, enc_algo=enc_algo)
     st = c.step(w.dt, STEPS)
     Q, V, _, pairs = ref[-1]
     x, v = c.download(nb.NB_DH)
@@ -104,17 +109,25 @@ def c3_ref():
     return w, _oracle_run(w)
 
 
-@pytest.mark.parametrize("mode,qtol,atol", [(0, 1e-11, 1e-12), (1, 1e-7, 1e-6)])
-def test_c3_steps_match_oracle(c3_ref, mode, qtol, atol):
+@pytest.mark.parametrize("mode,qtol,atol,enc_algo", [(0, 1e-11, 1e-12, 0), (1, 1e-7, 1e-6, 0),
+                                                     (1, 1e-7, 1e-6, 4)])
+def test_c3_steps_match_oracle(c3_ref, mode, qtol, atol, enc_algo):
+    """enc_algo 4: the encounter test inside the force pass over the sorted order."""
     w, ref = c3_ref
-    _compare_steps(w, mode, ref, qtol, atol)
-    _compare_run(w, mode, ref, qtol)
+    _compare_steps(w, mode, ref, qtol, atol, enc_algo)
+    _compare_run(w, mode, ref, qtol, enc_algo)
 
 
-def test_c4_batch_steps_match_oracle():
+@pytest.fixture(scope="module")
+def c4_ref():
     w = workloads.c4(nsys=64)
+    return w, _oracle_run(w)
+
+
+@pytest.mark.parametrize("enc_algo", [0, 4])
+def test_c4_batch_steps_match_oracle(c4_ref, enc_algo):
+    w, ref = c4_ref
     sizes = np.diff(w.off)
     assert w.nsys == 64 and sizes.min() >= 200 and sizes.max() <= 4000 and sizes.max() > 3500
-    ref = _oracle_run(w)
-    _compare_steps(w, 1, ref, 1e-7, 1e-6)
-    _compare_run(w, 1, ref, 1e-7)
+    _compare_steps(w, 1, ref, 1e-7, 1e-6, enc_algo)
+    _compare_run(w, 1, ref, 1e-7, enc_algo)
