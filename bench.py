@@ -80,9 +80,9 @@ def _dev_ms(ctx, torch, fn):
 
 
 def run_mode(w, mode: str, steps: int, warmup: int, torch, nb, resolve: bool = False,
-             energy_steps: int = 0):
+             energy_steps: int = 0, overrides=None):
     p = nb.default_params(G=w.G, mode=nb.NB_FP32C if mode == "fp32c" else nb.NB_FP64, drag=int(w.drag),
-                          resolve=int(resolve))
+                          resolve=int(resolve), **(overrides or {}))
     ctx = nb.Context(w.off, p, enc_cap=1 << 18, device="cuda:0", nbig=w.nbig)
     tiles = {"source": ctx.tiles, "force_r": ctx.params.force_r, "force_jchunk": ctx.params.force_jchunk,
              "enc_jchunk": ctx.params.enc_jchunk, **ctx.choices()}
@@ -310,6 +310,10 @@ def main():
                          "else 0 = none)")
     ap.add_argument("--no-full-method", action="store_true",
                     help="skip the full-method lines (c3 adds them by default)")
+    ap.add_argument("--force-g", type=int, default=0,
+                    help="super-tile width of the symmetric force (0: tuned or automatic)")
+    ap.add_argument("--enc-algo", type=int, default=0,
+                    help="encounter check algorithm (0: tuned or automatic; 4: inside the force pass)")
     ap.add_argument("--log", default=None,
                     help="also append the result line to this JSON-lines run log")
     ap.add_argument("--copy-probe", action="store_true",
@@ -334,8 +338,9 @@ def main():
     for mode in modes:
         print(f"[bench] {w.name} mode {mode}: ntot={w.ntot}, warmup {args.warmup}, steps {args.steps}",
               file=sys.stderr, flush=True)
+        over = {k: v for k, v in (("force_g", args.force_g), ("enc_algo", args.enc_algo)) if v}
         res[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb, resolve=args.resolve,
-                             energy_steps=energy_steps)
+                             energy_steps=energy_steps, overrides=over)
         enc = res[mode]["encounter_ms"]
         print(f"[bench] mode {mode}: {res[mode]['ms_per_step']:.4f} ms/step (replay median "
               f"{res[mode]['replay_median_ms_per_step']:.4f}, wall {res[mode]['wall_ms_per_step']:.4f}), "

@@ -125,10 +125,11 @@ typedef struct nb_params {
                              class the table lacks keeps the defaults.  An unreadable
                              file is NB_E_INVALID.  Read during the call only. */
     int32_t force_g;      /* symmetric force: tiles of 64 force_r bodies per super-tile, 1, 2
-                             or 4 (0: automatic, 4 when that gives at least 8192 work items,
-                             else 2 when that gives 2048, else 1).  A body receives one
-                             partial sum per super-tile of its system, so wider super-tiles
-                             write fewer partials. */
+                             or 4 (0: the tuning table's, else automatic: 4 when that gives at
+                             least 8192 work items, else 2 when that does, else 1).  A body
+                             receives one partial sum per super-tile of its system, so wider
+                             super-tiles write fewer partials, at the cost of a barrier per
+                             round in the force kernel. */
 } nb_params;
 
 /* largest system the persistent step launch accepts */

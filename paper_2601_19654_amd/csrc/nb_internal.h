@@ -9,9 +9,9 @@ namespace nb {
 
 constexpr int kBlock = 256;      // threads of every O(N) kernel and of the pair kernels
 
-// Work items the automatic super-tile width g of the symmetric force needs (one
-// workgroup of g waves per item): 2048 for g = 2, 8192 for g = 4.
-constexpr long long kSymMinItems(int g) { return g >= 4 ? 8192 : 2048; }
+// Work items the automatic super-tile width g (2 or 4) of the symmetric force
+// needs (one workgroup of g waves per item).
+constexpr long long kSymMinItems(int g) { return g >= 2 ? 8192 : 0; }
 
 // A block of an O(N) kernel: bodies [start, end) of one system (end - start <= kBlock).
 struct RBlk {
@@ -147,7 +147,8 @@ struct Dev {
     int2 *units; int nunit;   // culling units: tile A against tiles [b0, b0 + 64) (B >= A)
     int *tile_first;      // nsys: first tile of every system
     // force and encounter check in one pass over the sorted order (FP32C,
-    // every body big): per sorted position an FP32 midpoint and widened reach
+    // every body big): per sorted position two FP32 records, the chord midpoint
+    // with the widened bound of 3/4 eps + rc, and the chord
     int enc_fused;
     float4 *em;
     // persistent step launch

@@ -1570,29 +1570,34 @@ __device__ __noinline__ void enc_candidate(const SRec *__restrict__ srec, double
                                            DevStats *stats, int pi, int pj);
 
 // The tile of 64 R sources with, after the FP32C fields, each source's
-// encounter record: chord midpoint M and reach R widened for FP32 (x, y, z, R').
-// The FP32C tile is a member, not a base: a base's tail padding may hold the
-// derived members, while a member object keeps its whole size, so em[] starts
-// exactly sizeof(SymTile32<T>) bytes after the tile's first record.
+// encounter records in FP32: chord midpoint M with the widened bound b' of
+// 3/4 eps + rc (em), and chord c (ec).  The FP32C tile is a member, not a base:
+// a base's tail padding may hold the derived members, while a member object
+// keeps its whole size, so em[] starts exactly sizeof(SymTile32<T>) bytes after
+// the tile's first record and ec[] 16 T bytes after that.
 template <int T>
 struct alignas(1024) SymTile32E {
     SymTile32<T> t;
     float4 em[T];
+    float4 ec[T];
 };
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winvalid-offsetof"
 static_assert(offsetof(SymTile32E<64>, em) == sizeof(SymTile32<64>) &&
                   offsetof(SymTile32E<128>, em) == sizeof(SymTile32<128>) &&
-                  offsetof(SymTile32E<256>, em) == sizeof(SymTile32<256>),
-              "SymTile32E: em[] right after the FP32C tile");
+                  offsetof(SymTile32E<256>, em) == sizeof(SymTile32<256>) &&
+                  offsetof(SymTile32E<64>, ec) == sizeof(SymTile32<64>) + 16 * 64 &&
+                  offsetof(SymTile32E<128>, ec) == sizeof(SymTile32<128>) + 16 * 128 &&
+                  offsetof(SymTile32E<256>, ec) == sizeof(SymTile32<256>) + 16 * 256,
+              "SymTile32E: em[] and ec[] right after the FP32C tile");
 #pragma clang diagnostic pop
 
 // ENC: the encounter test fused in (sorted order).  Target r of sub-tile t is
 // tested against the sources when bit t R + r of `live` is set (the tile pair
-// survived the culling): its FP32 midpoint distance against the widened reaches
-// (emi[r] and the source's em), and the pairs that pass go to the exact test.
-// The source records are read from the LDS tile at a fixed offset past the
-// FP32C fields (em of SymTile32E).
+// survived the culling): the relative-chord filter in FP32 (midpoints emi[r],
+// chords eci[r] and the source's em, ec records), and the pairs that pass go to
+// the exact test.  The source records are read from the LDS tile at fixed
+// offsets past the FP32C fields (em, ec of SymTile32E).
 template <int R, bool DIAG, int T, bool ENC = false>
 __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, int ni, int j0,
                                             double *fp, size_t plane, double inner,
@@ -1609,7 +1614,7 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                                             float (&lx)[R], float (&ly)[R], float (&lz)[R],
                                             int &rare, int &near, const int *__restrict__ ord,
                                             const EncCtx &ec, const float4 (&emi)[R],
-                                            unsigned live)
+                                            const float4 (&eci)[R], unsigned live)
 {
 #pragma unroll 1
     for (int t = 0; t < R; ++t) {
@@ -1659,20 +1664,25 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                     if (DIAG)
                         qr[r] = on ? qr[r] : 0.0f;
                 }
-                // fused encounter test: midpoint distance against the summed
-                // reaches, in FP32 (padded targets and sources carry NaN
-                // midpoints and never pass)
+                // fused encounter test: the relative-chord filter in FP32,
+                // |dM|^2 <= 2 (|dc|^2 + (b'_i + b'_j)^2) with the bounds b'
+                // widened for the FP32 rounding (padded targets and sources
+                // carry NaN midpoints and never pass)
                 bool encr[R] = {};
                 bool ecand = false;
                 if (ENC && livet) {
                     const float4 E = lds_ld4(ac + (uint32_t)sizeof(SymTile32<T>));
+                    const float4 F = lds_ld4(ac + (uint32_t)(sizeof(SymTile32<T>) + 16 * T));
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const float ex = E.x - emi[r].x, ey = E.y - emi[r].y, ez = E.z - emi[r].z;
+                        const float cx = F.x - eci[r].x, cy = F.y - eci[r].y, cz = F.z - eci[r].z;
                         const float D2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+                        const float C2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
                         const float Sr = E.w + emi[r].w;
                         const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
-                        encr[r] = ((livet >> r) & 1u) && on && D2 <= Sr * Sr;
+                        encr[r] = ((livet >> r) & 1u) && on &&
+                                  D2 <= fmaf(Sr, Sr, C2) * (2.0f * (1.0f + 0x1p-18f));
                         ecand |= encr[r];
                     }
                 }
@@ -1805,12 +1815,12 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
                     sym_tile32c<R, true, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, fp, plane, inner,
                                             pk, qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi,
                                             hx, hy, hz, lx, ly, lz, rare, near, nullptr, noenc,
-                                            noem, 0u);
+                                            noem, noem, 0u);
                 else
                     sym_tile32c<R, false, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, fp, plane,
                                              inner, pk, qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl,
                                              mi, tmi, hx, hy, hz, lx, ly, lz, rare, near, nullptr,
-                                             noenc, noem, 0u);
+                                             noenc, noem, noem, 0u);
             }
             __syncthreads();
         }
@@ -2443,16 +2453,18 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ c
 
 // Sorted position of every body: its cell's offset plus the slot the binning
 // took (the order inside a cell follows the atomics' timing until
-// k_cell_order puts it in index order).
+// k_cell_order puts it in index order).  slot_of[i] becomes the position.
 __global__ void k_scatter(const RBlk *__restrict__ rblk, const int *__restrict__ cell_of,
-                          const int *__restrict__ slot_of, const int *__restrict__ cell_off,
+                          int *__restrict__ slot_of, const int *__restrict__ cell_off,
                           int *__restrict__ ord)
 {
     const RBlk b = rblk[blockIdx.x];
     const int i = b.start + threadIdx.x;
     if (i >= b.end)
         return;
-    ord[cell_off[cell_of[i]] + slot_of[i]] = i;
+    const int pos = cell_off[cell_of[i]] + slot_of[i];
+    ord[pos] = i;
+    slot_of[i] = pos;
 }
 
 // The bodies of every cell in index order, so that the sorted order, its tiles
@@ -2462,7 +2474,8 @@ __global__ void k_scatter(const RBlk *__restrict__ rblk, const int *__restrict__
 constexpr int kCellSortMax = 512;
 
 __global__ __launch_bounds__(kBlock) void k_cell_order(const int *__restrict__ cell_off, int ncell,
-                                                       int ntot, int *__restrict__ ord)
+                                                       int ntot, int *__restrict__ ord,
+                                                       int *__restrict__ pos_of)
 {
     __shared__ int sb[kBlock / 64][kCellSortMax];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -2484,11 +2497,13 @@ __global__ __launch_bounds__(kBlock) void k_cell_order(const int *__restrict__ c
             for (int q = 0; q < k; ++q)
                 rank += sb[wv][q] < me;
             ord[start + rank] = me;
+            pos_of[me] = start + rank;
         }
 }
 
-// The sorted records, position by position, from the drift outputs.
-__global__ void k_srec(int ntot, const int *__restrict__ ord, const int *__restrict__ sys_of,
+// The sorted records from the drift outputs, body by body (coalesced reads),
+// each written to the body's sorted position.
+__global__ void k_srec(int ntot, const int *__restrict__ pos_of, const int *__restrict__ sys_of,
                        const double *__restrict__ q0x, const double *__restrict__ q0y,
                        const double *__restrict__ q0z, const double *__restrict__ v0x,
                        const double *__restrict__ v0y, const double *__restrict__ v0z,
@@ -2500,10 +2515,10 @@ __global__ void k_srec(int ntot, const int *__restrict__ ord, const int *__restr
                        const int *__restrict__ nbig, SRec *__restrict__ srec,
                        float4 *__restrict__ em)
 {
-    const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pos >= ntot)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ntot)
         return;
-    const int i = ord[pos];
+    const int pos = pos_of[i];
     const int sy = sys_of[i];
     SRec r;
     r.q0[0] = q0x[i]; r.q0[1] = q0y[i]; r.q0[2] = q0z[i];
@@ -2520,11 +2535,14 @@ __global__ void k_srec(int ntot, const int *__restrict__ ord, const int *__restr
     r.pad = 0.0;
     srec[pos] = r;
     if (em) {
-        // FP32 midpoint and reach for the fused test: the reach widened by
-        // 2^-21 |M|_1 for the FP32 rounding of the midpoints and their
-        // differences, and by 2^-18 relative for that of the distance and sums
-        const double w = (M.w + 0x1p-21 * (fabs(M.x) + fabs(M.y) + fabs(M.z))) * (1.0 + 0x1p-18);
-        em[pos] = make_float4((float)M.x, (float)M.y, (float)M.z, (float)w);
+        // FP32 records of the fused test: midpoint M and chord c, and the bound
+        // b' of 3/4 eps + rc widened by 2^-21 (|M|_1 + |c|_1) for the FP32
+        // rounding of M, c and their differences, and by 2^-18 relative for the
+        // rounding of the bound itself
+        const double w = (C.w + rc[i] + 0x1p-21 * (fabs(M.x) + fabs(M.y) + fabs(M.z) + fabs(C.x) +
+                                                   fabs(C.y) + fabs(C.z))) * (1.0 + 0x1p-18);
+        em[2 * (size_t)pos] = make_float4((float)M.x, (float)M.y, (float)M.z, (float)w);
+        em[2 * (size_t)pos + 1] = make_float4((float)C.x, (float)C.y, (float)C.z, 0.0f);
     }
 }
 
@@ -2698,6 +2716,17 @@ __global__ __launch_bounds__(64 * kTpWaves) void k_tile_pairs(const Tile *__rest
 // One workgroup per surviving tile pair (grid-stride over the count): each of
 // its waves holds tile A's bodies in its lanes and tests a quarter of tile B's
 // records, staged once in LDS.
+// One wave per kept tile pair (A, B): lane L holds body L of tile A, tile B's
+// filter fields (midpoint, chord, 3/4 eps, rc, big flag: 72 B a body) sit in
+// the wave's LDS slice, and every lane meets the 64 sources in turn, so the
+// per-target setup (record, geometry, bound against tile B) serves 64 tests.
+// The exact test's fields of the rare survivors are read from the sorted
+// records in memory.
+struct FRec {
+    double M[3], c[3];
+    double e34, rc;
+};
+
 __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ tiles,
                                                       const TileB *__restrict__ tileb,
                                                       const int2 *__restrict__ tpairs, int tp_cap,
@@ -2706,72 +2735,76 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
                                                       int cap, int *__restrict__ ce,
                                                       DevStats *stats)
 {
-    __shared__ SRec sb[64];
+    __shared__ FRec sb[kBlock / 64][64];
+    __shared__ int sbig[kBlock / 64][64];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int npair = min(stats->cur_tp, tp_cap);
     const double t2 = 2.0 * dt;
     const double k427 = 4.0 / 27.0;
-    for (int p = blockIdx.x; p < npair; p += gridDim.x) {
+    for (int p = blockIdx.x * (kBlock / 64) + wv; p < npair; p += gridDim.x * (kBlock / 64)) {
         const int2 AB = tpairs[p];
         const Tile TA = tiles[AB.x], TB = tiles[AB.y];
-        __syncthreads();
-        if (threadIdx.x < TB.count)
-            sb[threadIdx.x] = srec[TB.start + threadIdx.x];
-        __syncthreads();
+        if (lane < TB.count) {
+            const SRec &r = srec[TB.start + lane];
+            FRec f;
+            for (int k = 0; k < 3; ++k) {
+                f.M[k] = r.M[k];
+                f.c[k] = r.c[k];
+            }
+            f.e34 = r.e34;
+            f.rc = r.rc;
+            sb[wv][lane] = f;
+            sbig[wv][lane] = r.big;
+        }
+        wave_lds_sync();
         const bool on = lane < TA.count;
         const SRec me = srec[TA.start + (on ? lane : 0)];
         double M[3], c[3], eb[3], se;
         rec_geometry(me, dt, M, c, eb, se);
         const bool lane_ok = on && may_meet(M, 0.0, c, 0.0, eb, se, me.rc, tileb[AB.y]);
-        if (!__any(lane_ok))
-            continue;
-        const bool diag = AB.x == AB.y;
-        const int j1 = min(TB.count, 16 * wv + 16);
-        for (int jj = 16 * wv; jj < j1; ++jj) {
-            const SRec &J = sb[jj];
-            bool hit = false;
-            // relative chord filter (see k_encounter), evaluated by every lane
-            // without a branch (the source record is one broadcast read)
-            const double mx = J.M[0] - me.M[0], my = J.M[1] - me.M[1], mz = J.M[2] - me.M[2];
-            const double cx = J.c[0] - me.c[0], cy = J.c[1] - me.c[1], cz = J.c[2] - me.c[2];
-            const double D2 = fma(mz, mz, fma(my, my, mx * mx));
-            const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
-            const double bb = J.e34 + me.e34 + fmax(J.rc, me.rc);
-            const bool cand = lane_ok & (!diag | (jj > lane)) & ((me.big | J.big) != 0) &
-                              (D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20));
-            if (__any(cand) && cand) {
-                double d0x = J.q0[0] - me.q0[0], d0y = J.q0[1] - me.q0[1], d0z = J.q0[2] - me.q0[2];
-                double d1x = J.q1[0] - me.q1[0], d1y = J.q1[1] - me.q1[1], d1z = J.q1[2] - me.q1[2];
-                double e0x = J.v0[0] - me.v0[0], e0y = J.v0[1] - me.v0[1], e0z = J.v0[2] - me.v0[2];
-                double e1x = J.v1[0] - me.v1[0], e1y = J.v1[1] - me.v1[1], e1z = J.v1[2] - me.v1[2];
-                double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
-                double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
-                double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
-                double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
-                double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
-                double rcij = fmax(me.rc, J.rc);
-                double thr = rcij * rcij;
-                if (lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1)))
-                    hit = hermite_min(f0, f1, g0, g1) <= thr;
-            }
-            const unsigned long long mask = __ballot(hit);
-            if (mask) {
-                const int leader = __ffsll((long long)mask) - 1;
-                int base = 0;
-                if (lane == leader)
-                    base = atomicAdd(&stats->cur_nce, (int)__popcll(mask));
-                base = __shfl(base, leader);
-                if (hit) {
-                    const int pos = base + (int)__popcll(mask & ((1ull << lane) - 1ull));
-                    const int bi = me.body, bj = J.body;
-                    const unsigned lo = (unsigned)min(bi, bj), hi = (unsigned)max(bi, bj);
-                    if (pos < cap)
-                        keys[pos] = ((unsigned long long)lo << 32) | hi;
-                    __hip_atomic_store(&ce[bi], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store(&ce[bj], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__any(lane_ok)) {
+            const bool diag = AB.x == AB.y;
+            for (int jj = 0; jj < TB.count; ++jj) {
+                const FRec &J = sb[wv][jj];
+                bool hit = false;
+                // relative chord filter (see k_encounter), every lane without a
+                // branch (the source record is one broadcast read)
+                const double mx = J.M[0] - me.M[0], my = J.M[1] - me.M[1], mz = J.M[2] - me.M[2];
+                const double cx = J.c[0] - me.c[0], cy = J.c[1] - me.c[1], cz = J.c[2] - me.c[2];
+                const double D2 = fma(mz, mz, fma(my, my, mx * mx));
+                const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
+                const double bb = J.e34 + me.e34 + fmax(J.rc, me.rc);
+                const bool cand = lane_ok & (!diag | (jj > lane)) & ((me.big | sbig[wv][jj]) != 0) &
+                                  (D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20));
+                if (__any(cand) && cand) {
+                    const SRec &Jr = srec[TB.start + jj];
+                    double d0x = Jr.q0[0] - me.q0[0], d0y = Jr.q0[1] - me.q0[1], d0z = Jr.q0[2] - me.q0[2];
+                    double d1x = Jr.q1[0] - me.q1[0], d1y = Jr.q1[1] - me.q1[1], d1z = Jr.q1[2] - me.q1[2];
+                    double e0x = Jr.v0[0] - me.v0[0], e0y = Jr.v0[1] - me.v0[1], e0z = Jr.v0[2] - me.v0[2];
+                    double e1x = Jr.v1[0] - me.v1[0], e1y = Jr.v1[1] - me.v1[1], e1z = Jr.v1[2] - me.v1[2];
+                    double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
+                    double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
+                    double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
+                    double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
+                    double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
+                    double rcij = fmax(me.rc, Jr.rc);
+                    double thr = rcij * rcij;
+                    if (lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1)))
+                        hit = hermite_min(f0, f1, g0, g1) <= thr;
+                    if (hit) {
+                        const int pos = atomicAdd(&stats->cur_nce, 1);
+                        const int bi = me.body, bj = Jr.body;
+                        const unsigned lo = (unsigned)min(bi, bj), hi = (unsigned)max(bi, bj);
+                        if (pos < cap)
+                            keys[pos] = ((unsigned long long)lo << 32) | hi;
+                        __hip_atomic_store(&ce[bi], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        __hip_atomic_store(&ce[bj], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
             }
         }
+        // the slice is refilled for the next pair only after every lane's reads
+        wave_lds_sync();
     }
 }
 
@@ -2859,11 +2892,13 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 1 : 2) void k_force32c_fused(
                 const int b = ord[wk.j0 + k];
                 S.a[e] = pk[2 * (size_t)b];
                 S.b[e] = pk[2 * (size_t)b + 1];
-                tl[k / T].em[e] = em[wk.j0 + k];
+                tl[k / T].em[e] = em[2 * (size_t)(wk.j0 + k)];
+                tl[k / T].ec[e] = em[2 * (size_t)(wk.j0 + k) + 1];
             } else {
                 S.a[e] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
                 S.b[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
                 tl[k / T].em[e] = make_float4(qnan, qnan, qnan, 0.0f);
+                tl[k / T].ec[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             }
             S.run[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             S.ax[e] = S.ay[e] = S.az[e] = 0.0;
@@ -2873,7 +2908,7 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 1 : 2) void k_force32c_fused(
         const int tni = min(T, wk.ni - wv * T);
         float xh[R], yh[R], zh[R], xl[R], yl[R], zl[R], mi[R];
         float hx[R], hy[R], hz[R], lx[R], ly[R], lz[R];
-        float4 emi[R];
+        float4 emi[R], eci[R];
         float tmi = 0.0f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -2885,41 +2920,49 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 1 : 2) void k_force32c_fused(
             xl[r] = B.x; yl[r] = B.y; zl[r] = B.z;
             mi[r] = ok ? A.w : 0.0f;
             tmi = max_nonneg(tmi, B.w);
-            emi[r] = ok ? em[ti0 + li] : make_float4(qnan, qnan, qnan, 0.0f);
+            emi[r] = ok ? em[2 * (size_t)(ti0 + li)] : make_float4(qnan, qnan, qnan, 0.0f);
+            eci[r] = ok ? em[2 * (size_t)(ti0 + li) + 1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
         }
         tmi = wave_max_nonneg(tmi);
         int rare = 0;
         double *fp = fpart + (size_t)wk.slot * ntot;
         const int nr = diag ? G / 2 + 1 : G;
+        // The tile pairs that may hold a flagged pair, for every round at once:
+        // lane (k R + t) R + r bounds target sub-tile r against sub-tile t of
+        // round k's source tile (G R^2 <= 64 lanes), so the bounds' loads and
+        // square roots are in flight together, once per item.
+        unsigned long long livemask;
+        {
+            constexpr int RR = R * R;
+            const int k = lane / RR, t = (lane % RR) / R, r = lane % R;
+            const int s = (wv + k) % G;
+            bool lv = false;
+            if (k < nr && 64 * r < tni && s * T + 64 * t < wk.nj) {
+                const TileB &A = tileb[tile_of(tile_first, off, wk.sys, ti0 + 64 * r)];
+                lv = may_meet(A.cm, A.sm, A.cc, A.sc, A.ce, A.se, A.rc,
+                              tileb[tile_of(tile_first, off, wk.sys, wk.j0 + s * T + 64 * t)]);
+            }
+            livemask = __ballot(lv);
+        }
         for (int k = 0; k < nr; ++k) {
             const int s = (wv + k) % G;
             const bool go = tni > 0 && s * T < wk.nj && !(diag && 2 * k == G && wv >= G / 2);
             if (go) {
-                // tile pairs (target sub-tile r, source sub-tile t) that may hold
-                // a flagged pair: bit t R + r
-                const int sj0 = wk.j0 + s * T, snj = min(T, wk.nj - s * T);
-                unsigned live = 0u;
-                for (int r = 0; r < R; ++r) {
-                    if (64 * r >= tni)
-                        continue;
-                    const TileB A = tileb[tile_of(tile_first, off, wk.sys, ti0 + 64 * r)];
-                    for (int t = 0; t < R; ++t)
-                        if (64 * t < snj &&
-                            may_meet(A.cm, A.sm, A.cc, A.sc, A.ce, A.se, A.rc,
-                                     tileb[tile_of(tile_first, off, wk.sys, sj0 + 64 * t)]))
-                            live |= 1u << (t * R + r);
-                }
+                // this round's bits: t R + r
+                const int sj0 = wk.j0 + s * T;
+                const unsigned live =
+                    (unsigned)(livemask >> (k * R * R)) & (unsigned)((1ull << (R * R)) - 1ull);
                 if (diag && k == 0)
                     sym_tile32c<R, true, T, true>(tl[s].t, lane, ti0, tni, sj0, fp, plane, inner, pk,
                                                   qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi,
                                                   tmi, hx, hy, hz, lx, ly, lz, rare, near, ord, ec,
-                                                  emi, live);
+                                                  emi, eci, live);
                 else
                     sym_tile32c<R, false, T, true>(tl[s].t, lane, ti0, tni, sj0, fp, plane, inner, pk,
                                                    qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi,
                                                    tmi, hx, hy, hz, lx, ly, lz, rare, near, ord, ec,
-                                                   emi, live);
+                                                   emi, eci, live);
             }
             __syncthreads();
         }
@@ -3879,8 +3922,9 @@ hipError_t launch_enc_gather(const Dev &d, hipStream_t s)
                                                          d.scan_part, d.stats);
         }
         k_scatter<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.cell_of, d.slot_of, d.cell_off, d.ord);
-        k_cell_order<<<cdiv(d.ncell, kBlock / 64), kBlock, 0, s>>>(d.cell_off, d.ncell, d.ntot, d.ord);
-        k_srec<<<cdiv(d.ntot, kBlock), kBlock, 0, s>>>(d.ntot, d.ord, d.sys_of, d.q0x, d.q0y, d.q0z,
+        k_cell_order<<<cdiv(d.ncell, kBlock / 64), kBlock, 0, s>>>(d.cell_off, d.ncell, d.ntot, d.ord,
+                                                                    d.slot_of);
+        k_srec<<<cdiv(d.ntot, kBlock), kBlock, 0, s>>>(d.ntot, d.slot_of, d.sys_of, d.q0x, d.q0y, d.q0z,
                                                        d.v0x, d.v0y, d.v0z, d.q1x, d.q1y, d.q1z,
                                                        d.v1x, d.v1y, d.v1z, d.rc1, d.mr, d.cr, d.off,
                                                        d.nbig, d.srec, d.enc_fused ? d.em : nullptr);
@@ -3896,7 +3940,8 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
                                                                          d.tileb);
             k_tile_pairs<<<cdiv(d.nunit, kTpWaves), 64 * kTpWaves, 0, s>>>(
                 d.tiles, d.units, d.nunit, d.tileb, d.tpairs, d.tp_cap, d.stats);
-            int grid = std::min(std::max(1, d.tp_cap), 8192);
+            // one wave per kept tile pair
+            int grid = std::min(std::max(1, cdiv(d.tp_cap, kBlock / 64)), 8192);
             k_enc_pairs<<<grid, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.srec, dt,
                                                  d.keys, d.enc_cap, d.ce, d.stats);
         }

@@ -228,6 +228,16 @@ int max_big(int nsys, const int32_t *off, const int32_t *nbig)
     return mb;
 }
 
+int choose_enc_algo(const Params &p, int nsys, const int32_t *off, const int32_t *nbig);
+
+// The force pass with the encounter test in it holds four targets per lane only
+// by spilling registers: with enc_algo 4 it takes tiles of 128 (two per lane).
+void fused_tiles(Params &p, int nsys, const int32_t *off, const int32_t *nbig)
+{
+    if (choose_enc_algo(p, nsys, off, nbig) == 4 && p.force_r == 4)
+        p.force_r = 2;
+}
+
 int choose_enc_algo(const Params &p, int nsys, const int32_t *off, const int32_t *nbig)
 {
     // 4: the sorted check fused into the symmetric force pass, where it applies
@@ -367,9 +377,10 @@ long long sym_items(int nsys, const int32_t *off, int TI)
 
 // Tiles per super-tile of the symmetric force: the one asked for, else the
 // widest whose work items (super-tile pairs, one workgroup each) reach
-// kSymMinItems(g): measured, a width of 2 pays from about 8 workgroups per
-// compute unit (16384 bodies) and one of 4 from about 32 (131072 bodies, where
-// it also beats 2; not at 256 systems of 200-4000 bodies).
+// kSymMinItems(g).  Measured on whole steps: wider super-tiles write fewer
+// partials but cost the force kernel its rounds' barriers, which pays from
+// about 32 workgroups per compute unit (256 systems of 200-4000 bodies: 2;
+// 131072 bodies: 4), not at 16384 bodies (1).
 int sym_width(const Params &p, int nsys, const int32_t *off)
 {
     if (p.force_g == 1 || p.force_g == 2 || p.force_g == 4)
@@ -622,7 +633,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
         d.tile_first = (int *)take((size_t)nsys * sizeof(int));
     }
     d.enc_fused = t.enc_fused ? 1 : 0;
-    d.em = t.enc_fused ? (float4 *)take((size_t)ntot * sizeof(float4)) : nullptr;
+    d.em = t.enc_fused ? (float4 *)take((size_t)ntot * 2 * sizeof(float4)) : nullptr;
     d.flag = (int *)take(4 * sizeof(int));
     d.stage = (double *)take((size_t)7 * nd);
     d.lost = (int *)take((size_t)ntot * sizeof(int));
@@ -1173,6 +1184,7 @@ int nb_workspace_size(const nb_params *p, int nsys, const int32_t *off, const in
         return NB_E_INVALID;
     if (q.enc_algo == 3 && max_big(nsys, off, nbig) > kBlock)
         q.enc_algo = 0;
+    fused_tiles(q, nsys, off, nbig);
     Tables t;
     build_tables(q, nsys, off, nbig, t);
     Dev d{};
@@ -1202,6 +1214,7 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *n
         }
         if (c->p.enc_algo == 3 && max_big(nsys, off, nbig) > kBlock)
             c->p.enc_algo = 0;
+        fused_tiles(c->p, nsys, off, nbig);
     }
     c->enc_cap = enc_cap;
     c->stream = (hipStream_t)stream;

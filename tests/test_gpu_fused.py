@@ -37,7 +37,10 @@ def case(request):
 def test_fused_list_equals_sorted_check(case, r, g):
     name, w = case
     a = ctx_for(w, mode=nb.NB_FP32C, enc_algo=4, force_r=r, force_g=g, force_algo=2)
-    b = ctx_for(w, mode=nb.NB_FP32C, enc_algo=2, force_r=r, force_g=g, force_algo=2)
+    # the same tiles (the fused mode takes two targets per lane where four were asked)
+    assert a.params.force_r == min(r, 2)
+    b = ctx_for(w, mode=nb.NB_FP32C, enc_algo=2, force_r=a.params.force_r, force_g=a.choices()["force_g"],
+                force_algo=2)
     assert a.choices()["enc_algo"] == 4 and b.choices()["enc_algo"] == 2
     sa, sb = a.step(w.dt, 1), b.step(w.dt, 1)
     ea, eb = a.last_encounters(), b.last_encounters()
