@@ -8,6 +8,7 @@
 namespace nb {
 
 constexpr int kBlock = 256;      // threads of every O(N) kernel and of the pair kernels
+constexpr int kScanChunkCells = 1024;   // cells per block of the counting sort's scan
 
 // Work items the automatic super-tile width g (2 or 4) of the symmetric force
 // needs (one workgroup of g waves per item).
@@ -123,7 +124,8 @@ struct Dev {
     double *ptot;         // nsys x 4: per-system sums of m V for the stellar drifts
     int sys_total;        // some system has more than 64 blocks: its momentum is summed once
                           // per stellar drift into ptot instead of by each of its blocks
-    double *fpart;        // 3 x maxs x ntot force partials
+    double *fpart;        // 3 x maxs x ntot force partials (FP64 pair arithmetic)
+    float *fpart32;       // the same in FP32 (FP32C pair arithmetic; fpart is then null)
     double *dpart;        // ndw x 4 double-double pair sums (E pair, EK pair)
     double *bpart;        // nrb x 16 body partial sums for diagnostics
     double *diag;         // nsys x 8 results: E, EK, L3, P3
@@ -140,7 +142,7 @@ struct Dev {
     int *sys_cell_base, *sys_cell_cnt;   // nsys
     int *ord;             // ntot: sorted position -> body
     SRec *srec;           // ntot
-    int *scan_part;       // per chunk of 4096 cells: count sums (large grids)
+    int *scan_part;       // per chunk of kScanChunkCells cells: count sums (large grids)
     Tile *tiles; int ntile;
     TileB *tileb;         // ntile
     int2 *tpairs; int tp_cap;

@@ -21,6 +21,7 @@
 #include <cstdint>
 #include <float.h>
 #include <math.h>
+#include <type_traits>
 
 namespace nb {
 
@@ -859,7 +860,7 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
                                                      const double *__restrict__ m,
                                                      const double *__restrict__ rc,
                                                      const double *__restrict__ tile_rc2,
-                                                     double *__restrict__ fpart, int ntot,
+                                                     float *__restrict__ fpart, int ntot,
                                                      int maxs, double inner, DevStats *stats)
 {
     __shared__ float4 sa[kBlock];
@@ -971,9 +972,9 @@ __global__ __launch_bounds__(kBlock) void k_force32c(const FWork *__restrict__ w
             int li = lane + 64 * k;
             if (li < wk.ni) {
                 int i = wk.i0 + li;
-                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = sx_[k];
-                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = sy_[k];
-                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = sz_[k];
+                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = (float)sx_[k];
+                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = (float)sy_[k];
+                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = (float)sz_[k];
             }
         }
     }
@@ -1085,7 +1086,7 @@ __global__ __launch_bounds__(kBlock) void k_force32c_few(const FWork *__restrict
                                                          const double *__restrict__ m,
                                                          const double *__restrict__ rc,
                                                          const double *__restrict__ tile_rc2,
-                                                         double *__restrict__ fpart, int ntot,
+                                                         float *__restrict__ fpart, int ntot,
                                                          int maxs, double inner, DevStats *stats)
 {
     __shared__ float4 sa[kWaves][kFewMax];
@@ -1165,9 +1166,9 @@ __global__ __launch_bounds__(kBlock) void k_force32c_few(const FWork *__restrict
             const int li = lane + 64 * k;
             if (li < wk.ni) {
                 const int i = wk.i0 + li;
-                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = ((double)hx[k] + (double)lx[k]) + nx[k];
-                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = ((double)hy[k] + (double)ly[k]) + ny[k];
-                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = ((double)hz[k] + (double)lz[k]) + nz[k];
+                fpart[((size_t)0 * maxs + wk.slot) * ntot + i] = (float)(((double)hx[k] + (double)lx[k]) + nx[k]);
+                fpart[((size_t)1 * maxs + wk.slot) * ntot + i] = (float)(((double)hy[k] + (double)ly[k]) + ny[k]);
+                fpart[((size_t)2 * maxs + wk.slot) * ntot + i] = (float)(((double)hz[k] + (double)lz[k]) + nz[k]);
             }
         }
     }
@@ -1373,6 +1374,163 @@ __device__ __forceinline__ void sym_tile64(SymTile64<T> &L, int lane, int i0, in
     }
 }
 
+// A double moved one lane down the wave: lane L gets lane (L + 1) mod 64's
+// value (DPP wave rotate, one VALU per 32-bit half).
+__device__ __forceinline__ double wave_rotl1(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x134, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x134, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Tile J of one wave for the FP64 loop with source sums in registers (R <= 2).
+// Each sub-tile's source records are stored twice over (entry 64 + j repeats
+// j), so that lane L reads source (L + k) mod 64 at entry L + k: a fixed
+// offset from the lane's own entry, no wrap.  Only the FP64 totals of the
+// sources' sums live here.
+template <int R>
+struct alignas(512) SymTile64R {
+    struct Sub {
+        double x[128], y[128], z[128], m[128];
+    } s[R];
+    double r2[64 * R];                 // max(rc^2, DBL_MIN)
+    double rc[64 * R];
+    double ax[64 * R], ay[64 * R], az[64 * R];   // tile J's FP64 totals
+};
+
+template <int R>
+__device__ __forceinline__ void put_src64(SymTile64R<R> &S, int e, double x, double y, double z,
+                                          double m, double rcj)
+{
+    typename SymTile64R<R>::Sub &U = S.s[e / 64];
+    const int j = e % 64;
+    U.x[j] = U.x[j + 64] = x;
+    U.y[j] = U.y[j + 64] = y;
+    U.z[j] = U.z[j + 64] = z;
+    U.m[j] = U.m[j + 64] = m;
+    S.rc[e] = rcj;
+    S.r2[e] = fmax(rcj * rcj, DBL_MIN);
+    S.ax[e] = S.ay[e] = S.az[e] = 0.0;
+}
+
+template <int T>
+__device__ __forceinline__ void put_src64(SymTile64<T> &S, int e, double x, double y, double z,
+                                          double m, double rcj)
+{
+    S.x[e] = x;
+    S.y[e] = y;
+    S.z[e] = z;
+    S.m[e] = m;
+    S.rc[e] = rcj;
+    S.r2[e] = fmax(rcj * rcj, DBL_MIN);
+    S.ax[e] = S.ay[e] = S.az[e] = 0.0;
+}
+
+// The tile pair of sym_tile64 with the sources' running sums in registers:
+// in step k lane L pairs its targets with source (L + k) mod 64 of sub-tile t
+// and holds that source's sums; after the step the sums move one lane down
+// (wave_rotl1), where that source is met next.  After 64 steps every lane
+// holds its own source's sums again and adds them to the FP64 totals.  The LDS
+// then carries only the source records (32 B per lane and step instead of 80
+// with the sums' read-modify-write), which keeps the FP64 loop off the LDS
+// bandwidth limit; the moves cost 6 VALU per step.
+template <int R, bool DIAG>
+__device__ __forceinline__ void sym_tile64_rot(SymTile64R<R> &L, int lane, int i0, int ni,
+                                               double inner, const double *__restrict__ rc,
+                                               const double (&xi)[R], const double (&yi)[R],
+                                               const double (&zi)[R], const double (&mi)[R],
+                                               double tmi, double (&ax)[R], double (&ay)[R],
+                                               double (&az)[R], int &near)
+{
+#pragma unroll 1
+    for (int t = 0; t < R; ++t) {
+        const double thr = fmax(tmi, wave_max(L.r2[64 * t + lane]));
+        // LDS address of x[lane] of sub-tile t; y, z, m at fixed offsets
+        constexpr uint32_t kY = 8 * 128, kZ = 16 * 128, kM = 24 * 128;
+        uint32_t ac = lds_addr(&L.s[t].x[lane]);
+        double jxs = lds_ld8(ac), jys = lds_ld8(ac + kY), jzs = lds_ld8(ac + kZ), jms = lds_ld8(ac + kM);
+        double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll 2
+        for (int k = 0; k < 64; ++k) {
+            const uint32_t an = ac + 8;
+            const double xn = lds_ld8(an), yn = lds_ld8(an + kY), zn = lds_ld8(an + kZ),
+                         mn = lds_ld8(an + kM);
+            double dxr[R], dyr[R], dzr[R], r2r[R], qr[R];
+            bool cand = false;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                dxr[r] = jxs - xi[r];
+                dyr[r] = jys - yi[r];
+                dzr[r] = jzs - zi[r];
+                r2r[r] = fma(dzr[r], dzr[r], fma(dyr[r], dyr[r], dxr[r] * dxr[r]));
+                qr[r] = rinv3(r2r[r]);
+                const bool on = !DIAG || (64 * r + lane < 64 * t + ((lane + k) & 63));
+                cand |= r2r[r] < thr && on;
+                if (DIAG)
+                    qr[r] = on ? qr[r] : 0.0;
+            }
+            if (cand) {
+                const int sj = 64 * t + ((lane + k) & 63);
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const bool on = !DIAG || (64 * r + lane < sj);
+                    if (r2r[r] < thr && on) {
+                        const int li = 64 * r + lane;
+                        const double rci = rc[i0 + (li < ni ? li : 0)];
+                        if (r2r[r] < fmax(fmax(rci * rci, DBL_MIN), L.r2[sj])) {
+                            qr[r] = changeover_w(r2r[r], fmax(rci, L.rc[sj]), inner);
+                            ++near;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double dx = dxr[r], dy = dyr[r], dz = dzr[r], q = qr[r];
+                const double wi = jms * q, wj = mi[r] * q;
+                ax[r] = fma(wi, dx, ax[r]);
+                ay[r] = fma(wi, dy, ay[r]);
+                az[r] = fma(wi, dz, az[r]);
+                jx = fma(-wj, dx, jx);
+                jy = fma(-wj, dy, jy);
+                jz = fma(-wj, dz, jz);
+            }
+            jx = wave_rotl1(jx);
+            jy = wave_rotl1(jy);
+            jz = wave_rotl1(jz);
+            ac = an;
+            jxs = xn;
+            jys = yn;
+            jzs = zn;
+            jms = mn;
+        }
+        L.ax[64 * t + lane] += jx;
+        L.ay[64 * t + lane] += jy;
+        L.az[64 * t + lane] += jz;
+    }
+}
+
+template <int R, bool DIAG, int T>
+__device__ __forceinline__ void sym_round64(SymTile64R<R> &L, int lane, int i0, int ni, double inner,
+                                            const double *__restrict__ rc, const double (&xi)[R],
+                                            const double (&yi)[R], const double (&zi)[R],
+                                            const double (&mi)[R], double tmi, double (&ax)[R],
+                                            double (&ay)[R], double (&az)[R], int &near)
+{
+    sym_tile64_rot<R, DIAG>(L, lane, i0, ni, inner, rc, xi, yi, zi, mi, tmi, ax, ay, az, near);
+}
+
+template <int R, bool DIAG, int T>
+__device__ __forceinline__ void sym_round64(SymTile64<T> &L, int lane, int i0, int ni, double inner,
+                                            const double *__restrict__ rc, const double (&xi)[R],
+                                            const double (&yi)[R], const double (&zi)[R],
+                                            const double (&mi)[R], double tmi, double (&ax)[R],
+                                            double (&ay)[R], double (&az)[R], int &near)
+{
+    sym_tile64<R, DIAG, T>(L, lane, i0, ni, inner, rc, xi, yi, zi, mi, tmi, ax, ay, az, near);
+}
+
 template <int R, int G>
 __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force64_sym(const FWork *__restrict__ work, int nitems,
                                                         const double *__restrict__ qx,
@@ -1384,7 +1542,11 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force64_sym(const FW
                                                         double inner, DevStats *stats)
 {
     constexpr int T = 64 * R;
-    __shared__ SymTile64<T> tl[G];
+    // R <= 2: the sources' sums in registers, moved between lanes (LDS holds
+    // the records only); R = 4 amortises the sums' LDS traffic over four
+    // targets per lane and keeps them in LDS, within its LDS budget
+    using Tile = typename std::conditional<(R <= 2), SymTile64R<R>, SymTile64<T>>::type;
+    __shared__ Tile tl[G];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int near = 0;
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
@@ -1392,20 +1554,12 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force64_sym(const FW
         const bool diag = wk.i0 == wk.j0;
         // the G source tiles of super-tile J (nj real records from j0)
         for (int k = threadIdx.x; k < G * T; k += 64 * G) {
-            SymTile64<T> &S = tl[k / T];
-            const int e = k % T;
             // sources past the end: massless and far away (r^2 ~ 1e300, so
             // their weight underflows to 0 instead of meeting a target at r = 0)
             const bool ok = k < wk.nj;
             const int j = wk.j0 + (ok ? k : 0);
-            S.x[e] = ok ? qx[j] : 1e150;
-            S.y[e] = ok ? qy[j] : 1e150;
-            S.z[e] = ok ? qz[j] : 1e150;
-            S.m[e] = ok ? m[j] : 0.0;
-            const double rcj = ok ? rc[j] : 0.0;
-            S.rc[e] = rcj;
-            S.r2[e] = fmax(rcj * rcj, DBL_MIN);
-            S.ax[e] = S.ay[e] = S.az[e] = 0.0;
+            put_src64(tl[k / T], k % T, ok ? qx[j] : 1e150, ok ? qy[j] : 1e150, ok ? qz[j] : 1e150,
+                      ok ? m[j] : 0.0, ok ? rc[j] : 0.0);
         }
         __syncthreads();
         // this wave's target tile: tni bodies from ti0 (none when tni <= 0)
@@ -1434,11 +1588,11 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force64_sym(const FW
             const bool go = tni > 0 && s * T < wk.nj && !(diag && 2 * k == G && wv >= G / 2);
             if (go) {
                 if (diag && k == 0)
-                    sym_tile64<R, true, T>(tl[s], lane, ti0, tni, inner, rc, xi, yi, zi, mi, tmi,
-                                           ax, ay, az, near);
-                else
-                    sym_tile64<R, false, T>(tl[s], lane, ti0, tni, inner, rc, xi, yi, zi, mi, tmi,
+                    sym_round64<R, true, T>(tl[s], lane, ti0, tni, inner, rc, xi, yi, zi, mi, tmi,
                                             ax, ay, az, near);
+                else
+                    sym_round64<R, false, T>(tl[s], lane, ti0, tni, inner, rc, xi, yi, zi, mi, tmi,
+                                             ax, ay, az, near);
             }
             __syncthreads();
         }
@@ -1463,7 +1617,7 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force64_sym(const FW
         if (!diag) {
             // super-tile J's sums to slot I
             for (int k = threadIdx.x; k < wk.nj; k += 64 * G) {
-                const SymTile64<T> &S = tl[k / T];
+                const Tile &S = tl[k / T];
                 const int e = k % T, j = wk.j0 + k;
                 fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = S.ax[e];
                 fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = S.ay[e];
@@ -1483,8 +1637,11 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force64_sym(const FW
 // merged by two-sum into a (hi, lo) pair per target.  Tile J's sums: an FP32
 // run sum per source in LDS over the same 32 steps, added to the source's FP64
 // total when the run ends.  Changeover pairs in FP64 from the FP64 state: the
-// target's part goes straight to its split partial (read back and added when
-// the item ends), the source's part to its FP64 total.
+// target's part into its (hi, lo) pair, the source's part to its FP64 total.
+// Each split partial is stored rounded to FP32: a rounding of at most 2^-24 of
+// the partial, which is at most the sum of its terms' magnitudes, so all of a
+// body's partials together add at most 2^-24 A_i (A_i the sum of the magnitudes
+// of its pair terms), below the FP32 pair terms' own error.
 // Aligned to 1024 bytes, so that the LDS address of a[64 t + (lane xor k)]
 // is that of a[64 t + lane] with 16 k xored in (k < 64): one VALU per step
 // addresses a[], b[] and run[] (fixed offsets 16 T and 32 T from a[]).
@@ -1500,34 +1657,39 @@ static_assert(offsetof(SymTile32<64>, b) == 16 * 64 && offsetof(SymTile32<64>, r
 static_assert(offsetof(SymTile32<128>, b) == 16 * 128 && offsetof(SymTile32<128>, run) == 32 * 128,
               "SymTile32 layout");
 
+// The target's FP64 part of a changeover pair (hit: the pair was one).
+struct ChgPart {
+    double x, y, z;
+    int hit;
+};
+
 // The rare branch of the FP32C pair loop, out of line so that it adds nothing
 // to the loop: target li of the item (position i0 + li, or a padded copy of
 // position i0 when li >= ni) against source jj (position j0 + jj, found from the
 // LDS addresses of its record, ja, and of the tile's first record, a0) at FP32
 // squared distance r2.  Positions are body indices, or with a sorted order
 // (ord != nullptr) the bodies ord[position].
-// Unless r2 is inside the pair's widened critical radius it returns false.
-// Otherwise the pair is evaluated in FP64 from the FP64 state: m_j w (Q_j - Q_i)
-// goes to the target's split partial at fp[i], fp[plane + i], fp[2 plane + i]
-// (i its position; stored when `first`, else added; nothing for a padded
-// target) and -m_i w (Q_j - Q_i) to source jj's FP64 totals tot[jj],
-// tot[T + jj], tot[2 T + jj]; it returns true.
-__device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4 *__restrict__ pk,
-                                               int i0, int li, int ni, int j0, uint32_t ja,
-                                               uint32_t a0, int T,
-                                               double *tot, double *fp, size_t plane, bool first,
-                                               const double *__restrict__ qx,
-                                               const double *__restrict__ qy,
-                                               const double *__restrict__ qz,
-                                               const double *__restrict__ m,
-                                               const double *__restrict__ rc, double inner,
-                                               const int *__restrict__ ord)
+// Unless r2 is inside the pair's widened critical radius it returns hit = 0.
+// Otherwise the pair is evaluated in FP64 from the FP64 state: -m_i w (Q_j - Q_i)
+// goes to source jj's FP64 totals tot[jj], tot[T + jj], tot[2 T + jj], and the
+// target's part m_j w (Q_j - Q_i) is returned (zero for a padded target).
+__device__ __noinline__ ChgPart changeover_pair32(float r2, float r2j, const float4 *__restrict__ pk,
+                                                  int i0, int li, int ni, int j0, uint32_t ja,
+                                                  uint32_t a0, int T, double *tot,
+                                                  const double *__restrict__ qx,
+                                                  const double *__restrict__ qy,
+                                                  const double *__restrict__ qz,
+                                                  const double *__restrict__ m,
+                                                  const double *__restrict__ rc, double inner,
+                                                  const int *__restrict__ ord)
 {
+    ChgPart out{0.0, 0.0, 0.0, 0};
     const bool ok = li < ni;
     const int i = i0 + (ok ? li : 0);
     const int bi = ord ? ord[i] : i;
     if (!(r2 < max_nonneg(pk[2 * (size_t)bi + 1].w, r2j)))
-        return false;
+        return out;
+    out.hit = 1;
     const int jj = (int)((ja - a0) >> 4);
     const int bj = ord ? ord[j0 + jj] : j0 + jj;
     const double gx = qx[bj] - qx[bi], gy = qy[bj] - qy[bi], gz = qz[bj] - qz[bi];
@@ -1535,21 +1697,24 @@ __device__ __noinline__ bool changeover_pair32(float r2, float r2j, const float4
     const double w = changeover_w_inl(d2, fmax(rc[bi], rc[bj]), inner);
     if (ok) {
         const double wi = m[bj] * w;
-        if (first) {
-            fp[i] = wi * gx;
-            fp[plane + i] = wi * gy;
-            fp[2 * plane + i] = wi * gz;
-        } else {
-            fp[i] = fma(wi, gx, fp[i]);
-            fp[plane + i] = fma(wi, gy, fp[plane + i]);
-            fp[2 * plane + i] = fma(wi, gz, fp[2 * plane + i]);
-        }
+        out.x = wi * gx;
+        out.y = wi * gy;
+        out.z = wi * gz;
         const double wj = m[bi] * w;
         tot[jj] = fma(-wj, gx, tot[jj]);
         tot[T + jj] = fma(-wj, gy, tot[T + jj]);
         tot[2 * T + jj] = fma(-wj, gz, tot[2 * T + jj]);
     }
-    return true;
+    return out;
+}
+
+// An FP64 term into a (hi, lo) FP32 accumulator: its leading float by two-sum,
+// the float of the remainder into lo.
+__device__ __forceinline__ void add_f64_to_pair(float &hi, float &lo, double v)
+{
+    const float vh = (float)v;
+    two_sum_f(hi, lo, vh);
+    lo += (float)(v - (double)vh);
 }
 
 // What the FP32C pair loop needs for the encounter test fused into it (sorted
@@ -1600,8 +1765,7 @@ static_assert(offsetof(SymTile32E<64>, em) == sizeof(SymTile32<64>) &&
 // offsets past the FP32C fields (em, ec of SymTile32E).
 template <int R, bool DIAG, int T, bool ENC = false>
 __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, int ni, int j0,
-                                            double *fp, size_t plane, double inner,
-                                            const float4 *__restrict__ pk,
+                                            double inner, const float4 *__restrict__ pk,
                                             const double *__restrict__ qx,
                                             const double *__restrict__ qy,
                                             const double *__restrict__ qz,
@@ -1612,7 +1776,7 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                                             const float (&zl)[R], const float (&mi)[R], float tmi,
                                             float (&hx)[R], float (&hy)[R], float (&hz)[R],
                                             float (&lx)[R], float (&ly)[R], float (&lz)[R],
-                                            int &rare, int &near, const int *__restrict__ ord,
+                                            int &near, const int *__restrict__ ord,
                                             const EncCtx &ec, const float4 (&emi)[R],
                                             const float4 (&eci)[R], unsigned live)
 {
@@ -1690,13 +1854,17 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
 #pragma unroll
                     for (int r = 0; r < R; ++r) {
                         const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
-                        if (r2r[r] < thr && on &&
-                            changeover_pair32(r2r[r], B.w, pk, i0, 64 * r + lane, ni, j0, ac, a0, T,
-                                              L.ax, fp, plane, !((rare >> r) & 1), qx, qy, qz, m,
-                                              rc, inner, ord)) {
-                            rare |= 1 << r;
-                            qr[r] = 0.0f;
-                            ++near;
+                        if (r2r[r] < thr && on) {
+                            const ChgPart c = changeover_pair32(r2r[r], B.w, pk, i0, 64 * r + lane,
+                                                                ni, j0, ac, a0, T, L.ax, qx, qy,
+                                                                qz, m, rc, inner, ord);
+                            if (c.hit) {
+                                add_f64_to_pair(hx[r], lx[r], c.x);
+                                add_f64_to_pair(hy[r], ly[r], c.y);
+                                add_f64_to_pair(hz[r], lz[r], c.z);
+                                qr[r] = 0.0f;
+                                ++near;
+                            }
                         }
                         if (ENC && encr[r])
                             enc_candidate(ec.srec, ec.dt, ec.keys, ec.cap, ec.ce, ec.stats,
@@ -1747,7 +1915,7 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
                                                          const double *__restrict__ qz,
                                                          const double *__restrict__ m,
                                                          const double *__restrict__ rc,
-                                                         double *__restrict__ fpart, int ntot,
+                                                         float *__restrict__ fpart, int ntot,
                                                          int maxs, double inner, DevStats *stats)
 {
     constexpr int T = 64 * R;
@@ -1795,9 +1963,6 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
             hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
         }
         tmi = wave_max_nonneg(tmi);
-        // bit r: target r's split partial already holds FP64 changeover terms
-        int rare = 0;
-        double *fp = fpart + (size_t)wk.slot * ntot;
         const EncCtx noenc{};
         float4 noem[R];
         // Round k: wave w pairs its target tile with source tile (w + k) mod G, so
@@ -1812,15 +1977,14 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
             const bool go = tni > 0 && s * T < wk.nj && !(diag && 2 * k == G && wv >= G / 2);
             if (go) {
                 if (diag && k == 0)
-                    sym_tile32c<R, true, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, fp, plane, inner,
-                                            pk, qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi,
-                                            hx, hy, hz, lx, ly, lz, rare, near, nullptr, noenc,
-                                            noem, noem, 0u);
+                    sym_tile32c<R, true, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, inner, pk, qx,
+                                            qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx, hy,
+                                            hz, lx, ly, lz, near, nullptr, noenc, noem, noem, 0u);
                 else
-                    sym_tile32c<R, false, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, fp, plane,
-                                             inner, pk, qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl,
-                                             mi, tmi, hx, hy, hz, lx, ly, lz, rare, near, nullptr,
-                                             noenc, noem, noem, 0u);
+                    sym_tile32c<R, false, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, inner, pk, qx,
+                                             qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx,
+                                             hy, hz, lx, ly, lz, near, nullptr, noenc, noem, noem,
+                                             0u);
             }
             __syncthreads();
         }
@@ -1834,19 +1998,14 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
                 double sx_ = (double)hx[r] + (double)lx[r];
                 double sy_ = (double)hy[r] + (double)ly[r];
                 double sz_ = (double)hz[r] + (double)lz[r];
-                if ((rare >> r) & 1) {
-                    sx_ += fp[i];
-                    sy_ += fp[plane + i];
-                    sz_ += fp[2 * plane + i];
-                }
                 if (diag) {
                     sx_ += tl[wv].ax[li];
                     sy_ += tl[wv].ay[li];
                     sz_ += tl[wv].az[li];
                 }
-                fp[i] = sx_;
-                fp[plane + i] = sy_;
-                fp[2 * plane + i] = sz_;
+                fpart[(size_t)wk.slot * ntot + i] = (float)sx_;
+                fpart[plane + (size_t)wk.slot * ntot + i] = (float)sy_;
+                fpart[2 * plane + (size_t)wk.slot * ntot + i] = (float)sz_;
             }
         }
         if (!diag) {
@@ -1854,9 +2013,9 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
             for (int k = threadIdx.x; k < wk.nj; k += 64 * G) {
                 const SymTile32<T> &S = tl[k / T];
                 const int e = k % T, j = wk.j0 + k;
-                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = S.ax[e];
-                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = S.ay[e];
-                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = S.az[e];
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = (float)S.ax[e];
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = (float)S.ay[e];
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = (float)S.az[e];
             }
         }
         __syncthreads();
@@ -1878,8 +2037,9 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
 // kicks.
 constexpr int kFinThreads = 1024;
 
+template <typename P>
 __global__ __launch_bounds__(kFinThreads) void k_force_finalize(
-    const int *__restrict__ sys_of, const int *__restrict__ nsplit, const double *__restrict__ fpart,
+    const int *__restrict__ sys_of, const int *__restrict__ nsplit, const P *__restrict__ fpart,
     int ntot, int maxs, int ns_all, int nsl, double G, double *__restrict__ ax,
     double *__restrict__ ay, double *__restrict__ az, double h, int kicks, double *vx, double *vy,
     double *vz, const int *__restrict__ ord, int count_cap, DevStats *stats)
@@ -1912,10 +2072,10 @@ __global__ __launch_bounds__(kFinThreads) void k_force_finalize(
         // ns_all != 0: every system has that split count
         const int ns = ns_all ? ns_all : nsplit[sys_of[i]];
         const int k0 = g * ns / nsl, k1 = (g + 1) * ns / nsl;
-        const double *px = fpart + i, *py = px + (size_t)maxs * ntot, *pz = py + (size_t)maxs * ntot;
+        const P *px = fpart + i, *py = px + (size_t)maxs * ntot, *pz = py + (size_t)maxs * ntot;
         int k = k0;
         for (; k + 8 <= k1; k += 8) {
-            double ux[8], uy[8], uz[8];
+            P ux[8], uy[8], uz[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 ux[u] = px[(size_t)(k + u) * ntot];
@@ -1924,15 +2084,15 @@ __global__ __launch_bounds__(kFinThreads) void k_force_finalize(
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                s0 += ux[u];
-                s1 += uy[u];
-                s2 += uz[u];
+                s0 += (double)ux[u];
+                s1 += (double)uy[u];
+                s2 += (double)uz[u];
             }
         }
         for (; k < k1; ++k) {
-            s0 += px[(size_t)k * ntot];
-            s1 += py[(size_t)k * ntot];
-            s2 += pz[(size_t)k * ntot];
+            s0 += (double)px[(size_t)k * ntot];
+            s1 += (double)py[(size_t)k * ntot];
+            s2 += (double)pz[(size_t)k * ntot];
         }
     }
     if (g > 0) {
@@ -2337,8 +2497,12 @@ __global__ void k_cells(const RBlk *__restrict__ rblk, const int *__restrict__ r
 
 // Exclusive scan of the cell counts (one workgroup), zeroing them for the next
 // step, and reset of the surviving-tile-pair counter.
-constexpr int kScanThreads = 1024;
-constexpr int kScanChunk = 4 * kScanThreads;   // cells per block pass, 4 per thread
+// 256 threads (one wave per SIMD): blocks this small still find room on a CU
+// beside the force pass's waves, so the encounter check's scan need not wait
+// for the force pass to drain a whole CU.
+constexpr int kScanThreads = 256;
+constexpr int kScanChunk = kScanChunkCells;    // cells per block pass, 4 per thread
+static_assert(kScanChunk == 4 * kScanThreads, "four cells per scan thread");
 
 // Exclusive scan over the kScanThreads threads of a block; *total gets the sum.
 __device__ __forceinline__ int block_exscan(int v, int *sh, int &total)
@@ -2872,7 +3036,7 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 1 : 2) void k_force32c_fused(
     const float4 *__restrict__ pk, const float4 *__restrict__ em, const TileB *__restrict__ tileb,
     const int *__restrict__ tile_first, const int *__restrict__ off, const double *__restrict__ qx,
     const double *__restrict__ qy, const double *__restrict__ qz, const double *__restrict__ m,
-    const double *__restrict__ rc, double *__restrict__ fpart, int ntot, int maxs, double inner,
+    const double *__restrict__ rc, float *__restrict__ fpart, int ntot, int maxs, double inner,
     EncCtx ec)
 {
     constexpr int T = 64 * R;
@@ -2925,8 +3089,6 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 1 : 2) void k_force32c_fused(
             hx[r] = hy[r] = hz[r] = lx[r] = ly[r] = lz[r] = 0.0f;
         }
         tmi = wave_max_nonneg(tmi);
-        int rare = 0;
-        double *fp = fpart + (size_t)wk.slot * ntot;
         const int nr = diag ? G / 2 + 1 : G;
         // The tile pairs that may hold a flagged pair, for every round at once:
         // lane (k R + t) R + r bounds target sub-tile r against sub-tile t of
@@ -2954,15 +3116,15 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 1 : 2) void k_force32c_fused(
                 const unsigned live =
                     (unsigned)(livemask >> (k * R * R)) & (unsigned)((1ull << (R * R)) - 1ull);
                 if (diag && k == 0)
-                    sym_tile32c<R, true, T, true>(tl[s].t, lane, ti0, tni, sj0, fp, plane, inner, pk,
-                                                  qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi,
-                                                  tmi, hx, hy, hz, lx, ly, lz, rare, near, ord, ec,
-                                                  emi, eci, live);
+                    sym_tile32c<R, true, T, true>(tl[s].t, lane, ti0, tni, sj0, inner, pk, qx, qy,
+                                                  qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx,
+                                                  hy, hz, lx, ly, lz, near, ord, ec, emi, eci,
+                                                  live);
                 else
-                    sym_tile32c<R, false, T, true>(tl[s].t, lane, ti0, tni, sj0, fp, plane, inner, pk,
-                                                   qx, qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi,
-                                                   tmi, hx, hy, hz, lx, ly, lz, rare, near, ord, ec,
-                                                   emi, eci, live);
+                    sym_tile32c<R, false, T, true>(tl[s].t, lane, ti0, tni, sj0, inner, pk, qx, qy,
+                                                   qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx,
+                                                   hy, hz, lx, ly, lz, near, ord, ec, emi, eci,
+                                                   live);
             }
             __syncthreads();
         }
@@ -2974,28 +3136,23 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 1 : 2) void k_force32c_fused(
                 double sx_ = (double)hx[r] + (double)lx[r];
                 double sy_ = (double)hy[r] + (double)ly[r];
                 double sz_ = (double)hz[r] + (double)lz[r];
-                if ((rare >> r) & 1) {
-                    sx_ += fp[i];
-                    sy_ += fp[plane + i];
-                    sz_ += fp[2 * plane + i];
-                }
                 if (diag) {
                     sx_ += tl[wv].t.ax[li];
                     sy_ += tl[wv].t.ay[li];
                     sz_ += tl[wv].t.az[li];
                 }
-                fp[i] = sx_;
-                fp[plane + i] = sy_;
-                fp[2 * plane + i] = sz_;
+                fpart[(size_t)wk.slot * ntot + i] = (float)sx_;
+                fpart[plane + (size_t)wk.slot * ntot + i] = (float)sy_;
+                fpart[2 * plane + (size_t)wk.slot * ntot + i] = (float)sz_;
             }
         }
         if (!diag) {
             for (int k = threadIdx.x; k < wk.nj; k += 64 * G) {
                 const SymTile32<T> &S = tl[k / T].t;
                 const int e = k % T, j = wk.j0 + k;
-                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = S.ax[e];
-                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = S.ay[e];
-                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = S.az[e];
+                fpart[((size_t)0 * maxs + wk.pad) * ntot + j] = (float)S.ax[e];
+                fpart[((size_t)1 * maxs + wk.pad) * ntot + j] = (float)S.ay[e];
+                fpart[((size_t)2 * maxs + wk.pad) * ntot + j] = (float)S.az[e];
             }
         }
         __syncthreads();
@@ -3795,7 +3952,7 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
         const int grid = std::min(d.nfw, 1 << 22);
 #define NB_SYM_ARGS d.fwork, d.nfw, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart, d.ntot, d.maxs, \
                     p.inner, d.stats
-#define NB_SYM32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart, d.ntot, \
+#define NB_SYM32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart32, d.ntot, \
                       d.maxs, p.inner, d.stats
 #define NB_SYM_G(R_)                                                                          \
     do {                                                                                      \
@@ -3831,7 +3988,7 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
         const int grid = std::min(cdiv(d.nfw, kWaves), 2048);
 #define NB_FEW_ARGS d.fwork, d.nfw, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart, d.ntot, d.maxs, \
                     p.inner, d.stats
-#define NB_FEW32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart, d.ntot, \
+#define NB_FEW32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.tile_rc2, d.fpart32, d.ntot, \
                       d.maxs, p.inner, d.stats
         if (p.mode == 1) {
             if (p.force_r == 1)
@@ -3856,15 +4013,15 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
         switch (p.force_r) {
         case 1:
             k_force32c<1><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
-                                                    d.tile_rc2, d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+                                                    d.tile_rc2, d.fpart32, d.ntot, d.maxs, p.inner, d.stats);
             break;
         case 4:
             k_force32c<4><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
-                                                    d.tile_rc2, d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+                                                    d.tile_rc2, d.fpart32, d.ntot, d.maxs, p.inner, d.stats);
             break;
         default:
             k_force32c<2><<<d.nfw, kBlock, 0, s>>>(d.fwork, d.pk, d.qx, d.qy, d.qz, d.m, d.rc,
-                                                    d.tile_rc2, d.fpart, d.ntot, d.maxs, p.inner, d.stats);
+                                                    d.tile_rc2, d.fpart32, d.ntot, d.maxs, p.inner, d.stats);
         }
     } else {
         switch (p.force_r) {
@@ -3896,9 +4053,15 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, i
     int nsl = 1;
     while (nsl < 16 && nsl * 8 < d.maxs)
         nsl *= 2;
-    k_force_finalize<<<cdiv(d.ntot, kFinThreads / nsl), kFinThreads, 0, s>>>(
-        d.sys_of, d.nsplit, d.fpart, d.ntot, d.maxs, d.ns_all, nsl, p.G, d.ax, d.ay, d.az, kick_h,
-        kicks, d.vx, d.vy, d.vz, ord, enc_count ? d.enc_cap : -1, d.stats);
+    const int grid = cdiv(d.ntot, kFinThreads / nsl), cc = enc_count ? d.enc_cap : -1;
+    if (d.fpart32)
+        k_force_finalize<float><<<grid, kFinThreads, 0, s>>>(
+            d.sys_of, d.nsplit, d.fpart32, d.ntot, d.maxs, d.ns_all, nsl, p.G, d.ax, d.ay, d.az,
+            kick_h, kicks, d.vx, d.vy, d.vz, ord, cc, d.stats);
+    else
+        k_force_finalize<double><<<grid, kFinThreads, 0, s>>>(
+            d.sys_of, d.nsplit, d.fpart, d.ntot, d.maxs, d.ns_all, nsl, p.G, d.ax, d.ay, d.az,
+            kick_h, kicks, d.vx, d.vy, d.vz, ord, cc, d.stats);
     return hipGetLastError();
 }
 
@@ -3976,7 +4139,7 @@ hipError_t launch_force_fused(const Dev &d, const Params &p, double dt, int coun
         const int grid = std::min(d.nfw, 1 << 22);
         const EncCtx ec{d.srec, dt, d.keys, d.enc_cap, d.ce, d.stats};
 #define NB_FUSED_ARGS d.fwork, d.nfw, d.ord, d.pk, d.em, d.tileb, d.tile_first, d.off, d.qx, d.qy, \
-                      d.qz, d.m, d.rc, d.fpart, d.ntot, d.maxs, p.inner, ec
+                      d.qz, d.m, d.rc, d.fpart32, d.ntot, d.maxs, p.inner, ec
 #define NB_FUSED_G(R_)                                                                        \
     do {                                                                                      \
         if (d.sym_g == 4)                                                                     \

@@ -103,7 +103,7 @@ int nb_force_noalloc(const nb_params *p, int n, double m0, const double *m, cons
     const size_t o_pk = take(p->mode == NB_FP32C ? (size_t)n * 2 * sizeof(float4) : 0);
     const size_t o_fw = take((size_t)nitems * sizeof(FWork));
     const size_t o_st = take(sizeof(DevStats));
-    const size_t o_fp = take((size_t)3 * nt * n * sizeof(double));
+    const size_t o_fp = take((size_t)3 * nt * n * (p->mode == NB_FP32C ? sizeof(float) : sizeof(double)));
     if (at > kScratchBytes)
         return NB_E_WORKSPACE;
 
@@ -129,7 +129,10 @@ int nb_force_noalloc(const nb_params *p, int n, double m0, const double *m, cons
     d.maxs = nt;
     d.ns_all = nt;
     d.stats = (DevStats *)(b + o_st);
-    d.fpart = (double *)(b + o_fp);
+    if (p->mode == NB_FP32C)
+        d.fpart32 = (float *)(b + o_fp);
+    else
+        d.fpart = (double *)(b + o_fp);
     d.force_sym = 1;
     d.sym_g = g;
 

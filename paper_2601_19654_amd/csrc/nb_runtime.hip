@@ -347,20 +347,22 @@ void pair_items(int a, int n, int nb, int J, std::vector<PWork> &out)
     }
 }
 
-// Split partials of the symmetric force: 3 doubles per body and super-tile of
-// TI bodies of its system (quadratic in the system size).
+// Split partials of the symmetric force: 3 values per body and super-tile of
+// TI bodies of its system (quadratic in the system size; doubles, or floats with
+// FP32C pair arithmetic).
 constexpr long long kSymPartialMax = 4ll << 30;
 
 // Most source chunks per system of the ordered force (its partials: 3 doubles
 // per body and chunk).
 constexpr int kMaxOrderedSplits = 64;
 
-long long sym_partial_bytes(int nsys, const int32_t *off, int TI)
+long long sym_partial_bytes(const Params &p, int nsys, const int32_t *off, int TI)
 {
+    const long long per = p.mode == NB_FP32C ? 3 * sizeof(float) : 3 * sizeof(double);
     long long b = 0;
     for (int s = 0; s < nsys; ++s) {
         const long long n = off[s + 1] - off[s];
-        b += 24 * n * ((n + TI - 1) / TI);
+        b += per * n * ((n + TI - 1) / TI);
     }
     return b;
 }
@@ -399,12 +401,12 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
     t.enc_few = ea == 3;
     t.enc_fused = ea == 4;
     // symmetric tile pairs: every body big (asked for, or automatic while their
-    // split partials, 3 doubles per body and tile of its system, stay within
+    // split partials, 3 values per body and tile of its system, stay within
     // kSymPartialMax; beyond that the ordered pairs' partials are bounded)
     t.sym_g = sym_width(p, nsys, off);
     t.force_sym = p.force_algo != 1 && !has_small(nsys, off, nbig) &&
                   (p.force_algo == 2 ||
-                   sym_partial_bytes(nsys, off, t.sym_g * 64 * p.force_r) <= kSymPartialMax);
+                   sym_partial_bytes(p, nsys, off, t.sym_g * 64 * p.force_r) <= kSymPartialMax);
     // the fused pass is the symmetric force's: without it, the sorted check alone
     t.enc_fused = t.enc_fused && t.force_sym;
     t.rb_first.assign(nsys, 0);
@@ -590,7 +592,14 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     for (int s = 0; s < nsys; ++s)
         if (t.rb_count[s] > 64)
             d.sys_total = 1;
-    d.fpart = (double *)take((size_t)3 * d.maxs * ntot * sizeof(double));
+    // split partials: FP32 with FP32C pair arithmetic (each rounding at most
+    // 2^-24 of a partial, so of A_i over all of a body's partials), else FP64
+    d.fpart = nullptr;
+    d.fpart32 = nullptr;
+    if (p.mode == NB_FP32C)
+        d.fpart32 = (float *)take((size_t)3 * d.maxs * ntot * sizeof(float));
+    else
+        d.fpart = (double *)take((size_t)3 * d.maxs * ntot * sizeof(double));
     d.dpart = (double *)take((size_t)std::max(d.ndw, 1) * 4 * sizeof(double));
     d.bpart = (double *)take((size_t)std::max(d.nrb, 1) * 8 * sizeof(double));
     d.diag = (double *)take((size_t)nsys * 8 * sizeof(double));
@@ -618,7 +627,7 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
         d.ncell = t.ncell;
         d.cell_cnt = (int *)take((size_t)t.ncell * sizeof(int));
         d.cell_off = (int *)take((size_t)t.ncell * sizeof(int));
-        d.scan_part = (int *)take((size_t)(t.ncell / 4096 + 1) * sizeof(int));
+        d.scan_part = (int *)take((size_t)(t.ncell / kScanChunkCells + 1) * sizeof(int));
         d.sys_cell_base = (int *)take((size_t)nsys * sizeof(int));
         d.sys_cell_cnt = (int *)take((size_t)nsys * sizeof(int));
         d.ord = (int *)take((size_t)ntot * sizeof(int));
