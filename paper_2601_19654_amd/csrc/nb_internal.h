@@ -9,6 +9,10 @@ namespace nb {
 
 constexpr int kBlock = 256;      // threads of every O(N) kernel and of the pair kernels
 constexpr int kScanChunkCells = 1024;   // cells per block of the counting sort's scan
+// Sets of drift outputs (what the encounter check of a step reads): one per
+// step of a captured run, so that the checks of a run, on a second queue, hold
+// up no drift of the run (a run ends with one join).
+constexpr int kSnapSets = 8;
 
 // Work items the automatic super-tile width g (2 or 4) of the symmetric force
 // needs (one workgroup of g waves per item).
@@ -176,18 +180,19 @@ struct Dev {
                           // the few-source force kernels
     int force_sym;        // every body big: work items are unordered pairs of super-tiles
     int sym_g;            // tiles per super-tile (1, 2 or 4; the symmetric kernels' waves)
-    Snap alt;             // the second set of drift outputs
+    Snap alt[kSnapSets - 1];   // sets 1 .. nsnap - 1 of drift outputs
+    int nsnap;            // sets of drift outputs (2 .. kSnapSets)
 
     Snap snap() const
     {
         return Snap{q0x, q0y, q0z, v0x, v0y, v0z, q1x, q1y, q1z, v1x, v1y, v1z, rc1, mr, cr, lnr_part};
     }
-    // this context with the drift outputs of set `parity` (0: the first set)
-    Dev with_snap(int parity) const
+    // this context with the drift outputs of set `set` (0: the first set)
+    Dev with_snap(int set) const
     {
         Dev e = *this;
-        if (parity) {
-            const Snap a = alt;
+        if (set > 0) {
+            const Snap a = alt[set - 1];
             e.q0x = a.q0x; e.q0y = a.q0y; e.q0z = a.q0z;
             e.v0x = a.v0x; e.v0y = a.v0y; e.v0z = a.v0z;
             e.q1x = a.q1x; e.q1y = a.q1y; e.q1z = a.q1z;

@@ -45,7 +45,7 @@ struct nb_ctx {
     // second stream on which the sorted encounter test overlaps S(h) and the force
     hipStream_t side = nullptr;
     // one fork and one join event per set of drift outputs
-    hipEvent_t ev_fork[2] = {nullptr, nullptr}, ev_join[2] = {nullptr, nullptr};
+    hipEvent_t ev_fork[kSnapSets] = {}, ev_join[kSnapSets] = {};
     int snap = 0;         // the set of drift outputs the latest drift wrote
     // rpart_prev() holds the momentum of the current V (kept by the steps)
     bool mom_valid = false;
@@ -533,6 +533,20 @@ int next_pow2(int n)
 }
 
 // Carve the workspace (base == nullptr: sizes only).  Returns total bytes.
+// Bytes of drift outputs the further sets may take.
+constexpr long long kSnapSetBytes = 1ll << 30;
+
+// Sets of drift outputs: kSnapSets when the check of a step may run on a second
+// queue (per-phase steps, the check outside the force pass, no host resolver)
+// and the further sets fit in kSnapSetBytes; else two.
+int snap_sets(const Params &p, const Tables &t, int ntot)
+{
+    const long long per = (long long)ntot * (13 * sizeof(double) + 2 * sizeof(double4));
+    if (p.resolve || p.step_algo == 2 || t.enc_fused || per * (kSnapSets - 1) > kSnapSetBytes)
+        return 2;
+    return kSnapSets;
+}
+
 size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, char *base, Dev &d)
 {
     size_t cur = 0;
@@ -552,15 +566,17 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.pk = (float4 *)take((size_t)ntot * 2 * sizeof(float4));
     d.mr = (double4 *)take((size_t)ntot * sizeof(double4));
     d.cr = (double4 *)take((size_t)ntot * sizeof(double4));
-    {
-        // the second set of drift outputs
-        double **alt[] = {&d.alt.q0x, &d.alt.q0y, &d.alt.q0z, &d.alt.v0x, &d.alt.v0y,
-                          &d.alt.v0z, &d.alt.q1x, &d.alt.q1y, &d.alt.q1z, &d.alt.v1x,
-                          &d.alt.v1y, &d.alt.v1z, &d.alt.rc1};
+    // further sets of drift outputs: one per step of a captured run when the
+    // check runs on a second queue and the sets stay within kSnapSetBytes, else two
+    d.nsnap = snap_sets(p, t, ntot);
+    for (int k = 0; k + 1 < d.nsnap; ++k) {
+        Snap &a = d.alt[k];
+        double **alt[] = {&a.q0x, &a.q0y, &a.q0z, &a.v0x, &a.v0y, &a.v0z, &a.q1x,
+                          &a.q1y, &a.q1z, &a.v1x, &a.v1y, &a.v1z, &a.rc1};
         for (double **pl : alt)
             *pl = (double *)take(nd);
-        d.alt.mr = (double4 *)take((size_t)ntot * sizeof(double4));
-        d.alt.cr = (double4 *)take((size_t)ntot * sizeof(double4));
+        a.mr = (double4 *)take((size_t)ntot * sizeof(double4));
+        a.cr = (double4 *)take((size_t)ntot * sizeof(double4));
     }
     d.kflag = (int *)take((size_t)ntot * sizeof(int));
     d.ce = (int *)take((size_t)ntot * sizeof(int));
@@ -621,7 +637,8 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.sym_g = t.sym_g;
     if (d.enc_sorted) {
         d.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
-        d.alt.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
+        for (int k = 0; k + 1 < d.nsnap; ++k)
+            d.alt[k].lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
         d.cell_of = (int *)take((size_t)ntot * sizeof(int));
         d.slot_of = (int *)take((size_t)ntot * sizeof(int));
         d.ncell = t.ncell;
@@ -757,9 +774,10 @@ int enqueue_step_tail(nb_ctx *c, double dt, bool last)
 
 // A run of `steps` steps (kicks merged between them).  On a context with a
 // stream the encounter check of a step runs on a second stream (graph branches
-// under capture) beside the rest of that step and the next one: the drifts
-// write the two sets of drift outputs in turn, and a drift waits only for the
-// check that read its set two steps earlier; the run ends with a join.  The
+// under capture) beside the rest of that step and the next ones: the drifts
+// write the nsnap sets of drift outputs in turn, and a drift waits only for the
+// check that read its set nsnap steps earlier (none in a captured run of at most
+// nsnap steps); the run ends with a join.  The
 // step's own chain is enqueued (recorded) before the branch, so that it keeps
 // the stream's hardware queue and only the branch and the joins cross queues.
 int enqueue_run(nb_ctx *c, double dt, int steps)
@@ -774,9 +792,9 @@ int enqueue_run(nb_ctx *c, double dt, int steps)
                 return r;
             continue;
         }
-        const int par = k & 1;
+        const int par = k % c->d.nsnap;
         const Dev d = c->d.with_snap(par);
-        if (k >= 2)
+        if (k >= c->d.nsnap)
             HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join[par], 0));
         if (first)
             HIP_OK(c, launch_kick(d, c->p, h, c->stream));
@@ -790,7 +808,7 @@ int enqueue_run(nb_ctx *c, double dt, int steps)
         c->snap = par;
     }
     if (c->side && !c->d.enc_fused && steps > 0)
-        HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join[(steps - 1) & 1], 0));
+        HIP_OK(c, hipStreamWaitEvent(c->stream, c->ev_join[(steps - 1) % c->d.nsnap], 0));
     return NB_OK;
 }
 
@@ -986,8 +1004,8 @@ int enqueue_steps(nb_ctx *c, double dt, int nsteps)
                 return r;
             HIP_OK(c, hipGraphLaunch(gx, c->stream));
         }
-        // a run's steps write the two sets of drift outputs in turn, from set 0
-        c->snap = ((rest > 0 ? rest : kMaxGraphSteps) - 1) & 1;
+        // a run's steps write the sets of drift outputs in turn, from set 0
+        c->snap = ((rest > 0 ? rest : kMaxGraphSteps) - 1) % c->d.nsnap;
         c->snap_valid = true;
         return NB_OK;
     }
@@ -1042,7 +1060,7 @@ void release(nb_ctx *c)
         (void)hipStreamSynchronize(c->side);
         (void)hipStreamDestroy(c->side);
     }
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kSnapSets; ++k) {
         if (c->ev_fork[k])
             (void)hipEventDestroy(c->ev_fork[k]);
         if (c->ev_join[k])
@@ -1240,12 +1258,12 @@ int nb_create(const nb_params *p, int nsys, const int32_t *off, const int32_t *n
     }
     if (r == NB_OK && c->stream) {
         // default priority, like every stream here
-        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_fork[0], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_join[0], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_fork[1], hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&c->ev_join[1], hipEventDisableTiming) != hipSuccess)
-            r = set_err(c, NB_E_HIP, "nb_create: side stream or events");
+        if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess)
+            r = set_err(c, NB_E_HIP, "nb_create: side stream");
+        for (int k = 0; r == NB_OK && k < kSnapSets; ++k)
+            if (hipEventCreateWithFlags(&c->ev_fork[k], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&c->ev_join[k], hipEventDisableTiming) != hipSuccess)
+                r = set_err(c, NB_E_HIP, "nb_create: side stream events");
     }
     if (r != NB_OK) {
         release(c);

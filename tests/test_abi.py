@@ -79,9 +79,11 @@ def test_workspace_size_and_validation(nb):
     assert _wsize(nb, [0, 10], resolve=2)[0] == nb.NB_E_INVALID
     assert _wsize(nb, [0, 10], resolve=1, step_algo=2)[0] == nb.NB_E_INVALID
     assert _wsize(nb, [0, 10], resolve=1, bs_tol=-1.0)[0] == nb.NB_E_INVALID
-    rc, plain = _wsize(nb, [0, 1000])
-    rc, full = _wsize(nb, [0, 1000], resolve=1)
-    assert rc == 0 and full > plain
+    # the resolver's buffers grow with the list capacity (records of both ends of
+    # every listed pair), beyond what the list itself takes
+    plain = [_wsize(nb, [0, 1000], enc_cap=cap)[1] for cap in (1024, 2048)]
+    full = [_wsize(nb, [0, 1000], enc_cap=cap, resolve=1)[1] for cap in (1024, 2048)]
+    assert full[1] - full[0] > plain[1] - plain[0] > 0
     # encounter check against the big bodies only: at most 256 big bodies per system
     assert _wsize(nb, [0, 1000], nbig=[100], enc_algo=3)[0] == 0
     assert _wsize(nb, [0, 1000], enc_algo=3)[0] == nb.NB_E_INVALID
