@@ -37,7 +37,8 @@ struct PWork {
     int i0, ni, j0, nj;
 };
 
-// A body's encounter record in spatially sorted order (sorted encounter check).
+// A body's encounter record in spatially sorted order (sorted encounter check;
+// the exact test reads the first 112 bytes, the filters read FP32 records).
 struct SRec {
     double q0[3], v0[3], q1[3], v1[3];
     double rc;
@@ -153,10 +154,15 @@ struct Dev {
     int2 *units; int nunit;   // culling units: tile A against tiles [b0, b0 + 64) (B >= A)
     int *tile_first;      // nsys: first tile of every system
     // force and encounter check in one pass over the sorted order (FP32C,
-    // every body big): per sorted position two FP32 records, the chord midpoint
-    // with the widened bound of 3/4 eps + rc, and the chord
+    // every body big)
     int enc_fused;
+    // sorted check: per sorted position two FP32 records for the pair filter,
+    // the chord midpoint with the widened bound of 3/4 eps + rc, and the chord
+    // with rc rounded up (its sign bit set for a small body) ...
     float4 *em;
+    // ... and one for the target's test against a tile's bounds: the mean
+    // endpoint deviation with the deviation radius rounded up
+    float4 *eg;
     // persistent step launch
     PSys *psys; int npsys; int pmax_n;
     int *step_nce; int step_chunk;   // flagged pairs per step of one launch
@@ -257,7 +263,7 @@ hipError_t launch_persistent_steps(const Dev &d, const Params &p, double dt, int
                                    hipStream_t s);
 hipError_t launch_step_stats(const Dev &d, int nsteps, hipStream_t s);
 hipError_t launch_enc_sort(const Dev &d, int accumulate, hipStream_t s);
-hipError_t launch_enc_gather(const Dev &d, hipStream_t s);
+hipError_t launch_enc_gather(const Dev &d, double dt, hipStream_t s);
 // fused mode, before the force: an empty list and no flags, the sorted order
 // and records of the last drift, and the tile bounds
 hipError_t launch_enc_prepare(const Dev &d, double dt, hipStream_t s);

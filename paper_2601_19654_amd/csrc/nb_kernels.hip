@@ -1728,8 +1728,8 @@ struct EncCtx {
     DevStats *stats;
 };
 
-// Relative-chord filter and exact encounter test of two sorted positions, with
-// the append of a flagged pair (defined with the encounter check).
+// Exact encounter test of two sorted positions, with the append of a flagged
+// pair (defined with the encounter check).
 __device__ __noinline__ void enc_candidate(const SRec *__restrict__ srec, double dt,
                                            unsigned long long *keys, int cap, int *ce,
                                            DevStats *stats, int pi, int pj);
@@ -1829,9 +1829,9 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                         qr[r] = on ? qr[r] : 0.0f;
                 }
                 // fused encounter test: the relative-chord filter in FP32,
-                // |dM|^2 <= 2 (|dc|^2 + (b'_i + b'_j)^2) with the bounds b'
-                // widened for the FP32 rounding (padded targets and sources
-                // carry NaN midpoints and never pass)
+                // |dM|^2 <= 2 (|dc|^2 + (b'_i + b'_j + max(rc_i, rc_j))^2) with
+                // the bounds b' widened for the FP32 rounding (padded targets
+                // and sources carry NaN midpoints and never pass)
                 bool encr[R] = {};
                 bool ecand = false;
                 if (ENC && livet) {
@@ -1843,7 +1843,7 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                         const float cx = F.x - eci[r].x, cy = F.y - eci[r].y, cz = F.z - eci[r].z;
                         const float D2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
                         const float C2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
-                        const float Sr = E.w + emi[r].w;
+                        const float Sr = (E.w + emi[r].w) + fmaxf(fabsf(F.w), fabsf(eci[r].w));
                         const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
                         encr[r] = ((livet >> r) & 1u) && on &&
                                   D2 <= fmaf(Sr, Sr, C2) * (2.0f * (1.0f + 0x1p-18f));
@@ -2677,7 +2677,7 @@ __global__ void k_srec(int ntot, const int *__restrict__ pos_of, const int *__re
                        const double *__restrict__ rc, const double4 *__restrict__ mr,
                        const double4 *__restrict__ cr, const int *__restrict__ off,
                        const int *__restrict__ nbig, SRec *__restrict__ srec,
-                       float4 *__restrict__ em)
+                       float4 *__restrict__ em, float4 *__restrict__ eg, double dt)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ntot)
@@ -2699,14 +2699,27 @@ __global__ void k_srec(int ntot, const int *__restrict__ pos_of, const int *__re
     r.pad = 0.0;
     srec[pos] = r;
     if (em) {
-        // FP32 records of the fused test: midpoint M and chord c, and the bound
-        // b' of 3/4 eps + rc widened by 2^-21 (|M|_1 + |c|_1) for the FP32
+        // FP32 records of the pair filter: midpoint M and chord c, and the
+        // bound b' of 3/4 eps widened by 2^-21 (|M|_1 + |c|_1) for the FP32
         // rounding of M, c and their differences, and by 2^-18 relative for the
-        // rounding of the bound itself
-        const double w = (C.w + rc[i] + 0x1p-21 * (fabs(M.x) + fabs(M.y) + fabs(M.z) + fabs(C.x) +
-                                                   fabs(C.y) + fabs(C.z))) * (1.0 + 0x1p-18);
+        // rounding of the bound itself; the chord's fourth word is rc rounded up,
+        // negated (sign bit set, also for rc = 0) for a small body.  A pair's
+        // bound is b'_i + b'_j + max(rc_i, rc_j).
+        const double w = (C.w + 0x1p-21 * (fabs(M.x) + fabs(M.y) + fabs(M.z) + fabs(C.x) +
+                                           fabs(C.y) + fabs(C.z))) * (1.0 + 0x1p-18);
+        const float rcu = (float)(rc[i] * (1.0 + 0x1p-20));
         em[2 * (size_t)pos] = make_float4((float)M.x, (float)M.y, (float)M.z, (float)w);
-        em[2 * (size_t)pos + 1] = make_float4((float)C.x, (float)C.y, (float)C.z, 0.0f);
+        em[2 * (size_t)pos + 1] = make_float4((float)C.x, (float)C.y, (float)C.z, r.big ? rcu : -rcu);
+        // the endpoint deviations of the step (as the tile bounds take them):
+        // their mean eb and half their difference's norm se, rounded up
+        double s2 = 0.0, eb[3];
+        for (int k = 0; k < 3; ++k) {
+            const double e0 = dt * r.v0[k] - (r.q1[k] - r.q0[k]), e1 = dt * r.v1[k] - (r.q1[k] - r.q0[k]);
+            eb[k] = 0.5 * (e0 + e1);
+            s2 += (e0 - e1) * (e0 - e1);
+        }
+        eg[pos] = make_float4((float)eb[0], (float)eb[1], (float)eb[2],
+                              (float)(0.5 * sqrt(s2) * (1.0 + 0x1p-20)));
     }
 }
 
@@ -2877,127 +2890,19 @@ __global__ __launch_bounds__(64 * kTpWaves) void k_tile_pairs(const Tile *__rest
     }
 }
 
-// One workgroup per surviving tile pair (grid-stride over the count): each of
-// its waves holds tile A's bodies in its lanes and tests a quarter of tile B's
-// records, staged once in LDS.
-// One wave per kept tile pair (A, B): lane L holds body L of tile A, tile B's
-// filter fields (midpoint, chord, 3/4 eps, rc, big flag: 72 B a body) sit in
-// the wave's LDS slice, and every lane meets the 64 sources in turn, so the
-// per-target setup (record, geometry, bound against tile B) serves 64 tests.
-// The exact test's fields of the rare survivors are read from the sorted
-// records in memory.
-struct FRec {
-    double M[3], c[3];
-    double e34, rc;
+// The exact test's fields of one sorted record.
+struct HRec {
+    double q0[3], v0[3], q1[3], v1[3];
+    double rc;
+    int body;
 };
 
-__global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ tiles,
-                                                      const TileB *__restrict__ tileb,
-                                                      const int2 *__restrict__ tpairs, int tp_cap,
-                                                      const SRec *__restrict__ srec, double dt,
-                                                      unsigned long long *__restrict__ keys,
-                                                      int cap, int *__restrict__ ce,
-                                                      DevStats *stats)
+// Exact encounter test of a pair (the Hermite bound, then the minimum over the
+// step) and the append of a flagged pair.
+__device__ __forceinline__ void enc_exact(const HRec &I, const SRec &J, double dt,
+                                          unsigned long long *keys, int cap, int *ce,
+                                          DevStats *stats)
 {
-    __shared__ FRec sb[kBlock / 64][64];
-    __shared__ int sbig[kBlock / 64][64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int npair = min(stats->cur_tp, tp_cap);
-    const double t2 = 2.0 * dt;
-    const double k427 = 4.0 / 27.0;
-    for (int p = blockIdx.x * (kBlock / 64) + wv; p < npair; p += gridDim.x * (kBlock / 64)) {
-        const int2 AB = tpairs[p];
-        const Tile TA = tiles[AB.x], TB = tiles[AB.y];
-        if (lane < TB.count) {
-            const SRec &r = srec[TB.start + lane];
-            FRec f;
-            for (int k = 0; k < 3; ++k) {
-                f.M[k] = r.M[k];
-                f.c[k] = r.c[k];
-            }
-            f.e34 = r.e34;
-            f.rc = r.rc;
-            sb[wv][lane] = f;
-            sbig[wv][lane] = r.big;
-        }
-        wave_lds_sync();
-        const bool on = lane < TA.count;
-        const SRec me = srec[TA.start + (on ? lane : 0)];
-        double M[3], c[3], eb[3], se;
-        rec_geometry(me, dt, M, c, eb, se);
-        const bool lane_ok = on && may_meet(M, 0.0, c, 0.0, eb, se, me.rc, tileb[AB.y]);
-        if (__any(lane_ok)) {
-            const bool diag = AB.x == AB.y;
-            for (int jj = 0; jj < TB.count; ++jj) {
-                const FRec &J = sb[wv][jj];
-                bool hit = false;
-                // relative chord filter (see k_encounter), every lane without a
-                // branch (the source record is one broadcast read)
-                const double mx = J.M[0] - me.M[0], my = J.M[1] - me.M[1], mz = J.M[2] - me.M[2];
-                const double cx = J.c[0] - me.c[0], cy = J.c[1] - me.c[1], cz = J.c[2] - me.c[2];
-                const double D2 = fma(mz, mz, fma(my, my, mx * mx));
-                const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
-                const double bb = J.e34 + me.e34 + fmax(J.rc, me.rc);
-                const bool cand = lane_ok & (!diag | (jj > lane)) & ((me.big | sbig[wv][jj]) != 0) &
-                                  (D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20));
-                if (__any(cand) && cand) {
-                    const SRec &Jr = srec[TB.start + jj];
-                    double d0x = Jr.q0[0] - me.q0[0], d0y = Jr.q0[1] - me.q0[1], d0z = Jr.q0[2] - me.q0[2];
-                    double d1x = Jr.q1[0] - me.q1[0], d1y = Jr.q1[1] - me.q1[1], d1z = Jr.q1[2] - me.q1[2];
-                    double e0x = Jr.v0[0] - me.v0[0], e0y = Jr.v0[1] - me.v0[1], e0z = Jr.v0[2] - me.v0[2];
-                    double e1x = Jr.v1[0] - me.v1[0], e1y = Jr.v1[1] - me.v1[1], e1z = Jr.v1[2] - me.v1[2];
-                    double f0 = fma(d0z, d0z, fma(d0y, d0y, d0x * d0x));
-                    double f1 = fma(d1z, d1z, fma(d1y, d1y, d1x * d1x));
-                    double g0 = t2 * fma(d0z, e0z, fma(d0y, e0y, d0x * e0x));
-                    double g1 = t2 * fma(d1z, e1z, fma(d1y, e1y, d1x * e1x));
-                    double lower = fmin(f0, f1) - k427 * (fmax(0.0, -g0) + fmax(0.0, g1));
-                    double rcij = fmax(me.rc, Jr.rc);
-                    double thr = rcij * rcij;
-                    if (lower <= thr * (1.0 + 1e-6) + 1e-15 * (f0 + f1 + fabs(g0) + fabs(g1)))
-                        hit = hermite_min(f0, f1, g0, g1) <= thr;
-                    if (hit) {
-                        const int pos = atomicAdd(&stats->cur_nce, 1);
-                        const int bi = me.body, bj = Jr.body;
-                        const unsigned lo = (unsigned)min(bi, bj), hi = (unsigned)max(bi, bj);
-                        if (pos < cap)
-                            keys[pos] = ((unsigned long long)lo << 32) | hi;
-                        __hip_atomic_store(&ce[bi], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        __hip_atomic_store(&ce[bj], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                }
-            }
-        }
-        // the slice is refilled for the next pair only after every lane's reads
-        wave_lds_sync();
-    }
-}
-
-// ----------------------------------------------------------------------------
-// Force and encounter check in one pass over spatially sorted tiles (FP32C,
-// every body big).  The symmetric force runs over super-tile pairs of sorted
-// positions (sources and targets gathered through the sorted order, split
-// partials by position, mapped back to bodies by the finalize).  In every
-// round the wave bounds the tile pairs of its target sub-tiles and the source
-// sub-tiles with the culling lemma of the sorted check (may_meet on the tiles
-// of 64); where a tile pair may hold a flagged pair, each pair of it also gets
-// the FP32 midpoint-reach filter, and the pairs it passes the relative-chord
-// filter and the exact Hermite test in FP64 from the sorted records.  Each
-// unordered pair is met once, so each flagged pair is appended once.
-// ----------------------------------------------------------------------------
-__device__ __noinline__ void enc_candidate(const SRec *__restrict__ srec, double dt,
-                                           unsigned long long *keys, int cap, int *ce,
-                                           DevStats *stats, int pi, int pj)
-{
-    const SRec &I = srec[pi];
-    const SRec &J = srec[pj];
-    // relative chord filter (see k_encounter)
-    const double mx = J.M[0] - I.M[0], my = J.M[1] - I.M[1], mz = J.M[2] - I.M[2];
-    const double cx = J.c[0] - I.c[0], cy = J.c[1] - I.c[1], cz = J.c[2] - I.c[2];
-    const double D2 = fma(mz, mz, fma(my, my, mx * mx));
-    const double C2 = fma(cz, cz, fma(cy, cy, cx * cx));
-    const double bb = J.e34 + I.e34 + fmax(J.rc, I.rc);
-    if (!(D2 <= fma(2.0, C2, 2.0 * bb * bb) * (1.0 + 0x1p-20)))
-        return;
     const double t2 = 2.0 * dt, k427 = 4.0 / 27.0;
     const double d0x = J.q0[0] - I.q0[0], d0y = J.q0[1] - I.q0[1], d0z = J.q0[2] - I.q0[2];
     const double d1x = J.q1[0] - I.q1[0], d1y = J.q1[1] - I.q1[1], d1z = J.q1[2] - I.q1[2];
@@ -3023,6 +2928,189 @@ __device__ __noinline__ void enc_candidate(const SRec *__restrict__ srec, double
     __hip_atomic_store(&ce[bj], 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The same for two sorted positions, every field of both records read at once.
+__device__ __noinline__ void enc_candidate(const SRec *__restrict__ srec, double dt,
+                                           unsigned long long *keys, int cap, int *ce,
+                                           DevStats *stats, int pi, int pj)
+{
+    const SRec &R = srec[pi];
+    HRec I;
+    for (int k = 0; k < 3; ++k) {
+        I.q0[k] = R.q0[k];
+        I.v0[k] = R.v0[k];
+        I.q1[k] = R.q1[k];
+        I.v1[k] = R.v1[k];
+    }
+    I.rc = R.rc;
+    I.body = R.body;
+    enc_exact(I, srec[pj], dt, keys, cap, ce, stats);
+}
+
+// One wave per kept tile pair (A, B), the waves striding over the count: lane
+// L holds the FP32 filter records of body L of tile A (midpoint with widened
+// bound, chord with big flag: 32 B), tile B's sit in the wave's LDS slice, and
+// every lane meets the 64 sources in turn with the relative-chord filter in
+// FP32, a superset of the pairs that can be flagged (the widening covers the
+// rounding).  A lane first meets tile B's bounds with the tile-pair test, as a
+// tile of one body whose FP32 records stand for small balls around its FP64
+// values (third record: the mean endpoint deviation and its radius).  The
+// pairs the filter keeps are queued in the wave's LDS and take the exact test
+// from the sorted FP64 records in memory 64 at a time, one per lane (with long
+// steps most pairs of a dense ring pass the filter, and a test per pass would
+// run on a few lanes); a tile pair reads 5 KB of filter records instead of the
+// 176-byte records of both tiles.
+__global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ tiles,
+                                                      const TileB *__restrict__ tileb,
+                                                      const int2 *__restrict__ tpairs, int tp_cap,
+                                                      const SRec *__restrict__ srec,
+                                                      const float4 *__restrict__ em,
+                                                      const float4 *__restrict__ eg, double dt,
+                                                      unsigned long long *__restrict__ keys,
+                                                      int cap, int *__restrict__ ce,
+                                                      DevStats *stats)
+{
+    __shared__ float4 sm_[kBlock / 64][64], sc_[kBlock / 64][64];
+    // per wave: queued pairs (lane | source << 8), fewer than 64 between drains
+    __shared__ int qe[kBlock / 64][128];
+    // per wave: tile A's exact-test fields (q0, v0, q1, v1, rc by plane; body
+    // index), staged at the tile pair's first full drain: a drain's 64 pairs
+    // hold many targets and few sources
+    __shared__ double ha[kBlock / 64][13][64];
+    __shared__ int hb[kBlock / 64][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int npair = min(stats->cur_tp, tp_cap);
+    const float qnan = __int_as_float(0x7fc00000);
+    for (int p = blockIdx.x * (kBlock / 64) + wv; p < npair; p += gridDim.x * (kBlock / 64)) {
+        const int2 AB = tpairs[p];
+        const Tile TA = tiles[AB.x], TB = tiles[AB.y];
+        // tile B's FP32 filter records in the wave's LDS slice (padding: NaN
+        // midpoints, which no test passes)
+        if (lane < TB.count) {
+            sm_[wv][lane] = em[2 * (size_t)(TB.start + lane)];
+            sc_[wv][lane] = em[2 * (size_t)(TB.start + lane) + 1];
+        } else {
+            sm_[wv][lane] = make_float4(qnan, qnan, qnan, 0.0f);
+            sc_[wv][lane] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        }
+        wave_lds_sync();
+        const bool on = lane < TA.count;
+        const float4 Mi = on ? em[2 * (size_t)(TA.start + lane)] : make_float4(qnan, qnan, qnan, 0.0f);
+        const float4 Ci = on ? em[2 * (size_t)(TA.start + lane) + 1] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        // the lane against tile B's bounds with the tile-pair test, the lane a
+        // tile of one body whose FP32 records stand for balls around them: 2^-23
+        // of each vector's norm covers its rounding, se and rc are rounded up
+        bool lane_ok = false;
+        if (on) {
+            const float4 Gi = eg[TA.start + lane];
+            const double Mv[3] = {Mi.x, Mi.y, Mi.z}, cv[3] = {Ci.x, Ci.y, Ci.z},
+                         ev[3] = {Gi.x, Gi.y, Gi.z};
+            const double sM = 0x1p-23 * norm3(Mv[0], Mv[1], Mv[2]);
+            const double sC = 0x1p-23 * norm3(cv[0], cv[1], cv[2]);
+            const double sE = (double)Gi.w + 0x1p-23 * norm3(ev[0], ev[1], ev[2]);
+            const TileB &BB = tileb[AB.y];
+            lane_ok = (__float_as_int(Ci.w) >= 0 || BB.big) &&
+                      may_meet(Mv, sM, cv, sC, ev, sE, (double)fabsf(Ci.w), BB);
+        }
+        const bool diag = AB.x == AB.y;
+        const int nj = __any(lane_ok) ? TB.count : 0;
+        int qn = 0;
+        bool staged = false;
+        // the exact test of queue entry e (this lane's): target from the staged
+        // fields, source record from memory
+        auto test_entry = [&](int e) {
+            const int li = e & 255;
+            HRec I;
+            for (int k = 0; k < 3; ++k) {
+                I.q0[k] = ha[wv][k][li];
+                I.v0[k] = ha[wv][3 + k][li];
+                I.q1[k] = ha[wv][6 + k][li];
+                I.v1[k] = ha[wv][9 + k][li];
+            }
+            I.rc = ha[wv][12][li];
+            I.body = hb[wv][li];
+            enc_exact(I, srec[TB.start + (e >> 8)], dt, keys, cap, ce, stats);
+        };
+        auto stage = [&]() {
+            if (!staged) {
+                if (on) {
+                    const SRec &R = srec[TA.start + lane];
+                    for (int k = 0; k < 3; ++k) {
+                        ha[wv][k][lane] = R.q0[k];
+                        ha[wv][3 + k][lane] = R.v0[k];
+                        ha[wv][6 + k][lane] = R.q1[k];
+                        ha[wv][9 + k][lane] = R.v1[k];
+                    }
+                    ha[wv][12][lane] = R.rc;
+                    hb[wv][lane] = R.body;
+                }
+                staged = true;
+            }
+        };
+        for (int jj = 0; jj < nj; ++jj) {
+            // source jj's FP32 filter records (one broadcast read each)
+            const float4 E = sm_[wv][jj], F = sc_[wv][jj];
+            // relative chord filter in FP32 (the bound's widening covers the
+            // rounding), every lane without a branch
+            const float ex = E.x - Mi.x, ey = E.y - Mi.y, ez = E.z - Mi.z;
+            const float cx = F.x - Ci.x, cy = F.y - Ci.y, cz = F.z - Ci.z;
+            const float D2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
+            const float C2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
+            const float Sr = (E.w + Mi.w) + fmaxf(fabsf(F.w), fabsf(Ci.w));
+            const bool cand = lane_ok & (!diag | (jj > lane)) &
+                              ((__float_as_int(F.w) & __float_as_int(Ci.w)) >= 0) &
+                              (D2 <= fmaf(Sr, Sr, C2) * (2.0f * (1.0f + 0x1p-18f)));
+            // the pairs the filter keeps join the wave's queue; 64 of them at a
+            // time take the exact test, one per lane
+            const unsigned long long mk = __ballot(cand);
+            if (mk) {
+                if (cand)
+                    qe[wv][qn + __popcll(mk & ((1ull << lane) - 1ull))] = lane | (jj << 8);
+                qn += __popcll(mk);
+                if (qn >= 64) {
+                    stage();
+                    wave_lds_sync();
+                    test_entry(qe[wv][lane]);
+                    const int rest = qn - 64;
+                    const int v = lane < rest ? qe[wv][64 + lane] : 0;
+                    wave_lds_sync();
+                    if (lane < rest)
+                        qe[wv][lane] = v;
+                    wave_lds_sync();
+                    qn = rest;
+                }
+            }
+        }
+        if (qn > 0) {
+            // the rest: from the staged fields if a full drain staged them, else
+            // both records from memory (a tile pair with few pairs to test)
+            wave_lds_sync();
+            if (lane < qn) {
+                const int e = qe[wv][lane];
+                if (staged)
+                    test_entry(e);
+                else
+                    enc_candidate(srec, dt, keys, cap, ce, stats, TA.start + (e & 255),
+                                  TB.start + (e >> 8));
+            }
+        }
+        // the slices, the queue and the staged fields are refilled for the
+        // next pair only after every lane's reads
+        wave_lds_sync();
+    }
+}
+
+// ----------------------------------------------------------------------------
+// Force and encounter check in one pass over spatially sorted tiles (FP32C,
+// every body big).  The symmetric force runs over super-tile pairs of sorted
+// positions (sources and targets gathered through the sorted order, split
+// partials by position, mapped back to bodies by the finalize).  In every
+// round the wave bounds the tile pairs of its target sub-tiles and the source
+// sub-tiles with the culling lemma of the sorted check (may_meet on the tiles
+// of 64); where a tile pair may hold a flagged pair, each pair of it also gets
+// the FP32 relative-chord filter, and the pairs it passes the exact Hermite
+// test in FP64 from the sorted records.  Each unordered pair is met once, so
+// each flagged pair is appended once.
+// ----------------------------------------------------------------------------
 // Tile of 64 sorted positions holding position p of system sy.
 __device__ __forceinline__ int tile_of(const int *__restrict__ tile_first, const int *__restrict__ off,
                                        int sy, int p)
@@ -4070,7 +4158,7 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, i
 // part tests pairs.  Both read only what the drift wrote (Q0, V0, the Q1, V1
 // and rc copies, the midpoint and chord records), so the whole check may run
 // beside the next S(h), force and kick.
-hipError_t launch_enc_gather(const Dev &d, hipStream_t s)
+hipError_t launch_enc_gather(const Dev &d, double dt, hipStream_t s)
 {
     if (d.enc_sorted && d.nrb > 0) {
         k_cells<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.lnr_part,
@@ -4090,7 +4178,7 @@ hipError_t launch_enc_gather(const Dev &d, hipStream_t s)
         k_srec<<<cdiv(d.ntot, kBlock), kBlock, 0, s>>>(d.ntot, d.slot_of, d.sys_of, d.q0x, d.q0y, d.q0z,
                                                        d.v0x, d.v0y, d.v0z, d.q1x, d.q1y, d.q1z,
                                                        d.v1x, d.v1y, d.v1z, d.rc1, d.mr, d.cr, d.off,
-                                                       d.nbig, d.srec, d.enc_fused ? d.em : nullptr);
+                                                       d.nbig, d.srec, d.em, d.eg, dt);
     }
     return hipGetLastError();
 }
@@ -4105,7 +4193,7 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
                 d.tiles, d.units, d.nunit, d.tileb, d.tpairs, d.tp_cap, d.stats);
             // one wave per kept tile pair
             int grid = std::min(std::max(1, cdiv(d.tp_cap, kBlock / 64)), 8192);
-            k_enc_pairs<<<grid, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.srec, dt,
+            k_enc_pairs<<<grid, kBlock, 0, s>>>(d.tiles, d.tileb, d.tpairs, d.tp_cap, d.srec, d.em, d.eg, dt,
                                                  d.keys, d.enc_cap, d.ce, d.stats);
         }
     } else if (d.enc_few) {
@@ -4126,7 +4214,7 @@ hipError_t launch_enc_test(const Dev &d, double dt, hipStream_t s)
 hipError_t launch_enc_prepare(const Dev &d, double dt, hipStream_t s)
 {
     // the binning clears the flags, the cell scan the list count
-    hipError_t e = launch_enc_gather(d, s);
+    hipError_t e = launch_enc_gather(d, dt, s);
     if (e == hipSuccess && d.ntile > 0)
         k_tile_bounds<<<cdiv(d.ntile, kBlock / 64), kBlock, 0, s>>>(d.tiles, d.ntile, d.srec, dt,
                                                                      d.tileb);
@@ -4166,12 +4254,16 @@ hipError_t launch_force_fused(const Dev &d, const Params &p, double dt, int coun
 hipError_t launch_encounters(const Dev &d, double dt, hipStream_t s)
 {
     // an empty list and no flags (the check may run beside the next drift, so
-    // the drift does not clear them)
-    hipError_t e = launch_fill_i32(&d.stats->cur_nce, 1, 0, s);
+    // the drift does not clear them); the sorted check's binning clears the
+    // flags and its scan the count
+    hipError_t e = hipSuccess;
+    if (!(d.enc_sorted && d.nrb > 0)) {
+        e = launch_fill_i32(&d.stats->cur_nce, 1, 0, s);
+        if (e == hipSuccess)
+            e = launch_fill_i32(d.ce, d.ntot, 0, s);
+    }
     if (e == hipSuccess)
-        e = launch_fill_i32(d.ce, d.ntot, 0, s);
-    if (e == hipSuccess)
-        e = launch_enc_gather(d, s);
+        e = launch_enc_gather(d, dt, s);
     return e != hipSuccess ? e : launch_enc_test(d, dt, s);
 }
 

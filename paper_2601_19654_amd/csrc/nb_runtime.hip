@@ -659,7 +659,8 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
         d.tile_first = (int *)take((size_t)nsys * sizeof(int));
     }
     d.enc_fused = t.enc_fused ? 1 : 0;
-    d.em = t.enc_fused ? (float4 *)take((size_t)ntot * 2 * sizeof(float4)) : nullptr;
+    d.em = t.enc_sorted ? (float4 *)take((size_t)ntot * 2 * sizeof(float4)) : nullptr;
+    d.eg = t.enc_sorted ? (float4 *)take((size_t)ntot * sizeof(float4)) : nullptr;
     d.flag = (int *)take(4 * sizeof(int));
     d.stage = (double *)take((size_t)7 * nd);
     d.lost = (int *)take((size_t)ntot * sizeof(int));

@@ -133,6 +133,51 @@ def test_tile_pair_bound_never_drops_a_flagged_pair():
     assert culled > 50 and checked == 400 * 36
 
 
+
+def lane_ball(body, rc, dt):
+    """One body as a tile of the tile-pair test, from its FP32 records as the
+    sorted check stores them: midpoint M, chord c and mean endpoint deviation eb
+    rounded to FP32, each a ball of 2^-23 of its norm; the deviation radius se
+    and rc rounded to FP32 after a 2^-20 relative increase."""
+    q0, v0, q1, v1 = body
+    c = q1 - q0
+    M = q0 + 0.5 * c
+    e0, e1 = dt * v0 - c, dt * v1 - c
+    eb, se = 0.5 * (e0 + e1), 0.5 * np.linalg.norm(e0 - e1)
+    f = np.float32
+    M32, c32, eb32 = (x.astype(f).astype(np.float64) for x in (M, c, eb))
+    se32 = float(f(se * (1 + 2.0 ** -20)))
+    rc32 = float(f(rc * (1 + 2.0 ** -20)))
+    n = np.linalg.norm
+    return (M32, 2.0 ** -23 * n(M32), c32, 2.0 ** -23 * n(c32), eb32, se32 + 2.0 ** -23 * n(eb32), rc32)
+
+
+def test_lane_ball_against_a_tile_never_drops_a_flagged_pair():
+    """The sorted check's lane test: a target body, from its rounded FP32 records,
+    against the bounds of a source tile.  Lanes pulled toward the tile so that
+    many sit near the cull boundary; whenever the oracle flags the lane with a
+    body of the tile, the test keeps the lane."""
+    rng = np.random.default_rng(99)
+    checked = culled = 0
+    for trial in range(3000):
+        dt = rng.uniform(0.01, 0.2)
+        spread = 10 ** rng.uniform(-3, -1)
+        B = _tile(rng, 8, 1.0, spread, dt)
+        a = _tile(rng, 1, 1.0, spread, dt)[0]
+        shift = (np.mean([b[0] for b in B], 0) - a[0]) * rng.uniform(0.6, 1.0)
+        a = (a[0] + shift, a[1], a[2] + shift, a[3])
+        rca = rng.uniform(0, 3 * spread)
+        rcb = rng.uniform(0, 3 * spread, 8)
+        ok = tiles_may_meet(lane_ball(a, rca, dt), tile_bounds(B, rcb, dt))
+        culled += not ok
+        for b, rb in zip(B, rcb):
+            d2 = oracle.pair_min_d2(dt, *a, *b)
+            if d2 <= max(rca, rb) ** 2:
+                assert ok, trial
+                checked += 1
+    assert culled > 300 and checked > 300
+
+
 def relative_bound_culls(bi, bj, rci, rcj, dt):
     """The pair filter on relative chords: with dM the midpoint difference, dc
     the chord difference, E = eps_i + eps_j and b = 3E/4 + max(rc_i, rc_j), a pair
