@@ -61,7 +61,7 @@ struct TileB {
     double cc[3], sc;
     double ce[3], se;
     double rc;
-    int big, pad;         // big: the tile holds at least one big body
+    int big, all_big;     // the tile holds at least one big body / only big bodies
     double pad2[2];
 };
 

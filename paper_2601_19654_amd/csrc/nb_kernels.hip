@@ -1831,7 +1831,8 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                 // fused encounter test: the relative-chord filter in FP32,
                 // |dM|^2 <= 2 (|dc|^2 + (b'_i + b'_j + max(rc_i, rc_j))^2) with
                 // the bounds b' widened for the FP32 rounding (padded targets
-                // and sources carry NaN midpoints and never pass)
+                // and sources carry NaN midpoints and never pass; every body is
+                // big on this path, so no b' carries the small-body sign)
                 bool encr[R] = {};
                 bool ecand = false;
                 if (ENC && livet) {
@@ -1843,7 +1844,7 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                         const float cx = F.x - eci[r].x, cy = F.y - eci[r].y, cz = F.z - eci[r].z;
                         const float D2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
                         const float C2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
-                        const float Sr = (E.w + emi[r].w) + fmaxf(fabsf(F.w), fabsf(eci[r].w));
+                        const float Sr = (E.w + emi[r].w) + fmaxf(F.w, eci[r].w);
                         const bool on = !DIAG || (64 * r + lane < 64 * t + (lane ^ (k0 + kk)));
                         encr[r] = ((livet >> r) & 1u) && on &&
                                   D2 <= fmaf(Sr, Sr, C2) * (2.0f * (1.0f + 0x1p-18f));
@@ -2702,14 +2703,14 @@ __global__ void k_srec(int ntot, const int *__restrict__ pos_of, const int *__re
         // FP32 records of the pair filter: midpoint M and chord c, and the
         // bound b' of 3/4 eps widened by 2^-21 (|M|_1 + |c|_1) for the FP32
         // rounding of M, c and their differences, and by 2^-18 relative for the
-        // rounding of the bound itself; the chord's fourth word is rc rounded up,
-        // negated (sign bit set, also for rc = 0) for a small body.  A pair's
-        // bound is b'_i + b'_j + max(rc_i, rc_j).
+        // rounding of the bound itself, negated (sign bit set) for a small body;
+        // the chord's fourth word is rc rounded up.  A pair's bound is
+        // |b'_i| + |b'_j| + max(rc_i, rc_j).
         const double w = (C.w + 0x1p-21 * (fabs(M.x) + fabs(M.y) + fabs(M.z) + fabs(C.x) +
                                            fabs(C.y) + fabs(C.z))) * (1.0 + 0x1p-18);
         const float rcu = (float)(rc[i] * (1.0 + 0x1p-20));
-        em[2 * (size_t)pos] = make_float4((float)M.x, (float)M.y, (float)M.z, (float)w);
-        em[2 * (size_t)pos + 1] = make_float4((float)C.x, (float)C.y, (float)C.z, r.big ? rcu : -rcu);
+        em[2 * (size_t)pos] = make_float4((float)M.x, (float)M.y, (float)M.z, r.big ? (float)w : -(float)w);
+        em[2 * (size_t)pos + 1] = make_float4((float)C.x, (float)C.y, (float)C.z, rcu);
         // the endpoint deviations of the step (as the tile bounds take them):
         // their mean eb and half their difference's norm se, rounded up
         double s2 = 0.0, eb[3];
@@ -2776,7 +2777,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_bounds(const Tile *__restrict__
         rc = r.rc;
         big = r.big != 0;
     }
-    const bool any_big = __any(big);
+    const bool any_big = __any(big), all_big = __all(!on || big);
     const double inv = 1.0 / (double)T.count;
     double cm[3], cc[3], ce[3];
     for (int k = 0; k < 3; ++k) {
@@ -2806,7 +2807,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_bounds(const Tile *__restrict__
         B.se = sde;
         B.rc = rcm;
         B.big = any_big ? 1 : 0;
-        B.pad = 0;
+        B.all_big = all_big ? 1 : 0;
         B.pad2[0] = B.pad2[1] = 0.0;
         tileb[tw] = B;
     }
@@ -2982,7 +2983,12 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
     const float qnan = __int_as_float(0x7fc00000);
     for (int p = blockIdx.x * (kBlock / 64) + wv; p < npair; p += gridDim.x * (kBlock / 64)) {
         const int2 AB = tpairs[p];
-        const Tile TA = tiles[AB.x], TB = tiles[AB.y];
+        Tile TA = tiles[AB.x], TB = tiles[AB.y];
+        // uniform over the wave (one tile pair a wave): kept in scalar registers
+        TA.start = __builtin_amdgcn_readfirstlane(TA.start);
+        TA.count = __builtin_amdgcn_readfirstlane(TA.count);
+        TB.start = __builtin_amdgcn_readfirstlane(TB.start);
+        TB.count = __builtin_amdgcn_readfirstlane(TB.count);
         // tile B's FP32 filter records in the wave's LDS slice (padding: NaN
         // midpoints, which no test passes)
         if (lane < TB.count) {
@@ -3008,11 +3014,12 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
             const double sC = 0x1p-23 * norm3(cv[0], cv[1], cv[2]);
             const double sE = (double)Gi.w + 0x1p-23 * norm3(ev[0], ev[1], ev[2]);
             const TileB &BB = tileb[AB.y];
-            lane_ok = (__float_as_int(Ci.w) >= 0 || BB.big) &&
-                      may_meet(Mv, sM, cv, sC, ev, sE, (double)fabsf(Ci.w), BB);
+            lane_ok = (__float_as_int(Mi.w) >= 0 || BB.big) &&
+                      may_meet(Mv, sM, cv, sC, ev, sE, (double)Ci.w, BB);
         }
         const bool diag = AB.x == AB.y;
-        const int nj = __any(lane_ok) ? TB.count : 0;
+        const int nj = __builtin_amdgcn_ballot_w64(lane_ok) ? TB.count : 0;
+        const float wi = fabsf(Mi.w);
         int qn = 0;
         bool staged = false;
         // the exact test of queue entry e (this lane's): target from the staged
@@ -3046,6 +3053,10 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
                 staged = true;
             }
         };
+        // the pair loop, with the diagonal's order test and the small-small
+        // test only where the tile pair needs them
+        auto pair_loop = [&](auto diag_c, auto small_c) {
+        constexpr bool DG = decltype(diag_c)::value, SM = decltype(small_c)::value;
         for (int jj = 0; jj < nj; ++jj) {
             // source jj's FP32 filter records (one broadcast read each)
             const float4 E = sm_[wv][jj], F = sc_[wv][jj];
@@ -3055,15 +3066,17 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
             const float cx = F.x - Ci.x, cy = F.y - Ci.y, cz = F.z - Ci.z;
             const float D2 = fmaf(ez, ez, fmaf(ey, ey, ex * ex));
             const float C2 = fmaf(cz, cz, fmaf(cy, cy, cx * cx));
-            const float Sr = (E.w + Mi.w) + fmaxf(fabsf(F.w), fabsf(Ci.w));
-            const bool cand = lane_ok & (!diag | (jj > lane)) &
-                              ((__float_as_int(F.w) & __float_as_int(Ci.w)) >= 0) &
-                              (D2 <= fmaf(Sr, Sr, C2) * (2.0f * (1.0f + 0x1p-18f)));
+            const float Sr = (fabsf(E.w) + wi) + max_nonneg(F.w, Ci.w);
+            bool cand = lane_ok & (D2 <= fmaf(Sr, Sr, C2) * (2.0f * (1.0f + 0x1p-18f)));
+            if (DG)
+                cand &= jj > lane;
+            if (SM)
+                cand &= (__float_as_int(E.w) & __float_as_int(Mi.w)) >= 0;
             // the pairs the filter keeps join the wave's queue; 64 of them at a
             // time take the exact test, one per lane
-            const unsigned long long mk = __ballot(cand);
+            const unsigned long long mk = __builtin_amdgcn_ballot_w64(cand);
             if (mk) {
-                if (cand)
+                if ((mk >> lane) & 1ull)
                     qe[wv][qn + __popcll(mk & ((1ull << lane) - 1ull))] = lane | (jj << 8);
                 qn += __popcll(mk);
                 if (qn >= 64) {
@@ -3079,6 +3092,21 @@ __global__ __launch_bounds__(kBlock) void k_enc_pairs(const Tile *__restrict__ t
                     qn = rest;
                 }
             }
+        }
+        };
+        // a small body in tile A (the sign of a lane's bound) or in tile B
+        const bool small = __builtin_amdgcn_ballot_w64(on && __float_as_int(Mi.w) < 0) != 0 ||
+                           !tileb[AB.y].all_big;
+        if (diag) {
+            if (small)
+                pair_loop(std::true_type{}, std::true_type{});
+            else
+                pair_loop(std::true_type{}, std::false_type{});
+        } else {
+            if (small)
+                pair_loop(std::false_type{}, std::true_type{});
+            else
+                pair_loop(std::false_type{}, std::false_type{});
         }
         if (qn > 0) {
             // the rest: from the staged fields if a full drain staged them, else
