@@ -312,6 +312,11 @@ def main():
                     help="skip the full-method lines (c3 adds them by default)")
     ap.add_argument("--force-g", type=int, default=0,
                     help="super-tile width of the symmetric force (0: tuned or automatic)")
+    ap.add_argument("--force-algo", type=int, default=0,
+                    help="force algorithm (0: tuned or automatic; 2: symmetric tile pairs; 4: "
+                         "symmetric over the radial order, FP32C)")
+    ap.add_argument("--force-r", type=int, default=0,
+                    help="target tiles of 64 force_r bodies (0: tuned or automatic)")
     ap.add_argument("--enc-algo", type=int, default=0,
                     help="encounter check algorithm (0: tuned or automatic; 4: inside the force pass)")
     ap.add_argument("--log", default=None,
@@ -338,7 +343,8 @@ def main():
     for mode in modes:
         print(f"[bench] {w.name} mode {mode}: ntot={w.ntot}, warmup {args.warmup}, steps {args.steps}",
               file=sys.stderr, flush=True)
-        over = {k: v for k, v in (("force_g", args.force_g), ("enc_algo", args.enc_algo)) if v}
+        over = {k: v for k, v in (("force_g", args.force_g), ("enc_algo", args.enc_algo),
+                                  ("force_algo", args.force_algo), ("force_r", args.force_r)) if v}
         res[mode] = run_mode(w, mode, args.steps, args.warmup, torch, nb, resolve=args.resolve,
                              energy_steps=energy_steps, overrides=over)
         enc = res[mode]["encounter_ms"]

@@ -113,7 +113,17 @@ typedef struct nb_params {
     int32_t resolve_threads; /* host threads of the resolver (0: up to 16, by the host) */
     int32_t force_algo;   /* force: 0 automatic, 1 every ordered pair (i, j) evaluated,
                              2 each unordered pair once and applied to both bodies (tile pairs;
-                             every body big); automatic takes 2 where it applies */
+                             every body big); automatic takes 2 where it applies;
+                             4 (FP32C) as 2 over the bodies of every system in order of
+                             distance from the star, the order set by nb_upload: tiles of 64
+                             consecutive bodies are thin shells, and a pair of them whose
+                             radial gap exceeds 2^21 times their low parts' norms and both
+                             critical radii takes the FP32 high parts only (each pair's
+                             difference within 2^-21 of its length, changeover weight K = 1,
+                             Sec. 3.1 force block).
+                             Results then depend on the order, so a run resumed by
+                             nb_upload rounds as a fresh upload of that state.  In FP64
+                             mode, and with enc_algo 4, it is 2. */
     double  bs_tol;       /* Bulirsch-Stoer relative tolerance (0: 1e-12) */
     const char *autotune_path; /* tuning table written by the autotuner (text; NULL: none).
                              When every tile and algorithm field (force_jchunk, force_r,
@@ -362,8 +372,8 @@ int nb_get_rcrit(nb_ctx *ctx, double *rc, int where);
 int nb_time_kernel(nb_ctx *ctx, int which, int reps, double dt, double *ms_per_launch);
 
 /* The algorithms the context resolved its automatic choices to (any pointer may
- * be NULL): force 1 (ordered pairs), 2 (symmetric tile pairs) or 3 (few-source
- * kernels); encounter check 1 (direct), 2 (sorted tiles), 3 (big bodies only as
+ * be NULL): force 1 (ordered pairs), 2 (symmetric tile pairs), 3 (few-source
+ * kernels) or 4 (symmetric tile pairs over the radial order); encounter check 1 (direct), 2 (sorted tiles), 3 (big bodies only as
  * partners) or 4 (sorted tiles inside the force pass); step launch 1
  * (per phase) or 2 (persistent). */
 int nb_get_choices(const nb_ctx *ctx, int32_t *force_algo, int32_t *enc_algo, int32_t *step_algo);

@@ -83,7 +83,8 @@ def tune(w, mode: str, reps: int = 10, verbose: bool = True) -> dict:
     from . import nb
     res_force, res_enc = {}, {}
     all_big = w.nbig is None or np.all(np.asarray(w.nbig) == np.diff(w.off))
-    for fa in ((1, 2) if all_big else (1,)):
+    # 4: the symmetric force over the radial order (FP32C only)
+    for fa in (((1, 2, 4) if mode == "fp32c" else (1, 2)) if all_big else (1,)):
         for r in FORCE_R:
             # the symmetric tile pairs have no source-chunk parameter, but a
             # super-tile width (tiles per workgroup)

@@ -20,7 +20,8 @@ constexpr long long kSymMinItems(int g) { return g >= 2 ? 8192 : 0; }
 
 // A block of an O(N) kernel: bodies [start, end) of one system (end - start <= kBlock).
 struct RBlk {
-    int sys, start, end, pad;
+    int sys, start, end;
+    int rt0;              // force over the radial order: the block's first tile of 64 positions
 };
 
 // A force work item: targets [i0, i0+ni), sources [j0, j0+nj) of one system;
@@ -156,6 +157,16 @@ struct Dev {
     // force and encounter check in one pass over the sorted order (FP32C,
     // every body big)
     int enc_fused;
+    // symmetric FP32C force over the radial order (bodies of each system by
+    // distance from the star, set at upload): rord position -> body, tiles of
+    // 64 positions from rtf[s] for system s, and their bounds written with the
+    // FP32C records (least and greatest |xh|, greatest low-part norm, largest
+    // widened rc^2)
+    int force_rsort;
+    int *rord;
+    int nrtile;
+    int *rtf;             // nsys
+    float4 *rtb;          // nrtile
     // sorted check: per sorted position two FP32 records for the pair filter,
     // the chord midpoint with the widened bound of 3/4 eps + rc, and the chord
     // with rc rounded up (its sign bit set for a small body) ...
@@ -217,7 +228,8 @@ struct Params {
     int enc_algo;         // 1: all pairs with the reach prefilter, 2: sorted tiles,
                           // 3: each body against its system's big bodies (at most kBlock)
     int step_algo;        // 1: per-phase launches, 2: persistent per-system launch
-    int force_algo;       // 0 automatic, 1 ordered pairs, 2 symmetric tile pairs
+    int force_algo;       // 0 automatic, 1 ordered pairs, 2 symmetric tile pairs, 4 symmetric
+                          // over the radial order (FP32C; FP64: as 2)
     int force_g;          // symmetric force: tiles per super-tile (0 automatic, 1, 2, 4)
     int resolve;          // 1: resolve flagged groups on the host every step
     int resolve_threads;

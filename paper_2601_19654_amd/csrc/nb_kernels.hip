@@ -370,7 +370,8 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
                             double *qz, int rcrit, const double *__restrict__ m, double n_hill,
                             double *__restrict__ rc, float4 *__restrict__ pk,
                             double *__restrict__ tile_rc2, double *__restrict__ copy_to,
-                            const double *__restrict__ ptot)
+                            const double *__restrict__ ptot, const int *__restrict__ rord,
+                            float4 *__restrict__ rtb)
 {
     // copy_to: this block's entry of `part` is copied there (nothing else reads
     // that array during the launch)
@@ -379,8 +380,12 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
     __shared__ double sh[3 * kBlock];
     double rc2 = 0.0;
     RBlk b = rblk[blockIdx.x];
-    const int i = b.start + threadIdx.x;
-    const bool on = i < b.end;
+    // rord: the block's positions of the radial order (their bodies from
+    // rord), each wave one tile of 64, whose bounds it writes to rtb
+    const int pos = b.start + threadIdx.x;
+    const bool on = pos < b.end;
+    const int i = rord && on ? rord[pos] : pos;
+    float tr = INFINITY, tR = 0.0f, tl = 0.0f, tc = 0.0f;
     // the body's position, loaded while the system's momentum is summed
     const double x0 = on ? qx[i] : 0.0, y0 = on ? qy[i] : 0.0, z0 = on ? qz[i] : 0.0;
     const double mi = on && rcrit ? m[i] : 0.0;
@@ -426,8 +431,30 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
                 r2 = fmaxf(r2, 0x1p-80f);
                 pk[2 * (size_t)i] = make_float4(hx, hy, hz, (float)mi);
                 pk[2 * (size_t)i + 1] = make_float4(lx, ly, lz, r2);
+                if (rtb) {
+                    // |xh| and |xl| in FP64 (products of floats are exact),
+                    // widened by 2^-22 before rounding to nearest so that the
+                    // floats bound them from the safe side
+                    const double rh = sqrt((double)hx * hx + (double)hy * hy + (double)hz * hz);
+                    const double rl = sqrt((double)lx * lx + (double)ly * ly + (double)lz * lz);
+                    tr = (float)(rh * (1.0 - 0x1p-22));
+                    tR = (float)(rh * (1.0 + 0x1p-22));
+                    tl = (float)(rl * (1.0 + 0x1p-22));
+                    tc = r2;
+                }
             }
         }
+    }
+    if (rtb) {
+        for (int o = 32; o > 0; o >>= 1) {
+            tr = fminf(tr, __shfl_xor(tr, o));
+            tR = fmaxf(tR, __shfl_xor(tR, o));
+            tl = fmaxf(tl, __shfl_xor(tl, o));
+            tc = fmaxf(tc, __shfl_xor(tc, o));
+        }
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0 && b.start + 64 * w < b.end)
+            rtb[b.rt0 + w] = make_float4(tr, tR, tl, tc);
     }
     if (rcrit) {
         // largest rc^2 of this block's bodies: the force kernel's per-tile zone threshold
@@ -1763,7 +1790,11 @@ static_assert(offsetof(SymTile32E<64>, em) == sizeof(SymTile32<64>) &&
 // chords eci[r] and the source's em, ec records), and the pairs that pass go to
 // the exact test.  The source records are read from the LDS tile at fixed
 // offsets past the FP32C fields (em, ec of SymTile32E).
-template <int R, bool DIAG, int T, bool ENC = false>
+// FAR: bit t of `far` set means every target of the wave lies apart from every
+// source of sub-tile t by more than 2^21 times their low parts' norms and
+// outside their critical radii (the radial tile bounds prove it): those pairs
+// take the differences of the high parts alone, with no changeover test.
+template <int R, bool DIAG, int T, bool ENC = false, bool FAR = false>
 __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, int ni, int j0,
                                             double inner, const float4 *__restrict__ pk,
                                             const double *__restrict__ qx,
@@ -1778,10 +1809,12 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                                             float (&lx)[R], float (&ly)[R], float (&lz)[R],
                                             int &near, const int *__restrict__ ord,
                                             const EncCtx &ec, const float4 (&emi)[R],
-                                            const float4 (&eci)[R], unsigned live)
+                                            const float4 (&eci)[R], unsigned live,
+                                            unsigned far = 0u)
 {
 #pragma unroll 1
     for (int t = 0; t < R; ++t) {
+        const bool fart = FAR && !DIAG && ((far >> t) & 1u);
         // the largest widened rc^2 of the wave's targets and of the sub-tile's
         // sources: one compare per pair outside the rare branch
         const float thr = max_nonneg(tmi, wave_max_nonneg(L.b[64 * t + lane].w));
@@ -1804,6 +1837,36 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
             const uint32_t a0 = lds_addr(&L.a[0]);
             const uint32_t self = lds_addr(&L.a[64 * t + lane]);
             uint32_t ac = self ^ (uint32_t)(k0 << 4);
+            if (fart) {
+                // far sub-tile: high parts only, no changeover test, no low
+                // records read
+                float4 A = lds_ld4(ac);
+#pragma unroll 2
+                for (int kk = 0; kk < 32; ++kk) {
+                    const uint32_t an = self ^ (uint32_t)(((k0 + kk + 1) & 63) << 4);
+                    const float4 An = lds_ld4(an);
+                    const lds_v3f S = lds_ld3(ac + 32 * T);
+                    float jx = S.x, jy = S.y, jz = S.z;
+#pragma unroll
+                    for (int r = 0; r < R; ++r) {
+                        const float dx = A.x - xh[r], dy = A.y - yh[r], dz = A.z - zh[r];
+                        const float r2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                        const float y = __builtin_amdgcn_rsqf(r2);
+                        const float q = y * (y * y);
+                        const float wi = A.w * q, wj = mi[r] * q;
+                        tx[r] = fmaf(wi, dx, tx[r]);
+                        ty[r] = fmaf(wi, dy, ty[r]);
+                        tz[r] = fmaf(wi, dz, tz[r]);
+                        jx = fmaf(-wj, dx, jx);
+                        jy = fmaf(-wj, dy, jy);
+                        jz = fmaf(-wj, dz, jz);
+                    }
+                    lds_st3(ac + 32 * T, jx, jy, jz);
+                    __asm__ __volatile__("" ::: "memory");
+                    ac = an;
+                    A = An;
+                }
+            } else {
             float4 A = lds_ld4(ac), B = lds_ld4(ac + 16 * T);
 #pragma unroll 2
             for (int kk = 0; kk < 32; ++kk) {
@@ -1889,6 +1952,7 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
                 A = An;
                 B = Bn;
             }
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 two_sum_f(hx[r], lx[r], tx[r]);
@@ -1908,7 +1972,25 @@ __device__ __forceinline__ void sym_tile32c(SymTile32<T> &L, int lane, int i0, i
     }
 }
 
-template <int R, int G>
+// Two 64-body tiles of the radial order are far apart for the FP32C pair loop
+// when the gap between their shells, |xh_i| in [rmin, rmax] (records written
+// by k_sun_drift with the FP32C records), exceeds 2^21 times the sum of their low parts' largest norms
+// and its square exceeds both largest widened rc^2.  Then for i in one and j in
+// the other |xh_j - xh_i| >= gap: dropping the low parts moves the pair's
+// difference by at most 2^-21 of its length, and the pair lies outside the
+// changeover zone (weight 1, no rare branch).  Margins of 2^-20 and 2^-18 cover
+// the FP32 rounding of the test itself.
+__device__ __forceinline__ bool far_tiles(float4 a, float4 b)
+{
+    const float gap = fmaxf(b.x - a.y, a.x - b.y) * (1.0f - 0x1p-20f);
+    return gap >= 0x1p21f * (a.z + b.z) * (1.0f + 0x1p-20f) &&
+           gap * gap >= fmaxf(a.w, b.w) * (1.0f + 0x1p-18f);
+}
+
+// SORT: the positions of the work items are positions of the radial order
+// (ord: position -> body), whose tile bounds rtb (system s's tiles from
+// rtf[s], 64 positions each from off[s]) mark the far sub-tile pairs.
+template <int R, int G, bool SORT = false>
 __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const FWork *__restrict__ work, int nitems,
                                                          const float4 *__restrict__ pk,
                                                          const double *__restrict__ qx,
@@ -1917,7 +1999,11 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
                                                          const double *__restrict__ m,
                                                          const double *__restrict__ rc,
                                                          float *__restrict__ fpart, int ntot,
-                                                         int maxs, double inner, DevStats *stats)
+                                                         int maxs, double inner, DevStats *stats,
+                                                         const int *__restrict__ ord = nullptr,
+                                                         const float4 *__restrict__ rtb = nullptr,
+                                                         const int *__restrict__ rtf = nullptr,
+                                                         const int *__restrict__ off = nullptr)
 {
     constexpr int T = 64 * R;
     __shared__ SymTile32<T> tl[G];
@@ -1934,8 +2020,9 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
             // sources past the end: massless and far away (r^2 ~ 1e36, so the
             // weight underflows to 0 instead of meeting a target at r = 0)
             if (k < wk.nj) {
-                S.a[e] = pk[2 * (size_t)(wk.j0 + k)];
-                S.b[e] = pk[2 * (size_t)(wk.j0 + k) + 1];
+                const int b = SORT ? ord[wk.j0 + k] : wk.j0 + k;
+                S.a[e] = pk[2 * (size_t)b];
+                S.b[e] = pk[2 * (size_t)b + 1];
             } else {
                 S.a[e] = make_float4(1e18f, 1e18f, 1e18f, 0.0f);
                 S.b[e] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
@@ -1954,7 +2041,7 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
         for (int r = 0; r < R; ++r) {
             const int li = 64 * r + lane;
             const bool ok = li < tni;
-            const int i = ok ? ti0 + li : wk.i0;
+            const int i = SORT ? ord[ok ? ti0 + li : wk.i0] : (ok ? ti0 + li : wk.i0);
             const float4 A = pk[2 * (size_t)i], B = pk[2 * (size_t)i + 1];
             xh[r] = A.x; yh[r] = A.y; zh[r] = A.z;
             xl[r] = B.x; yl[r] = B.y; zl[r] = B.z;
@@ -1977,15 +2064,34 @@ __global__ __launch_bounds__(64 * G, R == 4 ? 2 : 3) void k_force32c_sym(const F
             const int s = (wv + k) % G;
             const bool go = tni > 0 && s * T < wk.nj && !(diag && 2 * k == G && wv >= G / 2);
             if (go) {
-                if (diag && k == 0)
+                if (diag && k == 0) {
                     sym_tile32c<R, true, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, inner, pk, qx,
                                             qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx, hy,
-                                            hz, lx, ly, lz, near, nullptr, noenc, noem, noem, 0u);
-                else
-                    sym_tile32c<R, false, T>(tl[s], lane, ti0, tni, wk.j0 + s * T, inner, pk, qx,
-                                             qy, qz, m, rc, xh, yh, zh, xl, yl, zl, mi, tmi, hx,
-                                             hy, hz, lx, ly, lz, near, nullptr, noenc, noem, noem,
-                                             0u);
+                                            hz, lx, ly, lz, near, SORT ? ord : nullptr, noenc, noem,
+                                            noem, 0u);
+                } else {
+                    // far source sub-tiles (radial order, no padded targets)
+                    unsigned far = 0u;
+                    if (SORT && tni == T) {
+                        const int tb0 = rtf[wk.sys], o = off[wk.sys], sj0 = wk.j0 + s * T;
+#pragma unroll
+                        for (int t = 0; t < R; ++t) {
+                            if (s * T + 64 * t >= wk.nj)
+                                continue;
+                            const float4 Bt = rtb[tb0 + (sj0 + 64 * t - o) / 64];
+                            bool f = true;
+#pragma unroll
+                            for (int r = 0; r < R; ++r)
+                                f = f && far_tiles(rtb[tb0 + (ti0 + 64 * r - o) / 64], Bt);
+                            far |= f ? 1u << t : 0u;
+                        }
+                    }
+                    sym_tile32c<R, false, T, false, SORT>(tl[s], lane, ti0, tni, wk.j0 + s * T,
+                                                          inner, pk, qx, qy, qz, m, rc, xh, yh, zh,
+                                                          xl, yl, zl, mi, tmi, hx, hy, hz, lx, ly,
+                                                          lz, near, SORT ? ord : nullptr, noenc,
+                                                          noem, noem, 0u, far);
+                }
             }
             __syncthreads();
         }
@@ -4035,10 +4141,13 @@ hipError_t launch_sun_drift(const Dev &d, double h, int rcrit, const Params &p, 
     const bool pre = h != 0.0 && d.sys_total;
     if (pre)
         k_sys_total<<<d.nsys, kBlock, 0, s>>>(d.rb_first, d.rb_count, part, d.ptot);
+    // the FP32C records over the radial order, with its tile bounds
+    const bool rs = p.mode == 1 && rcrit && d.force_rsort;
     k_sun_drift<<<d.nrb, kBlock, 0, s>>>(d.rblk, d.rb_first, d.rb_count, d.m0, part, h, d.qx,
                                           d.qy, d.qz, rcrit, d.m, p.n_hill, d.rc,
                                           p.mode == 1 ? d.pk : nullptr, d.tile_rc2, copy_to,
-                                          pre ? d.ptot : nullptr);
+                                          pre ? d.ptot : nullptr, rs ? d.rord : nullptr,
+                                          rs ? d.rtb : nullptr);
     return hipGetLastError();
 }
 
@@ -4070,9 +4179,17 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
                     p.inner, d.stats
 #define NB_SYM32_ARGS d.fwork, d.nfw, d.pk, d.qx, d.qy, d.qz, d.m, d.rc, d.fpart32, d.ntot, \
                       d.maxs, p.inner, d.stats
+#define NB_RSYM32_ARGS NB_SYM32_ARGS, d.rord, d.rtb, d.rtf, d.off
 #define NB_SYM_G(R_)                                                                          \
     do {                                                                                      \
-        if (p.mode == 1) {                                                                    \
+        if (p.mode == 1 && d.force_rsort) {                                                   \
+            if (d.sym_g == 4)                                                                 \
+                k_force32c_sym<R_, 4, true><<<grid, 256, 0, s>>>(NB_RSYM32_ARGS);             \
+            else if (d.sym_g == 2)                                                            \
+                k_force32c_sym<R_, 2, true><<<grid, 128, 0, s>>>(NB_RSYM32_ARGS);             \
+            else                                                                              \
+                k_force32c_sym<R_, 1, true><<<grid, 64, 0, s>>>(NB_RSYM32_ARGS);              \
+        } else if (p.mode == 1) {                                                             \
             if (d.sym_g == 4)                                                                 \
                 k_force32c_sym<R_, 4><<<grid, 256, 0, s>>>(NB_SYM32_ARGS);                    \
             else if (d.sym_g == 2)                                                            \
@@ -4096,6 +4213,7 @@ hipError_t launch_force(const Dev &d, const Params &p, hipStream_t s)
             NB_SYM_G(2);
 #undef NB_SYM_G
 #undef NB_SYM_ARGS
+#undef NB_RSYM32_ARGS
 #undef NB_SYM32_ARGS
         return hipGetLastError();
     }
@@ -4170,6 +4288,9 @@ hipError_t launch_force_finalize(const Dev &d, const Params &p, double kick_h, i
     while (nsl < 16 && nsl * 8 < d.maxs)
         nsl *= 2;
     const int grid = cdiv(d.ntot, kFinThreads / nsl), cc = enc_count ? d.enc_cap : -1;
+    // the radial order's partials are by position too
+    if (!ord && d.force_rsort)
+        ord = d.rord;
     if (d.fpart32)
         k_force_finalize<float><<<grid, kFinThreads, 0, s>>>(
             d.sys_of, d.nsplit, d.fpart32, d.ntot, d.maxs, d.ns_all, nsl, p.G, d.ax, d.ay, d.az,

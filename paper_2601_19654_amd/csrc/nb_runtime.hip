@@ -184,7 +184,7 @@ int apply_tuning(const nb_params &u, int nsys, const int32_t *off, const int32_t
         const int nf = std::sscanf(line, "%255s %d %d %d %d %d %d %d", k, &fa, &fr, &fj, &ea, &ej, &sa, &fg);
         if (nf < 7 || key != k)
             continue;
-        if (fa < 0 || fa > 2 || (fr != 1 && fr != 2 && fr != 4) || fj <= 0 || ea < 0 || ea > 4 ||
+        if (fa < 0 || fa == 3 || fa > 4 || (fr != 1 && fr != 2 && fr != 4) || fj <= 0 || ea < 0 || ea > 4 ||
             ej <= 0 || sa < 0 || sa > 2 || (fg != 0 && fg != 1 && fg != 2 && fg != 4))
             break;     // a malformed entry is ignored
         q.force_algo = fa;
@@ -274,7 +274,7 @@ int check_params(const nb_params *p)
         p->step_algo < 0 || p->step_algo > 2)
         return NB_E_INVALID;
     if ((p->resolve != 0 && p->resolve != 1) || p->resolve_threads < 0 || p->force_algo < 0 ||
-        p->force_algo > 2 ||
+        (p->force_algo > 2 && p->force_algo != 4) ||
         !(p->bs_tol >= 0.0 && p->bs_tol < 1.0) || (p->resolve && p->step_algo == 2))
         return NB_E_INVALID;
     if (p->drag && !(p->drag_h > 0.0 && p->drag_h * p->drag_h * 3.0 < 1.0 && p->drag_rho_p > 0.0 &&
@@ -328,6 +328,10 @@ struct Tables {
     bool force_few = false;
     bool force_sym = false;
     int sym_g = 1;        // tiles per super-tile of the symmetric force
+    // symmetric FP32C force over the radial order: tiles of 64 positions
+    bool force_rsort = false;
+    int nrtile = 0;
+    std::vector<int> rtf;
     // persistent step launch: systems largest first
     std::vector<PSys> psys;
 };
@@ -405,10 +409,20 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
     // kSymPartialMax; beyond that the ordered pairs' partials are bounded)
     t.sym_g = sym_width(p, nsys, off);
     t.force_sym = p.force_algo != 1 && !has_small(nsys, off, nbig) &&
-                  (p.force_algo == 2 ||
+                  (p.force_algo == 2 || p.force_algo == 4 ||
                    sym_partial_bytes(p, nsys, off, t.sym_g * 64 * p.force_r) <= kSymPartialMax);
     // the fused pass is the symmetric force's: without it, the sorted check alone
     t.enc_fused = t.enc_fused && t.force_sym;
+    // 4: the symmetric FP32C force over the radial order (not with the fused
+    // pass, which runs over the encounter check's order)
+    t.force_rsort = p.force_algo == 4 && p.mode == NB_FP32C && t.force_sym && !t.enc_fused;
+    t.rtf.assign(nsys, 0);
+    t.nrtile = 0;
+    if (t.force_rsort)
+        for (int s = 0; s < nsys; ++s) {
+            t.rtf[s] = t.nrtile;
+            t.nrtile += (off[s + 1] - off[s] + 63) / 64;
+        }
     t.rb_first.assign(nsys, 0);
     t.rb_count.assign(nsys, 0);
     t.nsplit.assign(nsys, 0);
@@ -422,7 +436,7 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
             t.sys_of[i] = s;
         t.rb_first[s] = (int)t.rblk.size();
         for (int b = 0; b < n; b += kBlock)
-            t.rblk.push_back(RBlk{s, a + b, a + std::min(n, b + kBlock), 0});
+            t.rblk.push_back(RBlk{s, a + b, a + std::min(n, b + kBlock), t.rtf[s] + b / 64});
         t.rb_count[s] = (int)t.rblk.size() - t.rb_first[s];
         if (n == 0)
             continue;
@@ -498,9 +512,15 @@ void build_tables(const Params &p, int nsys, const int32_t *off, const int32_t *
                                   nbig ? nbig[s] : off[s + 1] - off[s]});
     std::stable_sort(t.psys.begin(), t.psys.end(),
                      [](const PSys &x, const PSys &y) { return x.n > y.n; });
-    // longest work first, so the hardware dispatcher packs the tail
-    std::stable_sort(t.fwork.begin(), t.fwork.end(), [](const FWork &x, const FWork &y) {
-        return (long long)x.ni * x.nj > (long long)y.ni * y.nj;
+    // longest work first, so the hardware dispatcher packs the tail; over the
+    // radial order the super-tile pairs nearest the diagonal (neighbouring
+    // shells: no far tile pairs, most changeover pairs) cost most
+    const bool rs = t.force_rsort;
+    std::stable_sort(t.fwork.begin(), t.fwork.end(), [rs](const FWork &x, const FWork &y) {
+        const long long cx = (long long)x.ni * x.nj, cy = (long long)y.ni * y.nj;
+        if (cx != cy || !rs)
+            return cx > cy;
+        return x.j0 - x.i0 < y.j0 - y.i0;
     });
     auto pairs = [](const PWork &w) {
         long long c = 0;
@@ -635,6 +655,11 @@ size_t carve(const Params &p, int nsys, int ntot, int enc_cap, const Tables &t, 
     d.force_few = t.force_few ? 1 : 0;
     d.force_sym = t.force_sym ? 1 : 0;
     d.sym_g = t.sym_g;
+    d.force_rsort = t.force_rsort ? 1 : 0;
+    d.nrtile = t.nrtile;
+    d.rord = d.force_rsort ? (int *)take((size_t)ntot * sizeof(int)) : nullptr;
+    d.rtf = d.force_rsort ? (int *)take((size_t)nsys * sizeof(int)) : nullptr;
+    d.rtb = d.force_rsort ? (float4 *)take((size_t)t.nrtile * sizeof(float4)) : nullptr;
     if (d.enc_sorted) {
         d.lnr_part = (double *)take((size_t)std::max(d.nrb, 1) * 2 * sizeof(double));
         for (int k = 0; k + 1 < d.nsnap; ++k)
@@ -1125,6 +1150,16 @@ int setup_layout(nb_ctx *c, int nsys, const int32_t *off, const int32_t *nbig)
         r = set_err(c, NB_E_HIP, "clearing the step counters failed");
     if (r == NB_OK && c->ntot > 0 && launch_fill_i32(c->d.lost, c->ntot, 0, c->stream) != hipSuccess)
         r = set_err(c, NB_E_HIP, "clearing the lost flags failed");
+    // the radial order's tiles; until the first upload sets the order, every
+    // body at its own position
+    std::vector<int> ident;
+    if (c->d.force_rsort) {
+        up(c->d.rtf, t.rtf.data(), nsys * sizeof(int));
+        ident.resize(c->ntot);
+        for (int i = 0; i < c->ntot; ++i)
+            ident[i] = i;
+        up(c->d.rord, ident.data(), ident.size() * sizeof(int));
+    }
     if (c->d.enc_sorted) {
         up(c->d.sys_cell_base, t.cell_base.data(), nsys * sizeof(int));
         up(c->d.sys_cell_cnt, t.cell_cnt.data(), nsys * sizeof(int));
@@ -1142,6 +1177,36 @@ int setup_layout(nb_ctx *c, int nsys, const int32_t *off, const int32_t *nbig)
     c->have_events = false;
     c->snap = 0;
     return r;
+}
+
+// The radial order of the symmetric FP32C force (force_algo 4): the bodies of
+// every system by distance from the star, ties by index, from the DH positions
+// on the device.  Any order gives the same pairs; this one makes tiles of 64
+// consecutive positions thin shells, so that most tile pairs are provably far
+// apart, and it stays so while orbits stay near-circular.
+int radial_order(nb_ctx *c)
+{
+    if (!c->d.force_rsort || c->ntot == 0)
+        return NB_OK;
+    const size_t n = (size_t)c->ntot;
+    std::vector<double> q(3 * n);
+    int r;
+    if ((r = copy(c, q.data(), c->d.qx, n * sizeof(double))) ||
+        (r = copy(c, q.data() + n, c->d.qy, n * sizeof(double))) ||
+        (r = copy(c, q.data() + 2 * n, c->d.qz, n * sizeof(double))) || (r = sync(c)))
+        return r;
+    std::vector<double> d2(n);
+    for (size_t i = 0; i < n; ++i)
+        d2[i] = q[i] * q[i] + q[n + i] * q[n + i] + q[2 * n + i] * q[2 * n + i];
+    std::vector<int> ord(n);
+    for (size_t i = 0; i < n; ++i)
+        ord[i] = (int)i;
+    for (int s = 0; s < c->nsys; ++s)
+        std::sort(ord.begin() + c->off[s], ord.begin() + c->off[s + 1],
+                  [&](int a, int b) { return d2[a] < d2[b] || (d2[a] == d2[b] && a < b); });
+    if ((r = copy(c, c->d.rord, ord.data(), n * sizeof(int))))
+        return r;
+    return sync(c);
 }
 
 int enter(nb_ctx *c)
@@ -1310,6 +1375,8 @@ int nb_upload(nb_ctx *c, const double *m0, const double *m, const double *x, con
         return set_err(c, NB_E_INVALID, "nb_upload: a small body has a nonzero mass");
     }
     HIP_OK(c, launch_to_dh(c->d, xs, vs, frame, c->stream));
+    if ((r = radial_order(c)))
+        return r;
     if ((r = enqueue_force(c)))
         return r;
     if ((r = sync(c)))
@@ -1846,7 +1913,7 @@ int nb_get_choices(const nb_ctx *c, int32_t *force_algo, int32_t *enc_algo, int3
     if (!c)
         return NB_E_INVALID;
     if (force_algo)
-        *force_algo = c->d.force_sym ? 2 : (c->d.force_few ? 3 : 1);
+        *force_algo = c->d.force_rsort ? 4 : (c->d.force_sym ? 2 : (c->d.force_few ? 3 : 1));
     if (enc_algo)
         *enc_algo = c->d.enc_fused ? 4 : (c->d.enc_sorted ? 2 : (c->d.enc_few ? 3 : 1));
     if (step_algo)

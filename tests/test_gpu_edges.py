@@ -48,7 +48,7 @@ def _massless_in_all_big():
 
 
 @pytest.mark.parametrize("mode,tol", [(0, 1e-12), (1, 1e-6)])
-@pytest.mark.parametrize("force_algo", [1, 2])
+@pytest.mark.parametrize("force_algo", [1, 2, 4])
 @pytest.mark.parametrize("maker", [_coincident, _massless_in_all_big])
 def test_degenerate_bodies_force_and_steps(maker, mode, tol, force_algo):
     w = maker()
@@ -134,10 +134,13 @@ def test_checkpoint_resume(mode, step_algo):
     assert du <= 1e-12 and su["total_nce"] == sr["total_nce"]
 
 
-def test_graph_runs_of_mixed_lengths():
-    w = workloads.ring(2500, m=3e-8)
-    a = ctx_for(w, mode=1)
-    b = ctx_for(w, mode=1)
+@pytest.mark.parametrize("force_algo", [0, 4])
+def test_graph_runs_of_mixed_lengths(force_algo):
+    """Captured runs of any lengths give the bits of single steps; with the
+    radial order too (it is set at upload, not by the runs)."""
+    w = workloads.ring(2500, m=3e-8, a_lo=0.6, a_hi=1.4) if force_algo == 4 else workloads.ring(2500, m=3e-8)
+    a = ctx_for(w, mode=1, force_algo=force_algo)
+    b = ctx_for(w, mode=1, force_algo=force_algo)
     lists = []
     for k in (8, 3, 8, 5, 20, 1, 8):
         a.prepare(w.dt, k)

@@ -9,7 +9,8 @@ kernels with their split partials) is compared with the oracle's step
 K S D C S F K (Sec. 3.1: force, Hamiltonian, drift and encounter blocks) after
 every one of three steps:
 
-  * 16384-body annulus (the headline workload), FP64 and FP32C pair arithmetic;
+  * 16384-body annulus (the headline workload), FP64 and FP32C pair arithmetic
+    (FP32C also with the force over the radial order, force_algo 4);
   * the first 64 systems of the 256-system batch (N_s from 200 to 4000, the
     largest system setting the split count, longest work first), FP32C.
 
@@ -62,8 +63,10 @@ def _sampled_scale(w, Q, nsample=512, seed=3):
     return np.concatenate(idx), np.concatenate(A)
 
 
-def _compare_steps(w, mode, ref, qtol, atol, enc_algo=0):
-    c = ctx_for(w, mode=mode, enc_cap=1 << 18, enc_algo=enc_algo)
+def _compare_steps(w, mode, ref, qtol, atol, enc_algo=0, force_algo=0):
+    c = ctx_for(w, mode=mode, enc_cap=1 << 18, enc_algo=enc_algo, force_algo=force_algo)
+    if force_algo == 4:
+        assert c.choices()["force_algo"] == 4
     if enc_algo == 4:
         assert c.choices()["enc_algo"] == 4
     print(f"[{w.name}] mode {mode} choices {c.choices()} tiles {c.tiles}", flush=True)
@@ -86,9 +89,9 @@ def _compare_steps(w, mode, ref, qtol, atol, enc_algo=0):
     c.close()
 
 
-def _compare_run(w, mode, ref, qtol, enc_algo=0):
+def _compare_run(w, mode, ref, qtol, enc_algo=0, force_algo=0):
     """The same three steps as one nb_step call (a captured run of three steps)."""
-    c = ctx_for(w, mode=mode, enc_cap=1 << 18, enc_algo=enc_algo)
+    c = ctx_for(w, mode=mode, enc_cap=1 << 18, enc_algo=enc_algo, force_algo=force_algo)
     st = c.step(w.dt, STEPS)
     Q, V, _, pairs = ref[-1]
     x, v = c.download(nb.NB_DH)
@@ -109,13 +112,14 @@ def c3_ref():
     return w, _oracle_run(w)
 
 
-@pytest.mark.parametrize("mode,qtol,atol,enc_algo", [(0, 1e-11, 1e-12, 0), (1, 1e-7, 1e-6, 0),
-                                                     (1, 1e-7, 1e-6, 4)])
-def test_c3_steps_match_oracle(c3_ref, mode, qtol, atol, enc_algo):
-    """enc_algo 4: the encounter test inside the force pass over the sorted order."""
+@pytest.mark.parametrize("mode,qtol,atol,enc_algo,force_algo", [(0, 1e-11, 1e-12, 0, 0), (1, 1e-7, 1e-6, 0, 0),
+                                                                (1, 1e-7, 1e-6, 4, 0), (1, 1e-7, 1e-6, 0, 4)])
+def test_c3_steps_match_oracle(c3_ref, mode, qtol, atol, enc_algo, force_algo):
+    """enc_algo 4: the encounter test inside the force pass over the sorted
+    order; force_algo 4: the symmetric force over the radial order."""
     w, ref = c3_ref
-    _compare_steps(w, mode, ref, qtol, atol, enc_algo)
-    _compare_run(w, mode, ref, qtol, enc_algo)
+    _compare_steps(w, mode, ref, qtol, atol, enc_algo, force_algo)
+    _compare_run(w, mode, ref, qtol, enc_algo, force_algo)
 
 
 @pytest.fixture(scope="module")
@@ -124,10 +128,10 @@ def c4_ref():
     return w, _oracle_run(w)
 
 
-@pytest.mark.parametrize("enc_algo", [0, 4])
-def test_c4_batch_steps_match_oracle(c4_ref, enc_algo):
+@pytest.mark.parametrize("enc_algo,force_algo", [(0, 0), (4, 0), (0, 4)])
+def test_c4_batch_steps_match_oracle(c4_ref, enc_algo, force_algo):
     w, ref = c4_ref
     sizes = np.diff(w.off)
     assert w.nsys == 64 and sizes.min() >= 200 and sizes.max() <= 4000 and sizes.max() > 3500
-    _compare_steps(w, 1, ref, 1e-7, 1e-6, enc_algo)
-    _compare_run(w, 1, ref, 1e-7, enc_algo)
+    _compare_steps(w, 1, ref, 1e-7, 1e-6, enc_algo, force_algo)
+    _compare_run(w, 1, ref, 1e-7, enc_algo, force_algo)

@@ -61,7 +61,7 @@ def test_force_fp64(case, r, jchunk, force_algo):
 
 
 @pytest.mark.parametrize("r,jchunk", [(2, 0), (1, 256), (4, 512)])
-@pytest.mark.parametrize("force_algo", [1, 2])
+@pytest.mark.parametrize("force_algo", [1, 2, 4])
 def test_force_fp32c(case, r, jchunk, force_algo):
     name, w, (Q, V, rc, a_ref) = case
     c = ctx_for(w, mode=nb.NB_FP32C, force_r=r, force_jchunk=jchunk, force_algo=force_algo)
@@ -76,6 +76,64 @@ def test_force_fp32c(case, r, jchunk, force_algo):
         worst = err if not (err <= worst) else worst      # a NaN error is kept
     print(f"FP32C force error {name} r={r} j={jchunk} algo={force_algo}: {worst:.3e} A_i")
     assert worst <= 1e-6, (name, worst)
+
+
+def _far_fraction(w, R):
+    """Fraction of the off-diagonal tile pairs (wave rows of 64 R targets
+    against source tiles of 64) that the radial order's far test takes from
+    the high parts, emulated on the host from the DH positions' FP32 split
+    (the test of the far-tile pin)."""
+    from test_far_tiles import far_tiles, tile_bounds
+    Q, _, rc, _ = oracle_dh(w)
+    far = tot = 0
+    for s, lo, hi in systems(w):
+        n = hi - lo
+        if n < 2 * 64 * R:
+            continue
+        order = np.lexsort((np.arange(n), np.einsum("ij,ij->i", Q[lo:hi], Q[lo:hi])))
+        q = Q[lo:hi][order]
+        xh = q.astype(np.float32)
+        xl = (q - xh.astype(np.float64)).astype(np.float32)
+        rc2 = (rc[lo:hi][order] ** 2).astype(np.float32)
+        recs = [tile_bounds(xh[b:b + 64], xl[b:b + 64], rc2[b:b + 64]) for b in range(0, n, 64)]
+        nrow = n // (64 * R)
+        for i in range(nrow):
+            for t in range(len(recs)):
+                if t // R <= i:
+                    continue
+                tot += 1
+                far += all(far_tiles(recs[i * R + r], recs[t]) for r in range(R))
+    return far / max(tot, 1)
+
+
+@pytest.mark.parametrize("r,g", [(2, 1), (1, 2), (4, 1), (2, 4)])
+def test_force_radial_order(r, g):
+    """force_algo 4: the symmetric FP32C force over the bodies of every system
+    by distance from the star, tile pairs proven far apart from the FP32 high
+    parts alone.  A 0.5-5 AU annulus (where most tile pairs are far) and a
+    ragged batch, against the oracle at the FP32C bar, and against the same
+    force over the index order (force_algo 2)."""
+    for w in (workloads.c3(n=4000), workloads.batch([1, 2, 300, 0, 1031, 2600], cfg_id=31, a_lo=0.5,
+                                                    a_hi=5.0)):
+        Q, V, rc, a_ref = oracle_dh(w)
+        frac = _far_fraction(w, r)
+        c = ctx_for(w, mode=nb.NB_FP32C, force_r=r, force_g=g, force_algo=4)
+        ch = c.choices()
+        assert ch["force_algo"] == 4 and ch["force_g"] == g, ch
+        a = c.accel()
+        a2 = ctx_for(w, mode=nb.NB_FP32C, force_r=r, force_g=g, force_algo=2).accel()
+        worst = worst2 = 0.0
+        for s, lo, hi in systems(w):
+            if hi - lo < 2:
+                assert np.all(a[lo:hi] == 0.0)
+                continue
+            A = pair_scale(w.m[lo:hi], Q[lo:hi], w.G)
+            worst = max(worst, accel_error(a[lo:hi], a_ref[lo:hi], A))
+            worst2 = max(worst2, accel_error(a2[lo:hi], a_ref[lo:hi], A))
+        print(f"radial order {w.name} r={r} g={g}: far tile pairs {frac:.2f}, error {worst:.3e} A_i "
+              f"(index order {worst2:.3e})", flush=True)
+        assert frac > 0.3
+        assert worst <= 1e-6 and worst <= 4 * worst2 + 1e-7
 
 
 @pytest.mark.parametrize("mode", [0, 1])
@@ -247,7 +305,7 @@ def test_diagnostics(case):
 
 # ---------------------------------------------------------------- full steps
 @pytest.mark.parametrize("mode,algo,step_algo,force_algo", [(0, 1, 1, 0), (1, 1, 1, 0), (0, 2, 1, 0),
-                                                            (0, 0, 2, 0), (0, 1, 1, 1)])
+                                                            (0, 0, 2, 0), (0, 1, 1, 1), (1, 2, 1, 4)])
 def test_steps_match_oracle(case, mode, algo, step_algo, force_algo):
     name, w, _ = case
     k = 5
@@ -511,6 +569,10 @@ def test_resolved_choices():
     ch = c.choices()
     assert ch["force_algo"] == 2 and ch["enc_algo"] in (1, 2) and ch["step_algo"] in (1, 2)
     assert ctx_for(ring, force_algo=1).choices()["force_algo"] == 1
+    # the radial order: FP32C only (FP64 takes the index order), not with the fused check
+    assert ctx_for(ring, mode=1, force_algo=4).choices()["force_algo"] == 4
+    assert ctx_for(ring, mode=0, force_algo=4).choices()["force_algo"] == 2
+    assert ctx_for(ring, mode=1, force_algo=4, enc_algo=4).choices()["force_algo"] == 2
     assert ctx_for(ring, enc_algo=2).choices()["enc_algo"] == 2
     assert ctx_for(ring, resolve=1).choices()["step_algo"] == 1
     bs = workloads.bigsmall(50, 140000)
