@@ -457,7 +457,9 @@ __global__ void k_sun_drift(const RBlk *__restrict__ rblk, const int *__restrict
             rtb[b.rt0 + w] = make_float4(tr, tR, tl, tc);
     }
     if (rcrit) {
-        // largest rc^2 of this block's bodies: the force kernel's per-tile zone threshold
+        // largest rc^2 of this block's bodies: the zone threshold of the ordered and
+        // few-source force kernels (over the radial order, which only the symmetric
+        // kernel uses, the bodies of the block's positions)
         for (int o = 32; o > 0; o >>= 1)
             rc2 = fmax(rc2, __shfl_xor(rc2, o));
         if ((threadIdx.x & 63) == 0)
